@@ -1,0 +1,257 @@
+/*
+ * ntu.h -- C ABI of libntu: the MI355X (gfx950) hot path of the neighbourhood
+ * tensor update (NTU) for iPEPS time evolution.
+ *
+ * Method: J. Dziarmaga, "Time evolution of an infinite projected entangled
+ * pair state: a neighborhood tensor update", arXiv:2107.06635, Sec. II
+ * (Figs. 2, 4, 5 and Eqs. (1)-(5)).
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions shared by every call
+ * ---------------------------------------------------------------------------
+ * Pointers.  Every tensor pointer is a DEVICE pointer to memory the caller
+ *   allocated; the library never frees or reallocates caller memory.  Batched
+ *   operands are dense: item i of a buffer starts at i * (item size).  Uneven
+ *   bond dimensions are handled by one call per dimension.
+ * Storage.  Row-major, last index fastest.  NTU_C128 is interleaved
+ *   (re, im) double pairs (the layout of a complex128 array), NTU_F64 plain
+ *   doubles, NTU_C64 interleaved float pairs (accepted for site tensors only,
+ *   upcast on load).  All results are written in the context's compute type
+ *   (NTU_F64 or NTU_C128).
+ * Site tensors.  Legs (p, t, l, b, r): physical block p = d * d_anc
+ *   (ancilla folded in as p = s * d_anc + a), then top, left, bottom, right
+ *   virtual legs of dimension D.  Size p * D^4.
+ * Canonical bond.  The updated bond joins X.r to Y.l.  r_g is the rank of the
+ *   gate split (Fig. 2(a)), R = D * r_g the dimension of the enlarged bond.
+ * Streams.  Work is enqueued on the context's stream (ntu_set_stream) and is
+ *   asynchronous; results are valid after that stream is synchronised.  No
+ *   call allocates device memory or synchronises: all scratch space comes from
+ *   the workspace allocated by ntu_ctx_create, so call sequences can be
+ *   captured into a HIP graph.
+ * Errors.  Argument, shape and dtype errors are detected on the host before
+ *   anything is launched; the call then returns a negative status and
+ *   ntu_last_error() describes it.  Numerical conditions (non-finite values)
+ *   are reported in the caller's device stats buffers.
+ * Concurrency.  One context serves one stream; calls on one context must not
+ *   overlap.  Distinct contexts are independent.
+ */
+#ifndef NTU_H
+#define NTU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ntu_ctx ntu_ctx;
+typedef int32_t ntu_status;
+
+enum {
+  NTU_OK = 0,
+  NTU_ERR_ARG = -1,         /* null pointer, bad enum, batch < 0 ...        */
+  NTU_ERR_SHAPE = -2,       /* D, p, r_g outside what the context supports   */
+  NTU_ERR_DTYPE = -3,       /* dtype not accepted for this operand           */
+  NTU_ERR_HIP = -4,         /* a HIP runtime call failed                     */
+  NTU_ERR_NONFINITE = -5,   /* reserved: non-finite values are flagged in stats */
+  NTU_ERR_WORKSPACE = -6,   /* request exceeds the context's workspace       */
+  NTU_ERR_UNSUPPORTED = -7  /* valid request this build does not implement   */
+};
+
+/* storage types */
+enum { NTU_F64 = 0, NTU_C128 = 1, NTU_C64 = 2 };
+
+/* arithmetic of the environment contraction (ntu_env_contract) */
+enum {
+  NTU_PREC_F64 = 0,    /* FP64 throughout                                      */
+  NTU_PREC_BF16X3 = 1, /* operands split hi+lo in bfloat16, 3 MFMA products,
+                          FP32 accumulation, FP32 intermediates               */
+  NTU_PREC_FP16X3 = 2, /* same with float16 and the low part scaled by 2^11    */
+  NTU_PREC_BF16X6 = 3  /* three-way bfloat16 split, 6 products                 */
+};
+
+/* metric repair modes (ntu_metric_fix) */
+enum { NTU_FIX_HERM = 0, NTU_FIX_HERM_CLIP = 1 };
+
+/* the four inequivalent bonds of the two-site checkerboard */
+enum { NTU_BOND_H1 = 0, NTU_BOND_H2 = 1, NTU_BOND_V1 = 2, NTU_BOND_V2 = 3 };
+
+/*
+ * Context.  Allocates the workspace for items up to bond dimension max_D,
+ * physical dimension d, ancilla dimension d_anc (1 = none), gate rank r_g and
+ * max_batch items per call, in compute type dtype (NTU_F64 or NTU_C128).
+ * device: HIP device ordinal.  The stream is the null stream until
+ * ntu_set_stream is called.  Returns NTU_ERR_HIP if the workspace cannot be
+ * allocated.
+ */
+ntu_status ntu_ctx_create(ntu_ctx** out, int device, int dtype, int d, int d_anc,
+                          int r_g, int max_D, int max_batch);
+ntu_status ntu_ctx_destroy(ntu_ctx* ctx);
+/* stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream). */
+ntu_status ntu_set_stream(ntu_ctx* ctx, void* stream);
+/* Message of the last failed call on ctx ("" if none).  Owned by ctx. */
+const char* ntu_last_error(const ntu_ctx* ctx);
+/* Bytes of device workspace held by ctx. */
+size_t ntu_workspace_bytes(const ntu_ctx* ctx);
+/* Library version string (static). */
+const char* ntu_version(void);
+
+/*
+ * Gate split, Fig. 2(a).  For each item, the two-site gate
+ * G[(s1' s2'), (s1 s2)] (d^2 x d^2, compute type) is regrouped as
+ * [(s1' s1), (s2' s2)] and SV-decomposed; the r_g leading terms give
+ * GA[s1', s1, k] = sqrt(sigma_k) U[(s1' s1), k] and
+ * GB[s2', s2, k] = sqrt(sigma_k) conj(V)[(s2' s2), k], so that
+ * G = sum_k GA[:, :, k] (x) GB[:, :, k] up to the discarded terms.
+ * Gauge: the first entry of U[:, k] whose modulus is within 1e-8 of the
+ * column maximum is made real and positive.
+ * gate: batch x d^4.  GA, GB: batch x (d, d, r_g).  sigma: batch x d^2
+ * doubles, all singular values in descending order (device).
+ */
+ntu_status ntu_gate_split(ntu_ctx* ctx, int batch, const void* gate, void* GA, void* GB,
+                          double* sigma);
+
+/*
+ * Reduction, Fig. 2(b).  Applies the gate factor to the site tensor and takes
+ * the thin QR decomposition of the result:
+ *   side 0 (X): W[(s',a,t,l,b), (r,k)] = sum_s GA[s',s,k] X[(s,a),t,l,b,r]
+ *   side 1 (Y): W[(s',a,t,b,r), (l,k)] = sum_s GB[s',s,k] Y[(s,a),t,l,b,r]
+ *   W = Q R,  Q: (p D^3) x R with orthonormal (or zero) columns,
+ *   R: R x R upper triangular with real non-negative diagonal.
+ * Q is computed by Gram-Schmidt with the projection applied twice; a column
+ * whose orthogonal part has norm <= 1e-10 * (largest column norm of W) is
+ * dependent: its Q column and R diagonal are exactly zero.
+ * site: batch x p D^4 in site_dtype (NTU_F64, NTU_C128 or NTU_C64).
+ * gate_factor: batch x (d, d, r_g).  Q: batch x (p D^3) x R.  R: batch x R x R.
+ */
+ntu_status ntu_reduce_qr(ntu_ctx* ctx, int batch, int D, const void* site, int site_dtype,
+                         const void* gate_factor, int side, void* Q, void* R);
+
+/*
+ * Environment contraction, Fig. 4.  Builds the bond metric
+ *   g[(a' b'), (a b)] = sum_e conj(Phi_{a'b'}(e)) Phi_{ab}(e)
+ * where Phi_{ab} is the eight-site cluster (Fig. 4(b)) with QX[:, a] and
+ * QY[:, b] in the two central sites and the six nearest neighbours
+ * nbr = [L, TX, BX, TY, BY, Rn] around them: L left of X, TX/BX above/below X,
+ * TY/BY above/below Y, Rn right of Y, with bonds TX.r-TY.l and BX.r-BY.l
+ * parallel to the updated one.  Physical legs of the neighbours and their
+ * virtual legs that leave the cluster are closed by contracting ket with bra
+ * (Fig. 4(a,b)).  The result is Hermitian and non-negative up to rounding.
+ * QX: batch x (p,t,l,b | a)  ((p D^3) x R, rows p,t,l,b), as ntu_reduce_qr side 0.
+ * QY: batch x (p,t,b,r | b)  ((p D^3) x R, rows p,t,b,r), as ntu_reduce_qr side 1.
+ * nbr: six pointers, each batch x p D^4 site tensors (compute type).
+ * precision: NTU_PREC_*.  g: batch x R^2 x R^2, compute type.
+ */
+ntu_status ntu_env_contract(ntu_ctx* ctx, int batch, int D, const void* QX, const void* QY,
+                            const void* const nbr[6], int precision, void* g);
+
+/*
+ * Metric repair.  The exact metric is Hermitian and non-negative (abstract;
+ * Sec. II).  NTU_FIX_HERM replaces g by (g + g^H)/2.  NTU_FIX_HERM_CLIP also
+ * sets negative eigenvalues to zero: g <- V max(Lambda, 0) V^H.  Rows and
+ * columns that are exactly zero are left out of the eigenproblem; when the
+ * remaining block is certified positive definite (Cholesky succeeds) the
+ * clip is the identity and is skipped.
+ * g: batch x n x n in place, n = (D r_g)^2.
+ * stats (device, may be NULL): batch x 8 doubles
+ *   [0] ||g - g^H||_F / ||g||_F  (input)      [1] ||g||_F (input)
+ *   [2] smallest eigenvalue (NaN if not computed)
+ *   [3] largest eigenvalue  (NaN if not computed)
+ *   [4] clipped mass sum(-lambda_neg)/sum|lambda| (0 if certified)
+ *   [5] 1 if the eigen-decomposition ran, 0 if certified
+ *   [6] number of non-finite entries in the input   [7] reserved
+ */
+ntu_status ntu_metric_fix(ntu_ctx* ctx, int batch, int D, void* g, int mode, double* stats);
+
+/* Options of the bond fit (Eqs. (3)-(5)). */
+typedef struct ntu_fit_opts {
+  int n_iter;        /* maximum ALS iterations (one = an X and a Y half-step) */
+  int early_stop;    /* 0: always n_iter; 1: stop when an iteration lowers the
+                        error by <= conv_tol * N                                */
+  double conv_tol;
+  double kappa;      /* rank threshold (default 1e-10): kept singular values
+                        S_i > kappa S_0                                          */
+  int n_tol;         /* pseudo-inverse tolerance ladder, ascending, relative   */
+  double tol[16];    /*   to the largest eigenvalue of g_X (Eq. (4))           */
+  double tie;        /* errors within tie * N count as equal; the larger
+                        tolerance wins                                          */
+} ntu_fit_opts;
+
+/* Fills o with the defaults: 20 iterations, no early stop, kappa 1e-10,
+   ladder 1e-15 ... 1e-8, tie 1e-15. */
+void ntu_fit_opts_default(ntu_fit_opts* o);
+
+/* Number of doubles per item in the stats buffer of ntu_bond_fit. */
+#define NTU_FIT_STATS_LEN(n_iter, D) (16 + 4 * (n_iter) + (D))
+
+/*
+ * Bond fit, Fig. 5 and Eqs. (2)-(5), with the SVDU initial guess (Fig. 2(c,d))
+ * and the final balancing (Fig. 5(d)).
+ *   P = RX RY^T;  SVDU: P ~ U S V^H truncated to Dn = min(D, #{S_i > kappa S_0});
+ *   error eps = d^H g d,  d = vec(MX MY^T - P) (row-major (a, b));
+ *   ALS: before the X half-step MY is made isometric with the product kept
+ *   (the tilt of Fig. 5), then MX = pinv(g_X) J_X with K = I (x) MY,
+ *   g_X = K^H g K, J_X = K^H g vec(P); the pseudo-inverse tolerance is the
+ *   ladder value minimising eps, evaluated directly.  The Y half-step mirrors
+ *   it.  Finally SVD of MX MY^T, singular values divided by the largest,
+ *   MX = U S^1/2, MY = conj(V) S^1/2, zero-padded to D columns.
+ * g: batch x R^2 x R^2 (Hermitian, non-negative).  RX, RY: batch x R x R.
+ * MX, MY: batch x R x D outputs.
+ * stats (device, may be NULL): batch x NTU_FIT_STATS_LEN(n_iter, D) doubles:
+ *   [0] N = vec(P)^H g vec(P)  [1] eps of the SVDU guess  [2] final eps
+ *   [3] final eps / N          [4] Dn   [5] Dk (kept after balancing)
+ *   [6] iterations done        [7] half-steps solved by eigendecomposition
+ *   [8] non-finite flag        [9..15] reserved
+ *   [16 + 2i + h]              eps after half-step h of iteration i
+ *   [16 + 2 n_iter + 2i + h]   chosen tolerance of that half-step
+ *   [16 + 4 n_iter + j]        normalised singular value j (0 beyond Dk)
+ */
+ntu_status ntu_bond_fit(ntu_ctx* ctx, int batch, int D, const void* g, const void* RX,
+                        const void* RY, const ntu_fit_opts* opts, void* MX, void* MY,
+                        double* stats);
+
+/*
+ * Recombination, Fig. 2(e): X' = QX MX (new leg r), Y' = QY MY (new leg l),
+ * written as site tensors (p, t, l, b, r).
+ * QX, QY: as from ntu_reduce_qr.  MX, MY: batch x R x D.
+ * Xn, Yn: batch x p D^4 outputs (must not alias QX/QY).
+ */
+ntu_status ntu_recombine(ntu_ctx* ctx, int batch, int D, const void* QX, const void* QY,
+                         const void* MX, const void* MY, void* Xn, void* Yn);
+
+/* Options of a Trotter step. */
+typedef struct ntu_step_opts {
+  int n_bonds;          /* number of bond updates in the sweep (<= 8)          */
+  int order[8];         /* NTU_BOND_* in sweep order (first order: H1,H2,V1,V2) */
+  int precision;        /* NTU_PREC_* for the environment contraction          */
+  int fix_mode;         /* NTU_FIX_*                                            */
+  ntu_fit_opts fit;
+} ntu_step_opts;
+
+void ntu_step_opts_default(ntu_step_opts* o);
+
+/* Number of doubles per item and bond update in the stats of ntu_trotter_step. */
+#define NTU_STEP_STATS_LEN(n_iter, D) (8 + NTU_FIT_STATS_LEN(n_iter, D))
+
+/*
+ * One Trotter step of the two-site checkerboard iPEPS (Secs. I, III): the
+ * bond updates of opts->order, one after another, each a full NTU update
+ * (reduce, environment, metric repair, fit, recombination) of the bond in the
+ * canonical frame: H1 updates A.r-B.l (X = A, Y = B); H2 updates B.r-A.l;
+ * V1 and V2 are H1 and H2 after rotating both tensors by 90 degrees clockwise
+ * (new (t, l, b, r) = old (l, b, r, t)), i.e. the bonds A.t-B.b and B.t-A.b.
+ * The environment of each update is made of the current A and B.
+ * A, B: batch x p D^4 in place (compute type).
+ * gate_factors: batch x 4 bonds x 2 x (d, d, r_g): for bond j (NTU_BOND_*) the
+ *   factors (GA, GB) of its gate, GA acting on X.  Items are independent.
+ * stats (device, may be NULL): batch x n_bonds x NTU_STEP_STATS_LEN doubles:
+ *   [0..7] metric stats of the update, then the bond-fit stats.
+ */
+ntu_status ntu_trotter_step(ntu_ctx* ctx, int batch, int D, void* A, void* B,
+                            const void* gate_factors, const ntu_step_opts* opts, double* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NTU_H */

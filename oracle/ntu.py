@@ -1,0 +1,484 @@
+"""Plain FP64 CPU oracle of the neighbourhood tensor update (NTU).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports this module:
+only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` use it.  It shares no code with the GPU library; both are fed the
+same arrays from ``paper_2107_06635_amd.inputs``.
+
+Everything is numpy in float64 / complex128 (real inputs stay real), written
+step by step in the order of Sec. II of the paper (Figs. 2, 4, 5 and
+Eqs. (2)-(5)).  Library primitives (matmul, einsum, QR/SVD/eigh) serve as
+single steps; there is no blocking or fusion.
+
+Index conventions
+-----------------
+* Site tensor legs ``(p, t, l, b, r)``; the bond being updated joins ``X.r``
+  to ``Y.l`` ("canonical frame").  Vertical bonds are brought into this frame
+  by a 90-degree rotation of both tensors.
+* Gate factors ``GA[s', s, k]``, ``GB[s', s, k]`` with
+  ``G[(s1' s2'), (s1 s2)] = sum_k GA[s1', s1, k] GB[s2', s2, k]`` (Fig. 2(a)).
+* Cluster (Fig. 4(b)): X, Y and their six nearest neighbours ``L`` (left of X),
+  ``TX``/``BX`` (above/below X), ``TY``/``BY`` (above/below Y), ``Rn`` (right
+  of Y); internal bonds are the six spokes and the two bonds ``TX.r-TY.l``,
+  ``BX.r-BY.l`` parallel to the updated bond.  All other virtual legs and all
+  physical legs of the neighbours are closed by contracting ket with bra.
+* Metric layout: ``g[(a' b'), (a b)] = sum_e conj(Phi_{a'b'}(e)) Phi_{ab}(e)``
+  (rows = bra pair), so that Eq. (2) reads ``eps = d^H g d`` with
+  ``d = vec(MX MY^T - RX RY^T)`` in row-major ``(a, b)`` order.
+
+Readings of the paper that this file fixes (each also listed in the design doc):
+rank rule ``KAPPA`` for the QR and the truncation, the pseudo-inverse tolerance
+ladder ``TOL_LADDER`` with direct evaluation of the error, ties going to the
+larger tolerance, normalisation of the singular values by the largest one, and
+the cluster estimator for observables.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# numerical-rank threshold, relative (QR columns and kept singular values)
+KAPPA = 1e-10
+# pseudo-inverse tolerances relative to the largest eigenvalue of g_X (Eq. 4)
+TOL_LADDER = tuple(10.0 ** e for e in range(-15, -7))
+# two ladder candidates whose errors differ by less than TIE * N are a tie
+TIE = 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Gate split, Fig. 2(a)
+# ---------------------------------------------------------------------------
+
+def _phase_fix_columns(U: np.ndarray) -> np.ndarray:
+    """Phase per column so that the first entry whose modulus is within 1e-8
+    of the column's largest modulus is real and positive."""
+    ph = np.ones(U.shape[1], dtype=U.dtype)
+    for k in range(U.shape[1]):
+        col = U[:, k]
+        m = np.abs(col)
+        i = int(np.argmax(m >= (1.0 - 1e-8) * m.max()))
+        if m[i] > 0:
+            ph[k] = np.conj(col[i]) / m[i]
+    return ph
+
+
+def gate_split(G: np.ndarray, d: int, r: int):
+    """Split a two-site gate into ``GA[s1', s1, k]`` and ``GB[s2', s2, k]``.
+
+    Fig. 2(a): the gate becomes two tensors joined by an index of dimension
+    ``r``.  Operator SVD of ``G`` regrouped as ``[(s1' s1), (s2' s2)]``,
+    ``sqrt(sigma_k)`` on each side, ``r`` leading terms kept.  Gauge: the
+    largest entry of each left singular vector is made real positive.
+    Returns ``(GA, GB, sigma_all)``.
+    """
+    G4 = G.reshape(d, d, d, d)                       # [s1', s2', s1, s2]
+    M = G4.transpose(0, 2, 1, 3).reshape(d * d, d * d)  # [(s1' s1), (s2' s2)]
+    U, s, Vh = np.linalg.svd(M)
+    ph = _phase_fix_columns(U)
+    U = U * ph[None, :]
+    Vh = Vh * np.conj(ph)[:, None]
+    sq = np.sqrt(s[:r])
+    GA = (U[:, :r] * sq[None, :]).reshape(d, d, r)
+    GB = (Vh[:r, :].T * sq[None, :]).reshape(d, d, r)
+    if np.isrealobj(G):
+        GA, GB = GA.real, GB.real
+    return GA, GB, s
+
+
+# ---------------------------------------------------------------------------
+# Reduction to isometry and reduced matrix, Fig. 2(b)
+# ---------------------------------------------------------------------------
+
+def thin_qr(W: np.ndarray, kappa: float = KAPPA):
+    """``W = Q R`` by Gram-Schmidt: column ``j`` of ``Q`` is the normalised part
+    of ``W[:, j]`` orthogonal to the earlier columns (projection applied twice
+    for accuracy), ``R`` upper triangular with real ``R[j, j] >= 0``.
+
+    Rank rule: when that orthogonal part has norm ``<= kappa * max_j |W[:, j]|``
+    the column is dependent; ``Q[:, j]`` and ``R[j, j]`` are then exactly zero,
+    so no arbitrary completion of ``Q`` can enter the metric.
+    """
+    m, n = W.shape
+    Q = np.zeros_like(W)
+    R = np.zeros((n, n), dtype=W.dtype)
+    scale = max((np.linalg.norm(W[:, j]) for j in range(n)), default=0.0)
+    for j in range(n):
+        v = W[:, j].copy()
+        c = np.zeros(j, dtype=W.dtype)
+        for _ in range(2):
+            h = Q[:, :j].conj().T @ v
+            v = v - Q[:, :j] @ h
+            c = c + h
+        R[:j, j] = c
+        nv = np.linalg.norm(v)
+        if scale > 0 and nv > kappa * scale:
+            Q[:, j] = v / nv
+            R[j, j] = nv
+    return Q, R
+
+
+def reduce_site(T: np.ndarray, gf: np.ndarray, side: str, d: int, kappa: float = KAPPA):
+    """Apply the gate factor and QR-decompose, Fig. 2(b).
+
+    ``side='X'``: ``W[(s', a, t, l, b), (r, k)] = sum_s GA[s', s, k] X[(s, a), t, l, b, r]``.
+    ``side='Y'``: ``W[(s', a, t, b, r), (l, k)] = sum_s GB[s', s, k] Y[(s, a), t, l, b, r]``.
+    Returns ``Q`` shaped ``(p, D, D, D, R)`` (row legs in the order above) and
+    ``R`` shaped ``(R, R)`` with ``R = D * r``.
+    """
+    p, D = T.shape[0], T.shape[1]
+    na = p // d
+    r = gf.shape[2]
+    T6 = T.reshape(d, na, D, D, D, D)
+    W = np.einsum('ysk,satlbq->yatlbqk', gf, T6)      # q = r leg (X) / l leg (Y)
+    if side == 'X':
+        Wm = W.reshape(p * D ** 3, D * r)             # rows (y a t l b), cols (r k)
+    else:
+        # rows must be (y a t b r); W currently has (y a t l b r k) with l = bond
+        W = W.transpose(0, 1, 2, 4, 5, 3, 6)          # (y a t b r l k)
+        Wm = W.reshape(p * D ** 3, D * r)
+    Q, R = thin_qr(Wm, kappa)
+    return Q.reshape(p, D, D, D, D * r), R
+
+
+# ---------------------------------------------------------------------------
+# SVDU initial guess, Fig. 2(c,d)
+# ---------------------------------------------------------------------------
+
+def svdu_guess(RX: np.ndarray, RY: np.ndarray, D: int, kappa: float = KAPPA):
+    """``P = RX RY^T = U S V^H`` (transpose, not dagger), keep
+    ``Dn = min(D, #{S_i > kappa S_0})``, ``MX = U S^1/2``, ``MY = conj(V) S^1/2``
+    so that ``MX MY^T`` is the truncated ``P``."""
+    P = RX @ RY.T
+    U, S, Vh = np.linalg.svd(P)
+    if S[0] <= 0:
+        Dn = 0
+    else:
+        Dn = int(min(D, np.count_nonzero(S > kappa * S[0])))
+    sq = np.sqrt(S[:Dn])
+    MX = U[:, :Dn] * sq[None, :]
+    MY = Vh[:Dn, :].T * sq[None, :]
+    return P, MX, MY, S, Dn
+
+
+# ---------------------------------------------------------------------------
+# Metric, Fig. 4
+# ---------------------------------------------------------------------------
+
+def _ein(spec, *ops):
+    """One pairwise contraction (einsum routed through BLAS)."""
+    return np.einsum(spec, *ops, optimize=True)
+
+
+def edge_tensors(L, TX, BX, TY, BY, Rn):
+    """Edge double tensors, Fig. 4(a,b): each neighbour's physical leg and its
+    external virtual legs are contracted ket with bra; the legs that touch the
+    cluster stay open as (ket, bra) pairs.
+
+    ``EL[x, x']``: L's right leg.  ``ER[x, x']``: Rn's left leg.
+    ``ETX[u, u', v, v']``: TX bottom (u, to X.t) and right (v, to TY.l).
+    ``ETY[u, u', v, v']``: TY bottom (u, to Y.t) and left (v, to TX.r).
+    ``EBX[u, u', v, v']``: BX top (u, to X.b) and right (v, to BY.l).
+    ``EBY[u, u', v, v']``: BY top (u, to Y.b) and left (v, to BX.r).
+    """
+    c = np.conj
+    EL = _ein('ptlbx,ptlby->xy', L, c(L))
+    ER = _ein('ptxbr,ptybr->xy', Rn, c(Rn))
+    ETX = _ein('ptluv,ptlwz->uwvz', TX, c(TX))
+    ETY = _ein('ptvur,ptzwr->uwvz', TY, c(TY))
+    EBX = _ein('pulbv,pwlbz->uwvz', BX, c(BX))
+    EBY = _ein('puvbr,pwzbr->uwvz', BY, c(BY))
+    return EL, ER, ETX, ETY, EBX, EBY
+
+
+def metric(QX: np.ndarray, QY: np.ndarray, nbr):
+    """Bond metric ``g`` of Fig. 4(d,e) for isometries ``QX`` (legs p,t,l,b,a)
+    and ``QY`` (legs p,t,b,r,b) inside the nearest-neighbour cluster ``nbr =
+    [L, TX, BX, TY, BY, Rn]``.  Exact contraction of the double layer:
+
+    1. edge double tensors (Fig. 4(a,b));
+    2. the two parallel bonds: ``Etop[t t' T T'] = sum ETX[t t' v v'] ETY[T T' v v']``
+       and the same for the bottom pair;
+    3. double isometries dressed with the left/right edges (Fig. 4(c)):
+       ``Left[a a' t t' b b'] = sum_{p l l'} QX[p t l b a] EL[l l'] conj(QX[p t' l' b' a'])``
+       and ``Right`` likewise with ``ER``;
+    4. assembly (Fig. 4(d)): ``G[a a' b b'] = sum Left Etop Ebot Right``.
+
+    Returns ``g`` shaped ``(R^2, R^2)`` with rows ``(a', b')``, cols ``(a, b)``.
+    """
+    c = np.conj
+    EL, ER, ETX, ETY, EBX, EBY = edge_tensors(*nbr)
+    Etop = _ein('tsvw,TSvw->tsTS', ETX, ETY)
+    Ebot = _ein('bcvw,BCvw->bcBC', EBX, EBY)
+    QXe = _ein('ptlba,lm->ptmba', QX, EL)
+    Left = _ein('ptmba,psmcz->aztsbc', QXe, c(QX))
+    QYe = _ein('ptbra,rm->ptbma', QY, ER)
+    Right = _ein('ptbma,pscmz->aztsbc', QYe, c(QY))
+    # contract the top pair of X-side (t t') with Etop, then bottom (b b') with Ebot
+    L1 = _ein('aztsbc,tsTS->azTSbc', Left, Etop)
+    L2 = _ein('azTSbc,bcBC->azTSBC', L1, Ebot)
+    G = _ein('azTSBC,ywTSBC->azyw', L2, Right)   # [a, a', b, b']
+    R = QX.shape[-1]
+    return G.transpose(1, 3, 0, 2).reshape(R * R, R * R)
+
+
+def metric_fix(g: np.ndarray, clip: bool = True):
+    """Hermitise ``g`` and (``clip``) set negative eigenvalues to zero.
+
+    The exact metric is Hermitian and non-negative (abstract; Sec. II); this
+    removes the rounding (or reduced-precision) departures from both.
+    Statistics are taken on the input: relative anti-Hermitian part,
+    smallest/largest eigenvalue of the Hermitian part and the clipped mass.
+    """
+    nrm = np.linalg.norm(g)
+    herm_err = np.linalg.norm(g - g.conj().T) / nrm if nrm > 0 else 0.0
+    h = 0.5 * (g + g.conj().T)
+    lam, V = np.linalg.eigh(h)
+    stats = dict(herm_err=float(herm_err), lam_min=float(lam[0]), lam_max=float(lam[-1]),
+                 clipped=float(np.sum(-lam[lam < 0]) / max(np.sum(np.abs(lam)), 1e-300)))
+    if clip:
+        lam_c = np.maximum(lam, 0.0)
+        h = (V * lam_c[None, :]) @ V.conj().T
+    return h, stats
+
+
+# ---------------------------------------------------------------------------
+# Fit, Eqs. (2)-(5) and Fig. 5
+# ---------------------------------------------------------------------------
+
+def error(g, MX, MY, y):
+    """Eq. (2): ``eps = d^H g d`` with ``d = vec(MX MY^T) - y`` (evaluated directly)."""
+    d = (MX @ MY.T).reshape(-1) - y
+    return float(np.real(np.vdot(d, g @ d)))
+
+
+def _pinv_ladder(gs, Js, K, g, y, ladder, N):
+    """Eq. (4) with the tolerance chosen to minimise Eq. (2): for each ladder
+    value ``tau``, ``m = sum_{lam_i > tau lam_max} w_i (w_i^H J) / lam_i`` and
+    the error of ``K m`` is evaluated directly against ``y``.  The smallest error
+    wins; near-ties (``< TIE * N``) go to the larger tolerance."""
+    lam, W = np.linalg.eigh(gs)
+    lmax = lam[-1]
+    proj = W.conj().T @ Js
+    cands = []
+    for tau in ladder:
+        keep = lam > tau * lmax
+        m = W[:, keep] @ (proj[keep] / lam[keep])
+        d = K @ m - y
+        e = float(np.real(np.vdot(d, g @ d)))
+        cands.append((e, m, tau))
+    e_min = min(c[0] for c in cands)
+    # largest tolerance whose error is within TIE * N of the smallest
+    return max((c for c in cands if c[0] <= e_min + TIE * N), key=lambda c: c[2])
+
+
+def bond_fit(g, RX, RY, D, n_iter=20, conv_tol=None, ladder=TOL_LADDER, kappa=KAPPA):
+    """Optimise ``MX, MY`` (Eqs. (3)-(5)) against the metric ``g``.
+
+    Starts from the SVDU guess.  Each iteration is an X half-step and a Y
+    half-step.  Before the X half-step the pair is tilted (Fig. 5): SVD
+    ``MX MY^T = U S V^H``, ``MX = U S``, ``MY = conj(V)`` (isometric); then
+    ``MX = pinv(g_X) J_X`` with ``K_X = I_R (x) MY``, ``g_X = K_X^H g K_X``,
+    ``J_X = K_X^H g y`` (Fig. 5(b,c)).  The Y half-step mirrors it.  With
+    ``conv_tol`` the loop stops once an iteration lowers the error by no more
+    than ``conv_tol * N`` ("until convergence of eps", Eq. (5)).
+
+    Returns a dict with ``MX, MY`` (shape ``(R, Dn)``), ``P``, ``N``,
+    ``eps_svdu``, per-half-step ``eps`` and chosen ``tau``, ``Dn`` and the
+    number of iterations done.
+    """
+    R = RX.shape[0]
+    P, MX, MY, S0, Dn = svdu_guess(RX, RY, D, kappa)
+    y = P.reshape(-1)
+    N = float(np.real(np.vdot(y, g @ y)))
+    out = dict(P=P, N=N, Dn=Dn, S_svdu=S0)
+    if Dn == 0:
+        out.update(MX=MX, MY=MY, eps_svdu=0.0, eps=[], tau=[], iters=0)
+        return out
+    eps_svdu = error(g, MX, MY, y)
+    eps_hist, tau_hist = [], []
+    I_R = np.eye(R, dtype=g.dtype)
+    prev = eps_svdu
+    iters = 0
+    for _ in range(n_iter):
+        # X half-step: tilt so that MY is isometric
+        U, S, Vh = np.linalg.svd(MX @ MY.T)
+        MX = U[:, :Dn] * S[None, :Dn]
+        MY = Vh[:Dn, :].T.copy()
+        K = np.kron(I_R, MY)                       # [(a, b), (a', j)] = delta_{a a'} MY[b, j]
+        gX = K.conj().T @ g @ K
+        JX = K.conj().T @ (g @ y)
+        e, m, tau = _pinv_ladder(gX, JX, K, g, y, ladder, N)
+        MX = m.reshape(R, Dn)
+        eps_hist.append(e)
+        tau_hist.append(tau)
+        # Y half-step: tilt so that MX is isometric
+        U, S, Vh = np.linalg.svd(MX @ MY.T)
+        MX = U[:, :Dn].copy()
+        MY = Vh[:Dn, :].T * S[None, :Dn]
+        K = np.kron(MX, I_R)                       # [(a, b), (j, b')] = MX[a, j] delta_{b b'}
+        gY = K.conj().T @ g @ K
+        JY = K.conj().T @ (g @ y)
+        e, m, tau = _pinv_ladder(gY, JY, K, g, y, ladder, N)
+        MY = m.reshape(Dn, R).T
+        eps_hist.append(e)
+        tau_hist.append(tau)
+        iters += 1
+        if conv_tol is not None and prev - e <= conv_tol * N:
+            break
+        prev = e
+    out.update(MX=MX, MY=MY, eps_svdu=eps_svdu, eps=eps_hist, tau=tau_hist, iters=iters)
+    return out
+
+
+def balance(MX, MY, D, kappa=KAPPA):
+    """Fig. 5(d): SVD of the converged product, singular values normalised by
+    the largest, ``MX = U S^1/2``, ``MY = conj(V) S^1/2``; kept
+    ``Dk = min(D, #{S_i > kappa S_0})`` columns, zero-padded to ``D``."""
+    R = MX.shape[0]
+    dtype = np.result_type(MX, MY)
+    U, S, Vh = np.linalg.svd(MX @ MY.T)
+    Dk = 0 if S[0] <= 0 else int(min(D, np.count_nonzero(S > kappa * S[0])))
+    Sn = S[:Dk] / S[0] if Dk else S[:0]
+    sq = np.sqrt(Sn)
+    MXb = np.zeros((R, D), dtype=dtype)
+    MYb = np.zeros((R, D), dtype=dtype)
+    MXb[:, :Dk] = U[:, :Dk] * sq[None, :]
+    MYb[:, :Dk] = Vh[:Dk, :].T * sq[None, :]
+    Sfull = np.zeros(D)
+    Sfull[:Dk] = Sn
+    return MXb, MYb, Sfull, Dk
+
+
+def recombine(QX, QY, MXb, MYb):
+    """Fig. 2(e): ``X' = QX . MX`` (new leg = r), ``Y' = QY . MY`` (new leg = l)."""
+    p, D = QX.shape[0], QX.shape[1]
+    Xn = np.tensordot(QX, MXb, axes=([4], [0]))            # (p t l b r)
+    Yn = np.tensordot(QY, MYb, axes=([4], [0]))            # (p t b r l)
+    Yn = Yn.transpose(0, 1, 4, 2, 3)                       # (p t l b r)
+    return Xn, Yn
+
+
+# ---------------------------------------------------------------------------
+# One bond update and the Trotter step
+# ---------------------------------------------------------------------------
+
+def bond_update(X, Y, nbr, GA, GB, D, d=2, n_iter=20, conv_tol=None, clip=True,
+                ladder=TOL_LADDER, kappa=KAPPA, metric_override=None):
+    """Full NTU update of the bond ``X.r - Y.l`` (Figs. 2-5).
+
+    ``nbr = [L, TX, BX, TY, BY, Rn]``.  ``metric_override`` replaces ``g`` (used
+    by pins that feed a known metric).  Returns new ``X', Y'`` and diagnostics.
+    """
+    QX, RX = reduce_site(X, GA, 'X', d, kappa)
+    QY, RY = reduce_site(Y, GB, 'Y', d, kappa)
+    if metric_override is None:
+        g_raw = metric(QX, QY, nbr)
+    else:
+        g_raw = metric_override
+    g, mstats = metric_fix(g_raw, clip=clip)
+    fit = bond_fit(g, RX, RY, D, n_iter=n_iter, conv_tol=conv_tol, ladder=ladder, kappa=kappa)
+    if fit['Dn'] == 0:
+        MXb = np.zeros((RX.shape[0], D), dtype=QX.dtype)
+        MYb = MXb.copy()
+        S, Dk = np.zeros(D), 0
+    else:
+        MXb, MYb, S, Dk = balance(fit['MX'], fit['MY'], D, kappa)
+    Xn, Yn = recombine(QX, QY, MXb, MYb)
+    eps = fit['eps'][-1] if fit['eps'] else fit.get('eps_svdu', 0.0)
+    info = dict(QX=QX, QY=QY, RX=RX, RY=RY, g_raw=g_raw, g=g, metric_stats=mstats,
+                S=S, Dk=Dk, eps_final=eps, delta=eps / fit['N'] if fit['N'] > 0 else 0.0, **fit)
+    return Xn, Yn, info
+
+
+def rot_cw(T):
+    """Rotate a site tensor by 90 degrees clockwise: new (t, l, b, r) = old (l, b, r, t)."""
+    return T.transpose(0, 2, 3, 4, 1)
+
+
+def rot_ccw(T):
+    """Inverse of :func:`rot_cw`."""
+    return T.transpose(0, 4, 1, 2, 3)
+
+
+def _cluster(X_is_A, A, B):
+    """Neighbours ``[L, TX, BX, TY, BY, Rn]`` of the canonical bond on the
+    two-site checkerboard: X's neighbours are of Y's type and vice versa."""
+    X, Y = (A, B) if X_is_A else (B, A)
+    return X, Y, [Y, Y, Y, X, X, X]
+
+
+BONDS = ('H1', 'H2', 'V1', 'V2')
+
+
+def trotter_step(A, B, gate_factors, D, d=2, n_iter=20, conv_tol=None, clip=True,
+                 order=BONDS):
+    """One first-order Trotter step: NTU updates of the four inequivalent bonds
+    of the checkerboard in ``order`` (default H1, H2, V1, V2).
+
+    H1: X=A, Y=B (A.r - B.l); H2: X=B, Y=A.  V1/V2 are H1/H2 after rotating
+    both tensors clockwise (A.t - B.b and B.t - A.b).  ``gate_factors[bond] =
+    (GA, GB)``.  Returns new ``A, B`` and the per-bond diagnostics.
+    """
+    infos = {}
+    for bond in order:
+        GA, GB = gate_factors[bond]
+        vertical = bond[0] == 'V'
+        a, b = (rot_cw(A), rot_cw(B)) if vertical else (A, B)
+        X, Y, nbr = _cluster(bond[1] == '1', a, b)
+        Xn, Yn, info = bond_update(X, Y, nbr, GA, GB, D, d=d, n_iter=n_iter,
+                                   conv_tol=conv_tol, clip=clip)
+        an, bn = (Xn, Yn) if bond[1] == '1' else (Yn, Xn)
+        if vertical:
+            an, bn = rot_ccw(an), rot_ccw(bn)
+        A, B = an, bn
+        infos[bond] = info
+    return A, B, infos
+
+
+# ---------------------------------------------------------------------------
+# Cluster estimator of observables (used to compare evolved states)
+# ---------------------------------------------------------------------------
+
+def bond_density_matrix(X, Y, nbr, d=2):
+    """Two-site reduced density matrix of the canonical bond from the same
+    eight-site cluster as the metric, with the bond contracted, the physical
+    legs of X and Y open, their ancillas traced and every other leg closed ket
+    with bra.  Returns ``rho[(s1 s2), (s1' s2')]`` normalised to unit trace."""
+    c = np.conj
+    p, D = X.shape[0], X.shape[1]
+    na = p // d
+    EL, ER, ETX, ETY, EBX, EBY = edge_tensors(*nbr)
+    Etop = _ein('tsvw,TSvw->tsTS', ETX, ETY)
+    Ebot = _ein('bcvw,BCvw->bcBC', EBX, EBY)
+    X6 = X.reshape(d, na, D, D, D, D)
+    Y6 = Y.reshape(d, na, D, D, D, D)
+    # Left with physical open: [s, s', a(=X.r), a', t, t', b, b']
+    X6e = _ein('xqtlba,lm->xqtmba', X6, EL)
+    Lf = _ein('xqtmba,yqsmcz->xyaztsbc', X6e, c(X6))
+    Y6e = _ein('xqtaur,rm->xqtaum', Y6, ER)
+    Rf = _ein('xqtaum,yqszvm->xyaztsuv', Y6e, c(Y6))
+    L1 = _ein('xyaztsbc,tsTS->xyazTSbc', Lf, Etop)
+    L2 = _ein('xyazTSbc,bcBC->xyazTSBC', L1, Ebot)
+    rho = _ein('xyazTSBC,uvazTSBC->xuyv', L2, Rf)     # [s1, s2, s1', s2']
+    rho = rho.reshape(d * d, d * d)
+    return rho / np.trace(rho)
+
+
+def observables(A, B, hx, d=2, hz=0.0):
+    """Energy per site ``e = 1/2 sum_bonds <h_b>`` and mean ``<sigma^x>`` from
+    the cluster density matrices of the four bonds (``h_b`` as in the inputs
+    module: ``-ZZ - hx/4 (XI + IX) - hz/4 (ZI + IZ)``)."""
+    X_ = np.array([[0, 1], [1, 0]], dtype=complex)
+    Z_ = np.diag([1.0, -1.0]).astype(complex)
+    I_ = np.eye(2, dtype=complex)
+    hb = (-np.kron(Z_, Z_) - 0.25 * hx * (np.kron(X_, I_) + np.kron(I_, X_))
+          - 0.25 * hz * (np.kron(Z_, I_) + np.kron(I_, Z_)))
+    xo = 0.5 * (np.kron(X_, I_) + np.kron(I_, X_))
+    e, sx = 0.0, 0.0
+    for bond in BONDS:
+        vertical = bond[0] == 'V'
+        a, b = (rot_cw(A), rot_cw(B)) if vertical else (A, B)
+        X, Y, nbr = _cluster(bond[1] == '1', a, b)
+        rho = bond_density_matrix(X, Y, nbr, d)
+        e += 0.5 * float(np.real(np.trace(rho @ hb)))
+        sx += 0.25 * float(np.real(np.trace(rho @ xo)))
+    return e, sx
