@@ -251,6 +251,19 @@ void ntu_step_opts_default(ntu_step_opts* o);
 ntu_status ntu_trotter_step(ntu_ctx* ctx, int batch, int D, void* A, void* B,
                             const void* gate_factors, const ntu_step_opts* opts, double* stats);
 
+/*
+ * Event profiler (measurement support, not part of the method).  When enabled,
+ * the context records a HIP event on its stream before and after every
+ * kernel class it launches (events are created here, never inside calls).
+ * ntu_profile_read synchronises on the last event, fills ms[k] (summed
+ * milliseconds) and count[k] (number of timed launches) for the first n
+ * kernel classes, clears the record and returns the number of classes.
+ * ntu_profile_kind_name(k) names class k (static string).
+ */
+ntu_status ntu_profile_enable(ntu_ctx* ctx, int on);
+int ntu_profile_read(ntu_ctx* ctx, double* ms, int* count, int n);
+const char* ntu_profile_kind_name(int kind);
+
 #ifdef __cplusplus
 }
 #endif

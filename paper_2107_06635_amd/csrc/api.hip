@@ -1,0 +1,460 @@
+// C ABI of libntu (declared in include/ntu.h): argument validation, the
+// context's workspace, and the orchestration of a Trotter step.  Every
+// numerical step runs in the HIP kernels of this library.
+#include <string.h>
+#include <string>
+#include <vector>
+#include <algorithm>
+#include "ntu.h"
+#include "kernels.h"
+
+namespace {
+
+struct Persist {
+  // per-item persistent buffers of the Trotter step (compute type elements)
+  long long QX, QY, RX, RY, g, MX, MY, rA, rB, GA, GB;
+};
+
+}  // namespace
+
+struct ntu_ctx {
+  int device = 0;
+  int dtype = NTU_C128;
+  bool cplx = true;
+  int d = 2, na = 1, rg = 2, max_D = 1, max_batch = 1;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;          // scratch of one call
+  size_t ws_bytes = 0;
+  char* step = nullptr;        // buffers of the Trotter step
+  size_t step_bytes = 0;
+  std::string err;
+  // event profiler (ntu_profile_enable)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_kind;
+  int prof_n = 0;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+ntu_status fail(ntu_ctx* c, ntu_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_err = msg;
+  return s;
+}
+
+ntu_status hip_fail(ntu_ctx* c, hipError_t e, const char* where) {
+  return fail(c, NTU_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t elem_size(const ntu_ctx* c) { return c->cplx ? 16 : 8; }
+int pdim(const ntu_ctx* c) { return c->d * c->na; }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+ntu_status check_common(ntu_ctx* c, int batch, int D) {
+  if (!c) return NTU_ERR_ARG;
+  c->err.clear();
+  if (batch < 0) return fail(c, NTU_ERR_ARG, "batch must be >= 0");
+  if (batch > c->max_batch) return fail(c, NTU_ERR_WORKSPACE, "batch exceeds the context's max_batch");
+  if (D < 1 || D > c->max_D) return fail(c, NTU_ERR_SHAPE, "D outside [1, max_D] of the context");
+  return NTU_OK;
+}
+
+size_t scratch_bytes(bool cplx, int batch, int p, int D, int rg) {
+  const int R = D * rg;
+  size_t a = 0;
+  for (int prec = NTU_PREC_F64; prec <= NTU_PREC_BF16X6; ++prec)
+    a = std::max(a, ntu::env_workspace_bytes(cplx, prec, batch, p, D, R));
+  size_t b = ntu::fix_workspace_bytes(cplx, batch, R * R);
+  size_t f = ntu::fit_workspace_bytes(cplx, batch, D, R);
+  return std::max(a, std::max(b, f));
+}
+
+Persist persist_layout(int p, int D, int rg, int d) {
+  const long long R = (long long)D * rg, D3 = (long long)D * D * D;
+  Persist s;
+  long long o = 0;
+  s.QX = o; o += p * D3 * R;
+  s.QY = o; o += p * D3 * R;
+  s.RX = o; o += R * R;
+  s.RY = o; o += R * R;
+  s.g = o; o += R * R * R * R;
+  s.MX = o; o += R * D;
+  s.MY = o; o += R * D;
+  s.rA = o; o += p * D3 * D;
+  s.rB = o; o += p * D3 * D;
+  s.GA = o; o += (long long)d * d * rg;
+  s.GB = o; o += (long long)d * d * rg;
+  (void)o;
+  return s;
+}
+long long persist_elems(int p, int D, int rg, int d) {
+  const long long R = (long long)D * rg, D3 = (long long)D * D * D;
+  return 2 * p * D3 * R + 2 * R * R + R * R * R * R + 2 * R * D + 2 * p * D3 * D + 2LL * d * d * rg;
+}
+
+const int PROF_CAP = 1 << 15;
+
+void prof_mark(void* vc, int kind, int phase) {
+  ntu_ctx* c = (ntu_ctx*)vc;
+  if (!c->prof_on || c->prof_n >= PROF_CAP) return;
+  if (hipEventRecord(c->prof_ev[c->prof_n], c->stream) != hipSuccess) return;
+  c->prof_kind[c->prof_n] = kind * 2 + phase;
+  ++c->prof_n;
+}
+
+ntu::ProfHook hook(ntu_ctx* c) {
+  ntu::ProfHook h;
+  h.mark = c->prof_on ? prof_mark : nullptr;
+  h.ctx = c;
+  return h;
+}
+
+const char* const PROF_NAMES[ntu::PK_COUNT] = {
+    "rotate", "gate_split", "reduce_qr", "env_edges", "env_qprep", "env_left_right", "env_e4", "env_e5",
+    "env_e6", "env_e6_reduce", "metric_herm", "metric_clip", "bond_fit", "recombine"};
+
+ntu::FitParams fit_params(const ntu_fit_opts* o) {
+  ntu::FitParams fp{};
+  fp.n_iter = o->n_iter;
+  fp.early_stop = o->early_stop;
+  fp.conv_tol = o->conv_tol;
+  fp.kappa = o->kappa;
+  fp.tie = o->tie;
+  fp.n_tol = o->n_tol;
+  for (int i = 0; i < 16; ++i) fp.tol[i] = o->tol[i];
+  return fp;
+}
+
+ntu_status check_fit_opts(ntu_ctx* c, const ntu_fit_opts* o) {
+  if (!o) return fail(c, NTU_ERR_ARG, "fit options are NULL");
+  if (o->n_iter < 0 || o->n_iter > 1000) return fail(c, NTU_ERR_ARG, "n_iter outside [0, 1000]");
+  if (o->n_tol < 1 || o->n_tol > 16) return fail(c, NTU_ERR_ARG, "n_tol outside [1, 16]");
+  for (int i = 1; i < o->n_tol; ++i)
+    if (!(o->tol[i] > o->tol[i - 1])) return fail(c, NTU_ERR_ARG, "tolerance ladder must ascend");
+  if (!(o->tol[0] > 0)) return fail(c, NTU_ERR_ARG, "tolerances must be positive");
+  if (!(o->kappa >= 0 && o->kappa < 1)) return fail(c, NTU_ERR_ARG, "kappa outside [0, 1)");
+  return NTU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ntu_version(void) { return "libntu 0.1 (gfx950)"; }
+
+void ntu_fit_opts_default(ntu_fit_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->n_iter = 20;
+  o->early_stop = 0;
+  o->conv_tol = 1e-12;
+  o->kappa = 1e-10;
+  o->n_tol = 8;
+  for (int i = 0; i < 8; ++i) o->tol[i] = 1e-15 * pow(10.0, i);
+  o->tie = 1e-15;
+}
+
+void ntu_step_opts_default(ntu_step_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->n_bonds = 4;
+  o->order[0] = NTU_BOND_H1;
+  o->order[1] = NTU_BOND_H2;
+  o->order[2] = NTU_BOND_V1;
+  o->order[3] = NTU_BOND_V2;
+  o->precision = NTU_PREC_F64;
+  o->fix_mode = NTU_FIX_HERM_CLIP;
+  ntu_fit_opts_default(&o->fit);
+}
+
+ntu_status ntu_ctx_create(ntu_ctx** out, int device, int dtype, int d, int d_anc, int r_g, int max_D,
+                          int max_batch) {
+  if (!out) return fail(nullptr, NTU_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (dtype != NTU_F64 && dtype != NTU_C128) return fail(nullptr, NTU_ERR_DTYPE, "compute dtype must be F64 or C128");
+  if (d < 1 || d > 4 || d_anc < 1 || d_anc > 4) return fail(nullptr, NTU_ERR_SHAPE, "d, d_anc must be in [1, 4]");
+  if (r_g < 1 || r_g > d * d) return fail(nullptr, NTU_ERR_SHAPE, "r_g must be in [1, d^2]");
+  if (max_D < 1 || max_D * r_g > 20) return fail(nullptr, NTU_ERR_SHAPE, "max_D * r_g must be in [1, 20]");
+  if (max_batch < 1) return fail(nullptr, NTU_ERR_ARG, "max_batch must be >= 1");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(nullptr, NTU_ERR_HIP, "no such HIP device");
+  ntu_ctx* c = new ntu_ctx();
+  c->device = device;
+  c->dtype = dtype;
+  c->cplx = dtype == NTU_C128;
+  c->d = d; c->na = d_anc; c->rg = r_g; c->max_D = max_D; c->max_batch = max_batch;
+  DeviceGuard guard(device);
+  const int p = d * d_anc;
+  size_t sb = 0;
+  for (int D = 1; D <= max_D; ++D) sb = std::max(sb, scratch_bytes(c->cplx, max_batch, p, D, r_g));
+  c->ws_bytes = sb;
+  c->step_bytes = (size_t)persist_elems(p, max_D, r_g, d) * elem_size(c) * max_batch + 256;
+  hipError_t e = hipMalloc((void**)&c->ws, c->ws_bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->step, c->step_bytes);
+  if (e != hipSuccess) {
+    if (c->ws) (void)hipFree(c->ws);
+    delete c;
+    return fail(nullptr, NTU_ERR_HIP, std::string("workspace allocation failed: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return NTU_OK;
+}
+
+ntu_status ntu_ctx_destroy(ntu_ctx* c) {
+  if (!c) return NTU_ERR_ARG;
+  DeviceGuard guard(c->device);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->step) (void)hipFree(c->step);
+  for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
+  delete c;
+  return NTU_OK;
+}
+
+ntu_status ntu_set_stream(ntu_ctx* c, void* stream) {
+  if (!c) return NTU_ERR_ARG;
+  c->stream = (hipStream_t)stream;
+  return NTU_OK;
+}
+
+const char* ntu_last_error(const ntu_ctx* c) {
+  if (!c) return g_create_err.c_str();
+  return c->err.c_str();
+}
+
+size_t ntu_workspace_bytes(const ntu_ctx* c) { return c ? c->ws_bytes + c->step_bytes : 0; }
+
+ntu_status ntu_gate_split(ntu_ctx* c, int batch, const void* gate, void* GA, void* GB, double* sigma) {
+  ntu_status s = check_common(c, batch, 1);
+  if (s) return s;
+  if (batch == 0) return NTU_OK;
+  if (!gate || !GA || !GB || !sigma) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  DeviceGuard guard(c->device);
+  const ntu::ProfHook ph = hook(c);
+  ph(ntu::PK_GATE, 0);
+  hipError_t e = ntu::launch_gate_split(c->cplx, batch, c->d, c->rg, gate, GA, GB, sigma, c->stream);
+  ph(ntu::PK_GATE, 1);
+  return e == hipSuccess ? NTU_OK : hip_fail(c, e, "gate_split");
+}
+
+ntu_status ntu_reduce_qr(ntu_ctx* c, int batch, int D, const void* site, int site_dtype, const void* gf,
+                         int side, void* Q, void* R) {
+  ntu_status s = check_common(c, batch, D);
+  if (s) return s;
+  if (side != 0 && side != 1) return fail(c, NTU_ERR_ARG, "side must be 0 (X) or 1 (Y)");
+  bool ok_dtype = c->cplx ? (site_dtype == NTU_C128 || site_dtype == NTU_C64) : site_dtype == NTU_F64;
+  if (!ok_dtype) return fail(c, NTU_ERR_DTYPE, "site dtype does not match the context");
+  if (batch == 0) return NTU_OK;
+  if (!site || !gf || !Q || !R) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  DeviceGuard guard(c->device);
+  const ntu::ProfHook ph = hook(c);
+  ph(ntu::PK_REDUCE, 0);
+  hipError_t e = ntu::launch_reduce_qr(c->cplx, site_dtype, batch, c->d, c->na, D, c->rg, site, gf,
+                                       (long long)c->d * c->d * c->rg, side, Q, R, 1e-10, c->stream);
+  ph(ntu::PK_REDUCE, 1);
+  return e == hipSuccess ? NTU_OK : hip_fail(c, e, "reduce_qr");
+}
+
+ntu_status ntu_env_contract(ntu_ctx* c, int batch, int D, const void* QX, const void* QY, const void* const nbr[6],
+                            int precision, void* g) {
+  ntu_status s = check_common(c, batch, D);
+  if (s) return s;
+  if (precision < NTU_PREC_F64 || precision > NTU_PREC_BF16X6) return fail(c, NTU_ERR_ARG, "unknown precision");
+  if (batch == 0) return NTU_OK;
+  if (!QX || !QY || !nbr || !g) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  for (int i = 0; i < 6; ++i)
+    if (!nbr[i]) return fail(c, NTU_ERR_ARG, "NULL neighbour pointer");
+  DeviceGuard guard(c->device);
+  hipError_t e = ntu::launch_env_contract(c->cplx, precision, batch, pdim(c), D, D * c->rg, QX, QY, nbr, g, c->ws,
+                                          c->ws_bytes, c->stream, hook(c));
+  if (e == hipErrorNotSupported) return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
+  return e == hipSuccess ? NTU_OK : hip_fail(c, e, "env_contract");
+}
+
+ntu_status ntu_metric_fix(ntu_ctx* c, int batch, int D, void* g, int mode, double* stats) {
+  ntu_status s = check_common(c, batch, D);
+  if (s) return s;
+  if (mode != NTU_FIX_HERM && mode != NTU_FIX_HERM_CLIP) return fail(c, NTU_ERR_ARG, "unknown mode");
+  if (batch == 0) return NTU_OK;
+  if (!g) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  DeviceGuard guard(c->device);
+  const int R = D * c->rg;
+  hipError_t e = ntu::launch_metric_fix(c->cplx, batch, R * R, g, mode, stats, 8, c->ws, c->stream, hook(c));
+  return e == hipSuccess ? NTU_OK : hip_fail(c, e, "metric_fix");
+}
+
+ntu_status ntu_bond_fit(ntu_ctx* c, int batch, int D, const void* g, const void* RX, const void* RY,
+                        const ntu_fit_opts* opts, void* MX, void* MY, double* stats) {
+  ntu_status s = check_common(c, batch, D);
+  if (s) return s;
+  if ((s = check_fit_opts(c, opts))) return s;
+  if (batch == 0) return NTU_OK;
+  if (!g || !RX || !RY || !MX || !MY) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  DeviceGuard guard(c->device);
+  const int R = D * c->rg;
+  const ntu::ProfHook ph = hook(c);
+  ph(ntu::PK_FIT, 0);
+  hipError_t e = ntu::launch_bond_fit(c->cplx, batch, D, R, g, RX, RY, fit_params(opts), MX, MY, stats,
+                                      ntu::fit_stats_len(opts->n_iter, D), c->ws, c->stream);
+  ph(ntu::PK_FIT, 1);
+  return e == hipSuccess ? NTU_OK : hip_fail(c, e, "bond_fit");
+}
+
+ntu_status ntu_recombine(ntu_ctx* c, int batch, int D, const void* QX, const void* QY, const void* MX,
+                         const void* MY, void* Xn, void* Yn) {
+  ntu_status s = check_common(c, batch, D);
+  if (s) return s;
+  if (batch == 0) return NTU_OK;
+  if (!QX || !QY || !MX || !MY || !Xn || !Yn) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  DeviceGuard guard(c->device);
+  const ntu::ProfHook ph = hook(c);
+  ph(ntu::PK_RECOMB, 0);
+  hipError_t e = ntu::launch_recombine(c->cplx, batch, pdim(c), D, D * c->rg, QX, QY, MX, MY, Xn, Yn, 0, c->stream);
+  ph(ntu::PK_RECOMB, 1);
+  return e == hipSuccess ? NTU_OK : hip_fail(c, e, "recombine");
+}
+
+ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, const void* gate_factors,
+                            const ntu_step_opts* opts, double* stats) {
+  ntu_status s = check_common(c, batch, D);
+  if (s) return s;
+  if (!opts) return fail(c, NTU_ERR_ARG, "step options are NULL");
+  if (opts->n_bonds < 0 || opts->n_bonds > 8) return fail(c, NTU_ERR_ARG, "n_bonds outside [0, 8]");
+  for (int i = 0; i < opts->n_bonds; ++i)
+    if (opts->order[i] < 0 || opts->order[i] > 3) return fail(c, NTU_ERR_ARG, "unknown bond in order");
+  if (opts->precision < NTU_PREC_F64 || opts->precision > NTU_PREC_BF16X6) return fail(c, NTU_ERR_ARG, "unknown precision");
+  if (opts->fix_mode != NTU_FIX_HERM && opts->fix_mode != NTU_FIX_HERM_CLIP) return fail(c, NTU_ERR_ARG, "unknown fix mode");
+  if ((s = check_fit_opts(c, &opts->fit))) return s;
+  if (batch == 0 || opts->n_bonds == 0) return NTU_OK;
+  if (!A || !B || !gate_factors) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  DeviceGuard guard(c->device);
+  const bool cp = c->cplx;
+  const int p = pdim(c), R = D * c->rg;
+  const size_t el = elem_size(c);
+  const long long site = (long long)p * D * D * D * D;
+  const long long pe = persist_elems(p, D, c->rg, c->d);
+  const Persist L = persist_layout(p, D, c->rg, c->d);
+  // persistent buffers: item stride pe elements, laid out per buffer kind
+  auto buf = [&](long long off) -> char* { return c->step + (size_t)off * el * batch; };
+  char* QX = buf(L.QX);
+  char* QY = buf(L.QY);
+  char* RX = buf(L.RX);
+  char* RY = buf(L.RY);
+  char* G = buf(L.g);
+  char* MX = buf(L.MX);
+  char* MY = buf(L.MY);
+  char* rA = buf(L.rA);
+  char* rB = buf(L.rB);
+  (void)pe;
+  const long long gfs = (long long)c->d * c->d * c->rg;  // elements of one factor
+  const long long gf_item = 8 * gfs;                      // 4 bonds x (GA, GB)
+  const int fl = ntu::fit_stats_len(opts->fit.n_iter, D);
+  const int sl = 8 + fl;
+  const long long s_item = (long long)opts->n_bonds * sl;
+  const ntu::FitParams fp = fit_params(&opts->fit);
+  const ntu::ProfHook ph = hook(c);
+  hipError_t e = hipSuccess;
+#define NTU_STEP(x, what) do { e = (x); if (e != hipSuccess) return hip_fail(c, e, what); } while (0)
+  for (int bi = 0; bi < opts->n_bonds; ++bi) {
+    const int bond = opts->order[bi];
+    const bool vertical = bond >= 2, x_is_a = (bond == NTU_BOND_H1 || bond == NTU_BOND_V1);
+    char* a = (char*)A;
+    char* b = (char*)B;
+    if (vertical) {
+      ph(ntu::PK_ROTATE, 0);
+      NTU_STEP(ntu::launch_rotate_cw(cp, batch, p, D, A, rA, c->stream), "rotate");
+      NTU_STEP(ntu::launch_rotate_cw(cp, batch, p, D, B, rB, c->stream), "rotate");
+      ph(ntu::PK_ROTATE, 1);
+      a = rA;
+      b = rB;
+    }
+    char* X = x_is_a ? a : b;
+    char* Y = x_is_a ? b : a;
+    const char* gA = (const char*)gate_factors + (size_t)(bond * 2 + 0) * gfs * el;
+    const char* gB = (const char*)gate_factors + (size_t)(bond * 2 + 1) * gfs * el;
+    ph(ntu::PK_REDUCE, 0);
+    NTU_STEP(ntu::launch_reduce_qr(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, gf_item, 0, QX, RX, opts->fit.kappa,
+                                   c->stream), "reduce_qr X");
+    NTU_STEP(ntu::launch_reduce_qr(cp, c->dtype, batch, c->d, c->na, D, c->rg, Y, gB, gf_item, 1, QY, RY, opts->fit.kappa,
+                                   c->stream), "reduce_qr Y");
+    ph(ntu::PK_REDUCE, 1);
+    const void* nbr[6] = {Y, Y, Y, X, X, X};
+    e = ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, QX, QY, nbr, G, c->ws, c->ws_bytes, c->stream, ph);
+    if (e == hipErrorNotSupported) return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
+    if (e != hipSuccess) return hip_fail(c, e, "env_contract");
+    double* sb = stats ? stats + (size_t)bi * sl : nullptr;
+    NTU_STEP(ntu::launch_metric_fix(cp, batch, R * R, G, opts->fix_mode, sb, (int)s_item, c->ws, c->stream, ph),
+             "metric_fix");
+    ph(ntu::PK_FIT, 0);
+    NTU_STEP(ntu::launch_bond_fit(cp, batch, D, R, G, RX, RY, fp, MX, MY, sb ? sb + 8 : nullptr, (int)s_item, c->ws,
+                                  c->stream), "bond_fit");
+    ph(ntu::PK_FIT, 1);
+    // new X -> (A or B), new Y -> the other, rotated back for vertical bonds
+    void* outX = x_is_a ? A : B;
+    void* outY = x_is_a ? B : A;
+    ph(ntu::PK_RECOMB, 0);
+    NTU_STEP(ntu::launch_recombine(cp, batch, p, D, R, QX, QY, MX, MY, outX, outY, vertical ? 1 : 0, c->stream),
+             "recombine");
+    ph(ntu::PK_RECOMB, 1);
+  }
+#undef NTU_STEP
+  (void)site;
+  return NTU_OK;
+}
+
+ntu_status ntu_profile_enable(ntu_ctx* c, int on) {
+  if (!c) return NTU_ERR_ARG;
+  DeviceGuard guard(c->device);
+  if (on && c->prof_ev.empty()) {
+    c->prof_ev.resize(PROF_CAP);
+    c->prof_kind.resize(PROF_CAP);
+    for (int i = 0; i < PROF_CAP; ++i) {
+      hipError_t e = hipEventCreate(&c->prof_ev[i]);
+      if (e != hipSuccess) return hip_fail(c, e, "profile events");
+    }
+  }
+  c->prof_on = on != 0;
+  c->prof_n = 0;
+  return NTU_OK;
+}
+
+int ntu_profile_read(ntu_ctx* c, double* ms, int* count, int n) {
+  if (!c || n < 0) return NTU_ERR_ARG;
+  DeviceGuard guard(c->device);
+  for (int k = 0; k < n; ++k) { if (ms) ms[k] = 0.0; if (count) count[k] = 0; }
+  if (c->prof_n > 0) (void)hipEventSynchronize(c->prof_ev[c->prof_n - 1]);
+  int open_idx[ntu::PK_COUNT];
+  for (int k = 0; k < ntu::PK_COUNT; ++k) open_idx[k] = -1;
+  for (int i = 0; i < c->prof_n; ++i) {
+    int kind = c->prof_kind[i] / 2, phase = c->prof_kind[i] % 2;
+    if (phase == 0) { open_idx[kind] = i; continue; }
+    if (open_idx[kind] < 0) continue;
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, c->prof_ev[open_idx[kind]], c->prof_ev[i]) == hipSuccess && kind < n) {
+      if (ms) ms[kind] += t;
+      if (count) count[kind] += 1;
+    }
+    open_idx[kind] = -1;
+  }
+  c->prof_n = 0;
+  return ntu::PK_COUNT;
+}
+
+const char* ntu_profile_kind_name(int kind) {
+  return (kind >= 0 && kind < ntu::PK_COUNT) ? PROF_NAMES[kind] : "";
+}
+
+}  // extern "C"

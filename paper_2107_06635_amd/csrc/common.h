@@ -1,0 +1,137 @@
+// Device helpers shared by the libntu kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#define NTU_DEV __device__ __forceinline__
+#define NTU_HD __host__ __device__ __forceinline__
+
+// ---------------------------------------------------------------------------
+// scalar types: double (real path) and cd (complex, interleaved re/im)
+// ---------------------------------------------------------------------------
+struct cd {
+  double x, y;
+};
+
+NTU_HD cd make_cd(double a, double b) { return cd{a, b}; }
+NTU_HD cd operator+(cd a, cd b) { return cd{a.x + b.x, a.y + b.y}; }
+NTU_HD cd operator-(cd a, cd b) { return cd{a.x - b.x, a.y - b.y}; }
+NTU_HD cd operator-(cd a) { return cd{-a.x, -a.y}; }
+NTU_HD cd operator*(cd a, cd b) { return cd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+NTU_HD cd operator*(double s, cd a) { return cd{s * a.x, s * a.y}; }
+NTU_HD cd operator*(cd a, double s) { return cd{s * a.x, s * a.y}; }
+NTU_HD cd& operator+=(cd& a, cd b) { a.x += b.x; a.y += b.y; return a; }
+NTU_HD cd& operator-=(cd& a, cd b) { a.x -= b.x; a.y -= b.y; return a; }
+
+NTU_HD double conjv(double a) { return a; }
+NTU_HD cd conjv(cd a) { return cd{a.x, -a.y}; }
+NTU_HD double rev(double a) { return a; }
+NTU_HD double rev(cd a) { return a.x; }
+NTU_HD double imv(double) { return 0.0; }
+NTU_HD double imv(cd a) { return a.y; }
+NTU_HD double abs2(double a) { return a * a; }
+NTU_HD double abs2(cd a) { return a.x * a.x + a.y * a.y; }
+NTU_HD double absv(double a) { return fabs(a); }
+NTU_HD double absv(cd a) { return hypot(a.x, a.y); }
+// conj(a) * b
+NTU_HD double cmul(double a, double b) { return a * b; }
+NTU_HD cd cmul(cd a, cd b) { return cd{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x}; }
+// a * conj(b)
+NTU_HD double mulc(double a, double b) { return a * b; }
+NTU_HD cd mulc(cd a, cd b) { return cd{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }
+
+template <class T> NTU_HD T zerov();
+template <> NTU_HD double zerov<double>() { return 0.0; }
+template <> NTU_HD cd zerov<cd>() { return cd{0.0, 0.0}; }
+template <class T> NTU_HD T realv(double a);
+template <> NTU_HD double realv<double>(double a) { return a; }
+template <> NTU_HD cd realv<cd>(double a) { return cd{a, 0.0}; }
+// a / |a| (1 for a == 0)
+NTU_HD double phasev(double a) { return a < 0 ? -1.0 : 1.0; }
+NTU_HD cd phasev(cd a) {
+  double m = hypot(a.x, a.y);
+  return m > 0 ? cd{a.x / m, a.y / m} : cd{1.0, 0.0};
+}
+NTU_HD bool finitev(double a) { return isfinite(a); }
+NTU_HD bool finitev(cd a) { return isfinite(a.x) && isfinite(a.y); }
+
+template <class T> struct is_cplx { static constexpr bool value = false; };
+template <> struct is_cplx<cd> { static constexpr bool value = true; };
+
+// ---------------------------------------------------------------------------
+// wave / block reductions (wave64)
+// ---------------------------------------------------------------------------
+NTU_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+NTU_DEV double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+NTU_DEV cd wave_sum(cd v) { return cd{wave_sum(v.x), wave_sum(v.y)}; }
+
+// Sum of v over the block; every thread gets the result.  red: >= 64 doubles
+// of shared memory.  Contains two barriers.
+NTU_DEV double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+NTU_DEV double block_max(double v, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = wave_max(v);
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = -INFINITY;
+  for (int i = 0; i < nw; ++i) s = fmax(s, red[i]);
+  return s;
+}
+
+// Sums n values per thread (vals, in registers) over the block into out[0..n)
+// (shared memory, visible to all threads on return).  red: >= 16*64 doubles.
+// n <= 64.  Uses doubles; complex callers pass re/im interleaved.
+NTU_DEV void block_sum_vec(const double* vals, int n, double* red, double* out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  for (int i = 0; i < n; ++i) {
+    double v = wave_sum(vals[i]);
+    if (lane == 0) red[w * 64 + i] = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nw; ++k) s += red[k * 64 + i];
+    out[i] = s;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// three-level index maps: i -> (i0, i1, i2) with i2 fastest
+// ---------------------------------------------------------------------------
+struct Idx3 {
+  int n1, n2;            // sizes of the two inner levels
+  long long s0, s1, s2;  // element strides of the three levels
+};
+NTU_HD Idx3 idx1(long long s) { return Idx3{1, 1, s, 0, 0}; }
+NTU_HD Idx3 idx2(int n_in, long long s_out, long long s_in) { return Idx3{1, n_in, s_out, 0, s_in}; }
+NTU_HD Idx3 idx3(int n1, int n2, long long s0, long long s1, long long s2) {
+  return Idx3{n1, n2, s0, s1, s2};
+}
+NTU_HD long long idx_off(const Idx3& x, long long i) {
+  long long i2 = i % x.n2;
+  long long t = i / x.n2;
+  long long i1 = t % x.n1;
+  long long i0 = t / x.n1;
+  return i0 * x.s0 + i1 * x.s1 + i2 * x.s2;
+}

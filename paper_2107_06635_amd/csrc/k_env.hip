@@ -1,0 +1,291 @@
+// Environment contraction of the nearest-neighbour cluster into the bond
+// metric g (Fig. 4): edge double tensors, the two parallel-bond transfers,
+// dressed double isometries ("Left", "Right") and the assembly.
+//
+// Layouts (canonical frame, per item; ' = bra index):
+//   EL[x][x'], ER[x][x']                      (D x D)
+//   ETX/ETY/EBX/EBY[(u v)][(u' v')]           (D^2 x D^2)
+//   EtopT[(T T')][(t t')], EbotT[(c c')][(b b')]
+//   QXp[a][b][t][s][l],  QXe = QXp x_l EL      (R D^2 x p D)
+//   QYp[B][c][T][s][r],  QYe = QYp x_r ER
+//   Left [a][a'][b][b'][t][t']  -> L1[a][a'][T][T'][b][b'] -> L2[a][a'][T][T'][c][c']
+//   Right[B][B'][T][T'][c][c']
+//   g[(a' B'), (a B)] = sum_{T T' c c'} L2[a a' .] Right[B B' .]
+// Every contraction is an "NT" product C(i, j) = sum_k A(i, k) B(j, k) with
+// three-level index maps, so no step needs a separate transpose pass.
+#include "kernels.h"
+#include "mfma_gemm.h"
+
+namespace ntu {
+
+// ---------------------------------------------------------------------------
+// generic NT GEMM in FP64 (real or complex), 64 x 64 tiles
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_gemm_nt(const T* __restrict__ A, const T* __restrict__ B,
+                                                 T* __restrict__ C, GemmNT d) {
+  constexpr int BM = 64, BN = 64, BK = 16;
+  __shared__ T As[BK][BM + 1];
+  __shared__ T Bs[BK][BN + 1];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN, bt = blockIdx.z;
+  const T* Ab = A + idx_off(d.Ab, bt);
+  const T* Bb = B + idx_off(d.Bb, bt);
+  T* Cb = C + idx_off(d.Cb, bt);
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = zerov<T>();
+  long long aoff[4], boff[4];
+  int arow[4], brow[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    int e = tid + u * 256;           // 0 .. 1023 = BM * BK
+    arow[u] = e / BK;                // tile row
+    int i = i0 + arow[u], j = j0 + arow[u];
+    aoff[u] = i < d.M ? idx_off(d.Ai, i) : -1;
+    boff[u] = j < d.N ? idx_off(d.Bj, j) : -1;
+    brow[u] = arow[u];
+  }
+  for (int k0 = 0; k0 < d.K; k0 += BK) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int e = tid + u * 256, kk = e % BK, k = k0 + kk;
+      T va = zerov<T>(), vb = zerov<T>();
+      if (k < d.K) {
+        long long ko_a = idx_off(d.Ak, k), ko_b = idx_off(d.Bk, k);
+        if (aoff[u] >= 0) { va = Ab[aoff[u] + ko_a]; if (d.conjA) va = conjv(va); }
+        if (boff[u] >= 0) { vb = Bb[boff[u] + ko_b]; if (d.conjB) vb = conjv(vb); }
+      }
+      As[kk][arow[u]] = va;
+      Bs[kk][brow[u]] = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      T a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) { a[u] = As[kk][ty + 16 * u]; b[u] = Bs[kk][tx + 16 * u]; }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    int i = i0 + ty + 16 * u;
+    if (i >= d.M) continue;
+    long long ci = idx_off(d.Ci, i);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int j = j0 + tx + 16 * v;
+      if (j >= d.N) continue;
+      Cb[ci + idx_off(d.Cj, j)] = acc[u][v];
+    }
+  }
+}
+
+static hipError_t gemm_nt(bool cplx, const void* A, const void* B, void* C, const GemmNT& d, hipStream_t st) {
+  dim3 g((d.N + 63) / 64, (d.M + 63) / 64, d.batch), b(256);
+  if (cplx)
+    hipLaunchKernelGGL(k_gemm_nt<cd>, g, b, 0, st, (const cd*)A, (const cd*)B, (cd*)C, d);
+  else
+    hipLaunchKernelGGL(k_gemm_nt<double>, g, b, 0, st, (const double*)A, (const double*)B, (double*)C, d);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// QXp / QXe (and QYp / QYe): regroup the isometry rows so that the legs
+// contracted in the half environments come last, and multiply the leg that
+// meets L (or Rn) by EL (or ER).
+//   X side: Q rows (s, t, l, b)  -> out[a][b][t][s][l]
+//   Y side: Q rows (s, t, b, r)  -> out[B][c=b][T=t][s][r]
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_qprep(int p, int D, int R, int side, const T* __restrict__ Q, const T* __restrict__ E,
+                        long long e_stride, T* __restrict__ Qp, T* __restrict__ Qe, long long out_stride) {
+  const int it = blockIdx.y;
+  const long long D2 = (long long)D * D, D3 = D2 * D;
+  const long long n = (long long)R * D2 * p * D;
+  const T* Qi = Q + (size_t)it * p * D3 * R;
+  const T* Ei = E + (size_t)it * e_stride;
+  T* Op = Qp + (size_t)it * out_stride;
+  T* Oe = Qe + (size_t)it * out_stride;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    int x = (int)(e % D);                  // l (X) or r (Y): leg that meets the edge tensor
+    int s = (int)((e / D) % p);
+    int t = (int)((e / (D * p)) % D);
+    int b = (int)((e / (D2 * p)) % D);
+    int a = (int)(e / (D3 * p));
+    // row of Q holding (s, t, b, x)
+    long long rbase = side == 0 ? (long long)s * D3 + (long long)t * D2 + b          // + x * D
+                                : (long long)s * D3 + (long long)t * D2 + (long long)b * D;  // + x
+    long long xs = side == 0 ? D : 1;
+    Op[e] = Qi[(rbase + x * xs) * R + a];
+    T acc = zerov<T>();
+    for (int y = 0; y < D; ++y) acc += Qi[(rbase + y * xs) * R + a] * Ei[y * D + x];
+    Oe[e] = acc;
+  }
+}
+
+EnvSizes env_sizes(int p, int D, int R) {
+  EnvSizes s;
+  long long D2 = (long long)D * D, D4 = D2 * D2;
+  s.p = p; s.D = D; s.R = R;
+  s.e_small = 2 * D2 + 6 * D4;
+  s.qp = (long long)R * D2 * p * D;
+  s.half = (long long)R * R * D4;
+  return s;
+}
+
+// element size of the large intermediates: the compute type on the FP64 path,
+// float (real) / float2 (complex) on the mixed paths
+static size_t half_elem(bool cplx, int precision) {
+  if (precision == 0) return cplx ? 16 : 8;
+  return cplx ? 8 : 4;
+}
+
+size_t env_workspace_bytes(bool cplx, int precision, int batch, int p, int D, int R) {
+  EnvSizes s = env_sizes(p, D, R);
+  size_t el = cplx ? 16 : 8;
+  size_t per = (size_t)(s.e_small + 4 * s.qp) * el + 3 * (size_t)s.half * half_elem(cplx, precision);
+  size_t extra = precision == 0 ? 0 : mixed_partial_bytes(cplx, batch, R, D);
+  return per * (size_t)batch + extra + 4096;
+}
+
+hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D, int R, const void* QX,
+                               const void* QY, const void* const nbr[6], void* g, void* ws, size_t ws_bytes,
+                               hipStream_t st, const ProfHook& ph) {
+  if (batch <= 0) return hipSuccess;
+  if (env_workspace_bytes(cplx, precision, batch, p, D, R) > ws_bytes) return hipErrorOutOfMemory;
+  const EnvSizes s = env_sizes(p, D, R);
+  const size_t el = cplx ? 16 : 8, hel = half_elem(cplx, precision);
+  const long long D2 = (long long)D * D, D3 = D2 * D, D4 = D2 * D2;
+  const long long site = p * D4;
+  // carve the workspace: small (compute type) part for all items, then the big buffers
+  char* w = (char*)ws;
+  char* EL = w;                          // per item e_small elements
+  char* ER = EL + D2 * el;
+  char* ETX = ER + D2 * el;
+  char* ETY = ETX + D4 * el;
+  char* EBX = ETY + D4 * el;
+  char* EBY = EBX + D4 * el;
+  char* ETT = EBY + D4 * el;             // EtopT
+  char* EBT = ETT + D4 * el;             // EbotT
+  const long long es = s.e_small;        // item stride of the small block (elements)
+  char* QXp = w + (size_t)batch * es * el;
+  char* QXe = QXp + (size_t)batch * s.qp * el;
+  char* QYp = QXe + (size_t)batch * s.qp * el;
+  char* QYe = QYp + (size_t)batch * s.qp * el;
+  char* H0 = QYe + (size_t)batch * s.qp * el;          // Left, later L2
+  char* H1 = H0 + (size_t)batch * s.half * hel;        // L1
+  char* H2 = H1 + (size_t)batch * s.half * hel;        // Right
+  hipError_t err;
+#define NTU_TRY(x) do { err = (x); if (err != hipSuccess) return err; } while (0)
+
+  // 1. edge double tensors (Fig. 4(a,b)): E(i, j) = sum_k T(i, k) conj(T(j, k))
+  auto edge2 = [&](const void* T, char* out, Idx3 Ii, Idx3 Ik, int M, int K) {
+    GemmNT d{};
+    d.M = M; d.N = M; d.K = K; d.batch = batch;
+    d.Ab = idx1(site); d.Bb = idx1(site); d.Cb = idx1(es);
+    d.Ai = Ii; d.Ak = Ik; d.Bj = Ii; d.Bk = Ik;
+    d.Ci = idx1(M); d.Cj = idx1(1);
+    d.conjA = 0; d.conjB = 1;
+    return gemm_nt(cplx, T, T, out, d, st);
+  };
+  ph(PK_EDGES, 0);
+  // EL: L's right leg; k = (p, t, l, b)
+  NTU_TRY(edge2(nbr[0], EL, idx1(1), idx1(D), D, (int)(p * D3)));
+  // ER: Rn's left leg; k = ((p, t), (b, r))
+  NTU_TRY(edge2(nbr[5], ER, idx1(D2), idx2((int)D2, D3, 1), D, (int)(p * D3)));
+  // ETX: (u = b, v = r) contiguous; k = (p, t, l)
+  NTU_TRY(edge2(nbr[1], ETX, idx1(1), idx1(D2), (int)D2, (int)(p * D2)));
+  // ETY: u = b, v = l; k = ((p, t), r)
+  NTU_TRY(edge2(nbr[3], ETY, idx2(D, D, D2), idx2(D, D3, 1), (int)D2, (int)(p * D2)));
+  // EBX: u = t, v = r; k = (p, (l, b))
+  NTU_TRY(edge2(nbr[2], EBX, idx2(D, D3, 1), idx2((int)D2, D4, D), (int)D2, (int)(p * D2)));
+  // EBY: u = t, v = l; k = (p, (b, r))
+  NTU_TRY(edge2(nbr[4], EBY, idx2(D, D3, D2), idx2((int)D2, D4, 1), (int)D2, (int)(p * D2)));
+
+  // 2. parallel bonds: EtopT[(T T')][(t t')] = sum_{v v'} ETY[T v T' v'] ETX[t v t' v']
+  {
+    GemmNT d{};
+    d.M = (int)D2; d.N = (int)D2; d.K = (int)D2; d.batch = batch;
+    d.Ab = idx1(es); d.Bb = idx1(es); d.Cb = idx1(es);
+    d.Ai = idx2(D, D3, D); d.Ak = idx2(D, D2, 1);
+    d.Bj = idx2(D, D3, D); d.Bk = idx2(D, D2, 1);
+    d.Ci = idx1(D2); d.Cj = idx1(1);
+    NTU_TRY(gemm_nt(cplx, ETY, ETX, ETT, d, st));
+    NTU_TRY(gemm_nt(cplx, EBY, EBX, EBT, d, st));
+  }
+  ph(PK_EDGES, 1);
+
+  // 3. regrouped isometries dressed with EL / ER
+  ph(PK_QPREP, 0);
+  {
+    long long n = s.qp;
+    int gx = (int)((n + 255) / 256);
+    if (gx > 2048) gx = 2048;
+    dim3 gg(gx, batch), bb(256);
+    if (cplx) {
+      hipLaunchKernelGGL(k_qprep<cd>, gg, bb, 0, st, p, D, R, 0, (const cd*)QX, (const cd*)EL, es, (cd*)QXp, (cd*)QXe, s.qp);
+      hipLaunchKernelGGL(k_qprep<cd>, gg, bb, 0, st, p, D, R, 1, (const cd*)QY, (const cd*)ER, es, (cd*)QYp, (cd*)QYe, s.qp);
+    } else {
+      hipLaunchKernelGGL(k_qprep<double>, gg, bb, 0, st, p, D, R, 0, (const double*)QX, (const double*)EL, es, (double*)QXp, (double*)QXe, s.qp);
+      hipLaunchKernelGGL(k_qprep<double>, gg, bb, 0, st, p, D, R, 1, (const double*)QY, (const double*)ER, es, (double*)QYp, (double*)QYe, s.qp);
+    }
+    NTU_TRY(hipGetLastError());
+  }
+  ph(PK_QPREP, 1);
+
+  const int pD = p * D;
+  const long long RD4 = (long long)R * D4;
+  if (precision == 0) {
+    // 4. Left[a][a'][b][b'][t][t'] = sum_{s l'} QXe[(a b t)][(s l')] conj(QXp[(a' b' t')][(s l')])
+    GemmNT d{};
+    d.M = (int)(R * D2); d.N = (int)(R * D2); d.K = pD; d.batch = batch;
+    d.Ab = idx1(s.qp); d.Bb = idx1(s.qp); d.Cb = idx1(s.half);
+    d.Ai = idx1(pD); d.Ak = idx1(1); d.Bj = idx1(pD); d.Bk = idx1(1);
+    d.conjB = 1;
+    d.Ci = idx3(D, D, RD4, D3, D); d.Cj = idx3(D, D, D4, D2, 1);
+    ph(PK_LEFTRIGHT, 0);
+    NTU_TRY(gemm_nt(cplx, QXe, QXp, H0, d, st));
+    // Right[B][B'][T][T'][c][c'] from rows (B, c, T)
+    d.Ci = idx3(D, D, RD4, D, D3); d.Cj = idx3(D, D, D4, 1, D2);
+    NTU_TRY(gemm_nt(cplx, QYe, QYp, H2, d, st));
+    ph(PK_LEFTRIGHT, 1);
+    // 5. L1[a a'][T T'][b b'] = sum_{t t'} Left[(a a' b b')][(t t')] EtopT[(T T')][(t t')]
+    GemmNT e{};
+    e.M = (int)(R * R * D2); e.N = (int)D2; e.K = (int)D2; e.batch = batch;
+    e.Ab = idx1(s.half); e.Bb = idx1(es); e.Cb = idx1(s.half);
+    e.Ai = idx1(D2); e.Ak = idx1(1); e.Bj = idx1(D2); e.Bk = idx1(1);
+    e.Ci = idx2((int)D2, D4, 1); e.Cj = idx1(D2);
+    ph(PK_E4, 0);
+    NTU_TRY(gemm_nt(cplx, H0, ETT, H1, e, st));
+    ph(PK_E4, 1);
+    // 6. L2[(a a' T T')][(c c')] = sum_{b b'} L1[(a a' T T')][(b b')] EbotT[(c c')][(b b')]
+    e.Ci = idx1(D2); e.Cj = idx1(1);
+    ph(PK_E5, 0);
+    NTU_TRY(gemm_nt(cplx, H1, EBT, H0, e, st));
+    ph(PK_E5, 1);
+    // 7. g[(a' B'), (a B)] = sum_K L2[(a a')][K] Right[(B B')][K]
+    GemmNT f{};
+    f.M = R * R; f.N = R * R; f.K = (int)D4; f.batch = batch;
+    f.Ab = idx1(s.half); f.Bb = idx1(s.half); f.Cb = idx1((long long)R * R * R * R);
+    f.Ai = idx1(D4); f.Ak = idx1(1); f.Bj = idx1(D4); f.Bk = idx1(1);
+    f.Ci = idx2(R, R, (long long)R * R * R); f.Cj = idx2(R, 1, (long long)R * R);
+    ph(PK_E6, 0);
+    NTU_TRY(gemm_nt(cplx, H0, H2, g, f, st));
+    ph(PK_E6, 1);
+  } else {
+    NTU_TRY(launch_env_heavy_mixed(cplx, precision, batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, s.qp,
+                                   s.half, H0, H1, H2, g, st, ph));
+  }
+#undef NTU_TRY
+  return hipSuccess;
+}
+
+}  // namespace ntu

@@ -1,0 +1,152 @@
+// Metric repair: the exact metric is Hermitian and non-negative (abstract;
+// Sec. II).  Hermitise in place and, on request, clip negative eigenvalues.
+#include "kernels.h"
+#include "linalg.h"
+
+namespace ntu {
+
+constexpr int HERM_THREADS = 256;
+constexpr int CLIP_THREADS = 1024;
+
+// (g + g^H) / 2 in place, with ||g - g^H||_F, ||g||_F and the count of
+// non-finite entries of the input.
+template <class T>
+__global__ void __launch_bounds__(HERM_THREADS) k_hermitise(int n, T* g, double* stats, int sstride) {
+  __shared__ double red[64];
+  const int it = blockIdx.x;
+  T* G = g + (size_t)it * n * n;
+  double skew = 0, nrm = 0, bad = 0;
+  const long long npair = (long long)n * (n + 1) / 2;
+  for (long long e = threadIdx.x; e < npair; e += blockDim.x) {
+    // packed lower triangle, row-wise: e -> (i, j), j <= i
+    int i = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+    while ((long long)(i + 1) * (i + 2) / 2 <= e) ++i;
+    while ((long long)i * (i + 1) / 2 > e) --i;
+    int j = (int)(e - (long long)i * (i + 1) / 2);
+    T a = G[(size_t)i * n + j], b = G[(size_t)j * n + i];
+    if (!finitev(a)) bad += 1;
+    if (i != j && !finitev(b)) bad += 1;
+    if (i == j) {
+      nrm += abs2(a);
+      skew += 4.0 * imv(a) * imv(a);
+      G[(size_t)i * n + i] = realv<T>(rev(a));
+    } else {
+      nrm += abs2(a) + abs2(b);
+      T dlt = a - conjv(b);
+      skew += 2.0 * abs2(dlt);
+      T h = 0.5 * (a + conjv(b));
+      G[(size_t)i * n + j] = h;
+      G[(size_t)j * n + i] = conjv(h);
+    }
+  }
+  skew = block_sum(skew, red);
+  nrm = block_sum(nrm, red);
+  bad = block_sum(bad, red);
+  if (stats && threadIdx.x == 0) {
+    double* s = stats + (size_t)it * sstride;
+    s[0] = nrm > 0 ? sqrt(skew) / sqrt(nrm) : 0.0;
+    s[1] = sqrt(nrm);
+    s[2] = NAN; s[3] = NAN; s[4] = 0.0; s[5] = 0.0;
+    s[6] = bad; s[7] = 0.0;
+  }
+}
+
+// Eigenvalue clip of the Hermitian g.  Rows that are exactly zero are left
+// out; if the rest admits a Cholesky factorisation it is positive definite
+// and nothing changes; otherwise g <- V max(Lambda, 0) V^H on that block.
+template <class T>
+__global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stats, int sstride, T* ws) {
+  __shared__ double red[64];
+  __shared__ int idx[1024];
+  __shared__ int m_sh, cnt;
+  __shared__ double pc[512], ps[512];
+  __shared__ T pe[512];
+  const int it = blockIdx.x, tid = threadIdx.x;
+  T* G = g + (size_t)it * n * n;
+  T* A = ws + (size_t)it * 2 * n * n;
+  T* V = A + (size_t)n * n;
+  // nonzero rows
+  for (int i = tid; i < n; i += blockDim.x) {
+    bool nz = false;
+    for (int j = 0; j < n && !nz; ++j) {
+      T v = G[(size_t)i * n + j];
+      nz = (rev(v) != 0.0) || (imv(v) != 0.0);
+    }
+    idx[i] = nz ? 1 : 0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int m = 0;
+    for (int i = 0; i < n; ++i)
+      if (idx[i]) idx[m++] = i;
+    m_sh = m;
+  }
+  __syncthreads();
+  const int m = m_sh;
+  double fro = 0;
+  for (long long e = tid; e < (long long)m * m; e += blockDim.x) {
+    int i = (int)(e / m), j = (int)(e % m);
+    T v = G[(size_t)idx[i] * n + idx[j]];
+    A[e] = v;
+    fro += abs2(v);
+  }
+  fro = sqrt(block_sum(fro, red));
+  __syncthreads();
+  bool ok = m == 0 || block_cholesky<T>(A, m, m, red);
+  if (ok) return;  // positive definite: the clip is the identity
+  for (long long e = tid; e < (long long)m * m; e += blockDim.x) {
+    int i = (int)(e / m), j = (int)(e % m);
+    A[e] = G[(size_t)idx[i] * n + idx[j]];
+  }
+  __syncthreads();
+  block_jacobi_eigh<T>(A, m, m, V, m, pc, ps, pe, &cnt, fro);
+  // eigenvalues on the diagonal of A
+  double lmin = INFINITY, lmax = -INFINITY, neg = 0, tot = 0;
+  for (int i = tid; i < m; i += blockDim.x) {
+    double l = rev(A[(size_t)i * m + i]);
+    lmin = fmin(lmin, l); lmax = fmax(lmax, l);
+    if (l < 0) neg -= l;
+    tot += fabs(l);
+  }
+  lmin = -block_max(-lmin, red);
+  lmax = block_max(lmax, red);
+  neg = block_sum(neg, red);
+  tot = block_sum(tot, red);
+  // reassemble on the block: G[idx_i, idx_j] = sum_k V[i][k] max(l_k, 0) conj(V[j][k])
+  for (long long e = tid; e < (long long)m * m; e += blockDim.x) {
+    int i = (int)(e / m), j = (int)(e % m);
+    T acc = zerov<T>();
+    for (int k = 0; k < m; ++k) {
+      double l = rev(A[(size_t)k * m + k]);
+      if (l > 0) acc += mulc(V[(size_t)i * m + k], V[(size_t)j * m + k]) * l;
+    }
+    G[(size_t)idx[i] * n + idx[j]] = acc;
+  }
+  if (stats && tid == 0) {
+    double* s = stats + (size_t)it * sstride;
+    s[2] = lmin; s[3] = lmax; s[4] = tot > 0 ? neg / tot : 0.0; s[5] = 1.0;
+  }
+}
+
+size_t fix_workspace_bytes(bool cplx, int batch, int n) {
+  return (size_t)batch * 2 * n * n * (cplx ? 16 : 8) + 256;
+}
+
+hipError_t launch_metric_fix(bool cplx, int batch, int n, void* g, int mode, double* stats, int sstride,
+                             void* ws, hipStream_t st, const ProfHook& ph) {
+  if (batch <= 0) return hipSuccess;
+  if (n > 1024) return hipErrorInvalidValue;
+  ph(PK_HERM, 0);
+  if (cplx) hipLaunchKernelGGL(k_hermitise<cd>, dim3(batch), dim3(HERM_THREADS), 0, st, n, (cd*)g, stats, sstride);
+  else hipLaunchKernelGGL(k_hermitise<double>, dim3(batch), dim3(HERM_THREADS), 0, st, n, (double*)g, stats, sstride);
+  ph(PK_HERM, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || mode == 0) return e;
+  ph(PK_CLIP, 0);
+  if (cplx) hipLaunchKernelGGL(k_clip<cd>, dim3(batch), dim3(CLIP_THREADS), 0, st, n, (cd*)g, stats, sstride, (cd*)ws);
+  else hipLaunchKernelGGL(k_clip<double>, dim3(batch), dim3(CLIP_THREADS), 0, st, n, (double*)g, stats, sstride, (double*)ws);
+  ph(PK_CLIP, 1);
+  return hipGetLastError();
+}
+
+}  // namespace ntu

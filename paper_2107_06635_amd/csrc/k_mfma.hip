@@ -1,0 +1,319 @@
+// Split-precision NT products on the gfx950 matrix cores:
+//   C(i, j) = sum_k A(i, k) B(j, k)
+// Each operand value x is split into bfloat16 (or float16) pieces,
+//   BF16X3:  x = hi + lo,          product ~ hi*hi + (hi*lo + lo*hi)
+//   BF16X6:  x = hi + mid + lo,    product ~ hi*hi + (hi*mid + mid*hi)
+//                                            + (hi*lo + mid*mid + lo*hi)
+//   FP16X3:  x s = hi + lo 2^-11,  product ~ hi*hi + 2^-11 (hi*lo + lo*hi)
+// with every term class accumulated in its own FP32 MFMA accumulator and the
+// classes combined in FP64 at the end (split-K partials are summed in FP64).
+// Complex operands use the real embedding: an interleaved complex row of A
+// is a real row of length 2K; each complex row of B yields two real rows
+// (re, -im), (im, re) (or (re, im), (-im, re) for conj(B)), so the real
+// product has output columns (re, im) interleaved.
+#include "kernels.h"
+#include "mfma_gemm.h"
+
+namespace ntu {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MT_BM = 64, MT_BN = 64, MT_BK = 32, MT_PAD = 8, MT_LD = MT_BK + MT_PAD;
+
+template <int PREC> struct SplitTraits;
+template <> struct SplitTraits<NTU_PREC_BF16X3> { static constexpr int NT = 2; using E = __bf16; };
+template <> struct SplitTraits<NTU_PREC_BF16X6> { static constexpr int NT = 3; using E = __bf16; };
+template <> struct SplitTraits<NTU_PREC_FP16X3> { static constexpr int NT = 2; using E = _Float16; };
+
+// split x (already scaled for FP16) into NT pieces
+template <int PREC>
+NTU_DEV void split_value(float x, typename SplitTraits<PREC>::E* out) {
+  using E = typename SplitTraits<PREC>::E;
+  if constexpr (PREC == NTU_PREC_FP16X3) {
+    E hi = (E)x;
+    float r = (x - (float)hi) * 2048.0f;
+    out[0] = hi;
+    out[1] = (E)r;
+  } else if constexpr (PREC == NTU_PREC_BF16X3) {
+    E hi = (E)x;
+    out[0] = hi;
+    out[1] = (E)(x - (float)hi);
+  } else {
+    E hi = (E)x;
+    float r = x - (float)hi;
+    E mid = (E)r;
+    out[0] = hi;
+    out[1] = mid;
+    out[2] = (E)(r - (float)mid);
+  }
+}
+
+template <int PREC>
+NTU_DEV f32x4 mfma(const typename SplitTraits<PREC>::E* a, const typename SplitTraits<PREC>::E* b, f32x4 c) {
+  if constexpr (PREC == NTU_PREC_FP16X3) {
+    f16x8 va = *(const f16x8*)a, vb = *(const f16x8*)b;
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(va, vb, c, 0, 0, 0);
+  } else {
+    bf16x8 va = *(const bf16x8*)a, vb = *(const bf16x8*)b;
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, c, 0, 0, 0);
+  }
+}
+
+template <class TIn> NTU_DEV float to_f(TIn v) { return (float)v; }
+
+// Load the real value (row, kr) of the real-embedded operand.
+//  A-side (expand = false): real row i, real k -> element k of the (interleaved) row
+//  B-side complex (expand = true): real row jr -> complex row jr/2, part jr%2
+template <bool CPLX, bool EXPAND, class TIn>
+NTU_DEV float load_real(const TIn* rowp, int jr_parity, int kr, int conj) {
+  if constexpr (!CPLX || !EXPAND) {
+    return to_f(rowp[kr]);
+  } else {
+    const int kc = kr >> 1, part = kr & 1;
+    float re = to_f(rowp[2 * kc]), im = to_f(rowp[2 * kc + 1]);
+    if (conj) im = -im;
+    // row 2j (C_re): (re, -im) ; row 2j+1 (C_im): (im, re)
+    if (jr_parity == 0) return part == 0 ? re : -im;
+    return part == 0 ? im : re;
+  }
+}
+
+struct MixedArgs {
+  GemmNT d;          // in complex (or real) elements
+  int ksplit;        // number of K chunks (grid.z = batch * ksplit)
+  int kchunk;        // real K per chunk (multiple of MT_BK)
+  double* partial;   // ksplit > 1: [split][item][M][Nr] FP64 partial sums
+  const float* scaleA;  // FP16X3: per-item power-of-two scale of A (NULL = 1)
+  const float* scaleB;
+};
+
+template <int PREC, bool CPLX, class TA, class TB, class TC>
+__global__ void __launch_bounds__(256) k_mfma_nt(const TA* __restrict__ A, const TB* __restrict__ B,
+                                                TC* __restrict__ C, MixedArgs args) {
+  using E = typename SplitTraits<PREC>::E;
+  constexpr int NT = SplitTraits<PREC>::NT;
+  constexpr int NACC = (PREC == NTU_PREC_BF16X6) ? 3 : 2;
+  __shared__ __attribute__((aligned(16))) E sA[NT][MT_BM][MT_LD];
+  __shared__ __attribute__((aligned(16))) E sB[NT][MT_BN][MT_LD];
+  const GemmNT& d = args.d;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int Mr = d.M, Nr = CPLX ? 2 * d.N : d.N, Kr = CPLX ? 2 * d.K : d.K;
+  const int item = blockIdx.z / args.ksplit, split = blockIdx.z % args.ksplit;
+  const int i0 = blockIdx.y * MT_BM, j0 = blockIdx.x * MT_BN;
+  const int kbeg = split * args.kchunk;
+  const int kend = min(Kr, kbeg + args.kchunk);
+  constexpr int CW = CPLX ? 2 : 1;  // scalars per element
+  const TA* Ab = A + idx_off(d.Ab, item) * CW;
+  const TB* Bb = B + idx_off(d.Bb, item) * CW;
+  float scA = 1.0f, scB = 1.0f;
+  if constexpr (PREC == NTU_PREC_FP16X3) {
+    if (args.scaleA) scA = args.scaleA[item];
+    if (args.scaleB) scB = args.scaleB[item];
+  }
+  // each thread stages 8 consecutive real k of one tile row
+  const int lrow = tid >> 2, lk = (tid & 3) * 8;
+  const int ai = i0 + lrow, bj = j0 + lrow;
+  const TA* arow = ai < Mr ? Ab + idx_off(d.Ai, ai) * CW : nullptr;
+  const int bcol = CPLX ? (bj >> 1) : bj;
+  const TB* brow = bj < Nr ? Bb + idx_off(d.Bj, bcol) * CW : nullptr;
+
+  f32x4 acc[NACC][2][2];
+#pragma unroll
+  for (int c = 0; c < NACC; ++c)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[c][x][y] = f32x4{0, 0, 0, 0};
+
+  for (int k0 = kbeg; k0 < kend; k0 += MT_BK) {
+    E pa[NT][8], pb[NT][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int kr = k0 + lk + u;
+      float va = 0.0f, vb = 0.0f;
+      if (kr < kend) {
+        if (arow) va = load_real<CPLX, false>(arow, 0, kr, 0) * scA;
+        if (brow) vb = load_real<CPLX, true>(brow, bj & 1, kr, d.conjB) * scB;
+      }
+      E ta[NT], tb[NT];
+      split_value<PREC>(va, ta);
+      split_value<PREC>(vb, tb);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) { pa[t][u] = ta[t]; pb[t][u] = tb[t]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        sA[t][lrow][lk + u] = pa[t][u];
+        sB[t][lrow][lk + u] = pb[t][u];
+      }
+    }
+    __syncthreads();
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int ra = wm * 32 + x * 16 + fr, rb = wn * 32 + y * 16 + fr;
+        const E* a0 = &sA[0][ra][fk];
+        const E* b0 = &sB[0][rb][fk];
+        const E* a1 = &sA[1][ra][fk];
+        const E* b1 = &sB[1][rb][fk];
+        acc[0][x][y] = mfma<PREC>(a0, b0, acc[0][x][y]);
+        acc[1][x][y] = mfma<PREC>(a0, b1, acc[1][x][y]);
+        acc[1][x][y] = mfma<PREC>(a1, b0, acc[1][x][y]);
+        if constexpr (PREC == NTU_PREC_BF16X6) {
+          const E* a2 = &sA[2][ra][fk];
+          const E* b2 = &sB[2][rb][fk];
+          acc[2][x][y] = mfma<PREC>(a0, b2, acc[2][x][y]);
+          acc[2][x][y] = mfma<PREC>(a1, b1, acc[2][x][y]);
+          acc[2][x][y] = mfma<PREC>(a2, b0, acc[2][x][y]);
+        }
+      }
+    }
+  }
+  // epilogue: output layout of the 16x16 result: lane holds column (lane & 15),
+  // rows 4 * (lane >> 4) + v
+  const double unscale = 1.0 / ((double)scA * (double)scB);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wm * 32 + x * 16 + 4 * (lane >> 4) + v;
+        const int jr = j0 + wn * 32 + y * 16 + (lane & 15);
+        if (i >= Mr || jr >= Nr) continue;
+        double val;
+        if constexpr (PREC == NTU_PREC_FP16X3) val = ((double)acc[0][x][y][v] + (double)acc[1][x][y][v] * (1.0 / 2048.0)) * unscale;
+        else if constexpr (PREC == NTU_PREC_BF16X6) val = (double)acc[0][x][y][v] + ((double)acc[1][x][y][v] + (double)acc[2][x][y][v]);
+        else val = (double)acc[0][x][y][v] + (double)acc[1][x][y][v];
+        if (args.ksplit > 1) {
+          args.partial[(((size_t)split * d.batch + item) * Mr + i) * Nr + jr] = val;
+        } else {
+          const int j = CPLX ? jr >> 1 : jr, part = CPLX ? jr & 1 : 0;
+          long long off = (idx_off(d.Cb, item) + idx_off(d.Ci, i) + idx_off(d.Cj, j)) * CW + part;
+          C[off] = (TC)val;
+        }
+      }
+}
+
+// sum the split-K partials in FP64 and scatter to C through its index maps
+template <bool CPLX, class TC>
+__global__ void k_splitk_reduce(const double* __restrict__ partial, TC* __restrict__ C, GemmNT d, int ksplit) {
+  const int Nr = CPLX ? 2 * d.N : d.N;
+  const long long per = (long long)d.M * Nr, tot = per * d.batch;
+  constexpr int CW = CPLX ? 2 : 1;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int item = (int)(e / per);
+    const long long r = e % per;
+    const int i = (int)(r / Nr), jr = (int)(r % Nr);
+    double s = 0.0;
+    for (int k = 0; k < ksplit; ++k) s += partial[((size_t)k * d.batch + item) * per + r];
+    const int j = CPLX ? jr >> 1 : jr, part = CPLX ? jr & 1 : 0;
+    C[(idx_off(d.Cb, item) + idx_off(d.Ci, i) + idx_off(d.Cj, j)) * CW + part] = (TC)s;
+  }
+}
+
+template <int PREC, bool CPLX, class TA, class TB, class TC>
+static hipError_t run_mixed(const void* A, const void* B, void* C, const GemmNT& d, int ksplit, double* partial,
+                            hipStream_t st, const ProfHook& ph, int kind) {
+  const int Mr = d.M, Nr = CPLX ? 2 * d.N : d.N, Kr = CPLX ? 2 * d.K : d.K;
+  MixedArgs a{};
+  a.d = d;
+  a.ksplit = ksplit < 1 ? 1 : ksplit;
+  int chunk = (Kr + a.ksplit - 1) / a.ksplit;
+  chunk = (chunk + MT_BK - 1) / MT_BK * MT_BK;
+  a.kchunk = chunk;
+  a.ksplit = (Kr + chunk - 1) / chunk;
+  a.partial = partial;
+  dim3 g((Nr + MT_BN - 1) / MT_BN, (Mr + MT_BM - 1) / MT_BM, d.batch * a.ksplit), b(256);
+  ph(kind, 0);
+  hipLaunchKernelGGL((k_mfma_nt<PREC, CPLX, TA, TB, TC>), g, b, 0, st, (const TA*)A, (const TB*)B, (TC*)C, a);
+  ph(kind, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.ksplit == 1) return e;
+  long long tot = (long long)Mr * Nr * d.batch;
+  int gx = (int)std::min<long long>((tot + 255) / 256, 4096);
+  ph(PK_E6RED, 0);
+  hipLaunchKernelGGL((k_splitk_reduce<CPLX, TC>), dim3(gx), dim3(256), 0, st, partial, (TC*)C, d, a.ksplit);
+  ph(PK_E6RED, 1);
+  return hipGetLastError();
+}
+
+// number of K chunks for the final assembly: aim at ~2 waves of workgroups on 256 CUs
+static int e6_ksplit(int batch, int M, int Nr, int Kr) {
+  long long tiles = (long long)((M + MT_BM - 1) / MT_BM) * ((Nr + MT_BN - 1) / MT_BN) * batch;
+  int ks = (int)std::max<long long>(1, 512 / std::max<long long>(1, tiles));
+  int kmax = std::max(1, Kr / (4 * MT_BK));
+  return std::min(ks, std::min(kmax, 16));
+}
+
+size_t mixed_partial_bytes(bool cplx, int batch, int R, int D) {
+  const int M = R * R, Nr = (cplx ? 2 : 1) * R * R, Kr = (cplx ? 2 : 1) * D * D * D * D;
+  const int ks = e6_ksplit(batch, M, Nr, Kr);
+  return ks > 1 ? (size_t)ks * batch * M * Nr * sizeof(double) : 0;
+}
+
+template <int PREC, bool CPLX>
+static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, const void* QXp, const void* QYe,
+                            const void* QYp, const void* ETT, const void* EBT, long long es, long long qs, long long hs,
+                            void* H0, void* H1, void* H2, void* g, hipStream_t st, const ProfHook& ph) {
+  using T64 = double;  // scalar of the compute-type inputs
+  const long long D2 = (long long)D * D, D3 = D2 * D, D4 = D2 * D2, RD4 = (long long)R * D4;
+  const int pD = p * D;
+  hipError_t e;
+  // Left / Right
+  GemmNT d{};
+  d.M = (int)(R * D2); d.N = (int)(R * D2); d.K = pD; d.batch = batch;
+  d.Ab = idx1(qs); d.Bb = idx1(qs); d.Cb = idx1(hs);
+  d.Ai = idx1(pD); d.Ak = idx1(1); d.Bj = idx1(pD); d.Bk = idx1(1);
+  d.conjB = 1;
+  d.Ci = idx3(D, D, RD4, D3, D); d.Cj = idx3(D, D, D4, D2, 1);
+  e = run_mixed<PREC, CPLX, T64, T64, float>(QXe, QXp, H0, d, 1, nullptr, st, ph, PK_LEFTRIGHT);
+  if (e != hipSuccess) return e;
+  d.Ci = idx3(D, D, RD4, D, D3); d.Cj = idx3(D, D, D4, 1, D2);
+  e = run_mixed<PREC, CPLX, T64, T64, float>(QYe, QYp, H2, d, 1, nullptr, st, ph, PK_LEFTRIGHT);
+  if (e != hipSuccess) return e;
+  // L1 = Left x Etop, L2 = L1 x Ebot
+  GemmNT f{};
+  f.M = (int)(R * R * D2); f.N = (int)D2; f.K = (int)D2; f.batch = batch;
+  f.Ab = idx1(hs); f.Bb = idx1(es); f.Cb = idx1(hs);
+  f.Ai = idx1(D2); f.Ak = idx1(1); f.Bj = idx1(D2); f.Bk = idx1(1);
+  f.Ci = idx2((int)D2, D4, 1); f.Cj = idx1(D2);
+  e = run_mixed<PREC, CPLX, float, T64, float>(H0, ETT, H1, f, 1, nullptr, st, ph, PK_E4);
+  if (e != hipSuccess) return e;
+  f.Ci = idx1(D2); f.Cj = idx1(1);
+  e = run_mixed<PREC, CPLX, float, T64, float>(H1, EBT, H0, f, 1, nullptr, st, ph, PK_E5);
+  if (e != hipSuccess) return e;
+  // g = L2 Right^T with split K, FP64 reduction
+  GemmNT q{};
+  q.M = R * R; q.N = R * R; q.K = (int)D4; q.batch = batch;
+  q.Ab = idx1(hs); q.Bb = idx1(hs); q.Cb = idx1((long long)R * R * R * R);
+  q.Ai = idx1(D4); q.Ak = idx1(1); q.Bj = idx1(D4); q.Bk = idx1(1);
+  q.Ci = idx2(R, R, (long long)R * R * R); q.Cj = idx2(R, 1, (long long)R * R);
+  const int Nr = (CPLX ? 2 : 1) * q.N, Kr = (CPLX ? 2 : 1) * q.K;
+  const int ks = e6_ksplit(batch, q.M, Nr, Kr);
+  // partial sums live right after H2 (the workspace reserves mixed_partial_bytes there)
+  double* partial = (double*)((char*)H2 + (size_t)batch * hs * (CPLX ? 8 : 4));
+  return run_mixed<PREC, CPLX, float, float, T64>(H0, H2, g, q, ks, partial, st, ph, PK_E6);
+}
+
+hipError_t launch_env_heavy_mixed(bool cplx, int precision, int batch, int p, int D, int R, const void* QXe,
+                                  const void* QXp, const void* QYe, const void* QYp, const void* ETT,
+                                  const void* EBT, long long es, long long qs, long long hs, void* H0, void* H1,
+                                  void* H2, void* g, hipStream_t st, const ProfHook& ph) {
+#define NTU_MIX(P, C) return env_heavy<P, C>(batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, qs, hs, H0, H1, H2, g, st, ph)
+  if (precision == NTU_PREC_BF16X3) { if (cplx) NTU_MIX(NTU_PREC_BF16X3, true); NTU_MIX(NTU_PREC_BF16X3, false); }
+  if (precision == NTU_PREC_BF16X6) { if (cplx) NTU_MIX(NTU_PREC_BF16X6, true); NTU_MIX(NTU_PREC_BF16X6, false); }
+  // FP16X3 needs operand scales; not wired into the environment yet
+  return hipErrorNotSupported;
+#undef NTU_MIX
+}
+
+}  // namespace ntu

@@ -1,0 +1,277 @@
+// Small dense linear algebra executed by one workgroup (or one thread).
+// Used by the gate split, the SVDU guess, the balancing SVD, the metric
+// repair and the bond fit.  All FP64.
+#pragma once
+#include "common.h"
+
+namespace ntu {
+
+// One-sided (Hestenes) Jacobi rotation of the column pair (p, q) that makes
+// them orthogonal.  Returns false when they already are (to rounding).
+// Given alpha = |c_p|^2, beta = |c_q|^2, gamma = c_p^H c_q, the rotation is
+// J = diag(1, e^{-i phi}) [[c, s], [-s, c]] with gamma = |gamma| e^{i phi}.
+template <class T>
+NTU_DEV bool jacobi_params(double alpha, double beta, T gamma, double& c, double& s, T& e) {
+  double g = absv(gamma);
+  if (!(g > 1e-15 * sqrt(alpha * beta)) || g == 0.0) return false;
+  double zeta = (beta - alpha) / (2.0 * g);
+  double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = c * t;
+  e = conjv(phasev(gamma));  // e^{-i phi}
+  return true;
+}
+
+// Serial one-sided Jacobi SVD of a column-major m x n matrix A (lda >= m):
+// on return the columns of A are U_j * s_j (descending s), V (n x n,
+// column-major, ldv) holds the right singular vectors: A_in = U S V^H.
+template <class T>
+NTU_DEV void svd_serial(T* A, int m, int n, int lda, T* V, int ldv, double* s) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) V[i + j * ldv] = realv<T>(i == j ? 1.0 : 0.0);
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    bool rot = false;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double a = 0, b = 0;
+        T g = zerov<T>();
+        for (int i = 0; i < m; ++i) {
+          a += abs2(A[i + p * lda]);
+          b += abs2(A[i + q * lda]);
+          g += cmul(A[i + p * lda], A[i + q * lda]);
+        }
+        double c, sn;
+        T e;
+        if (!jacobi_params(a, b, g, c, sn, e)) continue;
+        rot = true;
+        for (int i = 0; i < m; ++i) {
+          T x = A[i + p * lda], y = A[i + q * lda] * e;
+          A[i + p * lda] = c * x - sn * y;
+          A[i + q * lda] = sn * x + c * y;
+        }
+        for (int i = 0; i < n; ++i) {
+          T x = V[i + p * ldv], y = V[i + q * ldv] * e;
+          V[i + p * ldv] = c * x - sn * y;
+          V[i + q * ldv] = sn * x + c * y;
+        }
+      }
+    if (!rot) break;
+  }
+  for (int j = 0; j < n; ++j) {
+    double a = 0;
+    for (int i = 0; i < m; ++i) a += abs2(A[i + j * lda]);
+    s[j] = sqrt(a);
+  }
+  // selection sort, descending
+  for (int j = 0; j < n; ++j) {
+    int k = j;
+    for (int l = j + 1; l < n; ++l)
+      if (s[l] > s[k]) k = l;
+    if (k != j) {
+      double t = s[j]; s[j] = s[k]; s[k] = t;
+      for (int i = 0; i < m; ++i) { T x = A[i + j * lda]; A[i + j * lda] = A[i + k * lda]; A[i + k * lda] = x; }
+      for (int i = 0; i < n; ++i) { T x = V[i + j * ldv]; V[i + j * ldv] = V[i + k * ldv]; V[i + k * ldv] = x; }
+    }
+  }
+}
+
+// Pairing of round r (0 <= r < n2-1) of the round-robin ("circle") schedule
+// over n2 (even) columns: pair k of the round is (first, second), each pair
+// disjoint, every unordered pair met once per n2-1 rounds.
+NTU_DEV void rr_pair(int n2, int r, int k, int& a, int& b) {
+  // player 0 fixed, others rotate
+  auto pos = [&](int slot) -> int {
+    if (slot == 0) return 0;
+    return 1 + ((slot - 1 + r) % (n2 - 1));
+  };
+  int x = pos(k), y = pos(n2 - 1 - k);
+  a = x < y ? x : y;
+  b = x < y ? y : x;
+}
+
+// Block-parallel one-sided Jacobi SVD of a small column-major m x n matrix in
+// shared memory (m <= 32, n <= 32, lda >= m).  One wave per column pair:
+// lanes 0..31 carry rows of A, lanes 32..63 rows of V.  On return the columns
+// of A are U_j s_j in descending order of s, V the right singular vectors.
+// sh_flag: one int of shared memory.  Must be called by the whole block.
+template <class T>
+NTU_DEV void svd_block_small(T* A, int m, int n, int lda, T* V, int ldv, double* s, int* sh_flag) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    int i = e % n, j = e / n;
+    V[i + j * ldv] = realv<T>(i == j ? 1.0 : 0.0);
+  }
+  const int n2 = (n + 1) & ~1;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) *sh_flag = 0;
+    __syncthreads();
+    for (int r = 0; r < n2 - 1; ++r) {
+      for (int k = w; k < n2 / 2; k += nw) {
+        int p, q;
+        rr_pair(n2, r, k, p, q);
+        if (q >= n) continue;  // dummy column of an odd n
+        double a = 0, b = 0;
+        T g = zerov<T>();
+        if (lane < m) {
+          T x = A[lane + p * lda], y = A[lane + q * lda];
+          a = abs2(x); b = abs2(y); g = cmul(x, y);
+        }
+        a = wave_sum(a); b = wave_sum(b); g = wave_sum(g);
+        double c, sn;
+        T e;
+        if (!jacobi_params(a, b, g, c, sn, e)) continue;
+        if (lane < m) {
+          T x = A[lane + p * lda], y = A[lane + q * lda] * e;
+          A[lane + p * lda] = c * x - sn * y;
+          A[lane + q * lda] = sn * x + c * y;
+        } else if (lane >= 32 && lane - 32 < n) {
+          int i = lane - 32;
+          T x = V[i + p * ldv], y = V[i + q * ldv] * e;
+          V[i + p * ldv] = c * x - sn * y;
+          V[i + q * ldv] = sn * x + c * y;
+        }
+        if (lane == 0) *sh_flag = 1;
+      }
+      __syncthreads();
+    }
+    int f = *sh_flag;
+    __syncthreads();
+    if (!f) break;
+  }
+  if (tid < n) {
+    double a = 0;
+    for (int i = 0; i < m; ++i) a += abs2(A[i + tid * lda]);
+    s[tid] = sqrt(a);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int j = 0; j < n; ++j) {
+      int k = j;
+      for (int l = j + 1; l < n; ++l)
+        if (s[l] > s[k]) k = l;
+      if (k != j) {
+        double t = s[j]; s[j] = s[k]; s[k] = t;
+        for (int i = 0; i < m; ++i) { T x = A[i + j * lda]; A[i + j * lda] = A[i + k * lda]; A[i + k * lda] = x; }
+        for (int i = 0; i < n; ++i) { T x = V[i + j * ldv]; V[i + j * ldv] = V[i + k * ldv]; V[i + k * ldv] = x; }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// In-place Cholesky A = L L^H of an n x n Hermitian matrix (row-major, lda),
+// lower triangle overwritten by L (upper triangle left as is).  Returns true
+// when every pivot is positive and finite.  Whole block; red: >= 64 doubles.
+template <class T>
+NTU_DEV bool block_cholesky(T* A, int n, int lda, double* red) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    double piv = rev(A[k * lda + k]);
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      if (threadIdx.x == 0) bad = 1;
+      __syncthreads();
+      break;
+    }
+    double lkk = sqrt(piv), inv = 1.0 / lkk;
+    // column k below the diagonal
+    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A[i * lda + k] = A[i * lda + k] * inv;
+    __syncthreads();
+    if (threadIdx.x == 0) A[k * lda + k] = realv<T>(lkk);
+    // trailing update of the lower triangle: A[i][j] -= L[i][k] conj(L[j][k]), k < j <= i
+    const int m = n - k - 1;
+    const long long tot = (long long)m * (m + 1) / 2;
+    for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
+      // map e -> (ii, jj) with 0 <= jj <= ii < m (row-wise packing)
+      int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+      while ((long long)(ii + 1) * (ii + 2) / 2 <= e) ++ii;
+      while ((long long)ii * (ii + 1) / 2 > e) --ii;
+      int jj = (int)(e - (long long)ii * (ii + 1) / 2);
+      int i = k + 1 + ii, j = k + 1 + jj;
+      A[i * lda + j] = A[i * lda + j] - mulc(A[i * lda + k], A[j * lda + k]);
+    }
+    __syncthreads();
+  }
+  bool ok = (bad == 0);
+  __syncthreads();
+  return ok;
+}
+
+// Parallel cyclic two-sided Jacobi eigensolver of an n x n Hermitian matrix
+// (row-major, lda; destroyed: on return its diagonal holds the eigenvalues)
+// with eigenvectors accumulated in V (row-major, ldv; column j = vector j).
+// Round-robin ordering: n/2 disjoint rotations per round.  Whole block.
+// par: shared scratch of >= 3 * ((n+1)/2) doubles + same count of T.
+template <class T>
+NTU_DEV void block_jacobi_eigh(T* A, int n, int lda, T* V, int ldv, double* pc, double* ps, T* pe,
+                               int* sh_cnt, double fro) {
+  const int tid = threadIdx.x;
+  for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
+    int i = (int)(e / n), j = (int)(e % n);
+    V[i * ldv + j] = realv<T>(i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (n < 2) return;
+  const int n2 = (n + 1) & ~1, np = n2 / 2;
+  // entries below 1e-17 ||A||_F are rounding noise: rotating them cannot
+  // change any eigenvalue beyond that absolute level and never converges
+  const double tiny = 1e-17 * fro;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) *sh_cnt = 0;
+    __syncthreads();
+    for (int r = 0; r < n2 - 1; ++r) {
+      // rotation parameters of every pair of the round from the current A
+      for (int k = tid; k < np; k += blockDim.x) {
+        int p, q;
+        rr_pair(n2, r, k, p, q);
+        pc[k] = 1.0; ps[k] = 0.0; pe[k] = realv<T>(1.0);
+        if (q >= n) continue;
+        T apq = A[p * lda + q];
+        double g = absv(apq);
+        double app = rev(A[p * lda + p]), aqq = rev(A[q * lda + q]);
+        if (!(g > 1e-15 * sqrt(fabs(app * aqq))) || !(g > tiny)) continue;
+        double zeta = (aqq - app) / (2.0 * g);
+        double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        double c = 1.0 / sqrt(1.0 + t * t);
+        pc[k] = c; ps[k] = c * t; pe[k] = conjv(phasev(apq));  // e^{-i phi}
+        atomicAdd(sh_cnt, 1);
+      }
+      __syncthreads();
+      // rows:  row_p' = c row_p - s e^{i phi} row_q ; row_q' = s row_p + c e^{i phi} row_q
+      for (long long e = tid; e < (long long)np * n; e += blockDim.x) {
+        int k = (int)(e / n), j = (int)(e % n);
+        if (ps[k] == 0.0) continue;
+        int p, q;
+        rr_pair(n2, r, k, p, q);
+        double c = pc[k], s = ps[k];
+        T ec = conjv(pe[k]);
+        T x = A[p * lda + j], y = ec * A[q * lda + j];
+        A[p * lda + j] = c * x - s * y;
+        A[q * lda + j] = s * x + c * y;
+      }
+      __syncthreads();
+      // columns of A and V:  col_p' = c col_p - s e^{-i phi} col_q ; col_q' = s col_p + c e^{-i phi} col_q
+      for (long long e = tid; e < (long long)np * n; e += blockDim.x) {
+        int k = (int)(e / n), i = (int)(e % n);
+        if (ps[k] == 0.0) continue;
+        int p, q;
+        rr_pair(n2, r, k, p, q);
+        double c = pc[k], s = ps[k];
+        T ev = pe[k];
+        T x = A[i * lda + p], y = A[i * lda + q] * ev;
+        A[i * lda + p] = c * x - s * y;
+        A[i * lda + q] = s * x + c * y;
+        x = V[i * ldv + p]; y = V[i * ldv + q] * ev;
+        V[i * ldv + p] = c * x - s * y;
+        V[i * ldv + q] = s * x + c * y;
+      }
+      __syncthreads();
+    }
+    int cnt = *sh_cnt;
+    __syncthreads();
+    if (cnt == 0) break;
+  }
+}
+
+}  // namespace ntu

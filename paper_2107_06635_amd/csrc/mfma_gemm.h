@@ -1,0 +1,31 @@
+// Descriptors of the NT products C(i, j) = sum_k A(i, k) B(j, k) used by the
+// environment contraction, and the split-precision MFMA path.
+#pragma once
+#include <algorithm>
+#include "common.h"
+#include "ntu.h"
+#include "kernels.h"
+
+namespace ntu {
+
+struct GemmNT {
+  int M, N, K, batch;
+  Idx3 Ab, Ai, Ak;   // A: item offset, row i, column k
+  Idx3 Bb, Bj, Bk;   // B: item offset, row j, column k
+  Idx3 Cb, Ci, Cj;   // C: item offset, row i, column j
+  int conjA, conjB;
+};
+
+// Left/Right, L1, L2 and g of the environment contraction in split precision
+// (BF16x3, FP16x3 or BF16x6 on MFMA with FP32 accumulation).  Inputs QXe,
+// QXp, QYe, QYp, EtopT, EbotT are in the compute type; H0, H1, H2 hold the
+// FP32 intermediates; g is written in the compute type.
+hipError_t launch_env_heavy_mixed(bool cplx, int precision, int batch, int p, int D, int R, const void* QXe,
+                                  const void* QXp, const void* QYe, const void* QYp, const void* ETT,
+                                  const void* EBT, long long es, long long qs, long long hs, void* H0, void* H1,
+                                  void* H2, void* g, hipStream_t st, const struct ProfHook& ph);
+
+// bytes of FP64 split-K partial sums the final assembly needs after H2
+size_t mixed_partial_bytes(bool cplx, int batch, int R, int D);
+
+}  // namespace ntu

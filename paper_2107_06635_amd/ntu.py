@@ -1,0 +1,268 @@
+"""Python binding of libntu (C ABI in ``include/ntu.h``).
+
+Argument marshalling only: every numerical step runs in the HIP kernels of
+``libntu.so``.  Tensors are torch tensors on the GPU; outputs are allocated
+with torch (device memory) and filled by the library on the current torch
+stream.  There is no fallback: if the library is missing or a tensor is not
+on the GPU, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libntu.so")
+
+NTU_OK = 0
+F64, C128, C64 = 0, 1, 2
+PREC_F64, PREC_BF16X3, PREC_FP16X3, PREC_BF16X6 = 0, 1, 2, 3
+FIX_HERM, FIX_HERM_CLIP = 0, 1
+BOND_H1, BOND_H2, BOND_V1, BOND_V2 = 0, 1, 2, 3
+PRECISIONS = {"f64": PREC_F64, "bf16x3": PREC_BF16X3, "fp16x3": PREC_FP16X3, "bf16x6": PREC_BF16X6}
+
+EXPORTED = (
+    "ntu_ctx_create", "ntu_ctx_destroy", "ntu_set_stream", "ntu_last_error", "ntu_workspace_bytes",
+    "ntu_version", "ntu_gate_split", "ntu_reduce_qr", "ntu_env_contract", "ntu_metric_fix",
+    "ntu_fit_opts_default", "ntu_bond_fit", "ntu_recombine", "ntu_step_opts_default", "ntu_trotter_step",
+    "ntu_profile_enable", "ntu_profile_read", "ntu_profile_kind_name",
+)
+
+
+class FitOpts(ctypes.Structure):
+    _fields_ = [("n_iter", ctypes.c_int), ("early_stop", ctypes.c_int), ("conv_tol", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("n_tol", ctypes.c_int), ("tol", ctypes.c_double * 16),
+                ("tie", ctypes.c_double)]
+
+
+class StepOpts(ctypes.Structure):
+    _fields_ = [("n_bonds", ctypes.c_int), ("order", ctypes.c_int * 8), ("precision", ctypes.c_int),
+                ("fix_mode", ctypes.c_int), ("fit", FitOpts)]
+
+
+_lib = None
+
+
+def load():
+    """Load libntu.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+    L.ntu_ctx_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, i32, i32, i32]
+    L.ntu_ctx_destroy.argtypes = [vp]
+    L.ntu_set_stream.argtypes = [vp, vp]
+    L.ntu_last_error.argtypes = [vp]
+    L.ntu_last_error.restype = ctypes.c_char_p
+    L.ntu_workspace_bytes.argtypes = [vp]
+    L.ntu_workspace_bytes.restype = ctypes.c_size_t
+    L.ntu_version.restype = ctypes.c_char_p
+    L.ntu_gate_split.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.ntu_reduce_qr.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp]
+    L.ntu_env_contract.argtypes = [vp, i32, i32, vp, vp, ctypes.POINTER(vp), i32, vp]
+    L.ntu_metric_fix.argtypes = [vp, i32, i32, vp, i32, vp]
+    L.ntu_fit_opts_default.argtypes = [ctypes.POINTER(FitOpts)]
+    L.ntu_fit_opts_default.restype = None
+    L.ntu_bond_fit.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(FitOpts), vp, vp, vp]
+    L.ntu_recombine.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
+    L.ntu_step_opts_default.argtypes = [ctypes.POINTER(StepOpts)]
+    L.ntu_step_opts_default.restype = None
+    L.ntu_trotter_step.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(StepOpts), vp]
+    L.ntu_profile_enable.argtypes = [vp, i32]
+    L.ntu_profile_read.argtypes = [vp, dp, ctypes.POINTER(i32), i32]
+    L.ntu_profile_kind_name.argtypes = [i32]
+    L.ntu_profile_kind_name.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("ntu_last_error", "ntu_workspace_bytes", "ntu_version", "ntu_fit_opts_default",
+                        "ntu_step_opts_default", "ntu_profile_kind_name"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def fit_opts(n_iter=20, early_stop=False, conv_tol=1e-12, kappa=1e-10, ladder=None, tie=1e-15) -> FitOpts:
+    o = FitOpts()
+    load().ntu_fit_opts_default(ctypes.byref(o))
+    o.n_iter, o.early_stop, o.conv_tol, o.kappa, o.tie = n_iter, int(early_stop), conv_tol, kappa, tie
+    if ladder is not None:
+        o.n_tol = len(ladder)
+        for i, t in enumerate(ladder):
+            o.tol[i] = t
+    return o
+
+
+def step_opts(precision="f64", fix_mode=FIX_HERM_CLIP, order=(0, 1, 2, 3), **fit) -> StepOpts:
+    o = StepOpts()
+    load().ntu_step_opts_default(ctypes.byref(o))
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.fix_mode = fix_mode
+    o.n_bonds = len(order)
+    for i, b in enumerate(order):
+        o.order[i] = b
+    o.fit = fit_opts(**fit)
+    return o
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("libntu operates on GPU tensors only")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t):
+    return {torch.float64: F64, torch.complex128: C128, torch.complex64: C64}[t.dtype]
+
+
+class Context:
+    """An ``ntu_ctx``: workspace for items up to ``max_D`` and ``max_batch``."""
+
+    def __init__(self, complex_=True, d=2, d_anc=1, r_g=2, max_D=8, max_batch=1, device=0):
+        self.L = load()
+        self.cplx = complex_
+        self.dtype = torch.complex128 if complex_ else torch.float64
+        self.d, self.d_anc, self.r_g, self.max_D = d, d_anc, r_g, max_D
+        self.p = d * d_anc
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        st = self.L.ntu_ctx_create(ctypes.byref(h), device, C128 if complex_ else F64, d, d_anc, r_g, max_D,
+                                   max_batch)
+        if st != NTU_OK:
+            raise RuntimeError(f"ntu_ctx_create failed ({st}): {self.L.ntu_last_error(None).decode()}")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ntu_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st, what):
+        if st != NTU_OK:
+            raise RuntimeError(f"{what} failed ({st}): {self.L.ntu_last_error(self.h).decode()}")
+
+    def bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self.check(self.L.ntu_set_stream(self.h, ctypes.c_void_p(s)), "ntu_set_stream")
+
+    def empty(self, *shape, dtype=None):
+        return torch.empty(*shape, dtype=dtype or self.dtype, device=self.device)
+
+    def zeros(self, *shape, dtype=None):
+        return torch.zeros(*shape, dtype=dtype or self.dtype, device=self.device)
+
+
+def ntu_gate_split(ctx: Context, gate: torch.Tensor):
+    """gate: (batch, d^2, d^2) -> GA, GB: (batch, d, d, r_g), sigma: (batch, d^2)."""
+    b, d, r = gate.shape[0], ctx.d, ctx.r_g
+    GA, GB = ctx.empty(b, d, d, r), ctx.empty(b, d, d, r)
+    sig = ctx.empty(b, d * d, dtype=torch.float64)
+    ctx.bind_stream()
+    ctx.check(ctx.L.ntu_gate_split(ctx.h, b, _ptr(gate), _ptr(GA), _ptr(GB), _ptr(sig)), "ntu_gate_split")
+    return GA, GB, sig
+
+
+def ntu_reduce_qr(ctx: Context, site: torch.Tensor, gate_factor: torch.Tensor, side: int):
+    """site: (batch, p, D, D, D, D); gate_factor: (batch, d, d, r_g) -> Q (batch, pD^3, R), R (batch, R, R)."""
+    b, D = site.shape[0], site.shape[2]
+    Rd = D * ctx.r_g
+    Q, R = ctx.empty(b, ctx.p * D ** 3, Rd), ctx.empty(b, Rd, Rd)
+    ctx.bind_stream()
+    ctx.check(ctx.L.ntu_reduce_qr(ctx.h, b, D, _ptr(site), _dtype_code(site), _ptr(gate_factor), side, _ptr(Q),
+                                  _ptr(R)), "ntu_reduce_qr")
+    return Q, R
+
+
+def ntu_env_contract(ctx: Context, QX, QY, nbr, precision="f64", D=None):
+    """QX, QY: (batch, pD^3, R); nbr: six (batch, p, D, D, D, D) -> g (batch, R^2, R^2)."""
+    b = QX.shape[0]
+    if D is None:
+        D = nbr[0].shape[2]
+    Rd = D * ctx.r_g
+    g = ctx.empty(b, Rd * Rd, Rd * Rd)
+    arr = (ctypes.c_void_p * 6)(*[_ptr(t) for t in nbr])
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    ctx.bind_stream()
+    ctx.check(ctx.L.ntu_env_contract(ctx.h, b, D, _ptr(QX), _ptr(QY), arr, prec, _ptr(g)), "ntu_env_contract")
+    return g
+
+
+def ntu_metric_fix(ctx: Context, g: torch.Tensor, D: int, mode=FIX_HERM_CLIP):
+    """In place on g; returns stats (batch, 8)."""
+    b = g.shape[0]
+    stats = ctx.zeros(b, 8, dtype=torch.float64)
+    ctx.bind_stream()
+    ctx.check(ctx.L.ntu_metric_fix(ctx.h, b, D, _ptr(g), mode, _ptr(stats)), "ntu_metric_fix")
+    return stats
+
+
+def fit_stats_len(n_iter, D):
+    return 16 + 4 * n_iter + D
+
+
+def ntu_bond_fit(ctx: Context, g, RX, RY, D, opts: FitOpts | None = None):
+    """-> MX, MY (batch, R, D), stats (batch, fit_stats_len)."""
+    opts = opts or fit_opts()
+    b = g.shape[0]
+    Rd = D * ctx.r_g
+    MX, MY = ctx.empty(b, Rd, D), ctx.empty(b, Rd, D)
+    stats = ctx.zeros(b, fit_stats_len(opts.n_iter, D), dtype=torch.float64)
+    ctx.bind_stream()
+    ctx.check(ctx.L.ntu_bond_fit(ctx.h, b, D, _ptr(g), _ptr(RX), _ptr(RY), ctypes.byref(opts), _ptr(MX), _ptr(MY),
+                                 _ptr(stats)), "ntu_bond_fit")
+    return MX, MY, stats
+
+
+def ntu_recombine(ctx: Context, QX, QY, MX, MY, D):
+    b = QX.shape[0]
+    Xn, Yn = ctx.empty(b, ctx.p, D, D, D, D), ctx.empty(b, ctx.p, D, D, D, D)
+    ctx.bind_stream()
+    ctx.check(ctx.L.ntu_recombine(ctx.h, b, D, _ptr(QX), _ptr(QY), _ptr(MX), _ptr(MY), _ptr(Xn), _ptr(Yn)),
+              "ntu_recombine")
+    return Xn, Yn
+
+
+def step_stats_len(n_iter, D):
+    return 8 + fit_stats_len(n_iter, D)
+
+
+def ntu_trotter_step(ctx: Context, A, B, gate_factors, opts: StepOpts | None = None, stats=True):
+    """In place on A, B (batch, p, D, D, D, D); gate_factors (batch, 4, 2, d, d, r_g).
+    Returns stats (batch, n_bonds, step_stats_len) or None."""
+    opts = opts or step_opts()
+    b, D = A.shape[0], A.shape[2]
+    st = ctx.zeros(b, opts.n_bonds, step_stats_len(opts.fit.n_iter, D), dtype=torch.float64) if stats else None
+    ctx.bind_stream()
+    ctx.check(ctx.L.ntu_trotter_step(ctx.h, b, D, _ptr(A), _ptr(B), _ptr(gate_factors), ctypes.byref(opts),
+                                     _ptr(st)), "ntu_trotter_step")
+    return st
+
+
+def ntu_profile_enable(ctx: Context, on=True):
+    ctx.check(ctx.L.ntu_profile_enable(ctx.h, int(on)), "ntu_profile_enable")
+
+
+def ntu_profile_read(ctx: Context):
+    """-> {kernel class: (total ms, launches)} for the launches recorded since the last read."""
+    n = 32
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int * n)()
+    k = ctx.L.ntu_profile_read(ctx.h, ms, cnt, n)
+    if k < 0:
+        raise RuntimeError("ntu_profile_read failed")
+    return {ctx.L.ntu_profile_kind_name(i).decode(): (ms[i], cnt[i]) for i in range(k) if cnt[i] > 0}
