@@ -1,12 +1,16 @@
 """Throughput of the NTU hot path on one MI355X.
 
-Workload (default): imaginary-time evolution of the thermal purification of
-the 2D transverse-field Ising model, D = 8, physical d = 2 plus ancilla d = 2
-(p = 4), real arithmetic, gate exp(-0.005 h_b) at h_x = 2.5, from the beta = 0
-product purification.  One step = one first-order Trotter sweep = 4 NTU bond
-updates (H1, H2, V1, V2), each: reduce + QR, environment contraction (split
-precision on MFMA), metric repair (FP64), bond fit (FP64, <= 20 ALS
-iterations, early stop at 1e-12 N), recombination.
+Default workload ("batched", configuration 4): 256 independent NTU updates
+of a horizontal bond of the 2D transverse-field Ising model, D drawn
+uniformly from {3..8}, field h_x uniform in [2.5, 3.5], real-time gate
+exp(-0.01 i h_b), random complex Gaussian site tensors (drawn as complex64).
+Items are grouped by D; one step = all 256 updates, each: gate split once at
+set-up, then reduce + QR, environment contraction (split precision on MFMA),
+metric repair (FP64), bond fit (FP64, <= 20 ALS iterations, early stop at
+1e-12 N), recombination.
+
+"thermal" (configuration 3): imaginary-time evolution of the D = 8 thermal
+purification (p = 4, real), one step = one Trotter sweep of 4 bond updates.
 
 Prints ONE JSON line.  ``value`` = bond updates per second of the mixed path;
 the plain FP64 GPU path runs the same steps from the same state beside it.
@@ -32,30 +36,79 @@ PEAK_HBM = 8.0e12        # B/s
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--D", type=int, default=8)
-    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16x6", "f64"])
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batched", choices=["batched", "thermal"])
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16x6", "fp16x3", "f64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--profile-steps", type=int, default=1)
     return ap.parse_args()
 
 
-def fit_flops_per_launch(R, Dn, half_steps, cplx):
-    """Algorithmic FP64 flops of one bond-fit launch (certified solves):
-    per half-step g_s = K^H g K (R^4 Dn + R^3 Dn^2 MACs), Cholesky (nx^3/3),
-    triangular inverse (nx^3/6), two triangular mat-vecs (nx^2), error
-    d^H g d (R^4); plus the SVDU / balancing products."""
+def fit_flops(R, Dn, half_steps, cplx):
+    """Algorithmic FP64 flops of one bond fit with certified solves:
+    per half-step g_s = K^H g K (R^4 Dn + R^3 Dn^2 MACs), Cholesky (nx^3/6),
+    two triangular solves (nx^2), error d^H g d (R^4); plus g y, the SVDU
+    error and the balancing product (3 R^4)."""
     nx = R * Dn
-    macs = half_steps * (R ** 4 * Dn + R ** 3 * Dn ** 2 + nx ** 3 / 2 + nx ** 2 + R ** 4)
-    macs += 3 * R ** 4   # g y, SVDU error, balancing product
+    macs = half_steps * (R ** 4 * Dn + R ** 3 * Dn ** 2 + nx ** 3 / 6 + nx ** 2 + R ** 4) + 3 * R ** 4
     return macs * (8 if cplx else 2)
 
 
-def e6_flops(R, D, cplx):
+def env_assembly_flops(R, D, cplx):
+    """g = L2 Right^T: (R^2 x D^4) times (D^4 x R^2)."""
     return (8 if cplx else 2) * (R * R) * (R * R) * D ** 4
+
+
+class Job:
+    """One workload: a list of (D, batch tensors) buckets and a step function."""
+
+
+def build_batched(ntu, inputs, dev, torch, np):
+    items = inputs.workload_batched()
+    buckets = {}
+    for it in items:
+        buckets.setdefault(it["D"], []).append(it)
+    job = Job()
+    job.cplx, job.n_updates, job.items = True, len(items), items
+    job.buckets = []
+    for D in sorted(buckets):
+        its = buckets[D]
+        # one context (workspace) and one stream per bond dimension: the buckets run concurrently
+        ctx = ntu.Context(complex_=True, d=2, d_anc=1, r_g=2, max_D=D, max_batch=len(its))
+        ctx.bind_stream()
+        # complex64 values upcast once at set-up; the hot path runs in complex128
+        A = torch.from_numpy(np.stack([i["A"] for i in its])).to(dev).to(torch.complex128).contiguous()
+        B = torch.from_numpy(np.stack([i["B"] for i in its])).to(dev).to(torch.complex128).contiguous()
+        G = torch.from_numpy(np.stack([i["gate"] for i in its])).to(dev).contiguous()
+        GA, GB, _ = ntu.ntu_gate_split(ctx, G)
+        gf = torch.zeros(len(its), 4, 2, 2, 2, 2, dtype=torch.complex128, device=dev)
+        gf[:, :, 0] = GA[:, None]
+        gf[:, :, 1] = GB[:, None]
+        job.buckets.append(dict(D=D, A=A, B=B, gf=gf.contiguous(), n=len(its), ctx=ctx,
+                                stream=torch.cuda.Stream(device=dev)))
+    job.order = (ntu.BOND_H1,)
+    job.bonds_per_item = 1
+    return job
+
+
+def build_thermal(ntu, inputs, dev, torch, np, D=8):
+    w = inputs.workload_thermal(D=D)
+    ctx = ntu.Context(complex_=False, d=2, d_anc=2, r_g=2, max_D=D, max_batch=1)
+    ctx.bind_stream()
+    G = torch.from_numpy(np.ascontiguousarray(w["gates"][0][None])).to(dev)
+    GA, GB, _ = ntu.ntu_gate_split(ctx, G)
+    gf = torch.stack([torch.stack([GA[0], GB[0]])] * 4)[None].contiguous()
+    A = torch.from_numpy(w["A"][None]).to(dev).contiguous()
+    B = torch.from_numpy(w["B"][None]).to(dev).contiguous()
+    job = Job()
+    job.cplx, job.n_updates, job.w = False, 4, w
+    job.buckets = [dict(D=D, A=A, B=B, gf=gf, n=1, ctx=ctx, stream=torch.cuda.current_stream(dev))]
+    job.order = (0, 1, 2, 3)
+    job.bonds_per_item = 4
+    return job
 
 
 def main():
@@ -70,44 +123,48 @@ def main():
     from paper_2107_06635_amd import ntu
 
     dev = torch.device("cuda", 0)
-    D, K, W = args.D, args.steps, args.warmup
-    w = inputs.workload_thermal(D=D)
-    ctx = ntu.Context(complex_=False, d=2, d_anc=2, r_g=2, max_D=D, max_batch=1)
-    ctx.bind_stream()
-    # gate factors on the GPU (the same gate on all four bonds)
-    G = torch.from_numpy(np.ascontiguousarray(w["gates"][0][None])).to(dev)
-    GA, GB, _ = ntu.ntu_gate_split(ctx, G)
-    gf = torch.stack([torch.stack([GA[0], GB[0]])] * 4)[None].contiguous()
-    A = torch.from_numpy(w["A"][None]).to(dev).contiguous()
-    B = torch.from_numpy(w["B"][None]).to(dev).contiguous()
+    K, W = args.steps, args.warmup
+    job = (build_batched if args.workload == "batched" else build_thermal)(ntu, inputs, dev, torch, np)
     fit = dict(n_iter=20, early_stop=True, conv_tol=1e-12)
-    opts = ntu.step_opts(args.precision, **fit)
-    opts64 = ntu.step_opts("f64", **fit)
+    opts = ntu.step_opts(args.precision, order=job.order, **fit)
+    opts64 = ntu.step_opts("f64", order=job.order, **fit)
 
-    # warm-up from beta = 0 on the FP64 path, so both paths start from the same state
+    def one_step(state, o, keep_stats):
+        # fork: every bucket stream waits for the main stream, join: the main stream waits for all
+        main = torch.cuda.current_stream(dev)
+        out = []
+        for bk, (A, B) in zip(job.buckets, state):
+            bk["stream"].wait_stream(main)
+            with torch.cuda.stream(bk["stream"]):
+                out.append(ntu.ntu_trotter_step(bk["ctx"], A, B, bk["gf"], o, stats=keep_stats))
+        for bk in job.buckets:
+            main.wait_stream(bk["stream"])
+        return out
+
+    # warm-up on the FP64 path so that both paths start from the same state
+    state0 = [(bk["A"], bk["B"]) for bk in job.buckets]
     for _ in range(W):
-        ntu.ntu_trotter_step(ctx, A, B, gf, opts64, stats=False)
+        one_step(state0, opts64, False)
     torch.cuda.synchronize()
-    A0, B0 = A.clone(), B.clone()
+    init = [(A.clone(), B.clone()) for A, B in state0]
 
     def run(o, steps, keep_stats=False):
-        Aw, Bw = A0.clone(), B0.clone()
+        state = [(A.clone(), B.clone()) for A, B in init]
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         stats = []
         ev0.record()
         for _ in range(steps):
-            st = ntu.ntu_trotter_step(ctx, Aw, Bw, gf, o, stats=keep_stats)
-            if keep_stats:
-                stats.append(st)
+            stats.append(one_step(state, o, keep_stats))
         ev1.record()
         torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1), Aw, Bw, stats
+        return ev0.elapsed_time(ev1), state, stats
 
-    ms, Am, Bm, stm = run(opts, K, keep_stats=True)
+    ms, state_m, stm = run(opts, K, keep_stats=True)
+    upd = job.n_updates
     result = {
         "metric": METRIC,
-        "value": 4 * K / (ms / 1e3),
+        "value": upd * K / (ms / 1e3),
         "unit": "bond_updates/s",
         "n_gpus": 1,
         "steps": K,
@@ -118,74 +175,122 @@ def main():
         "vs_baseline": None,
         "dtype": f"{args.precision}+f64",
         "data": "synthetic",
-        "config": {"workload": "thermal purification (configuration 3), D=8", "D": D, "p": 4, "d": 2, "d_anc": 2,
-                   "h_x": 2.5, "dbeta": 0.005, "env_precision": args.precision,
-                   "fit": "fp64, <=20 ALS iterations, early stop 1e-12 N", "bond_updates_per_step": 4,
-                   "start": f"beta=0 purification + {W} FP64 warm-up steps"},
     }
-    st_all = torch.stack(stm).cpu().numpy()[:, 0]          # steps x bonds x len
-    fl = ntu.fit_stats_len(20, D)
-    iters = st_all[:, :, 8 + 6]
-    dn = st_all[:, :, 8 + 4]
-    result["fit_iterations_mean"] = float(iters.mean())
-    result["fit_eig_fallbacks"] = int(st_all[:, :, 8 + 7].sum())
-    result["delta_max"] = float(st_all[:, :, 8 + 3].max())
+    if args.workload == "batched":
+        result["config"] = {"workload": "configuration 4: 256 independent bond updates, D uniform in {3..8}",
+                            "items": upd, "D_counts": {str(bk["D"]): bk["n"] for bk in job.buckets},
+                            "h_x": "uniform [2.5, 3.5]", "dt": 0.01, "env_precision": args.precision,
+                            "fit": "fp64, <=20 ALS iterations, early stop 1e-12 N",
+                            "storage": "values drawn as complex64, hot path in complex128"}
+    else:
+        result["config"] = {"workload": "configuration 3: thermal purification, D=8, p=4, real", "D": 8,
+                            "h_x": 2.5, "dbeta": 0.005, "env_precision": args.precision,
+                            "fit": "fp64, <=20 ALS iterations, early stop 1e-12 N", "bond_updates_per_step": 4,
+                            "start": f"beta=0 purification + {W} FP64 warm-up steps"}
+    # fit statistics per bucket
+    its, eig, dmax = {}, 0, 0.0
+    for bi, bk in enumerate(job.buckets):
+        st = torch.stack([s[bi] for s in stm]).cpu().numpy()  # steps x items x bonds x len
+        its[str(bk["D"])] = float(st[..., 8 + 6].mean())
+        eig += int(st[..., 8 + 7].sum())
+        dmax = max(dmax, float(st[..., 8 + 3].max()))
+    result["fit_iterations_mean"] = its
+    result["fit_eig_fallbacks"] = eig
+    result["delta_max"] = dmax
+    phases = {}
+    for bi, bk in enumerate(job.buckets):
+        st = torch.stack([s[bi] for s in stm]).cpu().numpy()
+        ph = st[..., 8 + 10:8 + 15].reshape(-1, 5).mean(axis=0)
+        phases[str(bk["D"])] = {"certified": float(st[..., 8 + 9].mean()), "cg_iters": float(st[..., 8 + 15].mean()),
+                                "kcycles": dict(zip(["setup", "form", "solve", "error", "balance"],
+                                                    [round(x / 1e3, 1) for x in ph]))}
+    result["fit_phases"] = phases
 
     if not args.no_fp64:
-        ms64, A64, B64, _ = run(opts64, K)
-        result["fp64_path"] = {"value": 4 * K / (ms64 / 1e3), "ms_per_step": ms64 / K}
+        ms64, state64, _ = run(opts64, K)
+        result["fp64_path"] = {"value": upd * K / (ms64 / 1e3), "ms_per_step": ms64 / K}
         result["speedup_vs_fp64_path"] = result["value"] / result["fp64_path"]["value"]
-        # metric error of the split path on the state reached: same isometries, both precisions
-        Q, Rm = ntu.ntu_reduce_qr(ctx, Am, gf[:, 0, 0].contiguous(), 0)
-        QY, _ = ntu.ntu_reduce_qr(ctx, Bm, gf[:, 0, 1].contiguous(), 1)
-        nb = [Bm, Bm, Bm, Am, Am, Am]
-        g64 = ntu.ntu_env_contract(ctx, Q, QY, nb, "f64", D=D)
-        gmx = ntu.ntu_env_contract(ctx, Q, QY, nb, args.precision, D=D)
-        result["metric_rel_err_vs_fp64_path"] = float(torch.linalg.norm(gmx - g64) / torch.linalg.norm(g64))
-        result["state_rel_diff_vs_fp64_path"] = float(
-            torch.linalg.norm(torch.cat([Am.flatten(), Bm.flatten()]) - torch.cat([A64.flatten(), B64.flatten()]))
-            / torch.linalg.norm(torch.cat([A64.flatten(), B64.flatten()])))
+        # metric error of the split path: largest bucket, same isometries, both precisions
+        bk = job.buckets[-1]
+        ctx = bk["ctx"]
+        ctx.bind_stream()
+        A, B = state_m[-1]
+        Q, _ = ntu.ntu_reduce_qr(ctx, A, bk["gf"][:, 0, 0].contiguous(), 0)
+        QY, _ = ntu.ntu_reduce_qr(ctx, B, bk["gf"][:, 0, 1].contiguous(), 1)
+        nb = [B, B, B, A, A, A]
+        g64 = ntu.ntu_env_contract(ctx, Q, QY, nb, "f64", D=bk["D"])
+        gmx = ntu.ntu_env_contract(ctx, Q, QY, nb, args.precision, D=bk["D"])
+        errs = [float(torch.linalg.norm(gmx[i] - g64[i]) / torch.linalg.norm(g64[i])) for i in range(gmx.shape[0])]
+        result["metric_rel_err_vs_fp64_path"] = {"D": bk["D"], "max": max(errs), "mean": sum(errs) / len(errs)}
 
-    # live per-kernel timing with HIP events on the library's stream
-    ntu.ntu_profile_enable(ctx, True)
+    # live per-kernel timing with HIP events on each context's stream (summed over buckets)
+    for bk in job.buckets:
+        ntu.ntu_profile_enable(bk["ctx"], True)
     run(opts, args.profile_steps)
-    prof = ntu.ntu_profile_read(ctx)
-    ntu.ntu_profile_enable(ctx, False)
+    prof = {}
+    for bk in job.buckets:
+        for k, (ms_k, n_k) in ntu.ntu_profile_read(bk["ctx"]).items():
+            a, b = prof.get(k, (0.0, 0))
+            prof[k] = (a + ms_k, b + n_k)
+        ntu.ntu_profile_enable(bk["ctx"], False)
     nprof = max(1, args.profile_steps)
-    result["kernel_ms_per_step"] = {k: v[0] / nprof for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
-    R = 2 * D
-    dom = max(prof.items(), key=lambda kv: kv[1][0])[0] if prof else None
-    roof = {}
-    if dom == "bond_fit":
-        t = prof["bond_fit"][0] / prof["bond_fit"][1] / 1e3
-        hs = 2 * float(iters.mean())
-        fl_launch = fit_flops_per_launch(R, float(dn.mean()), hs, cplx=False)
-        roof = {"kernel": "k_bond_fit", "bound": "alu", "achieved": fl_launch / t / 1e12, "peak": PEAK_FP64 / 1e12,
-                "unit": "TFLOP/s", "frac": fl_launch / t / PEAK_FP64, "traffic": None,
-                "avg_launch_us": t * 1e6, "flops_per_launch": fl_launch}
+    result["kernel_ms_per_step"] = {k: round(v[0] / nprof, 4) for k, v in
+                                    sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    # roofline of the dominant kernel class
+    fit_fl = 0.0
+    for bi, bk in enumerate(job.buckets):
+        st = torch.stack([s[bi] for s in stm]).cpu().numpy()
+        R = 2 * bk["D"]
+        for row in st.reshape(-1, st.shape[-1]):
+            fit_fl += fit_flops(R, row[8 + 4], 2 * row[8 + 6], job.cplx)
+    fit_fl /= K                                            # per step
+    e6_fl = sum(env_assembly_flops(2 * bk["D"], bk["D"], job.cplx) * bk["n"] * job.bonds_per_item
+                for bk in job.buckets)                    # per step
+    rl = {}
+    if "bond_fit" in prof:
+        t = prof["bond_fit"][0] / nprof / 1e3
+        n_l = prof["bond_fit"][1] / nprof
+        rl["bond_fit"] = {"kernel": "k_bond_fit", "bound": "alu", "achieved": fit_fl / t / 1e12,
+                          "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": fit_fl / t / PEAK_FP64,
+                          "traffic": None, "avg_launch_us": t / n_l * 1e6, "launches_per_step": n_l,
+                          "flops_per_step": fit_fl}
     if "env_e6" in prof:
-        t6 = prof["env_e6"][0] / prof["env_e6"][1] / 1e3
-        f6 = e6_flops(R, D, cplx=False)
-        e6 = {"kernel": "k_mfma_nt (metric assembly)", "bound": "mfma", "achieved": f6 / t6 / 1e12,
-              "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s", "frac": f6 / t6 / PEAK_BF16, "traffic": None,
-              "avg_launch_us": t6 * 1e6, "flops_per_launch": f6, "issued_mfma_flops_per_launch": 3 * f6}
-        result["roofline_env_assembly"] = e6
-        if not roof:
-            roof = e6
-    result["roofline"] = roof
+        t = prof["env_e6"][0] / nprof / 1e3
+        n_l = prof["env_e6"][1] / nprof
+        peak = PEAK_FP64 if args.precision == "f64" else PEAK_BF16
+        rl["env_e6"] = {"kernel": "k_mfma_nt (metric assembly)", "bound": "mfma", "achieved": e6_fl / t / 1e12,
+                        "peak": peak / 1e12, "unit": "TFLOP/s", "frac": e6_fl / t / peak, "traffic": None,
+                        "avg_launch_us": t / n_l * 1e6, "launches_per_step": n_l, "flops_per_step": e6_fl,
+                        "issued_mfma_flops_per_step": (3 if args.precision in ("bf16x3", "fp16x3") else 6) * e6_fl}
+    dom = max(prof.items(), key=lambda kv: kv[1][0])[0] if prof else None
+    result["roofline"] = rl.get(dom, rl.get("env_e6", {}))
+    result["roofline"]["dominant_class"] = dom
+    result["roofline_env_assembly"] = rl.get("env_e6")
 
     if not args.no_cpu:
         from oracle import ntu as O
-        An = A0.cpu().numpy()[0]
-        Bn = B0.cpu().numpy()[0]
-        GAo, GBo, _ = O.gate_split(w["gates"][0], 2, 2)
-        pairs = {b: (GAo, GBo) for b in O.BONDS}
         t0 = time.perf_counter()
         n_bonds = 0
-        while n_bonds < 16 and time.perf_counter() - t0 < args.cpu_seconds:
-            for b in O.BONDS:
-                An, Bn, _ = O.trotter_step(An, Bn, pairs, D, n_iter=20, conv_tol=1e-12, order=(b,))
+        if args.workload == "batched":
+            for it in job.items:
+                if time.perf_counter() - t0 > args.cpu_seconds:
+                    break
+                GAo, GBo, _ = O.gate_split(it["gate"], 2, 2)
+                A = it["A"].astype(np.complex128)
+                B = it["B"].astype(np.complex128)
+                X, Y, nbr = O._cluster(True, A, B)
+                O.bond_update(X, Y, nbr, GAo, GBo, it["D"], n_iter=20, conv_tol=1e-12)
                 n_bonds += 1
+            sample = f"first {n_bonds} of the 256 items in order (mixed D), oracle FP64 numpy/BLAS"
+        else:
+            An, Bn = init[0][0].cpu().numpy()[0], init[0][1].cpu().numpy()[0]
+            GAo, GBo, _ = O.gate_split(job.w["gates"][0], 2, 2)
+            pairs = {b: (GAo, GBo) for b in O.BONDS}
+            while n_bonds < 16 and time.perf_counter() - t0 < args.cpu_seconds:
+                for b in O.BONDS:
+                    An, Bn, _ = O.trotter_step(An, Bn, pairs, 8, n_iter=20, conv_tol=1e-12, order=(b,))
+                    n_bonds += 1
+            sample = f"{n_bonds} bond updates of the D=8 thermal state, oracle FP64 numpy/BLAS"
         el = time.perf_counter() - t0
         try:
             from threadpoolctl import threadpool_info
@@ -193,7 +298,7 @@ def main():
         except Exception:
             cores = os.cpu_count()
         result["cpu_baseline"] = {"value": n_bonds / el, "unit": "bond_updates/s", "cores": cores, "kind": "oracle",
-                                  "sample": f"{n_bonds} bond updates of the same D=8 state (oracle FP64, numpy/BLAS)"}
+                                  "sample": sample}
     print(json.dumps(result), flush=True)
 
 

@@ -202,7 +202,10 @@ void ntu_fit_opts_default(ntu_fit_opts* o);
  *   [0] N = vec(P)^H g vec(P)  [1] eps of the SVDU guess  [2] final eps
  *   [3] final eps / N          [4] Dn   [5] Dk (kept after balancing)
  *   [6] iterations done        [7] half-steps solved by eigendecomposition
- *   [8] non-finite flag        [9..15] reserved
+ *   [8] non-finite flag        [9] 1 if g was certified well conditioned
+ *   [10..14] GPU clock cycles spent in: set-up, half-step matrices, solves,
+ *            error evaluations, balancing
+ *   [15] mean conjugate-gradient iterations per certified half-step
  *   [16 + 2i + h]              eps after half-step h of iteration i
  *   [16 + 2 n_iter + 2i + h]   chosen tolerance of that half-step
  *   [16 + 4 n_iter + j]        normalised singular value j (0 beyond Dk)

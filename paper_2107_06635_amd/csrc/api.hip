@@ -124,7 +124,7 @@ ntu::ProfHook hook(ntu_ctx* c) {
 
 const char* const PROF_NAMES[ntu::PK_COUNT] = {
     "rotate", "gate_split", "reduce_qr", "env_edges", "env_qprep", "env_left_right", "env_e4", "env_e5",
-    "env_e6", "env_e6_reduce", "metric_herm", "metric_clip", "bond_fit", "recombine"};
+    "env_e6", "env_e6_reduce", "metric_herm", "metric_clip", "bond_fit", "recombine", "fit_certify"};
 
 ntu::FitParams fit_params(const ntu_fit_opts* o) {
   ntu::FitParams fp{};
@@ -305,11 +305,8 @@ ntu_status ntu_bond_fit(ntu_ctx* c, int batch, int D, const void* g, const void*
   if (!g || !RX || !RY || !MX || !MY) return fail(c, NTU_ERR_ARG, "NULL pointer");
   DeviceGuard guard(c->device);
   const int R = D * c->rg;
-  const ntu::ProfHook ph = hook(c);
-  ph(ntu::PK_FIT, 0);
   hipError_t e = ntu::launch_bond_fit(c->cplx, batch, D, R, g, RX, RY, fit_params(opts), MX, MY, stats,
-                                      ntu::fit_stats_len(opts->n_iter, D), c->ws, c->stream);
-  ph(ntu::PK_FIT, 1);
+                                      ntu::fit_stats_len(opts->n_iter, D), c->ws, c->stream, hook(c));
   return e == hipSuccess ? NTU_OK : hip_fail(c, e, "bond_fit");
 }
 
@@ -398,10 +395,8 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     double* sb = stats ? stats + (size_t)bi * sl : nullptr;
     NTU_STEP(ntu::launch_metric_fix(cp, batch, R * R, G, opts->fix_mode, sb, (int)s_item, c->ws, c->stream, ph),
              "metric_fix");
-    ph(ntu::PK_FIT, 0);
     NTU_STEP(ntu::launch_bond_fit(cp, batch, D, R, G, RX, RY, fp, MX, MY, sb ? sb + 8 : nullptr, (int)s_item, c->ws,
-                                  c->stream), "bond_fit");
-    ph(ntu::PK_FIT, 1);
+                                  c->stream, ph), "bond_fit");
     // new X -> (A or B), new Y -> the other, rotated back for vertical bonds
     void* outX = x_is_a ? A : B;
     void* outY = x_is_a ? B : A;

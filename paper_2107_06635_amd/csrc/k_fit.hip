@@ -14,6 +14,7 @@
 // zero (dependent directions) are removed first in both cases.
 #include "kernels.h"
 #include "linalg.h"
+#include <algorithm>
 
 namespace ntu {
 
@@ -26,11 +27,30 @@ NTU_HD long long fit_ws_elems(int D, int R) {
   long long n = (long long)R * R, nx = (long long)R * D;
   return n * nx      // G1
          + 3 * nx * nx  // g_s, A (Cholesky / eigen), X (inverse / eigenvectors)
-         + 3 * n;       // g y, d, g d
+         + 3 * n        // g y, d, g d
+         + n * n        // g with both index pairs swapped, (a b) -> (b a)
+         + 2 * n;       // g y in swapped order, spare
 }
 
 size_t fit_workspace_bytes(bool cplx, int batch, int D, int R) {
-  return (size_t)batch * fit_ws_elems(D, R) * (cplx ? 16 : 8) + 256;
+  // + one certification flag per item
+  return (size_t)batch * fit_ws_elems(D, R) * (cplx ? 16 : 8) + (size_t)batch * sizeof(int) + 512;
+}
+
+// ---------------------------------------------------------------------------
+// Certification of g (once per bond, in the fit kernel): a successful
+// Cholesky factorisation of g - s I with s = 10 tol_max ||g||_F proves
+// lambda_min(g) > s up to a backward error far below s.  Every half-step
+// matrix g_s = K^H g K has K with orthonormal (or exactly zero) columns, so
+// its eigenvalues lie in [lambda_min(g), lambda_max(g)] and no tolerance of
+// the ladder removes any of them.
+// ---------------------------------------------------------------------------
+constexpr int CHOL_BS = 16;
+
+// bytes of the fixed part of the fit kernel's dynamic shared memory
+NTU_HD size_t fit_shared_fixed_bytes(size_t el, int R) {
+  size_t b = (size_t)(R * R + 7 * FIT_RMAX * FIT_RMAX) * el + (FIT_RMAX + 16 * 64 + 64) * 8 + FIT_RMAX * FIT_RMAX * 4;
+  return (b + 15) / 16 * 16;
 }
 
 template <class T> struct FitShared {
@@ -241,6 +261,186 @@ NTU_DEV double fit_solve(const T* gs, int nx, const FitParams& fp, const FitShar
   return fp.tol[best];
 }
 
+
+// ---------------------------------------------------------------------------
+// Certified half-step.  g_s is assembled block by block: viewing g as R x R
+// blocks of size R x R, block (o, x) of the X half-step is
+//   g_s[(o, j'), (x, j)] = sum_{i, y} conj(Q[i][j']) g[(o i), (x y)] Q[y][j],
+// i.e. Q^H g_ox Q; the Y half-step does the same on the metric with both
+// index pairs swapped, gP[(b a), (b' a')] = g[(a b), (a' b')], and writes the
+// result in the (j, b) parameter order.  One wave per block, staged in
+// shared memory; every entry of g is read once.
+// ---------------------------------------------------------------------------
+constexpr int FAST_NX = 128;        // largest R D on the certified path
+constexpr int FIT_CERT_NMAX = 256;  // largest R^2 certified
+
+template <class T>
+NTU_DEV void fast_form_gs(const T* __restrict__ Gm, const T* __restrict__ gyv, int R, int Dn, int half, const T* Q,
+                          T* gs, T* J, T* wstage) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int n = R * R, nx = R * Dn, RR = R * R;
+  T* blk = wstage + (size_t)w * (RR + R * Dn);   // R x R block, then R x Dn product
+  T* tmp = blk + RR;
+  for (int bo = w; bo < RR; bo += nw) {
+    const int o = bo / R, x = bo % R;
+    // stage block (o, x): rows (o i), cols (x y)
+    for (int e = lane; e < RR; e += 64) {
+      const int i = e / R, y = e % R;
+      blk[e] = Gm[(size_t)(o * R + i) * n + x * R + y];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // tmp[i][j] = sum_y blk[i][y] Q[y][j]
+    for (int e = lane; e < R * Dn; e += 64) {
+      const int i = e / Dn, j = e % Dn;
+      T acc = zerov<T>();
+      for (int y = 0; y < R; ++y) acc += blk[i * R + y] * Q[y * FIT_RMAX + j];
+      tmp[e] = acc;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // g_s block = Q^H tmp
+    for (int e = lane; e < Dn * Dn; e += 64) {
+      const int jp = e / Dn, j = e % Dn;
+      T acc = zerov<T>();
+      for (int i = 0; i < R; ++i) acc += cmul(Q[i * FIT_RMAX + jp], tmp[i * Dn + j]);
+      const int row = half == 0 ? o * Dn + jp : jp * R + o;
+      const int colx = half == 0 ? x * Dn + j : j * R + x;
+      gs[(size_t)row * nx + colx] = acc;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  // J[(o, j')] = sum_i conj(Q[i][j']) gy[(o i)]
+  for (int e = threadIdx.x; e < nx; e += blockDim.x) {
+    const int o = half == 0 ? e / Dn : e % R, jp = half == 0 ? e % Dn : e / R;
+    T acc = zerov<T>();
+    for (int i = 0; i < R; ++i) acc += cmul(Q[i * FIT_RMAX + jp], gyv[o * R + i]);
+    J[e] = acc;
+  }
+  __syncthreads();
+}
+
+template <class T>
+NTU_DEV bool chol_certify(T* Wc, int n, T* pan, int* flag) {
+  return blocked_cholesky<T, CHOL_BS>(Wc, n, n, pan, flag);
+}
+
+// Conjugate gradients for g_s m = J with g_s held in registers: thread t
+// owns rows 4 (t / 16) .. +3 and columns 8 (t % 16) .. +7 (nx <= 128, zero
+// padding beyond nx).  Dependent directions (zero columns of Q) are unit
+// rows with zero right-hand side.  Iterates to a relative residual of
+// rtol (at most max_it iterations); returns false if it does not get there.
+constexpr int CG_NX = 128;
+
+template <class T>
+NTU_DEV bool cg_solve(const T* gs, int R, int Dn, int half, const int* zcol, const T* J, T* m, T* p, T* q, T* r,
+                      double* red, double rtol, int max_it, int* iters_out) {
+  const int tid = threadIdx.x, nx = R * Dn;
+  const int rg = tid >> 4, cc = tid & 15;
+  auto defl = [&](int e) { return zcol[half == 0 ? e % Dn : e / R] != 0; };
+  // entry (i, j) of the system matrix: g_s, or a unit row / column for dependent directions
+  auto Aij = [&](int i, int j) -> T {
+    if (i >= nx || j >= nx) return zerov<T>();
+    if (defl(i) || defl(j)) return realv<T>(i == j ? 1.0 : 0.0);
+    return gs[(size_t)i * nx + j];
+  };
+  double bb = 0;
+  for (int e = tid; e < CG_NX; e += blockDim.x) {
+    T v = (e < nx && !defl(e)) ? J[e] : zerov<T>();
+    r[e] = v; p[e] = v; m[e] = zerov<T>();
+    bb += abs2(v);
+  }
+  bb = block_sum(bb, red);  // contains barriers: r, p visible
+  double rr = bb;
+  const double stop = rtol * rtol * bb;
+  int it = 0;
+  bool conv = bb == 0.0;
+  for (; it < max_it && !conv; ++it) {
+    // q = A p
+    T acc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      acc[a] = zerov<T>();
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc[a] += Aij(4 * rg + a, 8 * cc + b) * p[8 * cc + b];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {
+        if constexpr (is_cplx<T>::value) {
+          acc[a].x += __shfl_xor(acc[a].x, o, 64);
+          acc[a].y += __shfl_xor(acc[a].y, o, 64);
+        } else {
+          acc[a] += __shfl_xor(acc[a], o, 64);
+        }
+      }
+    }
+    if (cc == 0)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) q[4 * rg + a] = acc[a];
+    __syncthreads();
+    double pq = 0;
+    for (int e = tid; e < CG_NX; e += blockDim.x) pq += rev(cmul(p[e], q[e]));
+    pq = block_sum(pq, red);
+    if (!(pq > 0.0)) break;
+    const double alpha = rr / pq;
+    double rn = 0;
+    for (int e = tid; e < CG_NX; e += blockDim.x) {
+      m[e] += alpha * p[e];
+      r[e] -= alpha * q[e];
+      rn += abs2(r[e]);
+    }
+    rn = block_sum(rn, red);
+    const double beta = rn / rr;
+    rr = rn;
+    conv = rn <= stop;
+    for (int e = tid; e < CG_NX; e += blockDim.x) p[e] = r[e] + beta * p[e];
+    __syncthreads();
+  }
+  *iters_out = it;
+  return conv;
+}
+
+// Solve g_s m = J by a blocked Cholesky factorisation of g_s (in place in
+// global memory).  Rows of dependent (zero) directions of Q are replaced by
+// unit rows with zero right-hand side, which is the same as leaving them out.
+// Returns false if the factorisation fails (the caller then takes the
+// eigendecomposition path, which reassembles g_s).
+template <class T>
+NTU_DEV bool fast_solve(T* gs, int R, int Dn, int half, const T* Q, const FitShared<T>& S, T* pan, T* dblk,
+                        T* bz, int* flag) {
+  const int nx = R * Dn;
+  __shared__ int zcol[FIT_RMAX];
+  if (threadIdx.x < Dn) {
+    bool z = true;
+    for (int i = 0; i < R; ++i) z = z && rev(Q[i * FIT_RMAX + threadIdx.x]) == 0.0 && imv(Q[i * FIT_RMAX + threadIdx.x]) == 0.0;
+    zcol[threadIdx.x] = z ? 1 : 0;
+  }
+  __syncthreads();
+  bool anyz = false;
+  for (int j = 0; j < Dn; ++j) anyz = anyz || zcol[j];
+  if (anyz) {
+    for (long long e = threadIdx.x; e < (long long)nx * nx; e += blockDim.x) {
+      const int i = (int)(e / nx), j = (int)(e % nx);
+      const int ji = half == 0 ? i % Dn : i / R, jj = half == 0 ? j % Dn : j / R;
+      if (zcol[ji] || zcol[jj]) gs[e] = realv<T>(i == j ? 1.0 : 0.0);
+    }
+  }
+  for (int e = threadIdx.x; e < nx; e += blockDim.x) {
+    const int je = half == 0 ? e % Dn : e / R;
+    bz[e] = zcol[je] ? zerov<T>() : S.J[e];
+  }
+  __syncthreads();
+  if (!blocked_cholesky<T, CHOL_BS>(gs, nx, nx, pan, flag)) return false;
+  blocked_chol_solve<T, CHOL_BS>(gs, nx, nx, bz, S.m, dblk);
+  return true;
+}
+
 template <class T>
 __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T* __restrict__ g,
                                                           const T* __restrict__ RX, const T* __restrict__ RY,
@@ -259,6 +459,8 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   T* gy = X + (size_t)R * D * R * D;
   T* dv = gy + n;
   T* gd = dv + n;
+  T* gP = gd + n;
+  T* gyP = gP + (size_t)n * n;
   // shared carve-up
   FitShared<T> S;
   {
@@ -277,8 +479,48 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
     S.vec = q; q += 64;
     S.idx = (int*)q;
   }
+  // after the fixed part, one work region used in turn for: the Cholesky panel
+  // of the certification, the per-wave block staging of g_s, and the
+  // Cholesky panel / diagonal block / right-hand side of the half-step solve
+  T* work = (T*)((char*)shmem + fit_shared_fixed_bytes(sizeof(T), R));
+  T* wstage = work;
+  T* pan = work;
+  T* dblk = work + (size_t)R * D * CHOL_BS;
+  T* sbz = dblk + CHOL_BS * CHOL_BS;
+  T* cgp = sbz + FAST_NX;
+  T* cgq = cgp + CG_NX;
+  T* cgr = cgq + CG_NX;
+  __shared__ int chol_flag;
+  __shared__ int zcol_sh[FIT_RMAX];
+  int cg_iters_total = 0, cg_solves = 0;
+  // certification: Cholesky of g - s I (copy in the workspace)
+  bool certified = false;
+  const bool cert_fits = (long long)n * n <= (long long)n * R * D + 3LL * R * D * R * D;
+  if (R * D <= FAST_NX) certified = gershgorin_certify<T>(G, n, 10.0 * fp.tol[fp.n_tol - 1], S.red);
+  if (!certified && n <= FIT_CERT_NMAX && R * D <= FAST_NX && cert_fits) {
+    T* Wc = W;  // n^2 elements fit in G1 .. X (cert_fits)
+    double fro = 0;
+    for (long long e = tid; e < (long long)n * n; e += blockDim.x) fro += abs2(G[e]);
+    fro = sqrt(block_sum(fro, S.red));
+    const double shift = 10.0 * fp.tol[fp.n_tol - 1] * fro;
+    for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
+      T v = G[e];
+      if (e / n == e % n) v = v - realv<T>(shift);
+      Wc[e] = v;
+    }
+    __syncthreads();
+    certified = fro > 0 && chol_certify<T>(Wc, n, pan, &chol_flag);
+  }
   double* st = stats ? stats + (size_t)it * stats_stride : nullptr;
   const double kappa = fp.kappa;
+  // phase cycle counters (thread 0): setup, g_s formation, solve, error, balance
+  long long tph[5] = {0, 0, 0, 0, 0};
+  long long t_mark = clock64();
+  auto tick = [&](int ph) {
+    long long t = clock64();
+    tph[ph] += t - t_mark;
+    t_mark = t;
+  };
 
   // P = RX RY^T  (column-major copy in sa for the SVD, row-major y = vec(P))
   for (int e = tid; e < n; e += blockDim.x) {
@@ -314,6 +556,15 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   double N = 0;
   for (int r = tid; r < n; r += blockDim.x) N += rev(cmul(S.y[r], gy[r]));
   N = block_sum(N, S.red);
+  if (certified) {
+    // metric and g y with both index pairs swapped (Y half-steps read contiguous blocks)
+    for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
+      const int r = (int)(e / n), c = (int)(e % n);
+      gP[(size_t)((r % R) * R + r / R) * n + (c % R) * R + c / R] = G[e];
+    }
+    for (int r = tid; r < n; r += blockDim.x) gyP[(r % R) * R + r / R] = gy[r];
+    __syncthreads();
+  }
   double eps = Dn > 0 ? fit_error<T>(G, R, Dn, S, dv, gd) : 0.0;
   if (st && tid == 0) {
     const int len = fit_stats_len(fp.n_iter, D);
@@ -323,6 +574,7 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   __syncthreads();
   int iters = 0, n_eig = 0;
   double prev = eps;
+  tick(0);
   for (int iter = 0; iter < fp.n_iter && Dn > 0; ++iter) {
     for (int half = 0; half < 2; ++half) {
       // fixed factor F (MY for the X half-step, MX for the Y half-step), made isometric
@@ -330,8 +582,49 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
       fit_orthonormalise<T>(F, S.Qf, R, Dn, kappa);
       __syncthreads();
       const int nx = R * Dn;
+      // candidate -> free factor, then error
+      auto set_free = [&](const T* mv) {
+        for (int e = tid; e < R * Dn; e += blockDim.x) {
+          if (half == 0) {
+            int a = e / Dn, j = e % Dn;
+            S.MX[a * FIT_RMAX + j] = mv[a * Dn + j];
+            S.MY[a * FIT_RMAX + j] = S.Qf[a * FIT_RMAX + j];
+          } else {
+            int j = e / R, b = e % R;
+            S.MY[b * FIT_RMAX + j] = mv[j * R + b];
+            S.MX[b * FIT_RMAX + j] = S.Qf[b * FIT_RMAX + j];
+          }
+        }
+        __syncthreads();
+      };
+      auto eval = [&](const T* mv) -> double {
+        set_free(mv);
+        return fit_error<T>(G, R, Dn, S, dv, gd);
+      };
+      int used_eig = 0;
+      double tau = fp.tol[fp.n_tol - 1];
+      bool fast_done = false;
+      if (certified) {
+        fast_form_gs<T>(half == 0 ? G : gP, half == 0 ? gy : gyP, R, Dn, half, S.Qf, gs, S.J, wstage);
+        tick(1);
+        if (tid < Dn) {
+          bool z = true;
+          for (int i = 0; i < R; ++i) z = z && rev(S.Qf[i * FIT_RMAX + tid]) == 0.0 && imv(S.Qf[i * FIT_RMAX + tid]) == 0.0;
+          zcol_sh[tid] = z ? 1 : 0;
+        }
+        __syncthreads();
+        int cgi = 0;
+        if (nx <= CG_NX) {
+          fast_done = cg_solve<T>(gs, R, Dn, half, zcol_sh, S.J, S.m, cgp, cgq, cgr, S.red, 1e-14, 64, &cgi);
+          cg_iters_total += cgi;
+          cg_solves += 1;
+        }
+        if (!fast_done) fast_done = fast_solve<T>(gs, R, Dn, half, S.Qf, S, pan, dblk, sbz, &chol_flag);
+        tick(2);
+      }
       // G1[(a' b'), c] :  X half: c = (a, j): sum_b g[(a' b'), (a b)] Q[b, j]
       //                   Y half: c = (j, b): sum_a g[(a' b'), (a b)] Q[a, j]
+      if (!fast_done) {
       for (long long e = tid; e < (long long)n * nx; e += blockDim.x) {
         int row = (int)(e / nx), c = (int)(e % nx);
         const T* gr = G + (size_t)row * n;
@@ -371,29 +664,12 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
         S.J[r] = v;
       }
       __syncthreads();
-      // candidate -> free factor, then error
-      auto set_free = [&](const T* mv) {
-        for (int e = tid; e < R * Dn; e += blockDim.x) {
-          if (half == 0) {
-            int a = e / Dn, j = e % Dn;
-            S.MX[a * FIT_RMAX + j] = mv[a * Dn + j];
-            S.MY[a * FIT_RMAX + j] = S.Qf[a * FIT_RMAX + j];
-          } else {
-            int j = e / R, b = e % R;
-            S.MY[b * FIT_RMAX + j] = mv[j * R + b];
-            S.MX[b * FIT_RMAX + j] = S.Qf[b * FIT_RMAX + j];
-          }
-        }
-        __syncthreads();
-      };
-      auto eval = [&](const T* mv) -> double {
-        set_free(mv);
-        return fit_error<T>(G, R, Dn, S, dv, gd);
-      };
-      int used_eig = 0;
-      double tau = fit_solve<T>(gs, nx, fp, S, A, X, N, &used_eig, eval);
+      tau = fit_solve<T>(gs, nx, fp, S, A, X, N, &used_eig, eval);
+      }  // !fast_done
+      if (!fast_done) tick(2);
       set_free(S.m);
       eps = fit_error<T>(G, R, Dn, S, dv, gd);
+      tick(3);
       n_eig += used_eig;
       if (st && tid == 0) {
         st[16 + 2 * iter + half] = eps;
@@ -432,7 +708,11 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
     MXo[(size_t)it * R * D + e] = mx;
     MYo[(size_t)it * R * D + e] = my;
   }
+  tick(4);
   if (st && tid == 0) {
+    st[9] = certified ? 1.0 : 0.0;
+    st[15] = cg_solves > 0 ? (double)cg_iters_total / cg_solves : 0.0;
+    for (int q = 0; q < 5; ++q) st[10 + q] = (double)tph[q];
     st[2] = eps;
     st[3] = N > 0 ? eps / N : 0.0;
     st[5] = Dk;
@@ -445,11 +725,24 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
 
 hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, const void* RX, const void* RY,
                            const FitParams& fp, void* MX, void* MY, double* stats, int stats_stride, void* ws,
-                           hipStream_t st) {
+                           hipStream_t st, const ProfHook& ph) {
   if (batch <= 0) return hipSuccess;
   if (R > FIT_RMAX || D > FIT_RMAX || R * D > 256) return hipErrorInvalidValue;
   size_t el = cplx ? 16 : 8;
-  size_t shm = (size_t)(R * R + 7 * FIT_RMAX * FIT_RMAX) * el + (FIT_RMAX + 16 * 64 + 64) * 8 + FIT_RMAX * FIT_RMAX * 4;
+  const int nw = FIT_THREADS / 64;
+  const size_t work_el = std::max<size_t>({(size_t)R * R * CHOL_BS, (size_t)nw * (R * R + R * D),
+                                           (size_t)R * D * CHOL_BS + CHOL_BS * CHOL_BS + FAST_NX + 3 * CG_NX});
+  size_t shm = fit_shared_fixed_bytes(el, R) + work_el * el;
+  ph(PK_FIT, 0);
+  static bool attr_set[2] = {false, false};
+  if (!attr_set[cplx ? 1 : 0]) {
+    // allow the full 160 KiB of LDS for the dynamic part
+    hipError_t e = cplx ? hipFuncSetAttribute((const void*)k_bond_fit<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 16 * 1024)
+                        : hipFuncSetAttribute((const void*)k_bond_fit<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 16 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set[cplx ? 1 : 0] = true;
+  }
+  if (shm > 160 * 1024 - 16 * 1024) return hipErrorInvalidValue;
   if (cplx)
     hipLaunchKernelGGL(k_bond_fit<cd>, dim3(batch), dim3(FIT_THREADS), shm, st, D, R, (const cd*)g, (const cd*)RX,
                        (const cd*)RY, fp, (cd*)MX, (cd*)MY, stats, stats_stride, (cd*)ws);
@@ -457,6 +750,7 @@ hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, co
     hipLaunchKernelGGL(k_bond_fit<double>, dim3(batch), dim3(FIT_THREADS), shm, st, D, R, (const double*)g,
                        (const double*)RX, (const double*)RY, fp, (double*)MX, (double*)MY, stats, stats_stride,
                        (double*)ws);
+  ph(PK_FIT, 1);
   return hipGetLastError();
 }
 

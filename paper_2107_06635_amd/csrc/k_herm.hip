@@ -92,8 +92,11 @@ __global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stat
   }
   fro = sqrt(block_sum(fro, red));
   __syncthreads();
+  // positive definite (the clip is the identity) if the Gershgorin discs of
+  // the full matrix stay right of zero, or else if a Cholesky factor exists
+  if (m == n && gershgorin_certify<T>(G, n, 0.0, red)) return;
   bool ok = m == 0 || block_cholesky<T>(A, m, m, red);
-  if (ok) return;  // positive definite: the clip is the identity
+  if (ok) return;
   for (long long e = tid; e < (long long)m * m; e += blockDim.x) {
     int i = (int)(e / m), j = (int)(e % m);
     A[e] = G[(size_t)idx[i] * n + idx[j]];

@@ -9,7 +9,7 @@ namespace ntu {
 // Kernel classes timed by the optional event profiler of a context.
 enum ProfKind {
   PK_ROTATE = 0, PK_GATE, PK_REDUCE, PK_EDGES, PK_QPREP, PK_LEFTRIGHT, PK_E4, PK_E5, PK_E6, PK_E6RED,
-  PK_HERM, PK_CLIP, PK_FIT, PK_RECOMB, PK_COUNT
+  PK_HERM, PK_CLIP, PK_FIT, PK_RECOMB, PK_CERT, PK_COUNT
 };
 // mark(ctx, kind, 0) before and mark(ctx, kind, 1) after a launch (nullable)
 struct ProfHook {
@@ -64,6 +64,6 @@ size_t fit_workspace_bytes(bool cplx, int batch, int D, int R);
 NTU_HD int fit_stats_len(int n_iter, int D) { return 16 + 4 * n_iter + D; }
 hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, const void* RX, const void* RY,
                            const FitParams& fp, void* MX, void* MY, double* stats, int stats_stride, void* ws,
-                           hipStream_t st);
+                           hipStream_t st, const ProfHook& ph);
 
 }  // namespace ntu

@@ -275,3 +275,188 @@ NTU_DEV void block_jacobi_eigh(T* A, int n, int lda, T* V, int ldv, double* pc, 
 }
 
 }  // namespace ntu
+
+
+
+namespace ntu {
+
+NTU_DEV void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// Blocked right-looking Cholesky A = L L^H of an n x n Hermitian matrix held
+// row-major in global memory (lower triangle read and overwritten by L).
+// Per block column of width BS: the panel (rows k0..n-1) is staged in shared
+// memory, wave 0 factors the diagonal block, every thread solves panel rows,
+// and the trailing lower triangle gets a rank-BS update in 4 x 4 register
+// tiles.  pan: shared T[n * BS]; flag: one shared int.  Returns false
+// (uniformly) on a non-positive or non-finite pivot.  Whole block.
+// ---------------------------------------------------------------------------
+template <class T, int BS>
+NTU_DEV bool blocked_cholesky(T* A, int n, int lda, T* pan, int* flag) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+  for (int k0 = 0; k0 < n; k0 += BS) {
+    const int bs = min(BS, n - k0), m = n - k0;
+    for (int e = tid; e < m * bs; e += nt) {
+      const int i = e / bs, c = e % bs;
+      pan[i * BS + c] = (i < c) ? zerov<T>() : A[(size_t)(k0 + i) * lda + k0 + c];
+    }
+    __syncthreads();
+    if (wv == 0) {
+      for (int c = 0; c < bs; ++c) {
+        const double piv = rev(pan[c * BS + c]);
+        if (!(piv > 0.0) || !isfinite(piv)) {
+          if (lane == 0) *flag = 1;
+          break;
+        }
+        const double lcc = sqrt(piv), inv = 1.0 / lcc;
+        if (lane > c && lane < bs) pan[lane * BS + c] = pan[lane * BS + c] * inv;
+        wave_sync_lds();
+        if (lane == c) pan[c * BS + c] = realv<T>(lcc);
+        const int w2 = bs - 1 - c;
+        for (int e = lane; e < w2 * w2; e += 64) {
+          const int r = c + 1 + e / w2, q = c + 1 + e % w2;
+          if (q <= r) pan[r * BS + q] -= mulc(pan[r * BS + c], pan[q * BS + c]);
+        }
+        wave_sync_lds();
+      }
+    }
+    __syncthreads();
+    if (*flag) return false;
+    // panel rows below the diagonal block: L_i. = A_i. L_kk^{-H}
+    for (int i = bs + tid; i < m; i += nt) {
+      for (int c = 0; c < bs; ++c) {
+        T v = pan[i * BS + c];
+        for (int q = 0; q < c; ++q) v -= mulc(pan[i * BS + q], pan[c * BS + q]);
+        pan[i * BS + c] = v * (1.0 / rev(pan[c * BS + c]));
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < m * bs; e += nt) {
+      const int i = e / bs, c = e % bs;
+      if (i >= c) A[(size_t)(k0 + i) * lda + k0 + c] = pan[i * BS + c];
+    }
+    // trailing update, lower triangle of rows/cols k0 + bs .. n-1, in 4 x 4 tiles
+    const int mt = m - bs, tt = (mt + 3) / 4;
+    const int ntile = tt * (tt + 1) / 2;
+    for (int t = tid; t < ntile; t += nt) {
+      int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+      while (ti * (ti + 1) / 2 > t) --ti;
+      const int tj = t - ti * (ti + 1) / 2;
+      T acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = zerov<T>();
+      for (int c = 0; c < bs; ++c) {
+        T li[4], lj[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int i = bs + 4 * ti + a, j = bs + 4 * tj + a;
+          li[a] = i < m ? pan[i * BS + c] : zerov<T>();
+          lj[a] = j < m ? pan[j * BS + c] : zerov<T>();
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] += mulc(li[a], lj[b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = 4 * ti + a, j = 4 * tj + b;
+          if (i < mt && j <= i) {
+            T* p = &A[(size_t)(k0 + bs + i) * lda + k0 + bs + j];
+            *p = *p - acc[a][b];
+          }
+        }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// Solve L L^H x = b with the factor of blocked_cholesky (L in the lower
+// triangle of A, global).  b, x: shared, length n (b is overwritten).
+// Whole block.
+template <class T, int BS>
+NTU_DEV void blocked_chol_solve(const T* A, int n, int lda, T* b, T* x, T* dblk) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // forward: L z = b, z stored in b
+  for (int k0 = 0; k0 < n; k0 += BS) {
+    const int bs = min(BS, n - k0);
+    for (int e = tid; e < bs * bs; e += nt) dblk[e] = A[(size_t)(k0 + e / bs) * lda + k0 + e % bs];
+    __syncthreads();
+    if (tid == 0) {
+      for (int c = 0; c < bs; ++c) {
+        const int r = k0 + c;
+        T v = b[r];
+        for (int q = 0; q < c; ++q) v -= dblk[c * bs + q] * b[k0 + q];
+        b[r] = v * (1.0 / rev(dblk[c * bs + c]));
+      }
+    }
+    __syncthreads();
+    for (int i = k0 + bs + tid; i < n; i += nt) {
+      T v = b[i];
+      for (int c = 0; c < bs; ++c) v -= A[(size_t)i * lda + k0 + c] * b[k0 + c];
+      b[i] = v;
+    }
+    __syncthreads();
+  }
+  // backward: L^H x = z
+  const int nb = (n + BS - 1) / BS;
+  for (int kb = nb - 1; kb >= 0; --kb) {
+    const int k0 = kb * BS, bs = min(BS, n - k0);
+    for (int e = tid; e < bs * bs; e += nt) dblk[e] = A[(size_t)(k0 + e / bs) * lda + k0 + e % bs];
+    __syncthreads();
+    if (tid == 0) {
+      for (int c = bs - 1; c >= 0; --c) {
+        const int r = k0 + c;
+        T v = b[r];
+        for (int q = c + 1; q < bs; ++q) v -= cmul(dblk[q * bs + c], x[k0 + q]);
+        x[r] = v * (1.0 / rev(dblk[c * bs + c]));
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < k0; i += nt) {
+      T v = b[i];
+      for (int c = 0; c < bs; ++c) v -= cmul(A[(size_t)(k0 + c) * lda + i], x[k0 + c]);
+      b[i] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Gershgorin certification of g: every eigenvalue lies in the union of the
+// discs |lambda - g_ii| <= sum_{j != i} |g_ij|, so lo = min_i (g_ii - r_i)
+// bounds lambda_min from below and hi = max_i (g_ii + r_i) bounds lambda_max
+// from above.  Certified if lo > margin * hi.  Whole block.
+template <class T>
+NTU_DEV bool gershgorin_certify(const T* __restrict__ G, int n, double margin, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int r = w; r < n; r += nw) {
+    const T* gr = G + (size_t)r * n;
+    double off = 0, dg = 0;
+    for (int c = lane; c < n; c += 64) {
+      if (c == r) dg = rev(gr[c]);
+      else off += absv(gr[c]);
+    }
+    off = wave_sum(off);
+    dg = wave_sum(dg);
+    lo = fmin(lo, dg - off);
+    hi = fmax(hi, dg + off);
+  }
+  lo = -block_max(-lo, red);
+  hi = block_max(hi, red);
+  return lo > 0.0 && hi > 0.0 && lo > margin * hi;
+}
+
+}  // namespace ntu
