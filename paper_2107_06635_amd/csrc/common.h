@@ -128,10 +128,13 @@ NTU_HD Idx3 idx2(int n_in, long long s_out, long long s_in) { return Idx3{1, n_i
 NTU_HD Idx3 idx3(int n1, int n2, long long s0, long long s1, long long s2) {
   return Idx3{n1, n2, s0, s1, s2};
 }
+// Offset of index i (0 <= i < 2^32: rows, columns, contraction indices and
+// items are all far below that) under the three-level map.  32-bit unsigned
+// division; the one-level case needs none.
 NTU_HD long long idx_off(const Idx3& x, long long i) {
-  long long i2 = i % x.n2;
-  long long t = i / x.n2;
-  long long i1 = t % x.n1;
-  long long i0 = t / x.n1;
-  return i0 * x.s0 + i1 * x.s1 + i2 * x.s2;
+  if (x.n1 == 1 && x.n2 == 1) return i * x.s0;
+  const unsigned u = (unsigned)i, n2 = (unsigned)x.n2, n1 = (unsigned)x.n1;
+  const unsigned i2 = u % n2, t = u / n2;
+  const unsigned i1 = t % n1, i0 = t / n1;
+  return (long long)i0 * x.s0 + (long long)i1 * x.s1 + (long long)i2 * x.s2;
 }
