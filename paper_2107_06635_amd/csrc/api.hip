@@ -201,7 +201,8 @@ ntu_status ntu_ctx_create(ntu_ctx** out, int device, int dtype, int d, int d_anc
   const int p = d * d_anc;
   size_t sb = 0;
   for (int D = 1; D <= max_D; ++D) sb = std::max(sb, scratch_bytes(c->cplx, max_batch, p, D, r_g));
-  c->ws_bytes = sb;
+  // the reduction's per-item path flags also live at the start of the workspace
+  c->ws_bytes = std::max(sb, (size_t)max_batch * sizeof(int) + 256);
   c->step_bytes = (size_t)persist_elems(p, max_D, r_g, d) * elem_size(c) * max_batch + 256;
   hipError_t e = hipMalloc((void**)&c->ws, c->ws_bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&c->step, c->step_bytes);
@@ -263,7 +264,7 @@ ntu_status ntu_reduce_qr(ntu_ctx* c, int batch, int D, const void* site, int sit
   const ntu::ProfHook ph = hook(c);
   ph(ntu::PK_REDUCE, 0);
   hipError_t e = ntu::launch_reduce_qr(c->cplx, site_dtype, batch, c->d, c->na, D, c->rg, site, gf,
-                                       (long long)c->d * c->d * c->rg, side, Q, R, 1e-10, c->stream);
+                                       (long long)c->d * c->d * c->rg, side, Q, R, 1e-10, (int*)c->ws, c->stream);
   ph(ntu::PK_REDUCE, 1);
   return e == hipSuccess ? NTU_OK : hip_fail(c, e, "reduce_qr");
 }
@@ -384,9 +385,9 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     const char* gB = (const char*)gate_factors + (size_t)(bond * 2 + 1) * gfs * el;
     ph(ntu::PK_REDUCE, 0);
     NTU_STEP(ntu::launch_reduce_qr(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, gf_item, 0, QX, RX, opts->fit.kappa,
-                                   c->stream), "reduce_qr X");
+                                   (int*)c->ws, c->stream), "reduce_qr X");
     NTU_STEP(ntu::launch_reduce_qr(cp, c->dtype, batch, c->d, c->na, D, c->rg, Y, gB, gf_item, 1, QY, RY, opts->fit.kappa,
-                                   c->stream), "reduce_qr Y");
+                                   (int*)c->ws, c->stream), "reduce_qr Y");
     ph(ntu::PK_REDUCE, 1);
     const void* nbr[6] = {Y, Y, Y, X, X, X};
     e = ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, QX, QY, nbr, G, c->ws, c->ws_bytes, c->stream, ph);

@@ -62,9 +62,30 @@ template <> struct is_cplx<cd> { static constexpr bool value = true; };
 // ---------------------------------------------------------------------------
 // wave / block reductions (wave64)
 // ---------------------------------------------------------------------------
+// Cross-lane move of a double inside rows of 16 lanes (DPP).  CTRL 0xB1 and
+// 0x4E exchange lanes at distance 1 and 2 inside each quad (quad_perm
+// [1,0,3,2], [2,3,0,1]), 0x141 mirrors each half-row, 0x140 each row.
+template <int CTRL> NTU_DEV double dpp_move(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  int lo = (int)(unsigned)(u & 0xffffffffull), hi = (int)(unsigned)(u >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// Sum over each row of 16 lanes, as a butterfly: after each step the lanes of
+// the merged group hold bit-identical values, so all 16 lanes agree.
+NTU_DEV double row_sum16(double v) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x141>(v);
+  v += dpp_move<0x140>(v);
+  return v;
+}
+// Sum over the wave; every lane gets the same (bit-identical) value.
 NTU_DEV double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = row_sum16(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
   return v;
 }
 NTU_DEV double wave_max(double v) {

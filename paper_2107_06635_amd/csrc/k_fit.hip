@@ -27,9 +27,7 @@ NTU_HD long long fit_ws_elems(int D, int R) {
   long long n = (long long)R * R, nx = (long long)R * D;
   return n * nx      // G1
          + 3 * nx * nx  // g_s, A (Cholesky / eigen), X (inverse / eigenvectors)
-         + 3 * n        // g y, d, g d
-         + n * n        // g with both index pairs swapped, (a b) -> (b a)
-         + 2 * n;       // g y in swapped order, spare
+         + 3 * n;       // g y, d, g d
 }
 
 size_t fit_workspace_bytes(bool cplx, int batch, int D, int R) {
@@ -68,17 +66,28 @@ template <class T> struct FitShared {
   double* vec;  // 64
 };
 
-// out[r] = sum_c g[r][c] v[c] for r < n: one wave per row, lanes over columns.
+// out = g v for a Hermitian n x n g (row-major), n <= blockDim.x:
+//   out[r] = sum_c conj(g[c][r]) v[c].
+// Thread (r, part), r fastest, sums a contiguous range of c, so a wave reads
+// consecutive entries of each row of g; the parts meet in mv (blockDim.x
+// elements of shared memory).  Whole block.
 template <class T>
-NTU_DEV void fit_matvec(const T* __restrict__ g, int n, const T* v, T* out) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int r = w; r < n; r += nw) {
-    const T* gr = g + (size_t)r * n;
+NTU_DEV void fit_matvec(const T* __restrict__ g, int n, const T* v, T* out, T* mv) {
+  const int tid = threadIdx.x, parts = (int)blockDim.x / n, cs = (n + parts - 1) / parts;
+  if (tid < parts * n) {
+    const int r = tid % n, part = tid / n;
+    const int c1 = min(n, (part + 1) * cs);
     T acc = zerov<T>();
-    for (int c = lane; c < n; c += 64) acc += gr[c] * v[c];
-    acc = wave_sum(acc);
-    if (lane == 0) out[r] = acc;
+    for (int c = part * cs; c < c1; ++c) acc += cmul(g[(size_t)c * n + r], v[c]);
+    mv[tid] = acc;
   }
+  __syncthreads();
+  for (int r = tid; r < n; r += blockDim.x) {
+    T acc = zerov<T>();
+    for (int part = 0; part < parts; ++part) acc += mv[part * n + r];
+    out[r] = acc;
+  }
+  __syncthreads();
 }
 
 // d = vec(MX MY^T) - y ; eps = Re(d^H g d).  Whole block.
@@ -92,8 +101,7 @@ NTU_DEV double fit_error(const T* __restrict__ g, int R, int Dn, const FitShared
     d[e] = v - S.y[e];
   }
   __syncthreads();
-  fit_matvec<T>(g, n, d, gd);
-  __syncthreads();
+  fit_matvec<T>(g, n, d, gd, S.sa);
   double acc = 0.0;
   for (int r = threadIdx.x; r < n; r += blockDim.x) acc += rev(cmul(d[r], gd[r]));
   return block_sum(acc, S.red);
@@ -263,64 +271,90 @@ NTU_DEV double fit_solve(const T* gs, int nx, const FitParams& fp, const FitShar
 
 
 // ---------------------------------------------------------------------------
-// Certified half-step.  g_s is assembled block by block: viewing g as R x R
-// blocks of size R x R, block (o, x) of the X half-step is
-//   g_s[(o, j'), (x, j)] = sum_{i, y} conj(Q[i][j']) g[(o i), (x y)] Q[y][j],
-// i.e. Q^H g_ox Q; the Y half-step does the same on the metric with both
-// index pairs swapped, gP[(b a), (b' a')] = g[(a b), (a' b')], and writes the
-// result in the (j, b) parameter order.  One wave per block, staged in
-// shared memory; every entry of g is read once.
+// Half-step matrix g_s = K^H g K and J = K^H g y in two block-wide passes
+// (K = I (x) Q for the X half-step, parameters (a, j); K = Q (x) I for the
+// Y half-step, parameters (j, b)):
+//   pass 1  G1[r][(x, j)] = sum_y g[r][col(x, y)] Q[y][j]
+//                         = sum_y conj(g[col(x, y)][r]) Q[y][j]   (g Hermitian)
+//           X: col = x R + y, G1 column x Dn + j;  Y: col = y R + x, column j R + x
+//   pass 2  g_s[(o, j')][c] = sum_i conj(Q[i][j']) G1[row(o, i)][c]
+//           X: row = o R + i, g_s row o Dn + j';   Y: row = i R + o, row j' R + o
+// Pass 1 runs r fastest (coalesced reads of g), pass 2 c fastest.  Each
+// thread carries FORM_JB columns of Q in registers.
 // ---------------------------------------------------------------------------
 constexpr int FAST_NX = 128;        // largest R D on the certified path
-constexpr int FIT_CERT_NMAX = 256;  // largest R^2 certified
+constexpr int FIT_CERT_NMAX = 256;  // largest R^2 certified by the shifted Cholesky
+constexpr int FORM_JB = 8;
+constexpr int CG_NX = 128;          // largest R D solved by conjugate gradients
 
 template <class T>
-NTU_DEV void fast_form_gs(const T* __restrict__ Gm, const T* __restrict__ gyv, int R, int Dn, int half, const T* Q,
-                          T* gs, T* J, T* wstage) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int n = R * R, nx = R * Dn, RR = R * R;
-  T* blk = wstage + (size_t)w * (RR + R * Dn);   // R x R block, then R x Dn product
-  T* tmp = blk + RR;
-  for (int bo = w; bo < RR; bo += nw) {
-    const int o = bo / R, x = bo % R;
-    // stage block (o, x): rows (o i), cols (x y)
-    for (int e = lane; e < RR; e += 64) {
-      const int i = e / R, y = e % R;
-      blk[e] = Gm[(size_t)(o * R + i) * n + x * R + y];
+NTU_DEV void form_gs(const T* __restrict__ Gm, const T* __restrict__ gyv, int R, int Dn, int half, const T* Q,
+                     T* __restrict__ G1, T* __restrict__ gs, T* J) {
+  const int tid = threadIdx.x, nt = blockDim.x, n = R * R, nx = R * Dn;
+  const int njb = (Dn + FORM_JB - 1) / FORM_JB;
+  const int w1 = n * R * njb;
+  for (int e = tid; e < w1; e += nt) {
+    const int r = e % n, t = e / n, x = t % R, jb = t / R;
+    T acc[FORM_JB];
+#pragma unroll
+    for (int u = 0; u < FORM_JB; ++u) acc[u] = zerov<T>();
+    for (int y = 0; y < R; ++y) {
+      const int col = half == 0 ? x * R + y : y * R + x;
+      const T gv = conjv(Gm[(size_t)col * n + r]);
+      const T* qy = Q + y * FIT_RMAX + jb * FORM_JB;
+#pragma unroll
+      for (int u = 0; u < FORM_JB; ++u) acc[u] += gv * qy[u];
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // tmp[i][j] = sum_y blk[i][y] Q[y][j]
-    for (int e = lane; e < R * Dn; e += 64) {
-      const int i = e / Dn, j = e % Dn;
-      T acc = zerov<T>();
-      for (int y = 0; y < R; ++y) acc += blk[i * R + y] * Q[y * FIT_RMAX + j];
-      tmp[e] = acc;
+#pragma unroll
+    for (int u = 0; u < FORM_JB; ++u) {
+      const int j = jb * FORM_JB + u;
+      if (j < Dn) G1[(size_t)r * nx + (half == 0 ? x * Dn + j : j * R + x)] = acc[u];
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // g_s block = Q^H tmp
-    for (int e = lane; e < Dn * Dn; e += 64) {
-      const int jp = e / Dn, j = e % Dn;
-      T acc = zerov<T>();
-      for (int i = 0; i < R; ++i) acc += cmul(Q[i * FIT_RMAX + jp], tmp[i * Dn + j]);
-      const int row = half == 0 ? o * Dn + jp : jp * R + o;
-      const int colx = half == 0 ? x * Dn + j : j * R + x;
-      gs[(size_t)row * nx + colx] = acc;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  // J[(o, j')] = sum_i conj(Q[i][j']) gy[(o i)]
-  for (int e = threadIdx.x; e < nx; e += blockDim.x) {
+  __syncthreads();
+  const int w2 = nx * R * njb;
+  for (int e = tid; e < w2; e += nt) {
+    const int c = e % nx, t = e / nx, o = t % R, jb = t / R;
+    T acc[FORM_JB];
+#pragma unroll
+    for (int u = 0; u < FORM_JB; ++u) acc[u] = zerov<T>();
+    for (int i = 0; i < R; ++i) {
+      const T v = G1[(size_t)(half == 0 ? o * R + i : i * R + o) * nx + c];
+      const T* qi = Q + i * FIT_RMAX + jb * FORM_JB;
+#pragma unroll
+      for (int u = 0; u < FORM_JB; ++u) acc[u] += cmul(qi[u], v);
+    }
+#pragma unroll
+    for (int u = 0; u < FORM_JB; ++u) {
+      const int j = jb * FORM_JB + u;
+      if (j < Dn) gs[(size_t)(half == 0 ? o * Dn + j : j * R + o) * nx + c] = acc[u];
+    }
+  }
+  // J[(o, j')] = sum_i conj(Q[i][j']) gy[row(o, i)]
+  for (int e = tid; e < nx; e += nt) {
     const int o = half == 0 ? e / Dn : e % R, jp = half == 0 ? e % Dn : e / R;
     T acc = zerov<T>();
-    for (int i = 0; i < R; ++i) acc += cmul(Q[i * FIT_RMAX + jp], gyv[o * R + i]);
+    for (int i = 0; i < R; ++i) acc += cmul(Q[i * FIT_RMAX + jp], gyv[half == 0 ? o * R + i : i * R + o]);
     J[e] = acc;
   }
+  __syncthreads();
+}
+
+// Dependent directions (zero columns of Q) of g_s: unit rows and columns,
+// zero right-hand side.  zcol[j] != 0 marks column j of Q.  Whole block.
+template <class T>
+NTU_DEV void deflate_gs(T* gs, T* J, int R, int Dn, int half, const int* zcol) {
+  bool anyz = false;
+  for (int j = 0; j < Dn; ++j) anyz = anyz || zcol[j] != 0;
+  if (!anyz) return;
+  const int nx = R * Dn;
+  for (int e = threadIdx.x; e < nx * nx; e += blockDim.x) {
+    const int i = e / nx, j = e % nx;
+    const int ji = half == 0 ? i % Dn : i / R, jj = half == 0 ? j % Dn : j / R;
+    if (zcol[ji] || zcol[jj]) gs[e] = realv<T>(i == j ? 1.0 : 0.0);
+  }
+  for (int e = threadIdx.x; e < nx; e += blockDim.x)
+    if (zcol[half == 0 ? e % Dn : e / R]) J[e] = zerov<T>();
   __syncthreads();
 }
 
@@ -329,28 +363,19 @@ NTU_DEV bool chol_certify(T* Wc, int n, T* pan, int* flag) {
   return blocked_cholesky<T, CHOL_BS>(Wc, n, n, pan, flag);
 }
 
-// Conjugate gradients for g_s m = J with g_s held in registers: thread t
-// owns rows 4 (t / 16) .. +3 and columns 8 (t % 16) .. +7 (nx <= 128, zero
-// padding beyond nx).  Dependent directions (zero columns of Q) are unit
-// rows with zero right-hand side.  Iterates to a relative residual of
-// rtol (at most max_it iterations); returns false if it does not get there.
-constexpr int CG_NX = 128;
-
+// Conjugate gradients for g_s m = J (g_s Hermitian positive definite, nx x nx
+// in global memory, dependent directions already deflated).  The product
+// q = g_s p reads g_s column-wise through its Hermitian symmetry, r fastest,
+// with the partial sums meeting in mv (blockDim.x elements).  p, q, r: nx
+// elements of shared memory.  Iterates to a relative residual of rtol (at
+// most max_it iterations); returns false if it does not get there.
 template <class T>
-NTU_DEV bool cg_solve(const T* gs, int R, int Dn, int half, const int* zcol, const T* J, T* m, T* p, T* q, T* r,
-                      double* red, double rtol, int max_it, int* iters_out) {
-  const int tid = threadIdx.x, nx = R * Dn;
-  const int rg = tid >> 4, cc = tid & 15;
-  auto defl = [&](int e) { return zcol[half == 0 ? e % Dn : e / R] != 0; };
-  // entry (i, j) of the system matrix: g_s, or a unit row / column for dependent directions
-  auto Aij = [&](int i, int j) -> T {
-    if (i >= nx || j >= nx) return zerov<T>();
-    if (defl(i) || defl(j)) return realv<T>(i == j ? 1.0 : 0.0);
-    return gs[(size_t)i * nx + j];
-  };
+NTU_DEV bool cg_solve(const T* __restrict__ gs, int nx, const T* J, T* m, T* p, T* q, T* r, T* mv, double* red,
+                      double rtol, int max_it, int* iters_out) {
+  const int tid = threadIdx.x, parts = (int)blockDim.x / nx, cs = (nx + parts - 1) / parts;
   double bb = 0;
-  for (int e = tid; e < CG_NX; e += blockDim.x) {
-    T v = (e < nx && !defl(e)) ? J[e] : zerov<T>();
+  for (int e = tid; e < nx; e += blockDim.x) {
+    const T v = J[e];
     r[e] = v; p[e] = v; m[e] = zerov<T>();
     bb += abs2(v);
   }
@@ -360,37 +385,26 @@ NTU_DEV bool cg_solve(const T* gs, int R, int Dn, int half, const int* zcol, con
   int it = 0;
   bool conv = bb == 0.0;
   for (; it < max_it && !conv; ++it) {
-    // q = A p
-    T acc[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      acc[a] = zerov<T>();
-#pragma unroll
-      for (int b = 0; b < 8; ++b) acc[a] += Aij(4 * rg + a, 8 * cc + b) * p[8 * cc + b];
+    if (tid < parts * nx) {
+      const int i = tid % nx, part = tid / nx;
+      const int j1 = min(nx, (part + 1) * cs);
+      T acc = zerov<T>();
+      for (int j = part * cs; j < j1; ++j) acc += cmul(gs[(size_t)j * nx + i], p[j]);
+      mv[tid] = acc;
     }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) {
-        if constexpr (is_cplx<T>::value) {
-          acc[a].x += __shfl_xor(acc[a].x, o, 64);
-          acc[a].y += __shfl_xor(acc[a].y, o, 64);
-        } else {
-          acc[a] += __shfl_xor(acc[a], o, 64);
-        }
-      }
-    }
-    if (cc == 0)
-#pragma unroll
-      for (int a = 0; a < 4; ++a) q[4 * rg + a] = acc[a];
     __syncthreads();
     double pq = 0;
-    for (int e = tid; e < CG_NX; e += blockDim.x) pq += rev(cmul(p[e], q[e]));
+    for (int e = tid; e < nx; e += blockDim.x) {
+      T acc = zerov<T>();
+      for (int part = 0; part < parts; ++part) acc += mv[part * nx + e];
+      q[e] = acc;
+      pq += rev(cmul(p[e], acc));
+    }
     pq = block_sum(pq, red);
     if (!(pq > 0.0)) break;
     const double alpha = rr / pq;
     double rn = 0;
-    for (int e = tid; e < CG_NX; e += blockDim.x) {
+    for (int e = tid; e < nx; e += blockDim.x) {
       m[e] += alpha * p[e];
       r[e] -= alpha * q[e];
       rn += abs2(r[e]);
@@ -399,7 +413,7 @@ NTU_DEV bool cg_solve(const T* gs, int R, int Dn, int half, const int* zcol, con
     const double beta = rn / rr;
     rr = rn;
     conv = rn <= stop;
-    for (int e = tid; e < CG_NX; e += blockDim.x) p[e] = r[e] + beta * p[e];
+    for (int e = tid; e < nx; e += blockDim.x) p[e] = r[e] + beta * p[e];
     __syncthreads();
   }
   *iters_out = it;
@@ -459,8 +473,6 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   T* gy = X + (size_t)R * D * R * D;
   T* dv = gy + n;
   T* gd = dv + n;
-  T* gP = gd + n;
-  T* gyP = gP + (size_t)n * n;
   // shared carve-up
   FitShared<T> S;
   {
@@ -480,10 +492,9 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
     S.idx = (int*)q;
   }
   // after the fixed part, one work region used in turn for: the Cholesky panel
-  // of the certification, the per-wave block staging of g_s, and the
-  // Cholesky panel / diagonal block / right-hand side of the half-step solve
+  // of the certification, and the Cholesky panel / diagonal block /
+  // right-hand side of the half-step solve followed by the CG vectors
   T* work = (T*)((char*)shmem + fit_shared_fixed_bytes(sizeof(T), R));
-  T* wstage = work;
   T* pan = work;
   T* dblk = work + (size_t)R * D * CHOL_BS;
   T* sbz = dblk + CHOL_BS * CHOL_BS;
@@ -514,11 +525,16 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   double* st = stats ? stats + (size_t)it * stats_stride : nullptr;
   const double kappa = fp.kappa;
   // phase cycle counters (thread 0): setup, g_s formation, solve, error, balance
-  long long tph[5] = {0, 0, 0, 0, 0};
+  long long tph0 = 0, tph1 = 0, tph2 = 0, tph3 = 0, tph4 = 0;
   long long t_mark = clock64();
   auto tick = [&](int ph) {
     long long t = clock64();
-    tph[ph] += t - t_mark;
+    const long long dt = t - t_mark;
+    if (ph == 0) tph0 += dt;
+    else if (ph == 1) tph1 += dt;
+    else if (ph == 2) tph2 += dt;
+    else if (ph == 3) tph3 += dt;
+    else tph4 += dt;
     t_mark = t;
   };
 
@@ -551,20 +567,10 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   }
   // g y and N
   __syncthreads();
-  fit_matvec<T>(G, n, S.y, gy);
-  __syncthreads();
+  fit_matvec<T>(G, n, S.y, gy, S.sa);
   double N = 0;
   for (int r = tid; r < n; r += blockDim.x) N += rev(cmul(S.y[r], gy[r]));
   N = block_sum(N, S.red);
-  if (certified) {
-    // metric and g y with both index pairs swapped (Y half-steps read contiguous blocks)
-    for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
-      const int r = (int)(e / n), c = (int)(e % n);
-      gP[(size_t)((r % R) * R + r / R) * n + (c % R) * R + c / R] = G[e];
-    }
-    for (int r = tid; r < n; r += blockDim.x) gyP[(r % R) * R + r / R] = gy[r];
-    __syncthreads();
-  }
   double eps = Dn > 0 ? fit_error<T>(G, R, Dn, S, dv, gd) : 0.0;
   if (st && tid == 0) {
     const int len = fit_stats_len(fp.n_iter, D);
@@ -605,7 +611,7 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
       double tau = fp.tol[fp.n_tol - 1];
       bool fast_done = false;
       if (certified) {
-        fast_form_gs<T>(half == 0 ? G : gP, half == 0 ? gy : gyP, R, Dn, half, S.Qf, gs, S.J, wstage);
+        form_gs<T>(G, gy, R, Dn, half, S.Qf, G1, gs, S.J);
         tick(1);
         if (tid < Dn) {
           bool z = true;
@@ -613,9 +619,10 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
           zcol_sh[tid] = z ? 1 : 0;
         }
         __syncthreads();
+        deflate_gs<T>(gs, S.J, R, Dn, half, zcol_sh);
         int cgi = 0;
         if (nx <= CG_NX) {
-          fast_done = cg_solve<T>(gs, R, Dn, half, zcol_sh, S.J, S.m, cgp, cgq, cgr, S.red, 1e-14, 64, &cgi);
+          fast_done = cg_solve<T>(gs, nx, S.J, S.m, cgp, cgq, cgr, S.sa, S.red, 1e-14, 64, &cgi);
           cg_iters_total += cgi;
           cg_solves += 1;
         }
@@ -712,7 +719,8 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   if (st && tid == 0) {
     st[9] = certified ? 1.0 : 0.0;
     st[15] = cg_solves > 0 ? (double)cg_iters_total / cg_solves : 0.0;
-    for (int q = 0; q < 5; ++q) st[10 + q] = (double)tph[q];
+    st[10] = (double)tph0; st[11] = (double)tph1; st[12] = (double)tph2;
+    st[13] = (double)tph3; st[14] = (double)tph4;
     st[2] = eps;
     st[3] = N > 0 ? eps / N : 0.0;
     st[5] = Dk;
@@ -729,9 +737,9 @@ hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, co
   if (batch <= 0) return hipSuccess;
   if (R > FIT_RMAX || D > FIT_RMAX || R * D > 256) return hipErrorInvalidValue;
   size_t el = cplx ? 16 : 8;
-  const int nw = FIT_THREADS / 64;
-  const size_t work_el = std::max<size_t>({(size_t)R * R * CHOL_BS, (size_t)nw * (R * R + R * D),
-                                           (size_t)R * D * CHOL_BS + CHOL_BS * CHOL_BS + FAST_NX + 3 * CG_NX});
+  // the n x CHOL_BS panel of the certification only for metrics it certifies
+  const size_t cert_el = R * R <= FIT_CERT_NMAX ? (size_t)R * R * CHOL_BS : 0;
+  const size_t work_el = std::max<size_t>(cert_el, (size_t)R * D * CHOL_BS + CHOL_BS * CHOL_BS + FAST_NX + 3 * CG_NX);
   size_t shm = fit_shared_fixed_bytes(el, R) + work_el * el;
   ph(PK_FIT, 0);
   static bool attr_set[2] = {false, false};

@@ -86,12 +86,13 @@ constexpr int QR_RMAX = 32;
 template <class T, class S>
 __global__ void __launch_bounds__(QR_THREADS) k_reduce_qr(int d, int na, int D, int rg, const S* site,
                                                          const T* gf, long long gf_stride, int side, T* Q, T* Rm,
-                                                         double kappa) {
+                                                         double kappa, const int* todo) {
   __shared__ double red[16 * 64];
   __shared__ double hv[2 * QR_RMAX];
   __shared__ double cacc[2 * QR_RMAX];
   constexpr int NC = is_cplx<T>::value ? 2 : 1;
   const int it = blockIdx.x, tid = threadIdx.x;
+  if (todo && todo[it] == 0) return;  // done by the Cholesky QR
   const int p = d * na, R = D * rg;
   const long long D2 = (long long)D * D, D3 = D2 * D, D4 = D3 * D;
   const long long nrow = p * D3;
@@ -179,20 +180,208 @@ __global__ void __launch_bounds__(QR_THREADS) k_reduce_qr(int d, int na, int D, 
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Reduction by Cholesky QR, applied twice (three sweeps over W instead of two
+// per column).  W is formed in chunks of rows staged in shared memory; the
+// Gram matrix W^H W = R1^H R1 gives Q1 = W R1^{-1}, and the same step on Q1
+// gives Q = Q1 R2^{-1}, R = R2 R1.  Taken only when every pivot of the first
+// factorisation exceeds (CQR_PIV * max_j |W_j|)^2: then every column is far
+// above the rank threshold, the Gram matrix resolves the factor to rounding,
+// and the result is the same QR (real positive diagonal) as Gram-Schmidt.
+// Otherwise todo[it] = 1 and the Gram-Schmidt kernel takes the item.
+// ---------------------------------------------------------------------------
+constexpr int CQR_THREADS = 512;
+constexpr int CQR_RMAX = 24;        // largest R on this path
+constexpr int CQR_CH = 64;          // rows per chunk
+constexpr int CQR_LD = CQR_RMAX + 1;
+constexpr double CQR_PIV = 1e-6;
+
+// Upper Cholesky factor Rf of the Hermitian n x n matrix G (G = Rf^H Rf) and
+// its inverse Ti, all row-major with stride CQR_RMAX.  Wave 0 (threadIdx.x <
+// 64); returns whether every pivot exceeds floor2 (same value on all lanes).
+template <class T>
+NTU_DEV bool cqr_chol(const T* G, int n, double floor2, T* Rf, T* Ti) {
+  const int lane = threadIdx.x;
+  for (int e = lane; e < CQR_RMAX * CQR_RMAX; e += 64) {
+    Rf[e] = zerov<T>();
+    Ti[e] = zerov<T>();
+  }
+  wave_sync_lds();
+  bool good = true;
+  for (int k = 0; k < n; ++k) {
+    T sv = zerov<T>();
+    if (lane >= k && lane < n) {
+      sv = G[k * CQR_RMAX + lane];
+      for (int i = 0; i < k; ++i) sv -= cmul(Rf[i * CQR_RMAX + k], Rf[i * CQR_RMAX + lane]);
+    }
+    const double piv = __shfl(rev(sv), k, 64);
+    good = good && piv > floor2 && isfinite(piv);
+    const double rkk = good ? sqrt(piv) : 1.0;
+    if (lane == k) Rf[k * CQR_RMAX + k] = realv<T>(rkk);
+    else if (lane > k && lane < n) Rf[k * CQR_RMAX + lane] = sv * (1.0 / rkk);
+    wave_sync_lds();
+  }
+  if (lane < n) {
+    const int j = lane;
+    Ti[j * CQR_RMAX + j] = realv<T>(1.0 / rev(Rf[j * CQR_RMAX + j]));
+    for (int i = j - 1; i >= 0; --i) {
+      T acc = zerov<T>();
+      for (int l = i + 1; l <= j; ++l) acc += Rf[i * CQR_RMAX + l] * Ti[l * CQR_RMAX + j];
+      Ti[i * CQR_RMAX + j] = acc * (-1.0 / rev(Rf[i * CQR_RMAX + i]));
+    }
+  }
+  wave_sync_lds();
+  return good;
+}
+
+template <class T, class S>
+__global__ void __launch_bounds__(CQR_THREADS) k_reduce_cholqr(int d, int na, int D, int rg, const S* site,
+                                                              const T* gf, long long gf_stride, int side, T* Q,
+                                                              T* Rm, double kappa, int* todo) {
+  __shared__ T ch[CQR_CH * CQR_LD];
+  __shared__ T ch2[CQR_CH * CQR_LD];
+  __shared__ T G[CQR_RMAX * CQR_RMAX];
+  __shared__ T R1[CQR_RMAX * CQR_RMAX];
+  __shared__ T T1[CQR_RMAX * CQR_RMAX];
+  __shared__ T R2[CQR_RMAX * CQR_RMAX];
+  __shared__ T T2[CQR_RMAX * CQR_RMAX];
+  __shared__ int ok;
+  const int it = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int p = d * na, R = D * rg;
+  if (R > CQR_RMAX) {
+    if (tid == 0) todo[it] = 1;
+    return;
+  }
+  const long long D2 = (long long)D * D, D3 = D2 * D, D4 = D3 * D;
+  const int nrow = (int)(p * D3);
+  const S* X = site + (size_t)it * p * D4;
+  const T* Gf = gf + (size_t)it * gf_stride;
+  T* Qi = Q + (size_t)it * nrow * R;
+  T* Ri = Rm + (size_t)it * R * R;
+  constexpr int NG = (CQR_RMAX * CQR_RMAX + CQR_THREADS - 1) / CQR_THREADS;  // Gram entries per thread
+  T acc[NG];
+
+  // sweep over the rows of `src` (global, row-major nrow x R) or of W:
+  // stage each chunk, optionally multiply by the upper triangular Tm, write
+  // the result back to Qi, and accumulate its Gram matrix into G.
+  auto sweep = [&](int mode, const T* Tm) {
+#pragma unroll
+    for (int u = 0; u < NG; ++u) acc[u] = zerov<T>();
+    for (int c0 = 0; c0 < nrow; c0 += CQR_CH) {
+      const int rows = min(CQR_CH, nrow - c0);
+      for (int e = tid; e < rows * R; e += nt) {
+        const int rl = e / R, col = e % R;
+        const int row = c0 + rl;
+        T v;
+        if (mode == 0) {
+          const int q = col / rg, k = col % rg;
+          const int i4 = row % D, i3 = (row / D) % D, t = (row / (int)D2) % D;
+          const int pa = row / (int)D3, sp = pa / na, a = pa % na;
+          v = zerov<T>();
+          for (int s = 0; s < d; ++s) {
+            const long long base = (long long)(s * na + a) * D4 + t * D3;
+            const long long off = side == 0 ? base + i3 * D2 + i4 * D + q : base + q * D2 + i3 * D + i4;
+            v += Gf[(sp * d + s) * rg + k] * load_site<T>(X, off);
+          }
+        } else {
+          v = Qi[(size_t)row * R + col];
+        }
+        ch[rl * CQR_LD + col] = v;
+      }
+      __syncthreads();
+      T* src = ch;
+      if (mode != 0) {
+        for (int e = tid; e < rows * R; e += nt) {
+          const int rl = e / R, j = e % R;
+          T v = zerov<T>();
+          for (int i = 0; i <= j; ++i) v += ch[rl * CQR_LD + i] * Tm[i * CQR_RMAX + j];
+          ch2[rl * CQR_LD + j] = v;
+        }
+        __syncthreads();
+        src = ch2;
+      }
+      for (int e = tid; e < rows * R; e += nt) Qi[(size_t)(c0 + e / R) * R + e % R] = src[(e / R) * CQR_LD + e % R];
+#pragma unroll
+      for (int u = 0; u < NG; ++u) {
+        const int e = tid + u * nt;
+        if (mode != 2 && e < R * R) {
+          const int i = e / R, j = e % R;
+          T a = acc[u];
+          for (int r = 0; r < rows; ++r) a += cmul(src[r * CQR_LD + i], src[r * CQR_LD + j]);
+          acc[u] = a;
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < NG; ++u) {
+      const int e = tid + u * nt;
+      if (e < R * R) G[(e / R) * CQR_RMAX + e % R] = acc[u];
+    }
+    __syncthreads();
+  };
+
+  // 1. W and its Gram matrix; first factor
+  sweep(0, nullptr);
+  if (tid < 64) {
+    double mx = 0;
+    for (int j = 0; j < R; ++j) mx = fmax(mx, rev(G[j * CQR_RMAX + j]));
+    const double piv = fmax(CQR_PIV, 1e3 * kappa);
+    const bool g1 = mx > 0 && cqr_chol<T>(G, R, piv * piv * mx, R1, T1);
+    if (tid == 0) ok = g1 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!ok) {
+    if (tid == 0) todo[it] = 1;
+    return;
+  }
+  __syncthreads();
+  // 2. Q1 = W R1^{-1} and its Gram matrix; second factor (pivots near 1)
+  sweep(1, T1);
+  if (tid < 64) {
+    const bool g2 = cqr_chol<T>(G, R, 0.25, R2, T2);
+    if (tid == 0) ok = g2 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!ok) {
+    if (tid == 0) todo[it] = 1;
+    return;
+  }
+  // 3. Q = Q1 R2^{-1} (Gram not needed), R = R2 R1
+  sweep(2, T2);
+  for (int e = tid; e < R * R; e += nt) {
+    const int i = e / R, j = e % R;
+    T v = zerov<T>();
+    for (int l = i; l <= j; ++l) v += R2[i * CQR_RMAX + l] * R1[l * CQR_RMAX + j];
+    Ri[e] = v;
+  }
+  if (tid == 0) todo[it] = 0;
+}
+
 hipError_t launch_reduce_qr(bool cplx, int site_dtype, int batch, int d, int na, int D, int rg,
                             const void* site, const void* gf, long long gf_stride, int side, void* Q, void* R,
-                            double kappa, hipStream_t st) {
+                            double kappa, int* todo, hipStream_t st) {
   if (batch <= 0) return hipSuccess;
-  dim3 g(batch), b(QR_THREADS);
+  dim3 g(batch), b(QR_THREADS), bc(CQR_THREADS);
   if (!cplx) {
+    if (todo)
+      hipLaunchKernelGGL((k_reduce_cholqr<double, double>), g, bc, 0, st, d, na, D, rg, (const double*)site,
+                         (const double*)gf, gf_stride, side, (double*)Q, (double*)R, kappa, todo);
     hipLaunchKernelGGL((k_reduce_qr<double, double>), g, b, 0, st, d, na, D, rg, (const double*)site,
-                       (const double*)gf, gf_stride, side, (double*)Q, (double*)R, kappa);
+                       (const double*)gf, gf_stride, side, (double*)Q, (double*)R, kappa, (const int*)todo);
   } else if (site_dtype == 2) {
+    if (todo)
+      hipLaunchKernelGGL((k_reduce_cholqr<cd, float2>), g, bc, 0, st, d, na, D, rg, (const float2*)site,
+                         (const cd*)gf, gf_stride, side, (cd*)Q, (cd*)R, kappa, todo);
     hipLaunchKernelGGL((k_reduce_qr<cd, float2>), g, b, 0, st, d, na, D, rg, (const float2*)site,
-                       (const cd*)gf, gf_stride, side, (cd*)Q, (cd*)R, kappa);
+                       (const cd*)gf, gf_stride, side, (cd*)Q, (cd*)R, kappa, (const int*)todo);
   } else {
+    if (todo)
+      hipLaunchKernelGGL((k_reduce_cholqr<cd, cd>), g, bc, 0, st, d, na, D, rg, (const cd*)site, (const cd*)gf,
+                         gf_stride, side, (cd*)Q, (cd*)R, kappa, todo);
     hipLaunchKernelGGL((k_reduce_qr<cd, cd>), g, b, 0, st, d, na, D, rg, (const cd*)site, (const cd*)gf,
-                       gf_stride, side, (cd*)Q, (cd*)R, kappa);
+                       gf_stride, side, (cd*)Q, (cd*)R, kappa, (const int*)todo);
   }
   return hipGetLastError();
 }

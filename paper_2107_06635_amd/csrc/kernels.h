@@ -24,7 +24,7 @@ hipError_t launch_gate_split(bool cplx, int batch, int d, int rg, const void* ga
                              double* sigma, hipStream_t st);
 hipError_t launch_reduce_qr(bool cplx, int site_dtype, int batch, int d, int na, int D, int rg,
                             const void* site, const void* gf, long long gf_stride, int side, void* Q, void* R,
-                            double kappa, hipStream_t st);
+                            double kappa, int* todo, hipStream_t st);
 hipError_t launch_recombine(bool cplx, int batch, int p, int D, int R, const void* QX, const void* QY,
                             const void* MX, const void* MY, void* Xn, void* Yn, int rot, hipStream_t st);
 hipError_t launch_rotate_cw(bool cplx, int batch, int p, int D, const void* src, void* dst, hipStream_t st);
