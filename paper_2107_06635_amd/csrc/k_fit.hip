@@ -78,7 +78,14 @@ NTU_DEV void fit_matvec(const T* __restrict__ g, int n, const T* v, T* out, T* m
     const int r = tid % n, part = tid / n;
     const int c1 = min(n, (part + 1) * cs);
     T acc = zerov<T>();
-    for (int c = part * cs; c < c1; ++c) acc += cmul(g[(size_t)c * n + r], v[c]);
+    for (int c0 = part * cs; c0 < c1; c0 += 8) {
+      T gv[8];
+#pragma unroll
+      for (int l = 0; l < 8; ++l) gv[l] = c0 + l < c1 ? g[(size_t)(c0 + l) * n + r] : zerov<T>();
+#pragma unroll
+      for (int l = 0; l < 8; ++l)
+        if (c0 + l < c1) acc += cmul(gv[l], v[c0 + l]);
+    }
     mv[tid] = acc;
   }
   __syncthreads();
@@ -284,7 +291,8 @@ NTU_DEV double fit_solve(const T* gs, int nx, const FitParams& fp, const FitShar
 // ---------------------------------------------------------------------------
 constexpr int FAST_NX = 128;        // largest R D on the certified path
 constexpr int FIT_CERT_NMAX = 256;  // largest R^2 certified by the shifted Cholesky
-constexpr int FORM_JB = 8;
+constexpr int FORM_JB = 8;          // columns of Q per thread
+constexpr int FORM_LB = 8;          // loads issued together
 constexpr int CG_NX = 128;          // largest R D solved by conjugate gradients
 
 template <class T>
@@ -298,12 +306,21 @@ NTU_DEV void form_gs(const T* __restrict__ Gm, const T* __restrict__ gyv, int R,
     T acc[FORM_JB];
 #pragma unroll
     for (int u = 0; u < FORM_JB; ++u) acc[u] = zerov<T>();
-    for (int y = 0; y < R; ++y) {
-      const int col = half == 0 ? x * R + y : y * R + x;
-      const T gv = conjv(Gm[(size_t)col * n + r]);
-      const T* qy = Q + y * FIT_RMAX + jb * FORM_JB;
+    for (int y0 = 0; y0 < R; y0 += FORM_LB) {
+      // FORM_LB loads in flight, then their products
+      T gv[FORM_LB];
 #pragma unroll
-      for (int u = 0; u < FORM_JB; ++u) acc[u] += gv * qy[u];
+      for (int l = 0; l < FORM_LB; ++l) {
+        const int y = y0 + l;
+        const int col = half == 0 ? x * R + y : y * R + x;
+        gv[l] = y < R ? conjv(Gm[(size_t)col * n + r]) : zerov<T>();
+      }
+#pragma unroll
+      for (int l = 0; l < FORM_LB; ++l) {
+        const T* qy = Q + min(y0 + l, R - 1) * FIT_RMAX + jb * FORM_JB;
+#pragma unroll
+        for (int u = 0; u < FORM_JB; ++u) acc[u] += gv[l] * qy[u];
+      }
     }
 #pragma unroll
     for (int u = 0; u < FORM_JB; ++u) {
@@ -318,11 +335,19 @@ NTU_DEV void form_gs(const T* __restrict__ Gm, const T* __restrict__ gyv, int R,
     T acc[FORM_JB];
 #pragma unroll
     for (int u = 0; u < FORM_JB; ++u) acc[u] = zerov<T>();
-    for (int i = 0; i < R; ++i) {
-      const T v = G1[(size_t)(half == 0 ? o * R + i : i * R + o) * nx + c];
-      const T* qi = Q + i * FIT_RMAX + jb * FORM_JB;
+    for (int i0 = 0; i0 < R; i0 += FORM_LB) {
+      T v[FORM_LB];
 #pragma unroll
-      for (int u = 0; u < FORM_JB; ++u) acc[u] += cmul(qi[u], v);
+      for (int l = 0; l < FORM_LB; ++l) {
+        const int i = i0 + l;
+        v[l] = i < R ? G1[(size_t)(half == 0 ? o * R + i : i * R + o) * nx + c] : zerov<T>();
+      }
+#pragma unroll
+      for (int l = 0; l < FORM_LB; ++l) {
+        const T* qi = Q + min(i0 + l, R - 1) * FIT_RMAX + jb * FORM_JB;
+#pragma unroll
+        for (int u = 0; u < FORM_JB; ++u) acc[u] += cmul(qi[u], v[l]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < FORM_JB; ++u) {
@@ -389,7 +414,14 @@ NTU_DEV bool cg_solve(const T* __restrict__ gs, int nx, const T* J, T* m, T* p, 
       const int i = tid % nx, part = tid / nx;
       const int j1 = min(nx, (part + 1) * cs);
       T acc = zerov<T>();
-      for (int j = part * cs; j < j1; ++j) acc += cmul(gs[(size_t)j * nx + i], p[j]);
+      for (int j0 = part * cs; j0 < j1; j0 += FORM_LB) {
+        T v[FORM_LB];
+#pragma unroll
+        for (int l = 0; l < FORM_LB; ++l) v[l] = j0 + l < j1 ? gs[(size_t)(j0 + l) * nx + i] : zerov<T>();
+#pragma unroll
+        for (int l = 0; l < FORM_LB; ++l)
+          if (j0 + l < j1) acc += cmul(v[l], p[j0 + l]);
+      }
       mv[tid] = acc;
     }
     __syncthreads();

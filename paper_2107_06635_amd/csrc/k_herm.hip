@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(HERM_THREADS) k_hermitise(int n, T* g, double*
 // and nothing changes; otherwise g <- V max(Lambda, 0) V^H on that block.
 template <class T>
 __global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stats, int sstride, T* ws) {
-  __shared__ double red[64];
+  __shared__ double red[1024];  // >= blockDim.x (Gershgorin partial sums)
   __shared__ int idx[1024];
   __shared__ int m_sh, cnt;
   __shared__ double pc[512], ps[512];

@@ -203,6 +203,234 @@ __global__ void __launch_bounds__(256) k_mfma_nt(const TA* __restrict__ A, const
       }
 }
 
+// ---------------------------------------------------------------------------
+// Tiled variant for operands whose rows are contiguous in K (all products of
+// the environment contraction): 128 x 128 real-embedded output tiles, four
+// waves of 64 x 64 (4 x 4 MFMA tiles each), K in steps of 32 with the next
+// step's global loads in registers while the current step runs on the
+// matrix cores, double-buffered shared memory, one barrier per step.
+// Blocks are dealt to the 8 XCDs round-robin by id; the tile order puts the
+// tiles (and K chunks) of one item on one XCD, consecutively, so they share
+// that XCD's L2.  Output offsets are tabulated once per block.
+// VEC = 2: pairs of values per load (K and all row strides even).
+// ---------------------------------------------------------------------------
+constexpr int TL_M = 128, TL_N = 128, TL_K = 32, TL_LD = TL_K + 8;
+
+struct alignas(8) f2v { float v[2]; };
+struct alignas(16) d2v { double v[2]; };
+template <int VEC, class TIn> NTU_DEV void load_pair(const TIn* p, float* out);
+template <> NTU_DEV void load_pair<2, float>(const float* p, float* out) {
+  const f2v x = *(const f2v*)p;
+  out[0] = x.v[0]; out[1] = x.v[1];
+}
+template <> NTU_DEV void load_pair<2, double>(const double* p, float* out) {
+  const d2v x = *(const d2v*)p;
+  out[0] = (float)x.v[0]; out[1] = (float)x.v[1];
+}
+
+struct TileArgs {
+  GemmNT d;
+  int tiles_m, tiles_n, ksplit, kchunk;  // kchunk: real K per chunk, multiple of TL_K
+  int nwork;                             // batch * tiles * ksplit
+  double* partial;                       // ksplit > 1: [split][item][Mr][Nr]
+};
+
+template <int PREC, bool CPLX, int VEC, class TA, class TB, class TC>
+__global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, const TB* __restrict__ B,
+                                                  TC* __restrict__ C, TileArgs ta) {
+  using E = typename SplitTraits<PREC>::E;
+  constexpr int NT = SplitTraits<PREC>::NT;
+  constexpr int NACC = (PREC == NTU_PREC_BF16X6) ? 3 : 2;
+  constexpr int CW = CPLX ? 2 : 1;
+  constexpr int NGA = TL_M * TL_K / 4 / 256;                 // groups of 4 reals of A per thread (4)
+  constexpr int NGB = CPLX ? NGA / 2 : NGA;                  // of B (complex rows give two real rows)
+  __shared__ __attribute__((aligned(16))) E sA[2][NT][TL_M][TL_LD];
+  __shared__ __attribute__((aligned(16))) E sB[2][NT][TL_N][TL_LD];
+  __shared__ long long rowoff[TL_M];
+  __shared__ long long coloff[TL_N];
+  const GemmNT& d = ta.d;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
+  const int per = (ta.nwork + 7) / 8;
+  const int q = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (q >= ta.nwork) return;
+  const int T = ta.tiles_m * ta.tiles_n;
+  const int item = q / (T * ta.ksplit), rem = q % (T * ta.ksplit);
+  const int tile = rem / ta.ksplit, split = rem % ta.ksplit;
+  const int i0 = (tile / ta.tiles_n) * TL_M, j0 = (tile % ta.tiles_n) * TL_N;
+  const int Mr = d.M, Nr = CW * d.N, Kr = CW * d.K;
+  const int kbeg = split * ta.kchunk, kend = min(Kr, kbeg + ta.kchunk);
+  const TA* Ab = A + idx_off(d.Ab, item) * CW;
+  const TB* Bb = B + idx_off(d.Bb, item) * CW;
+
+  for (int r = tid; r < TL_M; r += 256) {
+    const int i = i0 + r;
+    rowoff[r] = i < Mr ? idx_off(d.Ci, i) * CW : -1;
+  }
+  for (int c = tid; c < TL_N; c += 256) {
+    const int jr = j0 + c;
+    coloff[c] = jr < Nr ? idx_off(d.Cj, CPLX ? jr >> 1 : jr) * CW + (CPLX ? (jr & 1) : 0) : -1;
+  }
+  // this thread's load groups: (row, 4 reals at kq)
+  const TA* arow[NGA];
+  int akq[NGA], arl[NGA];
+#pragma unroll
+  for (int u = 0; u < NGA; ++u) {
+    const int g = tid + 256 * u, rl = g / (TL_K / 4);
+    arl[u] = rl;
+    akq[u] = (g % (TL_K / 4)) * 4;
+    arow[u] = i0 + rl < Mr ? Ab + idx_off(d.Ai, i0 + rl) * CW : nullptr;
+  }
+  const TB* brow[NGB];
+  int bkq[NGB], brl[NGB];
+#pragma unroll
+  for (int u = 0; u < NGB; ++u) {
+    const int g = tid + 256 * u, rl = g / (TL_K / 4);   // rl: complex row (CPLX) or real row
+    brl[u] = rl;
+    bkq[u] = (g % (TL_K / 4)) * 4;
+    const int jrow = CPLX ? j0 / 2 + rl : j0 + rl;
+    const bool ok = CPLX ? 2 * jrow < Nr : jrow < Nr;
+    brow[u] = ok ? Bb + idx_off(d.Bj, jrow) * CW : nullptr;
+  }
+  float ra[NGA][4], rb[NGB][4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NGA; ++u) {
+      const int k = k0 + akq[u];
+      ra[u][0] = ra[u][1] = ra[u][2] = ra[u][3] = 0.0f;
+      if (arow[u]) {
+        if constexpr (VEC == 2) {
+          if (k < kend) load_pair<2, TA>(arow[u] + k, &ra[u][0]);
+          if (k + 2 < kend) load_pair<2, TA>(arow[u] + k + 2, &ra[u][2]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (k + e < kend) ra[u][e] = (float)arow[u][k + e];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NGB; ++u) {
+      const int k = k0 + bkq[u];
+      rb[u][0] = rb[u][1] = rb[u][2] = rb[u][3] = 0.0f;
+      if (brow[u]) {
+        if constexpr (VEC == 2) {
+          if (k < kend) load_pair<2, TB>(brow[u] + k, &rb[u][0]);
+          if (k + 2 < kend) load_pair<2, TB>(brow[u] + k + 2, &rb[u][2]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (k + e < kend) rb[u][e] = (float)brow[u][k + e];
+        }
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NGA; ++u) {
+      E t[4][NT];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) split_value<PREC>(ra[u][e], t[e]);
+#pragma unroll
+      for (int p = 0; p < NT; ++p)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sA[buf][p][arl[u]][akq[u] + e] = t[e][p];
+    }
+#pragma unroll
+    for (int u = 0; u < NGB; ++u) {
+      if constexpr (CPLX) {
+        // complex values (re0, im0), (re1, im1) -> real rows 2r: (re, -im), 2r+1: (im, re)
+        const float s = d.conjB ? -1.0f : 1.0f;
+        const float re0 = rb[u][0], im0 = s * rb[u][1], re1 = rb[u][2], im1 = s * rb[u][3];
+        const float v0[4] = {re0, -im0, re1, -im1}, v1[4] = {im0, re0, im1, re1};
+        E t0[4][NT], t1[4][NT];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          split_value<PREC>(v0[e], t0[e]);
+          split_value<PREC>(v1[e], t1[e]);
+        }
+#pragma unroll
+        for (int p = 0; p < NT; ++p)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            sB[buf][p][2 * brl[u]][bkq[u] + e] = t0[e][p];
+            sB[buf][p][2 * brl[u] + 1][bkq[u] + e] = t1[e][p];
+          }
+      } else {
+        E t[4][NT];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) split_value<PREC>(rb[u][e], t[e]);
+#pragma unroll
+        for (int p = 0; p < NT; ++p)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) sB[buf][p][brl[u]][bkq[u] + e] = t[e][p];
+      }
+    }
+  };
+
+  f32x4 acc[NACC][4][4];
+#pragma unroll
+  for (int c = 0; c < NACC; ++c)
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[c][x][y] = f32x4{0, 0, 0, 0};
+
+  const int nsteps = (kend - kbeg + TL_K - 1) / TL_K;
+  gload(kbeg);
+  lstore(0);
+  __syncthreads();
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  for (int s = 0; s < nsteps; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nsteps) gload(kbeg + (s + 1) * TL_K);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int ra_ = wm * 64 + x * 16 + fr;
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int rb_ = wn * 64 + y * 16 + fr;
+        const E* a0 = &sA[buf][0][ra_][fk];
+        const E* a1 = &sA[buf][1][ra_][fk];
+        const E* b0 = &sB[buf][0][rb_][fk];
+        const E* b1 = &sB[buf][1][rb_][fk];
+        acc[0][x][y] = mfma<PREC>(a0, b0, acc[0][x][y]);
+        acc[1][x][y] = mfma<PREC>(a0, b1, acc[1][x][y]);
+        acc[1][x][y] = mfma<PREC>(a1, b0, acc[1][x][y]);
+        if constexpr (PREC == NTU_PREC_BF16X6) {
+          const E* a2 = &sA[buf][2][ra_][fk];
+          const E* b2 = &sB[buf][2][rb_][fk];
+          acc[2][x][y] = mfma<PREC>(a0, b2, acc[2][x][y]);
+          acc[2][x][y] = mfma<PREC>(a1, b1, acc[2][x][y]);
+          acc[2][x][y] = mfma<PREC>(a2, b0, acc[2][x][y]);
+        }
+      }
+    }
+    if (s + 1 < nsteps) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  // epilogue: lane holds column (lane & 15), rows 4 (lane >> 4) + v of each 16 x 16 tile
+  const long long cbase = idx_off(d.Cb, item) * CW;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int il = wm * 64 + x * 16 + 4 * (lane >> 4) + v;
+        const int jl = wn * 64 + y * 16 + (lane & 15);
+        double val;
+        if constexpr (PREC == NTU_PREC_BF16X6) val = (double)acc[0][x][y][v] + ((double)acc[1][x][y][v] + (double)acc[2][x][y][v]);
+        else val = (double)acc[0][x][y][v] + (double)acc[1][x][y][v];
+        if (ta.ksplit > 1) {
+          const int i = i0 + il, jr = j0 + jl;
+          if (i < Mr && jr < Nr) ta.partial[(((size_t)split * d.batch + item) * Mr + i) * Nr + jr] = val;
+        } else {
+          const long long ro = rowoff[il], co = coloff[jl];
+          if (ro >= 0 && co >= 0) C[cbase + ro + co] = (TC)val;
+        }
+      }
+}
+
 // sum the split-K partials in FP64 and scatter to C through its index maps
 template <bool CPLX, class TC>
 __global__ void k_splitk_reduce(const double* __restrict__ partial, TC* __restrict__ C, GemmNT d, int ksplit) {
@@ -246,6 +474,55 @@ static hipError_t run_mixed(const void* A, const void* B, void* C, const GemmNT&
   return hipGetLastError();
 }
 
+// all offsets of an index map even (in scalars)
+static bool idx_even(const Idx3& x, int cw) {
+  return ((x.s0 * cw) % 2 == 0) && ((x.s1 * cw) % 2 == 0) && ((x.s2 * cw) % 2 == 0);
+}
+
+template <int PREC, bool CPLX, class TA, class TB, class TC>
+static hipError_t run_tile(const void* A, const void* B, void* C, const GemmNT& d, int ksplit, double* partial,
+                           hipStream_t st, const ProfHook& ph, int kind) {
+  constexpr int CW = CPLX ? 2 : 1;
+  const int Mr = d.M, Nr = CW * d.N, Kr = CW * d.K;
+  TileArgs a{};
+  a.d = d;
+  a.tiles_m = (Mr + TL_M - 1) / TL_M;
+  a.tiles_n = (Nr + TL_N - 1) / TL_N;
+  a.ksplit = ksplit < 1 ? 1 : ksplit;
+  int chunk = (Kr + a.ksplit - 1) / a.ksplit;
+  chunk = (chunk + TL_K - 1) / TL_K * TL_K;
+  a.kchunk = chunk;
+  a.ksplit = (Kr + chunk - 1) / chunk;
+  a.nwork = a.tiles_m * a.tiles_n * a.ksplit * d.batch;
+  a.partial = partial;
+  const bool vec = (Kr % 2 == 0) && idx_even(d.Ab, CW) && idx_even(d.Ai, CW) && idx_even(d.Bb, CW) &&
+                   idx_even(d.Bj, CW) && ((uintptr_t)A % (2 * sizeof(TA)) == 0) && ((uintptr_t)B % (2 * sizeof(TB)) == 0);
+  const int per = (a.nwork + 7) / 8;
+  dim3 g(8 * per), b(256);
+  ph(kind, 0);
+  if (vec)
+    hipLaunchKernelGGL((k_mfma_tile<PREC, CPLX, 2, TA, TB, TC>), g, b, 0, st, (const TA*)A, (const TB*)B, (TC*)C, a);
+  else
+    hipLaunchKernelGGL((k_mfma_tile<PREC, CPLX, 1, TA, TB, TC>), g, b, 0, st, (const TA*)A, (const TB*)B, (TC*)C, a);
+  ph(kind, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.ksplit == 1) return e;
+  long long tot = (long long)Mr * Nr * d.batch;
+  int gx = (int)std::min<long long>((tot + 255) / 256, 4096);
+  ph(PK_E6RED, 0);
+  hipLaunchKernelGGL((k_splitk_reduce<CPLX, TC>), dim3(gx), dim3(256), 0, st, partial, (TC*)C, d, a.ksplit);
+  ph(PK_E6RED, 1);
+  return hipGetLastError();
+}
+
+// K chunks of the tiled assembly: enough blocks for ~one per CU, chunks of >= 8 steps
+static int tile_ksplit(int batch, int M, int Nr, int Kr) {
+  const long long tiles = (long long)((M + TL_M - 1) / TL_M) * ((Nr + TL_N - 1) / TL_N) * batch;
+  int ks = (int)std::max<long long>(1, 256 / std::max<long long>(1, tiles));
+  const int kmax = std::max(1, Kr / (8 * TL_K));
+  return std::min(ks, std::min(kmax, 32));
+}
+
 // number of K chunks for the final assembly: aim at ~2 waves of workgroups on 256 CUs
 static int e6_ksplit(int batch, int M, int Nr, int Kr) {
   long long tiles = (long long)((M + MT_BM - 1) / MT_BM) * ((Nr + MT_BN - 1) / MT_BN) * batch;
@@ -256,7 +533,7 @@ static int e6_ksplit(int batch, int M, int Nr, int Kr) {
 
 size_t mixed_partial_bytes(bool cplx, int batch, int R, int D) {
   const int M = R * R, Nr = (cplx ? 2 : 1) * R * R, Kr = (cplx ? 2 : 1) * D * D * D * D;
-  const int ks = e6_ksplit(batch, M, Nr, Kr);
+  const int ks = tile_ksplit(batch, M, Nr, Kr);
   return ks > 1 ? (size_t)ks * batch * M * Nr * sizeof(double) : 0;
 }
 
@@ -275,10 +552,10 @@ static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, con
   d.Ai = idx1(pD); d.Ak = idx1(1); d.Bj = idx1(pD); d.Bk = idx1(1);
   d.conjB = 1;
   d.Ci = idx3(D, D, RD4, D3, D); d.Cj = idx3(D, D, D4, D2, 1);
-  e = run_mixed<PREC, CPLX, T64, T64, float>(QXe, QXp, H0, d, 1, nullptr, st, ph, PK_LEFTRIGHT);
+  e = run_tile<PREC, CPLX, T64, T64, float>(QXe, QXp, H0, d, 1, nullptr, st, ph, PK_LEFTRIGHT);
   if (e != hipSuccess) return e;
   d.Ci = idx3(D, D, RD4, D, D3); d.Cj = idx3(D, D, D4, 1, D2);
-  e = run_mixed<PREC, CPLX, T64, T64, float>(QYe, QYp, H2, d, 1, nullptr, st, ph, PK_LEFTRIGHT);
+  e = run_tile<PREC, CPLX, T64, T64, float>(QYe, QYp, H2, d, 1, nullptr, st, ph, PK_LEFTRIGHT);
   if (e != hipSuccess) return e;
   // L1 = Left x Etop, L2 = L1 x Ebot
   GemmNT f{};
@@ -286,10 +563,10 @@ static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, con
   f.Ab = idx1(hs); f.Bb = idx1(es); f.Cb = idx1(hs);
   f.Ai = idx1(D2); f.Ak = idx1(1); f.Bj = idx1(D2); f.Bk = idx1(1);
   f.Ci = idx2((int)D2, D4, 1); f.Cj = idx1(D2);
-  e = run_mixed<PREC, CPLX, float, T64, float>(H0, ETT, H1, f, 1, nullptr, st, ph, PK_E4);
+  e = run_tile<PREC, CPLX, float, T64, float>(H0, ETT, H1, f, 1, nullptr, st, ph, PK_E4);
   if (e != hipSuccess) return e;
   f.Ci = idx1(D2); f.Cj = idx1(1);
-  e = run_mixed<PREC, CPLX, float, T64, float>(H1, EBT, H0, f, 1, nullptr, st, ph, PK_E5);
+  e = run_tile<PREC, CPLX, float, T64, float>(H1, EBT, H0, f, 1, nullptr, st, ph, PK_E5);
   if (e != hipSuccess) return e;
   // g = L2 Right^T with split K, FP64 reduction
   GemmNT q{};
@@ -298,10 +575,10 @@ static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, con
   q.Ai = idx1(D4); q.Ak = idx1(1); q.Bj = idx1(D4); q.Bk = idx1(1);
   q.Ci = idx2(R, R, (long long)R * R * R); q.Cj = idx2(R, 1, (long long)R * R);
   const int Nr = (CPLX ? 2 : 1) * q.N, Kr = (CPLX ? 2 : 1) * q.K;
-  const int ks = e6_ksplit(batch, q.M, Nr, Kr);
+  const int ks = tile_ksplit(batch, q.M, Nr, Kr);
   // partial sums live right after H2 (the workspace reserves mixed_partial_bytes there)
   double* partial = (double*)((char*)H2 + (size_t)batch * hs * (CPLX ? 8 : 4));
-  return run_mixed<PREC, CPLX, float, float, T64>(H0, H2, g, q, ks, partial, st, ph, PK_E6);
+  return run_tile<PREC, CPLX, float, float, T64>(H0, H2, g, q, ks, partial, st, ph, PK_E6);
 }
 
 hipError_t launch_env_heavy_mixed(bool cplx, int precision, int batch, int p, int D, int R, const void* QXe,

@@ -437,20 +437,34 @@ NTU_DEV void blocked_chol_solve(const T* A, int n, int lda, T* b, T* x, T* dblk)
 // Gershgorin certification of g: every eigenvalue lies in the union of the
 // discs |lambda - g_ii| <= sum_{j != i} |g_ij|, so lo = min_i (g_ii - r_i)
 // bounds lambda_min from below and hi = max_i (g_ii + r_i) bounds lambda_max
-// from above.  Certified if lo > margin * hi.  Whole block.
+// from above.  Certified if lo > margin * hi.  Whole block; n <= blockDim.x;
+// red: >= blockDim.x doubles of shared memory.
 template <class T>
 NTU_DEV bool gershgorin_certify(const T* __restrict__ G, int n, double margin, double* red) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // Hermitian G: the off-diagonal absolute row sum of row r equals that of
+  // column r, read with r fastest (coalesced).  Thread (r, part) sums a range
+  // of rows c; parts meet in red (n <= blockDim.x <= 1024).
+  const int tid = threadIdx.x, parts = (int)blockDim.x / n, cs = (n + parts - 1) / parts;
   double lo = INFINITY, hi = -INFINITY;
-  for (int r = w; r < n; r += nw) {
-    const T* gr = G + (size_t)r * n;
-    double off = 0, dg = 0;
-    for (int c = lane; c < n; c += 64) {
-      if (c == r) dg = rev(gr[c]);
-      else off += absv(gr[c]);
+  if (tid < parts * n) {
+    const int r = tid % n, part = tid / n;
+    const int c1 = min(n, (part + 1) * cs);
+    double off = 0.0;
+    for (int c0 = part * cs; c0 < c1; c0 += 8) {
+      T v[8];
+#pragma unroll
+      for (int l = 0; l < 8; ++l) v[l] = c0 + l < c1 ? G[(size_t)(c0 + l) * n + r] : zerov<T>();
+#pragma unroll
+      for (int l = 0; l < 8; ++l)
+        if (c0 + l < c1 && c0 + l != r) off += sqrt(abs2(v[l]));
     }
-    off = wave_sum(off);
-    dg = wave_sum(dg);
+    red[tid] = off;
+  }
+  __syncthreads();
+  for (int r = tid; r < n; r += blockDim.x) {
+    double off = 0.0;
+    for (int part = 0; part < parts; ++part) off += red[part * n + r];
+    const double dg = rev(G[(size_t)r * n + r]);
     lo = fmin(lo, dg - off);
     hi = fmax(hi, dg + off);
   }
