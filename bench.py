@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="batched", choices=["batched", "thermal"])
-    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16x6", "fp16x3", "f64"])
+    ap.add_argument("--precision", default="bf16x6", choices=["bf16x3", "bf16x6", "fp16x3", "f64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)

@@ -98,6 +98,130 @@ static hipError_t gemm_nt(bool cplx, const void* A, const void* B, void* C, cons
 }
 
 // ---------------------------------------------------------------------------
+// Small products of the environment (edge double tensors and the two
+// parallel-bond transfers), M, N <= 64: C(i, j) = sum_k A(i, k) op(B(j, k)),
+// op = conj or identity, several products per launch (blockIdx.x selects the
+// product, blockIdx.y the item).  K is staged through shared memory in
+// chunks, loaded with the fastest-varying index of each operand's memory
+// layout on consecutive threads, from offset tables built once per chunk.
+// M, N > 16: 4 x 4 outputs per thread over a 64 x 64 tile.  M, N <= 16 (the
+// D x D edges with long K): each output is summed by 256 / (M N) threads over
+// interleaved k and the parts meet in shared memory.
+// ---------------------------------------------------------------------------
+struct SmallNT {
+  const void* A;
+  const void* B;
+  void* C;
+  long long sa, sb, sc;  // item strides (elements)
+  Idx3 Ai, Ak, Bj, Bk;   // row / contraction maps
+  long long ldc;         // C row stride
+  int M, N, K;
+  int conjB;
+  int a_kfast, b_kfast;  // 1: consecutive k are adjacent in memory
+};
+struct SmallBatch {
+  SmallNT p[8];
+};
+constexpr int SM_T = 64, SM_KC = 32, SM_KCS = 128;
+
+template <class T>
+__global__ void __launch_bounds__(256) k_small_nt(SmallBatch sb) {
+  const SmallNT& d = sb.p[blockIdx.x];
+  const int it = blockIdx.y, tid = threadIdx.x;
+  const T* A = (const T*)d.A + (size_t)it * d.sa;
+  const T* B = (const T*)d.B + (size_t)it * d.sb;
+  T* C = (T*)d.C + (size_t)it * d.sc;
+  const int M = d.M, N = d.N, K = d.K;
+  const bool small = M <= 16 && N <= 16;
+  const int KC = small ? SM_KCS : SM_KC;
+  __shared__ T SA[SM_KCS * 17 > SM_KC * (SM_T + 1) ? SM_KCS * 17 : SM_KC * (SM_T + 1)];
+  __shared__ T SB[SM_KCS * 17 > SM_KC * (SM_T + 1) ? SM_KCS * 17 : SM_KC * (SM_T + 1)];
+  __shared__ long long roA[SM_T], roB[SM_T];
+  __shared__ long long koA[SM_KCS], koB[SM_KCS];
+  __shared__ T part[256];
+  const int lda = small ? 17 : SM_T + 1;  // S[k * lda + i]
+  for (int i = tid; i < SM_T; i += 256) {
+    roA[i] = i < M ? idx_off(d.Ai, i) : 0;
+    roB[i] = i < N ? idx_off(d.Bj, i) : 0;
+  }
+  const int ty = tid >> 4, tx = tid & 15;
+  T acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = zerov<T>();
+  const int mn = M * N, kpar = small ? 256 / (mn > 0 ? mn : 1) : 1;
+  const int si = small ? tid % (mn > 0 ? mn : 1) / N : 0, sj = small ? tid % (mn > 0 ? mn : 1) % N : 0;
+  const int skp = small ? tid / (mn > 0 ? mn : 1) : 0;
+  T sacc = zerov<T>();
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    const int kc = min(KC, K - k0);
+    __syncthreads();  // previous chunk consumed
+    for (int k = tid; k < kc; k += 256) {
+      koA[k] = idx_off(d.Ak, k0 + k);
+      koB[k] = idx_off(d.Bk, k0 + k);
+    }
+    __syncthreads();
+    // stage A (M x kc) and B (N x kc) as S[k][i]
+    for (int e = tid; e < M * kc; e += 256) {
+      const int i = d.a_kfast ? e / kc : e % M, k = d.a_kfast ? e % kc : e / M;
+      SA[k * lda + i] = A[roA[i] + koA[k]];
+    }
+    for (int e = tid; e < N * kc; e += 256) {
+      const int j = d.b_kfast ? e / kc : e % N, k = d.b_kfast ? e % kc : e / N;
+      const T v = B[roB[j] + koB[k]];
+      SB[k * lda + j] = d.conjB ? conjv(v) : v;
+    }
+    __syncthreads();
+    if (small) {
+      if (skp < kpar && tid < kpar * mn)
+        for (int k = skp; k < kc; k += kpar) sacc += SA[k * lda + si] * SB[k * lda + sj];
+    } else {
+      for (int k = 0; k < kc; ++k) {
+        T a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u] = SA[k * lda + ty + 16 * u];
+          b[u] = SB[k * lda + tx + 16 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+      }
+    }
+  }
+  if (small) {
+    __syncthreads();
+    part[tid] = sacc;
+    __syncthreads();
+    if (tid < mn) {
+      T s = zerov<T>();
+      for (int q = 0; q < kpar; ++q) s += part[q * mn + tid];
+      C[(size_t)(tid / N) * d.ldc + tid % N] = s;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = ty + 16 * u;
+      if (i >= M) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = tx + 16 * v;
+        if (j < N) C[(size_t)i * d.ldc + j] = acc[u][v];
+      }
+    }
+  }
+}
+
+static hipError_t small_nt(bool cplx, const SmallBatch& b, int np, int batch, hipStream_t st) {
+  dim3 g(np, batch), bl(256);
+  if (cplx) hipLaunchKernelGGL(k_small_nt<cd>, g, bl, 0, st, b);
+  else hipLaunchKernelGGL(k_small_nt<double>, g, bl, 0, st, b);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // QXp / QXe (and QYp / QYe): regroup the isometry rows so that the legs
 // contracted in the half environments come last, and multiply the leg that
 // meets L (or Rn) by EL (or ER).
@@ -186,7 +310,41 @@ hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D
   hipError_t err;
 #define NTU_TRY(x) do { err = (x); if (err != hipSuccess) return err; } while (0)
 
-  // 1. edge double tensors (Fig. 4(a,b)): E(i, j) = sum_k T(i, k) conj(T(j, k))
+  // 1. edge double tensors (Fig. 4(a,b)): E(i, j) = sum_k T(i, k) conj(T(j, k)),
+  //    and 2. the parallel-bond transfers
+  //    EtopT[(T T')][(t t')] = sum_{v v'} ETY[T v T' v'] ETX[t v t' v'] (EbotT alike)
+  ph(PK_EDGES, 0);
+  if (D2 <= SM_T) {
+    SmallBatch eb{};
+    auto gram = [&](int slot, const void* Tn, char* out, Idx3 Ii, Idx3 Ik, int M, int K, int kfast) {
+      SmallNT& q = eb.p[slot];
+      q.A = Tn; q.B = Tn; q.C = out;
+      q.sa = site; q.sb = site; q.sc = es;
+      q.Ai = Ii; q.Ak = Ik; q.Bj = Ii; q.Bk = Ik;
+      q.ldc = M; q.M = M; q.N = M; q.K = K; q.conjB = 1;
+      q.a_kfast = kfast; q.b_kfast = kfast;
+    };
+    gram(0, nbr[0], EL, idx1(1), idx1(D), D, (int)(p * D3), 0);                                 // k = (p, t, l, b)
+    gram(1, nbr[5], ER, idx1(D2), idx2((int)D2, D3, 1), D, (int)(p * D3), 1);                   // k = ((p, t), (b, r))
+    gram(2, nbr[1], ETX, idx1(1), idx1(D2), (int)D2, (int)(p * D2), 0);                          // u = b, v = r
+    gram(3, nbr[3], ETY, idx2(D, D, D2), idx2(D, D3, 1), (int)D2, (int)(p * D2), 1);             // u = b, v = l
+    gram(4, nbr[2], EBX, idx2(D, D3, 1), idx2((int)D2, D4, D), (int)D2, (int)(p * D2), 0);       // u = t, v = r
+    gram(5, nbr[4], EBY, idx2(D, D3, D2), idx2((int)D2, D4, 1), (int)D2, (int)(p * D2), 1);      // u = t, v = l
+    NTU_TRY(small_nt(cplx, eb, 6, batch, st));
+    SmallBatch tb{};
+    auto transfer = [&](int slot, const char* Ay, const char* Bx, char* out) {
+      SmallNT& q = tb.p[slot];
+      q.A = Ay; q.B = Bx; q.C = out;
+      q.sa = es; q.sb = es; q.sc = es;
+      q.Ai = idx2(D, D3, D); q.Ak = idx2(D, D2, 1);
+      q.Bj = idx2(D, D3, D); q.Bk = idx2(D, D2, 1);
+      q.ldc = D2; q.M = (int)D2; q.N = (int)D2; q.K = (int)D2; q.conjB = 0;
+      q.a_kfast = 1; q.b_kfast = 1;
+    };
+    transfer(0, ETY, ETX, ETT);
+    transfer(1, EBY, EBX, EBT);
+    NTU_TRY(small_nt(cplx, tb, 2, batch, st));
+  } else {
   auto edge2 = [&](const void* T, char* out, Idx3 Ii, Idx3 Ik, int M, int K) {
     GemmNT d{};
     d.M = M; d.N = M; d.K = K; d.batch = batch;
@@ -196,30 +354,20 @@ hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D
     d.conjA = 0; d.conjB = 1;
     return gemm_nt(cplx, T, T, out, d, st);
   };
-  ph(PK_EDGES, 0);
-  // EL: L's right leg; k = (p, t, l, b)
   NTU_TRY(edge2(nbr[0], EL, idx1(1), idx1(D), D, (int)(p * D3)));
-  // ER: Rn's left leg; k = ((p, t), (b, r))
   NTU_TRY(edge2(nbr[5], ER, idx1(D2), idx2((int)D2, D3, 1), D, (int)(p * D3)));
-  // ETX: (u = b, v = r) contiguous; k = (p, t, l)
   NTU_TRY(edge2(nbr[1], ETX, idx1(1), idx1(D2), (int)D2, (int)(p * D2)));
-  // ETY: u = b, v = l; k = ((p, t), r)
   NTU_TRY(edge2(nbr[3], ETY, idx2(D, D, D2), idx2(D, D3, 1), (int)D2, (int)(p * D2)));
-  // EBX: u = t, v = r; k = (p, (l, b))
   NTU_TRY(edge2(nbr[2], EBX, idx2(D, D3, 1), idx2((int)D2, D4, D), (int)D2, (int)(p * D2)));
-  // EBY: u = t, v = l; k = (p, (b, r))
   NTU_TRY(edge2(nbr[4], EBY, idx2(D, D3, D2), idx2((int)D2, D4, 1), (int)D2, (int)(p * D2)));
-
-  // 2. parallel bonds: EtopT[(T T')][(t t')] = sum_{v v'} ETY[T v T' v'] ETX[t v t' v']
-  {
-    GemmNT d{};
-    d.M = (int)D2; d.N = (int)D2; d.K = (int)D2; d.batch = batch;
-    d.Ab = idx1(es); d.Bb = idx1(es); d.Cb = idx1(es);
-    d.Ai = idx2(D, D3, D); d.Ak = idx2(D, D2, 1);
-    d.Bj = idx2(D, D3, D); d.Bk = idx2(D, D2, 1);
-    d.Ci = idx1(D2); d.Cj = idx1(1);
-    NTU_TRY(gemm_nt(cplx, ETY, ETX, ETT, d, st));
-    NTU_TRY(gemm_nt(cplx, EBY, EBX, EBT, d, st));
+  GemmNT d{};
+  d.M = (int)D2; d.N = (int)D2; d.K = (int)D2; d.batch = batch;
+  d.Ab = idx1(es); d.Bb = idx1(es); d.Cb = idx1(es);
+  d.Ai = idx2(D, D3, D); d.Ak = idx2(D, D2, 1);
+  d.Bj = idx2(D, D3, D); d.Bk = idx2(D, D2, 1);
+  d.Ci = idx1(D2); d.Cj = idx1(1);
+  NTU_TRY(gemm_nt(cplx, ETY, ETX, ETT, d, st));
+  NTU_TRY(gemm_nt(cplx, EBY, EBX, EBT, d, st));
   }
   ph(PK_EDGES, 1);
 
