@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-steps", type=int, default=1)
+    ap.add_argument("--bucket", type=int, default=0,
+                    help="batched workload: only the items of this bond dimension (0 = all 256)")
     return ap.parse_args()
 
 
@@ -66,8 +68,10 @@ class Job:
     """One workload: a list of (D, batch tensors) buckets and a step function."""
 
 
-def build_batched(ntu, inputs, dev, torch, np):
+def build_batched(ntu, inputs, dev, torch, np, only_D=None):
     items = inputs.workload_batched()
+    if only_D:
+        items = [it for it in items if it["D"] == only_D]
     buckets = {}
     for it in items:
         buckets.setdefault(it["D"], []).append(it)
@@ -124,7 +128,10 @@ def main():
 
     dev = torch.device("cuda", 0)
     K, W = args.steps, args.warmup
-    job = (build_batched if args.workload == "batched" else build_thermal)(ntu, inputs, dev, torch, np)
+    if args.workload == "batched":
+        job = build_batched(ntu, inputs, dev, torch, np, only_D=args.bucket)
+    else:
+        job = build_thermal(ntu, inputs, dev, torch, np)
     fit = dict(n_iter=20, early_stop=True, conv_tol=1e-12)
     opts = ntu.step_opts(args.precision, order=job.order, **fit)
     opts64 = ntu.step_opts("f64", order=job.order, **fit)
@@ -177,7 +184,8 @@ def main():
         "data": "synthetic",
     }
     if args.workload == "batched":
-        result["config"] = {"workload": "configuration 4: 256 independent bond updates, D uniform in {3..8}",
+        result["config"] = {"workload": "configuration 4: 256 independent bond updates, D uniform in {3..8}"
+                            + (f", only the D={args.bucket} items" if args.bucket else ""),
                             "items": upd, "D_counts": {str(bk["D"]): bk["n"] for bk in job.buckets},
                             "h_x": "uniform [2.5, 3.5]", "dt": 0.01, "env_precision": args.precision,
                             "fit": "fp64, <=20 ALS iterations, early stop 1e-12 N",

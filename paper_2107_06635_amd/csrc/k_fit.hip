@@ -365,6 +365,159 @@ NTU_DEV void form_gs(const T* __restrict__ Gm, const T* __restrict__ gyv, int R,
   __syncthreads();
 }
 
+// The same two passes on the FP64 matrix cores (v_mfma_f64_16x16x4: lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16] and receives
+// D[l / 16 + 4 v][l % 16]).  Complex products use two real products into one
+// accumulator: with B' = [Re Q | Im Q] and B'' = [-Im Q | Re Q] (columns
+// 0-7 | 8-15), Re(A) B' + Im(A) B'' = [Re(A Q) | Im(A Q)]; pass 2 stacks the
+// rows the same way.  Each wave takes whole 16 x 16 output tiles.  Needs
+// R <= FIT_RMAX, Dn <= 8 (complex) or 16 (real).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+NTU_DEV void form_gs_mfma(const T* __restrict__ Gm, const T* __restrict__ gyv, int R, int Dn, int half, const T* Q,
+                          T* __restrict__ G1, T* __restrict__ gs, T* J) {
+  constexpr bool CPLX = is_cplx<T>::value;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int n = R * R, nx = R * Dn, nkc = (R + 3) / 4;
+  const int l16 = lane & 15, lk = lane >> 4;
+  double* G1d = (double*)G1;
+  double* gsd = (double*)gs;
+  // pass 1 B operands for every K chunk: row y = 4 kc + lk, column l16
+  double b1[(FIT_RMAX + 3) / 4], b2[(FIT_RMAX + 3) / 4];
+#pragma unroll
+  for (int kc = 0; kc < (FIT_RMAX + 3) / 4; ++kc) {
+    const int y = 4 * kc + lk;
+    double v1 = 0.0, v2 = 0.0;
+    if (kc < nkc && y < R) {
+      if constexpr (CPLX) {
+        const int j = l16 & 7;
+        if (j < Dn) {
+          const T q = Q[y * FIT_RMAX + j];
+          v1 = l16 < 8 ? rev(q) : imv(q);
+          v2 = l16 < 8 ? -imv(q) : rev(q);
+        }
+      } else {
+        if (l16 < Dn) v1 = rev(Q[y * FIT_RMAX + l16]);
+      }
+    }
+    b1[kc] = v1;
+    b2[kc] = v2;
+  }
+  // two output tiles per wave at a time: their loads are in flight together
+  const int nrt = (n + 15) / 16, nu1 = R * nrt;
+  for (int u0 = w; u0 < nu1; u0 += 2 * nw) {
+    T gv[2][(FIT_RMAX + 3) / 4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int u = u0 + h * nw;
+      const int x = u / nrt, r = (u % nrt) * 16 + l16;
+#pragma unroll
+      for (int kc = 0; kc < (FIT_RMAX + 3) / 4; ++kc) {
+        const int y = 4 * kc + lk;
+        gv[h][kc] = zerov<T>();
+        if (u < nu1 && kc < nkc && y < R && r < n)
+          gv[h][kc] = conjv(Gm[(size_t)(half == 0 ? x * R + y : y * R + x) * n + r]);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int u = u0 + h * nw;
+      if (u >= nu1) break;
+      const int x = u / nrt, r0 = (u % nrt) * 16;
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kc = 0; kc < (FIT_RMAX + 3) / 4; ++kc) {
+        if (kc < nkc) {
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(rev(gv[h][kc]), b1[kc], acc, 0, 0, 0);
+          if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(imv(gv[h][kc]), b2[kc], acc, 0, 0, 0);
+        }
+      }
+      // lane holds rows r0 + lk + 4 v, column l16
+      const int j = CPLX ? (l16 & 7) : l16, part = CPLX ? (l16 >> 3) : 0;
+      if (j < Dn) {
+        const int c = half == 0 ? x * Dn + j : j * R + x;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = r0 + lk + 4 * v;
+          if (rr < n) G1d[((size_t)rr * nx + c) * (CPLX ? 2 : 1) + part] = acc[v];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // pass 2: A operands (rows j' stacked re / im for complex) for every K chunk
+  double a1[(FIT_RMAX + 3) / 4], a2[(FIT_RMAX + 3) / 4];
+#pragma unroll
+  for (int kc = 0; kc < (FIT_RMAX + 3) / 4; ++kc) {
+    const int i = 4 * kc + lk;
+    double v1 = 0.0, v2 = 0.0;
+    if (kc < nkc && i < R) {
+      if constexpr (CPLX) {
+        const int jp = l16 & 7;
+        if (jp < Dn) {
+          const T q = Q[i * FIT_RMAX + jp];
+          // conj(Q) = Pr + i Pi with Pr = Re Q, Pi = -Im Q;  A' = [Pr; Pi], A'' = [-Pi; Pr]
+          v1 = l16 < 8 ? rev(q) : -imv(q);
+          v2 = l16 < 8 ? imv(q) : rev(q);
+        }
+      } else {
+        if (l16 < Dn) v1 = rev(Q[i * FIT_RMAX + l16]);
+      }
+    }
+    a1[kc] = v1;
+    a2[kc] = v2;
+  }
+  const int nct = (nx + 15) / 16, nu2 = R * nct;
+  for (int u0 = w; u0 < nu2; u0 += 2 * nw) {
+    T gv[2][(FIT_RMAX + 3) / 4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int u = u0 + h * nw;
+      const int o = u / nct, c = (u % nct) * 16 + l16;
+#pragma unroll
+      for (int kc = 0; kc < (FIT_RMAX + 3) / 4; ++kc) {
+        const int i = 4 * kc + lk;
+        gv[h][kc] = zerov<T>();
+        if (u < nu2 && kc < nkc && i < R && c < nx) gv[h][kc] = G1[(size_t)(half == 0 ? o * R + i : i * R + o) * nx + c];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int u = u0 + h * nw;
+      if (u >= nu2) break;
+      const int o = u / nct, c = (u % nct) * 16 + l16;
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kc = 0; kc < (FIT_RMAX + 3) / 4; ++kc) {
+        if (kc < nkc) {
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[kc], rev(gv[h][kc]), acc, 0, 0, 0);
+          if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[kc], imv(gv[h][kc]), acc, 0, 0, 0);
+        }
+      }
+      if (c < nx) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i16 = lk + 4 * v;
+          const int jp = CPLX ? (i16 & 7) : i16, part = CPLX ? (i16 >> 3) : 0;
+          if (jp < Dn) {
+            const int row = half == 0 ? o * Dn + jp : jp * R + o;
+            gsd[((size_t)row * nx + c) * (CPLX ? 2 : 1) + part] = acc[v];
+          }
+        }
+      }
+    }
+  }
+  // J[(o, j')] = sum_i conj(Q[i][j']) gy[row(o, i)]
+  for (int e = threadIdx.x; e < nx; e += blockDim.x) {
+    const int o = half == 0 ? e / Dn : e % R, jp = half == 0 ? e % Dn : e / R;
+    T acc = zerov<T>();
+    for (int i = 0; i < R; ++i) acc += cmul(Q[i * FIT_RMAX + jp], gyv[half == 0 ? o * R + i : i * R + o]);
+    J[e] = acc;
+  }
+  __syncthreads();
+}
+
 // Dependent directions (zero columns of Q) of g_s: unit rows and columns,
 // zero right-hand side.  zcol[j] != 0 marks column j of Q.  Whole block.
 template <class T>
@@ -643,7 +796,8 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
       double tau = fp.tol[fp.n_tol - 1];
       bool fast_done = false;
       if (certified) {
-        form_gs<T>(G, gy, R, Dn, half, S.Qf, G1, gs, S.J);
+        if (Dn <= (is_cplx<T>::value ? 8 : 16)) form_gs_mfma<T>(G, gy, R, Dn, half, S.Qf, G1, gs, S.J);
+        else form_gs<T>(G, gy, R, Dn, half, S.Qf, G1, gs, S.J);
         tick(1);
         if (tid < Dn) {
           bool z = true;

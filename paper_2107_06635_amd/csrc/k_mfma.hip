@@ -244,8 +244,11 @@ __global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, con
   constexpr int CW = CPLX ? 2 : 1;
   constexpr int NGA = TL_M * TL_K / 4 / 256;                 // groups of 4 reals of A per thread (4)
   constexpr int NGB = CPLX ? NGA / 2 : NGA;                  // of B (complex rows give two real rows)
-  __shared__ __attribute__((aligned(16))) E sA[2][NT][TL_M][TL_LD];
-  __shared__ __attribute__((aligned(16))) E sB[2][NT][TL_N][TL_LD];
+  // one buffer for both operands (double-buffered); the output tile reuses it
+  constexpr int SA_EL = 2 * NT * TL_M * TL_LD, SB_EL = 2 * NT * TL_N * TL_LD;
+  __shared__ __attribute__((aligned(16))) E smem[SA_EL + SB_EL];
+  E (*sA)[NT][TL_M][TL_LD] = reinterpret_cast<E (*)[NT][TL_M][TL_LD]>(smem);
+  E (*sB)[NT][TL_N][TL_LD] = reinterpret_cast<E (*)[NT][TL_N][TL_LD]>(smem + SA_EL);
   __shared__ long long rowoff[TL_M];
   __shared__ long long coloff[TL_N];
   const GemmNT& d = ta.d;
@@ -410,6 +413,49 @@ __global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, con
   }
   // epilogue: lane holds column (lane & 15), rows 4 (lane >> 4) + v of each 16 x 16 tile
   const long long cbase = idx_off(d.Cb, item) * CW;
+  if constexpr (sizeof(TC) == 4) {
+    if (ta.ksplit == 1) {
+      // stage the tile in shared memory (the operand buffers are free after the
+      // last barrier), then write it in the order that is contiguous in C:
+      // row-major if consecutive real columns are adjacent, else column-major
+      // (complex: (re, im) of consecutive rows adjacent)
+      constexpr int OLD = TL_N + 1;
+      static_assert(TL_M * OLD * sizeof(TC) <= (SA_EL + SB_EL) * sizeof(E), "output tile must fit the operand buffers");
+      TC* ot = (TC*)smem;
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int il = wm * 64 + x * 16 + 4 * (lane >> 4) + v;
+            const int jl = wn * 64 + y * 16 + (lane & 15);
+            double val;
+            if constexpr (PREC == NTU_PREC_BF16X6) val = (double)acc[0][x][y][v] + ((double)acc[1][x][y][v] + (double)acc[2][x][y][v]);
+            else val = (double)acc[0][x][y][v] + (double)acc[1][x][y][v];
+            ot[il * OLD + jl] = (TC)val;
+          }
+      __syncthreads();
+      const bool rowmajor = coloff[1] - coloff[0] == 1;
+      for (int e = tid; e < TL_M * TL_N; e += 256) {
+        int il, jl;
+        if (rowmajor) {
+          il = e / TL_N;
+          jl = e % TL_N;
+        } else if (CPLX) {
+          const int part = e & 1, t = e >> 1;
+          il = t % TL_M;
+          jl = 2 * (t / TL_M) + part;
+        } else {
+          il = e % TL_M;
+          jl = e / TL_M;
+        }
+        const long long ro = rowoff[il], co = coloff[jl];
+        if (ro >= 0 && co >= 0) C[cbase + ro + co] = ot[il * OLD + jl];
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
