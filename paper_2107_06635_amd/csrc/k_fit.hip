@@ -374,22 +374,22 @@ NTU_DEV void form_gs(const T* __restrict__ Gm, const T* __restrict__ gyv, int R,
 // R <= FIT_RMAX, Dn <= 8 (complex) or 16 (real).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <class T>
-NTU_DEV void form_gs_mfma(const T* __restrict__ Gm, const T* __restrict__ gyv, int R, int Dn, int half, const T* Q,
-                          T* __restrict__ G1, T* __restrict__ gs, T* J) {
+template <class T, int NKC>
+NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv, int R, int Dn, int half, const T* Q,
+                            T* __restrict__ G1, T* __restrict__ gs, T* J) {
   constexpr bool CPLX = is_cplx<T>::value;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int n = R * R, nx = R * Dn, nkc = (R + 3) / 4;
+  const int n = R * R, nx = R * Dn;
   const int l16 = lane & 15, lk = lane >> 4;
   double* G1d = (double*)G1;
   double* gsd = (double*)gs;
   // pass 1 B operands for every K chunk: row y = 4 kc + lk, column l16
-  double b1[(FIT_RMAX + 3) / 4], b2[(FIT_RMAX + 3) / 4];
+  double b1[NKC], b2[NKC];
 #pragma unroll
-  for (int kc = 0; kc < (FIT_RMAX + 3) / 4; ++kc) {
+  for (int kc = 0; kc < NKC; ++kc) {
     const int y = 4 * kc + lk;
     double v1 = 0.0, v2 = 0.0;
-    if (kc < nkc && y < R) {
+    if (y < R) {
       if constexpr (CPLX) {
         const int j = l16 & 7;
         if (j < Dn) {
@@ -407,17 +407,18 @@ NTU_DEV void form_gs_mfma(const T* __restrict__ Gm, const T* __restrict__ gyv, i
   // two output tiles per wave at a time: their loads are in flight together
   const int nrt = (n + 15) / 16, nu1 = R * nrt;
   for (int u0 = w; u0 < nu1; u0 += 2 * nw) {
-    T gv[2][(FIT_RMAX + 3) / 4];
+    T gv[2][NKC];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int u = u0 + h * nw;
       const int x = u / nrt, r = (u % nrt) * 16 + l16;
 #pragma unroll
-      for (int kc = 0; kc < (FIT_RMAX + 3) / 4; ++kc) {
+      for (int kc = 0; kc < NKC; ++kc) {
         const int y = 4 * kc + lk;
-        gv[h][kc] = zerov<T>();
-        if (u < nu1 && kc < nkc && y < R && r < n)
-          gv[h][kc] = conjv(Gm[(size_t)(half == 0 ? x * R + y : y * R + x) * n + r]);
+        // branch-free: invalid entries load element 0 and are replaced by zero
+        const bool ok = u < nu1 && y < R && r < n;
+        const T gl = Gm[ok ? (size_t)(half == 0 ? x * R + y : y * R + x) * n + r : 0];
+        gv[h][kc] = ok ? conjv(gl) : zerov<T>();
       }
     }
 #pragma unroll
@@ -427,8 +428,8 @@ NTU_DEV void form_gs_mfma(const T* __restrict__ Gm, const T* __restrict__ gyv, i
       const int x = u / nrt, r0 = (u % nrt) * 16;
       f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int kc = 0; kc < (FIT_RMAX + 3) / 4; ++kc) {
-        if (kc < nkc) {
+      for (int kc = 0; kc < NKC; ++kc) {
+        {
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(rev(gv[h][kc]), b1[kc], acc, 0, 0, 0);
           if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(imv(gv[h][kc]), b2[kc], acc, 0, 0, 0);
         }
@@ -447,12 +448,12 @@ NTU_DEV void form_gs_mfma(const T* __restrict__ Gm, const T* __restrict__ gyv, i
   }
   __syncthreads();
   // pass 2: A operands (rows j' stacked re / im for complex) for every K chunk
-  double a1[(FIT_RMAX + 3) / 4], a2[(FIT_RMAX + 3) / 4];
+  double a1[NKC], a2[NKC];
 #pragma unroll
-  for (int kc = 0; kc < (FIT_RMAX + 3) / 4; ++kc) {
+  for (int kc = 0; kc < NKC; ++kc) {
     const int i = 4 * kc + lk;
     double v1 = 0.0, v2 = 0.0;
-    if (kc < nkc && i < R) {
+    if (i < R) {
       if constexpr (CPLX) {
         const int jp = l16 & 7;
         if (jp < Dn) {
@@ -470,16 +471,17 @@ NTU_DEV void form_gs_mfma(const T* __restrict__ Gm, const T* __restrict__ gyv, i
   }
   const int nct = (nx + 15) / 16, nu2 = R * nct;
   for (int u0 = w; u0 < nu2; u0 += 2 * nw) {
-    T gv[2][(FIT_RMAX + 3) / 4];
+    T gv[2][NKC];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int u = u0 + h * nw;
       const int o = u / nct, c = (u % nct) * 16 + l16;
 #pragma unroll
-      for (int kc = 0; kc < (FIT_RMAX + 3) / 4; ++kc) {
+      for (int kc = 0; kc < NKC; ++kc) {
         const int i = 4 * kc + lk;
-        gv[h][kc] = zerov<T>();
-        if (u < nu2 && kc < nkc && i < R && c < nx) gv[h][kc] = G1[(size_t)(half == 0 ? o * R + i : i * R + o) * nx + c];
+        const bool ok = u < nu2 && i < R && c < nx;
+        const T gl = G1[ok ? (size_t)(half == 0 ? o * R + i : i * R + o) * nx + c : 0];
+        gv[h][kc] = ok ? gl : zerov<T>();
       }
     }
 #pragma unroll
@@ -489,8 +491,8 @@ NTU_DEV void form_gs_mfma(const T* __restrict__ Gm, const T* __restrict__ gyv, i
       const int o = u / nct, c = (u % nct) * 16 + l16;
       f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int kc = 0; kc < (FIT_RMAX + 3) / 4; ++kc) {
-        if (kc < nkc) {
+      for (int kc = 0; kc < NKC; ++kc) {
+        {
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[kc], rev(gv[h][kc]), acc, 0, 0, 0);
           if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[kc], imv(gv[h][kc]), acc, 0, 0, 0);
         }
@@ -516,6 +518,18 @@ NTU_DEV void form_gs_mfma(const T* __restrict__ Gm, const T* __restrict__ gyv, i
     J[e] = acc;
   }
   __syncthreads();
+}
+
+template <class T>
+NTU_DEV void form_gs_mfma(const T* __restrict__ Gm, const T* __restrict__ gyv, int R, int Dn, int half, const T* Q,
+                          T* __restrict__ G1, T* __restrict__ gs, T* J) {
+  switch ((R + 3) / 4) {
+    case 1: form_gs_mfma_k<T, 1>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
+    case 2: form_gs_mfma_k<T, 2>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
+    case 3: form_gs_mfma_k<T, 3>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
+    case 4: form_gs_mfma_k<T, 4>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
+    default: form_gs_mfma_k<T, 5>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
+  }
 }
 
 // Dependent directions (zero columns of Q) of g_s: unit rows and columns,

@@ -205,16 +205,19 @@ __global__ void __launch_bounds__(256) k_mfma_nt(const TA* __restrict__ A, const
 
 // ---------------------------------------------------------------------------
 // Tiled variant for operands whose rows are contiguous in K (all products of
-// the environment contraction): 128 x 128 real-embedded output tiles, four
-// waves of 64 x 64 (4 x 4 MFMA tiles each), K in steps of 32 with the next
+// the environment contraction): 128 x 128 real-embedded output tiles, eight
+// waves of 64 x 32 (4 x 2 MFMA tiles each), K in steps of 32 with the next
 // step's global loads in registers while the current step runs on the
 // matrix cores, double-buffered shared memory, one barrier per step.
 // Blocks are dealt to the 8 XCDs round-robin by id; the tile order puts the
 // tiles (and K chunks) of one item on one XCD, consecutively, so they share
-// that XCD's L2.  Output offsets are tabulated once per block.
+// that XCD's L2.  Output offsets are tabulated once per block.  Eight waves
+// (two per SIMD) so that one wave's matrix-core work overlaps another's
+// operand staging.
 // VEC = 2: pairs of values per load (K and all row strides even).
 // ---------------------------------------------------------------------------
 constexpr int TL_M = 128, TL_N = 128, TL_K = 32, TL_LD = TL_K + 8;
+constexpr int TL_THREADS = 512, TL_WY = 2;  // 8 waves; each 64 x (16 TL_WY)
 
 struct alignas(8) f2v { float v[2]; };
 struct alignas(16) d2v { double v[2]; };
@@ -236,13 +239,13 @@ struct TileArgs {
 };
 
 template <int PREC, bool CPLX, int VEC, class TA, class TB, class TC>
-__global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, const TB* __restrict__ B,
+__global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__ A, const TB* __restrict__ B,
                                                   TC* __restrict__ C, TileArgs ta) {
   using E = typename SplitTraits<PREC>::E;
   constexpr int NT = SplitTraits<PREC>::NT;
   constexpr int NACC = (PREC == NTU_PREC_BF16X6) ? 3 : 2;
   constexpr int CW = CPLX ? 2 : 1;
-  constexpr int NGA = TL_M * TL_K / 4 / 256;                 // groups of 4 reals of A per thread (4)
+  constexpr int NGA = TL_M * TL_K / 4 / TL_THREADS;          // groups of 4 reals of A per thread
   constexpr int NGB = CPLX ? NGA / 2 : NGA;                  // of B (complex rows give two real rows)
   // one buffer for both operands (double-buffered); the output tile reuses it
   constexpr int SA_EL = 2 * NT * TL_M * TL_LD, SB_EL = 2 * NT * TL_N * TL_LD;
@@ -252,7 +255,8 @@ __global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, con
   __shared__ long long rowoff[TL_M];
   __shared__ long long coloff[TL_N];
   const GemmNT& d = ta.d;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
+  // 8 waves: 2 along M (64 rows each) x 4 along N (32 columns each)
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 2, wn = wv & 3;
   const int per = (ta.nwork + 7) / 8;
   const int q = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (q >= ta.nwork) return;
@@ -265,11 +269,11 @@ __global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, con
   const TA* Ab = A + idx_off(d.Ab, item) * CW;
   const TB* Bb = B + idx_off(d.Bb, item) * CW;
 
-  for (int r = tid; r < TL_M; r += 256) {
+  for (int r = tid; r < TL_M; r += TL_THREADS) {
     const int i = i0 + r;
     rowoff[r] = i < Mr ? idx_off(d.Ci, i) * CW : -1;
   }
-  for (int c = tid; c < TL_N; c += 256) {
+  for (int c = tid; c < TL_N; c += TL_THREADS) {
     const int jr = j0 + c;
     coloff[c] = jr < Nr ? idx_off(d.Cj, CPLX ? jr >> 1 : jr) * CW + (CPLX ? (jr & 1) : 0) : -1;
   }
@@ -278,7 +282,7 @@ __global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, con
   int akq[NGA], arl[NGA];
 #pragma unroll
   for (int u = 0; u < NGA; ++u) {
-    const int g = tid + 256 * u, rl = g / (TL_K / 4);
+    const int g = tid + TL_THREADS * u, rl = g / (TL_K / 4);
     arl[u] = rl;
     akq[u] = (g % (TL_K / 4)) * 4;
     arow[u] = i0 + rl < Mr ? Ab + idx_off(d.Ai, i0 + rl) * CW : nullptr;
@@ -287,7 +291,7 @@ __global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, con
   int bkq[NGB], brl[NGB];
 #pragma unroll
   for (int u = 0; u < NGB; ++u) {
-    const int g = tid + 256 * u, rl = g / (TL_K / 4);   // rl: complex row (CPLX) or real row
+    const int g = tid + TL_THREADS * u, rl = g / (TL_K / 4);   // rl: complex row (CPLX) or real row
     brl[u] = rl;
     bkq[u] = (g % (TL_K / 4)) * 4;
     const int jrow = CPLX ? j0 / 2 + rl : j0 + rl;
@@ -370,13 +374,13 @@ __global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, con
     }
   };
 
-  f32x4 acc[NACC][4][4];
+  f32x4 acc[NACC][4][TL_WY];
 #pragma unroll
   for (int c = 0; c < NACC; ++c)
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[c][x][y] = f32x4{0, 0, 0, 0};
+      for (int y = 0; y < TL_WY; ++y) acc[c][x][y] = f32x4{0, 0, 0, 0};
 
   const int nsteps = (kend - kbeg + TL_K - 1) / TL_K;
   gload(kbeg);
@@ -390,8 +394,8 @@ __global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, con
     for (int x = 0; x < 4; ++x) {
       const int ra_ = wm * 64 + x * 16 + fr;
 #pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        const int rb_ = wn * 64 + y * 16 + fr;
+      for (int y = 0; y < TL_WY; ++y) {
+        const int rb_ = wn * (16 * TL_WY) + y * 16 + fr;
         const E* a0 = &sA[buf][0][ra_][fk];
         const E* a1 = &sA[buf][1][ra_][fk];
         const E* b0 = &sB[buf][0][rb_][fk];
@@ -425,11 +429,11 @@ __global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, con
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
+        for (int y = 0; y < TL_WY; ++y)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int il = wm * 64 + x * 16 + 4 * (lane >> 4) + v;
-            const int jl = wn * 64 + y * 16 + (lane & 15);
+            const int jl = wn * (16 * TL_WY) + y * 16 + (lane & 15);
             double val;
             if constexpr (PREC == NTU_PREC_BF16X6) val = (double)acc[0][x][y][v] + ((double)acc[1][x][y][v] + (double)acc[2][x][y][v]);
             else val = (double)acc[0][x][y][v] + (double)acc[1][x][y][v];
@@ -437,7 +441,7 @@ __global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, con
           }
       __syncthreads();
       const bool rowmajor = coloff[1] - coloff[0] == 1;
-      for (int e = tid; e < TL_M * TL_N; e += 256) {
+      for (int e = tid; e < TL_M * TL_N; e += TL_THREADS) {
         int il, jl;
         if (rowmajor) {
           il = e / TL_N;
@@ -459,11 +463,11 @@ __global__ void __launch_bounds__(256) k_mfma_tile(const TA* __restrict__ A, con
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+    for (int y = 0; y < TL_WY; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int il = wm * 64 + x * 16 + 4 * (lane >> 4) + v;
-        const int jl = wn * 64 + y * 16 + (lane & 15);
+        const int jl = wn * (16 * TL_WY) + y * 16 + (lane & 15);
         double val;
         if constexpr (PREC == NTU_PREC_BF16X6) val = (double)acc[0][x][y][v] + ((double)acc[1][x][y][v] + (double)acc[2][x][y][v]);
         else val = (double)acc[0][x][y][v] + (double)acc[1][x][y][v];
@@ -544,7 +548,7 @@ static hipError_t run_tile(const void* A, const void* B, void* C, const GemmNT& 
   const bool vec = (Kr % 2 == 0) && idx_even(d.Ab, CW) && idx_even(d.Ai, CW) && idx_even(d.Bb, CW) &&
                    idx_even(d.Bj, CW) && ((uintptr_t)A % (2 * sizeof(TA)) == 0) && ((uintptr_t)B % (2 * sizeof(TB)) == 0);
   const int per = (a.nwork + 7) / 8;
-  dim3 g(8 * per), b(256);
+  dim3 g(8 * per), b(TL_THREADS);
   ph(kind, 0);
   if (vec)
     hipLaunchKernelGGL((k_mfma_tile<PREC, CPLX, 2, TA, TB, TC>), g, b, 0, st, (const TA*)A, (const TB*)B, (TC*)C, a);
