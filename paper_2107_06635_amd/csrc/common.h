@@ -88,6 +88,20 @@ NTU_DEV double wave_sum(double v) {
   v += __shfl_xor(v, 32, 64);
   return v;
 }
+// Value of lane `src` (uniform across the wave, through a scalar register).
+NTU_DEV double lane_value(double v, int src) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), src);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// Sum over lanes 0..31 only (rows of a small matrix held one per lane); the
+// result is the same scalar on every lane.  Lanes 32..63 do not contribute.
+NTU_DEV double lanes32_sum(double v) {
+  const double r = row_sum16(v);
+  return lane_value(r, 0) + lane_value(r, 16);
+}
+NTU_DEV cd lanes32_sum(cd v) { return cd{lanes32_sum(v.x), lanes32_sum(v.y)}; }
 NTU_DEV double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));

@@ -123,19 +123,52 @@ NTU_DEV void fit_orthonormalise(const T* M, T* Q, int R, int Dn, double kappa) {
   double scale = 0;
   for (int j = 0; j < Dn; ++j) {
     double v = lane < R ? abs2(M[lane * FIT_RMAX + j]) : 0.0;
-    scale = fmax(scale, sqrt(wave_sum(v)));
+    scale = fmax(scale, sqrt(lanes32_sum(v)));
   }
   for (int j = 0; j < Dn; ++j) {
     T v = lane < R ? M[lane * FIT_RMAX + j] : zerov<T>();
     for (int pass = 0; pass < 2; ++pass)
       for (int i = 0; i < j; ++i) {
         T qi = lane < R ? Q[lane * FIT_RMAX + i] : zerov<T>();
-        T h = wave_sum(cmul(qi, v));
+        T h = lanes32_sum(cmul(qi, v));
         v -= qi * h;
       }
-    double nn = sqrt(wave_sum(abs2(v)));
+    double nn = sqrt(lanes32_sum(abs2(v)));
     double inv = (scale > 0 && nn > kappa * scale) ? 1.0 / nn : 0.0;
     if (lane < R) Q[lane * FIT_RMAX + j] = v * inv;
+  }
+}
+
+// Thin QR of the R x Dn matrix M (row-major, stride FIT_RMAX) by Gram-Schmidt
+// with the projection applied twice: Q (R x Dn) and the upper triangular Rf
+// (Dn x Dn, row-major, stride FIT_RMAX), M = Q Rf up to dropped residuals of
+// dependent columns (norm <= kappa * largest column norm), whose Q column and
+// diagonal entry are then exactly zero.  Wave `wv` of the block.
+template <class T>
+NTU_DEV void fit_qr_small(const T* M, T* Q, T* Rf, int R, int Dn, double kappa, int wv) {
+  if ((int)(threadIdx.x >> 6) != wv) return;
+  const int lane = threadIdx.x & 63;
+  double scale = 0;
+  for (int j = 0; j < Dn; ++j) {
+    double v = lane < R ? abs2(M[lane * FIT_RMAX + j]) : 0.0;
+    scale = fmax(scale, sqrt(lanes32_sum(v)));
+  }
+  for (int e = lane; e < Dn * FIT_RMAX; e += 64) Rf[e] = zerov<T>();
+  for (int j = 0; j < Dn; ++j) {
+    T v = lane < R ? M[lane * FIT_RMAX + j] : zerov<T>();
+    T racc = zerov<T>();  // lane i < j accumulates Rf[i][j]
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i < j; ++i) {
+        T qi = lane < R ? Q[lane * FIT_RMAX + i] : zerov<T>();
+        T h = lanes32_sum(cmul(qi, v));
+        v -= qi * h;
+        if (lane == i) racc += h;
+      }
+    double nn = sqrt(lanes32_sum(abs2(v)));
+    const bool keep = scale > 0 && nn > kappa * scale;
+    if (lane < R) Q[lane * FIT_RMAX + j] = v * (keep ? 1.0 / nn : 0.0);
+    if (lane < j) Rf[lane * FIT_RMAX + j] = racc;
+    if (lane == j) Rf[j * FIT_RMAX + j] = realv<T>(keep ? nn : 0.0);
   }
 }
 
@@ -556,27 +589,19 @@ NTU_DEV bool chol_certify(T* Wc, int n, T* pan, int* flag) {
 }
 
 // Conjugate gradients for g_s m = J (g_s Hermitian positive definite, nx x nx
-// in global memory, dependent directions already deflated).  The product
+// in global memory, dependent directions already deflated), from m = 0 or,
+// with warm, from the m given (the stopping rule stays relative to |J|).  The product
 // q = g_s p reads g_s column-wise through its Hermitian symmetry, r fastest,
 // with the partial sums meeting in mv (blockDim.x elements).  p, q, r: nx
 // elements of shared memory.  Iterates to a relative residual of rtol (at
 // most max_it iterations); returns false if it does not get there.
 template <class T>
 NTU_DEV bool cg_solve(const T* __restrict__ gs, int nx, const T* J, T* m, T* p, T* q, T* r, T* mv, double* red,
-                      double rtol, int max_it, int* iters_out) {
+                      double rtol, int max_it, int* iters_out, bool warm) {
   const int tid = threadIdx.x, parts = (int)blockDim.x / nx, cs = (nx + parts - 1) / parts;
-  double bb = 0;
-  for (int e = tid; e < nx; e += blockDim.x) {
-    const T v = J[e];
-    r[e] = v; p[e] = v; m[e] = zerov<T>();
-    bb += abs2(v);
-  }
-  bb = block_sum(bb, red);  // contains barriers: r, p visible
-  double rr = bb;
-  const double stop = rtol * rtol * bb;
-  int it = 0;
-  bool conv = bb == 0.0;
-  for (; it < max_it && !conv; ++it) {
+  // dst = g_s src, read column-wise through the Hermitian symmetry; the parts
+  // meet in mv; ends with a barrier
+  auto matvec = [&](const T* src, T* dst) {
     if (tid < parts * nx) {
       const int i = tid % nx, part = tid / nx;
       const int j1 = min(nx, (part + 1) * cs);
@@ -587,18 +612,41 @@ NTU_DEV bool cg_solve(const T* __restrict__ gs, int nx, const T* J, T* m, T* p, 
         for (int l = 0; l < FORM_LB; ++l) v[l] = j0 + l < j1 ? gs[(size_t)(j0 + l) * nx + i] : zerov<T>();
 #pragma unroll
         for (int l = 0; l < FORM_LB; ++l)
-          if (j0 + l < j1) acc += cmul(v[l], p[j0 + l]);
+          if (j0 + l < j1) acc += cmul(v[l], src[j0 + l]);
       }
       mv[tid] = acc;
     }
     __syncthreads();
-    double pq = 0;
     for (int e = tid; e < nx; e += blockDim.x) {
       T acc = zerov<T>();
       for (int part = 0; part < parts; ++part) acc += mv[part * nx + e];
-      q[e] = acc;
-      pq += rev(cmul(p[e], acc));
+      dst[e] = acc;
     }
+    __syncthreads();
+  };
+  double bb = 0;
+  for (int e = tid; e < nx; e += blockDim.x) {
+    if (!warm) m[e] = zerov<T>();
+    bb += abs2(J[e]);
+  }
+  bb = block_sum(bb, red);  // contains barriers: m visible
+  // r = J - g_s m (m = 0 unless warm), p = r
+  if (warm) matvec(m, q);
+  double rr = 0;
+  for (int e = tid; e < nx; e += blockDim.x) {
+    const T v = warm ? J[e] - q[e] : J[e];
+    r[e] = v;
+    p[e] = v;
+    rr += abs2(v);
+  }
+  rr = block_sum(rr, red);
+  const double stop = rtol * rtol * bb;
+  int it = 0;
+  bool conv = rr <= stop;
+  for (; it < max_it && !conv; ++it) {
+    matvec(p, q);
+    double pq = 0;
+    for (int e = tid; e < nx; e += blockDim.x) pq += rev(cmul(p[e], q[e]));
     pq = block_sum(pq, red);
     if (!(pq > 0.0)) break;
     const double alpha = rr / pq;
@@ -808,7 +856,8 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
       };
       int used_eig = 0;
       double tau = fp.tol[fp.n_tol - 1];
-      bool fast_done = false;
+      bool fast_done = false, have_est = false;
+      double eps_est = 0.0;
       if (certified) {
         if (Dn <= (is_cplx<T>::value ? 8 : 16)) form_gs_mfma<T>(G, gy, R, Dn, half, S.Qf, G1, gs, S.J);
         else form_gs<T>(G, gy, R, Dn, half, S.Qf, G1, gs, S.J);
@@ -822,9 +871,35 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
         deflate_gs<T>(gs, S.J, R, Dn, half, zcol_sh);
         int cgi = 0;
         if (nx <= CG_NX) {
-          fast_done = cg_solve<T>(gs, nx, S.J, S.m, cgp, cgq, cgr, S.sa, S.red, 1e-14, 64, &cgi);
+          // warm start: the current pair in this half-step's parameters.  The
+          // fixed factor lies in the span of Q, F = Q W with W = Q^H F, so
+          // X half: MX F^T = (MX W^T) Q^T;  Y half: F MY^T = Q (W MY^T).
+          const T* Fx = half == 0 ? S.MY : S.MX;
+          const T* Fr = half == 0 ? S.MX : S.MY;
+          for (int e = tid; e < Dn * Dn; e += blockDim.x) {
+            const int j = e / Dn, k = e % Dn;
+            T w = zerov<T>();
+            for (int b = 0; b < R; ++b) w += cmul(S.Qf[b * FIT_RMAX + j], Fx[b * FIT_RMAX + k]);
+            S.sv[j * FIT_RMAX + k] = w;
+          }
+          __syncthreads();
+          for (int e = tid; e < nx; e += blockDim.x) {
+            const int a = half == 0 ? e / Dn : e % R, j = half == 0 ? e % Dn : e / R;
+            T v = zerov<T>();
+            for (int k = 0; k < Dn; ++k) v += Fr[a * FIT_RMAX + k] * S.sv[j * FIT_RMAX + k];
+            S.m[e] = v;
+          }
+          fast_done = cg_solve<T>(gs, nx, S.J, S.m, cgp, cgq, cgr, S.sa, S.red, 1e-14, 64, &cgi, true);
           cg_iters_total += cgi;
           cg_solves += 1;
+          if (fast_done) {
+            // eps = m^H g_s m - 2 Re(m^H J) + N = N - Re(m^H (J + r)) with the
+            // residual r = J - g_s m of the solve
+            double pj = 0.0;
+            for (int e = tid; e < nx; e += blockDim.x) pj += rev(cmul(S.m[e], S.J[e] + cgr[e]));
+            eps_est = N - block_sum(pj, S.red);
+            have_est = true;
+          }
         }
         if (!fast_done) fast_done = fast_solve<T>(gs, R, Dn, half, S.Qf, S, pan, dblk, sbz, &chol_flag);
         tick(2);
@@ -875,7 +950,10 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
       }  // !fast_done
       if (!fast_done) tick(2);
       set_free(S.m);
-      eps = fit_error<T>(G, R, Dn, S, dv, gd);
+      // the residual form loses about log10(N / eps) digits: above 1e-8 N it is
+      // kept, below that the error is evaluated directly
+      if (have_est && eps_est > 1e-8 * N) eps = eps_est;
+      else eps = fit_error<T>(G, R, Dn, S, dv, gd);
       tick(3);
       n_eig += used_eig;
       if (st && tid == 0) {
@@ -889,28 +967,44 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
     if (stop) break;
   }
   __syncthreads();
-  // balance: SVD of MX MY^T, normalise by the largest singular value
-  for (int e = tid; e < R * R; e += blockDim.x) {
-    int a = e % R, b = e / R;
-    T v = zerov<T>();
-    for (int j = 0; j < Dn; ++j) v += S.MX[a * FIT_RMAX + j] * S.MY[b * FIT_RMAX + j];
-    S.sa[a + b * FIT_RMAX] = v;
+  // balance: SVD of MX MY^T, normalised by the largest singular value.  With
+  // MX = Qx Rx and MY = Qy Ry, MX MY^T = Qx (Rx Ry^T) Qy^T, so for
+  // Rx Ry^T = Uc S Vc^H the singular vectors are U = Qx Uc, V = conj(Qy) Vc:
+  // a Dn x Dn SVD instead of an R x R one.
+  // Buffers: Qx -> Qf, Qy -> J, Rx -> sa, Ry -> sv, C = Rx Ry^T (column-major) -> m.
+  if (Dn > 0) {
+    fit_qr_small<T>(S.MX, S.Qf, S.sa, R, Dn, kappa, 0);
+    fit_qr_small<T>(S.MY, S.J, S.sv, R, Dn, kappa, 1);
+    __syncthreads();
+    for (int e = tid; e < Dn * Dn; e += blockDim.x) {
+      const int i = e % Dn, k = e / Dn;
+      T v = zerov<T>();
+      for (int l = (i > k ? i : k); l < Dn; ++l) v += S.sa[i * FIT_RMAX + l] * S.sv[k * FIT_RMAX + l];
+      S.m[i + k * FIT_RMAX] = v;
+    }
+    __syncthreads();
+    svd_block_small<T>(S.m, Dn, Dn, FIT_RMAX, S.sv, FIT_RMAX, S.s, &flag);
+  } else {
+    if (tid == 0) S.s[0] = 0.0;
+    __syncthreads();
   }
-  __syncthreads();
-  svd_block_small<T>(S.sa, R, R, FIT_RMAX, S.sv, FIT_RMAX, S.s, &flag);
   const double c0 = S.s[0];
   int Dk = 0;
   if (c0 > 0)
-    for (int j = 0; j < R && Dk < D; ++j)
+    for (int j = 0; j < Dn && Dk < D; ++j)
       if (S.s[j] > kappa * c0) ++Dk;
-  if (Dk > Dn) Dk = Dn;
   for (int e = tid; e < R * D; e += blockDim.x) {
     int a = e / D, j = e % D;
     T mx = zerov<T>(), my = zerov<T>();
     if (j < Dk) {
       double sn = S.s[j] / c0, sq = sqrt(sn);
-      mx = S.sa[a + j * FIT_RMAX] * (sq / S.s[j]);
-      my = conjv(S.sv[a + j * FIT_RMAX]) * sq;
+      T us = zerov<T>(), vv = zerov<T>();
+      for (int i = 0; i < Dn; ++i) {
+        us += S.Qf[a * FIT_RMAX + i] * S.m[i + j * FIT_RMAX];          // (U S)[a][j]
+        vv += conjv(S.J[a * FIT_RMAX + i]) * S.sv[i + j * FIT_RMAX];   // V[a][j]
+      }
+      mx = us * (sq / S.s[j]);
+      my = conjv(vv) * sq;
     }
     MXo[(size_t)it * R * D + e] = mx;
     MYo[(size_t)it * R * D + e] = my;

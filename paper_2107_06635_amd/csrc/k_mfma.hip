@@ -565,10 +565,12 @@ static hipError_t run_tile(const void* A, const void* B, void* C, const GemmNT& 
   return hipGetLastError();
 }
 
-// K chunks of the tiled assembly: enough blocks for ~one per CU, chunks of >= 8 steps
+// K chunks of the tiled assembly: about three blocks per CU (one runs at a
+// time per CU, so the last round is at most a third of the work), chunks of
+// at least 8 steps
 static int tile_ksplit(int batch, int M, int Nr, int Kr) {
   const long long tiles = (long long)((M + TL_M - 1) / TL_M) * ((Nr + TL_N - 1) / TL_N) * batch;
-  int ks = (int)std::max<long long>(1, 256 / std::max<long long>(1, tiles));
+  int ks = (int)std::max<long long>(1, (768 + tiles / 2) / std::max<long long>(1, tiles));
   const int kmax = std::max(1, Kr / (8 * TL_K));
   return std::min(ks, std::min(kmax, 32));
 }

@@ -116,7 +116,8 @@ NTU_DEV void svd_block_small(T* A, int m, int n, int lda, T* V, int ldv, double*
           T x = A[lane + p * lda], y = A[lane + q * lda];
           a = abs2(x); b = abs2(y); g = cmul(x, y);
         }
-        a = wave_sum(a); b = wave_sum(b); g = wave_sum(g);
+        // rows live in lanes 0..31 (m <= 32)
+        a = lanes32_sum(a); b = lanes32_sum(b); g = lanes32_sum(g);
         double c, sn;
         T e;
         if (!jacobi_params(a, b, g, c, sn, e)) continue;
