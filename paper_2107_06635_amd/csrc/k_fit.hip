@@ -407,10 +407,11 @@ NTU_DEV void form_gs(const T* __restrict__ Gm, const T* __restrict__ gyv, int R,
 // R <= FIT_RMAX, Dn <= 8 (complex) or 16 (real).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <class T, int NKC>
-NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv, int R, int Dn, int half, const T* Q,
-                            T* __restrict__ G1, T* __restrict__ gs, T* J) {
+template <class T, int NKC, int RC>
+NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv, int Rarg, int Dn, int half,
+                            const T* Q, T* __restrict__ G1, T* __restrict__ gs, T* J) {
   constexpr bool CPLX = is_cplx<T>::value;
+  const int R = RC > 0 ? RC : Rarg;  // compile-time R where instantiated
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int n = R * R, nx = R * Dn;
   const int l16 = lane & 15, lk = lane >> 4;
@@ -437,45 +438,32 @@ NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv,
     b1[kc] = v1;
     b2[kc] = v2;
   }
-  // two output tiles per wave at a time: their loads are in flight together
   const int nrt = (n + 15) / 16, nu1 = R * nrt;
-  for (int u0 = w; u0 < nu1; u0 += 2 * nw) {
-    T gv[2][NKC];
+  for (int u = w; u < nu1; u += nw) {
+    const int x = u / nrt, r0 = (u % nrt) * 16, r = r0 + l16;
+    T gv[NKC];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int u = u0 + h * nw;
-      const int x = u / nrt, r = (u % nrt) * 16 + l16;
-#pragma unroll
-      for (int kc = 0; kc < NKC; ++kc) {
-        const int y = 4 * kc + lk;
-        // branch-free: invalid entries load element 0 and are replaced by zero
-        const bool ok = u < nu1 && y < R && r < n;
-        const T gl = Gm[ok ? (size_t)(half == 0 ? x * R + y : y * R + x) * n + r : 0];
-        gv[h][kc] = ok ? conjv(gl) : zerov<T>();
-      }
+    for (int kc = 0; kc < NKC; ++kc) {
+      const int y = 4 * kc + lk;
+      // branch-free: invalid entries load element 0 and are replaced by zero
+      const bool ok = y < R && r < n;
+      const T gl = Gm[ok ? (size_t)(half == 0 ? x * R + y : y * R + x) * n + r : 0];
+      gv[kc] = ok ? conjv(gl) : zerov<T>();
     }
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int u = u0 + h * nw;
-      if (u >= nu1) break;
-      const int x = u / nrt, r0 = (u % nrt) * 16;
-      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < NKC; ++kc) {
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(rev(gv[kc]), b1[kc], acc, 0, 0, 0);
+      if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(imv(gv[kc]), b2[kc], acc, 0, 0, 0);
+    }
+    // lane holds rows r0 + lk + 4 v, column l16
+    const int j = CPLX ? (l16 & 7) : l16, part = CPLX ? (l16 >> 3) : 0;
+    if (j < Dn) {
+      const int c = half == 0 ? x * Dn + j : j * R + x;
 #pragma unroll
-      for (int kc = 0; kc < NKC; ++kc) {
-        {
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(rev(gv[h][kc]), b1[kc], acc, 0, 0, 0);
-          if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(imv(gv[h][kc]), b2[kc], acc, 0, 0, 0);
-        }
-      }
-      // lane holds rows r0 + lk + 4 v, column l16
-      const int j = CPLX ? (l16 & 7) : l16, part = CPLX ? (l16 >> 3) : 0;
-      if (j < Dn) {
-        const int c = half == 0 ? x * Dn + j : j * R + x;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int rr = r0 + lk + 4 * v;
-          if (rr < n) G1d[((size_t)rr * nx + c) * (CPLX ? 2 : 1) + part] = acc[v];
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int rr = r0 + lk + 4 * v;
+        if (rr < n) G1d[((size_t)rr * nx + c) * (CPLX ? 2 : 1) + part] = acc[v];
       }
     }
   }
@@ -503,42 +491,30 @@ NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv,
     a2[kc] = v2;
   }
   const int nct = (nx + 15) / 16, nu2 = R * nct;
-  for (int u0 = w; u0 < nu2; u0 += 2 * nw) {
-    T gv[2][NKC];
+  for (int u = w; u < nu2; u += nw) {
+    const int o = u / nct, c = (u % nct) * 16 + l16;
+    T gv[NKC];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int u = u0 + h * nw;
-      const int o = u / nct, c = (u % nct) * 16 + l16;
-#pragma unroll
-      for (int kc = 0; kc < NKC; ++kc) {
-        const int i = 4 * kc + lk;
-        const bool ok = u < nu2 && i < R && c < nx;
-        const T gl = G1[ok ? (size_t)(half == 0 ? o * R + i : i * R + o) * nx + c : 0];
-        gv[h][kc] = ok ? gl : zerov<T>();
-      }
+    for (int kc = 0; kc < NKC; ++kc) {
+      const int i = 4 * kc + lk;
+      const bool ok = i < R && c < nx;
+      const T gl = G1[ok ? (size_t)(half == 0 ? o * R + i : i * R + o) * nx + c : 0];
+      gv[kc] = ok ? gl : zerov<T>();
     }
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int u = u0 + h * nw;
-      if (u >= nu2) break;
-      const int o = u / nct, c = (u % nct) * 16 + l16;
-      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < NKC; ++kc) {
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[kc], rev(gv[kc]), acc, 0, 0, 0);
+      if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[kc], imv(gv[kc]), acc, 0, 0, 0);
+    }
+    if (c < nx) {
 #pragma unroll
-      for (int kc = 0; kc < NKC; ++kc) {
-        {
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[kc], rev(gv[h][kc]), acc, 0, 0, 0);
-          if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[kc], imv(gv[h][kc]), acc, 0, 0, 0);
-        }
-      }
-      if (c < nx) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i16 = lk + 4 * v;
-          const int jp = CPLX ? (i16 & 7) : i16, part = CPLX ? (i16 >> 3) : 0;
-          if (jp < Dn) {
-            const int row = half == 0 ? o * Dn + jp : jp * R + o;
-            gsd[((size_t)row * nx + c) * (CPLX ? 2 : 1) + part] = acc[v];
-          }
+      for (int v = 0; v < 4; ++v) {
+        const int i16 = lk + 4 * v;
+        const int jp = CPLX ? (i16 & 7) : i16, part = CPLX ? (i16 >> 3) : 0;
+        if (jp < Dn) {
+          const int row = half == 0 ? o * Dn + jp : jp * R + o;
+          gsd[((size_t)row * nx + c) * (CPLX ? 2 : 1) + part] = acc[v];
         }
       }
     }
@@ -556,12 +532,22 @@ NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv,
 template <class T>
 NTU_DEV void form_gs_mfma(const T* __restrict__ Gm, const T* __restrict__ gyv, int R, int Dn, int half, const T* Q,
                           T* __restrict__ G1, T* __restrict__ gs, T* J) {
+  switch (R) {  // the enlarged bond dimensions of a rank-2 gate on the certified path
+    case 4: form_gs_mfma_k<T, 1, 4>(Gm, gyv, R, Dn, half, Q, G1, gs, J); return;
+    case 6: form_gs_mfma_k<T, 2, 6>(Gm, gyv, R, Dn, half, Q, G1, gs, J); return;
+    case 8: form_gs_mfma_k<T, 2, 8>(Gm, gyv, R, Dn, half, Q, G1, gs, J); return;
+    case 10: form_gs_mfma_k<T, 3, 10>(Gm, gyv, R, Dn, half, Q, G1, gs, J); return;
+    case 12: form_gs_mfma_k<T, 3, 12>(Gm, gyv, R, Dn, half, Q, G1, gs, J); return;
+    case 14: form_gs_mfma_k<T, 4, 14>(Gm, gyv, R, Dn, half, Q, G1, gs, J); return;
+    case 16: form_gs_mfma_k<T, 4, 16>(Gm, gyv, R, Dn, half, Q, G1, gs, J); return;
+    default: break;
+  }
   switch ((R + 3) / 4) {
-    case 1: form_gs_mfma_k<T, 1>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
-    case 2: form_gs_mfma_k<T, 2>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
-    case 3: form_gs_mfma_k<T, 3>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
-    case 4: form_gs_mfma_k<T, 4>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
-    default: form_gs_mfma_k<T, 5>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
+    case 1: form_gs_mfma_k<T, 1, 0>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
+    case 2: form_gs_mfma_k<T, 2, 0>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
+    case 3: form_gs_mfma_k<T, 3, 0>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
+    case 4: form_gs_mfma_k<T, 4, 0>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
+    default: form_gs_mfma_k<T, 5, 0>(Gm, gyv, R, Dn, half, Q, G1, gs, J); break;
   }
 }
 
