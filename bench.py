@@ -209,7 +209,7 @@ def main():
     for bi, bk in enumerate(job.buckets):
         st = torch.stack([s[bi] for s in stm]).cpu().numpy()
         ph = st[..., 8 + 10:8 + 15].reshape(-1, 5).mean(axis=0)
-        phases[str(bk["D"])] = {"certified": float(st[..., 8 + 9].mean()), "cg_iters": float(st[..., 8 + 15].mean()),
+        phases[str(bk["D"])] = {"certificate_kind_mean": float(st[..., 8 + 9].mean()), "cg_iters": float(st[..., 8 + 15].mean()),
                                 "kcycles": dict(zip(["setup", "form", "solve", "error", "balance"],
                                                     [round(x / 1e3, 1) for x in ph]))}
     result["fit_phases"] = phases

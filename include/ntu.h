@@ -151,8 +151,9 @@ ntu_status ntu_env_contract(ntu_ctx* ctx, int batch, int D, const void* QX, cons
  * Sec. II).  NTU_FIX_HERM replaces g by (g + g^H)/2.  NTU_FIX_HERM_CLIP also
  * sets negative eigenvalues to zero: g <- V max(Lambda, 0) V^H.  Rows and
  * columns that are exactly zero are left out of the eigenproblem; when the
- * remaining block is certified positive definite (Cholesky succeeds) the
- * clip is the identity and is skipped.
+ * remaining block is certified positive definite (Gershgorin discs right of
+ * zero, else a Cholesky factor exists) the clip is the identity and is
+ * skipped.
  * g: batch x n x n in place, n = (D r_g)^2.
  * stats (device, may be NULL): batch x 8 doubles
  *   [0] ||g - g^H||_F / ||g||_F  (input)      [1] ||g||_F (input)
@@ -202,7 +203,12 @@ void ntu_fit_opts_default(ntu_fit_opts* o);
  *   [0] N = vec(P)^H g vec(P)  [1] eps of the SVDU guess  [2] final eps
  *   [3] final eps / N          [4] Dn   [5] Dk (kept after balancing)
  *   [6] iterations done        [7] half-steps solved by eigendecomposition
- *   [8] non-finite flag        [9] 1 if g was certified well conditioned
+ *   [8] non-finite flag        [9] how g was certified well conditioned:
+ *       0 not certified, 1 Gershgorin discs, 2 Cholesky of g - s I
+ *       (s = 10 * largest ladder tolerance * ||g||_F; a certified half-step
+ *       is solved by conjugate gradients instead of the ladder),
+ *       3 certified by the metric repair of the same Trotter step (the
+ *       clip's shifted test, run with the same s; ntu_trotter_step only)
  *   [10..14] GPU clock cycles spent in: set-up, half-step matrices, solves,
  *            error evaluations, balancing
  *   [15] mean conjugate-gradient iterations per certified half-step

@@ -12,7 +12,7 @@ namespace {
 
 struct Persist {
   // per-item persistent buffers of the Trotter step (compute type elements)
-  long long QX, QY, RX, RY, g, MX, MY, rA, rB, GA, GB;
+  long long QX, QY, RX, RY, g, MX, MY, rA, rB, GA, GB, cert;
 };
 
 }  // namespace
@@ -97,12 +97,13 @@ Persist persist_layout(int p, int D, int rg, int d) {
   s.rB = o; o += p * D3 * D;
   s.GA = o; o += (long long)d * d * rg;
   s.GB = o; o += (long long)d * d * rg;
+  s.cert = o; o += 1;  // the metric repair's certificate for the fit (one double per item)
   (void)o;
   return s;
 }
 long long persist_elems(int p, int D, int rg, int d) {
   const long long R = (long long)D * rg, D3 = (long long)D * D * D;
-  return 2 * p * D3 * R + 2 * R * R + R * R * R * R + 2 * R * D + 2 * p * D3 * D + 2LL * d * d * rg;
+  return 2 * p * D3 * R + 2 * R * R + R * R * R * R + 2 * R * D + 2 * p * D3 * D + 2LL * d * d * rg + 1;
 }
 
 const int PROF_CAP = 1 << 15;
@@ -356,6 +357,7 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
   char* MY = buf(L.MY);
   char* rA = buf(L.rA);
   char* rB = buf(L.rB);
+  double* cert = (double*)buf(L.cert);
   (void)pe;
   const long long gfs = (long long)c->d * c->d * c->rg;  // elements of one factor
   const long long gf_item = 8 * gfs;                      // 4 bonds x (GA, GB)
@@ -394,10 +396,15 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     if (e == hipErrorNotSupported) return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
     if (e != hipSuccess) return hip_fail(c, e, "env_contract");
     double* sb = stats ? stats + (size_t)bi * sl : nullptr;
-    NTU_STEP(ntu::launch_metric_fix(cp, batch, R * R, G, opts->fix_mode, sb, (int)s_item, c->ws, c->stream, ph),
+    // with the clip, the repair also tests the fit's certificate (g minus
+    // 10 tau_max ||g||_F I positive definite, see the fit) and hands it over
+    const bool clip = opts->fix_mode == NTU_FIX_HERM_CLIP;
+    const double shift = 10.0 * fp.tol[fp.n_tol - 1];
+    NTU_STEP(ntu::launch_metric_fix(cp, batch, R * R, G, opts->fix_mode, sb, (int)s_item, c->ws, c->stream, ph,
+                                    clip ? shift : 0.0, clip ? cert : nullptr),
              "metric_fix");
     NTU_STEP(ntu::launch_bond_fit(cp, batch, D, R, G, RX, RY, fp, MX, MY, sb ? sb + 8 : nullptr, (int)s_item, c->ws,
-                                  c->stream, ph), "bond_fit");
+                                  c->stream, ph, clip ? cert : nullptr), "bond_fit");
     // new X -> (A or B), new Y -> the other, rotated back for vertical bonds
     void* outX = x_is_a ? A : B;
     void* outY = x_is_a ? B : A;

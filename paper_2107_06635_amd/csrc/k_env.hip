@@ -255,6 +255,100 @@ __global__ void k_qprep(int p, int D, int R, int side, const T* __restrict__ Q, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Half environments (Fig. 4(c)) with the short contraction K = p D:
+//   Left[(a b t), (a' b' t')]  = sum_s QXe[(a b t), s] conj(QXp[(a' b' t'), s]),
+//     stored Left[a][a'][b][b'][t][t'];
+//   Right[(B c T), (B' c' T')] = sum_s QYe[(B c T), s] conj(QYp[(B' c' T'), s]),
+//     stored Right[B][B'][T][T'][c][c'].
+// The product is bound by its output writes, so it runs on the vector units:
+// one block per (item, a, a') holds the bra rows of a' in shared memory
+// (padded rows), loops over the ket index b (X) or T (Y), and consecutive
+// threads write consecutive output elements.  TO: output scalar (float for
+// the split-precision paths, double for the FP64 path); complex outputs are
+// (re, im) pairs.
+// ---------------------------------------------------------------------------
+template <class T, class TO>
+__global__ void __launch_bounds__(256) k_half_env(int p, int D, int R, int side, const T* __restrict__ Qe,
+                                                  const T* __restrict__ Qp, long long qstride, TO* __restrict__ out,
+                                                  long long ostride) {
+  extern __shared__ double shmem[];
+  constexpr int CW = is_cplx<T>::value ? 2 : 1;
+  const int pD = p * D, ld = pD + 1, D2 = D * D, D3 = D2 * D;
+  const long long D4 = (long long)D2 * D2;
+  const int RR = R * R;
+  const int it = blockIdx.x / RR, a = (blockIdx.x / R) % R, ap = blockIdx.x % R;
+  const int tid = threadIdx.x;
+  T* P = (T*)shmem;        // D2 bra rows of ap, padded
+  T* L = P + D2 * ld;      // D ket rows of the current b (X) or T (Y)
+  const T* Qei = Qe + (size_t)it * qstride;
+  const T* Qpi = Qp + (size_t)it * qstride;
+  TO* O = out + (size_t)it * ostride * CW;
+  // bra rows: X: (b', t') at P[b' D + t'];  Y: (c', T') at P[T' D + c']
+  for (int e = tid; e < D2 * pD; e += blockDim.x) {
+    const int r = e / pD, sg = e % pD;
+    const int slot = side == 0 ? r : (r % D) * D + r / D;
+    P[slot * ld + sg] = Qpi[((size_t)ap * D2 + r) * pD + sg];
+  }
+  for (int kb = 0; kb < D; ++kb) {
+    __syncthreads();
+    // ket rows: X: (a, kb, t) for t < D;  Y: (a, c, kb) for c < D
+    for (int e = tid; e < D * pD; e += blockDim.x) {
+      const int u = e / pD, sg = e % pD;
+      const size_t row = side == 0 ? ((size_t)a * D + kb) * D + u : ((size_t)a * D + u) * D + kb;
+      L[u * ld + sg] = Qei[row * pD + sg];
+    }
+    __syncthreads();
+    const size_t obase = (size_t)a * R * D4 + (size_t)ap * D4 + (size_t)kb * D3;
+    for (int e = tid; e < D3; e += blockDim.x) {
+      // X: e = (b', t, t'), ket row t, bra slot b' D + t'
+      // Y: e = (T', c, c'), ket row c, bra slot T' D + c'
+      const int hi = e / D2, mid = (e / D) % D, lo = e % D;
+      const int ku = mid, ps = hi * D + lo;
+      T acc = zerov<T>();
+      for (int sg = 0; sg < pD; ++sg) acc += mulc(L[ku * ld + sg], P[ps * ld + sg]);
+      if constexpr (CW == 2) {
+        O[2 * (obase + e)] = (TO)rev(acc);
+        O[2 * (obase + e) + 1] = (TO)imv(acc);
+      } else {
+        O[obase + e] = (TO)rev(acc);
+      }
+    }
+  }
+}
+
+static size_t half_env_shmem(bool cplx, int p, int D) {
+  return (size_t)(D * D + D) * (p * D + 1) * (cplx ? 16 : 8);
+}
+
+// Left into H0 and Right into H2; out_float: split-precision intermediates
+static hipError_t half_env(bool cplx, bool out_float, int batch, int p, int D, int R, const void* QXe,
+                           const void* QXp, const void* QYe, const void* QYp, long long qs, void* H0, void* H2,
+                           long long hs, hipStream_t st) {
+  const size_t shm = half_env_shmem(cplx, p, D);
+  dim3 g(batch * R * R), b(256);
+  for (int side = 0; side < 2; ++side) {
+    const void* Qe = side == 0 ? QXe : QYe;
+    const void* Qp = side == 0 ? QXp : QYp;
+    void* O = side == 0 ? H0 : H2;
+    if (cplx && out_float)
+      hipLaunchKernelGGL((k_half_env<cd, float>), g, b, shm, st, p, D, R, side, (const cd*)Qe, (const cd*)Qp, qs,
+                         (float*)O, hs);
+    else if (cplx)
+      hipLaunchKernelGGL((k_half_env<cd, double>), g, b, shm, st, p, D, R, side, (const cd*)Qe, (const cd*)Qp, qs,
+                         (double*)O, hs);
+    else if (out_float)
+      hipLaunchKernelGGL((k_half_env<double, float>), g, b, shm, st, p, D, R, side, (const double*)Qe,
+                         (const double*)Qp, qs, (float*)O, hs);
+    else
+      hipLaunchKernelGGL((k_half_env<double, double>), g, b, shm, st, p, D, R, side, (const double*)Qe,
+                         (const double*)Qp, qs, (double*)O, hs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 EnvSizes env_sizes(int p, int D, int R) {
   EnvSizes s;
   long long D2 = (long long)D * D, D4 = D2 * D2;
@@ -400,10 +494,14 @@ hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D
     d.conjB = 1;
     d.Ci = idx3(D, D, RD4, D3, D); d.Cj = idx3(D, D, D4, D2, 1);
     ph(PK_LEFTRIGHT, 0);
-    NTU_TRY(gemm_nt(cplx, QXe, QXp, H0, d, st));
-    // Right[B][B'][T][T'][c][c'] from rows (B, c, T)
-    d.Ci = idx3(D, D, RD4, D, D3); d.Cj = idx3(D, D, D4, 1, D2);
-    NTU_TRY(gemm_nt(cplx, QYe, QYp, H2, d, st));
+    if (half_env_shmem(cplx, p, D) <= 64 * 1024) {
+      NTU_TRY(half_env(cplx, false, batch, p, D, R, QXe, QXp, QYe, QYp, s.qp, H0, H2, s.half, st));
+    } else {
+      NTU_TRY(gemm_nt(cplx, QXe, QXp, H0, d, st));
+      // Right[B][B'][T][T'][c][c'] from rows (B, c, T)
+      d.Ci = idx3(D, D, RD4, D, D3); d.Cj = idx3(D, D, D4, 1, D2);
+      NTU_TRY(gemm_nt(cplx, QYe, QYp, H2, d, st));
+    }
     ph(PK_LEFTRIGHT, 1);
     // 5. L1[a a'][T T'][b b'] = sum_{t t'} Left[(a a' b b')][(t t')] EtopT[(T T')][(t t')]
     GemmNT e{};
@@ -429,8 +527,15 @@ hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D
     NTU_TRY(gemm_nt(cplx, H0, H2, g, f, st));
     ph(PK_E6, 1);
   } else {
+    // Left / Right on the vector units (FP32 out), then the long products on the matrix cores
+    const bool lr_done = half_env_shmem(cplx, p, D) <= 64 * 1024;
+    if (lr_done) {
+      ph(PK_LEFTRIGHT, 0);
+      NTU_TRY(half_env(cplx, true, batch, p, D, R, QXe, QXp, QYe, QYp, s.qp, H0, H2, s.half, st));
+      ph(PK_LEFTRIGHT, 1);
+    }
     NTU_TRY(launch_env_heavy_mixed(cplx, precision, batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, s.qp,
-                                   s.half, H0, H1, H2, g, st, ph));
+                                   s.half, H0, H1, H2, g, st, ph, lr_done));
   }
 #undef NTU_TRY
   return hipSuccess;

@@ -692,7 +692,7 @@ template <class T>
 __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T* __restrict__ g,
                                                           const T* __restrict__ RX, const T* __restrict__ RY,
                                                           FitParams fp, T* MXo, T* MYo, double* stats,
-                                                          int stats_stride, T* ws) {
+                                                          int stats_stride, T* ws, const double* cert) {
   extern __shared__ double shmem[];
   __shared__ int flag;
   const int it = blockIdx.x, tid = threadIdx.x;
@@ -740,8 +740,16 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   // certification: Cholesky of g - s I (copy in the workspace)
   bool certified = false;
   const bool cert_fits = (long long)n * n <= (long long)n * R * D + 3LL * R * D * R * D;
-  if (R * D <= FAST_NX) certified = gershgorin_certify<T>(G, n, 10.0 * fp.tol[fp.n_tol - 1], S.red);
-  if (!certified && n <= FIT_CERT_NMAX && R * D <= FAST_NX && cert_fits) {
+  int cert_kind = 0;  // 1: Gershgorin discs, 2: shifted Cholesky, 3: by the metric repair
+  if (cert) {
+    // the metric repair already tested the same two certificates on this g
+    certified = R * D <= FAST_NX && cert[it] > 0.5;
+    if (certified) cert_kind = 3;
+  } else {
+    if (R * D <= FAST_NX) certified = gershgorin_certify<T>(G, n, 10.0 * fp.tol[fp.n_tol - 1], S.red);
+    if (certified) cert_kind = 1;
+  }
+  if (!cert && !certified && n <= FIT_CERT_NMAX && R * D <= FAST_NX && cert_fits) {
     T* Wc = W;  // n^2 elements fit in G1 .. X (cert_fits)
     double fro = 0;
     for (long long e = tid; e < (long long)n * n; e += blockDim.x) fro += abs2(G[e]);
@@ -754,6 +762,7 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
     }
     __syncthreads();
     certified = fro > 0 && chol_certify<T>(Wc, n, pan, &chol_flag);
+    if (certified) cert_kind = 2;
   }
   double* st = stats ? stats + (size_t)it * stats_stride : nullptr;
   const double kappa = fp.kappa;
@@ -997,7 +1006,7 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   }
   tick(4);
   if (st && tid == 0) {
-    st[9] = certified ? 1.0 : 0.0;
+    st[9] = (double)cert_kind;
     st[15] = cg_solves > 0 ? (double)cg_iters_total / cg_solves : 0.0;
     st[10] = (double)tph0; st[11] = (double)tph1; st[12] = (double)tph2;
     st[13] = (double)tph3; st[14] = (double)tph4;
@@ -1013,7 +1022,7 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
 
 hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, const void* RX, const void* RY,
                            const FitParams& fp, void* MX, void* MY, double* stats, int stats_stride, void* ws,
-                           hipStream_t st, const ProfHook& ph) {
+                           hipStream_t st, const ProfHook& ph, const double* cert) {
   if (batch <= 0) return hipSuccess;
   if (R > FIT_RMAX || D > FIT_RMAX || R * D > 256) return hipErrorInvalidValue;
   size_t el = cplx ? 16 : 8;
@@ -1033,11 +1042,11 @@ hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, co
   if (shm > 160 * 1024 - 16 * 1024) return hipErrorInvalidValue;
   if (cplx)
     hipLaunchKernelGGL(k_bond_fit<cd>, dim3(batch), dim3(FIT_THREADS), shm, st, D, R, (const cd*)g, (const cd*)RX,
-                       (const cd*)RY, fp, (cd*)MX, (cd*)MY, stats, stats_stride, (cd*)ws);
+                       (const cd*)RY, fp, (cd*)MX, (cd*)MY, stats, stats_stride, (cd*)ws, cert);
   else
     hipLaunchKernelGGL(k_bond_fit<double>, dim3(batch), dim3(FIT_THREADS), shm, st, D, R, (const double*)g,
                        (const double*)RX, (const double*)RY, fp, (double*)MX, (double*)MY, stats, stats_stride,
-                       (double*)ws);
+                       (double*)ws, cert);
   ph(PK_FIT, 1);
   return hipGetLastError();
 }

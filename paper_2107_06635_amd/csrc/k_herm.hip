@@ -54,8 +54,12 @@ __global__ void __launch_bounds__(HERM_THREADS) k_hermitise(int n, T* g, double*
 // Eigenvalue clip of the Hermitian g.  Rows that are exactly zero are left
 // out; if the rest admits a Cholesky factorisation it is positive definite
 // and nothing changes; otherwise g <- V max(Lambda, 0) V^H on that block.
+// With shift_rel > 0 the tests are first made on g - shift_rel ||g||_F I
+// (Gershgorin: lowest disc edge > shift_rel * highest); success there also
+// certifies g for the bond fit (cert[it] = 1, else 0; cert may be NULL).
 template <class T>
-__global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stats, int sstride, T* ws) {
+__global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stats, int sstride, T* ws,
+                                                       double shift_rel, double* cert) {
   __shared__ double red[1024];  // >= blockDim.x (Gershgorin partial sums)
   __shared__ int idx[1024];
   __shared__ int m_sh, cnt;
@@ -94,7 +98,25 @@ __global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stat
   __syncthreads();
   // positive definite (the clip is the identity) if the Gershgorin discs of
   // the full matrix stay right of zero, or else if a Cholesky factor exists
-  if (m == n && gershgorin_certify<T>(G, n, 0.0, red)) return;
+  if (m == n && gershgorin_certify<T>(G, n, shift_rel, red)) {
+    if (cert && tid == 0) cert[it] = 1.0;
+    return;
+  }
+  if (cert && tid == 0) cert[it] = 0.0;
+  if (shift_rel > 0.0 && m == n) {
+    const double sh = shift_rel * fro;
+    for (int i = tid; i < m; i += blockDim.x) A[(size_t)i * m + i] = A[(size_t)i * m + i] - realv<T>(sh);
+    __syncthreads();
+    if (block_cholesky<T>(A, m, m, red)) {
+      if (cert && tid == 0) cert[it] = 1.0;
+      return;
+    }
+    for (long long e = tid; e < (long long)m * m; e += blockDim.x) {
+      int i = (int)(e / m), j = (int)(e % m);
+      A[e] = G[(size_t)idx[i] * n + idx[j]];
+    }
+    __syncthreads();
+  }
   bool ok = m == 0 || block_cholesky<T>(A, m, m, red);
   if (ok) return;
   for (long long e = tid; e < (long long)m * m; e += blockDim.x) {
@@ -136,7 +158,7 @@ size_t fix_workspace_bytes(bool cplx, int batch, int n) {
 }
 
 hipError_t launch_metric_fix(bool cplx, int batch, int n, void* g, int mode, double* stats, int sstride,
-                             void* ws, hipStream_t st, const ProfHook& ph) {
+                             void* ws, hipStream_t st, const ProfHook& ph, double shift_rel, double* cert) {
   if (batch <= 0) return hipSuccess;
   if (n > 1024) return hipErrorInvalidValue;
   ph(PK_HERM, 0);
@@ -146,8 +168,12 @@ hipError_t launch_metric_fix(bool cplx, int batch, int n, void* g, int mode, dou
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || mode == 0) return e;
   ph(PK_CLIP, 0);
-  if (cplx) hipLaunchKernelGGL(k_clip<cd>, dim3(batch), dim3(CLIP_THREADS), 0, st, n, (cd*)g, stats, sstride, (cd*)ws);
-  else hipLaunchKernelGGL(k_clip<double>, dim3(batch), dim3(CLIP_THREADS), 0, st, n, (double*)g, stats, sstride, (double*)ws);
+  if (cplx)
+    hipLaunchKernelGGL(k_clip<cd>, dim3(batch), dim3(CLIP_THREADS), 0, st, n, (cd*)g, stats, sstride, (cd*)ws,
+                       shift_rel, cert);
+  else
+    hipLaunchKernelGGL(k_clip<double>, dim3(batch), dim3(CLIP_THREADS), 0, st, n, (double*)g, stats, sstride,
+                       (double*)ws, shift_rel, cert);
   ph(PK_CLIP, 1);
   return hipGetLastError();
 }

@@ -13,53 +13,11 @@
 // product has output columns (re, im) interleaved.
 #include "kernels.h"
 #include "mfma_gemm.h"
+#include "split_mfma.h"
 
 namespace ntu {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
 constexpr int MT_BM = 64, MT_BN = 64, MT_BK = 32, MT_PAD = 8, MT_LD = MT_BK + MT_PAD;
-
-template <int PREC> struct SplitTraits;
-template <> struct SplitTraits<NTU_PREC_BF16X3> { static constexpr int NT = 2; using E = __bf16; };
-template <> struct SplitTraits<NTU_PREC_BF16X6> { static constexpr int NT = 3; using E = __bf16; };
-template <> struct SplitTraits<NTU_PREC_FP16X3> { static constexpr int NT = 2; using E = _Float16; };
-
-// split x (already scaled for FP16) into NT pieces
-template <int PREC>
-NTU_DEV void split_value(float x, typename SplitTraits<PREC>::E* out) {
-  using E = typename SplitTraits<PREC>::E;
-  if constexpr (PREC == NTU_PREC_FP16X3) {
-    E hi = (E)x;
-    float r = (x - (float)hi) * 2048.0f;
-    out[0] = hi;
-    out[1] = (E)r;
-  } else if constexpr (PREC == NTU_PREC_BF16X3) {
-    E hi = (E)x;
-    out[0] = hi;
-    out[1] = (E)(x - (float)hi);
-  } else {
-    E hi = (E)x;
-    float r = x - (float)hi;
-    E mid = (E)r;
-    out[0] = hi;
-    out[1] = mid;
-    out[2] = (E)(r - (float)mid);
-  }
-}
-
-template <int PREC>
-NTU_DEV f32x4 mfma(const typename SplitTraits<PREC>::E* a, const typename SplitTraits<PREC>::E* b, f32x4 c) {
-  if constexpr (PREC == NTU_PREC_FP16X3) {
-    f16x8 va = *(const f16x8*)a, vb = *(const f16x8*)b;
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(va, vb, c, 0, 0, 0);
-  } else {
-    bf16x8 va = *(const bf16x8*)a, vb = *(const bf16x8*)b;
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, c, 0, 0, 0);
-  }
-}
 
 template <class TIn> NTU_DEV float to_f(TIn v) { return (float)v; }
 
@@ -592,7 +550,8 @@ size_t mixed_partial_bytes(bool cplx, int batch, int R, int D) {
 template <int PREC, bool CPLX>
 static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, const void* QXp, const void* QYe,
                             const void* QYp, const void* ETT, const void* EBT, long long es, long long qs, long long hs,
-                            void* H0, void* H1, void* H2, void* g, hipStream_t st, const ProfHook& ph) {
+                            void* H0, void* H1, void* H2, void* g, hipStream_t st, const ProfHook& ph,
+                            bool lr_done) {
   using T64 = double;  // scalar of the compute-type inputs
   const long long D2 = (long long)D * D, D3 = D2 * D, D4 = D2 * D2, RD4 = (long long)R * D4;
   const int pD = p * D;
@@ -604,22 +563,31 @@ static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, con
   d.Ai = idx1(pD); d.Ak = idx1(1); d.Bj = idx1(pD); d.Bk = idx1(1);
   d.conjB = 1;
   d.Ci = idx3(D, D, RD4, D3, D); d.Cj = idx3(D, D, D4, D2, 1);
-  e = run_tile<PREC, CPLX, T64, T64, float>(QXe, QXp, H0, d, 1, nullptr, st, ph, PK_LEFTRIGHT);
-  if (e != hipSuccess) return e;
-  d.Ci = idx3(D, D, RD4, D, D3); d.Cj = idx3(D, D, D4, 1, D2);
-  e = run_tile<PREC, CPLX, T64, T64, float>(QYe, QYp, H2, d, 1, nullptr, st, ph, PK_LEFTRIGHT);
-  if (e != hipSuccess) return e;
+  if (!lr_done) {
+    e = run_tile<PREC, CPLX, T64, T64, float>(QXe, QXp, H0, d, 1, nullptr, st, ph, PK_LEFTRIGHT);
+    if (e != hipSuccess) return e;
+    d.Ci = idx3(D, D, RD4, D, D3); d.Cj = idx3(D, D, D4, 1, D2);
+    e = run_tile<PREC, CPLX, T64, T64, float>(QYe, QYp, H2, d, 1, nullptr, st, ph, PK_LEFTRIGHT);
+    if (e != hipSuccess) return e;
+  }
   // L1 = Left x Etop, L2 = L1 x Ebot
-  GemmNT f{};
-  f.M = (int)(R * R * D2); f.N = (int)D2; f.K = (int)D2; f.batch = batch;
-  f.Ab = idx1(hs); f.Bb = idx1(es); f.Cb = idx1(hs);
-  f.Ai = idx1(D2); f.Ak = idx1(1); f.Bj = idx1(D2); f.Bk = idx1(1);
-  f.Ci = idx2((int)D2, D4, 1); f.Cj = idx1(D2);
-  e = run_tile<PREC, CPLX, float, T64, float>(H0, ETT, H1, f, 1, nullptr, st, ph, PK_E4);
-  if (e != hipSuccess) return e;
-  f.Ci = idx1(D2); f.Cj = idx1(1);
-  e = run_tile<PREC, CPLX, float, T64, float>(H1, EBT, H0, f, 1, nullptr, st, ph, PK_E5);
-  if (e != hipSuccess) return e;
+  if (e45_supported(CPLX, PREC, D) && e45_frag_bytes(PREC, batch, D) <= (size_t)batch * hs * (CPLX ? 8 : 4)) {
+    ph(PK_E4, 0);
+    e = launch_e45(PREC, batch, D, R, ETT, EBT, es, H0, hs, H1, st);
+    ph(PK_E4, 1);
+    if (e != hipSuccess) return e;
+  } else {
+    GemmNT f{};
+    f.M = (int)(R * R * D2); f.N = (int)D2; f.K = (int)D2; f.batch = batch;
+    f.Ab = idx1(hs); f.Bb = idx1(es); f.Cb = idx1(hs);
+    f.Ai = idx1(D2); f.Ak = idx1(1); f.Bj = idx1(D2); f.Bk = idx1(1);
+    f.Ci = idx2((int)D2, D4, 1); f.Cj = idx1(D2);
+    e = run_tile<PREC, CPLX, float, T64, float>(H0, ETT, H1, f, 1, nullptr, st, ph, PK_E4);
+    if (e != hipSuccess) return e;
+    f.Ci = idx1(D2); f.Cj = idx1(1);
+    e = run_tile<PREC, CPLX, float, T64, float>(H1, EBT, H0, f, 1, nullptr, st, ph, PK_E5);
+    if (e != hipSuccess) return e;
+  }
   // g = L2 Right^T with split K, FP64 reduction
   GemmNT q{};
   q.M = R * R; q.N = R * R; q.K = (int)D4; q.batch = batch;
@@ -636,8 +604,8 @@ static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, con
 hipError_t launch_env_heavy_mixed(bool cplx, int precision, int batch, int p, int D, int R, const void* QXe,
                                   const void* QXp, const void* QYe, const void* QYp, const void* ETT,
                                   const void* EBT, long long es, long long qs, long long hs, void* H0, void* H1,
-                                  void* H2, void* g, hipStream_t st, const ProfHook& ph) {
-#define NTU_MIX(P, C) return env_heavy<P, C>(batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, qs, hs, H0, H1, H2, g, st, ph)
+                                  void* H2, void* g, hipStream_t st, const ProfHook& ph, bool lr_done) {
+#define NTU_MIX(P, C) return env_heavy<P, C>(batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, qs, hs, H0, H1, H2, g, st, ph, lr_done)
   if (precision == NTU_PREC_BF16X3) { if (cplx) NTU_MIX(NTU_PREC_BF16X3, true); NTU_MIX(NTU_PREC_BF16X3, false); }
   if (precision == NTU_PREC_BF16X6) { if (cplx) NTU_MIX(NTU_PREC_BF16X6, true); NTU_MIX(NTU_PREC_BF16X6, false); }
   // FP16X3 needs operand scales; not wired into the environment yet

@@ -51,8 +51,11 @@ hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D
 // metric repair and fit
 // ---------------------------------------------------------------------------
 size_t fix_workspace_bytes(bool cplx, int batch, int n);
+// shift_rel > 0: also test g - shift_rel ||g||_F I and report per item in
+// cert (1 = certified, may be NULL)
 hipError_t launch_metric_fix(bool cplx, int batch, int n, void* g, int mode, double* stats, int stats_stride,
-                             void* ws, hipStream_t st, const ProfHook& ph);
+                             void* ws, hipStream_t st, const ProfHook& ph, double shift_rel = 0.0,
+                             double* cert = nullptr);
 
 struct FitParams {
   int n_iter, early_stop;
@@ -64,6 +67,6 @@ size_t fit_workspace_bytes(bool cplx, int batch, int D, int R);
 NTU_HD int fit_stats_len(int n_iter, int D) { return 16 + 4 * n_iter + D; }
 hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, const void* RX, const void* RY,
                            const FitParams& fp, void* MX, void* MY, double* stats, int stats_stride, void* ws,
-                           hipStream_t st, const ProfHook& ph);
+                           hipStream_t st, const ProfHook& ph, const double* cert = nullptr);
 
 }  // namespace ntu

@@ -1,0 +1,54 @@
+// Operand splitting for the split-precision products on the gfx950 matrix
+// cores: a value x becomes NT bfloat16 (or float16) pieces whose sum is x to
+// about 8 NT bits, and one 16 x 16 x 32 MFMA multiplies 16 x 32 by 32 x 16
+// pieces with FP32 accumulation.
+#pragma once
+#include "common.h"
+#include "ntu.h"
+
+namespace ntu {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int PREC> struct SplitTraits;
+template <> struct SplitTraits<NTU_PREC_BF16X3> { static constexpr int NT = 2; using E = __bf16; };
+template <> struct SplitTraits<NTU_PREC_BF16X6> { static constexpr int NT = 3; using E = __bf16; };
+template <> struct SplitTraits<NTU_PREC_FP16X3> { static constexpr int NT = 2; using E = _Float16; };
+
+// split x (already scaled for FP16) into NT pieces
+template <int PREC>
+NTU_DEV void split_value(float x, typename SplitTraits<PREC>::E* out) {
+  using E = typename SplitTraits<PREC>::E;
+  if constexpr (PREC == NTU_PREC_FP16X3) {
+    E hi = (E)x;
+    float r = (x - (float)hi) * 2048.0f;
+    out[0] = hi;
+    out[1] = (E)r;
+  } else if constexpr (PREC == NTU_PREC_BF16X3) {
+    E hi = (E)x;
+    out[0] = hi;
+    out[1] = (E)(x - (float)hi);
+  } else {
+    E hi = (E)x;
+    float r = x - (float)hi;
+    E mid = (E)r;
+    out[0] = hi;
+    out[1] = mid;
+    out[2] = (E)(r - (float)mid);
+  }
+}
+
+template <int PREC>
+NTU_DEV f32x4 mfma(const typename SplitTraits<PREC>::E* a, const typename SplitTraits<PREC>::E* b, f32x4 c) {
+  if constexpr (PREC == NTU_PREC_FP16X3) {
+    f16x8 va = *(const f16x8*)a, vb = *(const f16x8*)b;
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(va, vb, c, 0, 0, 0);
+  } else {
+    bf16x8 va = *(const bf16x8*)a, vb = *(const bf16x8*)b;
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, c, 0, 0, 0);
+  }
+}
+
+}  // namespace ntu
