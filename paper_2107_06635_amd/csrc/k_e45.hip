@@ -63,57 +63,100 @@ __global__ void __launch_bounds__(256) k_e45_prep(int n, int npad, const cd* __r
 
 struct alignas(4) bf16pair { __bf16 v[2]; };
 
-// NPAD / 16 waves; wave w computes real output columns [32 w, 32 w + 32) of
-// both products, all NPAD rows.  Workgroups are dealt to the 8 XCDs
-// round-robin by id; the order puts an item's workgroups on one XCD.
-// H: the Left blocks (FP32 (re, im) pairs), item stride hs complex elements,
-// (a a') block at (a R + a') n^2; overwritten by the L2 blocks.
-template <int PREC, int NPAD>
-__global__ void __launch_bounds__(NPAD * 4) k_e45(int n, int R2, int nwork, float* H, long long hs,
-                                                  const __bf16* __restrict__ frag) {
-  constexpr int NP = SplitTraits<PREC>::NT;
-  constexpr int NACC = (PREC == NTU_PREC_BF16X6) ? 3 : 2;
-  constexpr int MT = NPAD / 16, KS = NPAD / 16;
-  constexpr int LD = 2 * NPAD + 8;
-  __shared__ __attribute__((aligned(16))) __bf16 sA[NP][NPAD][LD];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int per = (nwork + 7) / 8;
-  const int q = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (q >= nwork) return;
-  const int item = q / R2, pair = q % R2;
-  float* X = H + ((size_t)item * hs + (size_t)pair * n * n) * 2;
-  const int per_m = e45_frag_elems(NPAD, NP);
-  const __bf16* F1 = frag + (size_t)item * 2 * per_m;
-  const __bf16* F2 = F1 + per_m;
+// Per-wave pieces shared by the kernels below.  A product's output tile
+// of NPAD rows x 2 NPAD real columns is split over NPAD / 16 waves: wave w
+// owns real columns [32 w, 32 w + 32) (two 16-wide MFMA tiles, y = 0, 1) of
+// every row tile mt; acc[c][mt][y] holds the term class c.
+template <int PREC, int NPAD> struct E45 {
+  static constexpr int NP = SplitTraits<PREC>::NT;
+  static constexpr int NACC = (PREC == NTU_PREC_BF16X6) ? 3 : 2;
+  static constexpr int MT = NPAD / 16, KS = NPAD / 16;
+  static constexpr int LD = 2 * NPAD + 8;
+  using Acc = f32x4[NACC][MT][2];
 
-  // Left block -> pieces in shared memory (zero padded)
-  for (int e = tid; e < NPAD * NPAD; e += blockDim.x) {
-    const int r = e / NPAD, c = e % NPAD;
-    float re = 0.0f, im = 0.0f;
-    if (r < n && c < n) {
-      const float2 z = *(const float2*)&X[2 * ((size_t)r * n + c)];
-      re = z.x; im = z.y;
-    }
-    __bf16 tr[NP], ti[NP];
-    split_value<PREC>(re, tr);
-    split_value<PREC>(im, ti);
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      bf16pair v;
-      v.v[0] = tr[p]; v.v[1] = ti[p];
-      *(bf16pair*)&sA[p][r][2 * c] = v;
-    }
-  }
-  __syncthreads();
-
-  f32x4 acc[NACC][MT][2];
-  auto product = [&](const __bf16* F) {
+  static NTU_DEV void zero(Acc& acc) {
 #pragma unroll
     for (int c = 0; c < NACC; ++c)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[c][mt][y] = f32x4{0, 0, 0, 0};
+  }
+
+  // the piece products kept, by term class: BF16x3 (hi, lo): hi hi |
+  // hi lo + lo hi; BF16x6 (hi, mid, lo): hi hi | hi mid + mid hi |
+  // hi lo + mid mid + lo hi
+  static NTU_DEV void mma(Acc& acc, int mt, int y, const bf16x8 (&a)[NP], const bf16x8 (&b)[NP]) {
+    acc[0][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc[0][mt][y], 0, 0, 0);
+    acc[1][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc[1][mt][y], 0, 0, 0);
+    acc[1][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc[1][mt][y], 0, 0, 0);
+    if constexpr (NACC == 3) {
+      acc[2][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], acc[2][mt][y], 0, 0, 0);
+      acc[2][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], acc[2][mt][y], 0, 0, 0);
+      acc[2][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], acc[2][mt][y], 0, 0, 0);
+    }
+  }
+
+  static NTU_DEV void split8(const float (&x)[8], bf16x8 (&f)[NP]) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 t[NP];
+      split_value<PREC>(x[e], t);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) f[p][e] = t[p];
+    }
+  }
+
+  // P[u][u'] = sum_s Qe[u][s] conj(Qp[u'][s]), u, u' < n, s < K (rows of
+  // length K, complex).  A fragment: row u = 16 mt + lane % 16, complex
+  // s = 16 kq + 4 (lane / 16) + h; B fragment: real row 32 w + 16 y +
+  // lane % 16 of the embedding of conj(Qp).
+  static NTU_DEV void pair_product(Acc& acc, const cd* __restrict__ Qe, const cd* __restrict__ Qp, int n, int K,
+                                   int w, int lane) {
+    zero(acc);
+    const int KQ = (K + 15) / 16;
+    for (int kq = 0; kq < KQ; ++kq) {
+      const int s0 = 16 * kq + 4 * (lane >> 4);
+      bf16x8 b[2][NP];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int ur = 32 * w + 16 * y + (lane & 15), u = ur >> 1;
+        float x[8];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const bool ok = u < n && s0 + h < K;
+          const cd z = Qp[ok ? (size_t)u * K + s0 + h : 0];
+          const float re = ok ? (float)z.x : 0.0f, im = ok ? -(float)z.y : 0.0f;
+          // real row 2u: (re, -im); 2u + 1: (im, re)
+          x[2 * h] = (ur & 1) ? im : re;
+          x[2 * h + 1] = (ur & 1) ? re : -im;
+        }
+        split8(x, b[y]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int u = 16 * mt + (lane & 15);
+        float x[8];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const bool ok = u < n && s0 + h < K;
+          const cd z = Qe[ok ? (size_t)u * K + s0 + h : 0];
+          const float re = ok ? (float)z.x : 0.0f, im = ok ? (float)z.y : 0.0f;
+          x[2 * h] = re;
+          x[2 * h + 1] = im;
+        }
+        bf16x8 a[NP];
+        split8(x, a);
+#pragma unroll
+        for (int y = 0; y < 2; ++y) mma(acc, mt, y, a, b[y]);
+      }
+    }
+  }
+
+  // acc += A B^T with A from the shared pieces sA (NPAD rows, 2 NPAD real
+  // columns) and B from prepared fragments F (layout of k_e45_prep)
+  static NTU_DEV void product(Acc& acc, const __bf16 (*sA)[NPAD][LD], const __bf16* __restrict__ F, int w, int lane) {
+    zero(acc);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       bf16x8 b[2][NP];
@@ -128,56 +171,134 @@ __global__ void __launch_bounds__(NPAD * 4) k_e45(int n, int R2, int nwork, floa
 #pragma unroll
         for (int p = 0; p < NP; ++p) a[p] = *(const bf16x8*)&sA[p][16 * mt + (lane & 15)][32 * ks + 8 * (lane >> 4)];
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          acc[0][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[y][0], acc[0][mt][y], 0, 0, 0);
-          acc[1][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[y][1], acc[1][mt][y], 0, 0, 0);
-          acc[1][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[y][0], acc[1][mt][y], 0, 0, 0);
-          if constexpr (NACC == 3) {
-            acc[2][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[y][2], acc[2][mt][y], 0, 0, 0);
-            acc[2][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[y][1], acc[2][mt][y], 0, 0, 0);
-            acc[2][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[y][0], acc[2][mt][y], 0, 0, 0);
-          }
-        }
+        for (int y = 0; y < 2; ++y) mma(acc, mt, y, a, b[y]);
       }
     }
-  };
-  auto value = [&](int mt, int y, int v) -> float {
-    double s = (double)acc[0][mt][y][v];
-    if constexpr (NACC == 3) s += (double)acc[1][mt][y][v] + (double)acc[2][mt][y][v];
-    else s += (double)acc[1][mt][y][v];
-    return (float)s;
-  };
+  }
 
-  product(F1);
-  __syncthreads();  // every wave has read the Left pieces
-  // L1 block -> shared memory as the A operand of the second product:
-  // output (row b b', real column 2 j + c) -> A row j, real k 2 (b b') + c
+  // Hands each complex output to fn(row, column, re, im).  Lanes 2i and
+  // 2i + 1 hold the real and imaginary parts of one complex column; one
+  // exchange (DPP quad_perm [1,0,3,2]) gives the even lane both parts of
+  // rows v = 0, 2 and the odd lane those of rows v = 1, 3.  The term
+  // classes are summed in FP32 (smallest first): the result is the FP32
+  // rounding of their sum up to one unit in the last place.
+  template <class Fn> static NTU_DEV void outputs(const Acc& acc, int w, int lane, Fn fn) {
+    const bool odd = lane & 1;
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < 2; ++y) {
+        float x[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int bb = 16 * mt + 4 * (lane >> 4) + v;
-        const int jr = 32 * w + 16 * y + (lane & 15);
-        __bf16 t[NP];
-        split_value<PREC>(value(mt, y, v), t);
-#pragma unroll
-        for (int p = 0; p < NP; ++p) sA[p][jr >> 1][2 * bb + (jr & 1)] = t[p];
+        for (int v = 0; v < 4; ++v) {
+          float s = acc[1][mt][y][v];
+          if constexpr (NACC == 3) s = acc[2][mt][y][v] + s;
+          x[v] = acc[0][mt][y][v] + s;
+        }
+        const float r0 = swap_pair(odd ? x[0] : x[1]);
+        const float r1 = swap_pair(odd ? x[2] : x[3]);
+        const int col = (32 * w + 16 * y + (lane & 15)) >> 1;
+        const int row = 16 * mt + 4 * (lane >> 4) + (odd ? 1 : 0);
+        fn(row, col, odd ? r0 : x[0], odd ? x[1] : r0);
+        fn(row + 2, col, odd ? r1 : x[2], odd ? x[3] : r1);
       }
+  }
+
+  static NTU_DEV float swap_pair(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xf, 0xf, false));
+  }
+
+  static NTU_DEV void store_pieces(__bf16 (*sA)[NPAD][LD], int row, int colc, float re, float im) {
+    __bf16 tr[NP], ti[NP];
+    split_value<PREC>(re, tr);
+    split_value<PREC>(im, ti);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      bf16pair v;
+      v.v[0] = tr[p]; v.v[1] = ti[p];
+      *(bf16pair*)&sA[p][row][2 * colc] = v;
+    }
+  }
+};
+
+// Workgroups are dealt to the 8 XCDs round-robin by id; this order puts an
+// item's workgroups on one XCD, consecutively.  The grid has 8 ceil(nwork / 8)
+// workgroups; ids beyond the work return at once.
+NTU_DEV int xcd_order(int nwork) {
+  const int per = (nwork + 7) / 8;
+  return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+}
+
+// One workgroup per (item, a, a'): the Left block from the dressed
+// isometries, then L1 and L2; the L2 block (FP32 (re, im) pairs, item stride
+// hs complex elements, block (a R + a') n^2, row-major [j][k]) goes to out.
+//   Left[b b'][t t'] = P[b D + t][b' D + t'],  P = QXe[a] QXp[a']^H
+template <int PREC, int D, int NPAD = ((D * D + 15) / 16) * 16>
+__global__ void __launch_bounds__(NPAD * 4, 2) k_left_e45(int R, int K, int nwork, const cd* __restrict__ QXe,
+                                                       const cd* __restrict__ QXp, long long qs, float* __restrict__ out,
+                                                       long long hs, const __bf16* __restrict__ frag) {
+  using S = E45<PREC, NPAD>;
+  constexpr int NP = S::NP, LD = S::LD;
+  __shared__ __attribute__((aligned(16))) __bf16 sA[NP][NPAD][LD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int q = xcd_order(nwork);
+  if (q >= nwork) return;
+  constexpr int n = D * D;
+  const int R2 = R * R;
+  const int item = q / R2, a = (q % R2) / R, ap = q % R;
+  const cd* Qe = QXe + (size_t)item * qs + (size_t)a * n * K;
+  const cd* Qp = QXp + (size_t)item * qs + (size_t)ap * n * K;
+  const int per_m = e45_frag_elems(NPAD, NP);
+  const __bf16* F1 = frag + (size_t)item * 2 * per_m;
+  const __bf16* F2 = F1 + per_m;
+
+  // zero the pieces when n < NPAD (rows and columns beyond n stay zero)
+  if constexpr (n < NPAD)
+    for (int e = tid; e < NP * NPAD * LD / 2; e += blockDim.x) ((unsigned*)&sA[0][0][0])[e] = 0u;
+  typename S::Acc acc;
+  S::pair_product(acc, Qe, Qp, n, K, w, lane);
   __syncthreads();
-  product(F2);
-  // L2 block over the Left block: row j, real column kr
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = 16 * mt + 4 * (lane >> 4) + v;
-        const int kr = 32 * w + 16 * y + (lane & 15);
-        if (j < n && kr < 2 * n) X[(size_t)j * 2 * n + kr] = value(mt, y, v);
-      }
+  S::outputs(acc, w, lane, [&](int u, int up, float re, float im) {
+    if (u < n && up < n) S::store_pieces(sA, (u / D) * D + up / D, (u % D) * D + up % D, re, im);
+  });
+  __syncthreads();
+  S::product(acc, sA, F1, w, lane);
+  __syncthreads();  // every wave has read the Left pieces
+  // L1 (row b b', column j) -> A operand of the second product: row j, column b b'
+  S::outputs(acc, w, lane, [&](int bb, int j, float re, float im) { S::store_pieces(sA, j, bb, re, im); });
+  __syncthreads();
+  S::product(acc, sA, F2, w, lane);
+  float* O = out + ((size_t)item * hs + (size_t)(q % R2) * n * n) * 2;
+  S::outputs(acc, w, lane, [&](int j, int k, float re, float im) {
+    if (j < n && k < n) *(float2*)&O[2 * ((size_t)j * n + k)] = make_float2(re, im);
+  });
+}
+
+// One workgroup per (item, B, B'):
+//   Right[T T'][c c'] = P[c D + T][c' D + T'],  P = QYe[B] QYp[B']^H,
+// staged in shared memory and written row-major (block (B R + B') n^2).
+template <int PREC, int D, int NPAD = ((D * D + 15) / 16) * 16>
+__global__ void __launch_bounds__(NPAD * 4, 2) k_right(int R, int K, int nwork, const cd* __restrict__ QYe,
+                                                    const cd* __restrict__ QYp, long long qs, float* __restrict__ out,
+                                                    long long hs) {
+  using S = E45<PREC, NPAD>;
+  __shared__ __attribute__((aligned(16))) float2 st[NPAD * NPAD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int q = xcd_order(nwork);
+  if (q >= nwork) return;
+  constexpr int n = D * D;
+  const int R2 = R * R;
+  const int item = q / R2, b = (q % R2) / R, bp = q % R;
+  const cd* Qe = QYe + (size_t)item * qs + (size_t)b * n * K;
+  const cd* Qp = QYp + (size_t)item * qs + (size_t)bp * n * K;
+  typename S::Acc acc;
+  S::pair_product(acc, Qe, Qp, n, K, w, lane);
+  S::outputs(acc, w, lane, [&](int u, int up, float re, float im) {
+    if (u < n && up < n) st[((u % D) * D + up % D) * n + (u / D) * D + up / D] = make_float2(re, im);
+  });
+  __syncthreads();
+  float2* O = (float2*)(out + ((size_t)item * hs + (size_t)(q % R2) * n * n) * 2);
+  for (int e = tid; e < n * n; e += blockDim.x) O[e] = st[e];
 }
 
 bool e45_supported(bool cplx, int precision, int D) {
@@ -189,35 +310,63 @@ size_t e45_frag_bytes(int precision, int batch, int D) {
   return (size_t)batch * 2 * e45_frag_elems(e45_npad(D), np) * sizeof(__bf16);
 }
 
+template <int PREC, int D>
+static void fused_launch(int batch, int p, int R, const cd* QXe, const cd* QXp, const cd* QYe, const cd* QYp,
+                         long long qs, float* L2, float* Right, long long hs, const __bf16* frag, hipStream_t st,
+                         const ProfHook& ph) {
+  constexpr int NPAD = ((D * D + 15) / 16) * 16;
+  const int nwork = batch * R * R;
+  const dim3 g(8 * ((nwork + 7) / 8)), b(NPAD * 4);
+  ph(PK_LEFTRIGHT, 0);
+  hipLaunchKernelGGL((k_right<PREC, D>), g, b, 0, st, R, p * D, nwork, QYe, QYp, qs, Right, hs);
+  ph(PK_LEFTRIGHT, 1);
+  ph(PK_E4, 0);
+  hipLaunchKernelGGL((k_left_e45<PREC, D>), g, b, 0, st, R, p * D, nwork, QXe, QXp, qs, L2, hs, frag);
+  ph(PK_E4, 1);
+}
+
 template <int PREC>
-static hipError_t e45_run(int batch, int D, int R, const void* ETT, const void* EBT, long long es, void* H,
-                          long long hs, void* frag, hipStream_t st) {
+static hipError_t fused_run(int batch, int p, int D, int R, const void* QXe, const void* QXp, const void* QYe,
+                            const void* QYp, const void* ETT, const void* EBT, long long es, long long qs, void* H0,
+                            void* H1, void* H2, long long hs, hipStream_t st, const ProfHook& ph) {
   const int n = D * D, npad = e45_npad(D);
   constexpr int NP = SplitTraits<PREC>::NT;
   const int nval = e45_frag_elems(npad, NP) / NP;
-  dim3 gp((nval + 255) / 256, batch, 2);
-  hipLaunchKernelGGL(k_e45_prep<PREC>, gp, dim3(256), 0, st, n, npad, (const cd*)ETT, (const cd*)EBT, es,
-                     (__bf16*)frag);
+  ph(PK_E5, 0);
+  hipLaunchKernelGGL(k_e45_prep<PREC>, dim3((nval + 255) / 256, batch, 2), dim3(256), 0, st, n, npad,
+                     (const cd*)ETT, (const cd*)EBT, es, (__bf16*)H1);
+  ph(PK_E5, 1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int nwork = batch * R * R;
-  dim3 g(8 * ((nwork + 7) / 8));  // the XCD order maps [0, 8 ceil(nwork / 8)) onto the work
-  switch (npad) {
-    case 16: hipLaunchKernelGGL((k_e45<PREC, 16>), g, dim3(64), 0, st, n, R * R, nwork, (float*)H, hs, (const __bf16*)frag); break;
-    case 32: hipLaunchKernelGGL((k_e45<PREC, 32>), g, dim3(128), 0, st, n, R * R, nwork, (float*)H, hs, (const __bf16*)frag); break;
-    case 48: hipLaunchKernelGGL((k_e45<PREC, 48>), g, dim3(192), 0, st, n, R * R, nwork, (float*)H, hs, (const __bf16*)frag); break;
-    case 64: hipLaunchKernelGGL((k_e45<PREC, 64>), g, dim3(256), 0, st, n, R * R, nwork, (float*)H, hs, (const __bf16*)frag); break;
+#define NTU_FUSED(D_)                                                                                           \
+  fused_launch<PREC, D_>(batch, p, R, (const cd*)QXe, (const cd*)QXp, (const cd*)QYe, (const cd*)QYp, qs, (float*)H0, \
+                         (float*)H2, hs, (const __bf16*)H1, st, ph)
+  switch (D) {
+    case 1: NTU_FUSED(1); break;
+    case 2: NTU_FUSED(2); break;
+    case 3: NTU_FUSED(3); break;
+    case 4: NTU_FUSED(4); break;
+    case 5: NTU_FUSED(5); break;
+    case 6: NTU_FUSED(6); break;
+    case 7: NTU_FUSED(7); break;
+    case 8: NTU_FUSED(8); break;
     default: return hipErrorInvalidValue;
   }
+#undef NTU_FUSED
   return hipGetLastError();
 }
 
-hipError_t launch_e45(int precision, int batch, int D, int R, const void* ETT, const void* EBT, long long es, void* H,
-                      long long hs, void* frag, hipStream_t st) {
+hipError_t launch_env_fused(int precision, int batch, int p, int D, int R, const void* QXe, const void* QXp,
+                            const void* QYe, const void* QYp, const void* ETT, const void* EBT, long long es,
+                            long long qs, void* H0, void* H1, void* H2, long long hs, hipStream_t st,
+                            const ProfHook& ph) {
   if (batch <= 0) return hipSuccess;
   if (D * D > 64) return hipErrorInvalidValue;
-  if (precision == NTU_PREC_BF16X6) return e45_run<NTU_PREC_BF16X6>(batch, D, R, ETT, EBT, es, H, hs, frag, st);
-  if (precision == NTU_PREC_BF16X3) return e45_run<NTU_PREC_BF16X3>(batch, D, R, ETT, EBT, es, H, hs, frag, st);
+  if (e45_frag_bytes(precision, batch, D) > (size_t)batch * hs * 8) return hipErrorInvalidValue;
+  if (precision == NTU_PREC_BF16X6)
+    return fused_run<NTU_PREC_BF16X6>(batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, qs, H0, H1, H2, hs, st, ph);
+  if (precision == NTU_PREC_BF16X3)
+    return fused_run<NTU_PREC_BF16X3>(batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, qs, H0, H1, H2, hs, st, ph);
   return hipErrorNotSupported;
 }
 

@@ -321,25 +321,19 @@ static size_t half_env_shmem(bool cplx, int p, int D) {
   return (size_t)(D * D + D) * (p * D + 1) * (cplx ? 16 : 8);
 }
 
-// Left into H0 and Right into H2; out_float: split-precision intermediates
-static hipError_t half_env(bool cplx, bool out_float, int batch, int p, int D, int R, const void* QXe,
-                           const void* QXp, const void* QYe, const void* QYp, long long qs, void* H0, void* H2,
-                           long long hs, hipStream_t st) {
+// Left into H0 and Right into H2 (FP64 path)
+static hipError_t half_env(bool cplx, int batch, int p, int D, int R, const void* QXe, const void* QXp,
+                           const void* QYe, const void* QYp, long long qs, void* H0, void* H2, long long hs,
+                           hipStream_t st) {
   const size_t shm = half_env_shmem(cplx, p, D);
   dim3 g(batch * R * R), b(256);
   for (int side = 0; side < 2; ++side) {
     const void* Qe = side == 0 ? QXe : QYe;
     const void* Qp = side == 0 ? QXp : QYp;
     void* O = side == 0 ? H0 : H2;
-    if (cplx && out_float)
-      hipLaunchKernelGGL((k_half_env<cd, float>), g, b, shm, st, p, D, R, side, (const cd*)Qe, (const cd*)Qp, qs,
-                         (float*)O, hs);
-    else if (cplx)
+    if (cplx)
       hipLaunchKernelGGL((k_half_env<cd, double>), g, b, shm, st, p, D, R, side, (const cd*)Qe, (const cd*)Qp, qs,
                          (double*)O, hs);
-    else if (out_float)
-      hipLaunchKernelGGL((k_half_env<double, float>), g, b, shm, st, p, D, R, side, (const double*)Qe,
-                         (const double*)Qp, qs, (float*)O, hs);
     else
       hipLaunchKernelGGL((k_half_env<double, double>), g, b, shm, st, p, D, R, side, (const double*)Qe,
                          (const double*)Qp, qs, (double*)O, hs);
@@ -495,7 +489,7 @@ hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D
     d.Ci = idx3(D, D, RD4, D3, D); d.Cj = idx3(D, D, D4, D2, 1);
     ph(PK_LEFTRIGHT, 0);
     if (half_env_shmem(cplx, p, D) <= 64 * 1024) {
-      NTU_TRY(half_env(cplx, false, batch, p, D, R, QXe, QXp, QYe, QYp, s.qp, H0, H2, s.half, st));
+      NTU_TRY(half_env(cplx, batch, p, D, R, QXe, QXp, QYe, QYp, s.qp, H0, H2, s.half, st));
     } else {
       NTU_TRY(gemm_nt(cplx, QXe, QXp, H0, d, st));
       // Right[B][B'][T][T'][c][c'] from rows (B, c, T)
@@ -527,15 +521,9 @@ hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D
     NTU_TRY(gemm_nt(cplx, H0, H2, g, f, st));
     ph(PK_E6, 1);
   } else {
-    // Left / Right on the vector units (FP32 out), then the long products on the matrix cores
-    const bool lr_done = half_env_shmem(cplx, p, D) <= 64 * 1024;
-    if (lr_done) {
-      ph(PK_LEFTRIGHT, 0);
-      NTU_TRY(half_env(cplx, true, batch, p, D, R, QXe, QXp, QYe, QYp, s.qp, H0, H2, s.half, st));
-      ph(PK_LEFTRIGHT, 1);
-    }
+    // the products of steps 4-7 on the matrix cores in split precision
     NTU_TRY(launch_env_heavy_mixed(cplx, precision, batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, s.qp,
-                                   s.half, H0, H1, H2, g, st, ph, lr_done));
+                                   s.half, H0, H1, H2, g, st, ph));
   }
 #undef NTU_TRY
   return hipSuccess;

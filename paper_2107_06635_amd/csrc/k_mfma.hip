@@ -550,33 +550,29 @@ size_t mixed_partial_bytes(bool cplx, int batch, int R, int D) {
 template <int PREC, bool CPLX>
 static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, const void* QXp, const void* QYe,
                             const void* QYp, const void* ETT, const void* EBT, long long es, long long qs, long long hs,
-                            void* H0, void* H1, void* H2, void* g, hipStream_t st, const ProfHook& ph,
-                            bool lr_done) {
+                            void* H0, void* H1, void* H2, void* g, hipStream_t st, const ProfHook& ph) {
   using T64 = double;  // scalar of the compute-type inputs
   const long long D2 = (long long)D * D, D3 = D2 * D, D4 = D2 * D2, RD4 = (long long)R * D4;
   const int pD = p * D;
   hipError_t e;
-  // Left / Right
-  GemmNT d{};
-  d.M = (int)(R * D2); d.N = (int)(R * D2); d.K = pD; d.batch = batch;
-  d.Ab = idx1(qs); d.Bb = idx1(qs); d.Cb = idx1(hs);
-  d.Ai = idx1(pD); d.Ak = idx1(1); d.Bj = idx1(pD); d.Bk = idx1(1);
-  d.conjB = 1;
-  d.Ci = idx3(D, D, RD4, D3, D); d.Cj = idx3(D, D, D4, D2, 1);
-  if (!lr_done) {
+  if (CPLX && e45_supported(CPLX, PREC, D)) {
+    // Right, and Left -> L1 -> L2 per (a, a') block, on the matrix cores
+    e = launch_env_fused(PREC, batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, qs, H0, H1, H2, hs, st, ph);
+    if (e != hipSuccess) return e;
+  } else {
+    // Left / Right
+    GemmNT d{};
+    d.M = (int)(R * D2); d.N = (int)(R * D2); d.K = pD; d.batch = batch;
+    d.Ab = idx1(qs); d.Bb = idx1(qs); d.Cb = idx1(hs);
+    d.Ai = idx1(pD); d.Ak = idx1(1); d.Bj = idx1(pD); d.Bk = idx1(1);
+    d.conjB = 1;
+    d.Ci = idx3(D, D, RD4, D3, D); d.Cj = idx3(D, D, D4, D2, 1);
     e = run_tile<PREC, CPLX, T64, T64, float>(QXe, QXp, H0, d, 1, nullptr, st, ph, PK_LEFTRIGHT);
     if (e != hipSuccess) return e;
     d.Ci = idx3(D, D, RD4, D, D3); d.Cj = idx3(D, D, D4, 1, D2);
     e = run_tile<PREC, CPLX, T64, T64, float>(QYe, QYp, H2, d, 1, nullptr, st, ph, PK_LEFTRIGHT);
     if (e != hipSuccess) return e;
-  }
-  // L1 = Left x Etop, L2 = L1 x Ebot
-  if (e45_supported(CPLX, PREC, D) && e45_frag_bytes(PREC, batch, D) <= (size_t)batch * hs * (CPLX ? 8 : 4)) {
-    ph(PK_E4, 0);
-    e = launch_e45(PREC, batch, D, R, ETT, EBT, es, H0, hs, H1, st);
-    ph(PK_E4, 1);
-    if (e != hipSuccess) return e;
-  } else {
+    // L1 = Left x Etop, L2 = L1 x Ebot
     GemmNT f{};
     f.M = (int)(R * R * D2); f.N = (int)D2; f.K = (int)D2; f.batch = batch;
     f.Ab = idx1(hs); f.Bb = idx1(es); f.Cb = idx1(hs);
@@ -604,8 +600,8 @@ static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, con
 hipError_t launch_env_heavy_mixed(bool cplx, int precision, int batch, int p, int D, int R, const void* QXe,
                                   const void* QXp, const void* QYe, const void* QYp, const void* ETT,
                                   const void* EBT, long long es, long long qs, long long hs, void* H0, void* H1,
-                                  void* H2, void* g, hipStream_t st, const ProfHook& ph, bool lr_done) {
-#define NTU_MIX(P, C) return env_heavy<P, C>(batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, qs, hs, H0, H1, H2, g, st, ph, lr_done)
+                                  void* H2, void* g, hipStream_t st, const ProfHook& ph) {
+#define NTU_MIX(P, C) return env_heavy<P, C>(batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, qs, hs, H0, H1, H2, g, st, ph)
   if (precision == NTU_PREC_BF16X3) { if (cplx) NTU_MIX(NTU_PREC_BF16X3, true); NTU_MIX(NTU_PREC_BF16X3, false); }
   if (precision == NTU_PREC_BF16X6) { if (cplx) NTU_MIX(NTU_PREC_BF16X6, true); NTU_MIX(NTU_PREC_BF16X6, false); }
   // FP16X3 needs operand scales; not wired into the environment yet

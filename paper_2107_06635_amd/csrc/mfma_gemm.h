@@ -23,16 +23,18 @@ struct GemmNT {
 hipError_t launch_env_heavy_mixed(bool cplx, int precision, int batch, int p, int D, int R, const void* QXe,
                                   const void* QXp, const void* QYe, const void* QYp, const void* ETT,
                                   const void* EBT, long long es, long long qs, long long hs, void* H0, void* H1,
-                                  void* H2, void* g, hipStream_t st, const struct ProfHook& ph, bool lr_done);
+                                  void* H2, void* g, hipStream_t st, const struct ProfHook& ph);
 
-// Fused L1 / L2 products of the environment (complex, BF16x3 or BF16x6,
-// D^2 <= 64): H holds the Left blocks (FP32 pairs, item stride hs complex
-// elements) and receives the L2 blocks in place; frag: e45_frag_bytes of
-// scratch for the prepared EtopT / EbotT operands.
+// Environment products fused per (item, a, a') block on the matrix cores
+// (complex, BF16x3 or BF16x6, D^2 <= 64): Right into H2, L2 (from Left, L1
+// formed and consumed in shared memory) into H0; H1 holds the prepared
+// EtopT / EbotT operands (e45_frag_bytes).  Item stride hs complex elements.
 bool e45_supported(bool cplx, int precision, int D);
 size_t e45_frag_bytes(int precision, int batch, int D);
-hipError_t launch_e45(int precision, int batch, int D, int R, const void* ETT, const void* EBT, long long es, void* H,
-                      long long hs, void* frag, hipStream_t st);
+hipError_t launch_env_fused(int precision, int batch, int p, int D, int R, const void* QXe, const void* QXp,
+                            const void* QYe, const void* QYp, const void* ETT, const void* EBT, long long es,
+                            long long qs, void* H0, void* H1, void* H2, long long hs, hipStream_t st,
+                            const struct ProfHook& ph);
 
 // bytes of FP64 split-K partial sums the final assembly needs after H2
 size_t mixed_partial_bytes(bool cplx, int batch, int R, int D);
