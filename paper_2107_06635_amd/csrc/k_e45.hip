@@ -61,12 +61,13 @@ __global__ void __launch_bounds__(256) k_e45_prep(int n, int npad, const cd* __r
   }
 }
 
-struct alignas(4) bf16pair { __bf16 v[2]; };
-
 // Per-wave pieces shared by the kernels below.  A product's output tile
 // of NPAD rows x 2 NPAD real columns is split over NPAD / 16 waves: wave w
 // owns real columns [32 w, 32 w + 32) (two 16-wide MFMA tiles, y = 0, 1) of
-// every row tile mt; acc[c][mt][y] holds the term class c.
+// every row tile mt; acc[c][mt][y] holds the term class c.  The MFMA runs
+// with the operands exchanged (it computes the transposed tile), so that
+// lane l holds row 16 mt + l % 16 and the four consecutive real columns
+// 32 w + 16 y + 4 (l / 16) + v: two whole complex outputs.
 template <int PREC, int NPAD> struct E45 {
   static constexpr int NP = SplitTraits<PREC>::NT;
   static constexpr int NACC = (PREC == NTU_PREC_BF16X6) ? 3 : 2;
@@ -74,36 +75,39 @@ template <int PREC, int NPAD> struct E45 {
   static constexpr int LD = 2 * NPAD + 8;
   using Acc = f32x4[NACC][MT][2];
 
-  static NTU_DEV void zero(Acc& acc) {
-#pragma unroll
-    for (int c = 0; c < NACC; ++c)
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) acc[c][mt][y] = f32x4{0, 0, 0, 0};
+  static NTU_DEV f32x4 mf(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a, c, 0, 0, 0);
   }
 
   // the piece products kept, by term class: BF16x3 (hi, lo): hi hi |
   // hi lo + lo hi; BF16x6 (hi, mid, lo): hi hi | hi mid + mid hi |
-  // hi lo + mid mid + lo hi
+  // hi lo + mid mid + lo hi.  FIRST: the accumulators start from zero.
+  template <bool FIRST>
   static NTU_DEV void mma(Acc& acc, int mt, int y, const bf16x8 (&a)[NP], const bf16x8 (&b)[NP]) {
-    acc[0][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc[0][mt][y], 0, 0, 0);
-    acc[1][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc[1][mt][y], 0, 0, 0);
-    acc[1][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc[1][mt][y], 0, 0, 0);
+    constexpr f32x4 z = {0, 0, 0, 0};
+    acc[0][mt][y] = mf(a[0], b[0], FIRST ? z : acc[0][mt][y]);
+    acc[1][mt][y] = mf(a[0], b[1], FIRST ? z : acc[1][mt][y]);
+    acc[1][mt][y] = mf(a[1], b[0], acc[1][mt][y]);
     if constexpr (NACC == 3) {
-      acc[2][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], acc[2][mt][y], 0, 0, 0);
-      acc[2][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], acc[2][mt][y], 0, 0, 0);
-      acc[2][mt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], acc[2][mt][y], 0, 0, 0);
+      acc[2][mt][y] = mf(a[0], b[2], FIRST ? z : acc[2][mt][y]);
+      acc[2][mt][y] = mf(a[1], b[1], acc[2][mt][y]);
+      acc[2][mt][y] = mf(a[2], b[0], acc[2][mt][y]);
     }
   }
 
   static NTU_DEV void split8(const float (&x)[8], bf16x8 (&f)[NP]) {
+    unsigned w[NP][4];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      __bf16 t[NP];
-      split_value<PREC>(x[e], t);
+    for (int h = 0; h < 4; ++h) {
+      unsigned t[NP];
+      split_pair<PREC>(x[2 * h], x[2 * h + 1], t);
 #pragma unroll
-      for (int p = 0; p < NP; ++p) f[p][e] = t[p];
+      for (int p = 0; p < NP; ++p) w[p][h] = t[p];
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+      f[p] = __builtin_bit_cast(bf16x8, (u32x4){w[p][0], w[p][1], w[p][2], w[p][3]});
     }
   }
 
@@ -113,7 +117,6 @@ template <int PREC, int NPAD> struct E45 {
   // lane % 16 of the embedding of conj(Qp).
   static NTU_DEV void pair_product(Acc& acc, const cd* __restrict__ Qe, const cd* __restrict__ Qp, int n, int K,
                                    int w, int lane) {
-    zero(acc);
     const int KQ = (K + 15) / 16;
     for (int kq = 0; kq < KQ; ++kq) {
       const int s0 = 16 * kq + 4 * (lane >> 4);
@@ -141,22 +144,25 @@ template <int PREC, int NPAD> struct E45 {
         for (int h = 0; h < 4; ++h) {
           const bool ok = u < n && s0 + h < K;
           const cd z = Qe[ok ? (size_t)u * K + s0 + h : 0];
-          const float re = ok ? (float)z.x : 0.0f, im = ok ? (float)z.y : 0.0f;
-          x[2 * h] = re;
-          x[2 * h + 1] = im;
+          x[2 * h] = ok ? (float)z.x : 0.0f;
+          x[2 * h + 1] = ok ? (float)z.y : 0.0f;
         }
         bf16x8 a[NP];
         split8(x, a);
+        if (kq == 0) {
 #pragma unroll
-        for (int y = 0; y < 2; ++y) mma(acc, mt, y, a, b[y]);
+          for (int y = 0; y < 2; ++y) mma<true>(acc, mt, y, a, b[y]);
+        } else {
+#pragma unroll
+          for (int y = 0; y < 2; ++y) mma<false>(acc, mt, y, a, b[y]);
+        }
       }
     }
   }
 
-  // acc += A B^T with A from the shared pieces sA (NPAD rows, 2 NPAD real
+  // acc = A B^T with A from the shared pieces sA (NPAD rows, 2 NPAD real
   // columns) and B from prepared fragments F (layout of k_e45_prep)
   static NTU_DEV void product(Acc& acc, const __bf16 (*sA)[NPAD][LD], const __bf16* __restrict__ F, int w, int lane) {
-    zero(acc);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       bf16x8 b[2][NP];
@@ -171,19 +177,18 @@ template <int PREC, int NPAD> struct E45 {
 #pragma unroll
         for (int p = 0; p < NP; ++p) a[p] = *(const bf16x8*)&sA[p][16 * mt + (lane & 15)][32 * ks + 8 * (lane >> 4)];
 #pragma unroll
-        for (int y = 0; y < 2; ++y) mma(acc, mt, y, a, b[y]);
+        for (int y = 0; y < 2; ++y) {
+          if (ks == 0) mma<true>(acc, mt, y, a, b[y]);
+          else mma<false>(acc, mt, y, a, b[y]);
+        }
       }
     }
   }
 
-  // Hands each complex output to fn(row, column, re, im).  Lanes 2i and
-  // 2i + 1 hold the real and imaginary parts of one complex column; one
-  // exchange (DPP quad_perm [1,0,3,2]) gives the even lane both parts of
-  // rows v = 0, 2 and the odd lane those of rows v = 1, 3.  The term
-  // classes are summed in FP32 (smallest first): the result is the FP32
-  // rounding of their sum up to one unit in the last place.
+  // Hands each complex output to fn(row, column, re, im); the term classes
+  // are summed in FP32 (smallest first): the FP32 rounding of their exact
+  // sum up to one unit in the last place.
   template <class Fn> static NTU_DEV void outputs(const Acc& acc, int w, int lane, Fn fn) {
-    const bool odd = lane & 1;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -195,29 +200,35 @@ template <int PREC, int NPAD> struct E45 {
           if constexpr (NACC == 3) s = acc[2][mt][y][v] + s;
           x[v] = acc[0][mt][y][v] + s;
         }
-        const float r0 = swap_pair(odd ? x[0] : x[1]);
-        const float r1 = swap_pair(odd ? x[2] : x[3]);
-        const int col = (32 * w + 16 * y + (lane & 15)) >> 1;
-        const int row = 16 * mt + 4 * (lane >> 4) + (odd ? 1 : 0);
-        fn(row, col, odd ? r0 : x[0], odd ? x[1] : r0);
-        fn(row + 2, col, odd ? r1 : x[2], odd ? x[3] : r1);
+        const int row = 16 * mt + (lane & 15);
+        const int col = 16 * w + 8 * y + 2 * (lane >> 4);
+        fn(row, col, x[0], x[1]);
+        fn(row, col + 1, x[2], x[3]);
       }
   }
 
-  static NTU_DEV float swap_pair(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xf, 0xf, false));
+  // the same with both complex columns (col, col + 1) of a lane at once
+  template <class Fn> static NTU_DEV void outputs4(const Acc& acc, int w, int lane, Fn fn) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        float x[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float s = acc[1][mt][y][v];
+          if constexpr (NACC == 3) s = acc[2][mt][y][v] + s;
+          x[v] = acc[0][mt][y][v] + s;
+        }
+        fn(16 * mt + (lane & 15), 16 * w + 8 * y + 2 * (lane >> 4), x);
+      }
   }
 
   static NTU_DEV void store_pieces(__bf16 (*sA)[NPAD][LD], int row, int colc, float re, float im) {
-    __bf16 tr[NP], ti[NP];
-    split_value<PREC>(re, tr);
-    split_value<PREC>(im, ti);
+    unsigned t[NP];
+    split_pair<PREC>(re, im, t);
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      bf16pair v;
-      v.v[0] = tr[p]; v.v[1] = ti[p];
-      *(bf16pair*)&sA[p][row][2 * colc] = v;
-    }
+    for (int p = 0; p < NP; ++p) *(unsigned*)&sA[p][row][2 * colc] = t[p];
   }
 };
 
@@ -269,9 +280,16 @@ __global__ void __launch_bounds__(NPAD * 4, 2) k_left_e45(int R, int K, int nwor
   __syncthreads();
   S::product(acc, sA, F2, w, lane);
   float* O = out + ((size_t)item * hs + (size_t)(q % R2) * n * n) * 2;
-  S::outputs(acc, w, lane, [&](int j, int k, float re, float im) {
-    if (j < n && k < n) *(float2*)&O[2 * ((size_t)j * n + k)] = make_float2(re, im);
-  });
+  if constexpr (n % 2 == 0) {
+    // columns come in even-odd pairs: one 16-byte store per pair (n even keeps it aligned)
+    S::outputs4(acc, w, lane, [&](int j, int k, const float (&x)[4]) {
+      if (j < n && k < n) *(float4*)&O[2 * ((size_t)j * n + k)] = make_float4(x[0], x[1], x[2], x[3]);
+    });
+  } else {
+    S::outputs(acc, w, lane, [&](int j, int k, float re, float im) {
+      if (j < n && k < n) *(float2*)&O[2 * ((size_t)j * n + k)] = make_float2(re, im);
+    });
+  }
 }
 
 // One workgroup per (item, B, B'):

@@ -40,6 +40,27 @@ NTU_DEV void split_value(float x, typename SplitTraits<PREC>::E* out) {
   }
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Split of two values at once (BF16 precisions): piece p of (x0, x1) as one
+// packed word (x0 in the low half).  One packed conversion per piece; the
+// FP32 value of a piece is its bits shifted or masked into place.
+template <int PREC>
+NTU_DEV void split_pair(float x0, float x1, unsigned* out) {
+  static_assert(PREC == NTU_PREC_BF16X3 || PREC == NTU_PREC_BF16X6, "bfloat16 pieces only");
+  constexpr int NT = SplitTraits<PREC>::NT;
+#pragma unroll
+  for (int p = 0; p < NT; ++p) {
+    const unsigned w = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){x0, x1}, bf16x2));
+    out[p] = w;
+    if (p + 1 < NT) {
+      x0 -= __builtin_bit_cast(float, w << 16);
+      x1 -= __builtin_bit_cast(float, w & 0xffff0000u);
+    }
+  }
+}
+
 template <int PREC>
 NTU_DEV f32x4 mfma(const typename SplitTraits<PREC>::E* a, const typename SplitTraits<PREC>::E* b, f32x4 c) {
   if constexpr (PREC == NTU_PREC_FP16X3) {
