@@ -46,7 +46,29 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=1)
     ap.add_argument("--bucket", type=int, default=0,
                     help="batched workload: only the items of this bond dimension (0 = all 256)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (20 times) and print its "
+                         "rate: the reference kernel for scaling HBM byte counters")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """A plain copy of known size (read mib MiB, write mib MiB per launch)."""
+    import torch
+    n = mib * 2 ** 20 // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(20):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / 20
+    print(json.dumps({"copy_mib": mib, "bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4,
+                      "avg_launch_us": ms * 1e3, "rate_GBps": 2 * n * 4 / (ms * 1e-3) / 1e9}))
 
 
 def fit_flops(R, Dn, half_steps, cplx):
@@ -118,9 +140,12 @@ def build_thermal(ntu, inputs, dev, torch, np, D=8):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); a multi-GPU run is not part of this build",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the bond updates of a step are "
+              "independent, and the multi-GPU layout is described but not run", file=sys.stderr)
         sys.exit(2)
+    if args.copy_mib:
+        copy_calibration(args.copy_mib)
+        return
     import numpy as np
     import torch
     from paper_2107_06635_amd import inputs

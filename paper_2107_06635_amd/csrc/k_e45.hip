@@ -64,13 +64,15 @@ __global__ void __launch_bounds__(256) k_e45_prep(int n, int npad, const cd* __r
 // Per-wave pieces shared by the kernels below.  A product's output tile
 // of NPAD rows x 2 NPAD real columns is split over NPAD / 16 waves: wave w
 // owns real columns [32 w, 32 w + 32) (two 16-wide MFMA tiles, y = 0, 1) of
-// every row tile mt; acc[c][mt][y] holds the term class c.  The MFMA runs
+// every row tile mt.  acc[0][mt][y] accumulates the hi x hi piece products,
+// acc[1][mt][y] all smaller ones (their sum is at most 2^-7 of the first, so
+// its FP32 rounding is far below that of the result).  The MFMA runs
 // with the operands exchanged (it computes the transposed tile), so that
 // lane l holds row 16 mt + l % 16 and the four consecutive real columns
 // 32 w + 16 y + 4 (l / 16) + v: two whole complex outputs.
 template <int PREC, int NPAD> struct E45 {
   static constexpr int NP = SplitTraits<PREC>::NT;
-  static constexpr int NACC = (PREC == NTU_PREC_BF16X6) ? 3 : 2;
+  static constexpr int NACC = 2;
   static constexpr int MT = NPAD / 16, KS = NPAD / 16;
   static constexpr int LD = 2 * NPAD + 8;
   using Acc = f32x4[NACC][MT][2];
@@ -79,20 +81,21 @@ template <int PREC, int NPAD> struct E45 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a, c, 0, 0, 0);
   }
 
-  // the piece products kept, by term class: BF16x3 (hi, lo): hi hi |
-  // hi lo + lo hi; BF16x6 (hi, mid, lo): hi hi | hi mid + mid hi |
-  // hi lo + mid mid + lo hi.  FIRST: the accumulators start from zero.
+  // the piece products kept: BF16x3 (hi, lo): hi hi | lo hi + hi lo;
+  // BF16x6 (hi, mid, lo): hi hi | lo hi + mid mid + hi lo + mid hi + hi mid
+  // (smallest first).  FIRST: the accumulators start from zero.
   template <bool FIRST>
   static NTU_DEV void mma(Acc& acc, int mt, int y, const bf16x8 (&a)[NP], const bf16x8 (&b)[NP]) {
     constexpr f32x4 z = {0, 0, 0, 0};
     acc[0][mt][y] = mf(a[0], b[0], FIRST ? z : acc[0][mt][y]);
-    acc[1][mt][y] = mf(a[0], b[1], FIRST ? z : acc[1][mt][y]);
-    acc[1][mt][y] = mf(a[1], b[0], acc[1][mt][y]);
-    if constexpr (NACC == 3) {
-      acc[2][mt][y] = mf(a[0], b[2], FIRST ? z : acc[2][mt][y]);
-      acc[2][mt][y] = mf(a[1], b[1], acc[2][mt][y]);
-      acc[2][mt][y] = mf(a[2], b[0], acc[2][mt][y]);
+    f32x4 t = FIRST ? z : acc[1][mt][y];
+    if constexpr (NP == 3) {
+      t = mf(a[2], b[0], t);
+      t = mf(a[1], b[1], t);
+      t = mf(a[0], b[2], t);
     }
+    t = mf(a[1], b[0], t);
+    acc[1][mt][y] = mf(a[0], b[1], t);
   }
 
   static NTU_DEV void split8(const float (&x)[8], bf16x8 (&f)[NP]) {
@@ -185,9 +188,8 @@ template <int PREC, int NPAD> struct E45 {
     }
   }
 
-  // Hands each complex output to fn(row, column, re, im); the term classes
-  // are summed in FP32 (smallest first): the FP32 rounding of their exact
-  // sum up to one unit in the last place.
+  // Hands each complex output to fn(row, column, re, im), the two
+  // accumulators summed in FP32.
   template <class Fn> static NTU_DEV void outputs(const Acc& acc, int w, int lane, Fn fn) {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -195,11 +197,7 @@ template <int PREC, int NPAD> struct E45 {
       for (int y = 0; y < 2; ++y) {
         float x[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          float s = acc[1][mt][y][v];
-          if constexpr (NACC == 3) s = acc[2][mt][y][v] + s;
-          x[v] = acc[0][mt][y][v] + s;
-        }
+        for (int v = 0; v < 4; ++v) x[v] = acc[0][mt][y][v] + acc[1][mt][y][v];
         const int row = 16 * mt + (lane & 15);
         const int col = 16 * w + 8 * y + 2 * (lane >> 4);
         fn(row, col, x[0], x[1]);
@@ -215,11 +213,7 @@ template <int PREC, int NPAD> struct E45 {
       for (int y = 0; y < 2; ++y) {
         float x[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          float s = acc[1][mt][y][v];
-          if constexpr (NACC == 3) s = acc[2][mt][y][v] + s;
-          x[v] = acc[0][mt][y][v] + s;
-        }
+        for (int v = 0; v < 4; ++v) x[v] = acc[0][mt][y][v] + acc[1][mt][y][v];
         fn(16 * mt + (lane & 15), 16 * w + 8 * y + 2 * (lane >> 4), x);
       }
   }
