@@ -137,7 +137,15 @@ def build_thermal(ntu, inputs, dev, torch, np, D=8):
     return job
 
 
+# The batched workload runs one stream per bond-dimension bucket (six) next to
+# the main stream; HIP maps streams onto GPU_MAX_HW_QUEUES hardware queues
+# (default 4), and streams that share a queue serialise.  Ask for enough
+# queues before the runtime starts.
+HW_QUEUES = 8
+
+
 def main():
+    os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the bond updates of a step are "
@@ -214,7 +222,8 @@ def main():
                             "items": upd, "D_counts": {str(bk["D"]): bk["n"] for bk in job.buckets},
                             "h_x": "uniform [2.5, 3.5]", "dt": 0.01, "env_precision": args.precision,
                             "fit": "fp64, <=20 ALS iterations, early stop 1e-12 N",
-                            "storage": "values drawn as complex64, hot path in complex128"}
+                            "storage": "values drawn as complex64, hot path in complex128",
+                            "streams": f"one per D bucket, {HW_QUEUES} hardware queues"}
     else:
         result["config"] = {"workload": "configuration 3: thermal purification, D=8, p=4, real", "D": 8,
                             "h_x": 2.5, "dbeta": 0.005, "env_precision": args.precision,
