@@ -12,7 +12,7 @@ namespace {
 
 struct Persist {
   // per-item persistent buffers of the Trotter step (compute type elements)
-  long long QX, QY, RX, RY, g, MX, MY, rA, rB, GA, GB, cert;
+  long long QX, QY, RX, RY, g, MX, MY, rA, rB, GA, GB, cert, guess;
 };
 
 }  // namespace
@@ -23,6 +23,9 @@ struct ntu_ctx {
   bool cplx = true;
   int d = 2, na = 1, rg = 2, max_D = 1, max_batch = 1;
   hipStream_t stream = nullptr;
+  // side stream of the Trotter step (default priority) and its fork / join events
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   char* ws = nullptr;          // scratch of one call
   size_t ws_bytes = 0;
   char* step = nullptr;        // buffers of the Trotter step
@@ -98,12 +101,14 @@ Persist persist_layout(int p, int D, int rg, int d) {
   s.GA = o; o += (long long)d * d * rg;
   s.GB = o; o += (long long)d * d * rg;
   s.cert = o; o += 1;  // the metric repair's certificate for the fit (one double per item)
+  s.guess = o; o += ntu::svdu_guess_elems();  // the fit's SVDU guess, computed beside the environment
   (void)o;
   return s;
 }
 long long persist_elems(int p, int D, int rg, int d) {
   const long long R = (long long)D * rg, D3 = (long long)D * D * D;
-  return 2 * p * D3 * R + 2 * R * R + R * R * R * R + 2 * R * D + 2 * p * D3 * D + 2LL * d * d * rg + 1;
+  return 2 * p * D3 * R + 2 * R * R + R * R * R * R + 2 * R * D + 2 * p * D3 * D + 2LL * d * d * rg + 1 +
+         ntu::svdu_guess_elems();
 }
 
 const int PROF_CAP = 1 << 15;
@@ -207,10 +212,16 @@ ntu_status ntu_ctx_create(ntu_ctx** out, int device, int dtype, int d, int d_anc
   c->step_bytes = (size_t)persist_elems(p, max_D, r_g, d) * elem_size(c) * max_batch + 256;
   hipError_t e = hipMalloc((void**)&c->ws, c->ws_bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&c->step, c->step_bytes);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
   if (e != hipSuccess) {
     if (c->ws) (void)hipFree(c->ws);
+    if (c->step) (void)hipFree(c->step);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     delete c;
-    return fail(nullptr, NTU_ERR_HIP, std::string("workspace allocation failed: ") + hipGetErrorString(e));
+    return fail(nullptr, NTU_ERR_HIP, std::string("context set-up failed: ") + hipGetErrorString(e));
   }
   *out = c;
   return NTU_OK;
@@ -221,6 +232,9 @@ ntu_status ntu_ctx_destroy(ntu_ctx* c) {
   DeviceGuard guard(c->device);
   if (c->ws) (void)hipFree(c->ws);
   if (c->step) (void)hipFree(c->step);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
   delete c;
   return NTU_OK;
@@ -358,6 +372,7 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
   char* rA = buf(L.rA);
   char* rB = buf(L.rB);
   double* cert = (double*)buf(L.cert);
+  char* guess = buf(L.guess);
   (void)pe;
   const long long gfs = (long long)c->d * c->d * c->rg;  // elements of one factor
   const long long gf_item = 8 * gfs;                      // 4 bonds x (GA, GB)
@@ -391,6 +406,12 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     NTU_STEP(ntu::launch_reduce_qr(cp, c->dtype, batch, c->d, c->na, D, c->rg, Y, gB, gf_item, 1, QY, RY, opts->fit.kappa,
                                    (int*)c->ws, c->stream), "reduce_qr Y");
     ph(ntu::PK_REDUCE, 1);
+    // the fit's SVDU guess needs only RX, RY: it runs on the side stream while
+    // the environment is contracted, and the fit waits for it
+    NTU_STEP(hipEventRecord(c->ev_fork, c->stream), "fork");
+    NTU_STEP(hipStreamWaitEvent(c->aux, c->ev_fork, 0), "fork");
+    NTU_STEP(ntu::launch_svdu_guess(cp, batch, D, R, RX, RY, opts->fit.kappa, guess, c->aux), "svdu_guess");
+    NTU_STEP(hipEventRecord(c->ev_join, c->aux), "join");
     const void* nbr[6] = {Y, Y, Y, X, X, X};
     e = ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, QX, QY, nbr, G, c->ws, c->ws_bytes, c->stream, ph);
     if (e == hipErrorNotSupported) return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
@@ -403,8 +424,9 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     NTU_STEP(ntu::launch_metric_fix(cp, batch, R * R, G, opts->fix_mode, sb, (int)s_item, c->ws, c->stream, ph,
                                     clip ? shift : 0.0, clip ? cert : nullptr),
              "metric_fix");
+    NTU_STEP(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join");
     NTU_STEP(ntu::launch_bond_fit(cp, batch, D, R, G, RX, RY, fp, MX, MY, sb ? sb + 8 : nullptr, (int)s_item, c->ws,
-                                  c->stream, ph, clip ? cert : nullptr), "bond_fit");
+                                  c->stream, ph, clip ? cert : nullptr, guess), "bond_fit");
     // new X -> (A or B), new Y -> the other, rotated back for vertical bonds
     void* outX = x_is_a ? A : B;
     void* outY = x_is_a ? B : A;

@@ -20,6 +20,7 @@ namespace ntu {
 
 constexpr int FIT_THREADS = 512;
 constexpr int FIT_RMAX = 20;
+static_assert(svdu_guess_elems() == 2 * FIT_RMAX * FIT_RMAX + 1, "guess layout");
 
 
 // per-item global workspace (elements of T)
@@ -688,11 +689,70 @@ NTU_DEV bool fast_solve(T* gs, int R, int Dn, int half, const T* Q, const FitSha
   return true;
 }
 
+// SVDU guess (Fig. 2(c,d)): P = RX RY^T = U S V^H (one-sided Jacobi),
+// Dn = min(D, #{S_j > kappa S_0}), MX = U S^1/2, MY = conj(V) S^1/2, row-major
+// R x FIT_RMAX and zero beyond column Dn.  Leaves vec(P) (row-major) in y;
+// sa, sv (FIT_RMAX^2) and s (FIT_RMAX) are scratch.  Whole block; returns Dn.
+template <class T>
+NTU_DEV int svdu_guess_dev(int D, int R, const T* RXi, const T* RYi, double kappa, T* y, T* sa, T* sv, double* s,
+                           T* MX, T* MY, int* flag) {
+  const int tid = threadIdx.x, n = R * R;
+  for (int e = tid; e < n; e += blockDim.x) {
+    int a = e / R, b = e % R;
+    T v = zerov<T>();
+    for (int k = 0; k < R; ++k) v += RXi[a * R + k] * RYi[b * R + k];
+    y[e] = v;
+    sa[a + b * FIT_RMAX] = v;
+  }
+  __syncthreads();
+  svd_block_small<T>(sa, R, R, FIT_RMAX, sv, FIT_RMAX, s, flag);
+  const double s0 = s[0];
+  int Dn = 0;
+  if (s0 > 0)
+    for (int j = 0; j < R && Dn < D; ++j)
+      if (s[j] > kappa * s0) ++Dn;
+  // columns of sa are U s
+  for (int e = tid; e < R * FIT_RMAX; e += blockDim.x) {
+    int a = e / FIT_RMAX, j = e % FIT_RMAX;
+    T mx = zerov<T>(), my = zerov<T>();
+    if (j < Dn) {
+      double sq = sqrt(s[j]);
+      mx = sa[a + j * FIT_RMAX] * (1.0 / sq);
+      my = conjv(sv[a + j * FIT_RMAX]) * sq;
+    }
+    MX[e] = mx;
+    MY[e] = my;
+  }
+  __syncthreads();
+  return Dn;
+}
+
+// The SVDU guess of every item, for a fit launched later (one block per item).
+// guess[item]: MX (FIT_RMAX^2 elements, row-major R x FIT_RMAX), MY (the
+// same), then Dn as the real part of one element.
+template <class T>
+__global__ void __launch_bounds__(FIT_THREADS) k_svdu_guess(int D, int R, const T* __restrict__ RX,
+                                                            const T* __restrict__ RY, double kappa, T* guess) {
+  __shared__ T y[FIT_RMAX * FIT_RMAX], sa[FIT_RMAX * FIT_RMAX], sv[FIT_RMAX * FIT_RMAX];
+  __shared__ T MX[FIT_RMAX * FIT_RMAX], MY[FIT_RMAX * FIT_RMAX];
+  __shared__ double s[FIT_RMAX];
+  __shared__ int flag;
+  const int it = blockIdx.x, n = R * R;
+  const int Dn = svdu_guess_dev<T>(D, R, RX + (size_t)it * n, RY + (size_t)it * n, kappa, y, sa, sv, s, MX, MY, &flag);
+  T* gi = guess + (size_t)it * svdu_guess_elems();
+  for (int e = threadIdx.x; e < R * FIT_RMAX; e += blockDim.x) {
+    gi[e] = MX[e];
+    gi[FIT_RMAX * FIT_RMAX + e] = MY[e];
+  }
+  if (threadIdx.x == 0) gi[2 * FIT_RMAX * FIT_RMAX] = realv<T>((double)Dn);
+}
+
 template <class T>
 __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T* __restrict__ g,
                                                           const T* __restrict__ RX, const T* __restrict__ RY,
                                                           FitParams fp, T* MXo, T* MYo, double* stats,
-                                                          int stats_stride, T* ws, const double* cert) {
+                                                          int stats_stride, T* ws, const double* cert,
+                                                          const T* __restrict__ guess) {
   extern __shared__ double shmem[];
   __shared__ int flag;
   const int it = blockIdx.x, tid = threadIdx.x;
@@ -780,32 +840,24 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
     t_mark = t;
   };
 
-  // P = RX RY^T  (column-major copy in sa for the SVD, row-major y = vec(P))
-  for (int e = tid; e < n; e += blockDim.x) {
-    int a = e / R, b = e % R;
-    T v = zerov<T>();
-    for (int k = 0; k < R; ++k) v += RX[(size_t)it * n + a * R + k] * RY[(size_t)it * n + b * R + k];
-    S.y[e] = v;
-    S.sa[a + b * FIT_RMAX] = v;
-  }
-  __syncthreads();
-  svd_block_small<T>(S.sa, R, R, FIT_RMAX, S.sv, FIT_RMAX, S.s, &flag);
-  const double s0 = S.s[0];
-  int Dn = 0;
-  if (s0 > 0)
-    for (int j = 0; j < R && Dn < D; ++j)
-      if (S.s[j] > kappa * s0) ++Dn;
-  // SVDU: MX = U S^1/2 (columns of sa are U s), MY = conj(V) S^1/2
-  for (int e = tid; e < R * FIT_RMAX; e += blockDim.x) {
-    int a = e / FIT_RMAX, j = e % FIT_RMAX;
-    T mx = zerov<T>(), my = zerov<T>();
-    if (j < Dn) {
-      double sq = sqrt(S.s[j]);
-      mx = S.sa[a + j * FIT_RMAX] * (1.0 / sq);
-      my = conjv(S.sv[a + j * FIT_RMAX]) * sq;
+  int Dn;
+  if (guess) {
+    // the SVDU guess was computed beforehand (k_svdu_guess): read it, form y
+    const T* gi = guess + (size_t)it * svdu_guess_elems();
+    for (int e = tid; e < R * FIT_RMAX; e += blockDim.x) {
+      S.MX[e] = gi[e];
+      S.MY[e] = gi[FIT_RMAX * FIT_RMAX + e];
     }
-    S.MX[e] = mx;
-    S.MY[e] = my;
+    for (int e = tid; e < n; e += blockDim.x) {
+      int a = e / R, b = e % R;
+      T v = zerov<T>();
+      for (int k = 0; k < R; ++k) v += RX[(size_t)it * n + a * R + k] * RY[(size_t)it * n + b * R + k];
+      S.y[e] = v;
+    }
+    Dn = (int)rev(gi[2 * FIT_RMAX * FIT_RMAX]);
+  } else {
+    Dn = svdu_guess_dev<T>(D, R, RX + (size_t)it * n, RY + (size_t)it * n, kappa, S.y, S.sa, S.sv, S.s, S.MX, S.MY,
+                           &flag);
   }
   // g y and N
   __syncthreads();
@@ -1022,7 +1074,7 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
 
 hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, const void* RX, const void* RY,
                            const FitParams& fp, void* MX, void* MY, double* stats, int stats_stride, void* ws,
-                           hipStream_t st, const ProfHook& ph, const double* cert) {
+                           hipStream_t st, const ProfHook& ph, const double* cert, const void* guess) {
   if (batch <= 0) return hipSuccess;
   if (R > FIT_RMAX || D > FIT_RMAX || R * D > 256) return hipErrorInvalidValue;
   size_t el = cplx ? 16 : 8;
@@ -1042,12 +1094,25 @@ hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, co
   if (shm > 160 * 1024 - 16 * 1024) return hipErrorInvalidValue;
   if (cplx)
     hipLaunchKernelGGL(k_bond_fit<cd>, dim3(batch), dim3(FIT_THREADS), shm, st, D, R, (const cd*)g, (const cd*)RX,
-                       (const cd*)RY, fp, (cd*)MX, (cd*)MY, stats, stats_stride, (cd*)ws, cert);
+                       (const cd*)RY, fp, (cd*)MX, (cd*)MY, stats, stats_stride, (cd*)ws, cert, (const cd*)guess);
   else
     hipLaunchKernelGGL(k_bond_fit<double>, dim3(batch), dim3(FIT_THREADS), shm, st, D, R, (const double*)g,
                        (const double*)RX, (const double*)RY, fp, (double*)MX, (double*)MY, stats, stats_stride,
-                       (double*)ws, cert);
+                       (double*)ws, cert, (const double*)guess);
   ph(PK_FIT, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_svdu_guess(bool cplx, int batch, int D, int R, const void* RX, const void* RY, double kappa,
+                             void* guess, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  if (R > FIT_RMAX || D > FIT_RMAX) return hipErrorInvalidValue;
+  if (cplx)
+    hipLaunchKernelGGL(k_svdu_guess<cd>, dim3(batch), dim3(FIT_THREADS), 0, st, D, R, (const cd*)RX, (const cd*)RY,
+                       kappa, (cd*)guess);
+  else
+    hipLaunchKernelGGL(k_svdu_guess<double>, dim3(batch), dim3(FIT_THREADS), 0, st, D, R, (const double*)RX,
+                       (const double*)RY, kappa, (double*)guess);
   return hipGetLastError();
 }
 

@@ -65,8 +65,15 @@ struct FitParams {
 };
 size_t fit_workspace_bytes(bool cplx, int batch, int D, int R);
 NTU_HD int fit_stats_len(int n_iter, int D) { return 16 + 4 * n_iter + D; }
+// guess (may be NULL: the fit computes it): the SVDU guess of every item
+// from launch_svdu_guess with the same RX, RY, D and kappa
 hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, const void* RX, const void* RY,
                            const FitParams& fp, void* MX, void* MY, double* stats, int stats_stride, void* ws,
-                           hipStream_t st, const ProfHook& ph, const double* cert = nullptr);
+                           hipStream_t st, const ProfHook& ph, const double* cert = nullptr,
+                           const void* guess = nullptr);
+// elements (compute type) of one item's SVDU guess
+NTU_HD constexpr long long svdu_guess_elems() { return 2 * 20 * 20 + 1; }
+hipError_t launch_svdu_guess(bool cplx, int batch, int D, int R, const void* RX, const void* RY, double kappa,
+                             void* guess, hipStream_t st);
 
 }  // namespace ntu
