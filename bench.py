@@ -7,7 +7,9 @@ exp(-0.01 i h_b), random complex Gaussian site tensors (drawn as complex64).
 Items are grouped by D; one step = all 256 updates, each: gate split once at
 set-up, then reduce + QR, environment contraction (split precision on MFMA),
 metric repair (FP64), bond fit (FP64, <= 20 ALS iterations, early stop at
-1e-12 N), recombination.
+1e-12 N), recombination.  Each D bucket runs on its own stream (one context
+each); the buckets are independent, so the timed region forks them once,
+runs the K steps of every bucket back to back and joins them at the end.
 
 "thermal" (configuration 3): imaginary-time evolution of the D = 8 thermal
 purification (p = 4, real), one step = one Trotter sweep of 4 bond updates.
@@ -137,11 +139,12 @@ def build_thermal(ntu, inputs, dev, torch, np, D=8):
     return job
 
 
-# The batched workload runs one stream per bond-dimension bucket (six) next to
-# the main stream; HIP maps streams onto GPU_MAX_HW_QUEUES hardware queues
-# (default 4), and streams that share a queue serialise.  Ask for enough
-# queues before the runtime starts.
-HW_QUEUES = 8
+# The batched workload runs one stream per bond-dimension bucket (six), each
+# with the library's side stream, next to the main stream; HIP maps streams
+# onto GPU_MAX_HW_QUEUES hardware queues round-robin (default 4), and streams
+# that share a queue serialise.  Ask for enough queues before the runtime
+# starts.
+HW_QUEUES = 16
 
 
 def main():
@@ -169,22 +172,33 @@ def main():
     opts = ntu.step_opts(args.precision, order=job.order, **fit)
     opts64 = ntu.step_opts("f64", order=job.order, **fit)
 
-    def one_step(state, o, keep_stats):
-        # fork: every bucket stream waits for the main stream, join: the main stream waits for all
+    def steps_on_buckets(state, o, keep_stats, nsteps):
+        """nsteps steps of every bucket.  The buckets are independent: each
+        stream waits for the main stream once, runs its nsteps steps back to
+        back, and the main stream waits for all of them at the end (main is
+        an ordinary stream: work on the legacy null stream would wait for
+        every blocking stream of the device)."""
         main = torch.cuda.current_stream(dev)
-        out = []
-        for bk, (A, B) in zip(job.buckets, state):
+        assert main.cuda_stream != 0, "run the steps from a non-default stream"
+        for bk in job.buckets:
             bk["stream"].wait_stream(main)
-            with torch.cuda.stream(bk["stream"]):
-                out.append(ntu.ntu_trotter_step(bk["ctx"], A, B, bk["gf"], o, stats=keep_stats))
+        out = []
+        for _ in range(nsteps):
+            st = []
+            for bk, (A, B) in zip(job.buckets, state):
+                with torch.cuda.stream(bk["stream"]):
+                    st.append(ntu.ntu_trotter_step(bk["ctx"], A, B, bk["gf"], o, stats=keep_stats))
+            out.append(st)
         for bk in job.buckets:
             main.wait_stream(bk["stream"])
         return out
 
+    main_stream = torch.cuda.Stream(device=dev)
     # warm-up on the FP64 path so that both paths start from the same state
     state0 = [(bk["A"], bk["B"]) for bk in job.buckets]
-    for _ in range(W):
-        one_step(state0, opts64, False)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(main_stream):
+        steps_on_buckets(state0, opts64, False, W)
     torch.cuda.synchronize()
     init = [(A.clone(), B.clone()) for A, B in state0]
 
@@ -192,11 +206,10 @@ def main():
         state = [(A.clone(), B.clone()) for A, B in init]
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        stats = []
-        ev0.record()
-        for _ in range(steps):
-            stats.append(one_step(state, o, keep_stats))
-        ev1.record()
+        with torch.cuda.stream(main_stream):
+            ev0.record()
+            stats = steps_on_buckets(state, o, keep_stats, steps)
+            ev1.record()
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1), state, stats
 
