@@ -207,8 +207,8 @@ ntu_status ntu_ctx_create(ntu_ctx** out, int device, int dtype, int d, int d_anc
   const int p = d * d_anc;
   size_t sb = 0;
   for (int D = 1; D <= max_D; ++D) sb = std::max(sb, scratch_bytes(c->cplx, max_batch, p, D, r_g));
-  // the reduction's per-item path flags also live at the start of the workspace
-  c->ws_bytes = std::max(sb, (size_t)max_batch * sizeof(int) + 256);
+  // the reduction's per-item path flags (both sides) also live at the start of the workspace
+  c->ws_bytes = std::max(sb, 2 * (size_t)max_batch * sizeof(int) + 256);
   c->step_bytes = (size_t)persist_elems(p, max_D, r_g, d) * elem_size(c) * max_batch + 256;
   hipError_t e = hipMalloc((void**)&c->ws, c->ws_bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&c->step, c->step_bytes);
@@ -401,10 +401,8 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     const char* gA = (const char*)gate_factors + (size_t)(bond * 2 + 0) * gfs * el;
     const char* gB = (const char*)gate_factors + (size_t)(bond * 2 + 1) * gfs * el;
     ph(ntu::PK_REDUCE, 0);
-    NTU_STEP(ntu::launch_reduce_qr(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, gf_item, 0, QX, RX, opts->fit.kappa,
-                                   (int*)c->ws, c->stream), "reduce_qr X");
-    NTU_STEP(ntu::launch_reduce_qr(cp, c->dtype, batch, c->d, c->na, D, c->rg, Y, gB, gf_item, 1, QY, RY, opts->fit.kappa,
-                                   (int*)c->ws, c->stream), "reduce_qr Y");
+    NTU_STEP(ntu::launch_reduce_qr_pair(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, Y, gB, gf_item, QX, RX, QY, RY,
+                                        opts->fit.kappa, (int*)c->ws, c->stream), "reduce_qr");
     ph(ntu::PK_REDUCE, 1);
     // the fit's SVDU guess needs only RX, RY: it runs on the side stream while
     // the environment is contracted, and the fit waits for it

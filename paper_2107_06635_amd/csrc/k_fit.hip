@@ -67,16 +67,16 @@ template <class T> struct FitShared {
   double* vec;  // 64
 };
 
-// out = g v for a Hermitian n x n g (row-major), n <= blockDim.x:
+// out = g v for a Hermitian n x n g (row-major):
 //   out[r] = sum_c conj(g[c][r]) v[c].
-// Thread (r, part), r fastest, sums a contiguous range of c, so a wave reads
-// consecutive entries of each row of g; the parts meet in mv (blockDim.x
-// elements of shared memory).  Whole block.
+// Work item (r, part), r fastest, sums a contiguous range of c, so a wave
+// reads consecutive entries of each row of g; the parts meet in mv
+// (max(n, blockDim.x) elements of shared memory).  Whole block.
 template <class T>
 NTU_DEV void fit_matvec(const T* __restrict__ g, int n, const T* v, T* out, T* mv) {
-  const int tid = threadIdx.x, parts = (int)blockDim.x / n, cs = (n + parts - 1) / parts;
-  if (tid < parts * n) {
-    const int r = tid % n, part = tid / n;
+  const int tid = threadIdx.x, parts = max(1, (int)blockDim.x / n), cs = (n + parts - 1) / parts;
+  for (int wi = tid; wi < parts * n; wi += blockDim.x) {
+    const int r = wi % n, part = wi / n;
     const int c1 = min(n, (part + 1) * cs);
     T acc = zerov<T>();
     for (int c0 = part * cs; c0 < c1; c0 += 8) {
@@ -87,7 +87,7 @@ NTU_DEV void fit_matvec(const T* __restrict__ g, int n, const T* v, T* out, T* m
       for (int l = 0; l < 8; ++l)
         if (c0 + l < c1) acc += cmul(gv[l], v[c0 + l]);
     }
-    mv[tid] = acc;
+    mv[wi] = acc;
   }
   __syncthreads();
   for (int r = tid; r < n; r += blockDim.x) {

@@ -83,16 +83,28 @@ template <> NTU_DEV cd load_site<cd>(const float2* p, long long i) {
 constexpr int QR_THREADS = 256;
 constexpr int QR_RMAX = 32;
 
+// The Y side of a launch that reduces both sides of a bond at once
+// (grid.y = 2); unused with grid.y = 1.
+template <class T, class S> struct ReduceY {
+  const S* site;
+  const T* gf;
+  T* Q;
+  T* R;
+};
+
 template <class T, class S>
 __global__ void __launch_bounds__(QR_THREADS) k_reduce_qr(int d, int na, int D, int rg, const S* site,
                                                          const T* gf, long long gf_stride, int side, T* Q, T* Rm,
-                                                         double kappa, const int* todo) {
+                                                         double kappa, const int* todo, ReduceY<T, S> yside) {
   __shared__ double red[16 * 64];
   __shared__ double hv[2 * QR_RMAX];
   __shared__ double cacc[2 * QR_RMAX];
   constexpr int NC = is_cplx<T>::value ? 2 : 1;
-  const int it = blockIdx.x, tid = threadIdx.x;
-  if (todo && todo[it] == 0) return;  // done by the Cholesky QR
+  if (blockIdx.y == 1) {  // the Y side of a two-sided launch
+    site = yside.site; gf = yside.gf; Q = yside.Q; Rm = yside.R; side = 1;
+  }
+  const int it = blockIdx.x, tid = threadIdx.x, ti = blockIdx.y * gridDim.x + blockIdx.x;
+  if (todo && todo[ti] == 0) return;  // done by the Cholesky QR
   const int p = d * na, R = D * rg;
   const long long D2 = (long long)D * D, D3 = D2 * D, D4 = D3 * D;
   const long long nrow = p * D3;
@@ -238,7 +250,7 @@ NTU_DEV bool cqr_chol(const T* G, int n, double floor2, T* Rf, T* Ti) {
 template <class T, class S>
 __global__ void __launch_bounds__(CQR_THREADS) k_reduce_cholqr(int d, int na, int D, int rg, const S* site,
                                                               const T* gf, long long gf_stride, int side, T* Q,
-                                                              T* Rm, double kappa, int* todo) {
+                                                              T* Rm, double kappa, int* todo, ReduceY<T, S> yside) {
   __shared__ T ch[CQR_CH * CQR_LD];
   __shared__ T ch2[CQR_CH * CQR_LD];
   __shared__ T G[CQR_RMAX * CQR_RMAX];
@@ -247,10 +259,13 @@ __global__ void __launch_bounds__(CQR_THREADS) k_reduce_cholqr(int d, int na, in
   __shared__ T R2[CQR_RMAX * CQR_RMAX];
   __shared__ T T2[CQR_RMAX * CQR_RMAX];
   __shared__ int ok;
-  const int it = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  if (blockIdx.y == 1) {  // the Y side of a two-sided launch
+    site = yside.site; gf = yside.gf; Q = yside.Q; Rm = yside.R; side = 1;
+  }
+  const int it = blockIdx.x, tid = threadIdx.x, nt = blockDim.x, ti = blockIdx.y * gridDim.x + blockIdx.x;
   const int p = d * na, R = D * rg;
   if (R > CQR_RMAX) {
-    if (tid == 0) todo[it] = 1;
+    if (tid == 0) todo[ti] = 1;
     return;
   }
   const long long D2 = (long long)D * D, D3 = D2 * D, D4 = D3 * D;
@@ -333,7 +348,7 @@ __global__ void __launch_bounds__(CQR_THREADS) k_reduce_cholqr(int d, int na, in
   }
   __syncthreads();
   if (!ok) {
-    if (tid == 0) todo[it] = 1;
+    if (tid == 0) todo[ti] = 1;
     return;
   }
   __syncthreads();
@@ -345,7 +360,7 @@ __global__ void __launch_bounds__(CQR_THREADS) k_reduce_cholqr(int d, int na, in
   }
   __syncthreads();
   if (!ok) {
-    if (tid == 0) todo[it] = 1;
+    if (tid == 0) todo[ti] = 1;
     return;
   }
   // 3. Q = Q1 R2^{-1} (Gram not needed), R = R2 R1
@@ -356,34 +371,52 @@ __global__ void __launch_bounds__(CQR_THREADS) k_reduce_cholqr(int d, int na, in
     for (int l = i; l <= j; ++l) v += R2[i * CQR_RMAX + l] * R1[l * CQR_RMAX + j];
     Ri[e] = v;
   }
-  if (tid == 0) todo[it] = 0;
+  if (tid == 0) todo[ti] = 0;
+}
+
+template <class T, class S>
+static void reduce_launch(int batch, int sides, int d, int na, int D, int rg, const void* site, const void* gf,
+                          long long gf_stride, int side, void* Q, void* R, const void* site_y, const void* gf_y,
+                          void* Q_y, void* R_y, double kappa, int* todo, hipStream_t st) {
+  const ReduceY<T, S> y{(const S*)site_y, (const T*)gf_y, (T*)Q_y, (T*)R_y};
+  const dim3 g(batch, sides);
+  if (todo)
+    hipLaunchKernelGGL((k_reduce_cholqr<T, S>), g, dim3(CQR_THREADS), 0, st, d, na, D, rg, (const S*)site,
+                       (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, todo, y);
+  hipLaunchKernelGGL((k_reduce_qr<T, S>), g, dim3(QR_THREADS), 0, st, d, na, D, rg, (const S*)site, (const T*)gf,
+                     gf_stride, side, (T*)Q, (T*)R, kappa, (const int*)todo, y);
+}
+
+static hipError_t reduce_dispatch(bool cplx, int site_dtype, int batch, int sides, int d, int na, int D, int rg,
+                                  const void* site, const void* gf, long long gf_stride, int side, void* Q, void* R,
+                                  const void* site_y, const void* gf_y, void* Q_y, void* R_y, double kappa, int* todo,
+                                  hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  if (!cplx)
+    reduce_launch<double, double>(batch, sides, d, na, D, rg, site, gf, gf_stride, side, Q, R, site_y, gf_y, Q_y, R_y,
+                                  kappa, todo, st);
+  else if (site_dtype == 2)
+    reduce_launch<cd, float2>(batch, sides, d, na, D, rg, site, gf, gf_stride, side, Q, R, site_y, gf_y, Q_y, R_y,
+                              kappa, todo, st);
+  else
+    reduce_launch<cd, cd>(batch, sides, d, na, D, rg, site, gf, gf_stride, side, Q, R, site_y, gf_y, Q_y, R_y, kappa,
+                          todo, st);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_qr(bool cplx, int site_dtype, int batch, int d, int na, int D, int rg,
                             const void* site, const void* gf, long long gf_stride, int side, void* Q, void* R,
                             double kappa, int* todo, hipStream_t st) {
-  if (batch <= 0) return hipSuccess;
-  dim3 g(batch), b(QR_THREADS), bc(CQR_THREADS);
-  if (!cplx) {
-    if (todo)
-      hipLaunchKernelGGL((k_reduce_cholqr<double, double>), g, bc, 0, st, d, na, D, rg, (const double*)site,
-                         (const double*)gf, gf_stride, side, (double*)Q, (double*)R, kappa, todo);
-    hipLaunchKernelGGL((k_reduce_qr<double, double>), g, b, 0, st, d, na, D, rg, (const double*)site,
-                       (const double*)gf, gf_stride, side, (double*)Q, (double*)R, kappa, (const int*)todo);
-  } else if (site_dtype == 2) {
-    if (todo)
-      hipLaunchKernelGGL((k_reduce_cholqr<cd, float2>), g, bc, 0, st, d, na, D, rg, (const float2*)site,
-                         (const cd*)gf, gf_stride, side, (cd*)Q, (cd*)R, kappa, todo);
-    hipLaunchKernelGGL((k_reduce_qr<cd, float2>), g, b, 0, st, d, na, D, rg, (const float2*)site,
-                       (const cd*)gf, gf_stride, side, (cd*)Q, (cd*)R, kappa, (const int*)todo);
-  } else {
-    if (todo)
-      hipLaunchKernelGGL((k_reduce_cholqr<cd, cd>), g, bc, 0, st, d, na, D, rg, (const cd*)site, (const cd*)gf,
-                         gf_stride, side, (cd*)Q, (cd*)R, kappa, todo);
-    hipLaunchKernelGGL((k_reduce_qr<cd, cd>), g, b, 0, st, d, na, D, rg, (const cd*)site, (const cd*)gf,
-                       gf_stride, side, (cd*)Q, (cd*)R, kappa, (const int*)todo);
-  }
-  return hipGetLastError();
+  return reduce_dispatch(cplx, site_dtype, batch, 1, d, na, D, rg, site, gf, gf_stride, side, Q, R, nullptr, nullptr,
+                         nullptr, nullptr, kappa, todo, st);
+}
+
+hipError_t launch_reduce_qr_pair(bool cplx, int site_dtype, int batch, int d, int na, int D, int rg,
+                                 const void* siteX, const void* gfX, const void* siteY, const void* gfY,
+                                 long long gf_stride, void* QX, void* RX, void* QY, void* RY, double kappa, int* todo,
+                                 hipStream_t st) {
+  return reduce_dispatch(cplx, site_dtype, batch, 2, d, na, D, rg, siteX, gfX, gf_stride, 0, QX, RX, siteY, gfY, QY,
+                         RY, kappa, todo, st);
 }
 
 // ---------------------------------------------------------------------------

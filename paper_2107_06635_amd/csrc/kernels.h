@@ -25,6 +25,11 @@ hipError_t launch_gate_split(bool cplx, int batch, int d, int rg, const void* ga
 hipError_t launch_reduce_qr(bool cplx, int site_dtype, int batch, int d, int na, int D, int rg,
                             const void* site, const void* gf, long long gf_stride, int side, void* Q, void* R,
                             double kappa, int* todo, hipStream_t st);
+// both sides of a bond in one launch (X: side 0, Y: side 1); todo: 2 batch ints
+hipError_t launch_reduce_qr_pair(bool cplx, int site_dtype, int batch, int d, int na, int D, int rg,
+                                 const void* siteX, const void* gfX, const void* siteY, const void* gfY,
+                                 long long gf_stride, void* QX, void* RX, void* QY, void* RY, double kappa, int* todo,
+                                 hipStream_t st);
 hipError_t launch_recombine(bool cplx, int batch, int p, int D, int R, const void* QX, const void* QY,
                             const void* MX, const void* MY, void* Xn, void* Yn, int rot, hipStream_t st);
 hipError_t launch_rotate_cw(bool cplx, int batch, int p, int D, const void* src, void* dst, hipStream_t st);

@@ -438,17 +438,17 @@ NTU_DEV void blocked_chol_solve(const T* A, int n, int lda, T* b, T* x, T* dblk)
 // Gershgorin certification of g: every eigenvalue lies in the union of the
 // discs |lambda - g_ii| <= sum_{j != i} |g_ij|, so lo = min_i (g_ii - r_i)
 // bounds lambda_min from below and hi = max_i (g_ii + r_i) bounds lambda_max
-// from above.  Certified if lo > margin * hi.  Whole block; n <= blockDim.x;
-// red: >= blockDim.x doubles of shared memory.
+// from above.  Certified if lo > margin * hi.  Whole block; red: >=
+// max(n, blockDim.x) doubles of shared memory.
 template <class T>
 NTU_DEV bool gershgorin_certify(const T* __restrict__ G, int n, double margin, double* red) {
   // Hermitian G: the off-diagonal absolute row sum of row r equals that of
-  // column r, read with r fastest (coalesced).  Thread (r, part) sums a range
-  // of rows c; parts meet in red (n <= blockDim.x <= 1024).
-  const int tid = threadIdx.x, parts = (int)blockDim.x / n, cs = (n + parts - 1) / parts;
+  // column r, read with r fastest (coalesced).  Work item (r, part) sums a
+  // range of rows c; parts meet in red.
+  const int tid = threadIdx.x, parts = max(1, (int)blockDim.x / n), cs = (n + parts - 1) / parts;
   double lo = INFINITY, hi = -INFINITY;
-  if (tid < parts * n) {
-    const int r = tid % n, part = tid / n;
+  for (int wi = tid; wi < parts * n; wi += blockDim.x) {
+    const int r = wi % n, part = wi / n;
     const int c1 = min(n, (part + 1) * cs);
     double off = 0.0;
     for (int c0 = part * cs; c0 < c1; c0 += 8) {
@@ -459,7 +459,7 @@ NTU_DEV bool gershgorin_certify(const T* __restrict__ G, int n, double margin, d
       for (int l = 0; l < 8; ++l)
         if (c0 + l < c1 && c0 + l != r) off += sqrt(abs2(v[l]));
     }
-    red[tid] = off;
+    red[wi] = off;
   }
   __syncthreads();
   for (int r = tid; r < n; r += blockDim.x) {
