@@ -290,47 +290,85 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
     }
   };
   auto lstore = [&](int buf) {
+    if constexpr (PREC != NTU_PREC_FP16X3) {
+      // bfloat16 pieces of two values at once (one packed word per piece)
 #pragma unroll
-    for (int u = 0; u < NGA; ++u) {
-      E t[4][NT];
+      for (int u = 0; u < NGA; ++u) {
+        unsigned w0[NT], w1[NT];
+        split_pair<PREC>(ra[u][0], ra[u][1], w0);
+        split_pair<PREC>(ra[u][2], ra[u][3], w1);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) split_value<PREC>(ra[u][e], t[e]);
+        for (int p = 0; p < NT; ++p) *(uint2*)&sA[buf][p][arl[u]][akq[u]] = make_uint2(w0[p], w1[p]);
+      }
 #pragma unroll
-      for (int p = 0; p < NT; ++p)
+      for (int u = 0; u < NGB; ++u) {
+        if constexpr (CPLX) {
+          // complex values (re0, im0), (re1, im1) -> real rows 2r: (re, -im), 2r+1: (im, re).
+          // The pieces of (re, im) are split once; the pieces of -x are those
+          // of x negated (sign bit), so row 2r flips the high halves and row
+          // 2r+1 swaps the halves.
+          const float s = d.conjB ? -1.0f : 1.0f;
+          unsigned w0[NT], w1[NT];
+          split_pair<PREC>(rb[u][0], s * rb[u][1], w0);
+          split_pair<PREC>(rb[u][2], s * rb[u][3], w1);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) sA[buf][p][arl[u]][akq[u] + e] = t[e][p];
-    }
-#pragma unroll
-    for (int u = 0; u < NGB; ++u) {
-      if constexpr (CPLX) {
-        // complex values (re0, im0), (re1, im1) -> real rows 2r: (re, -im), 2r+1: (im, re)
-        const float s = d.conjB ? -1.0f : 1.0f;
-        const float re0 = rb[u][0], im0 = s * rb[u][1], re1 = rb[u][2], im1 = s * rb[u][3];
-        const float v0[4] = {re0, -im0, re1, -im1}, v1[4] = {im0, re0, im1, re1};
-        E t0[4][NT], t1[4][NT];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          split_value<PREC>(v0[e], t0[e]);
-          split_value<PREC>(v1[e], t1[e]);
-        }
-#pragma unroll
-        for (int p = 0; p < NT; ++p)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            sB[buf][p][2 * brl[u]][bkq[u] + e] = t0[e][p];
-            sB[buf][p][2 * brl[u] + 1][bkq[u] + e] = t1[e][p];
+          for (int p = 0; p < NT; ++p) {
+            *(uint2*)&sB[buf][p][2 * brl[u]][bkq[u]] = make_uint2(w0[p] ^ 0x80000000u, w1[p] ^ 0x80000000u);
+            *(uint2*)&sB[buf][p][2 * brl[u] + 1][bkq[u]] =
+                make_uint2((w0[p] >> 16) | (w0[p] << 16), (w1[p] >> 16) | (w1[p] << 16));
           }
-      } else {
+        } else {
+          unsigned w0[NT], w1[NT];
+          split_pair<PREC>(rb[u][0], rb[u][1], w0);
+          split_pair<PREC>(rb[u][2], rb[u][3], w1);
+#pragma unroll
+          for (int p = 0; p < NT; ++p) *(uint2*)&sB[buf][p][brl[u]][bkq[u]] = make_uint2(w0[p], w1[p]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < NGA; ++u) {
         E t[4][NT];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) split_value<PREC>(rb[u][e], t[e]);
+        for (int e = 0; e < 4; ++e) split_value<PREC>(ra[u][e], t[e]);
 #pragma unroll
         for (int p = 0; p < NT; ++p)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) sB[buf][p][brl[u]][bkq[u] + e] = t[e][p];
+          for (int e = 0; e < 4; ++e) sA[buf][p][arl[u]][akq[u] + e] = t[e][p];
+      }
+#pragma unroll
+      for (int u = 0; u < NGB; ++u) {
+        if constexpr (CPLX) {
+          // complex values (re0, im0), (re1, im1) -> real rows 2r: (re, -im), 2r+1: (im, re)
+          const float s = d.conjB ? -1.0f : 1.0f;
+          const float re0 = rb[u][0], im0 = s * rb[u][1], re1 = rb[u][2], im1 = s * rb[u][3];
+          const float v0[4] = {re0, -im0, re1, -im1}, v1[4] = {im0, re0, im1, re1};
+          E t0[4][NT], t1[4][NT];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            split_value<PREC>(v0[e], t0[e]);
+            split_value<PREC>(v1[e], t1[e]);
+          }
+#pragma unroll
+          for (int p = 0; p < NT; ++p)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              sB[buf][p][2 * brl[u]][bkq[u] + e] = t0[e][p];
+              sB[buf][p][2 * brl[u] + 1][bkq[u] + e] = t1[e][p];
+            }
+        } else {
+          E t[4][NT];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) split_value<PREC>(rb[u][e], t[e]);
+#pragma unroll
+          for (int p = 0; p < NT; ++p)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) sB[buf][p][brl[u]][bkq[u] + e] = t[e][p];
+        }
       }
     }
   };
+
 
   f32x4 acc[NACC][4][TL_WY];
 #pragma unroll
