@@ -73,19 +73,55 @@ def copy_calibration(mib):
                       "avg_launch_us": ms * 1e3, "rate_GBps": 2 * n * 4 / (ms * 1e-3) / 1e9}))
 
 
-def fit_flops(R, Dn, half_steps, cplx):
-    """Algorithmic FP64 flops of one bond fit with certified solves:
-    per half-step g_s = K^H g K (R^4 Dn + R^3 Dn^2 MACs), Cholesky (nx^3/6),
-    two triangular solves (nx^2), error d^H g d (R^4); plus g y, the SVDU
-    error and the balancing product (3 R^4)."""
+def fit_flops(R, Dn, half_steps, cg_iters, cplx):
+    """Algorithmic FP64 flops of one bond fit on the certified path: per
+    half-step g_s = K^H g K and J = K^H g y (R^4 Dn + R^3 Dn^2 + R^3 Dn MACs)
+    and cg_iters products with g_s ((R Dn)^2 each); plus g y and the error of
+    the guess (2 R^4)."""
     nx = R * Dn
-    macs = half_steps * (R ** 4 * Dn + R ** 3 * Dn ** 2 + nx ** 3 / 6 + nx ** 2 + R ** 4) + 3 * R ** 4
+    macs = half_steps * (R ** 4 * Dn + R ** 3 * Dn ** 2 + R ** 3 * Dn + cg_iters * nx ** 2) + 2 * R ** 4
     return macs * (8 if cplx else 2)
+
+
+def env_work(R, D, p, cplx, fused):
+    """Algorithmic work per bond of the environment kernel classes (flops;
+    complex multiply-add = 8) and the bytes they must move (FP32 (re, im)
+    blocks on the split path).  fused: Right alone, then Left + E4 + E5 in
+    one kernel (complex, D^2 <= 64, split precision); otherwise Left and
+    Right, E4 and E5 are separate products."""
+    m, el = (8, 8) if cplx else (2, 4)
+    blk = R * R * D ** 4                      # elements of Left / Right / L2
+    q = R * D * D * p * D                     # elements of one dressed isometry
+    w = {"env_e6": (m * R ** 4 * D ** 4, 2 * blk * el)}
+    if fused:
+        w["env_left_right"] = (m * blk * p * D, blk * el + 2 * q * 2 * el)
+        w["env_e4"] = (m * (blk * p * D + 2 * R * R * D ** 6), blk * el + 2 * q * 2 * el)
+    else:
+        w["env_left_right"] = (2 * m * blk * p * D, 2 * blk * el + 4 * q * 2 * el)
+        w["env_e4"] = (m * R * R * D ** 6, 2 * blk * el)
+        w["env_e5"] = (m * R * R * D ** 6, 2 * blk * el)
+    return w
 
 
 def env_assembly_flops(R, D, cplx):
     """g = L2 Right^T: (R^2 x D^4) times (D^4 x R^2)."""
     return (8 if cplx else 2) * (R * R) * (R * R) * D ** 4
+
+
+def traffic_record(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter runs, or
+    None when the kernel's source has changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != rec["sha1"]:
+        return None
+    return rec
 
 
 class Job:
@@ -100,7 +136,7 @@ def build_batched(ntu, inputs, dev, torch, np, only_D=None):
     for it in items:
         buckets.setdefault(it["D"], []).append(it)
     job = Job()
-    job.cplx, job.n_updates, job.items = True, len(items), items
+    job.cplx, job.p, job.n_updates, job.items = True, 2, len(items), items
     job.buckets = []
     for D in sorted(buckets):
         its = buckets[D]
@@ -132,7 +168,7 @@ def build_thermal(ntu, inputs, dev, torch, np, D=8):
     A = torch.from_numpy(w["A"][None]).to(dev).contiguous()
     B = torch.from_numpy(w["B"][None]).to(dev).contiguous()
     job = Job()
-    job.cplx, job.n_updates, job.w = False, 4, w
+    job.cplx, job.p, job.n_updates, job.w = False, 4, 4, w
     job.buckets = [dict(D=D, A=A, B=B, gf=gf, n=1, ctx=ctx, stream=torch.cuda.current_stream(dev))]
     job.order = (0, 1, 2, 3)
     job.bonds_per_item = 4
@@ -291,36 +327,47 @@ def main():
     nprof = max(1, args.profile_steps)
     result["kernel_ms_per_step"] = {k: round(v[0] / nprof, 4) for k, v in
                                     sorted(prof.items(), key=lambda kv: -kv[1][0])}
-    # roofline of the dominant kernel class
+    # roofline of every kernel class with a model, and of the dominant one
+    issue = 1 if args.precision == "f64" else (3 if args.precision in ("bf16x3", "fp16x3") else 6)
     fit_fl = 0.0
+    env = {}
     for bi, bk in enumerate(job.buckets):
         st = torch.stack([s[bi] for s in stm]).cpu().numpy()
         R = 2 * bk["D"]
         for row in st.reshape(-1, st.shape[-1]):
-            fit_fl += fit_flops(R, row[8 + 4], 2 * row[8 + 6], job.cplx)
+            fit_fl += fit_flops(R, row[8 + 4], 2 * row[8 + 6], row[8 + 15], job.cplx)
+        fused = job.cplx and bk["D"] ** 2 <= 64 and args.precision in ("bf16x3", "bf16x6")
+        for k, (fl, by) in env_work(R, bk["D"], job.p, job.cplx, fused).items():
+            a0, b0 = env.get(k, (0.0, 0.0))
+            env[k] = (a0 + fl * bk["n"] * job.bonds_per_item, b0 + by * bk["n"] * job.bonds_per_item)
     fit_fl /= K                                            # per step
-    e6_fl = sum(env_assembly_flops(2 * bk["D"], bk["D"], job.cplx) * bk["n"] * job.bonds_per_item
-                for bk in job.buckets)                    # per step
+    peak_mx = PEAK_FP64 if args.precision == "f64" else PEAK_BF16
+    kernel_of = {"bond_fit": "k_bond_fit", "env_left_right": "k_right", "env_e4": "k_left_e45",
+                 "env_e5": "k_mfma_tile (L2)", "env_e6": "k_mfma_tile (g = L2 Right^T)"}
     rl = {}
-    if "bond_fit" in prof:
-        t = prof["bond_fit"][0] / nprof / 1e3
-        n_l = prof["bond_fit"][1] / nprof
-        rl["bond_fit"] = {"kernel": "k_bond_fit", "bound": "alu", "achieved": fit_fl / t / 1e12,
-                          "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": fit_fl / t / PEAK_FP64,
-                          "traffic": None, "avg_launch_us": t / n_l * 1e6, "launches_per_step": n_l,
-                          "flops_per_step": fit_fl}
-    if "env_e6" in prof:
-        t = prof["env_e6"][0] / nprof / 1e3
-        n_l = prof["env_e6"][1] / nprof
-        peak = PEAK_FP64 if args.precision == "f64" else PEAK_BF16
-        rl["env_e6"] = {"kernel": "k_mfma_nt (metric assembly)", "bound": "mfma", "achieved": e6_fl / t / 1e12,
-                        "peak": peak / 1e12, "unit": "TFLOP/s", "frac": e6_fl / t / peak, "traffic": None,
-                        "avg_launch_us": t / n_l * 1e6, "launches_per_step": n_l, "flops_per_step": e6_fl,
-                        "issued_mfma_flops_per_step": (3 if args.precision in ("bf16x3", "fp16x3") else 6) * e6_fl}
-    dom = max(prof.items(), key=lambda kv: kv[1][0])[0] if prof else None
-    result["roofline"] = rl.get(dom, rl.get("env_e6", {}))
-    result["roofline"]["dominant_class"] = dom
-    result["roofline_env_assembly"] = rl.get("env_e6")
+    for cls, (t_ms, n_l) in prof.items():
+        t = t_ms / nprof / 1e3                             # s per step
+        n_l = n_l / nprof
+        if cls == "bond_fit":
+            rl[cls] = {"kernel": kernel_of[cls], "bound": "alu", "achieved": fit_fl / t / 1e12,
+                       "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": fit_fl / t / PEAK_FP64,
+                       "flops_per_step": fit_fl}
+        elif cls in env:
+            fl, by = env[cls]
+            rl[cls] = {"kernel": kernel_of[cls], "bound": "mfma", "achieved": fl / t / 1e12, "peak": peak_mx / 1e12,
+                       "unit": "TFLOP/s", "frac": fl / t / peak_mx, "flops_per_step": fl,
+                       "issued_mfma_frac": issue * fl / t / peak_mx, "algorithmic_bytes_per_step": by,
+                       "algorithmic_GBps": by / t / 1e9}
+        else:
+            continue
+        rl[cls].update({"avg_launch_us": t / n_l * 1e6, "launches_per_step": n_l, "traffic": None})
+        rec = traffic_record(rl[cls]["kernel"].split(" ")[0])
+        if rec and rec.get("workload") == result["config"]["workload"] and rec.get("precision") == args.precision:
+            rl[cls]["traffic"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+            rl[cls]["traffic_source"] = "profiles/traffic.json"
+    dom = max((c for c in prof if c in rl), key=lambda c: prof[c][0], default=None)
+    result["roofline"] = dict(rl.get(dom, {}), dominant_class=dom)
+    result["roofline_by_class"] = rl
 
     if not args.no_cpu:
         from oracle import ntu as O
