@@ -440,9 +440,10 @@ NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv,
     b2[kc] = v2;
   }
   const int nrt = (n + 15) / 16, nu1 = R * nrt;
-  for (int u = w; u < nu1; u += nw) {
-    const int x = u / nrt, r0 = (u % nrt) * 16, r = r0 + l16;
-    T gv[NKC];
+  // the operands of the wave's next unit are loaded while the current one
+  // runs on the matrix cores
+  auto load1 = [&](int u, T (&gv)[NKC]) {
+    const int x = u / nrt, r = (u % nrt) * 16 + l16;
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) {
       const int y = 4 * kc + lk;
@@ -451,6 +452,15 @@ NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv,
       const T gl = Gm[ok ? (size_t)(half == 0 ? x * R + y : y * R + x) * n + r : 0];
       gv[kc] = ok ? conjv(gl) : zerov<T>();
     }
+  };
+  T gnext[NKC];
+  if (w < nu1) load1(w, gnext);
+  for (int u = w; u < nu1; u += nw) {
+    const int x = u / nrt, r0 = (u % nrt) * 16;
+    T gv[NKC];
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) gv[kc] = gnext[kc];
+    if (u + nw < nu1) load1(u + nw, gnext);
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) {
@@ -492,9 +502,8 @@ NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv,
     a2[kc] = v2;
   }
   const int nct = (nx + 15) / 16, nu2 = R * nct;
-  for (int u = w; u < nu2; u += nw) {
+  auto load2 = [&](int u, T (&gv)[NKC]) {
     const int o = u / nct, c = (u % nct) * 16 + l16;
-    T gv[NKC];
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) {
       const int i = 4 * kc + lk;
@@ -502,6 +511,14 @@ NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv,
       const T gl = G1[ok ? (size_t)(half == 0 ? o * R + i : i * R + o) * nx + c : 0];
       gv[kc] = ok ? gl : zerov<T>();
     }
+  };
+  if (w < nu2) load2(w, gnext);
+  for (int u = w; u < nu2; u += nw) {
+    const int o = u / nct, c = (u % nct) * 16 + l16;
+    T gv[NKC];
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) gv[kc] = gnext[kc];
+    if (u + nw < nu2) load2(u + nw, gnext);
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) {
@@ -530,8 +547,10 @@ NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv,
   __syncthreads();
 }
 
+// Kept out of line: the formation gets the kernel's full register budget
+// for its loads in flight instead of sharing it with the rest of the fit.
 template <class T>
-NTU_DEV void form_gs_mfma(const T* __restrict__ Gm, const T* __restrict__ gyv, int R, int Dn, int half, const T* Q,
+__device__ __noinline__ void form_gs_mfma(const T* __restrict__ Gm, const T* __restrict__ gyv, int R, int Dn, int half, const T* Q,
                           T* __restrict__ G1, T* __restrict__ gs, T* J) {
   switch (R) {  // the enlarged bond dimensions of a rank-2 gate on the certified path
     case 4: form_gs_mfma_k<T, 1, 4>(Gm, gyv, R, Dn, half, Q, G1, gs, J); return;
