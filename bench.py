@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=1)
     ap.add_argument("--bucket", type=int, default=0,
                     help="batched workload: only the items of this bond dimension (0 = all 256)")
+    ap.add_argument("--hw-queues", type=int, default=HW_QUEUES,
+                    help="GPU_MAX_HW_QUEUES for this process (hardware queues the streams are spread over)")
+    ap.add_argument("--aux", default="own", choices=["own", "shared"],
+                    help="side stream of each bucket's Trotter step: the context's own, or one shared by all")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (20 times) and print its "
                          "rate: the reference kernel for scaling HBM byte counters")
@@ -184,8 +188,8 @@ HW_QUEUES = 16
 
 
 def main():
-    os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
     args = parse()
+    os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the bond updates of a step are "
               "independent, and the multi-GPU layout is described but not run", file=sys.stderr)
@@ -204,6 +208,10 @@ def main():
         job = build_batched(ntu, inputs, dev, torch, np, only_D=args.bucket)
     else:
         job = build_thermal(ntu, inputs, dev, torch, np)
+    if args.aux == "shared":
+        job.aux = torch.cuda.Stream(device=dev)
+        for bk in job.buckets:
+            bk["ctx"].set_aux_stream(job.aux)
     fit = dict(n_iter=20, early_stop=True, conv_tol=1e-12)
     opts = ntu.step_opts(args.precision, order=job.order, **fit)
     opts64 = ntu.step_opts("f64", order=job.order, **fit)

@@ -90,6 +90,17 @@ ntu_status ntu_ctx_create(ntu_ctx** out, int device, int dtype, int d, int d_anc
 ntu_status ntu_ctx_destroy(ntu_ctx* ctx);
 /* stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream). */
 ntu_status ntu_set_stream(ntu_ctx* ctx, void* stream);
+/*
+ * Side stream of ntu_trotter_step.  Each bond's SVDU initial guess (Fig.
+ * 2(c,d)) needs only the reduction, so the step computes it on a second
+ * stream while the environment is contracted, ordered by events recorded on
+ * the context's stream (so the pair can be captured into a HIP graph).  By
+ * default the context owns that stream; stream != NULL makes the step use
+ * the caller's (hipStream_t, for instance one shared by several contexts, so
+ * that fewer streams compete for hardware queues); NULL restores the
+ * context's own.  The caller keeps the stream alive while the context uses it.
+ */
+ntu_status ntu_set_aux_stream(ntu_ctx* ctx, void* stream);
 /* Message of the last failed call on ctx ("" if none).  Owned by ctx. */
 const char* ntu_last_error(const ntu_ctx* ctx);
 /* Bytes of device workspace held by ctx. */

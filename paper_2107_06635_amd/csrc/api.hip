@@ -12,7 +12,7 @@ namespace {
 
 struct Persist {
   // per-item persistent buffers of the Trotter step (compute type elements)
-  long long QX, QY, RX, RY, g, MX, MY, rA, rB, GA, GB, cert, guess;
+  long long QX, QY, RX, RY, g, MX, MY, rA, rB, GA, GB, cert, guess, todo;
 };
 
 }  // namespace
@@ -23,9 +23,10 @@ struct ntu_ctx {
   bool cplx = true;
   int d = 2, na = 1, rg = 2, max_D = 1, max_batch = 1;
   hipStream_t stream = nullptr;
-  // side stream of the Trotter step (default priority) and its fork / join events
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // side stream of the Trotter step (default priority) and its fork / join
+  // events; aux_user (when set) replaces the context's own aux
+  hipStream_t aux = nullptr, aux_user = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_edges = nullptr, ev_red = nullptr, ev_join = nullptr;
   char* ws = nullptr;          // scratch of one call
   size_t ws_bytes = 0;
   char* step = nullptr;        // buffers of the Trotter step
@@ -102,13 +103,14 @@ Persist persist_layout(int p, int D, int rg, int d) {
   s.GB = o; o += (long long)d * d * rg;
   s.cert = o; o += 1;  // the metric repair's certificate for the fit (one double per item)
   s.guess = o; o += ntu::svdu_guess_elems();  // the fit's SVDU guess, computed beside the environment
+  s.todo = o; o += 1;  // the reduction's path flags, two ints per item
   (void)o;
   return s;
 }
 long long persist_elems(int p, int D, int rg, int d) {
   const long long R = (long long)D * rg, D3 = (long long)D * D * D;
   return 2 * p * D3 * R + 2 * R * R + R * R * R * R + 2 * R * D + 2 * p * D3 * D + 2LL * d * d * rg + 1 +
-         ntu::svdu_guess_elems();
+         ntu::svdu_guess_elems() + 1;
 }
 
 const int PROF_CAP = 1 << 15;
@@ -213,13 +215,14 @@ ntu_status ntu_ctx_create(ntu_ctx** out, int device, int dtype, int d, int d_anc
   hipError_t e = hipMalloc((void**)&c->ws, c->ws_bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&c->step, c->step_bytes);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+  for (hipEvent_t* ev : {&c->ev_fork, &c->ev_edges, &c->ev_red, &c->ev_join})
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     if (c->ws) (void)hipFree(c->ws);
     if (c->step) (void)hipFree(c->step);
     if (c->aux) (void)hipStreamDestroy(c->aux);
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    for (hipEvent_t ev : {c->ev_fork, c->ev_edges, c->ev_red, c->ev_join})
+      if (ev) (void)hipEventDestroy(ev);
     delete c;
     return fail(nullptr, NTU_ERR_HIP, std::string("context set-up failed: ") + hipGetErrorString(e));
   }
@@ -233,8 +236,8 @@ ntu_status ntu_ctx_destroy(ntu_ctx* c) {
   if (c->ws) (void)hipFree(c->ws);
   if (c->step) (void)hipFree(c->step);
   if (c->aux) (void)hipStreamDestroy(c->aux);
-  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  for (hipEvent_t ev : {c->ev_fork, c->ev_edges, c->ev_red, c->ev_join})
+    if (ev) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
   delete c;
   return NTU_OK;
@@ -243,6 +246,12 @@ ntu_status ntu_ctx_destroy(ntu_ctx* c) {
 ntu_status ntu_set_stream(ntu_ctx* c, void* stream) {
   if (!c) return NTU_ERR_ARG;
   c->stream = (hipStream_t)stream;
+  return NTU_OK;
+}
+
+ntu_status ntu_set_aux_stream(ntu_ctx* c, void* stream) {
+  if (!c) return NTU_ERR_ARG;
+  c->aux_user = (hipStream_t)stream;
   return NTU_OK;
 }
 
@@ -373,6 +382,7 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
   char* rB = buf(L.rB);
   double* cert = (double*)buf(L.cert);
   char* guess = buf(L.guess);
+  int* todo = (int*)buf(L.todo);
   (void)pe;
   const long long gfs = (long long)c->d * c->d * c->rg;  // elements of one factor
   const long long gf_item = 8 * gfs;                      // 4 bonds x (GA, GB)
@@ -400,18 +410,30 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     char* Y = x_is_a ? b : a;
     const char* gA = (const char*)gate_factors + (size_t)(bond * 2 + 0) * gfs * el;
     const char* gB = (const char*)gate_factors + (size_t)(bond * 2 + 1) * gfs * el;
+    // The side stream (aux) takes the work that does not need the reduction:
+    // the edge tensors and transfers (they read only the neighbours) while
+    // the reduction runs, then the fit's SVDU guess (it needs only RX, RY)
+    // while the environment is contracted.  Events order the two streams.
+    hipStream_t aux = c->aux_user ? c->aux_user : c->aux;
+    const void* nbr[6] = {Y, Y, Y, X, X, X};
+    const ntu::ProfHook none{nullptr, nullptr};
+    NTU_STEP(hipEventRecord(c->ev_fork, c->stream), "fork");
+    NTU_STEP(hipStreamWaitEvent(aux, c->ev_fork, 0), "fork");
+    e = ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, nullptr, nullptr, nbr, nullptr, c->ws,
+                                 c->ws_bytes, aux, none, 1);
+    if (e != hipSuccess) return hip_fail(c, e, "env_contract (edges)");
+    NTU_STEP(hipEventRecord(c->ev_edges, aux), "fork");
     ph(ntu::PK_REDUCE, 0);
     NTU_STEP(ntu::launch_reduce_qr_pair(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, Y, gB, gf_item, QX, RX, QY, RY,
-                                        opts->fit.kappa, (int*)c->ws, c->stream), "reduce_qr");
+                                        opts->fit.kappa, todo, c->stream), "reduce_qr");
     ph(ntu::PK_REDUCE, 1);
-    // the fit's SVDU guess needs only RX, RY: it runs on the side stream while
-    // the environment is contracted, and the fit waits for it
-    NTU_STEP(hipEventRecord(c->ev_fork, c->stream), "fork");
-    NTU_STEP(hipStreamWaitEvent(c->aux, c->ev_fork, 0), "fork");
-    NTU_STEP(ntu::launch_svdu_guess(cp, batch, D, R, RX, RY, opts->fit.kappa, guess, c->aux), "svdu_guess");
-    NTU_STEP(hipEventRecord(c->ev_join, c->aux), "join");
-    const void* nbr[6] = {Y, Y, Y, X, X, X};
-    e = ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, QX, QY, nbr, G, c->ws, c->ws_bytes, c->stream, ph);
+    NTU_STEP(hipEventRecord(c->ev_red, c->stream), "fork");
+    NTU_STEP(hipStreamWaitEvent(aux, c->ev_red, 0), "fork");
+    NTU_STEP(ntu::launch_svdu_guess(cp, batch, D, R, RX, RY, opts->fit.kappa, guess, aux), "svdu_guess");
+    NTU_STEP(hipEventRecord(c->ev_join, aux), "join");
+    NTU_STEP(hipStreamWaitEvent(c->stream, c->ev_edges, 0), "join");
+    e = ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, QX, QY, nbr, G, c->ws, c->ws_bytes, c->stream, ph,
+                                 2);
     if (e == hipErrorNotSupported) return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
     if (e != hipSuccess) return hip_fail(c, e, "env_contract");
     double* sb = stats ? stats + (size_t)bi * sl : nullptr;

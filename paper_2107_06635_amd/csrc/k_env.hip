@@ -370,7 +370,7 @@ size_t env_workspace_bytes(bool cplx, int precision, int batch, int p, int D, in
 
 hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D, int R, const void* QX,
                                const void* QY, const void* const nbr[6], void* g, void* ws, size_t ws_bytes,
-                               hipStream_t st, const ProfHook& ph) {
+                               hipStream_t st, const ProfHook& ph, int part) {
   if (batch <= 0) return hipSuccess;
   if (env_workspace_bytes(cplx, precision, batch, p, D, R) > ws_bytes) return hipErrorOutOfMemory;
   const EnvSizes s = env_sizes(p, D, R);
@@ -401,6 +401,7 @@ hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D
   // 1. edge double tensors (Fig. 4(a,b)): E(i, j) = sum_k T(i, k) conj(T(j, k)),
   //    and 2. the parallel-bond transfers
   //    EtopT[(T T')][(t t')] = sum_{v v'} ETY[T v T' v'] ETX[t v t' v'] (EbotT alike)
+  if (part != 2) {
   ph(PK_EDGES, 0);
   if (D2 <= SM_T) {
     SmallBatch eb{};
@@ -458,6 +459,8 @@ hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D
   NTU_TRY(gemm_nt(cplx, EBY, EBX, EBT, d, st));
   }
   ph(PK_EDGES, 1);
+  }
+  if (part == 1) return hipSuccess;
 
   // 3. regrouped isometries dressed with EL / ER
   ph(PK_QPREP, 0);

@@ -24,7 +24,8 @@ BOND_H1, BOND_H2, BOND_V1, BOND_V2 = 0, 1, 2, 3
 PRECISIONS = {"f64": PREC_F64, "bf16x3": PREC_BF16X3, "fp16x3": PREC_FP16X3, "bf16x6": PREC_BF16X6}
 
 EXPORTED = (
-    "ntu_ctx_create", "ntu_ctx_destroy", "ntu_set_stream", "ntu_last_error", "ntu_workspace_bytes",
+    "ntu_ctx_create", "ntu_ctx_destroy", "ntu_set_stream", "ntu_set_aux_stream", "ntu_last_error",
+    "ntu_workspace_bytes",
     "ntu_version", "ntu_gate_split", "ntu_reduce_qr", "ntu_env_contract", "ntu_metric_fix",
     "ntu_fit_opts_default", "ntu_bond_fit", "ntu_recombine", "ntu_step_opts_default", "ntu_trotter_step",
     "ntu_profile_enable", "ntu_profile_read", "ntu_profile_kind_name",
@@ -57,6 +58,7 @@ def load():
     L.ntu_ctx_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, i32, i32, i32]
     L.ntu_ctx_destroy.argtypes = [vp]
     L.ntu_set_stream.argtypes = [vp, vp]
+    L.ntu_set_aux_stream.argtypes = [vp, vp]
     L.ntu_last_error.argtypes = [vp]
     L.ntu_last_error.restype = ctypes.c_char_p
     L.ntu_workspace_bytes.argtypes = [vp]
@@ -159,6 +161,12 @@ class Context:
     def bind_stream(self):
         s = torch.cuda.current_stream(self.device).cuda_stream
         self.check(self.L.ntu_set_stream(self.h, ctypes.c_void_p(s)), "ntu_set_stream")
+
+    def set_aux_stream(self, stream=None):
+        """Side stream of the Trotter step (a torch.cuda.Stream, or None for
+        the context's own)."""
+        s = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        self.check(self.L.ntu_set_aux_stream(self.h, s), "ntu_set_aux_stream")
 
     def empty(self, *shape, dtype=None):
         return torch.empty(*shape, dtype=dtype or self.dtype, device=self.device)
