@@ -101,9 +101,11 @@ def test_env_contract_f64(D, p, real):
 
 
 @pytest.mark.parametrize("prec,tol", [("bf16x3", 3e-5), ("bf16x6", 1e-6)])
-@pytest.mark.parametrize("D,p,real", [(3, 2, False), (5, 2, False), (4, 4, True)])
+@pytest.mark.parametrize("D,p,real", [(3, 2, False), (5, 2, False), (5, 4, False), (4, 4, True)])
 def test_env_contract_mixed(prec, tol, D, p, real):
-    """Split-precision metric: relative Frobenius error within the mode's budget."""
+    """Split-precision metric: relative Frobenius error within the mode's budget.
+    Complex D <= 8 takes the fused kernels (D = 5, p = 4: contraction index
+    p D = 20 spans two MFMA K steps of the Left/Right blocks)."""
     X, Y, nbr, G, GA, GB = _case(300 + D, D, p, real)
     QX, _ = O.reduce_site(X, GA, 'X', 2)
     QY, _ = O.reduce_site(Y, GB, 'Y', 2)
@@ -267,3 +269,37 @@ def test_trotter_step_thermal_prefix():
         eo, _ = O.observables(A, B, 2.5)
         eg, _ = O.observables(Ag, Bg, 2.5)
         assert abs(eg - eo) < 1e-10
+
+
+def test_shared_side_stream_matches_own():
+    """Two contexts on two streams that share one side stream (ntu_set_aux_stream)
+    give the same Trotter steps, bit for bit, as with their own side streams."""
+    D = 4
+    w = inputs.workload_quench(seed=2, D=D)
+    GA, GB, _ = O.gate_split(w['gates'][0], 2, 2)
+    pairs = {b: (GA, GB) for b in O.BONDS}
+    gf = to_dev(gate_factors_array(pairs)[None])
+    opts = ntu.step_opts("bf16x6", n_iter=20, early_stop=True, conv_tol=1e-12)
+
+    def run(shared):
+        ctxs = [_ctx(max_D=D, max_batch=1) for _ in range(2)]
+        streams = [torch.cuda.Stream() for _ in range(2)]
+        aux = torch.cuda.Stream() if shared else None
+        states = [(to_dev(w['A'][None]), to_dev(w['B'][None])), (to_dev(w['B'][None]), to_dev(w['A'][None]))]
+        torch.cuda.synchronize()
+        for c, s, (A, B) in zip(ctxs, streams, states):
+            if shared:
+                c.set_aux_stream(aux)
+            with torch.cuda.stream(s):
+                for _ in range(2):
+                    ntu.ntu_trotter_step(c, A, B, gf, opts, stats=False)
+        torch.cuda.synchronize()
+        out = [(to_np(A), to_np(B)) for A, B in states]
+        for c in ctxs:
+            c.set_aux_stream(None)
+            c.close()
+        return out
+
+    own, shared = run(False), run(True)
+    for (a0, b0), (a1, b1) in zip(own, shared):
+        assert np.array_equal(a0, a1) and np.array_equal(b0, b1)
