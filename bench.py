@@ -323,59 +323,90 @@ def main():
         result["metric_rel_err_vs_fp64_path"] = {"D": bk["D"], "max": max(errs), "mean": sum(errs) / len(errs)}
 
     # live per-kernel timing with HIP events on each context's stream (summed over buckets)
-    for bk in job.buckets:
-        ntu.ntu_profile_enable(bk["ctx"], True)
-    run(opts, args.profile_steps)
-    prof = {}
-    for bk in job.buckets:
-        for k, (ms_k, n_k) in ntu.ntu_profile_read(bk["ctx"]).items():
-            a, b = prof.get(k, (0.0, 0))
-            prof[k] = (a + ms_k, b + n_k)
-        ntu.ntu_profile_enable(bk["ctx"], False)
     nprof = max(1, args.profile_steps)
-    result["kernel_ms_per_step"] = {k: round(v[0] / nprof, 4) for k, v in
-                                    sorted(prof.items(), key=lambda kv: -kv[1][0])}
-    # roofline of every kernel class with a model, and of the dominant one
     issue = 1 if args.precision == "f64" else (3 if args.precision in ("bf16x3", "fp16x3") else 6)
-    fit_fl = 0.0
-    env = {}
-    for bi, bk in enumerate(job.buckets):
-        st = torch.stack([s[bi] for s in stm]).cpu().numpy()
-        R = 2 * bk["D"]
-        for row in st.reshape(-1, st.shape[-1]):
-            fit_fl += fit_flops(R, row[8 + 4], 2 * row[8 + 6], row[8 + 15], job.cplx)
-        fused = job.cplx and bk["D"] ** 2 <= 64 and args.precision in ("bf16x3", "bf16x6")
-        for k, (fl, by) in env_work(R, bk["D"], job.p, job.cplx, fused).items():
-            a0, b0 = env.get(k, (0.0, 0.0))
-            env[k] = (a0 + fl * bk["n"] * job.bonds_per_item, b0 + by * bk["n"] * job.bonds_per_item)
-    fit_fl /= K                                            # per step
     peak_mx = PEAK_FP64 if args.precision == "f64" else PEAK_BF16
     kernel_of = {"bond_fit": "k_bond_fit", "env_left_right": "k_right", "env_e4": "k_left_e45",
                  "env_e5": "k_mfma_tile (L2)", "env_e6": "k_mfma_tile (g = L2 Right^T)"}
-    rl = {}
-    for cls, (t_ms, n_l) in prof.items():
-        t = t_ms / nprof / 1e3                             # s per step
-        n_l = n_l / nprof
-        if cls == "bond_fit":
-            rl[cls] = {"kernel": kernel_of[cls], "bound": "alu", "achieved": fit_fl / t / 1e12,
-                       "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": fit_fl / t / PEAK_FP64,
-                       "flops_per_step": fit_fl}
-        elif cls in env:
-            fl, by = env[cls]
-            rl[cls] = {"kernel": kernel_of[cls], "bound": "mfma", "achieved": fl / t / 1e12, "peak": peak_mx / 1e12,
-                       "unit": "TFLOP/s", "frac": fl / t / peak_mx, "flops_per_step": fl,
-                       "issued_mfma_frac": issue * fl / t / peak_mx, "algorithmic_bytes_per_step": by,
-                       "algorithmic_GBps": by / t / 1e9}
-        else:
-            continue
-        rl[cls].update({"avg_launch_us": t / n_l * 1e6, "launches_per_step": n_l, "traffic": None})
-        rec = traffic_record(rl[cls]["kernel"].split(" ")[0])
-        if rec and rec.get("workload") == result["config"]["workload"] and rec.get("precision") == args.precision:
-            rl[cls]["traffic"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
-            rl[cls]["traffic_source"] = "profiles/traffic.json"
-    dom = max((c for c in prof if c in rl), key=lambda c: prof[c][0], default=None)
+
+    def profile_classes(steps):
+        for bk in job.buckets:
+            ntu.ntu_profile_enable(bk["ctx"], True)
+        run(opts, steps)
+        prof = {}
+        for bk in job.buckets:
+            for k, (ms_k, n_k) in ntu.ntu_profile_read(bk["ctx"]).items():
+                a0, b0 = prof.get(k, (0.0, 0))
+                prof[k] = (a0 + ms_k, b0 + n_k)
+            ntu.ntu_profile_enable(bk["ctx"], False)
+        return prof
+
+    def rooflines(stats, nst, prof, workload):
+        """Per kernel class: algorithmic (and issued MFMA) rate over the average
+        launch time; stats: the timed steps' stats of job.buckets."""
+        fit_fl, env = 0.0, {}
+        for bi, bk in enumerate(job.buckets):
+            st = torch.stack([x[bi] for x in stats]).cpu().numpy()
+            R = 2 * bk["D"]
+            for row in st.reshape(-1, st.shape[-1]):
+                fit_fl += fit_flops(R, row[8 + 4], 2 * row[8 + 6], row[8 + 15], job.cplx)
+            fused = job.cplx and bk["D"] ** 2 <= 64 and args.precision in ("bf16x3", "bf16x6")
+            for k, (fl, by) in env_work(R, bk["D"], job.p, job.cplx, fused).items():
+                a0, b0 = env.get(k, (0.0, 0.0))
+                env[k] = (a0 + fl * bk["n"] * job.bonds_per_item, b0 + by * bk["n"] * job.bonds_per_item)
+        fit_fl /= nst                                      # per step
+        rl = {}
+        for cls, (t_ms, n_l) in prof.items():
+            t = t_ms / nprof / 1e3                         # s per step
+            n_l = n_l / nprof
+            if cls == "bond_fit":
+                rl[cls] = {"kernel": kernel_of[cls], "bound": "alu", "achieved": fit_fl / t / 1e12,
+                           "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": fit_fl / t / PEAK_FP64,
+                           "flops_per_step": fit_fl}
+            elif cls in env:
+                fl, by = env[cls]
+                rl[cls] = {"kernel": kernel_of[cls], "bound": "mfma", "achieved": fl / t / 1e12,
+                           "peak": peak_mx / 1e12, "unit": "TFLOP/s", "frac": fl / t / peak_mx,
+                           "flops_per_step": fl, "issued_mfma_frac": issue * fl / t / peak_mx,
+                           "algorithmic_bytes_per_step": by, "algorithmic_GBps": by / t / 1e9}
+            else:
+                continue
+            rl[cls].update({"avg_launch_us": t / n_l * 1e6, "launches_per_step": n_l, "traffic": None})
+            rec = traffic_record(rl[cls]["kernel"].split(" ")[0])
+            if rec and rec.get("workload") == workload and rec.get("precision") == args.precision:
+                rl[cls]["traffic"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+                rl[cls]["traffic_source"] = "profiles/traffic.json"
+        dom = max((c for c in prof if c in rl), key=lambda c: prof[c][0], default=None)
+        return rl, dom
+
+    prof = profile_classes(args.profile_steps)
+    result["kernel_ms_per_step"] = {k: round(v[0] / nprof, 4) for k, v in
+                                    sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    rl, dom = rooflines(stm, K, prof, result["config"]["workload"])
     result["roofline"] = dict(rl.get(dom, {}), dominant_class=dom)
     result["roofline_by_class"] = rl
+
+    # the D=8 items of the same workload alone on the GPU (the bond dimension
+    # the metric names): both paths from the same state, rooflines without
+    # other buckets sharing the chip
+    if args.workload == "batched" and not args.bucket and any(bk["D"] == 8 for bk in job.buckets):
+        all_b, all_init = job.buckets, init
+        i8 = next(i for i, bk in enumerate(all_b) if bk["D"] == 8)
+        job.buckets, init = [all_b[i8]], [all_init[i8]]
+        try:
+            ms8, _, st8 = run(opts, K, keep_stats=True)
+            ms8_64 = None if args.no_fp64 else run(opts64, K)[0]
+            prof8 = profile_classes(args.profile_steps)
+            rl8, dom8 = rooflines(st8, K, prof8, None)
+        finally:
+            job.buckets, init = all_b, all_init
+        n8 = all_b[i8]["n"]
+        d8 = {"items": n8, "value": n8 * K / (ms8 / 1e3), "unit": "bond_updates/s", "ms_per_step": ms8 / K,
+              "dominant_class": dom8, "roofline_by_class": rl8}
+        if ms8_64 is not None:
+            d8["fp64_path_value"] = n8 * K / (ms8_64 / 1e3)
+            d8["speedup_vs_fp64_path"] = ms8_64 / ms8
+        result["d8_bucket"] = d8
 
     if not args.no_cpu:
         from oracle import ntu as O
