@@ -163,17 +163,34 @@ template <int PREC, int NPAD> struct E45 {
     }
   }
 
+  using BFrag = bf16x8[2][NP];
+
+  // the B fragments of K step ks (both column tiles of the wave)
+  static NTU_DEV void load_b(BFrag& b, const __bf16* __restrict__ F, int ks, int w, int lane) {
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        b[y][p] = *(const bf16x8*)(F + ((size_t)(((2 * w + y) * KS + ks) * NP + p) * 64 + lane) * 8);
+  }
+
   // acc = A B^T with A from the shared pieces sA (NPAD rows, 2 NPAD real
-  // columns) and B from prepared fragments F (layout of k_e45_prep)
-  static NTU_DEV void product(Acc& acc, const __bf16 (*sA)[NPAD][LD], const __bf16* __restrict__ F, int w, int lane) {
+  // columns) and B from prepared fragments F (layout of k_e45_prep); b0
+  // holds the fragments of the first K step, loaded by the caller ahead of
+  // time
+  static NTU_DEV void product(Acc& acc, const __bf16 (*sA)[NPAD][LD], const __bf16* __restrict__ F, int w, int lane,
+                              const BFrag& b0) {
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      bf16x8 b[2][NP];
+      BFrag b;
+      if (ks == 0) {
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < 2; ++y)
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
-          b[y][p] = *(const bf16x8*)(F + ((size_t)(((2 * w + y) * KS + ks) * NP + p) * 64 + lane) * 8);
+          for (int p = 0; p < NP; ++p) b[y][p] = b0[y][p];
+      } else {
+        load_b(b, F, ks, w, lane);
+      }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         bf16x8 a[NP];
@@ -261,18 +278,21 @@ __global__ void __launch_bounds__(NPAD * 4, 2) k_left_e45(int R, int K, int nwor
   if constexpr (n < NPAD)
     for (int e = tid; e < NP * NPAD * LD / 2; e += blockDim.x) ((unsigned*)&sA[0][0][0])[e] = 0u;
   typename S::Acc acc;
+  typename S::BFrag b0;
+  S::load_b(b0, F1, 0, w, lane);  // in flight during the Left block
   S::pair_product(acc, Qe, Qp, n, K, w, lane);
   __syncthreads();
   S::outputs(acc, w, lane, [&](int u, int up, float re, float im) {
     if (u < n && up < n) S::store_pieces(sA, (u / D) * D + up / D, (u % D) * D + up % D, re, im);
   });
   __syncthreads();
-  S::product(acc, sA, F1, w, lane);
+  S::product(acc, sA, F1, w, lane, b0);
+  S::load_b(b0, F2, 0, w, lane);  // in flight during the L1 hand-over
   __syncthreads();  // every wave has read the Left pieces
   // L1 (row b b', column j) -> A operand of the second product: row j, column b b'
   S::outputs(acc, w, lane, [&](int bb, int j, float re, float im) { S::store_pieces(sA, j, bb, re, im); });
   __syncthreads();
-  S::product(acc, sA, F2, w, lane);
+  S::product(acc, sA, F2, w, lane, b0);
   float* O = out + ((size_t)item * hs + (size_t)(q % R2) * n * n) * 2;
   if constexpr (n % 2 == 0) {
     // columns come in even-odd pairs: one 16-byte store per pair (n even keeps it aligned)

@@ -174,8 +174,15 @@ __global__ void __launch_bounds__(256) k_mfma_nt(const TA* __restrict__ A, const
 // operand staging.
 // VEC = 2: pairs of values per load (K and all row strides even).
 // ---------------------------------------------------------------------------
-constexpr int TL_M = 128, TL_N = 128, TL_K = 32, TL_LD = TL_K + 8;
+constexpr int TL_M = 128, TL_N = 128, TL_K = 32, TL_LD = TL_K;
 constexpr int TL_THREADS = 512, TL_WY = 2;  // 8 waves; each 64 x (16 TL_WY)
+
+// Shared-memory layout of an operand tile: unpadded rows of TL_K pieces (64
+// bytes, a quarter of the 64 four-byte banks), the four 16-byte chunks of row
+// r permuted by chunk ^ ((r >> 1) & 3).  The matrix-core reads (16-byte
+// chunks, lanes 0-7 with 16-23 served together, and so on) then meet each
+// bank once, and so do the 8-byte stores of four consecutive rows.
+NTU_DEV int tl_col(int row, int k) { return (((k >> 3) ^ ((row >> 1) & 3)) << 3) | (k & 7); }
 
 struct alignas(8) f2v { float v[2]; };
 struct alignas(16) d2v { double v[2]; };
@@ -205,9 +212,12 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
   constexpr int CW = CPLX ? 2 : 1;
   constexpr int NGA = TL_M * TL_K / 4 / TL_THREADS;          // groups of 4 reals of A per thread
   constexpr int NGB = CPLX ? NGA / 2 : NGA;                  // of B (complex rows give two real rows)
-  // one buffer for both operands (double-buffered); the output tile reuses it
+  // one buffer for both operands (double-buffered); the output tile of a
+  // 4-byte result (rows of TL_N + 1) reuses it
   constexpr int SA_EL = 2 * NT * TL_M * TL_LD, SB_EL = 2 * NT * TL_N * TL_LD;
-  __shared__ __attribute__((aligned(16))) E smem[SA_EL + SB_EL];
+  constexpr int OUT_EL = sizeof(TC) == 4 ? (int)(TL_M * (TL_N + 1) * sizeof(TC) / sizeof(E)) : 0;
+  constexpr int SM_EL = SA_EL + SB_EL > OUT_EL ? SA_EL + SB_EL : OUT_EL;
+  __shared__ __attribute__((aligned(16))) E smem[SM_EL];
   E (*sA)[NT][TL_M][TL_LD] = reinterpret_cast<E (*)[NT][TL_M][TL_LD]>(smem);
   E (*sB)[NT][TL_N][TL_LD] = reinterpret_cast<E (*)[NT][TL_N][TL_LD]>(smem + SA_EL);
   __shared__ long long rowoff[TL_M];
@@ -298,7 +308,7 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
         split_pair<PREC>(ra[u][0], ra[u][1], w0);
         split_pair<PREC>(ra[u][2], ra[u][3], w1);
 #pragma unroll
-        for (int p = 0; p < NT; ++p) *(uint2*)&sA[buf][p][arl[u]][akq[u]] = make_uint2(w0[p], w1[p]);
+        for (int p = 0; p < NT; ++p) *(uint2*)&sA[buf][p][arl[u]][tl_col(arl[u], akq[u])] = make_uint2(w0[p], w1[p]);
       }
 #pragma unroll
       for (int u = 0; u < NGB; ++u) {
@@ -306,23 +316,28 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
           // complex values (re0, im0), (re1, im1) -> real rows 2r: (re, -im), 2r+1: (im, re).
           // The pieces of (re, im) are split once; the pieces of -x are those
           // of x negated (sign bit), so row 2r flips the high halves and row
-          // 2r+1 swaps the halves.
+          // 2r+1 swaps the halves.  Complex rows 0, 1, 2, 3 store real rows
+          // 0, 3, 5, 6 first (one row per bank quarter), then 1, 2, 4, 7.
           const float s = d.conjB ? -1.0f : 1.0f;
           unsigned w0[NT], w1[NT];
           split_pair<PREC>(rb[u][0], s * rb[u][1], w0);
           split_pair<PREC>(rb[u][2], s * rb[u][3], w1);
+          const int odd_first = (brl[u] ^ (brl[u] >> 1)) & 1;
+          const int r0 = 2 * brl[u] + odd_first, r1 = 2 * brl[u] + 1 - odd_first;
+          const int c0 = tl_col(r0, bkq[u]), c1 = tl_col(r1, bkq[u]);
 #pragma unroll
           for (int p = 0; p < NT; ++p) {
-            *(uint2*)&sB[buf][p][2 * brl[u]][bkq[u]] = make_uint2(w0[p] ^ 0x80000000u, w1[p] ^ 0x80000000u);
-            *(uint2*)&sB[buf][p][2 * brl[u] + 1][bkq[u]] =
-                make_uint2((w0[p] >> 16) | (w0[p] << 16), (w1[p] >> 16) | (w1[p] << 16));
+            const uint2 neg = make_uint2(w0[p] ^ 0x80000000u, w1[p] ^ 0x80000000u);
+            const uint2 swp = make_uint2((w0[p] >> 16) | (w0[p] << 16), (w1[p] >> 16) | (w1[p] << 16));
+            *(uint2*)&sB[buf][p][r0][c0] = odd_first ? swp : neg;
+            *(uint2*)&sB[buf][p][r1][c1] = odd_first ? neg : swp;
           }
         } else {
           unsigned w0[NT], w1[NT];
           split_pair<PREC>(rb[u][0], rb[u][1], w0);
           split_pair<PREC>(rb[u][2], rb[u][3], w1);
 #pragma unroll
-          for (int p = 0; p < NT; ++p) *(uint2*)&sB[buf][p][brl[u]][bkq[u]] = make_uint2(w0[p], w1[p]);
+          for (int p = 0; p < NT; ++p) *(uint2*)&sB[buf][p][brl[u]][tl_col(brl[u], bkq[u])] = make_uint2(w0[p], w1[p]);
         }
       }
     } else {
@@ -334,7 +349,7 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
 #pragma unroll
         for (int p = 0; p < NT; ++p)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) sA[buf][p][arl[u]][akq[u] + e] = t[e][p];
+          for (int e = 0; e < 4; ++e) sA[buf][p][arl[u]][tl_col(arl[u], akq[u]) + e] = t[e][p];
       }
 #pragma unroll
       for (int u = 0; u < NGB; ++u) {
@@ -353,8 +368,8 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
           for (int p = 0; p < NT; ++p)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              sB[buf][p][2 * brl[u]][bkq[u] + e] = t0[e][p];
-              sB[buf][p][2 * brl[u] + 1][bkq[u] + e] = t1[e][p];
+              sB[buf][p][2 * brl[u]][tl_col(2 * brl[u], bkq[u]) + e] = t0[e][p];
+              sB[buf][p][2 * brl[u] + 1][tl_col(2 * brl[u] + 1, bkq[u]) + e] = t1[e][p];
             }
         } else {
           E t[4][NT];
@@ -363,7 +378,7 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
 #pragma unroll
           for (int p = 0; p < NT; ++p)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) sB[buf][p][brl[u]][bkq[u] + e] = t[e][p];
+            for (int e = 0; e < 4; ++e) sB[buf][p][brl[u]][tl_col(brl[u], bkq[u]) + e] = t[e][p];
         }
       }
     }
@@ -383,6 +398,9 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
   lstore(0);
   __syncthreads();
   const int fr = lane & 15, fk = (lane >> 4) * 8;
+  // the 16-byte chunk this lane reads from each of its rows (tile rows are
+  // multiples of 16 plus fr, so the permutation depends on fr alone)
+  const int fks = tl_col(fr, fk);
   for (int s = 0; s < nsteps; ++s) {
     const int buf = s & 1;
     if (s + 1 < nsteps) gload(kbeg + (s + 1) * TL_K);
@@ -392,16 +410,16 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
 #pragma unroll
       for (int y = 0; y < TL_WY; ++y) {
         const int rb_ = wn * (16 * TL_WY) + y * 16 + fr;
-        const E* a0 = &sA[buf][0][ra_][fk];
-        const E* a1 = &sA[buf][1][ra_][fk];
-        const E* b0 = &sB[buf][0][rb_][fk];
-        const E* b1 = &sB[buf][1][rb_][fk];
+        const E* a0 = &sA[buf][0][ra_][fks];
+        const E* a1 = &sA[buf][1][ra_][fks];
+        const E* b0 = &sB[buf][0][rb_][fks];
+        const E* b1 = &sB[buf][1][rb_][fks];
         acc[0][x][y] = mfma<PREC>(a0, b0, acc[0][x][y]);
         acc[1][x][y] = mfma<PREC>(a0, b1, acc[1][x][y]);
         acc[1][x][y] = mfma<PREC>(a1, b0, acc[1][x][y]);
         if constexpr (PREC == NTU_PREC_BF16X6) {
-          const E* a2 = &sA[buf][2][ra_][fk];
-          const E* b2 = &sB[buf][2][rb_][fk];
+          const E* a2 = &sA[buf][2][ra_][fks];
+          const E* b2 = &sB[buf][2][rb_][fks];
           acc[2][x][y] = mfma<PREC>(a0, b2, acc[2][x][y]);
           acc[2][x][y] = mfma<PREC>(a1, b1, acc[2][x][y]);
           acc[2][x][y] = mfma<PREC>(a2, b0, acc[2][x][y]);
@@ -420,7 +438,7 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
       // row-major if consecutive real columns are adjacent, else column-major
       // (complex: (re, im) of consecutive rows adjacent)
       constexpr int OLD = TL_N + 1;
-      static_assert(TL_M * OLD * sizeof(TC) <= (SA_EL + SB_EL) * sizeof(E), "output tile must fit the operand buffers");
+      static_assert(TL_M * OLD * sizeof(TC) <= SM_EL * sizeof(E), "output tile must fit the shared buffer");
       TC* ot = (TC*)smem;
 #pragma unroll
       for (int x = 0; x < 4; ++x)
