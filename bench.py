@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--workload", default="batched", choices=["batched", "thermal"])
     ap.add_argument("--precision", default="bf16x6", choices=["bf16x3", "bf16x6", "fp16x3", "f64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
+    ap.add_argument("--no-d8", action="store_true",
+                    help="skip the second measurement of the D=8 items alone (profiles of the whole-workload step)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-steps", type=int, default=1)
@@ -389,7 +391,8 @@ def main():
     # the D=8 items of the same workload alone on the GPU (the bond dimension
     # the metric names): both paths from the same state, rooflines without
     # other buckets sharing the chip
-    if args.workload == "batched" and not args.bucket and any(bk["D"] == 8 for bk in job.buckets):
+    if (args.workload == "batched" and not args.bucket and not args.no_d8
+            and any(bk["D"] == 8 for bk in job.buckets)):
         all_b, all_init = job.buckets, init
         i8 = next(i for i, bk in enumerate(all_b) if bk["D"] == 8)
         job.buckets, init = [all_b[i8]], [all_init[i8]]
