@@ -282,7 +282,8 @@ def main():
                             "h_x": "uniform [2.5, 3.5]", "dt": 0.01, "env_precision": args.precision,
                             "fit": "fp64, <=20 ALS iterations, early stop 1e-12 N",
                             "storage": "values drawn as complex64, hot path in complex128",
-                            "streams": f"one per D bucket, {HW_QUEUES} hardware queues"}
+                            "streams": (f"one per D bucket, side streams {'one shared' if args.aux == 'shared' else 'one per bucket'}, "
+                                        f"{args.hw_queues} hardware queues")}
     else:
         result["config"] = {"workload": "configuration 3: thermal purification, D=8, p=4, real", "D": 8,
                             "h_x": 2.5, "dbeta": 0.005, "env_precision": args.precision,

@@ -389,6 +389,26 @@ def bond_update(X, Y, nbr, GA, GB, D, d=2, n_iter=20, conv_tol=None, clip=True,
     return Xn, Yn, info
 
 
+def svdu_update(X, Y, GA, GB, D, d=2, kappa=KAPPA):
+    """SVDU update of the bond ``X.r - Y.l`` (Fig. 2, no environment): the
+    reduction of both sides (Fig. 2(b)), the truncated SVD of ``P = RX RY^T``
+    (Fig. 2(c,d)), the same normalisation of the kept singular values by the
+    largest as at the end of the NTU update (Fig. 5(d)), recombination
+    (Fig. 2(e)).  Returns new ``X', Y'`` and diagnostics."""
+    QX, RX = reduce_site(X, GA, 'X', d, kappa)
+    QY, RY = reduce_site(Y, GB, 'Y', d, kappa)
+    P, MX, MY, S_svdu, Dn = svdu_guess(RX, RY, D, kappa)
+    if Dn == 0:
+        MXb = np.zeros((RX.shape[0], D), dtype=QX.dtype)
+        MYb = MXb.copy()
+        S, Dk = np.zeros(D), 0
+    else:
+        MXb, MYb, S, Dk = balance(MX, MY, D, kappa)
+    Xn, Yn = recombine(QX, QY, MXb, MYb)
+    info = dict(QX=QX, QY=QY, RX=RX, RY=RY, P=P, S_svdu=S_svdu, Dn=Dn, S=S, Dk=Dk, MX=MXb, MY=MYb)
+    return Xn, Yn, info
+
+
 def rot_cw(T):
     """Rotate a site tensor by 90 degrees clockwise: new (t, l, b, r) = old (l, b, r, t)."""
     return T.transpose(0, 2, 3, 4, 1)
@@ -410,9 +430,10 @@ BONDS = ('H1', 'H2', 'V1', 'V2')
 
 
 def trotter_step(A, B, gate_factors, D, d=2, n_iter=20, conv_tol=None, clip=True,
-                 order=BONDS):
+                 order=BONDS, scheme='ntu'):
     """One first-order Trotter step: NTU updates of the four inequivalent bonds
-    of the checkerboard in ``order`` (default H1, H2, V1, V2).
+    of the checkerboard in ``order`` (default H1, H2, V1, V2); ``scheme='svdu'``
+    makes every update an SVDU update (:func:`svdu_update`).
 
     H1: X=A, Y=B (A.r - B.l); H2: X=B, Y=A.  V1/V2 are H1/H2 after rotating
     both tensors clockwise (A.t - B.b and B.t - A.b).  ``gate_factors[bond] =
@@ -424,8 +445,11 @@ def trotter_step(A, B, gate_factors, D, d=2, n_iter=20, conv_tol=None, clip=True
         vertical = bond[0] == 'V'
         a, b = (rot_cw(A), rot_cw(B)) if vertical else (A, B)
         X, Y, nbr = _cluster(bond[1] == '1', a, b)
-        Xn, Yn, info = bond_update(X, Y, nbr, GA, GB, D, d=d, n_iter=n_iter,
-                                   conv_tol=conv_tol, clip=clip)
+        if scheme == 'svdu':
+            Xn, Yn, info = svdu_update(X, Y, GA, GB, D, d=d)
+        else:
+            Xn, Yn, info = bond_update(X, Y, nbr, GA, GB, D, d=d, n_iter=n_iter,
+                                       conv_tol=conv_tol, clip=clip)
         an, bn = (Xn, Yn) if bond[1] == '1' else (Yn, Xn)
         if vertical:
             an, bn = rot_ccw(an), rot_ccw(bn)
