@@ -30,6 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "NTU bond updates/sec at D=8, mixed-precision vs FP64 GPU path, at 1e-6 rel err"
+METRIC_SVDU = "SVDU bond updates/sec (reduction, truncated SVD, recombination; no environment)"
 PEAK_BF16 = 2.5e15       # dense MFMA, FLOP/s
 PEAK_FP64 = 78.6e12      # FLOP/s (vector and matrix)
 PEAK_HBM = 8.0e12        # B/s
@@ -43,6 +44,8 @@ def parse():
     ap.add_argument("--workload", default="batched", choices=["batched", "thermal"])
     ap.add_argument("--precision", default="bf16x6", choices=["bf16x3", "bf16x6", "fp16x3", "f64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
+    ap.add_argument("--scheme", default="ntu", choices=["ntu", "svdu"],
+                    help="bond-update scheme: full NTU, or the SVDU update (no environment; implies --no-fp64 --no-d8)")
     ap.add_argument("--no-d8", action="store_true",
                     help="skip the second measurement of the D=8 items alone (profiles of the whole-workload step)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -215,7 +218,9 @@ def main():
         for bk in job.buckets:
             bk["ctx"].set_aux_stream(job.aux)
     fit = dict(n_iter=20, early_stop=True, conv_tol=1e-12)
-    opts = ntu.step_opts(args.precision, order=job.order, **fit)
+    if args.scheme == "svdu":
+        args.no_fp64 = args.no_d8 = True
+    opts = ntu.step_opts(args.precision, order=job.order, scheme=args.scheme, **fit)
     opts64 = ntu.step_opts("f64", order=job.order, **fit)
 
     def steps_on_buckets(state, o, keep_stats, nsteps):
@@ -262,7 +267,7 @@ def main():
     ms, state_m, stm = run(opts, K, keep_stats=True)
     upd = job.n_updates
     result = {
-        "metric": METRIC,
+        "metric": METRIC if args.scheme == "ntu" else METRIC_SVDU,
         "value": upd * K / (ms / 1e3),
         "unit": "bond_updates/s",
         "n_gpus": 1,
@@ -280,7 +285,9 @@ def main():
                             + (f", only the D={args.bucket} items" if args.bucket else ""),
                             "items": upd, "D_counts": {str(bk["D"]): bk["n"] for bk in job.buckets},
                             "h_x": "uniform [2.5, 3.5]", "dt": 0.01, "env_precision": args.precision,
-                            "fit": "fp64, <=20 ALS iterations, early stop 1e-12 N",
+                            "fit": ("fp64, <=20 ALS iterations, early stop 1e-12 N" if args.scheme == "ntu"
+                                    else "none (SVDU scheme)"),
+                            "scheme": args.scheme,
                             "storage": "values drawn as complex64, hot path in complex128",
                             "streams": (f"one per D bucket, side streams {'one shared' if args.aux == 'shared' else 'one per bucket'}, "
                                         f"{args.hw_queues} hardware queues")}
@@ -330,6 +337,7 @@ def main():
     issue = 1 if args.precision == "f64" else (3 if args.precision in ("bf16x3", "fp16x3") else 6)
     peak_mx = PEAK_FP64 if args.precision == "f64" else PEAK_BF16
     kernel_of = {"bond_fit": "k_bond_fit", "env_left_right": "k_right", "env_e4": "k_left_e45",
+                 "reduce_qr": "k_reduce_cholqr", "recombine": "k_recombine",
                  "env_e5": "k_mfma_tile (L2)", "env_e6": "k_mfma_tile (g = L2 Right^T)"}
 
     def profile_classes(steps):
@@ -358,11 +366,27 @@ def main():
                 a0, b0 = env.get(k, (0.0, 0.0))
                 env[k] = (a0 + fl * bk["n"] * job.bonds_per_item, b0 + by * bk["n"] * job.bonds_per_item)
         fit_fl /= nst                                      # per step
+        # HBM classes, algorithmic bytes per step: the reduction reads both
+        # site tensors and writes Q and R of both sides; the recombination
+        # reads Q and M of both sides and writes both site tensors
+        hbm = {"reduce_qr": 0.0, "recombine": 0.0}
+        for bk in job.buckets:
+            D, R, el = bk["D"], 2 * bk["D"], 16 if job.cplx else 8
+            site, q = job.p * D ** 4, job.p * D ** 3 * R
+            nb = bk["n"] * job.bonds_per_item
+            hbm["reduce_qr"] += nb * el * 2 * (site + q + R * R)
+            hbm["recombine"] += nb * el * 2 * (q + R * D + site)
         rl = {}
         for cls, (t_ms, n_l) in prof.items():
             t = t_ms / nprof / 1e3                         # s per step
             n_l = n_l / nprof
-            if cls == "bond_fit":
+            if cls in hbm:
+                rl[cls] = {"kernel": kernel_of[cls], "bound": "hbm", "achieved": hbm[cls] / t / 1e9,
+                           "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": hbm[cls] / t / PEAK_HBM,
+                           "algorithmic_bytes_per_step": hbm[cls]}
+            elif cls == "bond_fit" and args.scheme == "svdu":
+                continue
+            elif cls == "bond_fit":
                 rl[cls] = {"kernel": kernel_of[cls], "bound": "alu", "achieved": fit_fl / t / 1e12,
                            "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": fit_fl / t / PEAK_FP64,
                            "flops_per_step": fit_fl}
@@ -417,23 +441,29 @@ def main():
         t0 = time.perf_counter()
         n_bonds = 0
         if args.workload == "batched":
-            for it in job.items:
-                if time.perf_counter() - t0 > args.cpu_seconds:
-                    break
+            # the items in order (SVDU updates are cheap: cycle through them
+            # until the time budget is spent)
+            while time.perf_counter() - t0 < args.cpu_seconds and (args.scheme == "svdu" or n_bonds < len(job.items)):
+                it = job.items[n_bonds % len(job.items)]
                 GAo, GBo, _ = O.gate_split(it["gate"], 2, 2)
                 A = it["A"].astype(np.complex128)
                 B = it["B"].astype(np.complex128)
                 X, Y, nbr = O._cluster(True, A, B)
-                O.bond_update(X, Y, nbr, GAo, GBo, it["D"], n_iter=20, conv_tol=1e-12)
+                if args.scheme == "svdu":
+                    O.svdu_update(X, Y, GAo, GBo, it["D"])
+                else:
+                    O.bond_update(X, Y, nbr, GAo, GBo, it["D"], n_iter=20, conv_tol=1e-12)
                 n_bonds += 1
-            sample = f"first {n_bonds} of the 256 items in order (mixed D), oracle FP64 numpy/BLAS"
+            sample = (f"{n_bonds} of the 256 items in order (mixed D), "
+                      f"oracle FP64 numpy/BLAS{', SVDU updates' if args.scheme == 'svdu' else ''}")
         else:
             An, Bn = init[0][0].cpu().numpy()[0], init[0][1].cpu().numpy()[0]
             GAo, GBo, _ = O.gate_split(job.w["gates"][0], 2, 2)
             pairs = {b: (GAo, GBo) for b in O.BONDS}
             while n_bonds < 16 and time.perf_counter() - t0 < args.cpu_seconds:
                 for b in O.BONDS:
-                    An, Bn, _ = O.trotter_step(An, Bn, pairs, 8, n_iter=20, conv_tol=1e-12, order=(b,))
+                    An, Bn, _ = O.trotter_step(An, Bn, pairs, 8, n_iter=20, conv_tol=1e-12, order=(b,),
+                                                scheme=args.scheme)
                     n_bonds += 1
             sample = f"{n_bonds} bond updates of the D=8 thermal state, oracle FP64 numpy/BLAS"
         el = time.perf_counter() - t0

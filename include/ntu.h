@@ -73,6 +73,11 @@ enum {
 
 /* metric repair modes (ntu_metric_fix) */
 enum { NTU_FIX_HERM = 0, NTU_FIX_HERM_CLIP = 1 };
+/* Bond-update scheme of a Trotter step: the full NTU update, or the SVDU
+ * update of Fig. 2 (reduction, truncated SVD of R_X R_Y^T, recombination; no
+ * environment), with the singular values normalised by the largest as at the
+ * end of the NTU update (Fig. 5(d)). */
+enum { NTU_SCHEME_NTU = 0, NTU_SCHEME_SVDU = 1 };
 
 /* the four inequivalent bonds of the two-site checkerboard */
 enum { NTU_BOND_H1 = 0, NTU_BOND_H2 = 1, NTU_BOND_V1 = 2, NTU_BOND_V2 = 3 };
@@ -247,6 +252,7 @@ typedef struct ntu_step_opts {
   int precision;        /* NTU_PREC_* for the environment contraction          */
   int fix_mode;         /* NTU_FIX_*                                            */
   ntu_fit_opts fit;
+  int scheme;           /* NTU_SCHEME_* (default NTU)                           */
 } ntu_step_opts;
 
 void ntu_step_opts_default(ntu_step_opts* o);
@@ -267,6 +273,11 @@ void ntu_step_opts_default(ntu_step_opts* o);
  *   factors (GA, GB) of its gate, GA acting on X.  Items are independent.
  * stats (device, may be NULL): batch x n_bonds x NTU_STEP_STATS_LEN doubles:
  *   [0..7] metric stats of the update, then the bond-fit stats.
+ * With opts->scheme == NTU_SCHEME_SVDU every update is an SVDU update (no
+ *   environment, metric repair or ALS fit; precision, fix_mode and the fit's
+ *   n_iter, conv_tol and ladder are not used, kappa is): the fit stats then
+ *   hold N = eps = 0, D_n, D_k and the normalised singular values, and the
+ *   metric stats [0..7] are not written.
  */
 ntu_status ntu_trotter_step(ntu_ctx* ctx, int batch, int D, void* A, void* B,
                             const void* gate_factors, const ntu_step_opts* opts, double* stats);

@@ -186,6 +186,7 @@ void ntu_step_opts_default(ntu_step_opts* o) {
   o->precision = NTU_PREC_F64;
   o->fix_mode = NTU_FIX_HERM_CLIP;
   ntu_fit_opts_default(&o->fit);
+  o->scheme = NTU_SCHEME_NTU;
 }
 
 ntu_status ntu_ctx_create(ntu_ctx** out, int device, int dtype, int d, int d_anc, int r_g, int max_D,
@@ -360,6 +361,7 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
   if (opts->precision < NTU_PREC_F64 || opts->precision > NTU_PREC_BF16X6) return fail(c, NTU_ERR_ARG, "unknown precision");
   if (opts->fix_mode != NTU_FIX_HERM && opts->fix_mode != NTU_FIX_HERM_CLIP) return fail(c, NTU_ERR_ARG, "unknown fix mode");
   if ((s = check_fit_opts(c, &opts->fit))) return s;
+  if (opts->scheme != NTU_SCHEME_NTU && opts->scheme != NTU_SCHEME_SVDU) return fail(c, NTU_ERR_ARG, "unknown scheme");
   if (batch == 0 || opts->n_bonds == 0) return NTU_OK;
   if (!A || !B || !gate_factors) return fail(c, NTU_ERR_ARG, "NULL pointer");
   DeviceGuard guard(c->device);
@@ -410,6 +412,26 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     char* Y = x_is_a ? b : a;
     const char* gA = (const char*)gate_factors + (size_t)(bond * 2 + 0) * gfs * el;
     const char* gB = (const char*)gate_factors + (size_t)(bond * 2 + 1) * gfs * el;
+    // new X -> (A or B), new Y -> the other, rotated back for vertical bonds
+    void* outX = x_is_a ? A : B;
+    void* outY = x_is_a ? B : A;
+    if (opts->scheme == NTU_SCHEME_SVDU) {
+      // SVDU update (Fig. 2): reduction, truncated SVD of RX RY^T, the fit's
+      // balancing without a metric, recombination; all on the context stream
+      double* sb = stats ? stats + (size_t)bi * sl : nullptr;
+      ph(ntu::PK_REDUCE, 0);
+      NTU_STEP(ntu::launch_reduce_qr_pair(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, Y, gB, gf_item, QX, RX, QY,
+                                          RY, opts->fit.kappa, todo, c->stream), "reduce_qr");
+      ph(ntu::PK_REDUCE, 1);
+      NTU_STEP(ntu::launch_svdu_guess(cp, batch, D, R, RX, RY, opts->fit.kappa, guess, c->stream), "svdu_guess");
+      NTU_STEP(ntu::launch_bond_fit(cp, batch, D, R, nullptr, RX, RY, fp, MX, MY, sb ? sb + 8 : nullptr, (int)s_item,
+                                    c->ws, c->stream, ph, nullptr, guess), "bond_fit");
+      ph(ntu::PK_RECOMB, 0);
+      NTU_STEP(ntu::launch_recombine(cp, batch, p, D, R, QX, QY, MX, MY, outX, outY, vertical ? 1 : 0, c->stream),
+               "recombine");
+      ph(ntu::PK_RECOMB, 1);
+      continue;
+    }
     // The side stream (aux) takes the work that does not need the reduction:
     // the edge tensors and transfers (they read only the neighbours) while
     // the reduction runs, then the fit's SVDU guess (it needs only RX, RY)
@@ -447,9 +469,6 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     NTU_STEP(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join");
     NTU_STEP(ntu::launch_bond_fit(cp, batch, D, R, G, RX, RY, fp, MX, MY, sb ? sb + 8 : nullptr, (int)s_item, c->ws,
                                   c->stream, ph, clip ? cert : nullptr, guess), "bond_fit");
-    // new X -> (A or B), new Y -> the other, rotated back for vertical bonds
-    void* outX = x_is_a ? A : B;
-    void* outY = x_is_a ? B : A;
     ph(ntu::PK_RECOMB, 0);
     NTU_STEP(ntu::launch_recombine(cp, batch, p, D, R, QX, QY, MX, MY, outX, outY, vertical ? 1 : 0, c->stream),
              "recombine");

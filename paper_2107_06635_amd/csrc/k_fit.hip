@@ -776,7 +776,9 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   __shared__ int flag;
   const int it = blockIdx.x, tid = threadIdx.x;
   const int n = R * R;
-  const T* G = g + (size_t)it * n * n;
+  // without a metric (g == NULL: the SVDU scheme) the fit returns the
+  // balanced SVDU guess: no certificate, no error, no iterations
+  const T* G = g ? g + (size_t)it * n * n : nullptr;
   T* W = ws + (size_t)it * fit_ws_elems(D, R);
   T* G1 = W;
   T* gs = G1 + (size_t)n * R * D;
@@ -820,7 +822,8 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   bool certified = false;
   const bool cert_fits = (long long)n * n <= (long long)n * R * D + 3LL * R * D * R * D;
   int cert_kind = 0;  // 1: Gershgorin discs, 2: shifted Cholesky, 3: by the metric repair
-  if (cert) {
+  if (!G) {
+  } else if (cert) {
     // the metric repair already tested the same two certificates on this g
     certified = R * D <= FAST_NX && cert[it] > 0.5;
     if (certified) cert_kind = 3;
@@ -828,7 +831,7 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
     if (R * D <= FAST_NX) certified = gershgorin_certify<T>(G, n, 10.0 * fp.tol[fp.n_tol - 1], S.red);
     if (certified) cert_kind = 1;
   }
-  if (!cert && !certified && n <= FIT_CERT_NMAX && R * D <= FAST_NX && cert_fits) {
+  if (G && !cert && !certified && n <= FIT_CERT_NMAX && R * D <= FAST_NX && cert_fits) {
     T* Wc = W;  // n^2 elements fit in G1 .. X (cert_fits)
     double fro = 0;
     for (long long e = tid; e < (long long)n * n; e += blockDim.x) fro += abs2(G[e]);
@@ -880,11 +883,13 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   }
   // g y and N
   __syncthreads();
-  fit_matvec<T>(G, n, S.y, gy, S.sa);
-  double N = 0;
-  for (int r = tid; r < n; r += blockDim.x) N += rev(cmul(S.y[r], gy[r]));
-  N = block_sum(N, S.red);
-  double eps = Dn > 0 ? fit_error<T>(G, R, Dn, S, dv, gd) : 0.0;
+  double N = 0, eps = 0.0;
+  if (G) {
+    fit_matvec<T>(G, n, S.y, gy, S.sa);
+    for (int r = tid; r < n; r += blockDim.x) N += rev(cmul(S.y[r], gy[r]));
+    N = block_sum(N, S.red);
+    eps = Dn > 0 ? fit_error<T>(G, R, Dn, S, dv, gd) : 0.0;
+  }
   if (st && tid == 0) {
     const int len = fit_stats_len(fp.n_iter, D);
     for (int i = 0; i < len; ++i) st[i] = 0.0;
@@ -894,7 +899,7 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   int iters = 0, n_eig = 0;
   double prev = eps;
   tick(0);
-  for (int iter = 0; iter < fp.n_iter && Dn > 0; ++iter) {
+  for (int iter = 0; iter < fp.n_iter && Dn > 0 && G; ++iter) {
     for (int half = 0; half < 2; ++half) {
       // fixed factor F (MY for the X half-step, MX for the Y half-step), made isometric
       const T* F = half == 0 ? S.MY : S.MX;

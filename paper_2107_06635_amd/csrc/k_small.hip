@@ -194,6 +194,175 @@ __global__ void __launch_bounds__(QR_THREADS) k_reduce_qr(int d, int na, int D, 
 
 
 // ---------------------------------------------------------------------------
+// The same Gram-Schmidt QR with W held in registers: thread t of NT owns
+// rows t, t + NT, ... (RPT of them, R <= QRR_RMAX columns each), so each
+// projection pass is register arithmetic plus one block reduction of a fixed
+// number of partial sums, with no sweep over W in memory.  Taken when the
+// rows fit (p D^3 <= RPT NT with the configurations of reduce_launch); same
+// steps, projection twice, same rank rule.
+// ---------------------------------------------------------------------------
+constexpr int QRR_RMAX = 16;
+
+// n partial sums per thread (registers) summed over the block into out[0..n)
+template <int N> NTU_DEV void block_sum_fixed(const double (&vals)[N], double* red, double* out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double v = wave_sum(vals[i]);
+    if (lane == 0) red[w * 64 + i] = v;
+    __builtin_amdgcn_sched_barrier(0);  // one reduction at a time (register pressure)
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    double sum = 0.0;
+    for (int k = 0; k < nw; ++k) sum += red[k * 64 + i];
+    out[i] = sum;
+  }
+  __syncthreads();
+}
+
+template <class T, class S, int RPT, int NT>
+__global__ void __launch_bounds__(NT) k_reduce_qr_reg(int d, int na, int D, int rg, const S* site,
+                                                              const T* gf, long long gf_stride, int side, T* Q,
+                                                              T* Rm, double kappa, const int* todo,
+                                                              ReduceY<T, S> yside) {
+  constexpr int NC = is_cplx<T>::value ? 2 : 1, RM = QRR_RMAX;
+  __shared__ double red[16 * 64];
+  __shared__ double hv[NC * RM];
+  __shared__ double cacc[NC * RM];
+  if (blockIdx.y == 1) {  // the Y side of a two-sided launch
+    site = yside.site; gf = yside.gf; Q = yside.Q; Rm = yside.R; side = 1;
+  }
+  const int it = blockIdx.x, tid = threadIdx.x, ti = blockIdx.y * gridDim.x + blockIdx.x;
+  if (todo && todo[ti] == 0) return;  // done by the Cholesky QR
+  const int p = d * na, R = D * rg;
+  const long long D2 = (long long)D * D, D3 = D2 * D, D4 = D3 * D;
+  const long long nrow = p * D3;
+  const S* X = site + (size_t)it * p * D4;
+  const T* G = gf + (size_t)it * gf_stride;
+  T* Qi = Q + (size_t)it * nrow * R;
+  T* Ri = Rm + (size_t)it * R * R;
+  for (int e = tid; e < R * R; e += blockDim.x) Ri[e] = zerov<T>();
+
+  // 1. W into Q (row-major nrow x R), then this thread's rows into registers
+  for (long long e = tid; e < nrow * R; e += blockDim.x) {
+    const long long row = e / R;
+    const int col = (int)(e % R), q = col / rg, kk = col % rg;
+    const int i4 = (int)(row % D), i3 = (int)((row / D) % D), t = (int)((row / D2) % D);
+    const int pa = (int)(row / D3), sp = pa / na, a = pa % na;
+    T v = zerov<T>();
+    for (int s2 = 0; s2 < d; ++s2) {
+      const long long base = (long long)(s2 * na + a) * D4 + t * D3;
+      // X side: rows (s',a,t,l=i3,b=i4), bond = r = q ; Y side: rows (s',a,t,b=i3,r=i4), bond = l = q
+      const long long off = side == 0 ? base + i3 * D2 + i4 * D + q : base + q * D2 + i3 * D + i4;
+      v += G[(sp * d + s2) * rg + kk] * load_site<T>(X, off);
+    }
+    Qi[e] = v;
+  }
+  __syncthreads();
+  T w[RPT][RM];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const long long row = tid + (long long)k * NT;
+#pragma unroll
+    for (int j = 0; j < RM; ++j) w[k][j] = (row < nrow && j < R) ? Qi[row * R + j] : zerov<T>();
+  }
+
+  // 2. largest column norm
+  double part[RM];
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    part[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) part[j] += abs2(w[k][j]);
+  }
+  block_sum_fixed<RM>(part, red, hv);
+  double scale = 0.0;
+  for (int j = 0; j < R; ++j) scale = fmax(scale, sqrt(hv[j]));
+
+  // 3. Gram-Schmidt, projection twice (column j picked out of the registers
+  // by comparison, so that every index into w stays a constant)
+  for (int j = 0; j < R; ++j) {
+    if (tid < NC * RM) cacc[tid] = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      double hp[NC * RM];
+#pragma unroll
+      for (int i = 0; i < NC * RM; ++i) hp[i] = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        T qj = zerov<T>();
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+          if (i == j) qj = w[k][i];
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+          if (i < j) {
+            const T h = cmul(w[k][i], qj);
+            hp[NC * i] += rev(h);
+            if constexpr (NC == 2) hp[NC * i + 1] += imv(h);
+          }
+      }
+      block_sum_fixed<NC * RM>(hp, red, hv);
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        T v = zerov<T>();
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+          if (i == j) v = w[k][i];
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+          if (i < j) {
+            T h;
+            if constexpr (NC == 2) h = T{hv[2 * i], hv[2 * i + 1]};
+            else h = realv<T>(hv[i]);
+            v -= w[k][i] * h;
+            // keeps the next coefficient's load below this use, so that the
+            // coefficients are not all held in registers beside the rows
+            __builtin_amdgcn_sched_barrier(0);
+          }
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+          if (i == j) w[k][i] = v;
+      }
+      if (tid < NC * j) cacc[tid] += hv[tid];
+    }
+    double nn[1] = {0.0};
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+#pragma unroll
+      for (int i = 0; i < RM; ++i)
+        if (i == j) nn[0] += abs2(w[k][i]);
+    block_sum_fixed<1>(nn, red, hv);
+    const double norm = sqrt(hv[0]);
+    const bool keep = scale > 0.0 && norm > kappa * scale;
+    const double inv = keep ? 1.0 / norm : 0.0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+#pragma unroll
+      for (int i = 0; i < RM; ++i)
+        if (i == j) w[k][i] = w[k][i] * inv;
+    if (tid == 0) {
+      Ri[j * R + j] = realv<T>(keep ? norm : 0.0);
+      for (int i = 0; i < j; ++i) {
+        if constexpr (NC == 2) Ri[i * R + j] = T{cacc[2 * i], cacc[2 * i + 1]};
+        else Ri[i * R + j] = realv<T>(cacc[i]);
+      }
+    }
+  }
+
+  // 4. Q rows
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const long long row = tid + (long long)k * NT;
+    if (row < nrow)
+#pragma unroll
+      for (int j = 0; j < RM; ++j)
+        if (j < R) Qi[row * R + j] = w[k][j];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Reduction by Cholesky QR, applied twice (three sweeps over W instead of two
 // per column).  W is formed in chunks of rows staged in shared memory; the
 // Gram matrix W^H W = R1^H R1 gives Q1 = W R1^{-1}, and the same step on Q1
@@ -383,8 +552,23 @@ static void reduce_launch(int batch, int sides, int d, int na, int D, int rg, co
   if (todo)
     hipLaunchKernelGGL((k_reduce_cholqr<T, S>), g, dim3(CQR_THREADS), 0, st, d, na, D, rg, (const S*)site,
                        (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, todo, y);
-  hipLaunchKernelGGL((k_reduce_qr<T, S>), g, dim3(QR_THREADS), 0, st, d, na, D, rg, (const S*)site, (const T*)gf,
-                     gf_stride, side, (T*)Q, (T*)R, kappa, (const int*)todo, y);
+  // Gram-Schmidt for the items the Cholesky QR left (all items without todo):
+  // rows in registers when they fit (real: up to 2048 rows, complex: up to
+  // 1024), else the version that sweeps W in memory
+  constexpr int NC = is_cplx<T>::value ? 2 : 1;
+  const long long nrow = (long long)d * na * D * D * D;
+  const bool cols = D * rg <= QRR_RMAX;
+#define NTU_QRR(RPT_, NT_)                                                                                         \
+  hipLaunchKernelGGL((k_reduce_qr_reg<T, S, RPT_, NT_>), g, dim3(NT_), 0, st, d, na, D, rg, (const S*)site,         \
+                     (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, (const int*)todo, y)
+  if (cols && nrow <= 512) NTU_QRR(1, 512);
+  else if (cols && NC == 1 && nrow <= 1024) NTU_QRR(2, 512);
+  else if (cols && NC == 1 && nrow <= 2048) NTU_QRR(2, 1024);
+  else if (cols && NC == 2 && nrow <= 1024) NTU_QRR(1, 1024);
+  else
+    hipLaunchKernelGGL((k_reduce_qr<T, S>), g, dim3(QR_THREADS), 0, st, d, na, D, rg, (const S*)site, (const T*)gf,
+                       gf_stride, side, (T*)Q, (T*)R, kappa, (const int*)todo, y);
+#undef NTU_QRR
 }
 
 static hipError_t reduce_dispatch(bool cplx, int site_dtype, int batch, int sides, int d, int na, int D, int rg,

@@ -239,31 +239,60 @@ NTU_DEV void block_jacobi_eigh(T* A, int n, int lda, T* V, int ldv, double* pc, 
         atomicAdd(sh_cnt, 1);
       }
       __syncthreads();
-      // rows:  row_p' = c row_p - s e^{i phi} row_q ; row_q' = s row_p + c e^{i phi} row_q
-      for (long long e = tid; e < (long long)np * n; e += blockDim.x) {
-        int k = (int)(e / n), j = (int)(e % n);
-        if (ps[k] == 0.0) continue;
-        int p, q;
-        rr_pair(n2, r, k, p, q);
-        double c = pc[k], s = ps[k];
-        T ec = conjv(pe[k]);
-        T x = A[p * lda + j], y = ec * A[q * lda + j];
-        A[p * lda + j] = c * x - s * y;
-        A[q * lda + j] = s * x + c * y;
+      // A <- J^H A J and V <- V J in one pass.  Every entry lies in the 2 x 2
+      // block of one pair of pairs (k1 for its row, k2 for its column): the
+      // row rotation of k1, row_p' = c row_p - s e^{i phi} row_q, row_q' =
+      // s row_p + c e^{i phi} row_q, then the column rotation of k2, col_p' =
+      // c col_p - s e^{-i phi} col_q, col_q' = s col_p + c e^{-i phi} col_q
+      // (the same operations, in the same order, as a pass over all rows
+      // followed by a pass over all columns).  k2 runs fastest over the
+      // threads, so a wave touches two rows of A.  Indices >= n belong to the
+      // dummy of an odd n and are left out.
+      for (long long e = tid; e < (long long)np * np; e += blockDim.x) {
+        const int k1 = (int)(e / np), k2 = (int)(e % np);
+        const double s1 = ps[k1], s2 = ps[k2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        int p1, q1, p2, q2;
+        rr_pair(n2, r, k1, p1, q1);
+        rr_pair(n2, r, k2, p2, q2);
+        const bool hq1 = q1 < n, hq2 = q2 < n;
+        T a = A[p1 * lda + p2];
+        T b = hq2 ? A[p1 * lda + q2] : zerov<T>();
+        T c_ = hq1 ? A[q1 * lda + p2] : zerov<T>();
+        T d_ = hq1 && hq2 ? A[q1 * lda + q2] : zerov<T>();
+        if (s1 != 0.0) {
+          const double c = pc[k1];
+          const T ec = conjv(pe[k1]);
+          T x = a, y = ec * c_;
+          a = c * x - s1 * y;
+          c_ = s1 * x + c * y;
+          x = b; y = ec * d_;
+          b = c * x - s1 * y;
+          d_ = s1 * x + c * y;
+        }
+        if (s2 != 0.0) {
+          const double c = pc[k2];
+          const T ev = pe[k2];
+          T x = a, y = b * ev;
+          a = c * x - s2 * y;
+          b = s2 * x + c * y;
+          x = c_; y = d_ * ev;
+          c_ = c * x - s2 * y;
+          d_ = s2 * x + c * y;
+        }
+        A[p1 * lda + p2] = a;
+        if (hq2) A[p1 * lda + q2] = b;
+        if (hq1) A[q1 * lda + p2] = c_;
+        if (hq1 && hq2) A[q1 * lda + q2] = d_;
       }
-      __syncthreads();
-      // columns of A and V:  col_p' = c col_p - s e^{-i phi} col_q ; col_q' = s col_p + c e^{-i phi} col_q
-      for (long long e = tid; e < (long long)np * n; e += blockDim.x) {
-        int k = (int)(e / n), i = (int)(e % n);
+      for (long long e = tid; e < (long long)n * np; e += blockDim.x) {
+        const int i = (int)(e / np), k = (int)(e % np);
         if (ps[k] == 0.0) continue;
         int p, q;
         rr_pair(n2, r, k, p, q);
-        double c = pc[k], s = ps[k];
-        T ev = pe[k];
-        T x = A[i * lda + p], y = A[i * lda + q] * ev;
-        A[i * lda + p] = c * x - s * y;
-        A[i * lda + q] = s * x + c * y;
-        x = V[i * ldv + p]; y = V[i * ldv + q] * ev;
+        const double c = pc[k], s = ps[k];
+        const T ev = pe[k];
+        const T x = V[i * ldv + p], y = V[i * ldv + q] * ev;
         V[i * ldv + p] = c * x - s * y;
         V[i * ldv + q] = s * x + c * y;
       }

@@ -22,6 +22,8 @@ PREC_F64, PREC_BF16X3, PREC_FP16X3, PREC_BF16X6 = 0, 1, 2, 3
 FIX_HERM, FIX_HERM_CLIP = 0, 1
 BOND_H1, BOND_H2, BOND_V1, BOND_V2 = 0, 1, 2, 3
 PRECISIONS = {"f64": PREC_F64, "bf16x3": PREC_BF16X3, "fp16x3": PREC_FP16X3, "bf16x6": PREC_BF16X6}
+SCHEME_NTU, SCHEME_SVDU = 0, 1
+SCHEMES = {"ntu": SCHEME_NTU, "svdu": SCHEME_SVDU}
 
 EXPORTED = (
     "ntu_ctx_create", "ntu_ctx_destroy", "ntu_set_stream", "ntu_set_aux_stream", "ntu_last_error",
@@ -40,7 +42,7 @@ class FitOpts(ctypes.Structure):
 
 class StepOpts(ctypes.Structure):
     _fields_ = [("n_bonds", ctypes.c_int), ("order", ctypes.c_int * 8), ("precision", ctypes.c_int),
-                ("fix_mode", ctypes.c_int), ("fit", FitOpts)]
+                ("fix_mode", ctypes.c_int), ("fit", FitOpts), ("scheme", ctypes.c_int)]
 
 
 _lib = None
@@ -98,9 +100,10 @@ def fit_opts(n_iter=20, early_stop=False, conv_tol=1e-12, kappa=1e-10, ladder=No
     return o
 
 
-def step_opts(precision="f64", fix_mode=FIX_HERM_CLIP, order=(0, 1, 2, 3), **fit) -> StepOpts:
+def step_opts(precision="f64", fix_mode=FIX_HERM_CLIP, order=(0, 1, 2, 3), scheme="ntu", **fit) -> StepOpts:
     o = StepOpts()
     load().ntu_step_opts_default(ctypes.byref(o))
+    o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.fix_mode = fix_mode
     o.n_bonds = len(order)

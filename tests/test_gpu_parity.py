@@ -61,18 +61,38 @@ def test_reduce_qr(D, p, real):
             assert rel(R[i], Ro) < 1e-12
 
 
-def test_reduce_qr_rank_deficient_and_complex64():
-    # beta = 0 purification: most columns of W are dependent (rank rule)
-    A, B = inputs.thermal_product_purification(4)
+@pytest.mark.parametrize("D", [4, 6, 8])
+def test_reduce_qr_rank_deficient_and_complex64(D):
+    # beta = 0 purification (real, p = 4): most columns of W are dependent
+    # (rank rule); D = 4, 6, 8 give 256, 864, 2048 rows of W (one and two rows
+    # per thread of the register-resident Gram-Schmidt, 512 and 1024 threads)
+    A, B = inputs.thermal_product_purification(D)
     G = inputs.bond_gate(inputs.ising_bond_hamiltonian(2.5).real, 0.005, imaginary=True)
     GA, GB, _ = O.gate_split(G, 2, 2)
-    Qo, Ro = O.reduce_site(A, GA, 'X', 2)
-    ctx = _ctx(cplx=False, d_anc=2, max_D=4)
-    Q, R = ntu.ntu_reduce_qr(ctx, batched([A]), batched([GA]), 0)
-    Q, R = to_np(Q)[0], to_np(R)[0]
-    zero_cols = np.all(Qo.reshape(Q.shape) == 0, axis=0)
-    assert zero_cols.sum() > 0 and np.array_equal(np.all(Q == 0, axis=0), zero_cols)
-    assert rel(Q, Qo.reshape(Q.shape)) < 1e-12 and rel(R, Ro) < 1e-12
+    ctx = _ctx(cplx=False, d_anc=2, max_D=D)
+    for side, T, gf in ((0, A, GA), (1, B, GB)):
+        Qo, Ro = O.reduce_site(T, gf, 'XY'[side], 2)
+        Q, R = ntu.ntu_reduce_qr(ctx, batched([T]), batched([gf]), side)
+        Q, R = to_np(Q)[0], to_np(R)[0]
+        zero_cols = np.all(Qo.reshape(Q.shape) == 0, axis=0)
+        assert zero_cols.sum() > 0 and np.array_equal(np.all(Q == 0, axis=0), zero_cols)
+        assert rel(Q, Qo.reshape(Q.shape)) < 1e-12 and rel(R, Ro) < 1e-12
+    # complex, p = 2: the |+> product state padded to D (rank-deficient W of
+    # 2 D^3 rows), and a random state with a few of its bond columns zero
+    rng = np.random.default_rng(40 + D)
+    Gc = inputs.bond_gate(inputs.ising_bond_hamiltonian(3.0), 0.01)
+    GA, GB, _ = O.gate_split(Gc, 2, 2)
+    Pa, Pb = inputs.plus_product_state(D)
+    X, Y = inputs.random_site_pair(rng, 2, D)
+    X[..., D // 2:] = 0.0
+    ctx = _ctx(max_D=D)
+    for T in (Pa.astype(np.complex128), X):
+        Qo, Ro = O.reduce_site(T, GA, 'X', 2)
+        Q, R = ntu.ntu_reduce_qr(ctx, batched([T]), batched([GA]), 0)
+        Q, R = to_np(Q)[0], to_np(R)[0]
+        zero_cols = np.all(Qo.reshape(Q.shape) == 0, axis=0)
+        assert zero_cols.sum() > 0 and np.array_equal(np.all(Q == 0, axis=0), zero_cols)
+        assert rel(Q, Qo.reshape(Q.shape)) < 1e-12 and rel(R, Ro) < 1e-12
     # complex64 storage of the site tensor, upcast on load
     rng = np.random.default_rng(5)
     X, _ = inputs.random_site_pair(rng, 2, 3, np.complex64)
@@ -144,6 +164,20 @@ def test_metric_fix(real):
     gt = batched([gpd])
     st = to_np(ntu.ntu_metric_fix(ctx, gt, 3, ntu.FIX_HERM_CLIP))[0]
     assert st[5] == 0.0 and rel(to_np(gt)[0], O.metric_fix(gpd)[0]) < 1e-13
+    # indefinite with exactly zero rows and columns: the eigensolver runs on the
+    # nonzero block, here of odd size (a pair with a dummy index in every round)
+    for n, D, zero in ((16, 2, (5,)), (64, 4, (0, 17, 40))):
+        M = rng.standard_normal((n, n)) + (0 if real else 1j * rng.standard_normal((n, n)))
+        gz = (M + M.conj().T) / 2
+        for z in zero:
+            gz[z, :] = 0.0
+            gz[:, z] = 0.0
+        go, so = O.metric_fix(gz)
+        ctx = _ctx(cplx=not real, max_D=D)
+        gt = batched([gz])
+        st = to_np(ntu.ntu_metric_fix(ctx, gt, D, ntu.FIX_HERM_CLIP))[0]
+        assert rel(to_np(gt)[0], go) < 1e-12 and st[5] == 1.0
+        assert abs(st[2] - so['lam_min']) < 1e-12 * abs(so['lam_max'])
 
 
 # ------------------------------------------------------------------ fit
@@ -269,6 +303,61 @@ def test_trotter_step_thermal_prefix():
         eo, _ = O.observables(A, B, 2.5)
         eg, _ = O.observables(Ag, Bg, 2.5)
         assert abs(eg - eo) < 1e-10
+
+
+@pytest.mark.parametrize("D, real", [(3, False), (4, False), (3, True)])
+def test_svdu_trotter_steps(D, real):
+    """SVDU scheme (Fig. 2 without an environment) over Trotter sweeps against
+    the oracle: ranks, normalised singular values of every update, and the
+    cluster observables of the evolved state (gauge-invariant)."""
+    if real:
+        w, hx = inputs.workload_thermal(D=D), 2.5
+        ctx = _ctx(cplx=False, d_anc=2, max_D=D)
+    else:
+        w, hx = inputs.workload_quench(seed=2, D=D), inputs.H_CRIT
+        ctx = _ctx(max_D=D)
+    GA, GB, _ = O.gate_split(w['gates'][0], 2, 2)
+    pairs = {b: (GA, GB) for b in O.BONDS}
+    A, B = w['A'], w['B']
+    Ag, Bg = A.copy(), B.copy()
+    for step in range(3):
+        A, B, infos = O.trotter_step(A, B, pairs, D, scheme='svdu')
+        Ag, Bg, st = _gpu_step(ctx, Ag, Bg, pairs, 2, cplx=not real, scheme="svdu")
+        for bi, b in enumerate(O.BONDS):
+            f = fit_stat_fields(st[bi, 8:], 2, D)
+            assert f['Dn'] == infos[b]['Dn'] and f['Dk'] == infos[b]['Dk']
+            assert np.allclose(f['S'], infos[b]['S'], atol=1e-10)
+            assert f['N'] == 0.0 and f['eps'] == 0.0 and f['iters'] == 0
+        eo, xo = O.observables(A, B, hx)
+        eg, xg = O.observables(Ag, Bg, hx)
+        assert abs(eg - eo) < 1e-10 and abs(xg - xo) < 1e-10
+
+
+def test_second_order_sweep():
+    """A symmetric sweep H1 H2 V1 V2 V2 V1 H2 H1 of half-time gates (second
+    order in the time step) through an 8-entry sweep order, against the
+    oracle: the last update of every bond and the observables."""
+    D = 2
+    w = inputs.workload_quench(seed=2, D=D)
+    G_half = inputs.bond_gate(inputs.ising_bond_hamiltonian(inputs.H_CRIT), 0.005)
+    GA, GB, _ = O.gate_split(G_half, 2, 2)
+    pairs = {b: (GA, GB) for b in O.BONDS}
+    names = ('H1', 'H2', 'V1', 'V2', 'V2', 'V1', 'H2', 'H1')
+    codes = tuple(O.BONDS.index(b) for b in names)
+    A, B = w['A'], w['B']
+    Ag, Bg = A.copy(), B.copy()
+    ctx = _ctx(max_D=D)
+    for step in range(2):
+        A, B, infos = O.trotter_step(A, B, pairs, D, n_iter=4, order=names)
+        Ag, Bg, st = _gpu_step(ctx, Ag, Bg, pairs, 4, order=codes)
+        for bi in range(4, 8):          # the oracle keeps the last update of each bond
+            f = fit_stat_fields(st[bi, 8:], 4, D)
+            info = infos[names[bi]]
+            assert abs(f['delta'] - info['delta']) <= 1e-7 * info['delta'] + 1e-14
+            assert np.allclose(f['S'], info['S'], atol=1e-8)
+        eo, xo = O.observables(A, B, inputs.H_CRIT)
+        eg, xg = O.observables(Ag, Bg, inputs.H_CRIT)
+        assert abs(eg - eo) < 1e-9 and abs(xg - xo) < 1e-9
 
 
 def test_shared_side_stream_matches_own():
