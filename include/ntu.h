@@ -177,7 +177,8 @@ ntu_status ntu_env_contract(ntu_ctx* ctx, int batch, int D, const void* QX, cons
  *   [3] largest eigenvalue  (NaN if not computed)
  *   [4] clipped mass sum(-lambda_neg)/sum|lambda| (0 if certified)
  *   [5] 1 if the eigen-decomposition ran, 0 if certified
- *   [6] number of non-finite entries in the input   [7] reserved
+ *   [6] number of non-finite entries in the input
+ *   [7] Jacobi sweeps of the eigen-decomposition (0 when none was needed)
  */
 ntu_status ntu_metric_fix(ntu_ctx* ctx, int batch, int D, void* g, int mode, double* stats);
 

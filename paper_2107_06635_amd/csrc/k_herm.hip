@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stat
     A[e] = G[(size_t)idx[i] * n + idx[j]];
   }
   __syncthreads();
-  block_jacobi_eigh<T>(A, m, m, V, m, pc, ps, pe, &cnt, fro);
+  const int sweeps = block_jacobi_eigh<T>(A, m, m, V, m, pc, ps, pe, &cnt, fro);
   // eigenvalues on the diagonal of A
   double lmin = INFINITY, lmax = -INFINITY, neg = 0, tot = 0;
   for (int i = tid; i < m; i += blockDim.x) {
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stat
   }
   if (stats && tid == 0) {
     double* s = stats + (size_t)it * sstride;
-    s[2] = lmin; s[3] = lmax; s[4] = tot > 0 ? neg / tot : 0.0; s[5] = 1.0;
+    s[2] = lmin; s[3] = lmax; s[4] = tot > 0 ? neg / tot : 0.0; s[5] = 1.0; s[7] = sweeps;
   }
 }
 
