@@ -266,8 +266,10 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
     const bool ok = CPLX ? 2 * jrow < Nr : jrow < Nr;
     brow[u] = ok ? Bb + idx_off(d.Bj, jrow) * CW : nullptr;
   }
-  float ra[NGA][4], rb[NGB][4];
-  auto gload = [&](int k0) {
+  // two register sets of operand values: the loads of step s + 2 are in
+  // flight while step s runs and step s + 1's values are split and stored
+  float ra0[NGA][4], rb0[NGB][4], ra1[NGA][4], rb1[NGB][4];
+  auto gload = [&](int k0, float (&ra)[NGA][4], float (&rb)[NGB][4]) {
 #pragma unroll
     for (int u = 0; u < NGA; ++u) {
       const int k = k0 + akq[u];
@@ -299,7 +301,7 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
       }
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, const float (&ra)[NGA][4], const float (&rb)[NGB][4]) {
     if constexpr (PREC != NTU_PREC_FP16X3) {
       // bfloat16 pieces of two values at once (one packed word per piece)
 #pragma unroll
@@ -394,16 +396,20 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
       for (int y = 0; y < TL_WY; ++y) acc[c][x][y] = f32x4{0, 0, 0, 0};
 
   const int nsteps = (kend - kbeg + TL_K - 1) / TL_K;
-  gload(kbeg);
-  lstore(0);
+  gload(kbeg, ra0, rb0);
+  lstore(0, ra0, rb0);
+  if (nsteps > 1) gload(kbeg + TL_K, ra1, rb1);
   __syncthreads();
   const int fr = lane & 15, fk = (lane >> 4) * 8;
   // the 16-byte chunk this lane reads from each of its rows (tile rows are
   // multiples of 16 plus fr, so the permutation depends on fr alone)
   const int fks = tl_col(fr, fk);
-  for (int s = 0; s < nsteps; ++s) {
+  // step s: set (xa, xb) is free (its values are stored) and takes the loads
+  // of step s + 2; set (ya, yb) holds step s + 1, stored after the products
+  auto step = [&](int s, float (&xa)[NGA][4], float (&xb)[NGB][4], const float (&ya)[NGA][4],
+                  const float (&yb)[NGB][4]) {
     const int buf = s & 1;
-    if (s + 1 < nsteps) gload(kbeg + (s + 1) * TL_K);
+    if (s + 2 < nsteps) gload(kbeg + (s + 2) * TL_K, xa, xb);
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
       const int ra_ = wm * 64 + x * 16 + fr;
@@ -426,8 +432,12 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
         }
       }
     }
-    if (s + 1 < nsteps) lstore(buf ^ 1);
+    if (s + 1 < nsteps) lstore(buf ^ 1, ya, yb);
     __syncthreads();
+  };
+  for (int s = 0; s < nsteps; s += 2) {
+    step(s, ra0, rb0, ra1, rb1);
+    if (s + 1 < nsteps) step(s + 1, ra1, rb1, ra0, rb0);
   }
   // epilogue: lane holds column (lane & 15), rows 4 (lane >> 4) + v of each 16 x 16 tile
   const long long cbase = idx_off(d.Cb, item) * CW;

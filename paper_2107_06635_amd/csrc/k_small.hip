@@ -197,9 +197,9 @@ __global__ void __launch_bounds__(QR_THREADS) k_reduce_qr(int d, int na, int D, 
 // The same Gram-Schmidt QR with W held in registers: thread t of NT owns
 // rows t, t + NT, ... (RPT of them, R <= QRR_RMAX columns each), so each
 // projection pass is register arithmetic plus one block reduction of a fixed
-// number of partial sums, with no sweep over W in memory.  Taken when the
-// rows fit (p D^3 <= RPT NT with the configurations of reduce_launch); same
-// steps, projection twice, same rank rule.
+// number of partial sums, with no sweep over W in memory.  Taken for real
+// types when the rows fit (p D^3 <= RPT NT with the configurations of
+// reduce_launch); same steps, projection twice, same rank rule.
 // ---------------------------------------------------------------------------
 constexpr int QRR_RMAX = 16;
 
@@ -552,23 +552,28 @@ static void reduce_launch(int batch, int sides, int d, int na, int D, int rg, co
   if (todo)
     hipLaunchKernelGGL((k_reduce_cholqr<T, S>), g, dim3(CQR_THREADS), 0, st, d, na, D, rg, (const S*)site,
                        (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, todo, y);
-  // Gram-Schmidt for the items the Cholesky QR left (all items without todo):
-  // rows in registers when they fit (real: up to 2048 rows, complex: up to
-  // 1024), else the version that sweeps W in memory
-  constexpr int NC = is_cplx<T>::value ? 2 : 1;
+  // Gram-Schmidt for the items the Cholesky QR left (all items without todo).
+  // Real: rows in registers when they fit (up to 2048 rows; measured four
+  // times faster at 2048 rows).  Complex: the version that sweeps W in memory
+  // (the register version measured slower there: it spills at 1024 rows).
   const long long nrow = (long long)d * na * D * D * D;
-  const bool cols = D * rg <= QRR_RMAX;
-#define NTU_QRR(RPT_, NT_)                                                                                         \
-  hipLaunchKernelGGL((k_reduce_qr_reg<T, S, RPT_, NT_>), g, dim3(NT_), 0, st, d, na, D, rg, (const S*)site,         \
-                     (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, (const int*)todo, y)
-  if (cols && nrow <= 512) NTU_QRR(1, 512);
-  else if (cols && NC == 1 && nrow <= 1024) NTU_QRR(2, 512);
-  else if (cols && NC == 1 && nrow <= 2048) NTU_QRR(2, 1024);
-  else if (cols && NC == 2 && nrow <= 1024) NTU_QRR(1, 1024);
-  else
+  const bool regs = !is_cplx<T>::value && D * rg <= QRR_RMAX && nrow <= 2048;
+  if constexpr (!is_cplx<T>::value) {
+    if (regs) {
+      if (nrow <= 512)
+        hipLaunchKernelGGL((k_reduce_qr_reg<T, S, 1, 512>), g, dim3(512), 0, st, d, na, D, rg, (const S*)site,
+                           (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, (const int*)todo, y);
+      else if (nrow <= 1024)
+        hipLaunchKernelGGL((k_reduce_qr_reg<T, S, 2, 512>), g, dim3(512), 0, st, d, na, D, rg, (const S*)site,
+                           (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, (const int*)todo, y);
+      else
+        hipLaunchKernelGGL((k_reduce_qr_reg<T, S, 2, 1024>), g, dim3(1024), 0, st, d, na, D, rg, (const S*)site,
+                           (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, (const int*)todo, y);
+    }
+  }
+  if (!regs)
     hipLaunchKernelGGL((k_reduce_qr<T, S>), g, dim3(QR_THREADS), 0, st, d, na, D, rg, (const S*)site, (const T*)gf,
                        gf_stride, side, (T*)Q, (T*)R, kappa, (const int*)todo, y);
-#undef NTU_QRR
 }
 
 static hipError_t reduce_dispatch(bool cplx, int site_dtype, int batch, int sides, int d, int na, int D, int rg,

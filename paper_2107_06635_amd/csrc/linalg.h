@@ -249,114 +249,57 @@ NTU_DEV int block_jacobi_eigh(T* A, int n, int lda, T* V, int ldv, double* pc, d
       // row rotation of k1, row_p' = c row_p - s e^{i phi} row_q, row_q' =
       // s row_p + c e^{i phi} row_q, then the column rotation of k2, col_p' =
       // c col_p - s e^{-i phi} col_q, col_q' = s col_p + c e^{-i phi} col_q
-      // (the same operations as a pass over all rows followed by a pass over
-      // all columns).  A stays Hermitian, so only the blocks with k1 <= k2
-      // are formed and each off-diagonal one is also written, conjugate
-      // transposed, in place of block (k2, k1).  Indices >= n belong to the
+      // (the same operations, in the same order, as a pass over all rows
+      // followed by a pass over all columns).  k2 runs fastest over the
+      // threads, so a wave touches two rows of A.  Indices >= n belong to the
       // dummy of an odd n and are left out.
-      // Two blocks per thread at a time: all their loads are issued before
-      // any store (the compiler cannot reorder loads and stores of A itself),
-      // so their memory latencies overlap.
-      constexpr int GB = 2;
-      const long long nblk = (long long)np * (np + 1) / 2;
-      auto before = [&](long long k) { return k * np - k * (k - 1) / 2; };
-      for (long long e0 = tid; e0 < nblk; e0 += (long long)GB * blockDim.x) {
-        int k1v[GB], k2v[GB], p1v[GB], q1v[GB], p2v[GB], q2v[GB];
-        bool live[GB];
-        T av[GB], bv[GB], cv[GB], dv[GB];
-#pragma unroll
-        for (int u = 0; u < GB; ++u) {
-          const long long e = e0 + (long long)u * blockDim.x;
-          live[u] = false;
-          k1v[u] = k2v[u] = 0;
-          if (e >= nblk) continue;
-          // (k1, k2), k1 <= k2, from the row-major index e of the upper triangle
-          const double bq = 2.0 * np + 1.0;
-          long long k1 = (long long)((bq - sqrt(bq * bq - 8.0 * (double)e)) * 0.5);
-          if (k1 < 0) k1 = 0;
-          if (k1 > np - 1) k1 = np - 1;
-          while (k1 + 1 < np && before(k1 + 1) <= e) ++k1;
-          while (k1 > 0 && before(k1) > e) --k1;
-          k1v[u] = (int)k1;
-          k2v[u] = (int)(k1 + (e - before(k1)));
-          if (ps[k1v[u]] == 0.0 && ps[k2v[u]] == 0.0) continue;
-          live[u] = true;
-          rr_pair(n2, r, k1v[u], p1v[u], q1v[u]);
-          rr_pair(n2, r, k2v[u], p2v[u], q2v[u]);
-          const bool hq1 = q1v[u] < n, hq2 = q2v[u] < n;
-          av[u] = A[p1v[u] * lda + p2v[u]];
-          bv[u] = hq2 ? A[p1v[u] * lda + q2v[u]] : zerov<T>();
-          cv[u] = hq1 ? A[q1v[u] * lda + p2v[u]] : zerov<T>();
-          dv[u] = hq1 && hq2 ? A[q1v[u] * lda + q2v[u]] : zerov<T>();
+      for (long long e = tid; e < (long long)np * np; e += blockDim.x) {
+        const int k1 = (int)(e / np), k2 = (int)(e % np);
+        const double s1 = ps[k1], s2 = ps[k2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        int p1, q1, p2, q2;
+        rr_pair(n2, r, k1, p1, q1);
+        rr_pair(n2, r, k2, p2, q2);
+        const bool hq1 = q1 < n, hq2 = q2 < n;
+        T a = A[p1 * lda + p2];
+        T b = hq2 ? A[p1 * lda + q2] : zerov<T>();
+        T c_ = hq1 ? A[q1 * lda + p2] : zerov<T>();
+        T d_ = hq1 && hq2 ? A[q1 * lda + q2] : zerov<T>();
+        if (s1 != 0.0) {
+          const double c = pc[k1];
+          const T ec = conjv(pe[k1]);
+          T x = a, y = ec * c_;
+          a = c * x - s1 * y;
+          c_ = s1 * x + c * y;
+          x = b; y = ec * d_;
+          b = c * x - s1 * y;
+          d_ = s1 * x + c * y;
         }
-#pragma unroll
-        for (int u = 0; u < GB; ++u) {
-          if (!live[u]) continue;
-          T a = av[u], b = bv[u], c_ = cv[u], d_ = dv[u];
-          const double s1 = ps[k1v[u]], s2 = ps[k2v[u]];
-          if (s1 != 0.0) {
-            const double c = pc[k1v[u]];
-            const T ec = conjv(pe[k1v[u]]);
-            T x = a, y = ec * c_;
-            a = c * x - s1 * y;
-            c_ = s1 * x + c * y;
-            x = b; y = ec * d_;
-            b = c * x - s1 * y;
-            d_ = s1 * x + c * y;
-          }
-          if (s2 != 0.0) {
-            const double c = pc[k2v[u]];
-            const T ev = pe[k2v[u]];
-            T x = a, y = b * ev;
-            a = c * x - s2 * y;
-            b = s2 * x + c * y;
-            x = c_; y = d_ * ev;
-            c_ = c * x - s2 * y;
-            d_ = s2 * x + c * y;
-          }
-          const int p1 = p1v[u], q1 = q1v[u], p2 = p2v[u], q2 = q2v[u];
-          const bool hq1 = q1 < n, hq2 = q2 < n;
-          A[p1 * lda + p2] = a;
-          if (hq2) A[p1 * lda + q2] = b;
-          if (hq1) A[q1 * lda + p2] = c_;
-          if (hq1 && hq2) A[q1 * lda + q2] = d_;
-          if (k1v[u] != k2v[u]) {
-            A[p2 * lda + p1] = conjv(a);
-            if (hq2) A[q2 * lda + p1] = conjv(b);
-            if (hq1) A[p2 * lda + q1] = conjv(c_);
-            if (hq1 && hq2) A[q2 * lda + q1] = conjv(d_);
-          }
+        if (s2 != 0.0) {
+          const double c = pc[k2];
+          const T ev = pe[k2];
+          T x = a, y = b * ev;
+          a = c * x - s2 * y;
+          b = s2 * x + c * y;
+          x = c_; y = d_ * ev;
+          c_ = c * x - s2 * y;
+          d_ = s2 * x + c * y;
         }
+        A[p1 * lda + p2] = a;
+        if (hq2) A[p1 * lda + q2] = b;
+        if (hq1) A[q1 * lda + p2] = c_;
+        if (hq1 && hq2) A[q1 * lda + q2] = d_;
       }
-      for (long long e0 = tid; e0 < (long long)n * np; e0 += (long long)GB * blockDim.x) {
-        int pv[GB], qv[GB], kv[GB];
-        bool live[GB];
-        T xv[GB], yv[GB];
-#pragma unroll
-        for (int u = 0; u < GB; ++u) {
-          const long long e = e0 + (long long)u * blockDim.x;
-          live[u] = false;
-          kv[u] = 0;
-          if (e >= (long long)n * np) continue;
-          const int i = (int)(e / np), k = (int)(e % np);
-          kv[u] = k;
-          if (ps[k] == 0.0) continue;
-          live[u] = true;
-          int p, q;
-          rr_pair(n2, r, k, p, q);
-          pv[u] = i * ldv + p;
-          qv[u] = i * ldv + q;
-          xv[u] = V[pv[u]];
-          yv[u] = V[qv[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < GB; ++u) {
-          if (!live[u]) continue;
-          const double c = pc[kv[u]], s = ps[kv[u]];
-          const T x = xv[u], y = yv[u] * pe[kv[u]];
-          V[pv[u]] = c * x - s * y;
-          V[qv[u]] = s * x + c * y;
-        }
+      for (long long e = tid; e < (long long)n * np; e += blockDim.x) {
+        const int i = (int)(e / np), k = (int)(e % np);
+        if (ps[k] == 0.0) continue;
+        int p, q;
+        rr_pair(n2, r, k, p, q);
+        const double c = pc[k], s = ps[k];
+        const T ev = pe[k];
+        const T x = V[i * ldv + p], y = V[i * ldv + q] * ev;
+        V[i * ldv + p] = c * x - s * y;
+        V[i * ldv + q] = s * x + c * y;
       }
       __syncthreads();
     }
