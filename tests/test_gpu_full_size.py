@@ -3,7 +3,8 @@
 Configuration 4: all 256 independent bond updates (D uniform in 3..8), one
 context and one batched Trotter-step call per bond dimension, compared item
 by item with the FP64 oracle through gauge-invariant quantities (final error,
-norm, the bond-contracted pair).  Configuration 5: one Trotter sweep of the
+norm, the bond-contracted pair), and the same items under the SVDU scheme.
+Configuration 5: one Trotter sweep of the
 D = 10 state.  Graph capture: a captured sweep replayed several times, with
 eager work and synchronisations between replays, matches the eager sweep.
 """
@@ -77,6 +78,38 @@ def test_config4_all_items(config4_oracle, precision, tol):
             assert abs(f['eps'] - r['eps']) <= t * r['eps'] + 1e-11 * r['N'], (D, i, f['eps'], r['eps'])
             assert rel(_pair(An[k], Bn[k]), r['pair']) < t, (D, i)
     assert n_other_iters <= 5, n_other_iters
+
+
+def test_config4_all_items_svdu():
+    """SVDU scheme on all 256 items of configuration 4, in the batched
+    launches bench.py --scheme svdu times: ranks, normalised singular values
+    and the bond-contracted pair of every item against the oracle's SVDU
+    update (precision argument unused by the scheme)."""
+    items = inputs.workload_batched()
+    buckets = {}
+    for i, it in enumerate(items):
+        buckets.setdefault(it['D'], []).append(i)
+    for D, idx in sorted(buckets.items()):
+        ctx = ntu.Context(complex_=True, d=2, d_anc=1, r_g=2, max_D=D, max_batch=len(idx))
+        A = to_dev(np.stack([items[i]['A'] for i in idx]), torch.complex128)
+        B = to_dev(np.stack([items[i]['B'] for i in idx]), torch.complex128)
+        G = to_dev(np.stack([items[i]['gate'] for i in idx]))
+        GA, GB, _ = ntu.ntu_gate_split(ctx, G)
+        gf = torch.zeros(len(idx), 4, 2, 2, 2, 2, dtype=torch.complex128, device=DEV)
+        gf[:, :, 0] = GA[:, None]
+        gf[:, :, 1] = GB[:, None]
+        opts = ntu.step_opts("bf16x6", order=(ntu.BOND_H1,), scheme="svdu", n_iter=N_ITER)
+        st = to_np(ntu.ntu_trotter_step(ctx, A, B, gf.contiguous(), opts))
+        An, Bn = to_np(A), to_np(B)
+        for k, i in enumerate(idx):
+            it = items[i]
+            GAo, GBo, _ = O.gate_split(it['gate'], 2, 2)
+            X, Y, _ = O._cluster(True, it['A'].astype(np.complex128), it['B'].astype(np.complex128))
+            Xo, Yo, info = O.svdu_update(X, Y, GAo, GBo, D)
+            f = fit_stat_fields(st[k, 0, 8:], N_ITER, D)
+            assert f['Dn'] == info['Dn'] and f['Dk'] == info['Dk'], (D, i)
+            assert np.allclose(f['S'], info['S'], atol=1e-10), (D, i)
+            assert rel(_pair(An[k], Bn[k]), _pair(Xo, Yo)) < 1e-9, (D, i)
 
 
 def test_config5_one_sweep():
