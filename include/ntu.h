@@ -284,6 +284,37 @@ ntu_status ntu_trotter_step(ntu_ctx* ctx, int batch, int D, void* A, void* B,
                             const void* gate_factors, const ntu_step_opts* opts, double* stats);
 
 /*
+ * Autotuning of the split-precision environment contraction (a launch
+ * parameter, not part of the method): the number of K chunks of the final
+ * assembly g = L2 Right^T (Fig. 4(d,e)), whose FP64 partial sums are then
+ * added.  More chunks fill the GPU better at small batch; fewer move fewer
+ * partial sums.  Any choice gives the same metric up to FP64 rounding of the
+ * chunk sums.
+ *
+ * ntu_tune_env times ntu_env_contract on the caller's operands (same
+ * arguments; g is overwritten) for every candidate split (1 .. 4, and the
+ * built-in heuristic's choice when larger), reps timed calls each after one
+ * untimed call, with HIP events on the context stream, and synchronises.  It
+ * keeps the fastest for (D, precision) in the context, where
+ * ntu_env_contract and ntu_trotter_step then use it, and returns it in
+ * best_ks (and its mean time in best_ms), either may be NULL.  The choice is
+ * made for this batch size.  Precision must be NTU_PREC_BF16X3 or
+ * NTU_PREC_BF16X6 (NTU_ERR_ARG otherwise); reps >= 1.
+ * ntu_set_env_ksplit sets it directly (ks = 0: the heuristic again);
+ * ntu_get_env_ksplit returns it (0: the heuristic).
+ * ntu_tune_save writes the context's choices to a text file, one line
+ * "D precision ksplit" each; ntu_tune_load reads such a file into the
+ * context (entries for D > max_D or other precisions are skipped; a
+ * malformed line gives NTU_ERR_ARG, after the lines before it are taken).
+ */
+ntu_status ntu_tune_env(ntu_ctx* ctx, int batch, int D, int precision, const void* QX, const void* QY,
+                        const void* const nbr[6], void* g, int reps, int* best_ks, float* best_ms);
+ntu_status ntu_set_env_ksplit(ntu_ctx* ctx, int D, int precision, int ks);
+int ntu_get_env_ksplit(ntu_ctx* ctx, int D, int precision);
+ntu_status ntu_tune_save(ntu_ctx* ctx, const char* path);
+ntu_status ntu_tune_load(ntu_ctx* ctx, const char* path);
+
+/*
  * Event profiler (measurement support, not part of the method).  When enabled,
  * the context records a HIP event on its stream before and after every
  * kernel class it launches (events are created here, never inside calls).

@@ -1,12 +1,16 @@
 // C ABI of libntu (declared in include/ntu.h): argument validation, the
 // context's workspace, and the orchestration of a Trotter step.  Every
 // numerical step runs in the HIP kernels of this library.
+#include <stdio.h>
 #include <string.h>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 #include <algorithm>
 #include "ntu.h"
 #include "kernels.h"
+#include "mfma_gemm.h"
 
 namespace {
 
@@ -37,6 +41,9 @@ struct ntu_ctx {
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_kind;
   int prof_n = 0;
+  // tuned K split of the split-precision metric assembly per (D, precision)
+  // (ntu_tune_env / ntu_set_env_ksplit); absent: the heuristic
+  std::map<std::pair<int, int>, int> e6_ks;
 };
 
 namespace {
@@ -54,6 +61,12 @@ ntu_status hip_fail(ntu_ctx* c, hipError_t e, const char* where) {
 }
 
 size_t elem_size(const ntu_ctx* c) { return c->cplx ? 16 : 8; }
+
+// tuned K split of the metric assembly for (D, precision), 0 = heuristic
+int env_ks(const ntu_ctx* c, int D, int precision) {
+  auto it = c->e6_ks.find({D, precision});
+  return it == c->e6_ks.end() ? 0 : it->second;
+}
 int pdim(const ntu_ctx* c) { return c->d * c->na; }
 
 struct DeviceGuard {
@@ -305,7 +318,7 @@ ntu_status ntu_env_contract(ntu_ctx* c, int batch, int D, const void* QX, const 
     if (!nbr[i]) return fail(c, NTU_ERR_ARG, "NULL neighbour pointer");
   DeviceGuard guard(c->device);
   hipError_t e = ntu::launch_env_contract(c->cplx, precision, batch, pdim(c), D, D * c->rg, QX, QY, nbr, g, c->ws,
-                                          c->ws_bytes, c->stream, hook(c));
+                                          c->ws_bytes, c->stream, hook(c), 0, env_ks(c, D, precision));
   if (e == hipErrorNotSupported) return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
   return e == hipSuccess ? NTU_OK : hip_fail(c, e, "env_contract");
 }
@@ -455,7 +468,7 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     NTU_STEP(hipEventRecord(c->ev_join, aux), "join");
     NTU_STEP(hipStreamWaitEvent(c->stream, c->ev_edges, 0), "join");
     e = ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, QX, QY, nbr, G, c->ws, c->ws_bytes, c->stream, ph,
-                                 2);
+                                 2, env_ks(c, D, opts->precision));
     if (e == hipErrorNotSupported) return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
     if (e != hipSuccess) return hip_fail(c, e, "env_contract");
     double* sb = stats ? stats + (size_t)bi * sl : nullptr;
@@ -477,6 +490,103 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
 #undef NTU_STEP
   (void)site;
   return NTU_OK;
+}
+
+ntu_status ntu_tune_env(ntu_ctx* c, int batch, int D, int precision, const void* QX, const void* QY,
+                        const void* const nbr[6], void* g, int reps, int* best_ks, float* best_ms) {
+  ntu_status s = check_common(c, batch, D);
+  if (s) return s;
+  if (precision != NTU_PREC_BF16X3 && precision != NTU_PREC_BF16X6)
+    return fail(c, NTU_ERR_ARG, "tuning applies to the split precisions BF16x3 and BF16x6");
+  if (reps < 1) return fail(c, NTU_ERR_ARG, "reps < 1");
+  if (batch == 0) return NTU_OK;
+  if (!QX || !QY || !nbr || !g) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  for (int i = 0; i < 6; ++i)
+    if (!nbr[i]) return fail(c, NTU_ERR_ARG, "NULL neighbour pointer");
+  DeviceGuard guard(c->device);
+  const int R = D * c->rg;
+  const int kdef = ntu::e6_ksplit_default(c->cplx, batch, R, D), kcap = ntu::e6_ksplit_max(c->cplx, batch, R, D);
+  std::vector<int> cand;
+  for (int k = 1; k <= std::min(kcap, ntu::E6_KS_TUNE_MAX); ++k) cand.push_back(k);
+  if (kdef > ntu::E6_KS_TUNE_MAX) cand.push_back(kdef);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int best = kdef;
+  float tbest = -1.0f;
+  const ntu::ProfHook none{nullptr, nullptr};
+  for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
+    auto launch = [&]() {
+      return ntu::launch_env_contract(c->cplx, precision, batch, pdim(c), D, R, QX, QY, nbr, g, c->ws, c->ws_bytes,
+                                      c->stream, none, 0, cand[i]);
+    };
+    e = launch();  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    ms /= reps;
+    if (e == hipSuccess && (tbest < 0.0f || ms < tbest)) {
+      tbest = ms;
+      best = cand[i];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e == hipErrorNotSupported) return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
+  if (e != hipSuccess) return hip_fail(c, e, "tune_env");
+  c->e6_ks[{D, precision}] = best;
+  if (best_ks) *best_ks = best;
+  if (best_ms) *best_ms = tbest;
+  return NTU_OK;
+}
+
+ntu_status ntu_set_env_ksplit(ntu_ctx* c, int D, int precision, int ks) {
+  if (!c) return NTU_ERR_ARG;
+  if (D < 1 || D > c->max_D) return fail(c, NTU_ERR_SHAPE, "D outside [1, max_D]");
+  if (precision != NTU_PREC_BF16X3 && precision != NTU_PREC_BF16X6)
+    return fail(c, NTU_ERR_ARG, "the K split applies to the split precisions BF16x3 and BF16x6");
+  if (ks < 0) return fail(c, NTU_ERR_ARG, "ks < 0");
+  if (ks == 0) c->e6_ks.erase({D, precision});
+  else c->e6_ks[{D, precision}] = ks;
+  return NTU_OK;
+}
+
+int ntu_get_env_ksplit(ntu_ctx* c, int D, int precision) {
+  if (!c) return NTU_ERR_ARG;
+  return env_ks(c, D, precision);
+}
+
+ntu_status ntu_tune_save(ntu_ctx* c, const char* path) {
+  if (!c || !path) return NTU_ERR_ARG;
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(c, NTU_ERR_ARG, std::string("cannot write ") + path);
+  fprintf(f, "# D precision e6_ksplit\n");
+  for (const auto& kv : c->e6_ks) fprintf(f, "%d %d %d\n", kv.first.first, kv.first.second, kv.second);
+  const bool ok = fclose(f) == 0;
+  return ok ? NTU_OK : fail(c, NTU_ERR_ARG, std::string("cannot write ") + path);
+}
+
+ntu_status ntu_tune_load(ntu_ctx* c, const char* path) {
+  if (!c || !path) return NTU_ERR_ARG;
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(c, NTU_ERR_ARG, std::string("cannot read ") + path);
+  char line[256];
+  ntu_status s = NTU_OK;
+  while (fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    int D = 0, prec = 0, ks = 0;
+    if (sscanf(line, "%d %d %d", &D, &prec, &ks) != 3) {
+      s = fail(c, NTU_ERR_ARG, std::string("malformed line in ") + path);
+      break;
+    }
+    if (D >= 1 && D <= c->max_D && (prec == NTU_PREC_BF16X3 || prec == NTU_PREC_BF16X6) && ks > 0)
+      c->e6_ks[{D, prec}] = ks;
+  }
+  fclose(f);
+  return s;
 }
 
 ntu_status ntu_profile_enable(ntu_ctx* c, int on) {

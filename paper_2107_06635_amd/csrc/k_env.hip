@@ -370,7 +370,7 @@ size_t env_workspace_bytes(bool cplx, int precision, int batch, int p, int D, in
 
 hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D, int R, const void* QX,
                                const void* QY, const void* const nbr[6], void* g, void* ws, size_t ws_bytes,
-                               hipStream_t st, const ProfHook& ph, int part) {
+                               hipStream_t st, const ProfHook& ph, int part, int e6_ks) {
   if (batch <= 0) return hipSuccess;
   if (env_workspace_bytes(cplx, precision, batch, p, D, R) > ws_bytes) return hipErrorOutOfMemory;
   const EnvSizes s = env_sizes(p, D, R);
@@ -526,7 +526,7 @@ hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D
   } else {
     // the products of steps 4-7 on the matrix cores in split precision
     NTU_TRY(launch_env_heavy_mixed(cplx, precision, batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, s.qp,
-                                   s.half, H0, H1, H2, g, st, ph));
+                                   s.half, H0, H1, H2, g, st, ph, e6_ks));
   }
 #undef NTU_TRY
   return hipSuccess;

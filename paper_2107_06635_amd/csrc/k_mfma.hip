@@ -607,16 +607,30 @@ static int e6_ksplit(int batch, int M, int Nr, int Kr) {
   return std::min(ks, std::min(kmax, 16));
 }
 
-size_t mixed_partial_bytes(bool cplx, int batch, int R, int D) {
+// largest K split of the final assembly: the heuristic's, or a tuned one of
+// at most E6_KS_TUNE_MAX (never more chunks than steps of 8 K tiles allow)
+static int e6_ks_cap(bool cplx, int batch, int R, int D) {
   const int M = R * R, Nr = (cplx ? 2 : 1) * R * R, Kr = (cplx ? 2 : 1) * D * D * D * D;
-  const int ks = tile_ksplit(batch, M, Nr, Kr);
-  return ks > 1 ? (size_t)ks * batch * M * Nr * sizeof(double) : 0;
+  const int kmax = std::max(1, Kr / (8 * TL_K));
+  return std::max(tile_ksplit(batch, M, Nr, Kr), std::min(E6_KS_TUNE_MAX, kmax));
 }
+
+size_t mixed_partial_bytes(bool cplx, int batch, int R, int D) {
+  const int ks = e6_ks_cap(cplx, batch, R, D);
+  return ks > 1 ? (size_t)ks * batch * R * R * (cplx ? 2 : 1) * R * R * sizeof(double) : 0;
+}
+
+int e6_ksplit_default(bool cplx, int batch, int R, int D) {
+  const int M = R * R, Nr = (cplx ? 2 : 1) * R * R, Kr = (cplx ? 2 : 1) * D * D * D * D;
+  return tile_ksplit(batch, M, Nr, Kr);
+}
+
+int e6_ksplit_max(bool cplx, int batch, int R, int D) { return e6_ks_cap(cplx, batch, R, D); }
 
 template <int PREC, bool CPLX>
 static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, const void* QXp, const void* QYe,
                             const void* QYp, const void* ETT, const void* EBT, long long es, long long qs, long long hs,
-                            void* H0, void* H1, void* H2, void* g, hipStream_t st, const ProfHook& ph) {
+                            void* H0, void* H1, void* H2, void* g, hipStream_t st, const ProfHook& ph, int e6_ks) {
   using T64 = double;  // scalar of the compute-type inputs
   const long long D2 = (long long)D * D, D3 = D2 * D, D4 = D2 * D2, RD4 = (long long)R * D4;
   const int pD = p * D;
@@ -657,7 +671,8 @@ static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, con
   q.Ai = idx1(D4); q.Ak = idx1(1); q.Bj = idx1(D4); q.Bk = idx1(1);
   q.Ci = idx2(R, R, (long long)R * R * R); q.Cj = idx2(R, 1, (long long)R * R);
   const int Nr = (CPLX ? 2 : 1) * q.N, Kr = (CPLX ? 2 : 1) * q.K;
-  const int ks = tile_ksplit(batch, q.M, Nr, Kr);
+  // the tuned K split when one is given (at most the reserved e6_ks_cap)
+  const int ks = e6_ks > 0 ? std::min(e6_ks, e6_ks_cap(CPLX, batch, R, D)) : tile_ksplit(batch, q.M, Nr, Kr);
   // partial sums live right after H2 (the workspace reserves mixed_partial_bytes there)
   double* partial = (double*)((char*)H2 + (size_t)batch * hs * (CPLX ? 8 : 4));
   return run_tile<PREC, CPLX, float, float, T64>(H0, H2, g, q, ks, partial, st, ph, PK_E6);
@@ -666,8 +681,8 @@ static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, con
 hipError_t launch_env_heavy_mixed(bool cplx, int precision, int batch, int p, int D, int R, const void* QXe,
                                   const void* QXp, const void* QYe, const void* QYp, const void* ETT,
                                   const void* EBT, long long es, long long qs, long long hs, void* H0, void* H1,
-                                  void* H2, void* g, hipStream_t st, const ProfHook& ph) {
-#define NTU_MIX(P, C) return env_heavy<P, C>(batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, qs, hs, H0, H1, H2, g, st, ph)
+                                  void* H2, void* g, hipStream_t st, const ProfHook& ph, int e6_ks) {
+#define NTU_MIX(P, C) return env_heavy<P, C>(batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, qs, hs, H0, H1, H2, g, st, ph, e6_ks)
   if (precision == NTU_PREC_BF16X3) { if (cplx) NTU_MIX(NTU_PREC_BF16X3, true); NTU_MIX(NTU_PREC_BF16X3, false); }
   if (precision == NTU_PREC_BF16X6) { if (cplx) NTU_MIX(NTU_PREC_BF16X6, true); NTU_MIX(NTU_PREC_BF16X6, false); }
   // FP16X3 needs operand scales; not wired into the environment yet

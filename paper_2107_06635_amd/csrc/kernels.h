@@ -52,7 +52,7 @@ size_t env_workspace_bytes(bool cplx, int precision, int batch, int p, int D, in
 // (steps 1-2, they read only the neighbours); 2: the rest (they must have run)
 hipError_t launch_env_contract(bool cplx, int precision, int batch, int p, int D, int R, const void* QX,
                                const void* QY, const void* const nbr[6], void* g, void* ws, size_t ws_bytes,
-                               hipStream_t st, const ProfHook& ph, int part = 0);
+                               hipStream_t st, const ProfHook& ph, int part = 0, int e6_ks = 0);
 
 // ---------------------------------------------------------------------------
 // metric repair and fit

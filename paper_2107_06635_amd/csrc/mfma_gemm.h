@@ -23,7 +23,7 @@ struct GemmNT {
 hipError_t launch_env_heavy_mixed(bool cplx, int precision, int batch, int p, int D, int R, const void* QXe,
                                   const void* QXp, const void* QYe, const void* QYp, const void* ETT,
                                   const void* EBT, long long es, long long qs, long long hs, void* H0, void* H1,
-                                  void* H2, void* g, hipStream_t st, const struct ProfHook& ph);
+                                  void* H2, void* g, hipStream_t st, const struct ProfHook& ph, int e6_ks = 0);
 
 // Environment products fused per (item, a, a') block on the matrix cores
 // (complex, BF16x3 or BF16x6, D^2 <= 64): Right into H2, L2 (from Left, L1
@@ -36,6 +36,12 @@ hipError_t launch_env_fused(int precision, int batch, int p, int D, int R, const
                             long long qs, void* H0, void* H1, void* H2, long long hs, hipStream_t st,
                             const struct ProfHook& ph);
 
+// K split of the final assembly g = L2 Right^T (E6): e6_ks > 0 asks for that
+// many K chunks (autotuning), at most e6_ksplit_max; 0 takes the heuristic
+// e6_ksplit_default.  The workspace reserves the partial sums of the largest.
+constexpr int E6_KS_TUNE_MAX = 4;
+int e6_ksplit_default(bool cplx, int batch, int R, int D);
+int e6_ksplit_max(bool cplx, int batch, int R, int D);
 // bytes of FP64 split-K partial sums the final assembly needs after H2
 size_t mixed_partial_bytes(bool cplx, int batch, int R, int D);
 

@@ -31,6 +31,7 @@ EXPORTED = (
     "ntu_version", "ntu_gate_split", "ntu_reduce_qr", "ntu_env_contract", "ntu_metric_fix",
     "ntu_fit_opts_default", "ntu_bond_fit", "ntu_recombine", "ntu_step_opts_default", "ntu_trotter_step",
     "ntu_profile_enable", "ntu_profile_read", "ntu_profile_kind_name",
+    "ntu_tune_env", "ntu_set_env_ksplit", "ntu_get_env_ksplit", "ntu_tune_save", "ntu_tune_load",
 )
 
 
@@ -78,6 +79,12 @@ def load():
     L.ntu_step_opts_default.restype = None
     L.ntu_trotter_step.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(StepOpts), vp]
     L.ntu_profile_enable.argtypes = [vp, i32]
+    L.ntu_tune_env.argtypes = [vp, i32, i32, i32, vp, vp, ctypes.POINTER(vp), vp, i32, ctypes.POINTER(i32),
+                               ctypes.POINTER(ctypes.c_float)]
+    L.ntu_set_env_ksplit.argtypes = [vp, i32, i32, i32]
+    L.ntu_get_env_ksplit.argtypes = [vp, i32, i32]
+    L.ntu_tune_save.argtypes = [vp, ctypes.c_char_p]
+    L.ntu_tune_load.argtypes = [vp, ctypes.c_char_p]
     L.ntu_profile_read.argtypes = [vp, dp, ctypes.POINTER(i32), i32]
     L.ntu_profile_kind_name.argtypes = [i32]
     L.ntu_profile_kind_name.restype = ctypes.c_char_p
@@ -211,6 +218,41 @@ def ntu_env_contract(ctx: Context, QX, QY, nbr, precision="f64", D=None):
     ctx.bind_stream()
     ctx.check(ctx.L.ntu_env_contract(ctx.h, b, D, _ptr(QX), _ptr(QY), arr, prec, _ptr(g)), "ntu_env_contract")
     return g
+
+
+def ntu_tune_env(ctx: Context, QX, QY, nbr, precision="bf16x6", D=None, reps=3):
+    """Times the metric assembly's K split candidates on these operands, keeps
+    the fastest in the context; -> (K split, mean ms)."""
+    b = QX.shape[0]
+    if D is None:
+        D = nbr[0].shape[2]
+    Rd = D * ctx.r_g
+    g = ctx.empty(b, Rd * Rd, Rd * Rd)
+    arr = (ctypes.c_void_p * 6)(*[_ptr(t) for t in nbr])
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    ks, ms = ctypes.c_int(0), ctypes.c_float(0.0)
+    ctx.bind_stream()
+    ctx.check(ctx.L.ntu_tune_env(ctx.h, b, D, prec, _ptr(QX), _ptr(QY), arr, _ptr(g), reps, ctypes.byref(ks),
+                                 ctypes.byref(ms)), "ntu_tune_env")
+    return ks.value, ms.value
+
+
+def ntu_set_env_ksplit(ctx: Context, D, precision, ks):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    ctx.check(ctx.L.ntu_set_env_ksplit(ctx.h, D, prec, ks), "ntu_set_env_ksplit")
+
+
+def ntu_get_env_ksplit(ctx: Context, D, precision):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return ctx.L.ntu_get_env_ksplit(ctx.h, D, prec)
+
+
+def ntu_tune_save(ctx: Context, path):
+    ctx.check(ctx.L.ntu_tune_save(ctx.h, str(path).encode()), "ntu_tune_save")
+
+
+def ntu_tune_load(ctx: Context, path):
+    ctx.check(ctx.L.ntu_tune_load(ctx.h, str(path).encode()), "ntu_tune_load")
 
 
 def ntu_metric_fix(ctx: Context, g: torch.Tensor, D: int, mode=FIX_HERM_CLIP):

@@ -139,6 +139,40 @@ def test_env_contract_mixed(prec, tol, D, p, real):
     assert err < tol
 
 
+def test_env_tuning(tmp_path):
+    """Autotuned K split of the split-precision metric assembly: every
+    candidate gives the metric within the BF16x6 budget of the oracle; the
+    tuned choice is kept and used, set and reset by hand, and survives a
+    save / load round trip into a fresh context."""
+    D, p = 5, 2
+    X, Y, nbr, G, GA, GB = _case(310, D, p, False)
+    QX, _ = O.reduce_site(X, GA, 'X', 2)
+    QY, _ = O.reduce_site(Y, GB, 'Y', 2)
+    go = O.metric(QX, QY, nbr)
+    R = D * 2
+    q = lambda Q: batched([Q.reshape(-1, R), Q.reshape(-1, R)])
+    nb = [batched([t, t]) for t in nbr]
+    ctx = _ctx(max_D=D)
+    ks, ms = ntu.ntu_tune_env(ctx, q(QX), q(QY), nb, "bf16x6", D=D)
+    assert 1 <= ks <= 4 and ms > 0 and ntu.ntu_get_env_ksplit(ctx, D, "bf16x6") == ks
+    assert ntu.ntu_get_env_ksplit(ctx, D, "bf16x3") == 0
+    for k in (1, 2, 3, 4, 0):
+        ntu.ntu_set_env_ksplit(ctx, D, "bf16x6", k)
+        assert ntu.ntu_get_env_ksplit(ctx, D, "bf16x6") == k
+        g = to_np(ntu.ntu_env_contract(ctx, q(QX), q(QY), nb, "bf16x6"))
+        for i in range(2):
+            assert rel(g[i], go) < 1e-6, (k, i)
+    ntu.ntu_set_env_ksplit(ctx, D, "bf16x6", 3)
+    ntu.ntu_set_env_ksplit(ctx, 4, "bf16x3", 2)
+    path = tmp_path / "tune.txt"
+    ntu.ntu_tune_save(ctx, path)
+    fresh = _ctx(max_D=D)
+    ntu.ntu_tune_load(fresh, path)
+    assert ntu.ntu_get_env_ksplit(fresh, D, "bf16x6") == 3 and ntu.ntu_get_env_ksplit(fresh, 4, "bf16x3") == 2
+    with pytest.raises(RuntimeError):
+        ntu.ntu_tune_env(ctx, q(QX), q(QY), nb, "f64", D=D)
+
+
 # ------------------------------------------------------------------ metric fix
 
 @pytest.mark.parametrize("real", [False, True])
