@@ -463,9 +463,9 @@ def main():
         t0 = time.perf_counter()
         n_bonds = 0
         if args.workload == "batched":
-            # the items in order (SVDU updates are cheap: cycle through them
-            # until the time budget is spent)
-            while time.perf_counter() - t0 < args.cpu_seconds and (args.scheme == "svdu" or n_bonds < len(job.items)):
+            # the items in order, cycling through them until the time budget
+            # is spent
+            while time.perf_counter() - t0 < args.cpu_seconds:
                 it = job.items[n_bonds % len(job.items)]
                 GAo, GBo, _ = O.gate_split(it["gate"], 2, 2)
                 A = it["A"].astype(np.complex128)
@@ -476,7 +476,7 @@ def main():
                 else:
                     O.bond_update(X, Y, nbr, GAo, GBo, it["D"], n_iter=20, conv_tol=1e-12)
                 n_bonds += 1
-            sample = (f"{n_bonds} of the 256 items in order (mixed D), "
+            sample = (f"{n_bonds} bond updates cycling through the 256 items in order (mixed D), "
                       f"oracle FP64 numpy/BLAS{', SVDU updates' if args.scheme == 'svdu' else ''}")
         else:
             An, Bn = init[0][0].cpu().numpy()[0], init[0][1].cpu().numpy()[0]
