@@ -112,6 +112,41 @@ def test_config2_quench_drift(D):
     assert worst["bf16x6"] < 1e-7, worst
 
 
+@pytest.mark.parametrize("D,tol", [(4, {"f64": 1e-11, "bf16x3": 1e-8, "bf16x6": 1e-8}),
+                                   (6, {"f64": 1e-6, "bf16x3": 1e-6, "bf16x6": 1e-6})])
+def test_config3_thermal_drift(D, tol):
+    """Configuration 3 prefix: 30 imaginary-time steps from the beta = 0
+    purification (real, p = 4) on the FP64, BF16x3 and BF16x6 GPU paths
+    beside the oracle: energy and <X> after every step (degenerate metrics:
+    rank rule, eigenvalue clip, ladder solves).  Measured at D = 4: 2e-13
+    (FP64), 1.3e-10 (BF16x3), 5e-12 (BF16x6).  At D = 6 every path, FP64
+    included, sits 2e-8 - 1.5e-7 from the oracle from the first steps on: the
+    metrics there are degenerate enough that the ladder's choice between
+    near-equal errors (and ranks at the cut) is decided by rounding, and both
+    sides take valid minimisers; the bound there is the 1e-6 the method's
+    precision target asks of the energy."""
+    w = inputs.workload_thermal(D=D)
+    GA, GB, _ = O.gate_split(w['gates'][0], 2, 2)
+    pairs = {b: (GA, GB) for b in O.BONDS}
+    gf = to_dev(gate_factors_array(pairs, False)[None])
+    ctx = ntu.Context(complex_=False, d=2, d_anc=2, r_g=2, max_D=D, max_batch=1)
+    A, B = w['A'], w['B']
+    paths = {p: [to_dev(A[None]), to_dev(B[None])] for p in ("f64", "bf16x3", "bf16x6")}
+    opts = {p: ntu.step_opts(p, n_iter=N_ITER, early_stop=True, conv_tol=CONV) for p in paths}
+    worst = {p: 0.0 for p in paths}
+    for step in range(30):
+        A, B, _ = O.trotter_step(A, B, pairs, D, n_iter=N_ITER, conv_tol=CONV)
+        eo, xo = O.observables(A, B, 2.5)
+        for p, (Ag, Bg) in paths.items():
+            ntu.ntu_trotter_step(ctx, Ag, Bg, gf, opts[p], stats=False)
+            eg, xg = O.observables(to_np(Ag)[0], to_np(Bg)[0], 2.5)
+            worst[p] = max(worst[p], abs(eg - eo), abs(xg - xo))
+        if step % 10 == 9:
+            print(f"D={D} step {step + 1}: energy {eo:.8f}, worst |difference| so far {worst}", flush=True)
+    for p in paths:
+        assert worst[p] < tol[p], (p, worst)
+
+
 def test_config4_all_items_svdu():
     """SVDU scheme on all 256 items of configuration 4, in the batched
     launches bench.py --scheme svdu times: ranks, normalised singular values
