@@ -121,7 +121,8 @@ def env_assembly_flops(R, D, cplx):
 
 def traffic_record(kernel):
     """HBM bytes per launch of `kernel` from the committed counter runs, or
-    None when the kernel's source has changed since they were taken."""
+    None when its source (the kernel's file and the shared headers) has
+    changed since they were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -129,8 +130,10 @@ def traffic_record(kernel):
     rec = json.load(open(path)).get(kernel)
     if not rec:
         return None
-    src = os.path.join(ROOT, rec["source"])
-    if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != rec["sha1"]:
+    srcs = [os.path.join(ROOT, f) for f in rec.get("sources", [rec["source"]])]
+    if not all(os.path.exists(f) for f in srcs):
+        return None
+    if hashlib.sha1(b"".join(open(f, "rb").read() for f in srcs)).hexdigest() != rec["sha1"]:
         return None
     return rec
 

@@ -11,9 +11,9 @@ namespace ntu {
 // Given alpha = |c_p|^2, beta = |c_q|^2, gamma = c_p^H c_q, the rotation is
 // J = diag(1, e^{-i phi}) [[c, s], [-s, c]] with gamma = |gamma| e^{i phi}.
 template <class T>
-NTU_DEV bool jacobi_params(double alpha, double beta, T gamma, double& c, double& s, T& e) {
+NTU_DEV bool jacobi_params(double alpha, double beta, T gamma, double& c, double& s, T& e, double gfloor = 0.0) {
   double g = absv(gamma);
-  if (!(g > 1e-15 * sqrt(alpha * beta)) || g == 0.0) return false;
+  if (!(g > 1e-15 * sqrt(alpha * beta)) || !(g > gfloor)) return false;
   double zeta = (beta - alpha) / (2.0 * g);
   double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   c = 1.0 / sqrt(1.0 + t * t);
@@ -101,6 +101,19 @@ NTU_DEV void svd_block_small(T* A, int m, int n, int lda, T* V, int ldv, double*
     int i = e % n, j = e / n;
     V[i + j * ldv] = realv<T>(i == j ? 1.0 : 0.0);
   }
+  // Column pairs whose inner product is below (1e-15 ||A||_F)^2 are left
+  // alone: such columns are rounding noise of the rotations (their singular
+  // values lie below 1e-15 of the largest), and rotating them against each
+  // other only makes new noise of the same size, so the sweeps would not end.
+  __shared__ double fro2_sh;
+  if (tid == 0) {
+    double f2 = 0.0;
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < m; ++i) f2 += abs2(A[i + j * lda]);
+    fro2_sh = f2;
+  }
+  __syncthreads();
+  const double gfloor = 1e-30 * fro2_sh;
   const int n2 = (n + 1) & ~1;
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) *sh_flag = 0;
@@ -120,7 +133,7 @@ NTU_DEV void svd_block_small(T* A, int m, int n, int lda, T* V, int ldv, double*
         a = lanes32_sum(a); b = lanes32_sum(b); g = lanes32_sum(g);
         double c, sn;
         T e;
-        if (!jacobi_params(a, b, g, c, sn, e)) continue;
+        if (!jacobi_params(a, b, g, c, sn, e, gfloor)) continue;
         if (lane < m) {
           T x = A[lane + p * lda], y = A[lane + q * lda] * e;
           A[lane + p * lda] = c * x - sn * y;
