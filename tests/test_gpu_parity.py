@@ -32,6 +32,53 @@ def _case(seed, D, p=2, real=False, dt=0.05, hx=3.0):
     return X, Y, nbr, G, GA, GB
 
 
+# ------------------------------------------------------------------ boundary
+
+def test_empty_batch_and_argument_errors():
+    """C ABI edge cases: batch 0 is a no-op on every compute call (NULL
+    buffers allowed); sizes outside the context, bad enums and NULL buffers
+    give their status codes and a message, before any launch; FP16x3 reports
+    itself unsupported."""
+    import ctypes
+    ctx = _ctx(max_D=3, max_batch=2)
+    L, h = ctx.L, ctx.h
+    NULL = None
+    nbr0 = (ctypes.c_void_p * 6)()
+    fo = ntu.fit_opts(n_iter=3)
+    so = ntu.step_opts("f64", n_iter=3)
+    OK, ARG, SHAPE, WS, UNSUP = 0, -1, -2, -6, -7
+    ctx.bind_stream()
+    assert L.ntu_gate_split(h, 0, NULL, NULL, NULL, NULL) == OK
+    assert L.ntu_reduce_qr(h, 0, 3, NULL, 1, NULL, 0, NULL, NULL) == OK
+    assert L.ntu_env_contract(h, 0, 3, NULL, NULL, nbr0, 3, NULL) == OK
+    assert L.ntu_metric_fix(h, 0, 3, NULL, 1, NULL) == OK
+    assert L.ntu_bond_fit(h, 0, 3, NULL, NULL, NULL, ctypes.byref(fo), NULL, NULL, NULL) == OK
+    assert L.ntu_recombine(h, 0, 3, NULL, NULL, NULL, NULL, NULL, NULL) == OK
+    assert L.ntu_trotter_step(h, 0, 3, NULL, NULL, NULL, ctypes.byref(so), NULL) == OK
+    # sizes outside the context, negative batch, NULL buffers, bad enums
+    assert L.ntu_reduce_qr(h, 1, 4, NULL, 1, NULL, 0, NULL, NULL) == SHAPE
+    assert L.ntu_reduce_qr(h, 3, 3, NULL, 1, NULL, 0, NULL, NULL) == WS
+    assert L.ntu_reduce_qr(h, -1, 3, NULL, 1, NULL, 0, NULL, NULL) == ARG
+    assert L.ntu_reduce_qr(h, 1, 3, NULL, 1, NULL, 0, NULL, NULL) == ARG
+    assert L.ntu_last_error(h).decode()
+    assert L.ntu_env_contract(h, 1, 3, NULL, NULL, nbr0, 9, NULL) == ARG
+    assert L.ntu_metric_fix(h, 1, 3, NULL, 7, NULL) == ARG
+    bad = ntu.step_opts("f64", n_iter=3)
+    bad.scheme = 5
+    assert L.ntu_trotter_step(h, 1, 3, NULL, NULL, NULL, ctypes.byref(bad), NULL) == ARG
+    bad = ntu.step_opts("f64", n_iter=3)
+    bad.n_bonds = 9
+    assert L.ntu_trotter_step(h, 1, 3, NULL, NULL, NULL, ctypes.byref(bad), NULL) == ARG
+    # FP16x3 is declared but not available: a clear status, not wrong numbers
+    X, Y, nbr, G, GA, GB = _case(320, 3)
+    QX, _ = O.reduce_site(X, GA, 'X', 2)
+    QY, _ = O.reduce_site(Y, GB, 'Y', 2)
+    q = lambda Q: batched([Q.reshape(-1, 6)])
+    with pytest.raises(RuntimeError, match="not available"):
+        ntu.ntu_env_contract(ctx, q(QX), q(QY), [batched([t]) for t in nbr], "fp16x3")
+    torch.cuda.synchronize()
+
+
 # ------------------------------------------------------------------ gate split
 
 @pytest.mark.parametrize("real", [False, True])
