@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(NT) k_reduce_qr_reg(int d, int na, int D, int 
 // ---------------------------------------------------------------------------
 constexpr int CQR_THREADS = 512;
 constexpr int CQR_RMAX = 24;        // largest R on this path
-constexpr int CQR_CH = 64;          // rows per chunk
+constexpr int CQR_CH = 128;         // rows per chunk
 constexpr int CQR_LD = CQR_RMAX + 1;
 constexpr double CQR_PIV = 1e-6;
 
