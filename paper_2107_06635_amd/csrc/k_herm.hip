@@ -6,18 +6,22 @@
 namespace ntu {
 
 constexpr int HERM_THREADS = 256;
+constexpr int HERM_SPLIT = 16;  // workgroups per item
 constexpr int CLIP_THREADS = 1024;
 
-// (g + g^H) / 2 in place, with ||g - g^H||_F, ||g||_F and the count of
-// non-finite entries of the input.
+// (g + g^H) / 2 in place.  Workgroup (item, b) of HERM_SPLIT takes the b-th
+// range of the pairs (i, j), j <= i, so each pair is written by one thread;
+// it leaves its partial ||g - g^H||_F^2, ||g||_F^2 and count of non-finite
+// input entries in part[item][b] (k_herm_stats adds them up).
 template <class T>
-__global__ void __launch_bounds__(HERM_THREADS) k_hermitise(int n, T* g, double* stats, int sstride) {
+__global__ void __launch_bounds__(HERM_THREADS) k_hermitise(int n, T* g, double* part) {
   __shared__ double red[64];
-  const int it = blockIdx.x;
+  const int it = blockIdx.x, b = blockIdx.y, nb = gridDim.y;
   T* G = g + (size_t)it * n * n;
   double skew = 0, nrm = 0, bad = 0;
   const long long npair = (long long)n * (n + 1) / 2;
-  for (long long e = threadIdx.x; e < npair; e += blockDim.x) {
+  const long long e0 = npair * b / nb, e1 = npair * (b + 1) / nb;
+  for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     // packed lower triangle, row-wise: e -> (i, j), j <= i
     int i = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
     while ((long long)(i + 1) * (i + 2) / 2 <= e) ++i;
@@ -42,13 +46,26 @@ __global__ void __launch_bounds__(HERM_THREADS) k_hermitise(int n, T* g, double*
   skew = block_sum(skew, red);
   nrm = block_sum(nrm, red);
   bad = block_sum(bad, red);
-  if (stats && threadIdx.x == 0) {
-    double* s = stats + (size_t)it * sstride;
-    s[0] = nrm > 0 ? sqrt(skew) / sqrt(nrm) : 0.0;
-    s[1] = sqrt(nrm);
-    s[2] = NAN; s[3] = NAN; s[4] = 0.0; s[5] = 0.0;
-    s[6] = bad; s[7] = 0.0;
+  if (part && threadIdx.x == 0) {
+    double* pp = part + ((size_t)it * nb + b) * 3;
+    pp[0] = skew; pp[1] = nrm; pp[2] = bad;
   }
+}
+
+// Stats of the Hermitisation from the partial sums: one thread per item.
+__global__ void k_herm_stats(int batch, int nb, const double* __restrict__ part, double* stats, int sstride) {
+  const int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= batch) return;
+  double skew = 0, nrm = 0, bad = 0;
+  for (int b = 0; b < nb; ++b) {
+    const double* pp = part + ((size_t)it * nb + b) * 3;
+    skew += pp[0]; nrm += pp[1]; bad += pp[2];
+  }
+  double* s = stats + (size_t)it * sstride;
+  s[0] = nrm > 0 ? sqrt(skew) / sqrt(nrm) : 0.0;
+  s[1] = sqrt(nrm);
+  s[2] = NAN; s[3] = NAN; s[4] = 0.0; s[5] = 0.0;
+  s[6] = bad; s[7] = 0.0;
 }
 
 // Eigenvalue clip of the Hermitian g.  Rows that are exactly zero are left
@@ -154,16 +171,25 @@ __global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stat
 }
 
 size_t fix_workspace_bytes(bool cplx, int batch, int n) {
-  return (size_t)batch * 2 * n * n * (cplx ? 16 : 8) + 256;
+  // the clip's two n x n matrices per item; the Hermitisation's partial sums
+  // (batch x HERM_SPLIT x 3 doubles) use the same space first
+  const size_t clip = (size_t)batch * 2 * n * n * (cplx ? 16 : 8);
+  const size_t part = (size_t)batch * HERM_SPLIT * 3 * sizeof(double);
+  return (clip > part ? clip : part) + 256;
 }
 
 hipError_t launch_metric_fix(bool cplx, int batch, int n, void* g, int mode, double* stats, int sstride,
                              void* ws, hipStream_t st, const ProfHook& ph, double shift_rel, double* cert) {
   if (batch <= 0) return hipSuccess;
   if (n > 1024) return hipErrorInvalidValue;
+  // partial sums at the start of the workspace (read by k_herm_stats before
+  // the clip reuses it; same stream)
+  double* part = stats ? (double*)ws : nullptr;
   ph(PK_HERM, 0);
-  if (cplx) hipLaunchKernelGGL(k_hermitise<cd>, dim3(batch), dim3(HERM_THREADS), 0, st, n, (cd*)g, stats, sstride);
-  else hipLaunchKernelGGL(k_hermitise<double>, dim3(batch), dim3(HERM_THREADS), 0, st, n, (double*)g, stats, sstride);
+  const dim3 hg(batch, HERM_SPLIT);
+  if (cplx) hipLaunchKernelGGL(k_hermitise<cd>, hg, dim3(HERM_THREADS), 0, st, n, (cd*)g, part);
+  else hipLaunchKernelGGL(k_hermitise<double>, hg, dim3(HERM_THREADS), 0, st, n, (double*)g, part);
+  if (stats) hipLaunchKernelGGL(k_herm_stats, dim3((batch + 63) / 64), dim3(64), 0, st, batch, HERM_SPLIT, part, stats, sstride);
   ph(PK_HERM, 1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || mode == 0) return e;
