@@ -104,6 +104,14 @@ __global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stat
   }
   __syncthreads();
   const int m = m_sh;
+  // positive definite (the clip is the identity) if the Gershgorin discs of
+  // the full matrix stay right of zero (tested first: it reads g once and
+  // needs no copy), or else if a Cholesky factor exists
+  if (m == n && gershgorin_certify<T>(G, n, shift_rel, red)) {
+    if (cert && tid == 0) cert[it] = 1.0;
+    return;
+  }
+  if (cert && tid == 0) cert[it] = 0.0;
   double fro = 0;
   for (long long e = tid; e < (long long)m * m; e += blockDim.x) {
     int i = (int)(e / m), j = (int)(e % m);
@@ -113,13 +121,6 @@ __global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stat
   }
   fro = sqrt(block_sum(fro, red));
   __syncthreads();
-  // positive definite (the clip is the identity) if the Gershgorin discs of
-  // the full matrix stay right of zero, or else if a Cholesky factor exists
-  if (m == n && gershgorin_certify<T>(G, n, shift_rel, red)) {
-    if (cert && tid == 0) cert[it] = 1.0;
-    return;
-  }
-  if (cert && tid == 0) cert[it] = 0.0;
   if (shift_rel > 0.0 && m == n) {
     const double sh = shift_rel * fro;
     for (int i = tid; i < m; i += blockDim.x) A[(size_t)i * m + i] = A[(size_t)i * m + i] - realv<T>(sh);
