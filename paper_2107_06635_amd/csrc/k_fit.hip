@@ -183,6 +183,7 @@ NTU_DEV double fit_solve(const T* gs, int nx, const FitParams& fp, const FitShar
   __shared__ int m_sh, cnt;
   __shared__ double pc[256], ps[256];
   __shared__ T pe[256];
+  __shared__ int pq[256];
   const int tid = threadIdx.x;
   // exactly-zero rows
   for (int i = tid; i < nx; i += blockDim.x) {
@@ -257,7 +258,7 @@ NTU_DEV double fit_solve(const T* gs, int nx, const FitParams& fp, const FitShar
   for (long long e = tid; e < (long long)m * m; e += blockDim.x)
     A[e] = gs[(size_t)S.idx[e / m] * nx + S.idx[e % m]];
   __syncthreads();
-  block_jacobi_eigh<T>(A, m, m, X, m, pc, ps, pe, &cnt, fro);
+  block_jacobi_eigh<T>(A, m, m, X, m, pc, ps, pe, pq, &cnt, fro);
   double lmax = -INFINITY;
   for (int i = tid; i < m; i += blockDim.x) lmax = fmax(lmax, rev(A[(size_t)i * m + i]));
   lmax = block_max(lmax, S.red);

@@ -82,6 +82,7 @@ __global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stat
   __shared__ int m_sh, cnt;
   __shared__ double pc[512], ps[512];
   __shared__ T pe[512];
+  __shared__ int pq[512];
   const int it = blockIdx.x, tid = threadIdx.x;
   T* G = g + (size_t)it * n * n;
   T* A = ws + (size_t)it * 2 * n * n;
@@ -142,7 +143,8 @@ __global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stat
     A[e] = G[(size_t)idx[i] * n + idx[j]];
   }
   __syncthreads();
-  const int sweeps = block_jacobi_eigh<T>(A, m, m, V, m, pc, ps, pe, &cnt, fro);
+  // a smaller load batch than the default keeps 1024 threads within 128 VGPRs
+  const int sweeps = block_jacobi_eigh<T, is_cplx<T>::value ? 2 : 4>(A, m, m, V, m, pc, ps, pe, pq, &cnt, fro);
   // eigenvalues on the diagonal of A
   double lmin = INFINITY, lmax = -INFINITY, neg = 0, tot = 0;
   for (int i = tid; i < m; i += blockDim.x) {

@@ -216,10 +216,12 @@ NTU_DEV bool block_cholesky(T* A, int n, int lda, double* red) {
 // (row-major, lda; destroyed: on return its diagonal holds the eigenvalues)
 // with eigenvectors accumulated in V (row-major, ldv; column j = vector j).
 // Round-robin ordering: n/2 disjoint rotations per round.  Whole block.
-// par: shared scratch of >= 3 * ((n+1)/2) doubles + same count of T.
-template <class T>
+// pc, ps, pe, pq: shared scratch of >= (n+1)/2 entries each (n <= 2^15).
+// JB: entries per thread whose loads are in flight together in the update
+// passes (registers: 4 JB values of T for A, 2 JB for V).
+template <class T, int JB = (is_cplx<T>::value ? 4 : 8)>
 NTU_DEV int block_jacobi_eigh(T* A, int n, int lda, T* V, int ldv, double* pc, double* ps, T* pe,
-                              int* sh_cnt, double fro) {
+                              int* pq, int* sh_cnt, double fro) {
   const int tid = threadIdx.x;
   for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
     int i = (int)(e / n), j = (int)(e % n);
@@ -228,6 +230,7 @@ NTU_DEV int block_jacobi_eigh(T* A, int n, int lda, T* V, int ldv, double* pc, d
   __syncthreads();
   if (n < 2) return 0;
   const int n2 = (n + 1) & ~1, np = n2 / 2;
+  const int bq = (int)blockDim.x / np, br = (int)blockDim.x % np;
   // Off-diagonal entries below 1e-14 ||A||_F are left alone.  That is the
   // rounding level of the input itself (a metric summed over thousands of
   // terms in FP64); rotating entries at that level (the mutual entries of a
@@ -244,6 +247,7 @@ NTU_DEV int block_jacobi_eigh(T* A, int n, int lda, T* V, int ldv, double* pc, d
       for (int k = tid; k < np; k += blockDim.x) {
         int p, q;
         rr_pair(n2, r, k, p, q);
+        pq[k] = p | (q << 16);  // the round's pairs for the update passes
         pc[k] = 1.0; ps[k] = 0.0; pe[k] = realv<T>(1.0);
         if (q >= n) continue;
         T apq = A[p * lda + q];
@@ -266,53 +270,101 @@ NTU_DEV int block_jacobi_eigh(T* A, int n, int lda, T* V, int ldv, double* pc, d
       // followed by a pass over all columns).  k2 runs fastest over the
       // threads, so a wave touches two rows of A.  Indices >= n belong to the
       // dummy of an odd n and are left out.
-      for (long long e = tid; e < (long long)np * np; e += blockDim.x) {
-        const int k1 = (int)(e / np), k2 = (int)(e % np);
-        const double s1 = ps[k1], s2 = ps[k2];
-        if (s1 == 0.0 && s2 == 0.0) continue;
-        int p1, q1, p2, q2;
-        rr_pair(n2, r, k1, p1, q1);
-        rr_pair(n2, r, k2, p2, q2);
-        const bool hq1 = q1 < n, hq2 = q2 < n;
-        T a = A[p1 * lda + p2];
-        T b = hq2 ? A[p1 * lda + q2] : zerov<T>();
-        T c_ = hq1 ? A[q1 * lda + p2] : zerov<T>();
-        T d_ = hq1 && hq2 ? A[q1 * lda + q2] : zerov<T>();
-        if (s1 != 0.0) {
-          const double c = pc[k1];
-          const T ec = conjv(pe[k1]);
-          T x = a, y = ec * c_;
-          a = c * x - s1 * y;
-          c_ = s1 * x + c * y;
-          x = b; y = ec * d_;
-          b = c * x - s1 * y;
-          d_ = s1 * x + c * y;
+      // A thread loads a chunk of JB entries before it updates any of them:
+      // taken one at a time, the loads of an entry would wait for the stores
+      // of the one before (the compiler cannot rule out that they alias), one
+      // memory round trip per entry.  Every entry of a round belongs to one
+      // thread, so the order does not change any result.  The pair indices
+      // of entry e = k1 np + k2 advance by blockDim.x = bq np + br per step
+      // (no integer divisions, which AMDGPU does in software).
+      const int na = np * np;
+      int k1 = tid / np, k2 = tid % np;
+      for (int e0 = tid; e0 < na; e0 += JB * (int)blockDim.x) {
+        int K1[JB], K2[JB];
+        T ea[JB], eb[JB], ec_[JB], ed[JB];
+#pragma unroll
+        for (int u = 0; u < JB; ++u) {
+          K1[u] = k1; K2[u] = k2;
+          k2 += br; k1 += bq;
+          if (k2 >= np) { k2 -= np; ++k1; }
         }
-        if (s2 != 0.0) {
-          const double c = pc[k2];
-          const T ev = pe[k2];
-          T x = a, y = b * ev;
-          a = c * x - s2 * y;
-          b = s2 * x + c * y;
-          x = c_; y = d_ * ev;
-          c_ = c * x - s2 * y;
-          d_ = s2 * x + c * y;
+#pragma unroll
+        for (int u = 0; u < JB; ++u) {
+          ea[u] = eb[u] = ec_[u] = ed[u] = zerov<T>();
+          if (K1[u] >= np) continue;
+          if (ps[K1[u]] == 0.0 && ps[K2[u]] == 0.0) continue;
+          const int pq1 = pq[K1[u]], pq2 = pq[K2[u]];
+          const int p1 = pq1 & 0xffff, q1 = pq1 >> 16, p2 = pq2 & 0xffff, q2 = pq2 >> 16;
+          const bool hq1 = q1 < n, hq2 = q2 < n;
+          ea[u] = A[p1 * lda + p2];
+          if (hq2) eb[u] = A[p1 * lda + q2];
+          if (hq1) ec_[u] = A[q1 * lda + p2];
+          if (hq1 && hq2) ed[u] = A[q1 * lda + q2];
         }
-        A[p1 * lda + p2] = a;
-        if (hq2) A[p1 * lda + q2] = b;
-        if (hq1) A[q1 * lda + p2] = c_;
-        if (hq1 && hq2) A[q1 * lda + q2] = d_;
+#pragma unroll
+        for (int u = 0; u < JB; ++u) {
+          if (K1[u] >= np) continue;
+          const double s1 = ps[K1[u]], s2 = ps[K2[u]];
+          if (s1 == 0.0 && s2 == 0.0) continue;
+          const int pq1 = pq[K1[u]], pq2 = pq[K2[u]];
+          const int p1 = pq1 & 0xffff, q1 = pq1 >> 16, p2 = pq2 & 0xffff, q2 = pq2 >> 16;
+          const bool hq1 = q1 < n, hq2 = q2 < n;
+          T a = ea[u], b = eb[u], c_ = ec_[u], d_ = ed[u];
+          if (s1 != 0.0) {
+            const double c = pc[K1[u]];
+            const T ec = conjv(pe[K1[u]]);
+            T x = a, y = ec * c_;
+            a = c * x - s1 * y;
+            c_ = s1 * x + c * y;
+            x = b; y = ec * d_;
+            b = c * x - s1 * y;
+            d_ = s1 * x + c * y;
+          }
+          if (s2 != 0.0) {
+            const double c = pc[K2[u]];
+            const T ev = pe[K2[u]];
+            T x = a, y = b * ev;
+            a = c * x - s2 * y;
+            b = s2 * x + c * y;
+            x = c_; y = d_ * ev;
+            c_ = c * x - s2 * y;
+            d_ = s2 * x + c * y;
+          }
+          A[p1 * lda + p2] = a;
+          if (hq2) A[p1 * lda + q2] = b;
+          if (hq1) A[q1 * lda + p2] = c_;
+          if (hq1 && hq2) A[q1 * lda + q2] = d_;
+        }
       }
-      for (long long e = tid; e < (long long)n * np; e += blockDim.x) {
-        const int i = (int)(e / np), k = (int)(e % np);
-        if (ps[k] == 0.0) continue;
-        int p, q;
-        rr_pair(n2, r, k, p, q);
-        const double c = pc[k], s = ps[k];
-        const T ev = pe[k];
-        const T x = V[i * ldv + p], y = V[i * ldv + q] * ev;
-        V[i * ldv + p] = c * x - s * y;
-        V[i * ldv + q] = s * x + c * y;
+      // V <- V J: entry e = i np + k, row i, pair k; the same stepping
+      const int nv = n * np;
+      int vi = tid / np, vk = tid % np;
+      for (int e0 = tid; e0 < nv; e0 += JB * (int)blockDim.x) {
+        int I[JB], K[JB];
+        T vx[JB], vy[JB];
+#pragma unroll
+        for (int u = 0; u < JB; ++u) {
+          I[u] = vi; K[u] = vk;
+          vk += br; vi += bq;
+          if (vk >= np) { vk -= np; ++vi; }
+        }
+#pragma unroll
+        for (int u = 0; u < JB; ++u) {
+          vx[u] = vy[u] = zerov<T>();
+          if (I[u] >= n || ps[K[u]] == 0.0) continue;
+          const int pqk = pq[K[u]];
+          vx[u] = V[I[u] * ldv + (pqk & 0xffff)];
+          vy[u] = V[I[u] * ldv + (pqk >> 16)];
+        }
+#pragma unroll
+        for (int u = 0; u < JB; ++u) {
+          if (I[u] >= n || ps[K[u]] == 0.0) continue;
+          const int pqk = pq[K[u]];
+          const double c = pc[K[u]], s = ps[K[u]];
+          const T x = vx[u], y = vy[u] * pe[K[u]];
+          V[I[u] * ldv + (pqk & 0xffff)] = c * x - s * y;
+          V[I[u] * ldv + (pqk >> 16)] = s * x + c * y;
+        }
       }
       __syncthreads();
     }
