@@ -143,8 +143,8 @@ __global__ void __launch_bounds__(CLIP_THREADS) k_clip(int n, T* g, double* stat
     A[e] = G[(size_t)idx[i] * n + idx[j]];
   }
   __syncthreads();
-  // a smaller load batch than the default keeps 1024 threads within 128 VGPRs
-  const int sweeps = block_jacobi_eigh<T, is_cplx<T>::value ? 2 : 4>(A, m, m, V, m, pc, ps, pe, pq, &cnt, fro);
+  // load batches that keep 1024 threads within 128 VGPRs (no spills)
+  const int sweeps = block_jacobi_eigh<T, is_cplx<T>::value ? 3 : 8>(A, m, m, V, m, pc, ps, pe, pq, &cnt, fro);
   // eigenvalues on the diagonal of A
   double lmin = INFINITY, lmax = -INFINITY, neg = 0, tot = 0;
   for (int i = tid; i < m; i += blockDim.x) {
