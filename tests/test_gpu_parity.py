@@ -261,6 +261,29 @@ def test_metric_fix(real):
         assert abs(st[2] - so['lam_min']) < 1e-12 * abs(so['lam_max'])
 
 
+
+@pytest.mark.parametrize("real", [False, True])
+def test_metric_fix_eigensolver_full_size(real):
+    """The clip's eigen-solve at the largest metric of the workloads (n = 256,
+    D = 8, r = 2) and on an odd block (n = 144 with one zero row and column):
+    each thread of the Jacobi takes several chunks of rotation and
+    eigenvector updates per round, and the pair indices wrap across rows."""
+    rng = np.random.default_rng(31 + int(real))
+    for n, D, zero in ((256, 8, ()), (144, 6, (7,))):
+        M = rng.standard_normal((n, n)) + (0 if real else 1j * rng.standard_normal((n, n)))
+        g = (M + M.conj().T) / 2
+        for z in zero:
+            g[z, :] = 0.0
+            g[:, z] = 0.0
+        go, so = O.metric_fix(g)
+        ctx = _ctx(cplx=not real, max_D=D, max_batch=2)
+        gt = batched([g, 2.0 * g])
+        st = to_np(ntu.ntu_metric_fix(ctx, gt, D, ntu.FIX_HERM_CLIP))
+        out = to_np(gt)
+        assert rel(out[0], go) < 1e-12 and rel(out[1], 2.0 * go) < 1e-12, (n, rel(out[0], go))
+        assert np.all(st[:, 5] == 1.0)
+        assert abs(st[0, 2] - so['lam_min']) < 1e-12 * abs(so['lam_max'])
+
 # ------------------------------------------------------------------ fit
 
 @pytest.mark.parametrize("D,p,real,n_iter", [(2, 2, False, 20), (3, 2, False, 6), (5, 2, False, 3), (3, 4, True, 6)])
