@@ -80,6 +80,33 @@ template <> NTU_DEV cd load_site<cd>(const float2* p, long long i) {
   return cd{(double)v.x, (double)v.y};
 }
 
+// W = (gate factor) x (site tensor), row-major nrow x R, for the Gram-Schmidt
+// reductions: row (s', a, t, i3, i4) with s' the gate's output index, column
+// (q, k) with q the bond index and k the gate's rank index; X side: (l, b) =
+// (i3, i4), bond r = q; Y side: (b, r) = (i3, i4), bond l = q.  A thread takes
+// whole rows and decodes a row's indices once in 32-bit arithmetic (AMDGPU
+// divides in software, 64-bit divisions far more slowly); each entry sums over
+// s in the same order as a per-entry loop would.
+template <class T, class S>
+NTU_DEV void form_w(const S* __restrict__ X, const T* __restrict__ G, int d, int na, int D, int rg, int side,
+                    int nrow, T* __restrict__ Qi) {
+  const int R = D * rg, D2 = D * D, D3 = D2 * D;
+  const long long D4 = (long long)D3 * D;
+  for (int row = threadIdx.x; row < nrow; row += blockDim.x) {
+    const int i4 = row % D, i3 = (row / D) % D, t = (row / D2) % D;
+    const int pa = row / D3, sp = pa / na, a = pa % na;
+    for (int q = 0; q < D; ++q) {
+      const long long inner = side == 0 ? (long long)(i3 * D2 + i4 * D + q) : (long long)(q * D2 + i3 * D + i4);
+      for (int k = 0; k < rg; ++k) {
+        T v = zerov<T>();
+        for (int s = 0; s < d; ++s)
+          v += G[(sp * d + s) * rg + k] * load_site<T>(X, (long long)(s * na + a) * D4 + (long long)t * D3 + inner);
+        Qi[(size_t)row * R + q * rg + k] = v;
+      }
+    }
+  }
+}
+
 constexpr int QR_THREADS = 256;
 constexpr int QR_RMAX = 32;
 
@@ -114,20 +141,7 @@ __global__ void __launch_bounds__(QR_THREADS) k_reduce_qr(int d, int na, int D, 
   T* Ri = Rm + (size_t)it * R * R;
 
   // 1. W into Q (row-major nrow x R)
-  for (long long e = tid; e < nrow * R; e += blockDim.x) {
-    long long row = e / R;
-    int col = (int)(e % R), q = col / rg, k = col % rg;
-    int i4 = (int)(row % D), i3 = (int)((row / D) % D), t = (int)((row / D2) % D);
-    int pa = (int)(row / D3), sp = pa / na, a = pa % na;
-    T v = zerov<T>();
-    for (int s = 0; s < d; ++s) {
-      long long base = (long long)(s * na + a) * D4 + t * D3;
-      // X side: rows (s',a,t,l=i3,b=i4), bond = r = q ; Y side: rows (s',a,t,b=i3,r=i4), bond = l = q
-      long long off = side == 0 ? base + i3 * D2 + i4 * D + q : base + q * D2 + i3 * D + i4;
-      v += G[(sp * d + s) * rg + k] * load_site<T>(X, off);
-    }
-    Qi[e] = v;
-  }
+  form_w<T, S>(X, G, d, na, D, rg, side, (int)nrow, Qi);
   for (int e = tid; e < R * R; e += blockDim.x) Ri[e] = zerov<T>();
   __syncthreads();
 
@@ -246,20 +260,7 @@ __global__ void __launch_bounds__(NT) k_reduce_qr_reg(int d, int na, int D, int 
   for (int e = tid; e < R * R; e += blockDim.x) Ri[e] = zerov<T>();
 
   // 1. W into Q (row-major nrow x R), then this thread's rows into registers
-  for (long long e = tid; e < nrow * R; e += blockDim.x) {
-    const long long row = e / R;
-    const int col = (int)(e % R), q = col / rg, kk = col % rg;
-    const int i4 = (int)(row % D), i3 = (int)((row / D) % D), t = (int)((row / D2) % D);
-    const int pa = (int)(row / D3), sp = pa / na, a = pa % na;
-    T v = zerov<T>();
-    for (int s2 = 0; s2 < d; ++s2) {
-      const long long base = (long long)(s2 * na + a) * D4 + t * D3;
-      // X side: rows (s',a,t,l=i3,b=i4), bond = r = q ; Y side: rows (s',a,t,b=i3,r=i4), bond = l = q
-      const long long off = side == 0 ? base + i3 * D2 + i4 * D + q : base + q * D2 + i3 * D + i4;
-      v += G[(sp * d + s2) * rg + kk] * load_site<T>(X, off);
-    }
-    Qi[e] = v;
-  }
+  form_w<T, S>(X, G, d, na, D, rg, side, (int)nrow, Qi);
   __syncthreads();
   T w[RPT][RM];
 #pragma unroll
