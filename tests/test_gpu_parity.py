@@ -168,17 +168,22 @@ def test_env_contract_f64(D, p, real):
 
 
 @pytest.mark.parametrize("prec,tol", [("bf16x3", 3e-5), ("bf16x6", 1e-6)])
-@pytest.mark.parametrize("D,p,real", [(3, 2, False), (5, 2, False), (5, 4, False), (4, 4, True)])
+@pytest.mark.parametrize("D,p,real", [(3, 2, False), (5, 2, False), (5, 4, False), (4, 4, True),
+                                      (6, 2, False), (7, 2, False), (8, 2, False), (9, 2, False),
+                                      (10, 2, False), (8, 4, True)])
 def test_env_contract_mixed(prec, tol, D, p, real):
-    """Split-precision metric: relative Frobenius error within the mode's budget.
-    Complex D <= 8 takes the fused kernels (D = 5, p = 4: contraction index
-    p D = 20 spans two MFMA K steps of the Left/Right blocks)."""
+    """Split-precision metric, element by element against the oracle:
+    relative Frobenius error within the mode's budget.  Complex D <= 8 takes
+    the fused kernels (D = 5, p = 4: contraction index p D = 20 spans two
+    MFMA K steps of the Left/Right blocks; D = 6, 7: D^2 = 36, 49 padded to
+    the next multiple of 16; D = 8: no padding); complex D = 9, 10 and every
+    real case take the tiled products for Left, Right, L1 and L2."""
     X, Y, nbr, G, GA, GB = _case(300 + D, D, p, real)
     QX, _ = O.reduce_site(X, GA, 'X', 2)
     QY, _ = O.reduce_site(Y, GB, 'Y', 2)
     go = O.metric(QX, QY, nbr)
     R = D * 2
-    ctx = _ctx(cplx=not real, d_anc=p // 2)
+    ctx = _ctx(cplx=not real, d_anc=p // 2, max_D=max(D, 6), max_batch=1)
     q = lambda Q: batched([Q.reshape(-1, R)])
     g = to_np(ntu.ntu_env_contract(ctx, q(QX), q(QY), [batched([t]) for t in nbr], prec))[0]
     err = rel(g, go)
