@@ -1,21 +1,25 @@
 """Throughput of the NTU hot path on one MI355X.
 
-Default workload ("batched", configuration 4): 256 independent NTU updates
-of a horizontal bond of the 2D transverse-field Ising model, D drawn
-uniformly from {3..8}, field h_x uniform in [2.5, 3.5], real-time gate
-exp(-0.01 i h_b), random complex Gaussian site tensors (drawn as complex64).
-Items are grouped by D; one step = all 256 updates, each: gate split once at
-set-up, then reduce + QR, environment contraction (split precision on MFMA),
-metric repair (FP64), bond fit (FP64, <= 20 ALS iterations, early stop at
-1e-12 N), recombination.  Each D bucket runs on its own stream (one context
-each); the buckets are independent, so the timed region forks them once,
-runs the K steps of every bucket back to back and joins them at the end.
+Headline ("batched" workload, default --bucket 8): the 48 items of bond
+dimension D = 8 of configuration 4 -- independent NTU updates of a
+horizontal bond of the 2D transverse-field Ising model, field h_x uniform in
+[2.5, 3.5], real-time gate exp(-0.01 i h_b), random complex Gaussian site
+tensors drawn as complex64 -- in one batched Trotter-step call per step.
+Each update: reduce + QR, environment contraction (split precision on the
+matrix cores), metric repair (FP64), bond fit (FP64, <= 20 ALS iterations,
+early stop at 1e-12 N), recombination.  The plain FP64 GPU path runs the same
+steps from the same state beside it.  ``value`` = bond updates per second of
+the split-precision path.
+
+Extra (``mixed_workload``): all 256 items of configuration 4, D uniform in
+{3..8}, grouped by D into six buckets, each on its own stream; the buckets
+are independent, so the timed region forks them once, runs the K steps of
+every bucket back to back and joins them.  --bucket 0 makes this the headline.
 
 "thermal" (configuration 3): imaginary-time evolution of the D = 8 thermal
 purification (p = 4, real), one step = one Trotter sweep of 4 bond updates.
 
-Prints ONE JSON line.  ``value`` = bond updates per second of the mixed path;
-the plain FP64 GPU path runs the same steps from the same state beside it.
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -35,6 +39,13 @@ PEAK_BF16 = 2.5e15       # dense MFMA, FLOP/s
 PEAK_FP64 = 78.6e12      # FLOP/s (vector and matrix)
 PEAK_HBM = 8.0e12        # B/s
 
+# The mixed workload runs one stream per bond-dimension bucket (six), each
+# with the library's side stream, next to the main stream; HIP maps streams
+# onto GPU_MAX_HW_QUEUES hardware queues round-robin (default 4), and streams
+# that share a queue serialise.  Ask for enough queues before the runtime
+# starts.
+HW_QUEUES = 16
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -45,16 +56,17 @@ def parse():
     ap.add_argument("--precision", default="bf16x6", choices=["bf16x3", "bf16x6", "fp16x3", "f64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--scheme", default="ntu", choices=["ntu", "svdu"],
-                    help="bond-update scheme: full NTU, or the SVDU update (no environment; implies --no-fp64 --no-d8)")
+                    help="bond-update scheme: full NTU, or the SVDU update (no environment; implies --no-fp64)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in K split of the metric assembly instead of autotuning it per bucket")
-    ap.add_argument("--no-d8", action="store_true",
-                    help="skip the second measurement of the D=8 items alone (profiles of the whole-workload step)")
+    ap.add_argument("--bucket", type=int, default=8,
+                    help="batched workload: headline on the items of this bond dimension (0 = all 256 items)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the extra measurement of all 256 items (mixed D)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--profile-steps", type=int, default=1)
-    ap.add_argument("--bucket", type=int, default=0,
-                    help="batched workload: only the items of this bond dimension (0 = all 256)")
+    ap.add_argument("--no-roofline", action="store_true",
+                    help="skip the K steps timed with per-kernel-class events")
     ap.add_argument("--hw-queues", type=int, default=HW_QUEUES,
                     help="GPU_MAX_HW_QUEUES for this process (hardware queues the streams are spread over)")
     ap.add_argument("--aux", default="own", choices=["own", "shared"],
@@ -114,11 +126,6 @@ def env_work(R, D, p, cplx, fused):
     return w
 
 
-def env_assembly_flops(R, D, cplx):
-    """g = L2 Right^T: (R^2 x D^4) times (D^4 x R^2)."""
-    return (8 if cplx else 2) * (R * R) * (R * R) * D ** 4
-
-
 def traffic_record(kernel):
     """HBM bytes per launch of `kernel` from the committed counter runs, or
     None when its source (the kernel's file and the shared headers) has
@@ -138,23 +145,38 @@ def traffic_record(kernel):
     return rec
 
 
+def host_cpu():
+    """CPU model, logical CPUs visible to this process."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count()
+    return model, n
+
+
 class Job:
-    """One workload: a list of (D, batch tensors) buckets and a step function."""
+    """One workload: a list of buckets (one context, stream and batch of items
+    each, all of one bond dimension) and the sweep order of a step."""
 
 
-def build_batched(ntu, inputs, dev, torch, np, only_D=None):
-    items = inputs.workload_batched()
-    if only_D:
-        items = [it for it in items if it["D"] == only_D]
+def bucket_job(ntu, torch, np, dev, items, label):
     buckets = {}
     for it in items:
         buckets.setdefault(it["D"], []).append(it)
     job = Job()
-    job.cplx, job.p, job.n_updates, job.items = True, 2, len(items), items
+    job.cplx, job.p, job.n_updates, job.items, job.label = True, 2, len(items), items, label
     job.buckets = []
     for D in sorted(buckets):
         its = buckets[D]
-        # one context (workspace) and one stream per bond dimension: the buckets run concurrently
         ctx = ntu.Context(complex_=True, d=2, d_anc=1, r_g=2, max_D=D, max_batch=len(its))
         ctx.bind_stream()
         # complex64 values upcast once at set-up; the hot path runs in complex128
@@ -172,7 +194,7 @@ def build_batched(ntu, inputs, dev, torch, np, only_D=None):
     return job
 
 
-def build_thermal(ntu, inputs, dev, torch, np, D=8):
+def thermal_job(ntu, torch, np, dev, inputs, D=8):
     w = inputs.workload_thermal(D=D)
     ctx = ntu.Context(complex_=False, d=2, d_anc=2, r_g=2, max_D=D, max_batch=1)
     ctx.bind_stream()
@@ -182,26 +204,222 @@ def build_thermal(ntu, inputs, dev, torch, np, D=8):
     A = torch.from_numpy(w["A"][None]).to(dev).contiguous()
     B = torch.from_numpy(w["B"][None]).to(dev).contiguous()
     job = Job()
-    job.cplx, job.p, job.n_updates, job.w = False, 4, 4, w
-    job.buckets = [dict(D=D, A=A, B=B, gf=gf, n=1, ctx=ctx, stream=torch.cuda.current_stream(dev))]
+    job.cplx, job.p, job.n_updates, job.w, job.label = False, 4, 4, w, "thermal"
+    job.buckets = [dict(D=D, A=A, B=B, gf=gf, n=1, ctx=ctx, stream=torch.cuda.Stream(device=dev))]
     job.order = (0, 1, 2, 3)
     job.bonds_per_item = 4
     return job
 
 
-# The batched workload runs one stream per bond-dimension bucket (six), each
-# with the library's side stream, next to the main stream; HIP maps streams
-# onto GPU_MAX_HW_QUEUES hardware queues round-robin (default 4), and streams
-# that share a queue serialise.  Ask for enough queues before the runtime
-# starts.
-HW_QUEUES = 16
+class Runner:
+    """Warm-up, tuning, timing and per-kernel-class events of one job."""
+
+    def __init__(self, job, args, ntu, torch, dev):
+        self.job, self.args, self.ntu, self.torch, self.dev = job, args, ntu, torch, dev
+        self.main = torch.cuda.Stream(device=dev)
+        self.init = None
+
+    def steps(self, state, o, keep_stats, nsteps):
+        """nsteps steps of every bucket.  The buckets are independent: each
+        stream waits for the main stream once, runs its nsteps steps back to
+        back, and the main stream waits for all of them at the end (main is
+        an ordinary stream: work on the legacy null stream would wait for
+        every blocking stream of the device)."""
+        torch, ntu = self.torch, self.ntu
+        main = torch.cuda.current_stream(self.dev)
+        assert main.cuda_stream != 0, "run the steps from a non-default stream"
+        for bk in self.job.buckets:
+            bk["stream"].wait_stream(main)
+        out = []
+        for _ in range(nsteps):
+            st = []
+            for bk, (A, B) in zip(self.job.buckets, state):
+                with torch.cuda.stream(bk["stream"]):
+                    st.append(ntu.ntu_trotter_step(bk["ctx"], A, B, bk["gf"], o, stats=keep_stats))
+            out.append(st)
+        for bk in self.job.buckets:
+            main.wait_stream(bk["stream"])
+        return out
+
+    def warm(self, opts64, W):
+        """W FP64 steps from the seeded state: both paths start from there."""
+        torch = self.torch
+        state0 = [(bk["A"].clone(), bk["B"].clone()) for bk in self.job.buckets]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(self.main):
+            self.steps(state0, opts64, False, W)
+        torch.cuda.synchronize()
+        self.init = state0
+
+    def tune(self, precision):
+        """The K split of the split-precision metric assembly, per bucket, on
+        that bucket's own isometries and neighbours after the warm-up (H1
+        cluster: neighbours B, B, B, A, A, A)."""
+        torch, ntu = self.torch, self.ntu
+        tuning = {}
+        with torch.cuda.stream(self.main):
+            for bk, (A, B) in zip(self.job.buckets, self.init):
+                ctx = bk["ctx"]
+                QX, _ = ntu.ntu_reduce_qr(ctx, A, bk["gf"][:, 0, 0].contiguous(), 0)
+                QY, _ = ntu.ntu_reduce_qr(ctx, B, bk["gf"][:, 0, 1].contiguous(), 1)
+                ks, tms = ntu.ntu_tune_env(ctx, QX, QY, [B, B, B, A, A, A], precision, D=bk["D"])
+                tuning[str(bk["D"])] = {"e6_ksplit": ks, "env_ms": round(tms, 4)}
+        torch.cuda.synchronize()
+        return tuning
+
+    def run(self, o, nsteps, keep_stats=False, profile=False):
+        """nsteps steps from the start state between two events on the main
+        stream; with profile, the contexts record an event pair around every
+        kernel class on their streams."""
+        torch, ntu = self.torch, self.ntu
+        state = [(A.clone(), B.clone()) for A, B in self.init]
+        if profile:
+            for bk in self.job.buckets:
+                ntu.ntu_profile_enable(bk["ctx"], True)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(self.main):
+            ev0.record()
+            stats = self.steps(state, o, keep_stats, nsteps)
+            ev1.record()
+        torch.cuda.synchronize()
+        prof = {}
+        if profile:
+            for bk in self.job.buckets:
+                for k, (ms_k, n_k) in ntu.ntu_profile_read(bk["ctx"]).items():
+                    a0, b0 = prof.get(k, (0.0, 0))
+                    prof[k] = (a0 + ms_k, b0 + n_k)
+                ntu.ntu_profile_enable(bk["ctx"], False)
+        return ev0.elapsed_time(ev1), state, stats, prof
+
+
+KERNEL_OF = {"bond_fit": "k_bond_fit", "env_left_right": "k_right", "env_e4": "k_left_e45",
+             "reduce_qr": "k_reduce_cholqr", "recombine": "k_recombine",
+             "env_e5": "k_mfma_tile (L2)", "env_e6": "k_mfma_tile (g = L2 Right^T)"}
+
+
+def rooflines(job, args, stats, nsteps, prof, workload):
+    """Per kernel class: algorithmic (and issued MFMA) rate over the average
+    launch time of the profiled steps; stats: those steps' stats."""
+    import numpy as np
+    issue = 1 if args.precision == "f64" else (3 if args.precision in ("bf16x3", "fp16x3") else 6)
+    peak_mx = PEAK_FP64 if args.precision == "f64" else PEAK_BF16
+    fit_fl, env = 0.0, {}
+    for bi, bk in enumerate(job.buckets):
+        st = np.stack([x[bi].cpu().numpy() for x in stats])
+        R = 2 * bk["D"]
+        for row in st.reshape(-1, st.shape[-1]):
+            fit_fl += fit_flops(R, row[8 + 4], 2 * row[8 + 6], row[8 + 15], job.cplx)
+        fused = job.cplx and bk["D"] ** 2 <= 64 and args.precision != "f64"
+        for k, (fl, by) in env_work(R, bk["D"], job.p, job.cplx, fused).items():
+            a0, b0 = env.get(k, (0.0, 0.0))
+            env[k] = (a0 + fl * bk["n"] * job.bonds_per_item, b0 + by * bk["n"] * job.bonds_per_item)
+    fit_fl /= nsteps                                   # per step
+    # HBM classes, algorithmic bytes per step: the reduction reads both site
+    # tensors and writes Q and R of both sides; the recombination reads Q and
+    # M of both sides and writes both site tensors
+    hbm = {"reduce_qr": 0.0, "recombine": 0.0}
+    for bk in job.buckets:
+        D, R, el = bk["D"], 2 * bk["D"], 16 if job.cplx else 8
+        site, q = job.p * D ** 4, job.p * D ** 3 * R
+        nb = bk["n"] * job.bonds_per_item
+        hbm["reduce_qr"] += nb * el * 2 * (site + q + R * R)
+        hbm["recombine"] += nb * el * 2 * (q + R * D + site)
+    rl = {}
+    for cls, (t_ms, n_l) in prof.items():
+        t = t_ms / nsteps / 1e3                        # s per step
+        n_l = n_l / nsteps
+        if cls in hbm:
+            rl[cls] = {"kernel": KERNEL_OF[cls], "bound": "hbm", "achieved": hbm[cls] / t / 1e9,
+                       "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": hbm[cls] / t / PEAK_HBM,
+                       "algorithmic_bytes_per_step": hbm[cls]}
+        elif cls == "bond_fit" and args.scheme == "svdu":
+            continue
+        elif cls == "bond_fit":
+            rl[cls] = {"kernel": KERNEL_OF[cls], "bound": "alu", "achieved": fit_fl / t / 1e12,
+                       "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": fit_fl / t / PEAK_FP64,
+                       "flops_per_step": fit_fl}
+        elif cls in env:
+            fl, by = env[cls]
+            rl[cls] = {"kernel": KERNEL_OF[cls], "bound": "mfma", "achieved": fl / t / 1e12,
+                       "peak": peak_mx / 1e12, "unit": "TFLOP/s", "frac": fl / t / peak_mx,
+                       "flops_per_step": fl, "issued_mfma_frac": issue * fl / t / peak_mx,
+                       "algorithmic_bytes_per_step": by, "algorithmic_GBps": by / t / 1e9}
+        else:
+            continue
+        rl[cls].update({"avg_launch_us": t / n_l * 1e6, "launches_per_step": n_l, "traffic": None})
+        rec = traffic_record(rl[cls]["kernel"].split(" ")[0])
+        if rec and rec.get("workload") == workload and rec.get("precision") == args.precision:
+            rl[cls]["traffic"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+            rl[cls]["traffic_source"] = "profiles/traffic.json"
+    dom = max((c for c in prof if c in rl), key=lambda c: prof[c][0], default=None)
+    return rl, dom
+
+
+def fit_summary(job, stats):
+    import numpy as np
+    its, eig, dmax, phases = {}, 0, 0.0, {}
+    for bi, bk in enumerate(job.buckets):
+        st = np.stack([s[bi].cpu().numpy() for s in stats])  # steps x items x bonds x len
+        its[str(bk["D"])] = float(st[..., 8 + 6].mean())
+        eig += int(st[..., 8 + 7].sum())
+        dmax = max(dmax, float(st[..., 8 + 3].max()))
+        ph = st[..., 8 + 10:8 + 15].reshape(-1, 5).mean(axis=0)
+        phases[str(bk["D"])] = {"certificate_kind_mean": float(st[..., 8 + 9].mean()),
+                                "cg_iters": float(st[..., 8 + 15].mean()),
+                                "kcycles": dict(zip(["setup", "form", "solve", "error", "balance"],
+                                                    [round(x / 1e3, 1) for x in ph]))}
+    return {"fit_iterations_mean": its, "fit_eig_fallbacks": eig, "delta_max": dmax, "fit_phases": phases}
+
+
+def measure(job, args, ntu, torch, dev, opts, opts64, K, W, tune=True):
+    """Both paths of one job from the same start state: value, FP64 path,
+    per-kernel-class rooflines (a second timed pass of K steps with events
+    around every kernel class)."""
+    r = Runner(job, args, ntu, torch, dev)
+    r.warm(opts64, W)
+    out = {}
+    if tune and args.precision in ("bf16x3", "bf16x6") and not args.no_tune and args.scheme == "ntu":
+        out["tuning"] = r.tune(args.precision)
+    # one untimed step of the measured path, so that no kernel of it is
+    # launched for the first time inside the timed region
+    r.run(opts, 1)
+    ms, state, stats, _ = r.run(opts, K, keep_stats=True)
+    upd = job.n_updates
+    out.update({"value": upd * K / (ms / 1e3), "ms_per_step": ms / K, "state": state, "stats": stats})
+    if not args.no_fp64:
+        r.run(opts64, 1)
+        ms64, _, _, _ = r.run(opts64, K)
+        out["fp64_path"] = {"value": upd * K / (ms64 / 1e3), "ms_per_step": ms64 / K}
+        out["speedup_vs_fp64_path"] = out["value"] / out["fp64_path"]["value"]
+    if not args.no_roofline:
+        msp, _, stp, prof = r.run(opts, K, keep_stats=True, profile=True)
+        out["prof"], out["prof_stats"], out["ms_per_step_with_kernel_events"] = prof, stp, msp / K
+    out["runner"] = r
+    return out
+
+
+def metric_sample(job, ntu, torch, precision, n_items=2):
+    """Metric of the first items of the first bucket, from the seeded state
+    (H1 cluster), on both GPU paths: for comparison with the oracle."""
+    bk = job.buckets[0]
+    ctx = bk["ctx"]
+    ctx.bind_stream()
+    A, B = bk["A"][:n_items].contiguous(), bk["B"][:n_items].contiguous()
+    QX, _ = ntu.ntu_reduce_qr(ctx, A, bk["gf"][:n_items, 0, 0].contiguous(), 0)
+    QY, _ = ntu.ntu_reduce_qr(ctx, B, bk["gf"][:n_items, 0, 1].contiguous(), 1)
+    nb = [B, B, B, A, A, A]
+    g64 = ntu.ntu_env_contract(ctx, QX, QY, nb, "f64", D=bk["D"])
+    gmx = ntu.ntu_env_contract(ctx, QX, QY, nb, precision, D=bk["D"])
+    torch.cuda.synchronize()
+    return g64.cpu().numpy(), gmx.cpu().numpy()
 
 
 def main():
     args = parse()
     os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the bond updates of a step are "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the bond updates of a step are "
               "independent, and the multi-GPU layout is described but not run", file=sys.stderr)
         sys.exit(2)
     if args.copy_mib:
@@ -214,260 +432,115 @@ def main():
 
     dev = torch.device("cuda", 0)
     K, W = args.steps, args.warmup
+    if args.scheme == "svdu":
+        args.no_fp64 = True
+    all_items = None
     if args.workload == "batched":
-        job = build_batched(ntu, inputs, dev, torch, np, only_D=args.bucket)
+        all_items = inputs.workload_batched()
+        if args.bucket:
+            items = [it for it in all_items if it["D"] == args.bucket]
+            label = (f"configuration 4, its {len(items)} D={args.bucket} items: independent H1 bond updates, "
+                     f"one batched call per step")
+        else:
+            items, label = all_items, "configuration 4: 256 independent bond updates, D uniform in {3..8}"
+        job = bucket_job(ntu, torch, np, dev, items, label)
     else:
-        job = build_thermal(ntu, inputs, dev, torch, np)
+        job = thermal_job(ntu, torch, np, dev, inputs)
     if args.aux == "shared":
         job.aux = torch.cuda.Stream(device=dev)
         for bk in job.buckets:
             bk["ctx"].set_aux_stream(job.aux)
     fit = dict(n_iter=20, early_stop=True, conv_tol=1e-12)
-    if args.scheme == "svdu":
-        args.no_fp64 = args.no_d8 = True
     opts = ntu.step_opts(args.precision, order=job.order, scheme=args.scheme, **fit)
     opts64 = ntu.step_opts("f64", order=job.order, **fit)
 
-    def steps_on_buckets(state, o, keep_stats, nsteps):
-        """nsteps steps of every bucket.  The buckets are independent: each
-        stream waits for the main stream once, runs its nsteps steps back to
-        back, and the main stream waits for all of them at the end (main is
-        an ordinary stream: work on the legacy null stream would wait for
-        every blocking stream of the device)."""
-        main = torch.cuda.current_stream(dev)
-        assert main.cuda_stream != 0, "run the steps from a non-default stream"
-        for bk in job.buckets:
-            bk["stream"].wait_stream(main)
-        out = []
-        for _ in range(nsteps):
-            st = []
-            for bk, (A, B) in zip(job.buckets, state):
-                with torch.cuda.stream(bk["stream"]):
-                    st.append(ntu.ntu_trotter_step(bk["ctx"], A, B, bk["gf"], o, stats=keep_stats))
-            out.append(st)
-        for bk in job.buckets:
-            main.wait_stream(bk["stream"])
-        return out
-
-    main_stream = torch.cuda.Stream(device=dev)
-    # warm-up on the FP64 path so that both paths start from the same state
-    state0 = [(bk["A"], bk["B"]) for bk in job.buckets]
-    torch.cuda.synchronize()
-    with torch.cuda.stream(main_stream):
-        steps_on_buckets(state0, opts64, False, W)
-    torch.cuda.synchronize()
-    init = [(A.clone(), B.clone()) for A, B in state0]
-
-    # autotuning (before any timing): the K split of the split-precision
-    # metric assembly, per bucket, on that bucket's own isometries and
-    # neighbours after the warm-up (H1 cluster: neighbours B, B, B, A, A, A)
-    tuning = {}
-    if args.precision in ("bf16x3", "bf16x6") and not args.no_tune and args.scheme == "ntu":
-        with torch.cuda.stream(main_stream):
-            for bk, (A, B) in zip(job.buckets, init):
-                ctx = bk["ctx"]
-                QX, _ = ntu.ntu_reduce_qr(ctx, A, bk["gf"][:, 0, 0].contiguous(), 0)
-                QY, _ = ntu.ntu_reduce_qr(ctx, B, bk["gf"][:, 0, 1].contiguous(), 1)
-                ks, tms = ntu.ntu_tune_env(ctx, QX, QY, [B, B, B, A, A, A], args.precision, D=bk["D"])
-                tuning[str(bk["D"])] = {"e6_ksplit": ks, "env_ms": round(tms, 4)}
-        torch.cuda.synchronize()
-
-    def run(o, steps, keep_stats=False):
-        state = [(A.clone(), B.clone()) for A, B in init]
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(main_stream):
-            ev0.record()
-            stats = steps_on_buckets(state, o, keep_stats, steps)
-            ev1.record()
-        torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1), state, stats
-
-    # one untimed step of the measured path on a copy of the start state, so
-    # that no kernel of it is launched for the first time inside the timed
-    # region (the warm-up steps above ran the FP64 path)
-    run(opts, 1)
-    ms, state_m, stm = run(opts, K, keep_stats=True)
-    upd = job.n_updates
+    m = measure(job, args, ntu, torch, dev, opts, opts64, K, W)
     result = {
         "metric": METRIC if args.scheme == "ntu" else METRIC_SVDU,
-        "value": upd * K / (ms / 1e3),
+        "value": m["value"],
         "unit": "bond_updates/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": ms / K,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": f"{args.precision}+f64",
         "data": "synthetic",
     }
-    if tuning:
-        result["tuning"] = tuning
     if args.workload == "batched":
-        result["config"] = {"workload": "configuration 4: 256 independent bond updates, D uniform in {3..8}"
-                            + (f", only the D={args.bucket} items" if args.bucket else ""),
-                            "items": upd, "D_counts": {str(bk["D"]): bk["n"] for bk in job.buckets},
+        result["config"] = {"workload": job.label, "items": job.n_updates,
+                            "D_counts": {str(bk["D"]): bk["n"] for bk in job.buckets},
                             "h_x": "uniform [2.5, 3.5]", "dt": 0.01, "env_precision": args.precision,
                             "fit": ("fp64, <=20 ALS iterations, early stop 1e-12 N" if args.scheme == "ntu"
                                     else "none (SVDU scheme)"),
                             "scheme": args.scheme,
                             "storage": "values drawn as complex64, hot path in complex128",
-                            "streams": (f"one per D bucket, side streams {'one shared' if args.aux == 'shared' else 'one per bucket'}, "
-                                        f"{args.hw_queues} hardware queues")}
+                            "start": f"seeded state + {W} FP64 warm-up steps"}
+        if len(job.buckets) > 1:
+            result["config"]["streams"] = (f"one per D bucket, side streams "
+                                           f"{'one shared' if args.aux == 'shared' else 'one per bucket'}, "
+                                           f"{args.hw_queues} hardware queues")
     else:
         result["config"] = {"workload": "configuration 3: thermal purification, D=8, p=4, real", "D": 8,
                             "h_x": 2.5, "dbeta": 0.005, "env_precision": args.precision,
                             "fit": "fp64, <=20 ALS iterations, early stop 1e-12 N", "bond_updates_per_step": 4,
                             "start": f"beta=0 purification + {W} FP64 warm-up steps"}
-    # fit statistics per bucket
-    its, eig, dmax = {}, 0, 0.0
-    for bi, bk in enumerate(job.buckets):
-        st = torch.stack([s[bi] for s in stm]).cpu().numpy()  # steps x items x bonds x len
-        its[str(bk["D"])] = float(st[..., 8 + 6].mean())
-        eig += int(st[..., 8 + 7].sum())
-        dmax = max(dmax, float(st[..., 8 + 3].max()))
-    result["fit_iterations_mean"] = its
-    result["fit_eig_fallbacks"] = eig
-    result["delta_max"] = dmax
-    phases = {}
-    for bi, bk in enumerate(job.buckets):
-        st = torch.stack([s[bi] for s in stm]).cpu().numpy()
-        ph = st[..., 8 + 10:8 + 15].reshape(-1, 5).mean(axis=0)
-        phases[str(bk["D"])] = {"certificate_kind_mean": float(st[..., 8 + 9].mean()), "cg_iters": float(st[..., 8 + 15].mean()),
-                                "kcycles": dict(zip(["setup", "form", "solve", "error", "balance"],
-                                                    [round(x / 1e3, 1) for x in ph]))}
-    result["fit_phases"] = phases
+    if "tuning" in m:
+        result["tuning"] = m["tuning"]
+    if "fp64_path" in m:
+        result["fp64_path"] = m["fp64_path"]
+        result["speedup_vs_fp64_path"] = m["speedup_vs_fp64_path"]
+    result.update(fit_summary(job, m["stats"]))
+    if "prof" in m:
+        prof = m["prof"]
+        result["ms_per_step_with_kernel_events"] = m["ms_per_step_with_kernel_events"]
+        result["kernel_ms_per_step"] = {k: round(v[0] / K, 4) for k, v in
+                                        sorted(prof.items(), key=lambda kv: -kv[1][0])}
+        rl, dom = rooflines(job, args, m["prof_stats"], K, prof, job.label)
+        result["roofline"] = dict(rl.get(dom, {}), dominant_class=dom)
+        result["roofline_by_class"] = rl
 
-    if not args.no_fp64:
-        ms64, state64, _ = run(opts64, K)
-        result["fp64_path"] = {"value": upd * K / (ms64 / 1e3), "ms_per_step": ms64 / K}
-        result["speedup_vs_fp64_path"] = result["value"] / result["fp64_path"]["value"]
-        # metric error of the split path: largest bucket, same isometries, both precisions
-        bk = job.buckets[-1]
-        ctx = bk["ctx"]
-        ctx.bind_stream()
-        A, B = state_m[-1]
-        Q, _ = ntu.ntu_reduce_qr(ctx, A, bk["gf"][:, 0, 0].contiguous(), 0)
-        QY, _ = ntu.ntu_reduce_qr(ctx, B, bk["gf"][:, 0, 1].contiguous(), 1)
-        nb = [B, B, B, A, A, A]
-        g64 = ntu.ntu_env_contract(ctx, Q, QY, nb, "f64", D=bk["D"])
-        gmx = ntu.ntu_env_contract(ctx, Q, QY, nb, args.precision, D=bk["D"])
-        errs = [float(torch.linalg.norm(gmx[i] - g64[i]) / torch.linalg.norm(g64[i])) for i in range(gmx.shape[0])]
-        result["metric_rel_err_vs_fp64_path"] = {"D": bk["D"], "max": max(errs), "mean": sum(errs) / len(errs)}
+    # metric of the first items from the seeded state, both GPU paths (the
+    # oracle's comparison is made in the CPU leg below)
+    gs = None
+    if args.workload == "batched" and args.scheme == "ntu" and args.precision != "f64":
+        gs = metric_sample(job, ntu, torch, args.precision)
+        g64, gmx = gs
+        errs = [float(np.linalg.norm(gmx[i] - g64[i]) / np.linalg.norm(g64[i])) for i in range(len(g64))]
+        result["metric_rel_err_vs_fp64_path"] = {"D": job.buckets[0]["D"], "items": len(errs), "max": max(errs)}
 
-    # live per-kernel timing with HIP events on each context's stream (summed over buckets)
-    nprof = max(1, args.profile_steps)
-    issue = 1 if args.precision == "f64" else (3 if args.precision in ("bf16x3", "fp16x3") else 6)
-    peak_mx = PEAK_FP64 if args.precision == "f64" else PEAK_BF16
-    kernel_of = {"bond_fit": "k_bond_fit", "env_left_right": "k_right", "env_e4": "k_left_e45",
-                 "reduce_qr": "k_reduce_cholqr", "recombine": "k_recombine",
-                 "env_e5": "k_mfma_tile (L2)", "env_e6": "k_mfma_tile (g = L2 Right^T)"}
-
-    def profile_classes(steps):
-        for bk in job.buckets:
-            ntu.ntu_profile_enable(bk["ctx"], True)
-        run(opts, steps)
-        prof = {}
-        for bk in job.buckets:
-            for k, (ms_k, n_k) in ntu.ntu_profile_read(bk["ctx"]).items():
-                a0, b0 = prof.get(k, (0.0, 0))
-                prof[k] = (a0 + ms_k, b0 + n_k)
-            ntu.ntu_profile_enable(bk["ctx"], False)
-        return prof
-
-    def rooflines(stats, nst, prof, workload):
-        """Per kernel class: algorithmic (and issued MFMA) rate over the average
-        launch time; stats: the timed steps' stats of job.buckets."""
-        fit_fl, env = 0.0, {}
-        for bi, bk in enumerate(job.buckets):
-            st = torch.stack([x[bi] for x in stats]).cpu().numpy()
-            R = 2 * bk["D"]
-            for row in st.reshape(-1, st.shape[-1]):
-                fit_fl += fit_flops(R, row[8 + 4], 2 * row[8 + 6], row[8 + 15], job.cplx)
-            fused = job.cplx and bk["D"] ** 2 <= 64 and args.precision in ("bf16x3", "bf16x6")
-            for k, (fl, by) in env_work(R, bk["D"], job.p, job.cplx, fused).items():
-                a0, b0 = env.get(k, (0.0, 0.0))
-                env[k] = (a0 + fl * bk["n"] * job.bonds_per_item, b0 + by * bk["n"] * job.bonds_per_item)
-        fit_fl /= nst                                      # per step
-        # HBM classes, algorithmic bytes per step: the reduction reads both
-        # site tensors and writes Q and R of both sides; the recombination
-        # reads Q and M of both sides and writes both site tensors
-        hbm = {"reduce_qr": 0.0, "recombine": 0.0}
-        for bk in job.buckets:
-            D, R, el = bk["D"], 2 * bk["D"], 16 if job.cplx else 8
-            site, q = job.p * D ** 4, job.p * D ** 3 * R
-            nb = bk["n"] * job.bonds_per_item
-            hbm["reduce_qr"] += nb * el * 2 * (site + q + R * R)
-            hbm["recombine"] += nb * el * 2 * (q + R * D + site)
-        rl = {}
-        for cls, (t_ms, n_l) in prof.items():
-            t = t_ms / nprof / 1e3                         # s per step
-            n_l = n_l / nprof
-            if cls in hbm:
-                rl[cls] = {"kernel": kernel_of[cls], "bound": "hbm", "achieved": hbm[cls] / t / 1e9,
-                           "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": hbm[cls] / t / PEAK_HBM,
-                           "algorithmic_bytes_per_step": hbm[cls]}
-            elif cls == "bond_fit" and args.scheme == "svdu":
-                continue
-            elif cls == "bond_fit":
-                rl[cls] = {"kernel": kernel_of[cls], "bound": "alu", "achieved": fit_fl / t / 1e12,
-                           "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": fit_fl / t / PEAK_FP64,
-                           "flops_per_step": fit_fl}
-            elif cls in env:
-                fl, by = env[cls]
-                rl[cls] = {"kernel": kernel_of[cls], "bound": "mfma", "achieved": fl / t / 1e12,
-                           "peak": peak_mx / 1e12, "unit": "TFLOP/s", "frac": fl / t / peak_mx,
-                           "flops_per_step": fl, "issued_mfma_frac": issue * fl / t / peak_mx,
-                           "algorithmic_bytes_per_step": by, "algorithmic_GBps": by / t / 1e9}
-            else:
-                continue
-            rl[cls].update({"avg_launch_us": t / n_l * 1e6, "launches_per_step": n_l, "traffic": None})
-            rec = traffic_record(rl[cls]["kernel"].split(" ")[0])
-            if rec and rec.get("workload") == workload and rec.get("precision") == args.precision:
-                rl[cls]["traffic"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
-                rl[cls]["traffic_source"] = "profiles/traffic.json"
-        dom = max((c for c in prof if c in rl), key=lambda c: prof[c][0], default=None)
-        return rl, dom
-
-    prof = profile_classes(args.profile_steps)
-    result["kernel_ms_per_step"] = {k: round(v[0] / nprof, 4) for k, v in
-                                    sorted(prof.items(), key=lambda kv: -kv[1][0])}
-    rl, dom = rooflines(stm, K, prof, result["config"]["workload"])
-    result["roofline"] = dict(rl.get(dom, {}), dominant_class=dom)
-    result["roofline_by_class"] = rl
-
-    # the D=8 items of the same workload alone on the GPU (the bond dimension
-    # the metric names): both paths from the same state, rooflines without
-    # other buckets sharing the chip
-    if (args.workload == "batched" and not args.bucket and not args.no_d8
-            and any(bk["D"] == 8 for bk in job.buckets)):
-        all_b, all_init = job.buckets, init
-        i8 = next(i for i, bk in enumerate(all_b) if bk["D"] == 8)
-        job.buckets, init = [all_b[i8]], [all_init[i8]]
-        try:
-            ms8, _, st8 = run(opts, K, keep_stats=True)
-            ms8_64 = None if args.no_fp64 else run(opts64, K)[0]
-            prof8 = profile_classes(args.profile_steps)
-            rl8, dom8 = rooflines(st8, K, prof8, None)
-        finally:
-            job.buckets, init = all_b, all_init
-        n8 = all_b[i8]["n"]
-        d8 = {"items": n8, "value": n8 * K / (ms8 / 1e3), "unit": "bond_updates/s", "ms_per_step": ms8 / K,
-              "dominant_class": dom8, "roofline_by_class": rl8}
-        if ms8_64 is not None:
-            d8["fp64_path_value"] = n8 * K / (ms8_64 / 1e3)
-            d8["speedup_vs_fp64_path"] = ms8_64 / ms8
-        result["d8_bucket"] = d8
+    # extra: all 256 items of configuration 4 (mixed D)
+    if args.workload == "batched" and args.bucket and not args.no_mixed:
+        jm = bucket_job(ntu, torch, np, dev, all_items,
+                        "configuration 4: 256 independent bond updates, D uniform in {3..8}")
+        if args.aux == "shared":
+            jm.aux = torch.cuda.Stream(device=dev)
+            for bk in jm.buckets:
+                bk["ctx"].set_aux_stream(jm.aux)
+        args_nr = argparse.Namespace(**vars(args))
+        args_nr.no_roofline = True
+        mm = measure(jm, args_nr, ntu, torch, dev, opts, opts64, K, W)
+        mixed = {"workload": jm.label, "items": jm.n_updates, "value": mm["value"], "unit": "bond_updates/s",
+                 "ms_per_step": mm["ms_per_step"], "D_counts": {str(bk["D"]): bk["n"] for bk in jm.buckets},
+                 "streams": (f"one per D bucket, side streams "
+                             f"{'one shared' if args.aux == 'shared' else 'one per bucket'}, "
+                             f"{args.hw_queues} hardware queues")}
+        if "fp64_path" in mm:
+            mixed["fp64_path"] = mm["fp64_path"]
+            mixed["speedup_vs_fp64_path"] = mm["speedup_vs_fp64_path"]
+        if "tuning" in mm:
+            mixed["tuning"] = mm["tuning"]
+        result["mixed_workload"] = mixed
 
     if not args.no_cpu:
         from oracle import ntu as O
         t0 = time.perf_counter()
         n_bonds = 0
+        g_oracle = []
         if args.workload == "batched":
-            # the items in order, cycling through them until the time budget
-            # is spent
+            # the headline items in order, cycling until the time budget is spent
             while time.perf_counter() - t0 < args.cpu_seconds:
                 it = job.items[n_bonds % len(job.items)]
                 GAo, GBo, _ = O.gate_split(it["gate"], 2, 2)
@@ -477,12 +550,16 @@ def main():
                 if args.scheme == "svdu":
                     O.svdu_update(X, Y, GAo, GBo, it["D"])
                 else:
-                    O.bond_update(X, Y, nbr, GAo, GBo, it["D"], n_iter=20, conv_tol=1e-12)
+                    _, _, info = O.bond_update(X, Y, nbr, GAo, GBo, it["D"], n_iter=20, conv_tol=1e-12)
+                    if gs is not None and n_bonds < len(gs[0]):
+                        g_oracle.append(info["g_raw"])
                 n_bonds += 1
-            sample = (f"{n_bonds} bond updates cycling through the 256 items in order (mixed D), "
-                      f"oracle FP64 numpy/BLAS{', SVDU updates' if args.scheme == 'svdu' else ''}")
+            sample = (f"{n_bonds} bond updates cycling in order through the {len(job.items)} items of the headline "
+                      f"workload from their seeded state, oracle FP64 numpy/BLAS"
+                      f"{', SVDU updates' if args.scheme == 'svdu' else ''}")
         else:
-            An, Bn = init[0][0].cpu().numpy()[0], init[0][1].cpu().numpy()[0]
+            r = m["runner"]
+            An, Bn = r.init[0][0].cpu().numpy()[0], r.init[0][1].cpu().numpy()[0]
             GAo, GBo, _ = O.gate_split(job.w["gates"][0], 2, 2)
             pairs = {b: (GAo, GBo) for b in O.BONDS}
             while n_bonds < 16 and time.perf_counter() - t0 < args.cpu_seconds:
@@ -497,8 +574,17 @@ def main():
             cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
         except Exception:
             cores = os.cpu_count()
+        model, ncpu = host_cpu()
         result["cpu_baseline"] = {"value": n_bonds / el, "unit": "bond_updates/s", "cores": cores, "kind": "oracle",
-                                  "sample": sample}
+                                  "sample": sample, "cpu_model": model, "logical_cpus_visible": ncpu}
+        if g_oracle:
+            g64, gmx = gs
+            k = len(g_oracle)
+            e_mx = [float(np.linalg.norm(gmx[i] - g_oracle[i]) / np.linalg.norm(g_oracle[i])) for i in range(k)]
+            e_64 = [float(np.linalg.norm(g64[i] - g_oracle[i]) / np.linalg.norm(g_oracle[i])) for i in range(k)]
+            result["metric_rel_err_vs_oracle"] = {"D": job.buckets[0]["D"], "items": k, "precision": args.precision,
+                                                  "max": max(e_mx), "fp64_path_max": max(e_64),
+                                                  "state": "seeded state, H1 cluster"}
     print(json.dumps(result), flush=True)
 
 
