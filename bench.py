@@ -61,6 +61,8 @@ def parse():
                     help="keep the built-in K split of the metric assembly instead of autotuning it per bucket")
     ap.add_argument("--bucket", type=int, default=8,
                     help="batched workload: headline on the items of this bond dimension (0 = all 256 items)")
+    ap.add_argument("--storage", default="c64", choices=["c64", "c128"],
+                    help="batched workload: site tensors stored as complex64 (as drawn) or complex128")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the extra measurement of all 256 items (mixed D)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -168,7 +170,7 @@ class Job:
     each, all of one bond dimension) and the sweep order of a step."""
 
 
-def bucket_job(ntu, torch, np, dev, items, label):
+def bucket_job(ntu, torch, np, dev, items, label, storage):
     buckets = {}
     for it in items:
         buckets.setdefault(it["D"], []).append(it)
@@ -179,9 +181,10 @@ def bucket_job(ntu, torch, np, dev, items, label):
         its = buckets[D]
         ctx = ntu.Context(complex_=True, d=2, d_anc=1, r_g=2, max_D=D, max_batch=len(its))
         ctx.bind_stream()
-        # complex64 values upcast once at set-up; the hot path runs in complex128
-        A = torch.from_numpy(np.stack([i["A"] for i in its])).to(dev).to(torch.complex128).contiguous()
-        B = torch.from_numpy(np.stack([i["B"] for i in its])).to(dev).to(torch.complex128).contiguous()
+        # site tensors stored as drawn (complex64; the step widens them, runs in
+        # complex128 and stores the new tensors rounded), or widened once here
+        A = torch.from_numpy(np.stack([i["A"] for i in its])).to(dev).to(storage).contiguous()
+        B = torch.from_numpy(np.stack([i["B"] for i in its])).to(dev).to(storage).contiguous()
         G = torch.from_numpy(np.stack([i["gate"] for i in its])).to(dev).contiguous()
         GA, GB, _ = ntu.ntu_gate_split(ctx, G)
         gf = torch.zeros(len(its), 4, 2, 2, 2, 2, dtype=torch.complex128, device=dev)
@@ -262,6 +265,7 @@ class Runner:
                 ctx = bk["ctx"]
                 QX, _ = ntu.ntu_reduce_qr(ctx, A, bk["gf"][:, 0, 0].contiguous(), 0)
                 QY, _ = ntu.ntu_reduce_qr(ctx, B, bk["gf"][:, 0, 1].contiguous(), 1)
+                A, B = A.to(torch.complex128), B.to(torch.complex128)
                 ks, tms = ntu.ntu_tune_env(ctx, QX, QY, [B, B, B, A, A, A], precision, D=bk["D"])
                 tuning[str(bk["D"])] = {"e6_ksplit": ks, "env_ms": round(tms, 4)}
         torch.cuda.synchronize()
@@ -405,7 +409,8 @@ def metric_sample(job, ntu, torch, precision, n_items=2):
     bk = job.buckets[0]
     ctx = bk["ctx"]
     ctx.bind_stream()
-    A, B = bk["A"][:n_items].contiguous(), bk["B"][:n_items].contiguous()
+    A = bk["A"][:n_items].to(torch.complex128).contiguous()
+    B = bk["B"][:n_items].to(torch.complex128).contiguous()
     QX, _ = ntu.ntu_reduce_qr(ctx, A, bk["gf"][:n_items, 0, 0].contiguous(), 0)
     QY, _ = ntu.ntu_reduce_qr(ctx, B, bk["gf"][:n_items, 0, 1].contiguous(), 1)
     nb = [B, B, B, A, A, A]
@@ -443,7 +448,8 @@ def main():
                      f"one batched call per step")
         else:
             items, label = all_items, "configuration 4: 256 independent bond updates, D uniform in {3..8}"
-        job = bucket_job(ntu, torch, np, dev, items, label)
+        storage = torch.complex64 if args.storage == "c64" else torch.complex128
+        job = bucket_job(ntu, torch, np, dev, items, label, storage)
     else:
         job = thermal_job(ntu, torch, np, dev, inputs)
     if args.aux == "shared":
@@ -476,7 +482,10 @@ def main():
                             "fit": ("fp64, <=20 ALS iterations, early stop 1e-12 N" if args.scheme == "ntu"
                                     else "none (SVDU scheme)"),
                             "scheme": args.scheme,
-                            "storage": "values drawn as complex64, hot path in complex128",
+                            "storage": ("site tensors stored in complex64 (widened at the start of each step, "
+                                        "written back rounded), step computed in complex128"
+                                        if args.storage == "c64" else
+                                        "values drawn as complex64, widened once, stored in complex128"),
                             "start": f"seeded state + {W} FP64 warm-up steps"}
         if len(job.buckets) > 1:
             result["config"]["streams"] = (f"one per D bucket, side streams "
@@ -514,7 +523,7 @@ def main():
     # extra: all 256 items of configuration 4 (mixed D)
     if args.workload == "batched" and args.bucket and not args.no_mixed:
         jm = bucket_job(ntu, torch, np, dev, all_items,
-                        "configuration 4: 256 independent bond updates, D uniform in {3..8}")
+                        "configuration 4: 256 independent bond updates, D uniform in {3..8}", storage)
         if args.aux == "shared":
             jm.aux = torch.cuda.Stream(device=dev)
             for bk in jm.buckets:

@@ -9,18 +9,24 @@
  * ---------------------------------------------------------------------------
  * Conventions shared by every call
  * ---------------------------------------------------------------------------
- * Pointers.  Every tensor pointer is a DEVICE pointer to memory the caller
- *   allocated; the library never frees or reallocates caller memory.  Batched
- *   operands are dense: item i of a buffer starts at i * (item size).  Uneven
- *   bond dimensions are handled by one call per dimension.
+ * Tensors.  Every array argument is an ntu_tensor descriptor: a DEVICE
+ *   pointer to memory the caller allocated, its element type, and its shape
+ *   and strides (in elements).  The library never frees or reallocates caller
+ *   memory.  Batched operands carry the batch as their leading dimension;
+ *   uneven bond dimensions are handled by one call per dimension.  Only
+ *   dense row-major layouts are accepted (stride of the last dimension 1,
+ *   each other stride the product of the later extents; extents of 1 may
+ *   have any stride).  Each call checks every descriptor against the shape
+ *   it needs (named below) before anything is launched: a NULL descriptor or
+ *   data pointer gives NTU_ERR_ARG, memory that is not device memory
+ *   NTU_ERR_ARG, a wrong element type NTU_ERR_DTYPE, a wrong rank, extent or
+ *   stride NTU_ERR_SHAPE.
  * Storage.  Row-major, last index fastest.  NTU_C128 is interleaved
  *   (re, im) double pairs (the layout of a complex128 array), NTU_F64 plain
- *   doubles, NTU_C64 interleaved float pairs (accepted for site tensors only,
- *   upcast on load).  All results are written in the context's compute type
+ *   doubles, NTU_C64 interleaved float pairs (accepted for site tensors
+ *   only: read with an upcast, and in ntu_trotter_step also written back
+ *   rounded).  All other results are written in the context's compute type
  *   (NTU_F64 or NTU_C128).
- * Site tensors.  Legs (p, t, l, b, r): physical block p = d * d_anc
- *   (ancilla folded in as p = s * d_anc + a), then top, left, bottom, right
- *   virtual legs of dimension D.  Size p * D^4.
  * Canonical bond.  The updated bond joins X.r to Y.l.  r_g is the rank of the
  *   gate split (Fig. 2(a)), R = D * r_g the dimension of the enlarged bond.
  * Streams.  Work is enqueued on the context's stream (ntu_set_stream) and is
@@ -59,8 +65,18 @@ enum {
   NTU_ERR_UNSUPPORTED = -7  /* valid request this build does not implement   */
 };
 
-/* storage types */
+/* element types */
 enum { NTU_F64 = 0, NTU_C128 = 1, NTU_C64 = 2 };
+
+#define NTU_MAX_DIMS 8
+/* A dense row-major device array (see "Tensors" above). */
+typedef struct ntu_tensor {
+  void* data;                     /* device pointer to the first element      */
+  int32_t dtype;                  /* NTU_F64, NTU_C128 or NTU_C64             */
+  int32_t ndim;                   /* 1 .. NTU_MAX_DIMS                        */
+  int64_t shape[NTU_MAX_DIMS];    /* extents                                  */
+  int64_t stride[NTU_MAX_DIMS];   /* in elements                              */
+} ntu_tensor;
 
 /* arithmetic of the environment contraction (ntu_env_contract) */
 enum {
@@ -122,11 +138,12 @@ const char* ntu_version(void);
  * G = sum_k GA[:, :, k] (x) GB[:, :, k] up to the discarded terms.
  * Gauge: the first entry of U[:, k] whose modulus is within 1e-8 of the
  * column maximum is made real and positive.
- * gate: batch x d^4.  GA, GB: batch x (d, d, r_g).  sigma: batch x d^2
- * doubles, all singular values in descending order (device).
+ * gate: (batch, d^2, d^2), compute type.  GA, GB: (batch, d, d, r_g), compute
+ * type, written.  sigma: (batch, d^2) NTU_F64, written: all singular values
+ * in descending order.
  */
-ntu_status ntu_gate_split(ntu_ctx* ctx, int batch, const void* gate, void* GA, void* GB,
-                          double* sigma);
+ntu_status ntu_gate_split(ntu_ctx* ctx, int batch, const ntu_tensor* gate, ntu_tensor* GA, ntu_tensor* GB,
+                          ntu_tensor* sigma);
 
 /*
  * Reduction, Fig. 2(b).  Applies the gate factor to the site tensor and takes
@@ -138,11 +155,12 @@ ntu_status ntu_gate_split(ntu_ctx* ctx, int batch, const void* gate, void* GA, v
  * Q is computed by Gram-Schmidt with the projection applied twice; a column
  * whose orthogonal part has norm <= 1e-10 * (largest column norm of W) is
  * dependent: its Q column and R diagonal are exactly zero.
- * site: batch x p D^4 in site_dtype (NTU_F64, NTU_C128 or NTU_C64).
- * gate_factor: batch x (d, d, r_g).  Q: batch x (p D^3) x R.  R: batch x R x R.
+ * site: (batch, p, D, D, D, D) in the compute type, or NTU_C64 with a
+ * complex context; D is taken from it.  gate_factor: (batch, d, d, r_g).
+ * Q: (batch, p D^3, R), written.  R: (batch, R, R), written.
  */
-ntu_status ntu_reduce_qr(ntu_ctx* ctx, int batch, int D, const void* site, int site_dtype,
-                         const void* gate_factor, int side, void* Q, void* R);
+ntu_status ntu_reduce_qr(ntu_ctx* ctx, int batch, const ntu_tensor* site, const ntu_tensor* gate_factor,
+                         int side, ntu_tensor* Q, ntu_tensor* R);
 
 /*
  * Environment contraction, Fig. 4.  Builds the bond metric
@@ -154,13 +172,14 @@ ntu_status ntu_reduce_qr(ntu_ctx* ctx, int batch, int D, const void* site, int s
  * parallel to the updated one.  Physical legs of the neighbours and their
  * virtual legs that leave the cluster are closed by contracting ket with bra
  * (Fig. 4(a,b)).  The result is Hermitian and non-negative up to rounding.
- * QX: batch x (p,t,l,b | a)  ((p D^3) x R, rows p,t,l,b), as ntu_reduce_qr side 0.
- * QY: batch x (p,t,b,r | b)  ((p D^3) x R, rows p,t,b,r), as ntu_reduce_qr side 1.
- * nbr: six pointers, each batch x p D^4 site tensors (compute type).
- * precision: NTU_PREC_*.  g: batch x R^2 x R^2, compute type.
+ * QX: (batch, p D^3, R), rows (p,t,l,b), as ntu_reduce_qr side 0.
+ * QY: (batch, p D^3, R), rows (p,t,b,r), as ntu_reduce_qr side 1.
+ * nbr: six descriptors, each (batch, p, D, D, D, D) site tensors (compute
+ * type); D is taken from nbr[0].  precision: NTU_PREC_*.
+ * g: (batch, R^2, R^2), compute type, written.
  */
-ntu_status ntu_env_contract(ntu_ctx* ctx, int batch, int D, const void* QX, const void* QY,
-                            const void* const nbr[6], int precision, void* g);
+ntu_status ntu_env_contract(ntu_ctx* ctx, int batch, const ntu_tensor* QX, const ntu_tensor* QY,
+                            const ntu_tensor nbr[6], int precision, ntu_tensor* g);
 
 /*
  * Metric repair.  The exact metric is Hermitian and non-negative (abstract;
@@ -170,8 +189,9 @@ ntu_status ntu_env_contract(ntu_ctx* ctx, int batch, int D, const void* QX, cons
  * remaining block is certified positive definite (Gershgorin discs right of
  * zero, else a Cholesky factor exists) the clip is the identity and is
  * skipped.
- * g: batch x n x n in place, n = (D r_g)^2.
- * stats (device, may be NULL): batch x 8 doubles
+ * g: (batch, n, n) in place, compute type, n = (D r_g)^2 for a D of the
+ * context.
+ * stats (may be NULL): (batch, 8) NTU_F64, written
  *   [0] ||g - g^H||_F / ||g||_F  (input)      [1] ||g||_F (input)
  *   [2] smallest eigenvalue (NaN if not computed)
  *   [3] largest eigenvalue  (NaN if not computed)
@@ -180,7 +200,7 @@ ntu_status ntu_env_contract(ntu_ctx* ctx, int batch, int D, const void* QX, cons
  *   [6] number of non-finite entries in the input
  *   [7] Jacobi sweeps of the eigen-decomposition (0 when none was needed)
  */
-ntu_status ntu_metric_fix(ntu_ctx* ctx, int batch, int D, void* g, int mode, double* stats);
+ntu_status ntu_metric_fix(ntu_ctx* ctx, int batch, ntu_tensor* g, int mode, ntu_tensor* stats);
 
 /* Options of the bond fit (Eqs. (3)-(5)). */
 typedef struct ntu_fit_opts {
@@ -214,9 +234,9 @@ void ntu_fit_opts_default(ntu_fit_opts* o);
  *   ladder value minimising eps, evaluated directly.  The Y half-step mirrors
  *   it.  Finally SVD of MX MY^T, singular values divided by the largest,
  *   MX = U S^1/2, MY = conj(V) S^1/2, zero-padded to D columns.
- * g: batch x R^2 x R^2 (Hermitian, non-negative).  RX, RY: batch x R x R.
- * MX, MY: batch x R x D outputs.
- * stats (device, may be NULL): batch x NTU_FIT_STATS_LEN(n_iter, D) doubles:
+ * g: (batch, R^2, R^2) (Hermitian, non-negative).  RX, RY: (batch, R, R).
+ * MX, MY: (batch, R, D), written; D is taken from MX.
+ * stats (may be NULL): (batch, NTU_FIT_STATS_LEN(n_iter, D)) NTU_F64, written:
  *   [0] N = vec(P)^H g vec(P)  [1] eps of the SVDU guess  [2] final eps
  *   [3] final eps / N          [4] Dn   [5] Dk (kept after balancing)
  *   [6] iterations done        [7] half-steps solved by eigendecomposition
@@ -233,18 +253,19 @@ void ntu_fit_opts_default(ntu_fit_opts* o);
  *   [16 + 2 n_iter + 2i + h]   chosen tolerance of that half-step
  *   [16 + 4 n_iter + j]        normalised singular value j (0 beyond Dk)
  */
-ntu_status ntu_bond_fit(ntu_ctx* ctx, int batch, int D, const void* g, const void* RX,
-                        const void* RY, const ntu_fit_opts* opts, void* MX, void* MY,
-                        double* stats);
+ntu_status ntu_bond_fit(ntu_ctx* ctx, int batch, const ntu_tensor* g, const ntu_tensor* RX,
+                        const ntu_tensor* RY, const ntu_fit_opts* opts, ntu_tensor* MX, ntu_tensor* MY,
+                        ntu_tensor* stats);
 
 /*
  * Recombination, Fig. 2(e): X' = QX MX (new leg r), Y' = QY MY (new leg l),
  * written as site tensors (p, t, l, b, r).
- * QX, QY: as from ntu_reduce_qr.  MX, MY: batch x R x D.
- * Xn, Yn: batch x p D^4 outputs (must not alias QX/QY).
+ * QX, QY: (batch, p D^3, R) as from ntu_reduce_qr.  MX, MY: (batch, R, D);
+ * D is taken from MX.  Xn, Yn: (batch, p, D, D, D, D), compute type, written
+ * (must not alias QX/QY).
  */
-ntu_status ntu_recombine(ntu_ctx* ctx, int batch, int D, const void* QX, const void* QY,
-                         const void* MX, const void* MY, void* Xn, void* Yn);
+ntu_status ntu_recombine(ntu_ctx* ctx, int batch, const ntu_tensor* QX, const ntu_tensor* QY,
+                         const ntu_tensor* MX, const ntu_tensor* MY, ntu_tensor* Xn, ntu_tensor* Yn);
 
 /* Options of a Trotter step. */
 typedef struct ntu_step_opts {
@@ -254,6 +275,12 @@ typedef struct ntu_step_opts {
   int fix_mode;         /* NTU_FIX_*                                            */
   ntu_fit_opts fit;
   int scheme;           /* NTU_SCHEME_* (default NTU)                           */
+  int graph;            /* 0: launch eagerly.  1: the first call captures the
+                           step into a HIP graph kept by the context, and later
+                           calls with the same arguments (buffers, batch, D,
+                           options) replay it; other arguments capture anew.
+                           Not allowed while the caller's stream is itself
+                           being captured (NTU_ERR_ARG).                       */
 } ntu_step_opts;
 
 void ntu_step_opts_default(ntu_step_opts* o);
@@ -269,10 +296,13 @@ void ntu_step_opts_default(ntu_step_opts* o);
  * V1 and V2 are H1 and H2 after rotating both tensors by 90 degrees clockwise
  * (new (t, l, b, r) = old (l, b, r, t)), i.e. the bonds A.t-B.b and B.t-A.b.
  * The environment of each update is made of the current A and B.
- * A, B: batch x p D^4 in place (compute type).
- * gate_factors: batch x 4 bonds x 2 x (d, d, r_g): for bond j (NTU_BOND_*) the
+ * A, B: (batch, p, D, D, D, D) in place, in the compute type, or both
+ *   NTU_C64 with a complex context (storage in complex64: read with an
+ *   upcast at the start of the step, the sweep runs in complex128, the new
+ *   tensors are written back rounded to complex64).  D is taken from A.
+ * gate_factors: (batch, 4, 2, d, d, r_g): for bond j (NTU_BOND_*) the
  *   factors (GA, GB) of its gate, GA acting on X.  Items are independent.
- * stats (device, may be NULL): batch x n_bonds x NTU_STEP_STATS_LEN doubles:
+ * stats (may be NULL): (batch, n_bonds, NTU_STEP_STATS_LEN) NTU_F64, written:
  *   [0..7] metric stats of the update, then the bond-fit stats.
  * With opts->scheme == NTU_SCHEME_SVDU every update is an SVDU update (no
  *   environment, metric repair or ALS fit; precision, fix_mode and the fit's
@@ -280,8 +310,8 @@ void ntu_step_opts_default(ntu_step_opts* o);
  *   hold N = eps = 0, D_n, D_k and the normalised singular values, and the
  *   metric stats [0..7] are not written.
  */
-ntu_status ntu_trotter_step(ntu_ctx* ctx, int batch, int D, void* A, void* B,
-                            const void* gate_factors, const ntu_step_opts* opts, double* stats);
+ntu_status ntu_trotter_step(ntu_ctx* ctx, int batch, ntu_tensor* A, ntu_tensor* B,
+                            const ntu_tensor* gate_factors, const ntu_step_opts* opts, ntu_tensor* stats);
 
 /*
  * Autotuning of the split-precision environment contraction (a launch
@@ -298,8 +328,9 @@ ntu_status ntu_trotter_step(ntu_ctx* ctx, int batch, int D, void* A, void* B,
  * keeps the fastest for (D, precision) in the context, where
  * ntu_env_contract and ntu_trotter_step then use it, and returns it in
  * best_ks (and its mean time in best_ms), either may be NULL.  The choice is
- * made for this batch size.  Precision must be NTU_PREC_BF16X3 or
- * NTU_PREC_BF16X6 (NTU_ERR_ARG otherwise); reps >= 1.
+ * made for this batch size.  Precision must be one of the split
+ * precisions (NTU_ERR_ARG otherwise); reps >= 1.  The operands are those of
+ * ntu_env_contract (D taken from nbr[0]).
  * ntu_set_env_ksplit sets it directly (ks = 0: the heuristic again);
  * ntu_get_env_ksplit returns it (0: the heuristic).
  * ntu_tune_save writes the context's choices to a text file, one line
@@ -307,8 +338,8 @@ ntu_status ntu_trotter_step(ntu_ctx* ctx, int batch, int D, void* A, void* B,
  * context (entries for D > max_D or other precisions are skipped; a
  * malformed line gives NTU_ERR_ARG, after the lines before it are taken).
  */
-ntu_status ntu_tune_env(ntu_ctx* ctx, int batch, int D, int precision, const void* QX, const void* QY,
-                        const void* const nbr[6], void* g, int reps, int* best_ks, float* best_ms);
+ntu_status ntu_tune_env(ntu_ctx* ctx, int batch, int precision, const ntu_tensor* QX, const ntu_tensor* QY,
+                        const ntu_tensor nbr[6], ntu_tensor* g, int reps, int* best_ks, float* best_ms);
 ntu_status ntu_set_env_ksplit(ntu_ctx* ctx, int D, int precision, int ks);
 int ntu_get_env_ksplit(ntu_ctx* ctx, int D, int precision);
 ntu_status ntu_tune_save(ntu_ctx* ctx, const char* path);

@@ -15,8 +15,9 @@
 namespace {
 
 struct Persist {
-  // per-item persistent buffers of the Trotter step (compute type elements)
-  long long QX, QY, RX, RY, g, MX, MY, rA, rB, GA, GB, cert, guess, todo;
+  // per-item persistent buffers of the Trotter step (compute type elements);
+  // wA, wB: the compute-type copies of complex64 site tensors
+  long long QX, QY, RX, RY, g, MX, MY, rA, rB, GA, GB, cert, guess, todo, wA, wB;
 };
 
 }  // namespace
@@ -44,6 +45,11 @@ struct ntu_ctx {
   // tuned K split of the split-precision metric assembly per (D, precision)
   // (ntu_tune_env / ntu_set_env_ksplit); absent: the heuristic
   std::map<std::pair<int, int>, int> e6_ks;
+  // the Trotter step captured by ntu_trotter_step (opts.graph = 1) and the
+  // arguments it was captured with
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<char> graph_key;
 };
 
 namespace {
@@ -117,13 +123,15 @@ Persist persist_layout(int p, int D, int rg, int d) {
   s.cert = o; o += 1;  // the metric repair's certificate for the fit (one double per item)
   s.guess = o; o += ntu::svdu_guess_elems();  // the fit's SVDU guess, computed beside the environment
   s.todo = o; o += 1;  // the reduction's path flags, two ints per item
+  s.wA = o; o += p * D3 * D;
+  s.wB = o; o += p * D3 * D;
   (void)o;
   return s;
 }
 long long persist_elems(int p, int D, int rg, int d) {
   const long long R = (long long)D * rg, D3 = (long long)D * D * D;
   return 2 * p * D3 * R + 2 * R * R + R * R * R * R + 2 * R * D + 2 * p * D3 * D + 2LL * d * d * rg + 1 +
-         ntu::svdu_guess_elems() + 1;
+         ntu::svdu_guess_elems() + 1 + 2 * p * D3 * D;
 }
 
 const int PROF_CAP = 1 << 15;
@@ -170,7 +178,93 @@ ntu_status check_fit_opts(ntu_ctx* c, const ntu_fit_opts* o) {
   return NTU_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// descriptor checks
+// ---------------------------------------------------------------------------
+constexpr unsigned M_F64 = 1u << NTU_F64, M_C128 = 1u << NTU_C128, M_C64 = 1u << NTU_C64;
+
+const char* dtype_name(int d) {
+  return d == NTU_F64 ? "F64" : d == NTU_C128 ? "C128" : d == NTU_C64 ? "C64" : "unknown";
+}
+
+std::string shape_str(const long long* s, int n) {
+  std::string o = "(";
+  for (int i = 0; i < n; ++i) o += (i ? ", " : "") + std::to_string(s[i]);
+  return o + ")";
+}
+
+unsigned compute_mask(const ntu_ctx* c) { return c->cplx ? M_C128 : M_F64; }
+
+// t must be a dense row-major device array of the given shape and one of
+// the element types in `dtypes`
+ntu_status check_tensor(ntu_ctx* c, const ntu_tensor* t, const char* name, unsigned dtypes,
+                        std::initializer_list<long long> want) {
+  const std::string nm(name);
+  if (!t) return fail(c, NTU_ERR_ARG, nm + ": NULL descriptor");
+  if (!t->data) return fail(c, NTU_ERR_ARG, nm + ": NULL data pointer");
+  if (t->dtype < 0 || t->dtype > NTU_C64 || !((dtypes >> t->dtype) & 1u)) {
+    std::string ok;
+    for (int d = 0; d <= NTU_C64; ++d)
+      if ((dtypes >> d) & 1u) ok += std::string(ok.empty() ? "" : " or ") + dtype_name(d);
+    return fail(c, NTU_ERR_DTYPE, nm + ": element type " + dtype_name(t->dtype) + ", expected " + ok);
+  }
+  const long long* w = want.begin();
+  const int n = (int)want.size();
+  if (t->ndim != n) {
+    const int nd = t->ndim < 0 ? 0 : std::min(t->ndim, NTU_MAX_DIMS);
+    long long got[NTU_MAX_DIMS];
+    for (int i = 0; i < nd; ++i) got[i] = t->shape[i];
+    return fail(c, NTU_ERR_SHAPE, nm + ": shape " + shape_str(got, nd) + ", expected " + shape_str(w, n));
+  }
+  for (int i = 0; i < n; ++i)
+    if (t->shape[i] != w[i]) {
+      long long got[NTU_MAX_DIMS];
+      for (int k = 0; k < n; ++k) got[k] = t->shape[k];
+      return fail(c, NTU_ERR_SHAPE, nm + ": shape " + shape_str(got, n) + ", expected " + shape_str(w, n));
+    }
+  long long st = 1;
+  for (int i = n - 1; i >= 0; --i) {
+    if (t->shape[i] != 1 && t->stride[i] != st)
+      return fail(c, NTU_ERR_SHAPE, nm + ": not a dense row-major array (stride of dimension " + std::to_string(i) +
+                                        " is " + std::to_string(t->stride[i]) + ", expected " + std::to_string(st) + ")");
+    st *= t->shape[i];
+  }
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, t->data) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, NTU_ERR_ARG, nm + ": not device memory");
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(c, NTU_ERR_ARG, nm + ": not device memory");
+  if (attr.device != c->device)
+    return fail(c, NTU_ERR_ARG, nm + ": memory of device " + std::to_string(attr.device) + ", the context's is " +
+                                    std::to_string(c->device));
+  return NTU_OK;
+}
+
+// the bond dimension a descriptor implies at dimension `dim` (0 if absent)
+int dim_of(const ntu_tensor* t, int dim) {
+  if (!t || t->ndim <= dim || t->shape[dim] < 1 || t->shape[dim] > 64) return 0;
+  return (int)t->shape[dim];
+}
+
+// the step graph captured by ntu_trotter_step, if any
+void drop_graph(ntu_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  c->graph_key.clear();
+}
+
+#define NTU_CHECK(x) do { ntu_status s_ = (x); if (s_) return s_; } while (0)
+
 }  // namespace
+
+namespace ntu {
+void set_global_error(const char* msg) { g_create_err = msg; }
+}  // namespace ntu
 
 extern "C" {
 
@@ -247,6 +341,7 @@ ntu_status ntu_ctx_create(ntu_ctx** out, int device, int dtype, int d, int d_anc
 ntu_status ntu_ctx_destroy(ntu_ctx* c) {
   if (!c) return NTU_ERR_ARG;
   DeviceGuard guard(c->device);
+  drop_graph(c);
   if (c->ws) (void)hipFree(c->ws);
   if (c->step) (void)hipFree(c->step);
   if (c->aux) (void)hipStreamDestroy(c->aux);
@@ -276,115 +371,165 @@ const char* ntu_last_error(const ntu_ctx* c) {
 
 size_t ntu_workspace_bytes(const ntu_ctx* c) { return c ? c->ws_bytes + c->step_bytes : 0; }
 
-ntu_status ntu_gate_split(ntu_ctx* c, int batch, const void* gate, void* GA, void* GB, double* sigma) {
-  ntu_status s = check_common(c, batch, 1);
-  if (s) return s;
+ntu_status ntu_gate_split(ntu_ctx* c, int batch, const ntu_tensor* gate, ntu_tensor* GA, ntu_tensor* GB,
+                          ntu_tensor* sigma) {
+  NTU_CHECK(check_common(c, batch, 1));
   if (batch == 0) return NTU_OK;
-  if (!gate || !GA || !GB || !sigma) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  const long long d = c->d, r = c->rg;
+  NTU_CHECK(check_tensor(c, gate, "gate", compute_mask(c), {batch, d * d, d * d}));
+  NTU_CHECK(check_tensor(c, GA, "GA", compute_mask(c), {batch, d, d, r}));
+  NTU_CHECK(check_tensor(c, GB, "GB", compute_mask(c), {batch, d, d, r}));
+  NTU_CHECK(check_tensor(c, sigma, "sigma", M_F64, {batch, d * d}));
   DeviceGuard guard(c->device);
   const ntu::ProfHook ph = hook(c);
   ph(ntu::PK_GATE, 0);
-  hipError_t e = ntu::launch_gate_split(c->cplx, batch, c->d, c->rg, gate, GA, GB, sigma, c->stream);
+  hipError_t e = ntu::launch_gate_split(c->cplx, batch, c->d, c->rg, gate->data, GA->data, GB->data,
+                                        (double*)sigma->data, c->stream);
   ph(ntu::PK_GATE, 1);
   return e == hipSuccess ? NTU_OK : hip_fail(c, e, "gate_split");
 }
 
-ntu_status ntu_reduce_qr(ntu_ctx* c, int batch, int D, const void* site, int site_dtype, const void* gf,
-                         int side, void* Q, void* R) {
-  ntu_status s = check_common(c, batch, D);
-  if (s) return s;
+ntu_status ntu_reduce_qr(ntu_ctx* c, int batch, const ntu_tensor* site, const ntu_tensor* gf, int side,
+                         ntu_tensor* Q, ntu_tensor* R) {
+  NTU_CHECK(check_common(c, batch, 1));
   if (side != 0 && side != 1) return fail(c, NTU_ERR_ARG, "side must be 0 (X) or 1 (Y)");
-  bool ok_dtype = c->cplx ? (site_dtype == NTU_C128 || site_dtype == NTU_C64) : site_dtype == NTU_F64;
-  if (!ok_dtype) return fail(c, NTU_ERR_DTYPE, "site dtype does not match the context");
   if (batch == 0) return NTU_OK;
-  if (!site || !gf || !Q || !R) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  const int D = dim_of(site, 2);
+  NTU_CHECK(check_common(c, batch, D));
+  const long long p = pdim(c), Rd = (long long)D * c->rg, D3 = (long long)D * D * D;
+  NTU_CHECK(check_tensor(c, site, "site", compute_mask(c) | (c->cplx ? M_C64 : 0u), {batch, p, D, D, D, D}));
+  NTU_CHECK(check_tensor(c, gf, "gate_factor", compute_mask(c), {batch, c->d, c->d, c->rg}));
+  NTU_CHECK(check_tensor(c, Q, "Q", compute_mask(c), {batch, p * D3, Rd}));
+  NTU_CHECK(check_tensor(c, R, "R", compute_mask(c), {batch, Rd, Rd}));
   DeviceGuard guard(c->device);
   const ntu::ProfHook ph = hook(c);
   ph(ntu::PK_REDUCE, 0);
-  hipError_t e = ntu::launch_reduce_qr(c->cplx, site_dtype, batch, c->d, c->na, D, c->rg, site, gf,
-                                       (long long)c->d * c->d * c->rg, side, Q, R, 1e-10, (int*)c->ws, c->stream);
+  hipError_t e = ntu::launch_reduce_qr(c->cplx, site->dtype, batch, c->d, c->na, D, c->rg, site->data, gf->data,
+                                       (long long)c->d * c->d * c->rg, side, Q->data, R->data, 1e-10, (int*)c->ws,
+                                       c->stream);
   ph(ntu::PK_REDUCE, 1);
   return e == hipSuccess ? NTU_OK : hip_fail(c, e, "reduce_qr");
 }
 
-ntu_status ntu_env_contract(ntu_ctx* c, int batch, int D, const void* QX, const void* QY, const void* const nbr[6],
-                            int precision, void* g) {
-  ntu_status s = check_common(c, batch, D);
-  if (s) return s;
+}  // extern "C"
+
+namespace {
+// operands of ntu_env_contract / ntu_tune_env; D from nbr[0]
+ntu_status check_env_operands(ntu_ctx* c, int batch, const ntu_tensor* QX, const ntu_tensor* QY,
+                              const ntu_tensor* nbr, const ntu_tensor* g, int* D_out) {
+  if (!nbr) return fail(c, NTU_ERR_ARG, "nbr: NULL descriptor array");
+  const int D = dim_of(&nbr[0], 2);
+  NTU_CHECK(check_common(c, batch, D));
+  const long long p = pdim(c), Rd = (long long)D * c->rg, D3 = (long long)D * D * D;
+  NTU_CHECK(check_tensor(c, QX, "QX", compute_mask(c), {batch, p * D3, Rd}));
+  NTU_CHECK(check_tensor(c, QY, "QY", compute_mask(c), {batch, p * D3, Rd}));
+  static const char* const names[6] = {"nbr[0] (L)", "nbr[1] (TX)", "nbr[2] (BX)", "nbr[3] (TY)", "nbr[4] (BY)",
+                                       "nbr[5] (Rn)"};
+  for (int i = 0; i < 6; ++i) NTU_CHECK(check_tensor(c, &nbr[i], names[i], compute_mask(c), {batch, p, D, D, D, D}));
+  NTU_CHECK(check_tensor(c, g, "g", compute_mask(c), {batch, Rd * Rd, Rd * Rd}));
+  *D_out = D;
+  return NTU_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ntu_status ntu_env_contract(ntu_ctx* c, int batch, const ntu_tensor* QX, const ntu_tensor* QY,
+                            const ntu_tensor nbr[6], int precision, ntu_tensor* g) {
+  NTU_CHECK(check_common(c, batch, 1));
   if (precision < NTU_PREC_F64 || precision > NTU_PREC_BF16X6) return fail(c, NTU_ERR_ARG, "unknown precision");
   if (batch == 0) return NTU_OK;
-  if (!QX || !QY || !nbr || !g) return fail(c, NTU_ERR_ARG, "NULL pointer");
-  for (int i = 0; i < 6; ++i)
-    if (!nbr[i]) return fail(c, NTU_ERR_ARG, "NULL neighbour pointer");
+  int D = 0;
+  NTU_CHECK(check_env_operands(c, batch, QX, QY, nbr, g, &D));
+  if (!ntu::env_precision_supported(c->cplx, precision, D))
+    return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
+  const void* nb[6];
+  for (int i = 0; i < 6; ++i) nb[i] = nbr[i].data;
   DeviceGuard guard(c->device);
-  hipError_t e = ntu::launch_env_contract(c->cplx, precision, batch, pdim(c), D, D * c->rg, QX, QY, nbr, g, c->ws,
-                                          c->ws_bytes, c->stream, hook(c), 0, env_ks(c, D, precision));
-  if (e == hipErrorNotSupported) return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
+  hipError_t e = ntu::launch_env_contract(c->cplx, precision, batch, pdim(c), D, D * c->rg, QX->data, QY->data, nb,
+                                          g->data, c->ws, c->ws_bytes, c->stream, hook(c), 0,
+                                          env_ks(c, D, precision));
   return e == hipSuccess ? NTU_OK : hip_fail(c, e, "env_contract");
 }
 
-ntu_status ntu_metric_fix(ntu_ctx* c, int batch, int D, void* g, int mode, double* stats) {
-  ntu_status s = check_common(c, batch, D);
-  if (s) return s;
+ntu_status ntu_metric_fix(ntu_ctx* c, int batch, ntu_tensor* g, int mode, ntu_tensor* stats) {
+  NTU_CHECK(check_common(c, batch, 1));
   if (mode != NTU_FIX_HERM && mode != NTU_FIX_HERM_CLIP) return fail(c, NTU_ERR_ARG, "unknown mode");
   if (batch == 0) return NTU_OK;
-  if (!g) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  if (!g || g->ndim != 3) return fail(c, NTU_ERR_SHAPE, "g: expected (batch, n, n)");
+  // n = (D r_g)^2 for some D of the context
+  int D = 0;
+  for (int k = 1; k <= c->max_D; ++k)
+    if ((long long)(k * c->rg) * (k * c->rg) == g->shape[1]) D = k;
+  if (!D) return fail(c, NTU_ERR_SHAPE, "g: n is not (D r_g)^2 for a D of the context");
+  const long long n = (long long)(D * c->rg) * (D * c->rg);
+  NTU_CHECK(check_tensor(c, g, "g", compute_mask(c), {batch, n, n}));
+  if (stats) NTU_CHECK(check_tensor(c, stats, "stats", M_F64, {batch, 8}));
   DeviceGuard guard(c->device);
-  const int R = D * c->rg;
-  hipError_t e = ntu::launch_metric_fix(c->cplx, batch, R * R, g, mode, stats, 8, c->ws, c->stream, hook(c));
+  hipError_t e = ntu::launch_metric_fix(c->cplx, batch, (int)n, g->data, mode, stats ? (double*)stats->data : nullptr,
+                                        8, c->ws, c->stream, hook(c));
   return e == hipSuccess ? NTU_OK : hip_fail(c, e, "metric_fix");
 }
 
-ntu_status ntu_bond_fit(ntu_ctx* c, int batch, int D, const void* g, const void* RX, const void* RY,
-                        const ntu_fit_opts* opts, void* MX, void* MY, double* stats) {
-  ntu_status s = check_common(c, batch, D);
-  if (s) return s;
-  if ((s = check_fit_opts(c, opts))) return s;
+ntu_status ntu_bond_fit(ntu_ctx* c, int batch, const ntu_tensor* g, const ntu_tensor* RX, const ntu_tensor* RY,
+                        const ntu_fit_opts* opts, ntu_tensor* MX, ntu_tensor* MY, ntu_tensor* stats) {
+  NTU_CHECK(check_common(c, batch, 1));
+  NTU_CHECK(check_fit_opts(c, opts));
   if (batch == 0) return NTU_OK;
-  if (!g || !RX || !RY || !MX || !MY) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  const int D = dim_of(MX, 2);
+  NTU_CHECK(check_common(c, batch, D));
+  const long long Rd = (long long)D * c->rg;
+  NTU_CHECK(check_tensor(c, g, "g", compute_mask(c), {batch, Rd * Rd, Rd * Rd}));
+  NTU_CHECK(check_tensor(c, RX, "RX", compute_mask(c), {batch, Rd, Rd}));
+  NTU_CHECK(check_tensor(c, RY, "RY", compute_mask(c), {batch, Rd, Rd}));
+  NTU_CHECK(check_tensor(c, MX, "MX", compute_mask(c), {batch, Rd, D}));
+  NTU_CHECK(check_tensor(c, MY, "MY", compute_mask(c), {batch, Rd, D}));
+  const int fl = ntu::fit_stats_len(opts->n_iter, D);
+  if (stats) NTU_CHECK(check_tensor(c, stats, "stats", M_F64, {batch, fl}));
   DeviceGuard guard(c->device);
-  const int R = D * c->rg;
-  hipError_t e = ntu::launch_bond_fit(c->cplx, batch, D, R, g, RX, RY, fit_params(opts), MX, MY, stats,
-                                      ntu::fit_stats_len(opts->n_iter, D), c->ws, c->stream, hook(c));
+  hipError_t e = ntu::launch_bond_fit(c->cplx, batch, D, (int)Rd, g->data, RX->data, RY->data, fit_params(opts),
+                                      MX->data, MY->data, stats ? (double*)stats->data : nullptr, fl, c->ws,
+                                      c->stream, hook(c));
   return e == hipSuccess ? NTU_OK : hip_fail(c, e, "bond_fit");
 }
 
-ntu_status ntu_recombine(ntu_ctx* c, int batch, int D, const void* QX, const void* QY, const void* MX,
-                         const void* MY, void* Xn, void* Yn) {
-  ntu_status s = check_common(c, batch, D);
-  if (s) return s;
+ntu_status ntu_recombine(ntu_ctx* c, int batch, const ntu_tensor* QX, const ntu_tensor* QY, const ntu_tensor* MX,
+                         const ntu_tensor* MY, ntu_tensor* Xn, ntu_tensor* Yn) {
+  NTU_CHECK(check_common(c, batch, 1));
   if (batch == 0) return NTU_OK;
-  if (!QX || !QY || !MX || !MY || !Xn || !Yn) return fail(c, NTU_ERR_ARG, "NULL pointer");
+  const int D = dim_of(MX, 2);
+  NTU_CHECK(check_common(c, batch, D));
+  const long long p = pdim(c), Rd = (long long)D * c->rg, D3 = (long long)D * D * D;
+  NTU_CHECK(check_tensor(c, QX, "QX", compute_mask(c), {batch, p * D3, Rd}));
+  NTU_CHECK(check_tensor(c, QY, "QY", compute_mask(c), {batch, p * D3, Rd}));
+  NTU_CHECK(check_tensor(c, MX, "MX", compute_mask(c), {batch, Rd, D}));
+  NTU_CHECK(check_tensor(c, MY, "MY", compute_mask(c), {batch, Rd, D}));
+  NTU_CHECK(check_tensor(c, Xn, "Xn", compute_mask(c), {batch, p, D, D, D, D}));
+  NTU_CHECK(check_tensor(c, Yn, "Yn", compute_mask(c), {batch, p, D, D, D, D}));
   DeviceGuard guard(c->device);
   const ntu::ProfHook ph = hook(c);
   ph(ntu::PK_RECOMB, 0);
-  hipError_t e = ntu::launch_recombine(c->cplx, batch, pdim(c), D, D * c->rg, QX, QY, MX, MY, Xn, Yn, 0, c->stream);
+  hipError_t e = ntu::launch_recombine(c->cplx, batch, pdim(c), D, (int)Rd, QX->data, QY->data, MX->data, MY->data,
+                                       Xn->data, Yn->data, 0, c->stream);
   ph(ntu::PK_RECOMB, 1);
   return e == hipSuccess ? NTU_OK : hip_fail(c, e, "recombine");
 }
 
-ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, const void* gate_factors,
-                            const ntu_step_opts* opts, double* stats) {
-  ntu_status s = check_common(c, batch, D);
-  if (s) return s;
-  if (!opts) return fail(c, NTU_ERR_ARG, "step options are NULL");
-  if (opts->n_bonds < 0 || opts->n_bonds > 8) return fail(c, NTU_ERR_ARG, "n_bonds outside [0, 8]");
-  for (int i = 0; i < opts->n_bonds; ++i)
-    if (opts->order[i] < 0 || opts->order[i] > 3) return fail(c, NTU_ERR_ARG, "unknown bond in order");
-  if (opts->precision < NTU_PREC_F64 || opts->precision > NTU_PREC_BF16X6) return fail(c, NTU_ERR_ARG, "unknown precision");
-  if (opts->fix_mode != NTU_FIX_HERM && opts->fix_mode != NTU_FIX_HERM_CLIP) return fail(c, NTU_ERR_ARG, "unknown fix mode");
-  if ((s = check_fit_opts(c, &opts->fit))) return s;
-  if (opts->scheme != NTU_SCHEME_NTU && opts->scheme != NTU_SCHEME_SVDU) return fail(c, NTU_ERR_ARG, "unknown scheme");
-  if (batch == 0 || opts->n_bonds == 0) return NTU_OK;
-  if (!A || !B || !gate_factors) return fail(c, NTU_ERR_ARG, "NULL pointer");
-  DeviceGuard guard(c->device);
+}  // extern "C"
+
+namespace {
+
+// The launches of one Trotter step (everything after argument checks).  A, B
+// are compute-type site tensors; for complex64 storage (c64) the caller's
+// tensors are A64, B64 and A, B are the context's working copies.
+hipError_t step_launches(ntu_ctx* c, int batch, int D, char* A, char* B, void* A64, void* B64, bool c64,
+                         const char* gate_factors, const ntu_step_opts* opts, double* stats, const ntu::ProfHook& ph,
+                         const char** where) {
   const bool cp = c->cplx;
   const int p = pdim(c), R = D * c->rg;
   const size_t el = elem_size(c);
-  const long long site = (long long)p * D * D * D * D;
-  const long long pe = persist_elems(p, D, c->rg, c->d);
   const Persist L = persist_layout(p, D, c->rg, c->d);
-  // persistent buffers: item stride pe elements, laid out per buffer kind
+  // persistent buffers: laid out per buffer kind, item stride = one item's elements
   auto buf = [&](long long off) -> char* { return c->step + (size_t)off * el * batch; };
   char* QX = buf(L.QX);
   char* QY = buf(L.QY);
@@ -398,21 +543,35 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
   double* cert = (double*)buf(L.cert);
   char* guess = buf(L.guess);
   int* todo = (int*)buf(L.todo);
-  (void)pe;
   const long long gfs = (long long)c->d * c->d * c->rg;  // elements of one factor
   const long long gf_item = 8 * gfs;                      // 4 bonds x (GA, GB)
   const int fl = ntu::fit_stats_len(opts->fit.n_iter, D);
   const int sl = 8 + fl;
   const long long s_item = (long long)opts->n_bonds * sl;
+  const long long nsite = (long long)p * D * D * D * D;
   const ntu::FitParams fp = fit_params(&opts->fit);
-  const ntu::ProfHook ph = hook(c);
   hipError_t e = hipSuccess;
-#define NTU_STEP(x, what) do { e = (x); if (e != hipSuccess) return hip_fail(c, e, what); } while (0)
+  // Fork/join bookkeeping: once the side stream has been forked, every exit
+  // joins it back into the context stream (an unjoined fork would leave the
+  // side stream's work unordered with later calls, and would make a capture
+  // that contains it invalid).
+  bool forked = false;
+  hipStream_t aux = c->aux_user ? c->aux_user : c->aux;
+  auto join = [&]() {
+    if (!forked) return;
+    forked = false;
+    if (hipEventRecord(c->ev_join, aux) == hipSuccess) (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
+  };
+#define NTU_STEP(x, what) do { e = (x); if (e != hipSuccess) { *where = what; join(); return e; } } while (0)
+  if (c64) {
+    NTU_STEP(ntu::launch_cast_c64(batch * nsite, A64, A, 0, c->stream), "complex64 load");
+    NTU_STEP(ntu::launch_cast_c64(batch * nsite, B64, B, 0, c->stream), "complex64 load");
+  }
   for (int bi = 0; bi < opts->n_bonds; ++bi) {
     const int bond = opts->order[bi];
     const bool vertical = bond >= 2, x_is_a = (bond == NTU_BOND_H1 || bond == NTU_BOND_V1);
-    char* a = (char*)A;
-    char* b = (char*)B;
+    char* a = A;
+    char* b = B;
     if (vertical) {
       ph(ntu::PK_ROTATE, 0);
       NTU_STEP(ntu::launch_rotate_cw(cp, batch, p, D, A, rA, c->stream), "rotate");
@@ -423,15 +582,15 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     }
     char* X = x_is_a ? a : b;
     char* Y = x_is_a ? b : a;
-    const char* gA = (const char*)gate_factors + (size_t)(bond * 2 + 0) * gfs * el;
-    const char* gB = (const char*)gate_factors + (size_t)(bond * 2 + 1) * gfs * el;
+    const char* gA = gate_factors + (size_t)(bond * 2 + 0) * gfs * el;
+    const char* gB = gate_factors + (size_t)(bond * 2 + 1) * gfs * el;
     // new X -> (A or B), new Y -> the other, rotated back for vertical bonds
     void* outX = x_is_a ? A : B;
     void* outY = x_is_a ? B : A;
+    double* sb = stats ? stats + (size_t)bi * sl : nullptr;
     if (opts->scheme == NTU_SCHEME_SVDU) {
       // SVDU update (Fig. 2): reduction, truncated SVD of RX RY^T, the fit's
       // balancing without a metric, recombination; all on the context stream
-      double* sb = stats ? stats + (size_t)bi * sl : nullptr;
       ph(ntu::PK_REDUCE, 0);
       NTU_STEP(ntu::launch_reduce_qr_pair(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, Y, gB, gf_item, QX, RX, QY,
                                           RY, opts->fit.kappa, todo, c->stream), "reduce_qr");
@@ -449,29 +608,24 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     // the edge tensors and transfers (they read only the neighbours) while
     // the reduction runs, then the fit's SVDU guess (it needs only RX, RY)
     // while the environment is contracted.  Events order the two streams.
-    hipStream_t aux = c->aux_user ? c->aux_user : c->aux;
     const void* nbr[6] = {Y, Y, Y, X, X, X};
     const ntu::ProfHook none{nullptr, nullptr};
     NTU_STEP(hipEventRecord(c->ev_fork, c->stream), "fork");
     NTU_STEP(hipStreamWaitEvent(aux, c->ev_fork, 0), "fork");
-    e = ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, nullptr, nullptr, nbr, nullptr, c->ws,
-                                 c->ws_bytes, aux, none, 1);
-    if (e != hipSuccess) return hip_fail(c, e, "env_contract (edges)");
+    forked = true;
+    NTU_STEP(ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, nullptr, nullptr, nbr, nullptr, c->ws,
+                                      c->ws_bytes, aux, none, 1), "env_contract (edges)");
     NTU_STEP(hipEventRecord(c->ev_edges, aux), "fork");
     ph(ntu::PK_REDUCE, 0);
-    NTU_STEP(ntu::launch_reduce_qr_pair(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, Y, gB, gf_item, QX, RX, QY, RY,
-                                        opts->fit.kappa, todo, c->stream), "reduce_qr");
+    NTU_STEP(ntu::launch_reduce_qr_pair(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, Y, gB, gf_item, QX, RX, QY,
+                                        RY, opts->fit.kappa, todo, c->stream), "reduce_qr");
     ph(ntu::PK_REDUCE, 1);
     NTU_STEP(hipEventRecord(c->ev_red, c->stream), "fork");
     NTU_STEP(hipStreamWaitEvent(aux, c->ev_red, 0), "fork");
     NTU_STEP(ntu::launch_svdu_guess(cp, batch, D, R, RX, RY, opts->fit.kappa, guess, aux), "svdu_guess");
-    NTU_STEP(hipEventRecord(c->ev_join, aux), "join");
     NTU_STEP(hipStreamWaitEvent(c->stream, c->ev_edges, 0), "join");
-    e = ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, QX, QY, nbr, G, c->ws, c->ws_bytes, c->stream, ph,
-                                 2, env_ks(c, D, opts->precision));
-    if (e == hipErrorNotSupported) return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
-    if (e != hipSuccess) return hip_fail(c, e, "env_contract");
-    double* sb = stats ? stats + (size_t)bi * sl : nullptr;
+    NTU_STEP(ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, QX, QY, nbr, G, c->ws, c->ws_bytes,
+                                      c->stream, ph, 2, env_ks(c, D, opts->precision)), "env_contract");
     // with the clip, the repair also tests the fit's certificate (g minus
     // 10 tau_max ||g||_F I positive definite, see the fit) and hands it over
     const bool clip = opts->fix_mode == NTU_FIX_HERM_CLIP;
@@ -479,7 +633,10 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
     NTU_STEP(ntu::launch_metric_fix(cp, batch, R * R, G, opts->fix_mode, sb, (int)s_item, c->ws, c->stream, ph,
                                     clip ? shift : 0.0, clip ? cert : nullptr),
              "metric_fix");
+    // the SVDU guess is ready: join the side stream
+    NTU_STEP(hipEventRecord(c->ev_join, aux), "join");
     NTU_STEP(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join");
+    forked = false;
     NTU_STEP(ntu::launch_bond_fit(cp, batch, D, R, G, RX, RY, fp, MX, MY, sb ? sb + 8 : nullptr, (int)s_item, c->ws,
                                   c->stream, ph, clip ? cert : nullptr, guess), "bond_fit");
     ph(ntu::PK_RECOMB, 0);
@@ -487,22 +644,120 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, int D, void* A, void* B, cons
              "recombine");
     ph(ntu::PK_RECOMB, 1);
   }
+  if (c64) {
+    NTU_STEP(ntu::launch_cast_c64(batch * nsite, A, A64, 1, c->stream), "complex64 store");
+    NTU_STEP(ntu::launch_cast_c64(batch * nsite, B, B64, 1, c->stream), "complex64 store");
+  }
 #undef NTU_STEP
-  (void)site;
-  return NTU_OK;
+  return hipSuccess;
 }
 
-ntu_status ntu_tune_env(ntu_ctx* c, int batch, int D, int precision, const void* QX, const void* QY,
-                        const void* const nbr[6], void* g, int reps, int* best_ks, float* best_ms) {
-  ntu_status s = check_common(c, batch, D);
-  if (s) return s;
-  if (precision != NTU_PREC_BF16X3 && precision != NTU_PREC_BF16X6)
-    return fail(c, NTU_ERR_ARG, "tuning applies to the split precisions BF16x3 and BF16x6");
+// the arguments a captured step depends on, as bytes (fields copied one by
+// one, so padding never enters the comparison)
+std::vector<char> step_key(int batch, int D, const void* A, const void* B, int a_dtype, const void* gf,
+                           const void* stats, const ntu_step_opts* o) {
+  std::vector<char> k;
+  auto put = [&](const void* p, size_t n) { k.insert(k.end(), (const char*)p, (const char*)p + n); };
+  put(&batch, sizeof batch); put(&D, sizeof D); put(&A, sizeof A); put(&B, sizeof B); put(&a_dtype, sizeof a_dtype);
+  put(&gf, sizeof gf); put(&stats, sizeof stats);
+  put(&o->n_bonds, sizeof(int)); put(o->order, sizeof o->order); put(&o->precision, sizeof(int));
+  put(&o->fix_mode, sizeof(int)); put(&o->scheme, sizeof(int));
+  const ntu_fit_opts& f = o->fit;
+  put(&f.n_iter, sizeof(int)); put(&f.early_stop, sizeof(int)); put(&f.conv_tol, sizeof(double));
+  put(&f.kappa, sizeof(double)); put(&f.n_tol, sizeof(int)); put(f.tol, sizeof f.tol); put(&f.tie, sizeof(double));
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+ntu_status ntu_trotter_step(ntu_ctx* c, int batch, ntu_tensor* A, ntu_tensor* B, const ntu_tensor* gate_factors,
+                            const ntu_step_opts* opts, ntu_tensor* stats) {
+  NTU_CHECK(check_common(c, batch, 1));
+  if (!opts) return fail(c, NTU_ERR_ARG, "step options are NULL");
+  if (opts->n_bonds < 0 || opts->n_bonds > 8) return fail(c, NTU_ERR_ARG, "n_bonds outside [0, 8]");
+  for (int i = 0; i < opts->n_bonds; ++i)
+    if (opts->order[i] < 0 || opts->order[i] > 3) return fail(c, NTU_ERR_ARG, "unknown bond in order");
+  if (opts->precision < NTU_PREC_F64 || opts->precision > NTU_PREC_BF16X6) return fail(c, NTU_ERR_ARG, "unknown precision");
+  if (opts->fix_mode != NTU_FIX_HERM && opts->fix_mode != NTU_FIX_HERM_CLIP) return fail(c, NTU_ERR_ARG, "unknown fix mode");
+  NTU_CHECK(check_fit_opts(c, &opts->fit));
+  if (opts->scheme != NTU_SCHEME_NTU && opts->scheme != NTU_SCHEME_SVDU) return fail(c, NTU_ERR_ARG, "unknown scheme");
+  if (opts->graph != 0 && opts->graph != 1) return fail(c, NTU_ERR_ARG, "graph must be 0 or 1");
+  if (batch == 0 || opts->n_bonds == 0) return NTU_OK;
+  const int D = dim_of(A, 2);
+  NTU_CHECK(check_common(c, batch, D));
+  const long long p = pdim(c);
+  const unsigned site_types = compute_mask(c) | (c->cplx ? M_C64 : 0u);
+  NTU_CHECK(check_tensor(c, A, "A", site_types, {batch, p, D, D, D, D}));
+  NTU_CHECK(check_tensor(c, B, "B", 1u << A->dtype, {batch, p, D, D, D, D}));
+  NTU_CHECK(check_tensor(c, gate_factors, "gate_factors", compute_mask(c), {batch, 4, 2, c->d, c->d, c->rg}));
+  const int fl = ntu::fit_stats_len(opts->fit.n_iter, D);
+  if (stats) NTU_CHECK(check_tensor(c, stats, "stats", M_F64, {batch, opts->n_bonds, 8 + fl}));
+  if (opts->scheme == NTU_SCHEME_NTU && !ntu::env_precision_supported(c->cplx, opts->precision, D))
+    return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
+  if (A->data == B->data) return fail(c, NTU_ERR_ARG, "A and B alias");
+  DeviceGuard guard(c->device);
+  const bool c64 = A->dtype == NTU_C64;
+  const Persist L = persist_layout((int)p, D, c->rg, c->d);
+  const size_t el = elem_size(c);
+  char* wa = c64 ? c->step + (size_t)L.wA * el * batch : (char*)A->data;
+  char* wb = c64 ? c->step + (size_t)L.wB * el * batch : (char*)B->data;
+  double* st = stats ? (double*)stats->data : nullptr;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(c->stream, &cs);
+  if (e != hipSuccess) return hip_fail(c, e, "stream capture query");
+  const bool capturing = cs != hipStreamCaptureStatusNone;
+  const char* where = "";
+  if (!opts->graph) {
+    // eager (possibly inside the caller's own capture: no profiler events then)
+    e = step_launches(c, batch, D, wa, wb, A->data, B->data, c64, (const char*)gate_factors->data, opts, st,
+                      capturing ? ntu::ProfHook{nullptr, nullptr} : hook(c), &where);
+    return e == hipSuccess ? NTU_OK : hip_fail(c, e, where);
+  }
+  if (capturing) return fail(c, NTU_ERR_ARG, "graph = 1 while the context stream is being captured by the caller");
+  if (!c->stream) return fail(c, NTU_ERR_ARG, "graph = 1 needs a context stream other than the null stream");
+  std::vector<char> key = step_key(batch, D, A->data, B->data, A->dtype, gate_factors->data, st, opts);
+  if (!c->graph_exec || key != c->graph_key) {
+    drop_graph(c);
+    e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(c, e, "begin capture");
+    hipError_t el_ = step_launches(c, batch, D, wa, wb, A->data, B->data, c64, (const char*)gate_factors->data, opts,
+                                   st, ntu::ProfHook{nullptr, nullptr}, &where);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->stream, &g);
+    if (el_ != hipSuccess || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      return el_ != hipSuccess ? hip_fail(c, el_, where) : hip_fail(c, e, "end capture");
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(c, e, "graph instantiate");
+    }
+    c->graph = g;
+    c->graph_exec = x;
+    c->graph_key.swap(key);
+  }
+  e = hipGraphLaunch(c->graph_exec, c->stream);
+  return e == hipSuccess ? NTU_OK : hip_fail(c, e, "graph launch");
+}
+
+ntu_status ntu_tune_env(ntu_ctx* c, int batch, int precision, const ntu_tensor* QX, const ntu_tensor* QY,
+                        const ntu_tensor nbr[6], ntu_tensor* g, int reps, int* best_ks, float* best_ms) {
+  NTU_CHECK(check_common(c, batch, 1));
+  if (precision != NTU_PREC_BF16X3 && precision != NTU_PREC_BF16X6 && precision != NTU_PREC_FP16X3)
+    return fail(c, NTU_ERR_ARG, "tuning applies to the split precisions");
   if (reps < 1) return fail(c, NTU_ERR_ARG, "reps < 1");
   if (batch == 0) return NTU_OK;
-  if (!QX || !QY || !nbr || !g) return fail(c, NTU_ERR_ARG, "NULL pointer");
-  for (int i = 0; i < 6; ++i)
-    if (!nbr[i]) return fail(c, NTU_ERR_ARG, "NULL neighbour pointer");
+  int D = 0;
+  NTU_CHECK(check_env_operands(c, batch, QX, QY, nbr, g, &D));
+  if (!ntu::env_precision_supported(c->cplx, precision, D))
+    return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
+  const void* nb[6];
+  for (int i = 0; i < 6; ++i) nb[i] = nbr[i].data;
   DeviceGuard guard(c->device);
   const int R = D * c->rg;
   const int kdef = ntu::e6_ksplit_default(c->cplx, batch, R, D), kcap = ntu::e6_ksplit_max(c->cplx, batch, R, D);
@@ -517,8 +772,8 @@ ntu_status ntu_tune_env(ntu_ctx* c, int batch, int D, int precision, const void*
   const ntu::ProfHook none{nullptr, nullptr};
   for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
     auto launch = [&]() {
-      return ntu::launch_env_contract(c->cplx, precision, batch, pdim(c), D, R, QX, QY, nbr, g, c->ws, c->ws_bytes,
-                                      c->stream, none, 0, cand[i]);
+      return ntu::launch_env_contract(c->cplx, precision, batch, pdim(c), D, R, QX->data, QY->data, nb, g->data,
+                                      c->ws, c->ws_bytes, c->stream, none, 0, cand[i]);
     };
     e = launch();  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
@@ -535,7 +790,6 @@ ntu_status ntu_tune_env(ntu_ctx* c, int batch, int D, int precision, const void*
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  if (e == hipErrorNotSupported) return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
   if (e != hipSuccess) return hip_fail(c, e, "tune_env");
   c->e6_ks[{D, precision}] = best;
   if (best_ks) *best_ks = best;
@@ -546,8 +800,8 @@ ntu_status ntu_tune_env(ntu_ctx* c, int batch, int D, int precision, const void*
 ntu_status ntu_set_env_ksplit(ntu_ctx* c, int D, int precision, int ks) {
   if (!c) return NTU_ERR_ARG;
   if (D < 1 || D > c->max_D) return fail(c, NTU_ERR_SHAPE, "D outside [1, max_D]");
-  if (precision != NTU_PREC_BF16X3 && precision != NTU_PREC_BF16X6)
-    return fail(c, NTU_ERR_ARG, "the K split applies to the split precisions BF16x3 and BF16x6");
+  if (precision != NTU_PREC_BF16X3 && precision != NTU_PREC_BF16X6 && precision != NTU_PREC_FP16X3)
+    return fail(c, NTU_ERR_ARG, "the K split applies to the split precisions");
   if (ks < 0) return fail(c, NTU_ERR_ARG, "ks < 0");
   if (ks == 0) c->e6_ks.erase({D, precision});
   else c->e6_ks[{D, precision}] = ks;
@@ -582,7 +836,8 @@ ntu_status ntu_tune_load(ntu_ctx* c, const char* path) {
       s = fail(c, NTU_ERR_ARG, std::string("malformed line in ") + path);
       break;
     }
-    if (D >= 1 && D <= c->max_D && (prec == NTU_PREC_BF16X3 || prec == NTU_PREC_BF16X6) && ks > 0)
+    if (D >= 1 && D <= c->max_D && (prec == NTU_PREC_BF16X3 || prec == NTU_PREC_BF16X6 || prec == NTU_PREC_FP16X3) &&
+        ks > 0)
       c->e6_ks[{D, prec}] = ks;
   }
   fclose(f);

@@ -121,6 +121,20 @@ NTU_DEV double block_sum(double v, double* red) {
   for (int i = 0; i < nw; ++i) s += red[i];
   return s;
 }
+// Largest v over the workgroup (float, wave64, at most 16 waves); red: 16
+// floats of shared memory.  Every thread gets the result.
+NTU_DEV float wg_maxf(float v, float* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  float m = red[0];
+  for (int i = 1; i < nw; ++i) m = fmaxf(m, red[i]);
+  return m;
+}
+
 NTU_DEV double block_max(double v, double* red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   v = wave_max(v);

@@ -360,6 +360,13 @@ static size_t half_elem(bool cplx, int precision) {
   return cplx ? 8 : 4;
 }
 
+bool env_precision_supported(bool cplx, int precision, int D) {
+  if (precision == NTU_PREC_F64 || precision == NTU_PREC_BF16X3 || precision == NTU_PREC_BF16X6) return true;
+  // FP16X3 scales each operand block by block inside the fused kernels:
+  // complex metrics with D^2 <= 64 (the fused path)
+  return precision == NTU_PREC_FP16X3 && e45_supported(cplx, precision, D);
+}
+
 size_t env_workspace_bytes(bool cplx, int precision, int batch, int p, int D, int R) {
   EnvSizes s = env_sizes(p, D, R);
   size_t el = cplx ? 16 : 8;

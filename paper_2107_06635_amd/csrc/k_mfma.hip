@@ -505,6 +505,176 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
       }
 }
 
+// ---------------------------------------------------------------------------
+// The final assembly g = L2 Right^T in FP16X3 from operands the fused kernels
+// wrote already split: each complex entry of a row is two packed words, the
+// float16 hi pieces (re, im) then the lo pieces, the row scaled by its power
+// of two (rows of A: sA[item][i], of B: sB[item][j]).  The
+// K loop only moves pieces: global -> registers -> shared memory (complex B
+// rows expanded to the two real rows (re, -im), (im, re) by a sign flip and a
+// half swap of the packed words) -> MFMA.  Same tiling, buffering and block
+// order as k_mfma_tile; C(i, j) = (hh + 2^-11 (hl + lh)) / (sA[i] sB[j]).
+// ---------------------------------------------------------------------------
+struct TileF16Args {
+  int M, N, Kc, batch;          // rows of A and of B, complex K
+  long long a_item, b_item;     // item strides (words) of A and B
+  long long a_row, b_row;       // row strides (words): 2 Kc for contiguous rows
+  const float* sA;              // [item][M]
+  const float* sB;              // [item][N]
+  Idx3 Cb, Ci, Cj;              // output maps (complex elements)
+  int tiles_m, tiles_n, ksplit, kchunk;  // kchunk: real K per chunk
+  int nwork;
+  double* partial;              // ksplit > 1: [split][item][M][2N]
+};
+
+template <class TC>
+__global__ void __launch_bounds__(TL_THREADS) k_mfma_tile_f16(const unsigned* __restrict__ A,
+                                                              const unsigned* __restrict__ B, TC* __restrict__ C,
+                                                              TileF16Args ta) {
+  using E = _Float16;
+  constexpr int NT = 2;
+  constexpr int NGA = TL_M * TL_K / 4 / TL_THREADS;  // groups of 4 reals (2 complex) of A per thread
+  constexpr int NGB = NGA / 2;                       // of B (each complex row gives two real rows)
+  constexpr int SA_EL = 2 * NT * TL_M * TL_LD, SB_EL = 2 * NT * TL_N * TL_LD;
+  __shared__ __attribute__((aligned(16))) E smem[SA_EL + SB_EL];
+  E (*sA)[NT][TL_M][TL_LD] = reinterpret_cast<E (*)[NT][TL_M][TL_LD]>(smem);
+  E (*sB)[NT][TL_N][TL_LD] = reinterpret_cast<E (*)[NT][TL_N][TL_LD]>(smem + SA_EL);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 2, wn = wv & 3;
+  const int per = (ta.nwork + 7) / 8;
+  const int q = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (q >= ta.nwork) return;
+  const int T = ta.tiles_m * ta.tiles_n;
+  const int item = q / (T * ta.ksplit), rem = q % (T * ta.ksplit);
+  const int tile = rem / ta.ksplit, split = rem % ta.ksplit;
+  const int i0 = (tile / ta.tiles_n) * TL_M, j0 = (tile % ta.tiles_n) * TL_N;
+  const int Mr = ta.M, Nr = 2 * ta.N, Kr = 2 * ta.Kc;
+  const int kbeg = split * ta.kchunk, kend = min(Kr, kbeg + ta.kchunk);
+  const unsigned* Ab = A + (size_t)item * ta.a_item;
+  const unsigned* Bb = B + (size_t)item * ta.b_item;
+  // this thread's load groups: A row, 4 reals (2 words per piece) at real kq
+  const unsigned* arow[NGA];
+  int akq[NGA], arl[NGA];
+#pragma unroll
+  for (int u = 0; u < NGA; ++u) {
+    const int g = tid + TL_THREADS * u, rl = g / (TL_K / 4);
+    arl[u] = rl;
+    akq[u] = (g % (TL_K / 4)) * 4;
+    arow[u] = i0 + rl < Mr ? Ab + (size_t)(i0 + rl) * ta.a_row : nullptr;
+  }
+  const unsigned* brow[NGB];
+  int bkq[NGB], brl[NGB];
+#pragma unroll
+  for (int u = 0; u < NGB; ++u) {
+    const int g = tid + TL_THREADS * u, rl = g / (TL_K / 4);  // complex row
+    brl[u] = rl;
+    bkq[u] = (g % (TL_K / 4)) * 4;
+    const int jrow = j0 / 2 + rl;
+    brow[u] = 2 * jrow < Nr ? Bb + (size_t)jrow * ta.b_row : nullptr;
+  }
+  // registers: per group and piece, the two packed words (2 complex)
+  uint2 ra0[NGA][NT], rb0[NGB][NT], ra1[NGA][NT], rb1[NGB][NT];
+  // complex entries k / 2 and k / 2 + 1 (words k .. k + 3, each entry an
+  // 8-byte aligned (hi, lo) pair; rows of odd length K end after the first)
+  auto ld2 = [&](const unsigned* row, int k, uint2 (&r)[NT]) {
+    const uint2 z = make_uint2(0u, 0u);
+    const uint2 v0 = row && k < kend ? *(const uint2*)(row + k) : z;
+    const uint2 v1 = row && k + 2 < kend ? *(const uint2*)(row + k + 2) : z;
+    r[0] = make_uint2(v0.x, v1.x);
+    r[1] = make_uint2(v0.y, v1.y);
+  };
+  auto gload = [&](int k0, uint2 (&ra)[NGA][NT], uint2 (&rb)[NGB][NT]) {
+#pragma unroll
+    for (int u = 0; u < NGA; ++u) ld2(arow[u], k0 + akq[u], ra[u]);
+#pragma unroll
+    for (int u = 0; u < NGB; ++u) ld2(brow[u], k0 + bkq[u], rb[u]);
+  };
+  auto lstore = [&](int buf, const uint2 (&ra)[NGA][NT], const uint2 (&rb)[NGB][NT]) {
+#pragma unroll
+    for (int u = 0; u < NGA; ++u)
+#pragma unroll
+      for (int p = 0; p < NT; ++p) *(uint2*)&sA[buf][p][arl[u]][tl_col(arl[u], akq[u])] = ra[u][p];
+#pragma unroll
+    for (int u = 0; u < NGB; ++u) {
+      // complex values (re0, im0), (re1, im1) -> real rows 2r: (re, -im),
+      // 2r+1: (im, re); rows stored in bank-quarter order as in k_mfma_tile
+      const int odd_first = (brl[u] ^ (brl[u] >> 1)) & 1;
+      const int r0 = 2 * brl[u] + odd_first, r1 = 2 * brl[u] + 1 - odd_first;
+      const int c0 = tl_col(r0, bkq[u]), c1 = tl_col(r1, bkq[u]);
+#pragma unroll
+      for (int p = 0; p < NT; ++p) {
+        const uint2 w = rb[u][p];
+        const uint2 neg = make_uint2(w.x ^ 0x80000000u, w.y ^ 0x80000000u);
+        const uint2 swp = make_uint2((w.x >> 16) | (w.x << 16), (w.y >> 16) | (w.y << 16));
+        *(uint2*)&sB[buf][p][r0][c0] = odd_first ? swp : neg;
+        *(uint2*)&sB[buf][p][r1][c1] = odd_first ? neg : swp;
+      }
+    }
+  };
+
+  f32x4 acc[2][4][TL_WY];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < TL_WY; ++y) acc[c][x][y] = f32x4{0, 0, 0, 0};
+
+  const int nsteps = (kend - kbeg + TL_K - 1) / TL_K;
+  gload(kbeg, ra0, rb0);
+  lstore(0, ra0, rb0);
+  if (nsteps > 1) gload(kbeg + TL_K, ra1, rb1);
+  __syncthreads();
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  const int fks = tl_col(fr, fk);
+  auto step = [&](int s, uint2 (&xa)[NGA][NT], uint2 (&xb)[NGB][NT], const uint2 (&ya)[NGA][NT],
+                  const uint2 (&yb)[NGB][NT]) {
+    const int buf = s & 1;
+    if (s + 2 < nsteps) gload(kbeg + (s + 2) * TL_K, xa, xb);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int ra_ = wm * 64 + x * 16 + fr;
+#pragma unroll
+      for (int y = 0; y < TL_WY; ++y) {
+        const int rb_ = wn * (16 * TL_WY) + y * 16 + fr;
+        const E* a0 = &sA[buf][0][ra_][fks];
+        const E* a1 = &sA[buf][1][ra_][fks];
+        const E* b0 = &sB[buf][0][rb_][fks];
+        const E* b1 = &sB[buf][1][rb_][fks];
+        acc[0][x][y] = mfma<NTU_PREC_FP16X3>(a0, b0, acc[0][x][y]);
+        acc[1][x][y] = mfma<NTU_PREC_FP16X3>(a0, b1, acc[1][x][y]);
+        acc[1][x][y] = mfma<NTU_PREC_FP16X3>(a1, b0, acc[1][x][y]);
+      }
+    }
+    if (s + 1 < nsteps) lstore(buf ^ 1, ya, yb);
+    __syncthreads();
+  };
+  for (int s = 0; s < nsteps; s += 2) {
+    step(s, ra0, rb0, ra1, rb1);
+    if (s + 1 < nsteps) step(s + 1, ra1, rb1, ra0, rb0);
+  }
+  // epilogue: lane holds column (lane & 15), rows 4 (lane >> 4) + v of each 16 x 16 tile
+  const float* sAi = ta.sA + (size_t)item * ta.M;
+  const float* sBi = ta.sB + (size_t)item * ta.N;
+  const long long cbase = idx_off(ta.Cb, item) * 2;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < TL_WY; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wm * 64 + x * 16 + 4 * (lane >> 4) + v;
+        const int jr = j0 + wn * (16 * TL_WY) + y * 16 + (lane & 15);
+        if (i >= Mr || jr >= Nr) continue;
+        const double un = 1.0 / ((double)sAi[i] * (double)sBi[jr >> 1]);
+        const double val = ((double)acc[0][x][y][v] + (double)acc[1][x][y][v] * (1.0 / 2048.0)) * un;
+        if (ta.ksplit > 1) {
+          ta.partial[(((size_t)split * ta.batch + item) * Mr + i) * Nr + jr] = val;
+        } else {
+          C[cbase + (idx_off(ta.Ci, i) + idx_off(ta.Cj, jr >> 1)) * 2 + (jr & 1)] = (TC)val;
+        }
+      }
+}
+
 // sum the split-K partials in FP64 and scatter to C through its index maps
 template <bool CPLX, class TC>
 __global__ void k_splitk_reduce(const double* __restrict__ partial, TC* __restrict__ C, GemmNT d, int ksplit) {
@@ -585,6 +755,43 @@ static hipError_t run_tile(const void* A, const void* B, void* C, const GemmNT& 
   int gx = (int)std::min<long long>((tot + 255) / 256, 4096);
   ph(PK_E6RED, 0);
   hipLaunchKernelGGL((k_splitk_reduce<CPLX, TC>), dim3(gx), dim3(256), 0, st, partial, (TC*)C, d, a.ksplit);
+  ph(PK_E6RED, 1);
+  return hipGetLastError();
+}
+
+// E6 in FP16X3 from the pre-split rows of the fused kernels (complex):
+// A rows (L2) and B rows (Right) of Kc complex entries, 2 Kc words each,
+// item strides in words; output through the maps of d (C side only)
+static hipError_t run_tile_f16(const void* A, const void* B, void* C, const GemmNT& d, long long a_item,
+                               long long b_item, const float* sA, const float* sB, int ksplit, double* partial,
+                               hipStream_t st, const ProfHook& ph, int kind) {
+  const int Mr = d.M, Nr = 2 * d.N, Kr = 2 * d.K;
+  TileF16Args a{};
+  a.M = d.M; a.N = d.N; a.Kc = d.K; a.batch = d.batch;
+  a.a_item = a_item; a.b_item = b_item;
+  a.a_row = 2LL * d.K; a.b_row = 2LL * d.K;
+  a.sA = sA; a.sB = sB;
+  a.Cb = d.Cb; a.Ci = d.Ci; a.Cj = d.Cj;
+  a.tiles_m = (Mr + TL_M - 1) / TL_M;
+  a.tiles_n = (Nr + TL_N - 1) / TL_N;
+  a.ksplit = ksplit < 1 ? 1 : ksplit;
+  int chunk = (Kr + a.ksplit - 1) / a.ksplit;
+  chunk = (chunk + TL_K - 1) / TL_K * TL_K;
+  a.kchunk = chunk;
+  a.ksplit = (Kr + chunk - 1) / chunk;
+  a.nwork = a.tiles_m * a.tiles_n * a.ksplit * d.batch;
+  a.partial = partial;
+  const int per = (a.nwork + 7) / 8;
+  ph(kind, 0);
+  hipLaunchKernelGGL((k_mfma_tile_f16<double>), dim3(8 * per), dim3(TL_THREADS), 0, st, (const unsigned*)A,
+                     (const unsigned*)B, (double*)C, a);
+  ph(kind, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.ksplit == 1) return e;
+  long long tot = (long long)Mr * Nr * d.batch;
+  int gx = (int)std::min<long long>((tot + 255) / 256, 4096);
+  ph(PK_E6RED, 0);
+  hipLaunchKernelGGL((k_splitk_reduce<true, double>), dim3(gx), dim3(256), 0, st, partial, (double*)C, d, a.ksplit);
   ph(PK_E6RED, 1);
   return hipGetLastError();
 }
@@ -675,6 +882,11 @@ static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, con
   const int ks = e6_ks > 0 ? std::min(e6_ks, e6_ks_cap(CPLX, batch, R, D)) : tile_ksplit(batch, q.M, Nr, Kr);
   // partial sums live right after H2 (the workspace reserves mixed_partial_bytes there)
   double* partial = (double*)((char*)H2 + (size_t)batch * hs * (CPLX ? 8 : 4));
+  if constexpr (PREC == NTU_PREC_FP16X3 && CPLX) {
+    // the fused kernels wrote L2 and Right as scaled float16 pieces
+    const E45Scales sc = e45_scales(H1, PREC, batch, D, R);
+    return run_tile_f16(H0, H2, g, q, 2 * hs, 2 * hs, sc.left, sc.right, ks, partial, st, ph, PK_E6);
+  }
   return run_tile<PREC, CPLX, float, float, T64>(H0, H2, g, q, ks, partial, st, ph, PK_E6);
 }
 
@@ -685,7 +897,9 @@ hipError_t launch_env_heavy_mixed(bool cplx, int precision, int batch, int p, in
 #define NTU_MIX(P, C) return env_heavy<P, C>(batch, p, D, R, QXe, QXp, QYe, QYp, ETT, EBT, es, qs, hs, H0, H1, H2, g, st, ph, e6_ks)
   if (precision == NTU_PREC_BF16X3) { if (cplx) NTU_MIX(NTU_PREC_BF16X3, true); NTU_MIX(NTU_PREC_BF16X3, false); }
   if (precision == NTU_PREC_BF16X6) { if (cplx) NTU_MIX(NTU_PREC_BF16X6, true); NTU_MIX(NTU_PREC_BF16X6, false); }
-  // FP16X3 needs operand scales; not wired into the environment yet
+  // FP16X3: the fused path only (complex, D^2 <= 64), where the operands are
+  // scaled block by block and E6 takes them pre-split
+  if (precision == NTU_PREC_FP16X3 && cplx && e45_supported(cplx, precision, D)) NTU_MIX(NTU_PREC_FP16X3, true);
   return hipErrorNotSupported;
 #undef NTU_MIX
 }

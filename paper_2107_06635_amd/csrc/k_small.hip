@@ -2,6 +2,7 @@
 // (Fig. 2(e)) and the 90-degree rotation of site tensors.
 #include "kernels.h"
 #include "linalg.h"
+#include <algorithm>
 
 namespace ntu {
 
@@ -685,6 +686,28 @@ hipError_t launch_rotate_cw(bool cplx, int batch, int p, int D, const void* src,
     hipLaunchKernelGGL(k_rotate_cw<cd>, g, b, 0, st, p, D, (const cd*)src, (cd*)dst);
   else
     hipLaunchKernelGGL(k_rotate_cw<double>, g, b, 0, st, p, D, (const double*)src, (double*)dst);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// complex64 storage of site tensors: widen to, or round from, complex128
+// ---------------------------------------------------------------------------
+__global__ void k_cast_c64(long long n, const void* __restrict__ src, void* __restrict__ dst, int dir) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    if (dir == 0) {
+      const float2 v = ((const float2*)src)[e];
+      ((double2*)dst)[e] = make_double2((double)v.x, (double)v.y);
+    } else {
+      const double2 v = ((const double2*)src)[e];
+      ((float2*)dst)[e] = make_float2((float)v.x, (float)v.y);
+    }
+  }
+}
+
+hipError_t launch_cast_c64(long long n, const void* src, void* dst, int dir, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int gx = (int)std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_cast_c64, dim3(gx), dim3(256), 0, st, n, src, dst, dir);
   return hipGetLastError();
 }
 

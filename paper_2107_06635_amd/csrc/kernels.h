@@ -6,6 +6,9 @@
 
 namespace ntu {
 
+// message returned by ntu_last_error(NULL) (calls without a context)
+void set_global_error(const char* msg);
+
 // Kernel classes timed by the optional event profiler of a context.
 enum ProfKind {
   PK_ROTATE = 0, PK_GATE, PK_REDUCE, PK_EDGES, PK_QPREP, PK_LEFTRIGHT, PK_E4, PK_E5, PK_E6, PK_E6RED,
@@ -33,6 +36,9 @@ hipError_t launch_reduce_qr_pair(bool cplx, int site_dtype, int batch, int d, in
 hipError_t launch_recombine(bool cplx, int batch, int p, int D, int R, const void* QX, const void* QY,
                             const void* MX, const void* MY, void* Xn, void* Yn, int rot, hipStream_t st);
 hipError_t launch_rotate_cw(bool cplx, int batch, int p, int D, const void* src, void* dst, hipStream_t st);
+// complex64 <-> complex128 copy of n elements: dir 0 widens src (complex64)
+// into dst (complex128), dir 1 rounds src (complex128) into dst (complex64)
+hipError_t launch_cast_c64(long long n, const void* src, void* dst, int dir, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // environment contraction
@@ -46,6 +52,8 @@ struct EnvSizes {
   long long half;      // Left / Right / L1 / L2: R^2 D^4 each
 };
 EnvSizes env_sizes(int p, int D, int R);
+// whether ntu_env_contract implements this precision for the compute type and D
+bool env_precision_supported(bool cplx, int precision, int D);
 // bytes of workspace needed for `batch` items at this shape and precision
 size_t env_workspace_bytes(bool cplx, int precision, int batch, int p, int D, int R);
 // part 0: the whole contraction; 1: only the edge tensors and transfers

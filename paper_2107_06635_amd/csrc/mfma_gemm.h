@@ -31,6 +31,16 @@ hipError_t launch_env_heavy_mixed(bool cplx, int precision, int batch, int p, in
 // EtopT / EbotT operands (e45_frag_bytes).  Item stride hs complex elements.
 bool e45_supported(bool cplx, int precision, int D);
 size_t e45_frag_bytes(int precision, int batch, int D);
+// FP16X3 scales (float, in H1 after the fragments): e[item][2] of EtopT /
+// EbotT; left[item][R^2], right[item][R^2]: the power-of-two factor each row
+// of the L2 / Right pieces carries
+struct E45Scales {
+  float* e;
+  float* left;
+  float* right;
+};
+E45Scales e45_scales(void* H1, int precision, int batch, int D, int R);
+size_t e45_scale_bytes(int batch, int R);
 hipError_t launch_env_fused(int precision, int batch, int p, int D, int R, const void* QXe, const void* QXp,
                             const void* QYe, const void* QYp, const void* ETT, const void* EBT, long long es,
                             long long qs, void* H0, void* H1, void* H2, long long hs, hipStream_t st,

@@ -72,4 +72,26 @@ NTU_DEV f32x4 mfma(const typename SplitTraits<PREC>::E* a, const typename SplitT
   }
 }
 
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// FP16X3 pieces of two values already scaled into float16's range:
+// hi = fp16(x), lo = fp16((x - hi) 2^11) (the residual is exact in FP32, the
+// scaling by 2^11 keeps lo in the normal range); one packed word per piece,
+// x0 in the low half.  x = hi + 2^-11 lo to about 2^-22 |x|.
+NTU_DEV void split_pair_f16(float x0, float x1, unsigned* out) {
+  const f16x2 h = __builtin_convertvector((f32x2){x0, x1}, f16x2);
+  const float r0 = (x0 - (float)h.x) * 2048.0f, r1 = (x1 - (float)h.y) * 2048.0f;
+  const f16x2 l = __builtin_convertvector((f32x2){r0, r1}, f16x2);
+  out[0] = __builtin_bit_cast(unsigned, h);
+  out[1] = __builtin_bit_cast(unsigned, l);
+}
+
+// Power-of-two scale that brings a block whose largest magnitude is m into
+// [2^12, 2^13) (float16 holds up to 65504 and is normal from 2^-14 on); 1
+// for an empty or zero block.
+NTU_DEV float f16_scale(float m) {
+  if (!(m > 0.0f) || !isfinite(m)) return 1.0f;
+  return ldexpf(1.0f, 12 - ilogbf(m));
+}
+
 }  // namespace ntu

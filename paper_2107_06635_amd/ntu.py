@@ -3,8 +3,9 @@
 Argument marshalling only: every numerical step runs in the HIP kernels of
 ``libntu.so``.  Tensors are torch tensors on the GPU; outputs are allocated
 with torch (device memory) and filled by the library on the current torch
-stream.  There is no fallback: if the library is missing or a tensor is not
-on the GPU, the call raises.
+stream.  There is no fallback: if the library is missing, or the library
+rejects a tensor (element type, shape, strides, memory that is not on the
+context's GPU), the call raises.
 """
 from __future__ import annotations
 
@@ -43,7 +44,16 @@ class FitOpts(ctypes.Structure):
 
 class StepOpts(ctypes.Structure):
     _fields_ = [("n_bonds", ctypes.c_int), ("order", ctypes.c_int * 8), ("precision", ctypes.c_int),
-                ("fix_mode", ctypes.c_int), ("fit", FitOpts), ("scheme", ctypes.c_int)]
+                ("fix_mode", ctypes.c_int), ("fit", FitOpts), ("scheme", ctypes.c_int), ("graph", ctypes.c_int)]
+
+
+MAX_DIMS = 8
+
+
+class Tensor(ctypes.Structure):
+    """``ntu_tensor``: data pointer, element type, shape and strides (elements)."""
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("ndim", ctypes.c_int32),
+                ("shape", ctypes.c_int64 * MAX_DIMS), ("stride", ctypes.c_int64 * MAX_DIMS)]
 
 
 _lib = None
@@ -67,20 +77,20 @@ def load():
     L.ntu_workspace_bytes.argtypes = [vp]
     L.ntu_workspace_bytes.restype = ctypes.c_size_t
     L.ntu_version.restype = ctypes.c_char_p
-    L.ntu_gate_split.argtypes = [vp, i32, vp, vp, vp, vp]
-    L.ntu_reduce_qr.argtypes = [vp, i32, i32, vp, i32, vp, i32, vp, vp]
-    L.ntu_env_contract.argtypes = [vp, i32, i32, vp, vp, ctypes.POINTER(vp), i32, vp]
-    L.ntu_metric_fix.argtypes = [vp, i32, i32, vp, i32, vp]
+    tp = ctypes.POINTER(Tensor)
+    L.ntu_gate_split.argtypes = [vp, i32, tp, tp, tp, tp]
+    L.ntu_reduce_qr.argtypes = [vp, i32, tp, tp, i32, tp, tp]
+    L.ntu_env_contract.argtypes = [vp, i32, tp, tp, tp, i32, tp]
+    L.ntu_metric_fix.argtypes = [vp, i32, tp, i32, tp]
     L.ntu_fit_opts_default.argtypes = [ctypes.POINTER(FitOpts)]
     L.ntu_fit_opts_default.restype = None
-    L.ntu_bond_fit.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(FitOpts), vp, vp, vp]
-    L.ntu_recombine.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
+    L.ntu_bond_fit.argtypes = [vp, i32, tp, tp, tp, ctypes.POINTER(FitOpts), tp, tp, tp]
+    L.ntu_recombine.argtypes = [vp, i32, tp, tp, tp, tp, tp, tp]
     L.ntu_step_opts_default.argtypes = [ctypes.POINTER(StepOpts)]
     L.ntu_step_opts_default.restype = None
-    L.ntu_trotter_step.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(StepOpts), vp]
+    L.ntu_trotter_step.argtypes = [vp, i32, tp, tp, tp, ctypes.POINTER(StepOpts), tp]
     L.ntu_profile_enable.argtypes = [vp, i32]
-    L.ntu_tune_env.argtypes = [vp, i32, i32, i32, vp, vp, ctypes.POINTER(vp), vp, i32, ctypes.POINTER(i32),
-                               ctypes.POINTER(ctypes.c_float)]
+    L.ntu_tune_env.argtypes = [vp, i32, i32, tp, tp, tp, tp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
     L.ntu_set_env_ksplit.argtypes = [vp, i32, i32, i32]
     L.ntu_get_env_ksplit.argtypes = [vp, i32, i32]
     L.ntu_tune_save.argtypes = [vp, ctypes.c_char_p]
@@ -107,10 +117,12 @@ def fit_opts(n_iter=20, early_stop=False, conv_tol=1e-12, kappa=1e-10, ladder=No
     return o
 
 
-def step_opts(precision="f64", fix_mode=FIX_HERM_CLIP, order=(0, 1, 2, 3), scheme="ntu", **fit) -> StepOpts:
+def step_opts(precision="f64", fix_mode=FIX_HERM_CLIP, order=(0, 1, 2, 3), scheme="ntu", graph=False,
+              **fit) -> StepOpts:
     o = StepOpts()
     load().ntu_step_opts_default(ctypes.byref(o))
     o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+    o.graph = int(graph)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.fix_mode = fix_mode
     o.n_bonds = len(order)
@@ -120,20 +132,30 @@ def step_opts(precision="f64", fix_mode=FIX_HERM_CLIP, order=(0, 1, 2, 3), schem
     return o
 
 
-def _ptr(t):
+_DTYPES = {torch.float64: F64, torch.complex128: C128, torch.complex64: C64}
+
+
+def tensor(t):
+    """Descriptor of a torch tensor (None -> NULL).  Marshalling only: the
+    library checks the element type, shape, strides and memory kind."""
     if t is None:
         return None
     if not isinstance(t, torch.Tensor):
         raise TypeError("expected a torch tensor")
-    if not t.is_cuda:
-        raise ValueError("libntu operates on GPU tensors only")
-    if not t.is_contiguous():
-        raise ValueError("tensor must be contiguous")
-    return ctypes.c_void_p(t.data_ptr())
+    if t.dim() > MAX_DIMS:
+        raise ValueError(f"at most {MAX_DIMS} dimensions")
+    d = Tensor()
+    d.data = t.data_ptr()
+    d.dtype = _DTYPES.get(t.dtype, -1)
+    d.ndim = t.dim()
+    for i, (n, st) in enumerate(zip(t.shape, t.stride())):
+        d.shape[i], d.stride[i] = n, st
+    return d
 
 
-def _dtype_code(t):
-    return {torch.float64: F64, torch.complex128: C128, torch.complex64: C64}[t.dtype]
+def _ref(t):
+    d = tensor(t)
+    return None if d is None else ctypes.byref(d)
 
 
 class Context:
@@ -191,7 +213,7 @@ def ntu_gate_split(ctx: Context, gate: torch.Tensor):
     GA, GB = ctx.empty(b, d, d, r), ctx.empty(b, d, d, r)
     sig = ctx.empty(b, d * d, dtype=torch.float64)
     ctx.bind_stream()
-    ctx.check(ctx.L.ntu_gate_split(ctx.h, b, _ptr(gate), _ptr(GA), _ptr(GB), _ptr(sig)), "ntu_gate_split")
+    ctx.check(ctx.L.ntu_gate_split(ctx.h, b, _ref(gate), _ref(GA), _ref(GB), _ref(sig)), "ntu_gate_split")
     return GA, GB, sig
 
 
@@ -201,9 +223,15 @@ def ntu_reduce_qr(ctx: Context, site: torch.Tensor, gate_factor: torch.Tensor, s
     Rd = D * ctx.r_g
     Q, R = ctx.empty(b, ctx.p * D ** 3, Rd), ctx.empty(b, Rd, Rd)
     ctx.bind_stream()
-    ctx.check(ctx.L.ntu_reduce_qr(ctx.h, b, D, _ptr(site), _dtype_code(site), _ptr(gate_factor), side, _ptr(Q),
-                                  _ptr(R)), "ntu_reduce_qr")
+    ctx.check(ctx.L.ntu_reduce_qr(ctx.h, b, _ref(site), _ref(gate_factor), side, _ref(Q), _ref(R)),
+              "ntu_reduce_qr")
     return Q, R
+
+
+def _nbr_array(nbr):
+    if len(nbr) != 6:
+        raise ValueError("six neighbour tensors expected")
+    return (Tensor * 6)(*[tensor(t) for t in nbr])
 
 
 def ntu_env_contract(ctx: Context, QX, QY, nbr, precision="f64", D=None):
@@ -213,10 +241,10 @@ def ntu_env_contract(ctx: Context, QX, QY, nbr, precision="f64", D=None):
         D = nbr[0].shape[2]
     Rd = D * ctx.r_g
     g = ctx.empty(b, Rd * Rd, Rd * Rd)
-    arr = (ctypes.c_void_p * 6)(*[_ptr(t) for t in nbr])
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     ctx.bind_stream()
-    ctx.check(ctx.L.ntu_env_contract(ctx.h, b, D, _ptr(QX), _ptr(QY), arr, prec, _ptr(g)), "ntu_env_contract")
+    ctx.check(ctx.L.ntu_env_contract(ctx.h, b, _ref(QX), _ref(QY), _nbr_array(nbr), prec, _ref(g)),
+              "ntu_env_contract")
     return g
 
 
@@ -228,12 +256,11 @@ def ntu_tune_env(ctx: Context, QX, QY, nbr, precision="bf16x6", D=None, reps=3):
         D = nbr[0].shape[2]
     Rd = D * ctx.r_g
     g = ctx.empty(b, Rd * Rd, Rd * Rd)
-    arr = (ctypes.c_void_p * 6)(*[_ptr(t) for t in nbr])
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     ks, ms = ctypes.c_int(0), ctypes.c_float(0.0)
     ctx.bind_stream()
-    ctx.check(ctx.L.ntu_tune_env(ctx.h, b, D, prec, _ptr(QX), _ptr(QY), arr, _ptr(g), reps, ctypes.byref(ks),
-                                 ctypes.byref(ms)), "ntu_tune_env")
+    ctx.check(ctx.L.ntu_tune_env(ctx.h, b, prec, _ref(QX), _ref(QY), _nbr_array(nbr), _ref(g), reps,
+                                 ctypes.byref(ks), ctypes.byref(ms)), "ntu_tune_env")
     return ks.value, ms.value
 
 
@@ -255,12 +282,12 @@ def ntu_tune_load(ctx: Context, path):
     ctx.check(ctx.L.ntu_tune_load(ctx.h, str(path).encode()), "ntu_tune_load")
 
 
-def ntu_metric_fix(ctx: Context, g: torch.Tensor, D: int, mode=FIX_HERM_CLIP):
-    """In place on g; returns stats (batch, 8)."""
+def ntu_metric_fix(ctx: Context, g: torch.Tensor, D: int | None = None, mode=FIX_HERM_CLIP):
+    """In place on g (batch, n, n); returns stats (batch, 8)."""
     b = g.shape[0]
     stats = ctx.zeros(b, 8, dtype=torch.float64)
     ctx.bind_stream()
-    ctx.check(ctx.L.ntu_metric_fix(ctx.h, b, D, _ptr(g), mode, _ptr(stats)), "ntu_metric_fix")
+    ctx.check(ctx.L.ntu_metric_fix(ctx.h, b, _ref(g), mode, _ref(stats)), "ntu_metric_fix")
     return stats
 
 
@@ -276,8 +303,8 @@ def ntu_bond_fit(ctx: Context, g, RX, RY, D, opts: FitOpts | None = None):
     MX, MY = ctx.empty(b, Rd, D), ctx.empty(b, Rd, D)
     stats = ctx.zeros(b, fit_stats_len(opts.n_iter, D), dtype=torch.float64)
     ctx.bind_stream()
-    ctx.check(ctx.L.ntu_bond_fit(ctx.h, b, D, _ptr(g), _ptr(RX), _ptr(RY), ctypes.byref(opts), _ptr(MX), _ptr(MY),
-                                 _ptr(stats)), "ntu_bond_fit")
+    ctx.check(ctx.L.ntu_bond_fit(ctx.h, b, _ref(g), _ref(RX), _ref(RY), ctypes.byref(opts), _ref(MX), _ref(MY),
+                                 _ref(stats)), "ntu_bond_fit")
     return MX, MY, stats
 
 
@@ -285,7 +312,7 @@ def ntu_recombine(ctx: Context, QX, QY, MX, MY, D):
     b = QX.shape[0]
     Xn, Yn = ctx.empty(b, ctx.p, D, D, D, D), ctx.empty(b, ctx.p, D, D, D, D)
     ctx.bind_stream()
-    ctx.check(ctx.L.ntu_recombine(ctx.h, b, D, _ptr(QX), _ptr(QY), _ptr(MX), _ptr(MY), _ptr(Xn), _ptr(Yn)),
+    ctx.check(ctx.L.ntu_recombine(ctx.h, b, _ref(QX), _ref(QY), _ref(MX), _ref(MY), _ref(Xn), _ref(Yn)),
               "ntu_recombine")
     return Xn, Yn
 
@@ -295,14 +322,19 @@ def step_stats_len(n_iter, D):
 
 
 def ntu_trotter_step(ctx: Context, A, B, gate_factors, opts: StepOpts | None = None, stats=True):
-    """In place on A, B (batch, p, D, D, D, D); gate_factors (batch, 4, 2, d, d, r_g).
-    Returns stats (batch, n_bonds, step_stats_len) or None."""
+    """In place on A, B (batch, p, D, D, D, D), compute type or complex64
+    storage; gate_factors (batch, 4, 2, d, d, r_g).  Returns stats
+    (batch, n_bonds, step_stats_len), a caller's stats tensor when one is
+    given, or None."""
     opts = opts or step_opts()
     b, D = A.shape[0], A.shape[2]
-    st = ctx.zeros(b, opts.n_bonds, step_stats_len(opts.fit.n_iter, D), dtype=torch.float64) if stats else None
+    if isinstance(stats, torch.Tensor):
+        st = stats
+    else:
+        st = ctx.zeros(b, opts.n_bonds, step_stats_len(opts.fit.n_iter, D), dtype=torch.float64) if stats else None
     ctx.bind_stream()
-    ctx.check(ctx.L.ntu_trotter_step(ctx.h, b, D, _ptr(A), _ptr(B), _ptr(gate_factors), ctypes.byref(opts),
-                                     _ptr(st)), "ntu_trotter_step")
+    ctx.check(ctx.L.ntu_trotter_step(ctx.h, b, _ref(A), _ref(B), _ref(gate_factors), ctypes.byref(opts), _ref(st)),
+              "ntu_trotter_step")
     return st
 
 

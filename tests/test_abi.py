@@ -54,4 +54,37 @@ def test_host_only_defaults(lib):
     assert b"gfx950" in lib.ntu_version()
     # invalid arguments are rejected on the host before any launch
     lib.ntu_reduce_qr.restype = ctypes.c_int
-    assert lib.ntu_reduce_qr(None, 1, 2, None, 0, None, 0, None, None) == -1
+    assert lib.ntu_reduce_qr(None, 1, None, None, 0, None, None) == -1
+    lib.ntu_trotter_step.restype = ctypes.c_int
+    assert lib.ntu_trotter_step(None, 1, None, None, None, None, None) == -1
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structures have the C layout of ntu_tensor,
+    ntu_fit_opts and ntu_step_opts (offsets printed by a program compiled
+    against the header with the host C compiler)."""
+    import shutil
+    import subprocess
+    from paper_2107_06635_amd import ntu
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    fields = {"ntu_tensor": (ntu.Tensor, ["data", "dtype", "ndim", "shape", "stride"]),
+              "ntu_fit_opts": (ntu.FitOpts, ["n_iter", "early_stop", "conv_tol", "kappa", "n_tol", "tol", "tie"]),
+              "ntu_step_opts": (ntu.StepOpts, ["n_bonds", "order", "precision", "fix_mode", "fit", "scheme",
+                                               "graph"])}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "ntu.h"', "int main(void) {"]
+    for st, (_, names) in fields.items():
+        src.append(f'  printf("{st} size %zu\\n", sizeof({st}));')
+        for f in names:
+            src.append(f'  printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    src.append("  return 0;\n}")
+    (tmp_path / "layout.c").write_text("\n".join(src))
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(tmp_path / "layout.c"), "-o",
+                    str(tmp_path / "layout")], check=True)
+    out = subprocess.run([str(tmp_path / "layout")], check=True, capture_output=True, text=True).stdout
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+    for st, (cls, names) in fields.items():
+        assert got[(st, "size")] == ctypes.sizeof(cls), st
+        for f in names:
+            assert got[(st, f)] == getattr(cls, f).offset, (st, f)

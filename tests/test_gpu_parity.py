@@ -36,47 +36,147 @@ def _case(seed, D, p=2, real=False, dt=0.05, hx=3.0):
 
 def test_empty_batch_and_argument_errors():
     """C ABI edge cases: batch 0 is a no-op on every compute call (NULL
-    buffers allowed); sizes outside the context, bad enums and NULL buffers
-    give their status codes and a message, before any launch; FP16x3 reports
-    itself unsupported."""
+    descriptors allowed); sizes outside the context, bad enums and NULL
+    buffers give their status codes and a message, before any launch."""
     import ctypes
     ctx = _ctx(max_D=3, max_batch=2)
     L, h = ctx.L, ctx.h
     NULL = None
-    nbr0 = (ctypes.c_void_p * 6)()
+    nbr0 = (ntu.Tensor * 6)()
     fo = ntu.fit_opts(n_iter=3)
     so = ntu.step_opts("f64", n_iter=3)
-    OK, ARG, SHAPE, WS, UNSUP = 0, -1, -2, -6, -7
+    OK, ARG, SHAPE, WS = 0, -1, -2, -6
     ctx.bind_stream()
     assert L.ntu_gate_split(h, 0, NULL, NULL, NULL, NULL) == OK
-    assert L.ntu_reduce_qr(h, 0, 3, NULL, 1, NULL, 0, NULL, NULL) == OK
-    assert L.ntu_env_contract(h, 0, 3, NULL, NULL, nbr0, 3, NULL) == OK
-    assert L.ntu_metric_fix(h, 0, 3, NULL, 1, NULL) == OK
-    assert L.ntu_bond_fit(h, 0, 3, NULL, NULL, NULL, ctypes.byref(fo), NULL, NULL, NULL) == OK
-    assert L.ntu_recombine(h, 0, 3, NULL, NULL, NULL, NULL, NULL, NULL) == OK
-    assert L.ntu_trotter_step(h, 0, 3, NULL, NULL, NULL, ctypes.byref(so), NULL) == OK
+    assert L.ntu_reduce_qr(h, 0, NULL, NULL, 0, NULL, NULL) == OK
+    assert L.ntu_env_contract(h, 0, NULL, NULL, nbr0, 3, NULL) == OK
+    assert L.ntu_metric_fix(h, 0, NULL, 1, NULL) == OK
+    assert L.ntu_bond_fit(h, 0, NULL, NULL, NULL, ctypes.byref(fo), NULL, NULL, NULL) == OK
+    assert L.ntu_recombine(h, 0, NULL, NULL, NULL, NULL, NULL, NULL) == OK
+    assert L.ntu_trotter_step(h, 0, NULL, NULL, NULL, ctypes.byref(so), NULL) == OK
     # sizes outside the context, negative batch, NULL buffers, bad enums
-    assert L.ntu_reduce_qr(h, 1, 4, NULL, 1, NULL, 0, NULL, NULL) == SHAPE
-    assert L.ntu_reduce_qr(h, 3, 3, NULL, 1, NULL, 0, NULL, NULL) == WS
-    assert L.ntu_reduce_qr(h, -1, 3, NULL, 1, NULL, 0, NULL, NULL) == ARG
-    assert L.ntu_reduce_qr(h, 1, 3, NULL, 1, NULL, 0, NULL, NULL) == ARG
+    site4 = ntu.tensor(torch.zeros(1, 2, 4, 4, 4, 4, dtype=torch.complex128, device=DEV))
+    assert L.ntu_reduce_qr(h, 1, ctypes.byref(site4), NULL, 0, NULL, NULL) == SHAPE
+    assert L.ntu_reduce_qr(h, 3, NULL, NULL, 0, NULL, NULL) == WS
+    assert L.ntu_reduce_qr(h, -1, NULL, NULL, 0, NULL, NULL) == ARG
+    assert L.ntu_reduce_qr(h, 1, NULL, NULL, 0, NULL, NULL) == SHAPE
     assert L.ntu_last_error(h).decode()
-    assert L.ntu_env_contract(h, 1, 3, NULL, NULL, nbr0, 9, NULL) == ARG
-    assert L.ntu_metric_fix(h, 1, 3, NULL, 7, NULL) == ARG
+    assert L.ntu_env_contract(h, 1, NULL, NULL, nbr0, 9, NULL) == ARG
+    assert L.ntu_metric_fix(h, 1, NULL, 7, NULL) == ARG
     bad = ntu.step_opts("f64", n_iter=3)
     bad.scheme = 5
-    assert L.ntu_trotter_step(h, 1, 3, NULL, NULL, NULL, ctypes.byref(bad), NULL) == ARG
+    assert L.ntu_trotter_step(h, 1, NULL, NULL, NULL, ctypes.byref(bad), NULL) == ARG
     bad = ntu.step_opts("f64", n_iter=3)
     bad.n_bonds = 9
-    assert L.ntu_trotter_step(h, 1, 3, NULL, NULL, NULL, ctypes.byref(bad), NULL) == ARG
-    # FP16x3 is declared but not available: a clear status, not wrong numbers
-    X, Y, nbr, G, GA, GB = _case(320, 3)
+    assert L.ntu_trotter_step(h, 1, NULL, NULL, NULL, ctypes.byref(bad), NULL) == ARG
+    torch.cuda.synchronize()
+
+
+def test_descriptor_errors_before_launch():
+    """Every operand's descriptor is checked on the host before anything is
+    launched: wrong element type (NTU_ERR_DTYPE), wrong extent, rank or a
+    strided view (NTU_ERR_SHAPE), host memory or a NULL data pointer
+    (NTU_ERR_ARG).  Complex64 site tensors pass where the header allows them
+    and are refused elsewhere.  After each refusal the buffers are
+    untouched and a correct call still works."""
+    D, b = 3, 2
+    ctx = _ctx(max_D=D, max_batch=b)
+    X, Y, nbr, G, GA, GB = _case(330, D)
+    A = batched([X, Y])
+    B = batched([Y, X])
+    gf = to_dev(np.stack([gate_factors_array({bb: (GA, GB) for bb in O.BONDS})] * b))
+    opts = ntu.step_opts("f64", n_iter=3)
+    A0, B0 = A.clone(), B.clone()
+
+    def step_status(a, bb, g=gf, st=None):
+        import ctypes
+        ctx.bind_stream()
+        return ctx.L.ntu_trotter_step(ctx.h, b, ntu._ref(a), ntu._ref(bb), ntu._ref(g), ctypes.byref(opts),
+                                      ntu._ref(st))
+
+    DTYPE, SHAPE, ARG = -3, -2, -1
+    # element types: real site tensors in a complex context; gate factors in complex64
+    assert step_status(A.real.contiguous(), B.real.contiguous()) == DTYPE
+    assert b"element type" in ctx.L.ntu_last_error(ctx.h)
+    assert step_status(A, B, gf.to(torch.complex64)) == DTYPE
+    # A and B of different element types
+    assert step_status(A, B.to(torch.complex64)) == DTYPE
+    # extents: D mismatch between A and B, a short batch, a wrong gate rank
+    assert step_status(A, B[:, :, :, :, :, :2].contiguous()) == SHAPE
+    assert step_status(A[:1], B[:1]) == SHAPE
+    assert step_status(A, B, gf[..., :1].contiguous()) == SHAPE
+    # a strided (transposed) view of the right shape
+    At = A.transpose(3, 4)
+    assert not At.is_contiguous()
+    assert step_status(At, B) == SHAPE
+    assert b"dense row-major" in ctx.L.ntu_last_error(ctx.h)
+    # stats of the wrong length
+    assert step_status(A, B, st=torch.zeros(b, 4, 5, dtype=torch.float64, device=DEV)) == SHAPE
+    # host memory
+    assert step_status(A.cpu(), B) == ARG
+    assert b"device memory" in ctx.L.ntu_last_error(ctx.h)
+    torch.cuda.synchronize()
+    assert torch.equal(A, A0) and torch.equal(B, B0)
+    # the other entry points check theirs too
     QX, _ = O.reduce_site(X, GA, 'X', 2)
     QY, _ = O.reduce_site(Y, GB, 'Y', 2)
-    q = lambda Q: batched([Q.reshape(-1, 6)])
-    with pytest.raises(RuntimeError, match="not available"):
-        ntu.ntu_env_contract(ctx, q(QX), q(QY), [batched([t]) for t in nbr], "fp16x3")
+    R = 2 * D
+    q = batched([QX.reshape(-1, R)] * b)
+    nb = [batched([t, t]) for t in nbr]
+    with pytest.raises(RuntimeError, match=r"\(-2\).*QY: shape"):
+        ntu.ntu_env_contract(ctx, q, q[:, :, :4].contiguous(), nb)
+    with pytest.raises(RuntimeError, match=r"\(-3\).*nbr\[2\]"):
+        ntu.ntu_env_contract(ctx, q, q, nb[:2] + [nb[2].to(torch.complex64)] + nb[3:])
+    with pytest.raises(RuntimeError, match=r"\(-2\).*site"):
+        ntu.ntu_reduce_qr(ctx, A.transpose(2, 3), batched([GA, GA]), 0)
+    g = ntu.ntu_env_contract(ctx, q, q, nb)
+    with pytest.raises(RuntimeError, match=r"\(-2\)"):
+        ntu.ntu_metric_fix(ctx, g[:, :, :30].contiguous())
+    with pytest.raises(RuntimeError, match=r"\(-3\).*RX"):
+        ntu.ntu_bond_fit(ctx, g, batched([np.eye(R)] * b, torch.complex64), batched([np.eye(R)] * b), D)
+    # complex64 site tensors are accepted by the reduction (read with an upcast)
+    Q64, R64 = ntu.ntu_reduce_qr(ctx, A.to(torch.complex64), batched([GA, GA]), 0)
+    Qo, Ro = O.reduce_site(X.astype(np.complex64).astype(np.complex128), GA, 'X', 2)
+    assert rel(to_np(R64)[0], Ro) < 1e-12
+    # and a correct step still runs
+    assert step_status(A, B) == 0
     torch.cuda.synchronize()
+
+
+def test_complex64_storage_trotter_step():
+    """Complex64 storage of A and B in the Trotter step (configuration 4's
+    storage): the step widens them, runs in complex128 and stores the result
+    rounded to complex64.  Against the oracle run on the same (widened)
+    values: after one H1 update the pair contracted over that bond (gauge
+    invariant) within the rounding of complex64 (relative 1e-6); after an
+    H1, V1 sweep the cluster energy and <X> within 1e-7; the errors of every
+    update at 1e-9."""
+    D = 3
+    rng = np.random.default_rng(41)
+    X, Y = inputs.random_site_pair(rng, 2, D, np.complex64)
+    G = inputs.bond_gate(inputs.ising_bond_hamiltonian(3.1), 0.01)
+    GA, GB, _ = O.gate_split(G, 2, 2)
+    pairs = {bb: (GA, GB) for bb in O.BONDS}
+    gf = to_dev(gate_factors_array(pairs)[None])
+    ctx = _ctx(max_D=D)
+    pair = lambda a, b: np.einsum('ptlbk,qTkBR->ptlbqTBR', a, b).reshape(-1)
+    for names, codes in ((('H1',), (0,)), (('H1', 'V1'), (0, 2))):
+        Ao, Bo, infos = O.trotter_step(X.astype(np.complex128), Y.astype(np.complex128), pairs, D, n_iter=4,
+                                       order=names)
+        At, Bt = to_dev(X[None]), to_dev(Y[None])
+        assert At.dtype == torch.complex64
+        st = to_np(ntu.ntu_trotter_step(ctx, At, Bt, gf, ntu.step_opts("f64", order=codes, n_iter=4)))[0]
+        assert At.dtype == torch.complex64 and Bt.dtype == torch.complex64
+        An, Bn = to_np(At)[0].astype(np.complex128), to_np(Bt)[0].astype(np.complex128)
+        if names == ('H1',):
+            assert rel(pair(An, Bn), pair(Ao, Bo)) < 1e-6
+        else:
+            eo, xo = O.observables(Ao, Bo, 3.1)
+            eg, xg = O.observables(An, Bn, 3.1)
+            assert abs(eg - eo) < 1e-7 and abs(xg - xo) < 1e-7, (eg - eo, xg - xo)
+        for bi, bb in enumerate(names):
+            f = fit_stat_fields(st[bi, 8:], 4, D)
+            assert abs(f['delta'] - infos[bb]['delta']) <= 1e-9 * infos[bb]['delta'] + 1e-14
 
 
 # ------------------------------------------------------------------ gate split
@@ -167,7 +267,7 @@ def test_env_contract_f64(D, p, real):
         assert rel(g[i], go) < 1e-12
 
 
-@pytest.mark.parametrize("prec,tol", [("bf16x3", 3e-5), ("bf16x6", 1e-6)])
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 3e-5), ("fp16x3", 1e-6), ("bf16x6", 1e-6)])
 @pytest.mark.parametrize("D,p,real", [(3, 2, False), (5, 2, False), (5, 4, False), (4, 4, True),
                                       (6, 2, False), (7, 2, False), (8, 2, False), (9, 2, False),
                                       (10, 2, False), (8, 4, True)])
@@ -177,14 +277,24 @@ def test_env_contract_mixed(prec, tol, D, p, real):
     the fused kernels (D = 5, p = 4: contraction index p D = 20 spans two
     MFMA K steps of the Left/Right blocks; D = 6, 7: D^2 = 36, 49 padded to
     the next multiple of 16; D = 8: no padding); complex D = 9, 10 and every
-    real case take the tiled products for Left, Right, L1 and L2."""
+    real case take the tiled products for Left, Right, L1 and L2.
+
+    FP16x3 (float16 pieces hi + 2^-11 lo, 22 bits, every operand block scaled
+    by a power of two, the final assembly from pre-split rows) exists on the
+    fused path only: elsewhere the call reports NTU_ERR_UNSUPPORTED.  Its
+    budget: 2^-22 per operand value against 2^-24 for BF16x6, the same FP32
+    accumulation; asserted at the 1e-6 target."""
     X, Y, nbr, G, GA, GB = _case(300 + D, D, p, real)
     QX, _ = O.reduce_site(X, GA, 'X', 2)
     QY, _ = O.reduce_site(Y, GB, 'Y', 2)
-    go = O.metric(QX, QY, nbr)
     R = D * 2
     ctx = _ctx(cplx=not real, d_anc=p // 2, max_D=max(D, 6), max_batch=1)
     q = lambda Q: batched([Q.reshape(-1, R)])
+    if prec == "fp16x3" and (real or D > 8):
+        with pytest.raises(RuntimeError, match=r"\(-7\)"):
+            ntu.ntu_env_contract(ctx, q(QX), q(QY), [batched([t]) for t in nbr], prec)
+        return
+    go = O.metric(QX, QY, nbr)
     g = to_np(ntu.ntu_env_contract(ctx, q(QX), q(QY), [batched([t]) for t in nbr], prec))[0]
     err = rel(g, go)
     print(f"{prec} D={D} p={p} real={real}: metric rel err {err:.3e}")
@@ -223,6 +333,12 @@ def test_env_tuning(tmp_path):
     assert ntu.ntu_get_env_ksplit(fresh, D, "bf16x6") == 3 and ntu.ntu_get_env_ksplit(fresh, 4, "bf16x3") == 2
     with pytest.raises(RuntimeError):
         ntu.ntu_tune_env(ctx, q(QX), q(QY), nb, "f64", D=D)
+    # FP16x3 tunes the same launch parameter
+    ks, ms = ntu.ntu_tune_env(ctx, q(QX), q(QY), nb, "fp16x3", D=D)
+    assert ks >= 1 and ntu.ntu_get_env_ksplit(ctx, D, "fp16x3") == ks
+    g = to_np(ntu.ntu_env_contract(ctx, q(QX), q(QY), nb, "fp16x3"))
+    for i in range(2):
+        assert rel(g[i], go) < 1e-6, i
 
 
 # ------------------------------------------------------------------ metric fix
