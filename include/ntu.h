@@ -358,6 +358,29 @@ ntu_status ntu_profile_enable(ntu_ctx* ctx, int on);
 int ntu_profile_read(ntu_ctx* ctx, double* ms, int* count, int n);
 const char* ntu_profile_kind_name(int kind);
 
+/*
+ * Metric repair without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same operation and kernels as ntu_metric_fix, with
+ * no context.  Its scratch space is a device array of
+ * NTU_NOALLOC_SCRATCH_BYTES held by the library on every GPU it runs on
+ * until the process ends; the call itself allocates nothing.
+ * stream: a hipStream_t of the current device (NULL: the null stream).
+ * g: (batch, n, n) in place, NTU_F64 or NTU_C128 (which selects real or
+ * complex arithmetic), n <= 1024, on the current device.
+ * stats (may be NULL): (batch, 8) NTU_F64, written as by ntu_metric_fix.
+ * The scratch needed is about 2 n^2 elements of g's type per item (the
+ * eigen-solve's two matrices): 2 MiB per complex item at n = 256, so up to
+ * 16 such items per call; larger requests return NTU_ERR_WORKSPACE before
+ * any launch.  Errors are described by ntu_last_error(NULL).
+ * Every call on one GPU uses that GPU's one scratch array: calls that
+ * overlap on a GPU (different streams or threads without ordering between
+ * them) race and give wrong results.  Nothing in the scratch needs to start
+ * at zero; it keeps the last call's contents.
+ */
+#define NTU_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+ntu_status ntu_metric_fix_noalloc(void* stream, int batch, ntu_tensor* g, int mode, ntu_tensor* stats);
+
 #ifdef __cplusplus
 }
 #endif

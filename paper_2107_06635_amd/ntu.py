@@ -33,6 +33,7 @@ EXPORTED = (
     "ntu_fit_opts_default", "ntu_bond_fit", "ntu_recombine", "ntu_step_opts_default", "ntu_trotter_step",
     "ntu_profile_enable", "ntu_profile_read", "ntu_profile_kind_name",
     "ntu_tune_env", "ntu_set_env_ksplit", "ntu_get_env_ksplit", "ntu_tune_save", "ntu_tune_load",
+    "ntu_metric_fix_noalloc",
 )
 
 
@@ -98,6 +99,7 @@ def load():
     L.ntu_profile_read.argtypes = [vp, dp, ctypes.POINTER(i32), i32]
     L.ntu_profile_kind_name.argtypes = [i32]
     L.ntu_profile_kind_name.restype = ctypes.c_char_p
+    L.ntu_metric_fix_noalloc.argtypes = [vp, i32, tp, i32, tp]
     for name in EXPORTED:
         if name not in ("ntu_last_error", "ntu_workspace_bytes", "ntu_version", "ntu_fit_opts_default",
                         "ntu_step_opts_default", "ntu_profile_kind_name"):
@@ -336,6 +338,18 @@ def ntu_trotter_step(ctx: Context, A, B, gate_factors, opts: StepOpts | None = N
     ctx.check(ctx.L.ntu_trotter_step(ctx.h, b, _ref(A), _ref(B), _ref(gate_factors), ctypes.byref(opts), _ref(st)),
               "ntu_trotter_step")
     return st
+
+
+def ntu_metric_fix_noalloc(g: torch.Tensor, mode=FIX_HERM_CLIP, stats=None):
+    """Metric repair without a context or allocation by the library, in
+    place on g (batch, n, n) on the current device and torch stream; stats: a
+    (batch, 8) float64 tensor or None."""
+    L = load()
+    s = torch.cuda.current_stream(g.device).cuda_stream
+    st = L.ntu_metric_fix_noalloc(ctypes.c_void_p(s), g.shape[0], _ref(g), mode, _ref(stats))
+    if st != NTU_OK:
+        raise RuntimeError(f"ntu_metric_fix_noalloc failed ({st}): {L.ntu_last_error(None).decode()}")
+    return stats
 
 
 def ntu_profile_enable(ctx: Context, on=True):
