@@ -383,7 +383,7 @@ def measure(job, args, ntu, torch, dev, opts, opts64, K, W, tune=True):
     r = Runner(job, args, ntu, torch, dev)
     r.warm(opts64, W)
     out = {}
-    if tune and args.precision in ("bf16x3", "bf16x6") and not args.no_tune and args.scheme == "ntu":
+    if tune and args.precision in ("bf16x3", "bf16x6", "fp16x3") and not args.no_tune and args.scheme == "ntu":
         out["tuning"] = r.tune(args.precision)
     # one untimed step of the measured path, so that no kernel of it is
     # launched for the first time inside the timed region

@@ -267,41 +267,48 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
     brow[u] = ok ? Bb + idx_off(d.Bj, jrow) * CW : nullptr;
   }
   // two register sets of operand values: the loads of step s + 2 are in
-  // flight while step s runs and step s + 1's values are split and stored
+  // flight while step s runs and step s + 1's values are split and stored.
+  // The loads are unconditional (a missing row reads the item's first row, a
+  // value beyond the chunk the chunk's first column, always in bounds) and
+  // the values that do not exist are zeroed when stored: loads under a
+  // branch would each wait for their data at the join.
   float ra0[NGA][4], rb0[NGB][4], ra1[NGA][4], rb1[NGB][4];
-  auto gload = [&](int k0, float (&ra)[NGA][4], float (&rb)[NGB][4]) {
+  unsigned oka0[NGA], okb0[NGB], oka1[NGA], okb1[NGB];  // bit e: value e exists
+  auto ld4 = [&](const auto* row, const auto* base, int k, float (&r)[4], unsigned& ok) {
+    const auto* p = row ? row : base;
+    ok = 0u;
+    if constexpr (VEC == 2) {
+      const bool o0 = row && k < kend, o1 = row && k + 2 < kend;
+      load_pair<2>(p + (o0 ? k : kbeg), &r[0]);
+      load_pair<2>(p + (o1 ? k + 2 : kbeg), &r[2]);
+      ok = (o0 ? 3u : 0u) | (o1 ? 12u : 0u);
+    } else {
 #pragma unroll
-    for (int u = 0; u < NGA; ++u) {
-      const int k = k0 + akq[u];
-      ra[u][0] = ra[u][1] = ra[u][2] = ra[u][3] = 0.0f;
-      if (arow[u]) {
-        if constexpr (VEC == 2) {
-          if (k < kend) load_pair<2, TA>(arow[u] + k, &ra[u][0]);
-          if (k + 2 < kend) load_pair<2, TA>(arow[u] + k + 2, &ra[u][2]);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (k + e < kend) ra[u][e] = (float)arow[u][k + e];
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < NGB; ++u) {
-      const int k = k0 + bkq[u];
-      rb[u][0] = rb[u][1] = rb[u][2] = rb[u][3] = 0.0f;
-      if (brow[u]) {
-        if constexpr (VEC == 2) {
-          if (k < kend) load_pair<2, TB>(brow[u] + k, &rb[u][0]);
-          if (k + 2 < kend) load_pair<2, TB>(brow[u] + k + 2, &rb[u][2]);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (k + e < kend) rb[u][e] = (float)brow[u][k + e];
-        }
+      for (int e = 0; e < 4; ++e) {
+        const bool o = row && k + e < kend;
+        r[e] = (float)p[o ? k + e : kbeg];
+        ok |= o ? (1u << e) : 0u;
       }
     }
   };
-  auto lstore = [&](int buf, const float (&ra)[NGA][4], const float (&rb)[NGB][4]) {
+  auto gload = [&](int k0, float (&ra)[NGA][4], float (&rb)[NGB][4], unsigned (&oka)[NGA], unsigned (&okb)[NGB]) {
+#pragma unroll
+    for (int u = 0; u < NGA; ++u) ld4(arow[u], Ab, k0 + akq[u], ra[u], oka[u]);
+#pragma unroll
+    for (int u = 0; u < NGB; ++u) ld4(brow[u], Bb, k0 + bkq[u], rb[u], okb[u]);
+  };
+  // zero the values that do not exist (in a copy, at store time)
+  auto masked = [](const float (&r)[4], unsigned ok, float (&o)[4]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[e] = (ok >> e) & 1u ? r[e] : 0.0f;
+  };
+  auto lstore = [&](int buf, const float (&ra_in)[NGA][4], const float (&rb_in)[NGB][4], const unsigned (&oka)[NGA],
+                    const unsigned (&okb)[NGB]) {
+    float ra[NGA][4], rb[NGB][4];
+#pragma unroll
+    for (int u = 0; u < NGA; ++u) masked(ra_in[u], oka[u], ra[u]);
+#pragma unroll
+    for (int u = 0; u < NGB; ++u) masked(rb_in[u], okb[u], rb[u]);
     if constexpr (PREC != NTU_PREC_FP16X3) {
       // bfloat16 pieces of two values at once (one packed word per piece)
 #pragma unroll
@@ -395,21 +402,18 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
 #pragma unroll
       for (int y = 0; y < TL_WY; ++y) acc[c][x][y] = f32x4{0, 0, 0, 0};
 
-  const int nsteps = (kend - kbeg + TL_K - 1) / TL_K;
-  gload(kbeg, ra0, rb0);
-  lstore(0, ra0, rb0);
-  if (nsteps > 1) gload(kbeg + TL_K, ra1, rb1);
+  // an even number of steps, every load and store unconditional (see above):
+  // a step beyond the chunk adds zero products
+  const int nsteps = (((kend - kbeg + TL_K - 1) / TL_K) + 1) & ~1;
+  gload(kbeg, ra0, rb0, oka0, okb0);
+  lstore(0, ra0, rb0, oka0, okb0);
+  gload(kbeg + TL_K, ra1, rb1, oka1, okb1);
   __syncthreads();
   const int fr = lane & 15, fk = (lane >> 4) * 8;
   // the 16-byte chunk this lane reads from each of its rows (tile rows are
   // multiples of 16 plus fr, so the permutation depends on fr alone)
   const int fks = tl_col(fr, fk);
-  // step s: set (xa, xb) is free (its values are stored) and takes the loads
-  // of step s + 2; set (ya, yb) holds step s + 1, stored after the products
-  auto step = [&](int s, float (&xa)[NGA][4], float (&xb)[NGB][4], const float (&ya)[NGA][4],
-                  const float (&yb)[NGB][4]) {
-    const int buf = s & 1;
-    if (s + 2 < nsteps) gload(kbeg + (s + 2) * TL_K, xa, xb);
+  auto products = [&](int buf) {
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
       const int ra_ = wm * 64 + x * 16 + fr;
@@ -432,12 +436,16 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile(const TA* __restrict__
         }
       }
     }
-    if (s + 1 < nsteps) lstore(buf ^ 1, ya, yb);
-    __syncthreads();
   };
   for (int s = 0; s < nsteps; s += 2) {
-    step(s, ra0, rb0, ra1, rb1);
-    if (s + 1 < nsteps) step(s + 1, ra1, rb1, ra0, rb0);
+    gload(kbeg + (s + 2) * TL_K, ra0, rb0, oka0, okb0);
+    products(0);
+    lstore(1, ra1, rb1, oka1, okb1);
+    __syncthreads();
+    gload(kbeg + (s + 3) * TL_K, ra1, rb1, oka1, okb1);
+    products(1);
+    lstore(0, ra0, rb0, oka0, okb0);
+    __syncthreads();
   }
   // epilogue: lane holds column (lane & 15), rows 4 (lane >> 4) + v of each 16 x 16 tile
   const long long cbase = idx_off(d.Cb, item) * CW;
@@ -574,25 +582,41 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile_f16(const unsigned* __
   // registers: per group and piece, the two packed words (2 complex)
   uint2 ra0[NGA][NT], rb0[NGB][NT], ra1[NGA][NT], rb1[NGB][NT];
   // complex entries k / 2 and k / 2 + 1 (words k .. k + 3, each entry an
-  // 8-byte aligned (hi, lo) pair; rows of odd length K end after the first)
-  auto ld2 = [&](const unsigned* row, int k, uint2 (&r)[NT]) {
-    const uint2 z = make_uint2(0u, 0u);
-    const uint2 v0 = row && k < kend ? *(const uint2*)(row + k) : z;
-    const uint2 v1 = row && k + 2 < kend ? *(const uint2*)(row + k + 2) : z;
-    r[0] = make_uint2(v0.x, v1.x);
-    r[1] = make_uint2(v0.y, v1.y);
+  // 8-byte aligned (hi, lo) pair; rows of odd length K end after the first).
+  // The registers keep the loaded pairs as they are: regrouping them into
+  // (hi, hi), (lo, lo) here would make the load wait at once; lstore
+  // regroups, when the values are due.
+  // The loads are unconditional (a missing row or an entry beyond the chunk
+  // reads the row start or the first entry of the chunk instead, always in
+  // bounds) and the entries that do not exist are zeroed when stored:
+  // loads under a branch would each wait for their data at the join.
+  auto ld2 = [&](const unsigned* row, const unsigned* base, int k, uint2 (&r)[NT], unsigned& ok) {
+    const unsigned* p = row ? row : base;
+    const bool ok0 = row && k < kend, ok1 = row && k + 2 < kend;
+    r[0] = *(const uint2*)(p + (ok0 ? k : kbeg));
+    r[1] = *(const uint2*)(p + (ok1 ? k + 2 : kbeg));
+    ok = (ok0 ? 1u : 0u) | (ok1 ? 2u : 0u);
   };
-  auto gload = [&](int k0, uint2 (&ra)[NGA][NT], uint2 (&rb)[NGB][NT]) {
+  unsigned oka0[NGA], okb0[NGB], oka1[NGA], okb1[NGB];
+  auto gload = [&](int k0, uint2 (&ra)[NGA][NT], uint2 (&rb)[NGB][NT], unsigned (&oka)[NGA],
+                   unsigned (&okb)[NGB]) {
 #pragma unroll
-    for (int u = 0; u < NGA; ++u) ld2(arow[u], k0 + akq[u], ra[u]);
+    for (int u = 0; u < NGA; ++u) ld2(arow[u], Ab, k0 + akq[u], ra[u], oka[u]);
 #pragma unroll
-    for (int u = 0; u < NGB; ++u) ld2(brow[u], k0 + bkq[u], rb[u]);
+    for (int u = 0; u < NGB; ++u) ld2(brow[u], Bb, k0 + bkq[u], rb[u], okb[u]);
   };
-  auto lstore = [&](int buf, const uint2 (&ra)[NGA][NT], const uint2 (&rb)[NGB][NT]) {
+  // piece p of the two entries: (entry 0, entry 1) words of that piece, zero
+  // where the entry does not exist
+  auto piece = [](const uint2 (&r)[NT], int p, unsigned ok) {
+    const unsigned w0 = p == 0 ? r[0].x : r[0].y, w1 = p == 0 ? r[1].x : r[1].y;
+    return make_uint2((ok & 1u) ? w0 : 0u, (ok & 2u) ? w1 : 0u);
+  };
+  auto lstore = [&](int buf, const uint2 (&ra)[NGA][NT], const uint2 (&rb)[NGB][NT], const unsigned (&oka)[NGA],
+                    const unsigned (&okb)[NGB]) {
 #pragma unroll
     for (int u = 0; u < NGA; ++u)
 #pragma unroll
-      for (int p = 0; p < NT; ++p) *(uint2*)&sA[buf][p][arl[u]][tl_col(arl[u], akq[u])] = ra[u][p];
+      for (int p = 0; p < NT; ++p) *(uint2*)&sA[buf][p][arl[u]][tl_col(arl[u], akq[u])] = piece(ra[u], p, oka[u]);
 #pragma unroll
     for (int u = 0; u < NGB; ++u) {
       // complex values (re0, im0), (re1, im1) -> real rows 2r: (re, -im),
@@ -602,7 +626,7 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile_f16(const unsigned* __
       const int c0 = tl_col(r0, bkq[u]), c1 = tl_col(r1, bkq[u]);
 #pragma unroll
       for (int p = 0; p < NT; ++p) {
-        const uint2 w = rb[u][p];
+        const uint2 w = piece(rb[u], p, okb[u]);
         const uint2 neg = make_uint2(w.x ^ 0x80000000u, w.y ^ 0x80000000u);
         const uint2 swp = make_uint2((w.x >> 16) | (w.x << 16), (w.y >> 16) | (w.y << 16));
         *(uint2*)&sB[buf][p][r0][c0] = odd_first ? swp : neg;
@@ -619,17 +643,18 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile_f16(const unsigned* __
 #pragma unroll
       for (int y = 0; y < TL_WY; ++y) acc[c][x][y] = f32x4{0, 0, 0, 0};
 
-  const int nsteps = (kend - kbeg + TL_K - 1) / TL_K;
-  gload(kbeg, ra0, rb0);
-  lstore(0, ra0, rb0);
-  if (nsteps > 1) gload(kbeg + TL_K, ra1, rb1);
+  // An even number of steps, every load and store unconditional: a step
+  // beyond the chunk loads clamped addresses whose values are zeroed, and
+  // adds zero products.  Without branches around them, the loads of step
+  // s + 2 stay in flight while step s runs and step s + 1 is stored.
+  const int nsteps = (((kend - kbeg + TL_K - 1) / TL_K) + 1) & ~1;
+  gload(kbeg, ra0, rb0, oka0, okb0);
+  lstore(0, ra0, rb0, oka0, okb0);
+  gload(kbeg + TL_K, ra1, rb1, oka1, okb1);
   __syncthreads();
   const int fr = lane & 15, fk = (lane >> 4) * 8;
   const int fks = tl_col(fr, fk);
-  auto step = [&](int s, uint2 (&xa)[NGA][NT], uint2 (&xb)[NGB][NT], const uint2 (&ya)[NGA][NT],
-                  const uint2 (&yb)[NGB][NT]) {
-    const int buf = s & 1;
-    if (s + 2 < nsteps) gload(kbeg + (s + 2) * TL_K, xa, xb);
+  auto products = [&](int buf) {
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
       const int ra_ = wm * 64 + x * 16 + fr;
@@ -645,12 +670,16 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile_f16(const unsigned* __
         acc[1][x][y] = mfma<NTU_PREC_FP16X3>(a1, b0, acc[1][x][y]);
       }
     }
-    if (s + 1 < nsteps) lstore(buf ^ 1, ya, yb);
-    __syncthreads();
   };
   for (int s = 0; s < nsteps; s += 2) {
-    step(s, ra0, rb0, ra1, rb1);
-    if (s + 1 < nsteps) step(s + 1, ra1, rb1, ra0, rb0);
+    gload(kbeg + (s + 2) * TL_K, ra0, rb0, oka0, okb0);
+    products(0);
+    lstore(1, ra1, rb1, oka1, okb1);
+    __syncthreads();
+    gload(kbeg + (s + 3) * TL_K, ra1, rb1, oka1, okb1);
+    products(1);
+    lstore(0, ra0, rb0, oka0, okb0);
+    __syncthreads();
   }
   // epilogue: lane holds column (lane & 15), rows 4 (lane >> 4) + v of each 16 x 16 tile
   const float* sAi = ta.sA + (size_t)item * ta.M;
