@@ -19,6 +19,14 @@ every bucket back to back and joins them.  --bucket 0 makes this the headline.
 "thermal" (configuration 3): imaginary-time evolution of the D = 8 thermal
 purification (p = 4, real), one step = one Trotter sweep of 4 bond updates.
 
+"large" (configuration 5): the D = 10 quench state (h_x = 3.04438, dt =
+0.005); the whole Trotter sweep is captured once into a HIP graph by the
+library (step option graph = 1) and replayed K times (default 1000), on the
+split-precision and the FP64 path, each replay followed by a copy of its
+statistics into a log, from which the per-step truncation error eps / N of
+every bond is reported; the cluster energy of both paths is evaluated every
+100 steps (CPU leg).
+
 Prints ONE JSON line.
 """
 from __future__ import annotations
@@ -52,8 +60,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batched", choices=["batched", "thermal"])
-    ap.add_argument("--precision", default="bf16x6", choices=["bf16x3", "bf16x6", "fp16x3", "f64"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "thermal", "large"])
+    ap.add_argument("--precision", default=None, choices=["bf16x3", "bf16x6", "fp16x3", "f64"],
+                    help="environment precision (default: fp16x3 for the batched workload; bf16x6 for the "
+                         "others, whose real or D > 8 metrics take the tiled path FP16x3 does not cover)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--scheme", default="ntu", choices=["ntu", "svdu"],
                     help="bond-update scheme: full NTU, or the SVDU update (no environment; implies --no-fp64)")
@@ -76,7 +86,9 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (20 times) and print its "
                          "rate: the reference kernel for scaling HBM byte counters")
-    return ap.parse_args()
+    args = ap.parse_args()
+    args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
+    return args
 
 
 def copy_calibration(mib):
@@ -212,6 +224,65 @@ def thermal_job(ntu, torch, np, dev, inputs, D=8):
     job.order = (0, 1, 2, 3)
     job.bonds_per_item = 4
     return job
+
+
+def large_job(ntu, torch, np, dev, inputs, D=10):
+    w = inputs.workload_large(D=D)
+    ctx = ntu.Context(complex_=True, d=2, d_anc=1, r_g=2, max_D=D, max_batch=1)
+    ctx.bind_stream()
+    G = torch.from_numpy(np.ascontiguousarray(w["gates"][0][None])).to(dev)
+    GA, GB, _ = ntu.ntu_gate_split(ctx, G)
+    gf = torch.stack([torch.stack([GA[0], GB[0]])] * 4)[None].contiguous()
+    A = torch.from_numpy(w["A"][None]).to(dev).contiguous()
+    B = torch.from_numpy(w["B"][None]).to(dev).contiguous()
+    job = Job()
+    job.cplx, job.p, job.n_updates, job.w, job.label = True, 2, 4, w, "large"
+    job.buckets = [dict(D=D, A=A, B=B, gf=gf, n=1, ctx=ctx, stream=torch.cuda.Stream(device=dev))]
+    job.order = (0, 1, 2, 3)
+    job.bonds_per_item = 4
+    return job
+
+
+def run_large(job, args, ntu, torch, np, dev, K):
+    """Configuration 5: the captured step replayed K times on each path from
+    the seeded state; per-step statistics copied into a log after every
+    replay (inside the timed region).  Returns per path: ms per step, the
+    logged eps / N of every bond and step, and the states every 100 steps."""
+    bk = job.buckets[0]
+    ctx, D = bk["ctx"], bk["D"]
+    stream = bk["stream"]
+    fit = dict(n_iter=20, early_stop=True, conv_tol=1e-12)
+    out = {}
+    for path in (args.precision, "f64"):
+        o = ntu.step_opts(path, order=job.order, graph=True, **fit)
+        A, B = bk["A"].clone(), bk["B"].clone()
+        st = torch.zeros(1, 4, ntu.step_stats_len(20, D), dtype=torch.float64, device=dev)
+        log = torch.zeros(K, 4, dtype=torch.float64, device=dev)
+        nsnap = K // 100
+        snapA = torch.empty((nsnap,) + tuple(A.shape[1:]), dtype=A.dtype, device=dev)
+        snapB = torch.empty_like(snapA)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            # capture + first launch (untimed), then back to the seeded state
+            ntu.ntu_trotter_step(ctx, A, B, bk["gf"], o, stats=st)
+            A.copy_(bk["A"])
+            B.copy_(bk["B"])
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            ev0.record()
+            for k in range(K):
+                ntu.ntu_trotter_step(ctx, A, B, bk["gf"], o, stats=st)
+                log[k].copy_(st[0, :, 8 + 3])          # eps / N of the four bonds
+                if (k + 1) % 100 == 0:                 # the state every 100 steps (device copies)
+                    snapA[(k + 1) // 100 - 1].copy_(A[0])
+                    snapB[(k + 1) // 100 - 1].copy_(B[0])
+            ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        snaps = [(100 * (i + 1), snapA[i].cpu().numpy(), snapB[i].cpu().numpy()) for i in range(nsnap)]
+        out[path] = {"ms_per_step": ms / K, "log": log.cpu().numpy(), "snaps": snaps}
+    return out
 
 
 class Runner:
@@ -420,6 +491,42 @@ def metric_sample(job, ntu, torch, precision, n_items=2):
     return g64.cpu().numpy(), gmx.cpu().numpy()
 
 
+def main_large(args, ntu, torch, np, dev, inputs):
+    """Configuration 5 (see the module docstring)."""
+    K = args.steps if args.steps_given else 1000
+    job = large_job(ntu, torch, np, dev, inputs)
+    res = run_large(job, args, ntu, torch, np, dev, K)
+    mx, f64 = res[args.precision], res["f64"]
+    result = {
+        "metric": METRIC, "value": 4 / (mx["ms_per_step"] / 1e3), "unit": "bond_updates/s", "n_gpus": 1,
+        "steps": K, "warmup": 0, "ms_per_step": mx["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": f"{args.precision}+f64", "data": "synthetic",
+        "config": {"workload": "configuration 5: D=10 quench (h_x=3.04438, dt=0.005), 2-site unit cell, "
+                               "whole Trotter step captured in a HIP graph by the library and replayed",
+                   "D": 10, "replays": K, "env_precision": args.precision,
+                   "fit": "fp64, <=20 ALS iterations, early stop 1e-12 N", "bond_updates_per_step": 4,
+                   "start": "seeded random state", "logging": "eps/N of every bond copied after every replay"},
+        "fp64_path": {"value": 4 / (f64["ms_per_step"] / 1e3), "ms_per_step": f64["ms_per_step"]},
+        "speedup_vs_fp64_path": f64["ms_per_step"] / mx["ms_per_step"],
+        "truncation_error": {p: {"mean": float(r["log"].mean()), "max": float(r["log"].max()),
+                                 "final_step": [float(x) for x in r["log"][-1]]}
+                             for p, r in ((args.precision, mx), ("f64", f64))},
+    }
+    if not args.no_cpu:
+        from oracle import ntu as O
+        t0 = time.perf_counter()
+        drift = []
+        e0, _ = O.observables(job.w["A"], job.w["B"], inputs.H_CRIT)
+        for (k, A1, B1), (_, A2, B2) in zip(mx["snaps"], f64["snaps"]):
+            e1, x1 = O.observables(A1, B1, inputs.H_CRIT)
+            e2, x2 = O.observables(A2, B2, inputs.H_CRIT)
+            drift.append({"step": k, "energy": e2, "energy_split_minus_fp64": e1 - e2, "sx_split_minus_fp64": x1 - x2})
+        result["energy_drift"] = {"initial_energy": e0, "samples": drift,
+                                  "estimator": "cluster estimator of the oracle (CPU)"}
+        result["energy_drift_cpu_seconds"] = time.perf_counter() - t0
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
@@ -437,8 +544,13 @@ def main():
 
     dev = torch.device("cuda", 0)
     K, W = args.steps, args.warmup
+    if args.precision is None:
+        args.precision = "fp16x3" if args.workload == "batched" else "bf16x6"
     if args.scheme == "svdu":
         args.no_fp64 = True
+    if args.workload == "large":
+        main_large(args, ntu, torch, np, dev, inputs)
+        return
     all_items = None
     if args.workload == "batched":
         all_items = inputs.workload_batched()
