@@ -324,11 +324,11 @@ NTU_DEV double fit_solve(const T* gs, int nx, const FitParams& fp, const FitShar
 // Pass 1 runs r fastest (coalesced reads of g), pass 2 c fastest.  Each
 // thread carries FORM_JB columns of Q in registers.
 // ---------------------------------------------------------------------------
-constexpr int FAST_NX = 128;        // largest R D on the certified path
+constexpr int FAST_NX = 200;        // largest R D on the certified path (R <= 20, D <= 10)
 constexpr int FIT_CERT_NMAX = 256;  // largest R^2 certified by the shifted Cholesky
 constexpr int FORM_JB = 8;          // columns of Q per thread
 constexpr int FORM_LB = 8;          // loads issued together
-constexpr int CG_NX = 128;          // largest R D solved by conjugate gradients
+constexpr int CG_NX = 200;          // largest R D solved by conjugate gradients
 
 template <class T>
 NTU_DEV void form_gs(const T* __restrict__ Gm, const T* __restrict__ gyv, int R, int Dn, int half, const T* Q,
