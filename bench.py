@@ -416,7 +416,10 @@ def rooflines(job, args, stats, nsteps, prof, workload):
                        "flops_per_step": fit_fl}
         elif cls in env:
             fl, by = env[cls]
-            rl[cls] = {"kernel": KERNEL_OF[cls], "bound": "mfma", "achieved": fl / t / 1e12,
+            kern = KERNEL_OF[cls]
+            if args.precision == "fp16x3":
+                kern = kern.replace("k_mfma_tile ", "k_mfma_tile_f16 ")
+            rl[cls] = {"kernel": kern, "bound": "mfma", "achieved": fl / t / 1e12,
                        "peak": peak_mx / 1e12, "unit": "TFLOP/s", "frac": fl / t / peak_mx,
                        "flops_per_step": fl, "issued_mfma_frac": issue * fl / t / peak_mx,
                        "algorithmic_bytes_per_step": by, "algorithmic_GBps": by / t / 1e9}
