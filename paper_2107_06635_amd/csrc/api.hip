@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -55,6 +56,29 @@ struct ntu_ctx {
 namespace {
 
 thread_local std::string g_create_err;
+
+// Stream captures of the caller that a context's Trotter step has joined
+// (capture id -> context).  A step forks its side stream from the context
+// stream and joins it back; one context inside a caller's capture is the
+// supported case, a second context inside the same capture is refused.
+std::mutex g_capture_mu;
+std::map<unsigned long long, const ntu_ctx*> g_capture_owner;
+
+bool claim_capture(const ntu_ctx* c, unsigned long long id) {
+  std::lock_guard<std::mutex> lock(g_capture_mu);
+  auto it = g_capture_owner.find(id);
+  if (it != g_capture_owner.end()) return it->second == c;
+  for (auto jt = g_capture_owner.begin(); jt != g_capture_owner.end();)
+    jt = jt->second == c ? g_capture_owner.erase(jt) : std::next(jt);  // the context's earlier captures
+  g_capture_owner[id] = c;
+  return true;
+}
+
+void release_captures(const ntu_ctx* c) {
+  std::lock_guard<std::mutex> lock(g_capture_mu);
+  for (auto jt = g_capture_owner.begin(); jt != g_capture_owner.end();)
+    jt = jt->second == c ? g_capture_owner.erase(jt) : std::next(jt);
+}
 
 ntu_status fail(ntu_ctx* c, ntu_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -341,6 +365,7 @@ ntu_status ntu_ctx_create(ntu_ctx** out, int device, int dtype, int d, int d_anc
 ntu_status ntu_ctx_destroy(ntu_ctx* c) {
   if (!c) return NTU_ERR_ARG;
   DeviceGuard guard(c->device);
+  release_captures(c);
   drop_graph(c);
   if (c->ws) (void)hipFree(c->ws);
   if (c->step) (void)hipFree(c->step);
@@ -705,9 +730,15 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, ntu_tensor* A, ntu_tensor* B,
   char* wb = c64 ? c->step + (size_t)L.wB * el * batch : (char*)B->data;
   double* st = stats ? (double*)stats->data : nullptr;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  hipError_t e = hipStreamIsCapturing(c->stream, &cs);
+  unsigned long long cap_id = 0;
+  hipError_t e = hipStreamGetCaptureInfo(c->stream, &cs, &cap_id);
   if (e != hipSuccess) return hip_fail(c, e, "stream capture query");
   const bool capturing = cs != hipStreamCaptureStatusNone;
+  if (capturing && cs != hipStreamCaptureStatusActive) return fail(c, NTU_ERR_ARG, "the caller's capture is invalidated");
+  // one context per caller capture: a second context's fork and join inside
+  // the same capture is not a supported configuration
+  if (capturing && !opts->graph && !claim_capture(c, cap_id))
+    return fail(c, NTU_ERR_UNSUPPORTED, "another context's Trotter step is already part of this stream capture");
   const char* where = "";
   if (!opts->graph) {
     // eager (possibly inside the caller's own capture: no profiler events then)

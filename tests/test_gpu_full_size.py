@@ -350,6 +350,63 @@ def test_graph_captured_sweep_replays():
     ctx.bind_stream()
 
 
+def test_two_contexts_in_one_capture():
+    """Two contexts inside one caller capture: the first context's Trotter
+    step joins the capture; the second context's step in the same capture is
+    refused before it launches anything (NTU_ERR_UNSUPPORTED), and the
+    capture stays valid.  The captured step, replayed twice, equals the eager
+    step bit for bit and the oracle's step in energy and <X>.  The refused context still runs eagerly and
+    in a capture of its own."""
+    D = 4
+    w = inputs.workload_quench(seed=2, D=D)
+    GA, GB, _ = O.gate_split(w['gates'][0], 2, 2)
+    pairs = {b: (GA, GB) for b in O.BONDS}
+    gf = to_dev(gate_factors_array(pairs)[None])
+    c1 = ntu.Context(complex_=True, d=2, d_anc=1, r_g=2, max_D=D, max_batch=1)
+    c2 = ntu.Context(complex_=True, d=2, d_anc=1, r_g=2, max_D=D, max_batch=1)
+    A0, B0 = to_dev(w['A'][None]), to_dev(w['B'][None])
+    opts = ntu.step_opts("bf16x6", n_iter=N_ITER, early_stop=True, conv_tol=CONV)
+    Ae, Be = A0.clone(), B0.clone()
+    ntu.ntu_trotter_step(c1, Ae, Be, gf, opts, stats=False)
+    torch.cuda.synchronize()
+    ref_A, ref_B = to_np(Ae), to_np(Be)
+    Ao, Bo, _ = O.trotter_step(w['A'], w['B'], pairs, D, n_iter=N_ITER, conv_tol=CONV)
+    As, Bs = A0.clone(), B0.clone()
+    A2, B2 = A0.clone(), B0.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ntu.ntu_trotter_step(c1, As, Bs, gf, opts, stats=False)
+        with pytest.raises(RuntimeError, match=r"\(-7\).*already part of this stream capture"):
+            ntu.ntu_trotter_step(c2, A2, B2, gf, opts, stats=False)
+    torch.cuda.synchronize()
+    o_ref = O.observables(Ao, Bo, inputs.H_CRIT)
+    for rep in range(2):
+        As.copy_(A0)
+        Bs.copy_(B0)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(As), ref_A) and np.array_equal(to_np(Bs), ref_B), rep
+        o = O.observables(to_np(As)[0], to_np(Bs)[0], inputs.H_CRIT)
+        for k in range(2):   # energy, <X>
+            assert abs(o[k] - o_ref[k]) <= 1e-6 * max(1.0, abs(o_ref[k])), (rep, k, o[k], o_ref[k])
+    # the refused context launched nothing; eagerly it gives the same step
+    assert np.array_equal(to_np(A2), to_np(A0))
+    ntu.ntu_trotter_step(c2, A2, B2, gf, opts, stats=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(A2), ref_A) and np.array_equal(to_np(B2), ref_B)
+    # and in a capture of its own
+    A2.copy_(A0)
+    B2.copy_(B0)
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2):
+        ntu.ntu_trotter_step(c2, A2, B2, gf, opts, stats=False)
+    g2.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(A2), ref_A) and np.array_equal(to_np(B2), ref_B)
+    c1.bind_stream()
+    c2.bind_stream()
+
+
 @pytest.mark.parametrize("D,precision,storage", [(4, "bf16x6", "c128"), (4, "f64", "c64"), (10, "bf16x6", "c128")])
 def test_library_graph_steps_match_oracle(D, precision, storage):
     """Library-side capture (step option graph = 1): the first call captures
