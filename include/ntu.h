@@ -247,7 +247,9 @@ void ntu_fit_opts_default(ntu_fit_opts* o);
  *       3 certified by the metric repair of the same Trotter step (the
  *       clip's shifted test, run with the same s; ntu_trotter_step only)
  *   [10..14] GPU clock cycles spent in: set-up, half-step matrices, solves,
- *            error evaluations, balancing
+ *            error evaluations, balancing (when a bond's fit is spread over
+ *            several workgroups, those of the first, and set-up includes each
+ *            half-step's isometry, right-hand side and starting point)
  *   [15] mean conjugate-gradient iterations per certified half-step
  *   [16 + 2i + h]              eps after half-step h of iteration i
  *   [16 + 2 n_iter + 2i + h]   chosen tolerance of that half-step

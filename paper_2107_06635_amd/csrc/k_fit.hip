@@ -20,6 +20,13 @@ namespace ntu {
 
 constexpr int FIT_THREADS = 512;
 constexpr int FIT_RMAX = 20;
+// the group fit (k_bond_fit_grp)
+constexpr int GRP_MAX = 16;                  // members per item
+constexpr int GRP_CTL = 64;                  // control words per item (own cache lines):
+                                             // [0] arrivals, [1] abort, [2] redo by k_bond_fit
+constexpr unsigned GRP_SPIN_LIMIT = 1u << 20;
+constexpr int GRP_NXMAX = 128;               // R Dn of the group path (R <= 16, Dn <= 8)
+constexpr int GRP_MIN_D = 5;                 // smallest D the group path takes
 static_assert(svdu_guess_elems() == 2 * FIT_RMAX * FIT_RMAX + 1, "guess layout");
 
 
@@ -31,9 +38,18 @@ NTU_HD long long fit_ws_elems(int D, int R) {
          + 3 * n;       // g y, d, g d
 }
 
+NTU_HD size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// the group fit's exchange area after the items' blocks: control words,
+// [2][n] row values per item (by barrier parity), [2][GRP_MAX][2] partial sums
+NTU_HD size_t grp_xch_bytes(size_t el, int batch, int R) {
+  return align256((size_t)batch * GRP_CTL * 4) + align256((size_t)batch * 2 * R * R * el) +
+         align256((size_t)batch * 2 * GRP_MAX * 2 * 8);
+}
+
 size_t fit_workspace_bytes(bool cplx, int batch, int D, int R) {
-  // + one certification flag per item
-  return (size_t)batch * fit_ws_elems(D, R) * (cplx ? 16 : 8) + (size_t)batch * sizeof(int) + 512;
+  const size_t el = cplx ? 16 : 8;
+  return align256((size_t)batch * fit_ws_elems(D, R) * el) + grp_xch_bytes(el, batch, R) + 512;
 }
 
 // ---------------------------------------------------------------------------
@@ -138,6 +154,62 @@ NTU_DEV void fit_orthonormalise(const T* M, T* Q, int R, int Dn, double kappa) {
     double inv = (scale > 0 && nn > kappa * scale) ? 1.0 / nn : 0.0;
     if (lane < R) Q[lane * FIT_RMAX + j] = v * inv;
   }
+}
+
+// The same orthonormal basis for R <= 16 and Dn <= 8 with classical
+// Gram-Schmidt applied twice.  A lane holds one row of every column (the four
+// 16-lane rows of the wave hold the same matrix); in each projection pass the
+// lanes of row g of the wave take the earlier columns g and g + 4 (row sums
+// over 16 lanes), and the four rows' corrections meet by two lane exchanges,
+// added in an order under which every row of the wave gets the same bits.
+// Wave 0.
+template <class T>
+NTU_DEV T lane_xor_t(T v, int m);
+template <> NTU_DEV double lane_xor_t<double>(double v, int m) { return __shfl_xor(v, m, 64); }
+template <> NTU_DEV cd lane_xor_t<cd>(cd v, int m) { return cd{__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)}; }
+template <class T>
+NTU_DEV T row_sum16_t(T v);
+template <> NTU_DEV double row_sum16_t<double>(double v) { return row_sum16(v); }
+template <> NTU_DEV cd row_sum16_t<cd>(cd v) { return cd{row_sum16(v.x), row_sum16(v.y)}; }
+
+template <class T>
+NTU_DEV void fit_orthonormalise16(const T* M, T* Q, int R, int Dn, double kappa) {
+  if (threadIdx.x >= 64) return;
+  const int row = threadIdx.x & 15, g = (threadIdx.x >> 4) & 3;
+  T q[8];
+  double scale = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const T v = (j < Dn && row < R) ? M[row * FIT_RMAX + j] : zerov<T>();
+    q[j] = v;  // the columns of M for now
+    scale = fmax(scale, sqrt(row_sum16(abs2(v))));
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (j >= Dn) break;
+    // this row's two earlier columns
+    const T qa = g == 0 ? q[0] : g == 1 ? q[1] : g == 2 ? q[2] : q[3];
+    const T qb = g == 0 ? q[4] : g == 1 ? q[5] : g == 2 ? q[6] : q[7];
+    const bool ua = g < j, ub = g + 4 < j;
+    T v = q[j];
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      const T ha = row_sum16_t<T>(cmul(qa, v)), hb = row_sum16_t<T>(cmul(qb, v));
+      T c = zerov<T>();
+      if (ua) c += qa * ha;
+      if (ub) c += qb * hb;
+      c += lane_xor_t<T>(c, 16);
+      c += lane_xor_t<T>(c, 32);
+      v -= c;
+    }
+    const double nn = sqrt(row_sum16(abs2(v)));
+    const double inv = (scale > 0 && nn > kappa * scale) ? 1.0 / nn : 0.0;
+    q[j] = v * inv;
+  }
+  if (threadIdx.x < 16 && row < R)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < Dn) Q[row * FIT_RMAX + j] = q[j];
 }
 
 // Thin QR of the R x Dn matrix M (row-major, stride FIT_RMAX) by Gram-Schmidt
@@ -448,25 +520,27 @@ NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv,
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) {
       const int y = 4 * kc + lk;
-      // branch-free: invalid entries load element 0 and are replaced by zero
+      // branch-free: invalid entries load element 0; the mask and the
+      // conjugation are applied at the use (work on a loaded register here
+      // would wait for the load)
       const bool ok = y < R && r < n;
-      const T gl = Gm[ok ? (size_t)(half == 0 ? x * R + y : y * R + x) * n + r : 0];
-      gv[kc] = ok ? conjv(gl) : zerov<T>();
+      gv[kc] = Gm[ok ? (size_t)(half == 0 ? x * R + y : y * R + x) * n + r : 0];
     }
   };
   T gnext[NKC];
-  if (w < nu1) load1(w, gnext);
+  load1(min(w, nu1 - 1), gnext);
   for (int u = w; u < nu1; u += nw) {
     const int x = u / nrt, r0 = (u % nrt) * 16;
     T gv[NKC];
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) gv[kc] = gnext[kc];
-    if (u + nw < nu1) load1(u + nw, gnext);
+    load1(min(u + nw, nu1 - 1), gnext);  // unconditional: stays in flight
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) {
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(rev(gv[kc]), b1[kc], acc, 0, 0, 0);
-      if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(imv(gv[kc]), b2[kc], acc, 0, 0, 0);
+      const bool ok = 4 * kc + lk < R && r0 + l16 < n;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok ? rev(gv[kc]) : 0.0, b1[kc], acc, 0, 0, 0);
+      if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok ? -imv(gv[kc]) : 0.0, b2[kc], acc, 0, 0, 0);
     }
     // lane holds rows r0 + lk + 4 v, column l16
     const int j = CPLX ? (l16 & 7) : l16, part = CPLX ? (l16 >> 3) : 0;
@@ -509,22 +583,22 @@ NTU_DEV void form_gs_mfma_k(const T* __restrict__ Gm, const T* __restrict__ gyv,
     for (int kc = 0; kc < NKC; ++kc) {
       const int i = 4 * kc + lk;
       const bool ok = i < R && c < nx;
-      const T gl = G1[ok ? (size_t)(half == 0 ? o * R + i : i * R + o) * nx + c : 0];
-      gv[kc] = ok ? gl : zerov<T>();
+      gv[kc] = G1[ok ? (size_t)(half == 0 ? o * R + i : i * R + o) * nx + c : 0];
     }
   };
-  if (w < nu2) load2(w, gnext);
+  load2(min(w, nu2 - 1), gnext);
   for (int u = w; u < nu2; u += nw) {
     const int o = u / nct, c = (u % nct) * 16 + l16;
     T gv[NKC];
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) gv[kc] = gnext[kc];
-    if (u + nw < nu2) load2(u + nw, gnext);
+    load2(min(u + nw, nu2 - 1), gnext);  // unconditional: stays in flight
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) {
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[kc], rev(gv[kc]), acc, 0, 0, 0);
-      if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[kc], imv(gv[kc]), acc, 0, 0, 0);
+      const bool ok = 4 * kc + lk < R && c < nx;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[kc], ok ? rev(gv[kc]) : 0.0, acc, 0, 0, 0);
+      if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[kc], ok ? imv(gv[kc]) : 0.0, acc, 0, 0, 0);
     }
     if (c < nx) {
 #pragma unroll
@@ -709,6 +783,57 @@ NTU_DEV bool fast_solve(T* gs, int R, int Dn, int half, const T* Q, const FitSha
   return true;
 }
 
+// Balance (Fig. 5(d)): SVD of MX MY^T, normalised by the largest singular
+// value.  With MX = Qx Rx and MY = Qy Ry, MX MY^T = Qx (Rx Ry^T) Qy^T, so for
+// Rx Ry^T = Uc S Vc^H the singular vectors are U = Qx Uc, V = conj(Qy) Vc:
+// a Dn x Dn SVD instead of an R x R one.  Writes MX = U S^1/2, MY = conj(V)
+// S^1/2 (R x D, zero beyond the kept Dk columns) to MXi, MYi and leaves the
+// singular values in S.s.  Buffers: Qx -> Qf, Qy -> J, Rx -> sa, Ry -> sv,
+// C = Rx Ry^T (column-major) -> m, each FIT_RMAX^2.  Whole block; returns Dk.
+template <class T>
+NTU_DEV int fit_balance(int D, int R, int Dn, double kappa, const FitShared<T>& S, T* MXi, T* MYi, int* flag) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if (Dn > 0) {
+    fit_qr_small<T>(S.MX, S.Qf, S.sa, R, Dn, kappa, 0);
+    fit_qr_small<T>(S.MY, S.J, S.sv, R, Dn, kappa, 1);
+    __syncthreads();
+    for (int e = tid; e < Dn * Dn; e += blockDim.x) {
+      const int i = e % Dn, k = e / Dn;
+      T v = zerov<T>();
+      for (int l = (i > k ? i : k); l < Dn; ++l) v += S.sa[i * FIT_RMAX + l] * S.sv[k * FIT_RMAX + l];
+      S.m[i + k * FIT_RMAX] = v;
+    }
+    __syncthreads();
+    svd_block_small<T>(S.m, Dn, Dn, FIT_RMAX, S.sv, FIT_RMAX, S.s, flag);
+  } else {
+    if (tid == 0) S.s[0] = 0.0;
+    __syncthreads();
+  }
+  const double c0 = S.s[0];
+  int Dk = 0;
+  if (c0 > 0)
+    for (int j = 0; j < Dn && Dk < D; ++j)
+      if (S.s[j] > kappa * c0) ++Dk;
+  for (int e = tid; e < R * D; e += blockDim.x) {
+    int a = e / D, j = e % D;
+    T mx = zerov<T>(), my = zerov<T>();
+    if (j < Dk) {
+      double sn = S.s[j] / c0, sq = sqrt(sn);
+      T us = zerov<T>(), vv = zerov<T>();
+      for (int i = 0; i < Dn; ++i) {
+        us += S.Qf[a * FIT_RMAX + i] * S.m[i + j * FIT_RMAX];          // (U S)[a][j]
+        vv += conjv(S.J[a * FIT_RMAX + i]) * S.sv[i + j * FIT_RMAX];   // V[a][j]
+      }
+      mx = us * (sq / S.s[j]);
+      my = conjv(vv) * sq;
+    }
+    MXi[e] = mx;
+    MYi[e] = my;
+  }
+  return Dk;
+}
+
 // SVDU guess (Fig. 2(c,d)): P = RX RY^T = U S V^H (one-sided Jacobi),
 // Dn = min(D, #{S_j > kappa S_0}), MX = U S^1/2, MY = conj(V) S^1/2, row-major
 // R x FIT_RMAX and zero beyond column Dn.  Leaves vec(P) (row-major) in y;
@@ -772,10 +897,12 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
                                                           const T* __restrict__ RX, const T* __restrict__ RY,
                                                           FitParams fp, T* MXo, T* MYo, double* stats,
                                                           int stats_stride, T* ws, const double* cert,
-                                                          const T* __restrict__ guess) {
+                                                          const T* __restrict__ guess, const unsigned* redo) {
   extern __shared__ double shmem[];
   __shared__ int flag;
   const int it = blockIdx.x, tid = threadIdx.x;
+  // after the group fit: only the items it left (redo flag set)
+  if (redo && redo[(size_t)it * GRP_CTL + 2] == 0u) return;
   const int n = R * R;
   // without a metric (g == NULL: the SVDU scheme) the fit returns the
   // balanced SVDU guess: no certificate, no error, no iterations
@@ -871,10 +998,16 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
       S.MX[e] = gi[e];
       S.MY[e] = gi[FIT_RMAX * FIT_RMAX + e];
     }
+    // RX and RY staged in shared memory (sa, sv: FIT_RMAX^2 >= R^2 each)
+    for (int e = tid; e < n; e += blockDim.x) {
+      S.sa[e] = RX[(size_t)it * n + e];
+      S.sv[e] = RY[(size_t)it * n + e];
+    }
+    __syncthreads();
     for (int e = tid; e < n; e += blockDim.x) {
       int a = e / R, b = e % R;
       T v = zerov<T>();
-      for (int k = 0; k < R; ++k) v += RX[(size_t)it * n + a * R + k] * RY[(size_t)it * n + b * R + k];
+      for (int k = 0; k < R; ++k) v += S.sa[a * R + k] * S.sv[b * R + k];
       S.y[e] = v;
     }
     Dn = (int)rev(gi[2 * FIT_RMAX * FIT_RMAX]);
@@ -1039,48 +1172,7 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
     if (stop) break;
   }
   __syncthreads();
-  // balance: SVD of MX MY^T, normalised by the largest singular value.  With
-  // MX = Qx Rx and MY = Qy Ry, MX MY^T = Qx (Rx Ry^T) Qy^T, so for
-  // Rx Ry^T = Uc S Vc^H the singular vectors are U = Qx Uc, V = conj(Qy) Vc:
-  // a Dn x Dn SVD instead of an R x R one.
-  // Buffers: Qx -> Qf, Qy -> J, Rx -> sa, Ry -> sv, C = Rx Ry^T (column-major) -> m.
-  if (Dn > 0) {
-    fit_qr_small<T>(S.MX, S.Qf, S.sa, R, Dn, kappa, 0);
-    fit_qr_small<T>(S.MY, S.J, S.sv, R, Dn, kappa, 1);
-    __syncthreads();
-    for (int e = tid; e < Dn * Dn; e += blockDim.x) {
-      const int i = e % Dn, k = e / Dn;
-      T v = zerov<T>();
-      for (int l = (i > k ? i : k); l < Dn; ++l) v += S.sa[i * FIT_RMAX + l] * S.sv[k * FIT_RMAX + l];
-      S.m[i + k * FIT_RMAX] = v;
-    }
-    __syncthreads();
-    svd_block_small<T>(S.m, Dn, Dn, FIT_RMAX, S.sv, FIT_RMAX, S.s, &flag);
-  } else {
-    if (tid == 0) S.s[0] = 0.0;
-    __syncthreads();
-  }
-  const double c0 = S.s[0];
-  int Dk = 0;
-  if (c0 > 0)
-    for (int j = 0; j < Dn && Dk < D; ++j)
-      if (S.s[j] > kappa * c0) ++Dk;
-  for (int e = tid; e < R * D; e += blockDim.x) {
-    int a = e / D, j = e % D;
-    T mx = zerov<T>(), my = zerov<T>();
-    if (j < Dk) {
-      double sn = S.s[j] / c0, sq = sqrt(sn);
-      T us = zerov<T>(), vv = zerov<T>();
-      for (int i = 0; i < Dn; ++i) {
-        us += S.Qf[a * FIT_RMAX + i] * S.m[i + j * FIT_RMAX];          // (U S)[a][j]
-        vv += conjv(S.J[a * FIT_RMAX + i]) * S.sv[i + j * FIT_RMAX];   // V[a][j]
-      }
-      mx = us * (sq / S.s[j]);
-      my = conjv(vv) * sq;
-    }
-    MXo[(size_t)it * R * D + e] = mx;
-    MYo[(size_t)it * R * D + e] = my;
-  }
+  const int Dk = fit_balance<T>(D, R, Dn, kappa, S, MXo + (size_t)it * R * D, MYo + (size_t)it * R * D, &flag);
   tick(4);
   if (st && tid == 0) {
     st[9] = (double)cert_kind;
@@ -1093,8 +1185,634 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
     st[6] = iters;
     st[7] = n_eig;
     st[8] = isfinite(eps) && isfinite(N) ? 0.0 : 1.0;
-    for (int j = 0; j < D; ++j) st[16 + 4 * fp.n_iter + j] = j < Dk ? S.s[j] / c0 : 0.0;
+    for (int j = 0; j < D; ++j) st[16 + 4 * fp.n_iter + j] = j < Dk ? S.s[j] / S.s[0] : 0.0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Group fit: the certified fit of one item spread over G workgroups, the
+// item's group (2 <= G <= R).  Every member keeps the small state (M_X, M_Y,
+// the isometric factor, vec(P), g vec(P), the conjugate-gradient vectors)
+// itself and does the same arithmetic on it in the same order, so the
+// members reach the same decisions without exchanging them.  Split between
+// them: the rows of g in the products with g (g vec(P), g d), and the rows of
+// each half-step matrix g_s, which a member forms from its slabs of g into
+// its own shared memory and multiplies in every conjugate-gradient iteration.
+// Between members pass only the rows of a product and partial sums, through
+// a per-item exchange area, one group barrier per iteration.
+// Items the group does not take (no certificate from the metric repair, an
+// empty guess, a solve that does not converge, a wait that runs out) are
+// flagged and redone whole by k_bond_fit, launched after this kernel.
+// ---------------------------------------------------------------------------
+
+// Exchanged values are written and read with agent-scope atomic accesses,
+// each coherent across the chip on its own; a writer's stores complete (the
+// wait in grp_sync) before its workgroup arrives at the counter, and a reader
+// loads only after it has seen the counter reach the barrier.  So the group
+// barrier needs no cache write-back or invalidation.
+NTU_DEV void xput(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+NTU_DEV double xget(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+NTU_DEV void xput(cd* p, cd v) {
+  xput(&p->x, v.x);
+  xput(&p->y, v.y);
+}
+NTU_DEV cd xget(const cd* p) { return cd{xget(&p->x), xget(&p->y)}; }
+
+// Group barrier on the item's arrival counter (count: the barriers this
+// member has passed).  Bounded: a wait that runs out, or an abort raised by
+// another member, returns false in every thread.  Whole block.
+NTU_DEV bool grp_sync(unsigned* ctl, int G, unsigned& count, int* ok_sh) {
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's exchange stores have completed
+  __syncthreads();
+  ++count;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(ctl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = count * (unsigned)G;
+    unsigned spins = 0;
+    int ok = 1;
+    while (__hip_atomic_load(ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > GRP_SPIN_LIMIT) {
+        __hip_atomic_store(ctl + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    *ok_sh = ok;
+  }
+  __syncthreads();
+  return *ok_sh != 0;
+}
+
+// out_k[r - r0] = (g v_k)_r (k < nv <= 2) for the rows r0 <= r < r1 of a
+// Hermitian n x n g, read column-wise: (g v)_r = sum_c conj(g[c][r]) v[c]
+// with r fastest.  Work item (r, part); the parts meet in mv (blockDim.x
+// elements per vector).  Whole block.
+template <class T>
+NTU_DEV void rows_matvec(const T* __restrict__ g, int n, int r0, int r1, int nv, const T* v0, const T* v1, T* o0,
+                         T* o1, T* mv) {
+  const int tid = threadIdx.x, nr = r1 - r0;
+  const int parts = max(1, (int)blockDim.x / max(nr, 1)), cs = (n + parts - 1) / parts;
+  if (tid < parts * nr) {
+    const int r = r0 + tid % nr, part = tid / nr;
+    const int c1 = min(n, (part + 1) * cs);
+    T a0 = zerov<T>(), a1 = zerov<T>();
+    for (int c0 = part * cs; c0 < c1; c0 += 8) {
+      T gv[8];
+#pragma unroll
+      for (int l = 0; l < 8; ++l) gv[l] = c0 + l < c1 ? g[(size_t)(c0 + l) * n + r] : zerov<T>();
+#pragma unroll
+      for (int l = 0; l < 8; ++l)
+        if (c0 + l < c1) {
+          a0 += cmul(gv[l], v0[c0 + l]);
+          if (nv > 1) a1 += cmul(gv[l], v1[c0 + l]);
+        }
+    }
+    mv[tid] = a0;
+    if (nv > 1) mv[blockDim.x + tid] = a1;
+  }
+  __syncthreads();
+  for (int r = tid; r < nr; r += blockDim.x) {
+    T s0 = zerov<T>(), s1 = zerov<T>();
+    for (int part = 0; part < parts; ++part) {
+      s0 += mv[part * nr + r];
+      if (nv > 1) s1 += mv[blockDim.x + part * nr + r];
+    }
+    o0[r] = s0;
+    if (nv > 1) o1[r] = s1;
+  }
+  __syncthreads();
+}
+
+// Rows of a half-step matrix from this member's slabs, on the FP64 matrix
+// cores (v_mfma_f64_16x16x4: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]
+// and receives D[l / 16 + 4 v][l % 16]).
+//   X half: g_s[(a',j'),(a,j)] = sum_{b',b} conj(Q[b',j']) g[(a' b'),(a b)] Q[b,j],
+//           rows (a', j') for the slabs a' = s0 .. s0 + nsl - 1, columns a Dn + j;
+//   Y half: g_s[(j',b'),(j,b)] = sum_{a',a} conj(Q[a',j']) g[(a' b'),(a b)] Q[a,j],
+//           rows (j', b') for the slabs b', columns j R + b.
+// h holds the entries with the slab index leading in the contracted pair:
+// h[(x R + y) ld + (x' - xoff) R + y'] = conj(entry of block (x', x) at
+// (y', y)), i.e. g itself for the X half (ld = n, xoff = 0: its Hermitian
+// symmetry gives lanes along the contiguous index) and the member's copy of
+// the Y half's entries (k_bond_fit_grp).  A unit is one block (x', x): pass 1
+// multiplies it by Q (complex as two real products into one accumulator,
+// columns [Re | Im]), pass 2 by Q^H straight from the accumulator (register v
+// of lane l is the B operand of K chunk v), and the real and imaginary parts
+// are recombined across the two column halves of each 16-lane row (DPP
+// rotate by 8).  Output: local row (x' - s0) Dn + j' of gsl (leading
+// dimension gld).  Needs R <= 16, Dn <= 8.  Whole block.
+template <class T, int NKC>
+NTU_DEV void form_rows_mfma(const T* __restrict__ h, long long ld, int xoff, int R, int Dn, int half, int s0, int nsl,
+                            const T* Q, T* gsl, int gld) {
+  constexpr bool CPLX = is_cplx<T>::value;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  double b1[NKC], b2[NKC], a2[NKC];
+#pragma unroll
+  for (int kc = 0; kc < NKC; ++kc) {
+    const int y = 4 * kc + lk;
+    double v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    if (y < R) {
+      if constexpr (CPLX) {
+        const int j = l16 & 7;
+        if (j < Dn) {
+          const T q = Q[y * FIT_RMAX + j];
+          v1 = l16 < 8 ? rev(q) : imv(q);   // B' = [Re Q | Im Q]
+          v2 = l16 < 8 ? -imv(q) : rev(q);  // B'' = [-Im Q | Re Q]
+          v3 = l16 < 8 ? rev(q) : imv(q);   // pass 2: A = [Re Q^T ; Im Q^T]
+        }
+      } else {
+        if (l16 < Dn) v1 = v3 = rev(Q[y * FIT_RMAX + l16]);
+      }
+    }
+    b1[kc] = v1;
+    b2[kc] = v2;
+    a2[kc] = v3;
+  }
+  const int nu = nsl * R;
+  // operands of unit u (clamped to the last unit, so that every load is
+  // unconditional and the loads of the next units stay in flight while the
+  // current ones are multiplied)
+  auto load = [&](int u, T (&gv)[NKC]) {
+    u = min(u, nu - 1);
+    const int xl = u / R, x = u % R;
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+      const int y = 4 * kc + lk;
+      const bool ok = y < R && l16 < R;
+      // raw: the mask and the conjugation are applied where the value is
+      // used (work on a loaded register here would wait for the load)
+      gv[kc] = h[ok ? (size_t)(x * R + y) * ld + (size_t)(s0 + xl - xoff) * R + l16 : 0];
+    }
+  };
+  double* gd = (double*)gsl;
+  auto unit = [&](int u, const T (&gv)[NKC]) {
+    const int xl = u / R, x = u % R;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+      const bool ok = 4 * kc + lk < R && l16 < R;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok ? rev(gv[kc]) : 0.0, b1[kc], acc, 0, 0, 0);
+      if constexpr (CPLX) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok ? -imv(gv[kc]) : 0.0, b2[kc], acc, 0, 0, 0);
+    }
+    f64x4 out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) out = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[kc], acc[kc], out, 0, 0, 0);
+    if constexpr (CPLX) {
+      // out rows 0-7: Re Q^T (G Q), rows 8-15: Im Q^T (G Q), columns [Re | Im];
+      // g_s = Q^H G Q:  Re = out[j'][j] + out[8+j'][8+j],  Im = out[j'][8+j] - out[8+j'][j]
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const double t = dpp_move<0x128>(out[v + 2]);
+        const double val = l16 < 8 ? out[v] + t : out[v] - t;
+        const int jp = lk + 4 * v, j = l16 & 7, part = l16 >> 3;
+        if (jp < Dn && j < Dn) {
+          const int col = half == 0 ? x * Dn + j : j * R + x;
+          gd[((size_t)(xl * Dn + jp) * gld + col) * 2 + part] = val;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jp = lk + 4 * v, j = l16;
+        if (jp < Dn && j < Dn) {
+          const int col = half == 0 ? x * Dn + j : j * R + x;
+          gd[(size_t)(xl * Dn + jp) * gld + col] = out[v];
+        }
+      }
+    }
+  };
+  // two units per step, the next two in flight
+  T ga[2][NKC], gb[2][NKC];
+  load(w, ga[0]);
+  load(w + nw, ga[1]);
+  for (int u = w; u < nu; u += 2 * nw) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc) gb[p][kc] = ga[p][kc];
+    load(u + 2 * nw, ga[0]);
+    load(u + 3 * nw, ga[1]);
+    unit(u, gb[0]);
+    if (u + nw < nu) unit(u + nw, gb[1]);
+  }
+  __syncthreads();
+}
+
+template <class T>
+__device__ __noinline__ void form_rows(const T* __restrict__ h, long long ld, int xoff, int R, int Dn, int half,
+                                       int s0, int nsl, const T* Q, T* gsl, int gld) {
+  switch ((R + 3) / 4) {
+    case 1: form_rows_mfma<T, 1>(h, ld, xoff, R, Dn, half, s0, nsl, Q, gsl, gld); break;
+    case 2: form_rows_mfma<T, 2>(h, ld, xoff, R, Dn, half, s0, nsl, Q, gsl, gld); break;
+    case 3: form_rows_mfma<T, 3>(h, ld, xoff, R, Dn, half, s0, nsl, Q, gsl, gld); break;
+    default: form_rows_mfma<T, 4>(h, ld, xoff, R, Dn, half, s0, nsl, Q, gsl, gld); break;
+  }
+}
+
+// bytes of the group kernel's dynamic shared memory
+NTU_HD size_t grp_gsl_elems(int R, int D, int G) {
+  size_t gs = (size_t)((R + G - 1) / G) * D * (R * D + 1);
+  return gs < 4 * FIT_RMAX * FIT_RMAX ? 4 * FIT_RMAX * FIT_RMAX : gs;  // the balancing's buffers alias it
+}
+NTU_HD size_t grp_shared_bytes(size_t el, int R, int D, int G) {
+  const size_t n = (size_t)R * R;
+  const size_t t_elems = 3 * 16 * FIT_RMAX + 3 * n + 7 * GRP_NXMAX + 8 * FIT_RMAX + 2 * FIT_THREADS + grp_gsl_elems(R, D, G);
+  const size_t d_elems = 16 * 64 + FIT_RMAX + 64;
+  return (t_elems * el + d_elems * 8 + 15) / 16 * 16;
+}
+
+template <class T>
+__global__ void __launch_bounds__(FIT_THREADS) k_bond_fit_grp(int batch, int G, int D, int R, const T* __restrict__ g,
+                                                              const T* __restrict__ RX, const T* __restrict__ RY,
+                                                              FitParams fp, T* MXo, T* MYo, double* stats,
+                                                              int stats_stride, T* ws, unsigned* ctl_all, T* xv_all,
+                                                              double* xs_all, const double* cert,
+                                                              const T* __restrict__ guess) {
+  extern __shared__ double shmem[];
+  __shared__ int sync_ok, flag;
+  __shared__ int zcol_sh[FIT_RMAX];
+  // workgroups are dealt to the eight XCDs in turn: the members of an item
+  // take consecutive turns on one XCD
+  const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
+  const int it = (slot / G) * 8 + xcd, mem = slot % G;
+  if (it >= batch) return;
+  const int tid = threadIdx.x, n = R * R;
+  const bool lead = mem == 0;
+  unsigned* ctl = ctl_all + (size_t)it * GRP_CTL;
+  T* xv = xv_all + (size_t)it * 2 * n;
+  double* xs = xs_all + (size_t)it * 2 * GRP_MAX * 2;
+  unsigned nsync = 0;
+  auto redo = [&]() {
+    if (lead && tid == 0) __hip_atomic_store(ctl + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  const T* G_ = g + (size_t)it * n * n;
+  const T* gi = guess + (size_t)it * svdu_guess_elems();
+  const int Dn = (int)rev(gi[2 * FIT_RMAX * FIT_RMAX]);
+  if (!(R * D <= GRP_NXMAX && R <= 16 && D <= 8 && cert[it] > 0.5) || Dn < 1) {
+    redo();
+    return;
+  }
+  // this member's slabs (of the first index for the X half, of the second
+  // for the Y half) and rows of g
+  const int s0 = (mem * R) / G, s1 = ((mem + 1) * R) / G, nsl = s1 - s0;
+  const int r0 = (mem * n) / G, r1 = ((mem + 1) * n) / G, nr = r1 - r0;
+  // shared carve-up
+  T* tp = (T*)shmem;
+  T* MXs = tp; tp += 16 * FIT_RMAX;
+  T* MYs = tp; tp += 16 * FIT_RMAX;
+  T* Qf = tp; tp += 16 * FIT_RMAX;
+  T* y = tp; tp += n;
+  T* gy = tp; tp += n;
+  T* dv = tp; tp += n;
+  T* J = tp; tp += GRP_NXMAX;
+  T* m = tp; tp += GRP_NXMAX;
+  T* rv = tp; tp += GRP_NXMAX;
+  T* pv = tp; tp += GRP_NXMAX;
+  T* qv = tp; tp += GRP_NXMAX;
+  T* o0 = tp; tp += GRP_NXMAX;   // this member's rows of a product with g (nr <= n / 2 <= 128)
+  T* o1 = tp; tp += GRP_NXMAX;
+  T* wsm = tp; tp += 8 * FIT_RMAX;
+  T* mv = tp; tp += 2 * FIT_THREADS;
+  T* gsl = tp; tp += grp_gsl_elems(R, D, G);
+  const int gld = R * D + 1;
+  double* red = (double*)tp;
+  double* sv_s = red + 16 * 64;
+  double* vec = sv_s + FIT_RMAX;
+  double* st = (stats && lead) ? stats + (size_t)it * stats_stride : nullptr;
+  long long tph0 = 0, tph1 = 0, tph2 = 0, tph3 = 0, tph4 = 0;
+  long long t_mark = clock64();
+  auto tick = [&](int ph) {
+    const long long t = clock64(), dt = t - t_mark;
+    if (ph == 0) tph0 += dt;
+    else if (ph == 1) tph1 += dt;
+    else if (ph == 2) tph2 += dt;
+    else if (ph == 3) tph3 += dt;
+    else tph4 += dt;
+    t_mark = t;
+  };
+  // the guess (k_svdu_guess) and vec(P), in every member
+  for (int e = tid; e < 16 * FIT_RMAX; e += blockDim.x) {
+    MXs[e] = e < R * FIT_RMAX ? gi[e] : zerov<T>();
+    MYs[e] = e < R * FIT_RMAX ? gi[FIT_RMAX * FIT_RMAX + e] : zerov<T>();
+  }
+  // vec(P) = vec(RX RY^T), RX and RY staged in shared memory first
+  for (int e = tid; e < n; e += blockDim.x) {
+    mv[e] = RX[(size_t)it * n + e];
+    mv[n + e] = RY[(size_t)it * n + e];
+  }
+  __syncthreads();
+  for (int e = tid; e < n; e += blockDim.x) {
+    const int a = e / R, b = e % R;
+    T v = zerov<T>();
+    for (int k = 0; k < R; ++k) v += mv[a * R + k] * mv[n + b * R + k];
+    y[e] = v;
+  }
+  // this member's copy of the Y half's entries (form_rows):
+  // h[(x R + y) W + xl R + y'] = g[(y R + x), (y' R + s0 + xl)], W = nsl R
+  T* hY = ws + (size_t)it * fit_ws_elems(D, R) + (size_t)n * R * s0;
+  const int W = nsl * R;
+  {
+    // element f = (row R + y') nsl + xl: consecutive lanes read consecutive
+    // entries of g; eight loads in flight per thread
+    const int total = n * W;
+    for (int f0 = tid; f0 < total; f0 += 8 * blockDim.x) {
+      T v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int f = min(f0 + k * (int)blockDim.x, total - 1);
+        const int xl = f % nsl, t = f / nsl, yp = t % R, row = t / R;
+        v[k] = G_[(size_t)((row % R) * R + row / R) * n + yp * R + s0 + xl];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int f = f0 + k * (int)blockDim.x;
+        if (f < total) {
+          const int xl = f % nsl, t = f / nsl, yp = t % R, row = t / R;
+          hY[(size_t)row * W + xl * R + yp] = v[k];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // d = vec(MX MY^T) - y
+  auto form_d = [&]() {
+    for (int e = tid; e < n; e += blockDim.x) {
+      const int a = e / R, b = e % R;
+      T v = zerov<T>();
+      for (int j = 0; j < Dn; ++j) v += MXs[a * FIT_RMAX + j] * MYs[b * FIT_RMAX + j];
+      dv[e] = v - y[e];
+    }
+    __syncthreads();
+  };
+  // partial sums of this member (k < 2) to the others; the group's sums in
+  // member order
+  auto exchange_sums = [&](double p0, double p1, double& t0, double& t1) -> bool {
+    const int par = (nsync + 1) & 1;
+    if (tid == 0) {
+      xput(xs + (par * GRP_MAX + mem) * 2, p0);
+      xput(xs + (par * GRP_MAX + mem) * 2 + 1, p1);
+    }
+    if (!grp_sync(ctl, G, nsync, &sync_ok)) return false;
+    t0 = t1 = 0.0;
+    for (int k = 0; k < G; ++k) {
+      t0 += xget(xs + (par * GRP_MAX + k) * 2);
+      t1 += xget(xs + (par * GRP_MAX + k) * 2 + 1);
+    }
+    return true;
+  };
+  // eps = d^H g d over the group
+  auto group_error = [&](double& eps_out) -> bool {
+    form_d();
+    rows_matvec<T>(G_, n, r0, r1, 1, dv, nullptr, o0, nullptr, mv);
+    double pe = 0.0;
+    for (int r = tid; r < nr; r += blockDim.x) pe += rev(cmul(dv[r0 + r], o0[r]));
+    pe = block_sum(pe, red);
+    double dummy;
+    return exchange_sums(pe, 0.0, eps_out, dummy);
+  };
+  // g y (rows exchanged), N = y^H g y and the guess's error d^H g d
+  double N = 0.0, eps = 0.0;
+  form_d();
+  rows_matvec<T>(G_, n, r0, r1, 2, y, dv, o0, o1, mv);
+  {
+    double pn = 0.0, pe = 0.0;
+    for (int r = tid; r < nr; r += blockDim.x) {
+      pn += rev(cmul(y[r0 + r], o0[r]));
+      pe += rev(cmul(dv[r0 + r], o1[r]));
+      xput(xv + ((nsync + 1) & 1) * n + r0 + r, o0[r]);
+    }
+    pn = block_sum(pn, red);
+    pe = block_sum(pe, red);
+    if (!exchange_sums(pn, pe, N, eps)) {
+      redo();
+      return;
+    }
+    for (int e = tid; e < n; e += blockDim.x) gy[e] = xget(xv + (nsync & 1) * n + e);
+    __syncthreads();
+  }
+  if (st && tid == 0) {
+    const int len = fit_stats_len(fp.n_iter, D);
+    for (int i = 0; i < len; ++i) st[i] = 0.0;
+    st[0] = N; st[1] = eps; st[4] = Dn;
+  }
+  // q = g_s src over the group: this member's rows from gsl, exchanged
+  int half = 0, nx = R * Dn;
+  auto grow = [&](int l) { return half == 0 ? s0 * Dn + l : (l % Dn) * R + s0 + l / Dn; };
+  // src in shared memory (visible to the whole block); the product q = g_s src
+  // goes to every wave's registers, elements lane and lane + 64 (q0, q1)
+  const int lane = tid & 63;
+  auto group_matvec = [&](const T* src, T& q0, T& q1) -> bool {
+    const int nrow = nsl * Dn, par = (nsync + 1) & 1;
+    if (nrow * 16 <= (int)blockDim.x) {
+      // 16 consecutive lanes per row, their partial sums added by DPP
+      const int l = min(tid >> 4, nrow - 1), part = tid & 15;
+      const T* row = gsl + (size_t)l * gld;
+      T acc = zerov<T>();
+      for (int c = part; c < nx; c += 16) acc += row[c] * src[c];
+      if constexpr (is_cplx<T>::value) acc = T{row_sum16(acc.x), row_sum16(acc.y)};
+      else acc = row_sum16(acc);
+      if (part == 0 && (tid >> 4) < nrow) xput(xv + par * n + grow(l), acc);
+    } else {
+      const int parts = max(1, (int)blockDim.x / nrow);
+      if (tid < parts * nrow) {
+        const int l = tid % nrow, part = tid / nrow;
+        const T* row = gsl + (size_t)l * gld;
+        T acc = zerov<T>();
+        for (int c = part; c < nx; c += parts) acc += row[c] * src[c];
+        mv[tid] = acc;
+      }
+      __syncthreads();
+      for (int l = tid; l < nrow; l += blockDim.x) {
+        T acc = zerov<T>();
+        for (int part = 0; part < parts; ++part) acc += mv[part * nrow + l];
+        xput(xv + par * n + grow(l), acc);
+      }
+    }
+    if (!grp_sync(ctl, G, nsync, &sync_ok)) return false;
+    q0 = lane < nx ? xget(xv + par * n + lane) : zerov<T>();
+    q1 = lane + 64 < nx ? xget(xv + par * n + lane + 64) : zerov<T>();
+    return true;
+  };
+  int iters = 0, cg_iters_total = 0, cg_solves = 0;
+  double prev = eps;
+  const double tau = fp.tol[fp.n_tol - 1];
+  const double kappa = fp.kappa;
+  tick(0);
+  bool ok = true;
+  for (int iter = 0; iter < fp.n_iter && ok; ++iter) {
+    for (half = 0; half < 2 && ok; ++half) {
+      nx = R * Dn;
+      const T* F = half == 0 ? MYs : MXs;
+      fit_orthonormalise16<T>(F, Qf, R, Dn, kappa);
+      __syncthreads();
+      if (tid < Dn) {
+        bool z = true;
+        for (int i = 0; i < R; ++i) z = z && rev(Qf[i * FIT_RMAX + tid]) == 0.0 && imv(Qf[i * FIT_RMAX + tid]) == 0.0;
+        zcol_sh[tid] = z ? 1 : 0;
+      }
+      // J[(o, j')] = sum_i conj(Q[i][j']) gy[row(o, i)]  (every member, all of it)
+      for (int e = tid; e < nx; e += blockDim.x) {
+        const int o = half == 0 ? e / Dn : e % R, jp = half == 0 ? e % Dn : e / R;
+        T acc = zerov<T>();
+        for (int i = 0; i < R; ++i) acc += cmul(Qf[i * FIT_RMAX + jp], gy[half == 0 ? o * R + i : i * R + o]);
+        J[e] = acc;
+      }
+      if (lead) tick(0);
+      if (half == 0) form_rows<T>(G_, n, 0, R, Dn, 0, s0, nsl, Qf, gsl, gld);
+      else form_rows<T>(hY, W, s0, R, Dn, 1, s0, nsl, Qf, gsl, gld);
+      // dependent directions (zero columns of Q): unit rows and columns, zero right-hand side
+      bool anyz = false;
+      for (int j = 0; j < Dn; ++j) anyz = anyz || zcol_sh[j] != 0;
+      if (anyz) {
+        const int nrow = nsl * Dn;
+        for (int e = tid; e < nrow * nx; e += blockDim.x) {
+          const int l = e / nx, c = e % nx, i = grow(l);
+          const int ji = half == 0 ? i % Dn : i / R, jj = half == 0 ? c % Dn : c / R;
+          if (zcol_sh[ji] || zcol_sh[jj]) gsl[(size_t)l * gld + c] = realv<T>(i == c ? 1.0 : 0.0);
+        }
+        for (int e = tid; e < nx; e += blockDim.x)
+          if (zcol_sh[half == 0 ? e % Dn : e / R]) J[e] = zerov<T>();
+      }
+      if (lead) tick(1);
+      // warm start: the current pair in this half-step's parameters (the
+      // fixed factor lies in the span of Q: F = Q W with W = Q^H F)
+      const T* Fx = half == 0 ? MYs : MXs;
+      const T* Fr = half == 0 ? MXs : MYs;
+      for (int e = tid; e < Dn * Dn; e += blockDim.x) {
+        const int j = e / Dn, k = e % Dn;
+        T wv = zerov<T>();
+        for (int b = 0; b < R; ++b) wv += cmul(Qf[b * FIT_RMAX + j], Fx[b * FIT_RMAX + k]);
+        wsm[j * FIT_RMAX + k] = wv;
+      }
+      __syncthreads();
+      for (int e = tid; e < nx; e += blockDim.x) {
+        const int a = half == 0 ? e / Dn : e % R, j = half == 0 ? e % Dn : e / R;
+        T v = zerov<T>();
+        for (int k = 0; k < Dn; ++k) v += Fr[a * FIT_RMAX + k] * wsm[j * FIT_RMAX + k];
+        m[e] = v;
+      }
+      __syncthreads();
+      if (lead) tick(0);
+      // conjugate gradients (g_s certified positive definite).  Every member
+      // holds every vector, and within a member every wave holds all of each
+      // in registers (elements lane and lane + 64), so a dot product is one
+      // wave sum, bit-identical in all waves and members; the product with
+      // g_s is split over the group.  pv in shared memory feeds the product.
+      const bool v0 = lane < nx, v1 = lane + 64 < nx;
+      const T J0 = v0 ? J[lane] : zerov<T>(), J1 = v1 ? J[lane + 64] : zerov<T>();
+      T m0 = v0 ? m[lane] : zerov<T>(), m1 = v1 ? m[lane + 64] : zerov<T>();
+      const double bb = wave_sum(abs2(J0) + abs2(J1));
+      T q0, q1;
+      if (!group_matvec(m, q0, q1)) { ok = false; break; }
+      T r0v = J0 - q0, r1v = J1 - q1, p0 = r0v, p1 = r1v;
+      double rr = wave_sum(abs2(r0v) + abs2(r1v));
+      const double stop = 1e-28 * bb;
+      bool conv = rr <= stop;
+      int cgi = 0;
+      for (; cgi < 64 && !conv; ++cgi) {
+        if (tid < 64) {
+          if (v0) pv[lane] = p0;
+          if (v1) pv[lane + 64] = p1;
+        }
+        __syncthreads();
+        if (!group_matvec(pv, q0, q1)) { ok = false; break; }
+        const double pq = wave_sum(rev(cmul(p0, q0)) + rev(cmul(p1, q1)));
+        if (!(pq > 0.0)) break;
+        const double alpha = rr / pq;
+        m0 += alpha * p0;
+        m1 += alpha * p1;
+        r0v -= alpha * q0;
+        r1v -= alpha * q1;
+        const double rn = wave_sum(abs2(r0v) + abs2(r1v));
+        const double beta = rn / rr;
+        rr = rn;
+        conv = rn <= stop;
+        p0 = r0v + beta * p0;
+        p1 = r1v + beta * p1;
+      }
+      if (!ok) break;
+      cg_iters_total += cgi;
+      cg_solves += 1;
+      if (!conv) { ok = false; break; }
+      // eps = m^H g_s m - 2 Re(m^H J) + N = N - Re(m^H (J + r)), r the residual
+      const double eps_est = N - wave_sum(rev(cmul(m0, J0 + r0v)) + rev(cmul(m1, J1 + r1v)));
+      if (tid < 64) {
+        if (v0) m[lane] = m0;
+        if (v1) m[lane + 64] = m1;
+      }
+      __syncthreads();
+      // the new free factor, the fixed one isometric
+      for (int e = tid; e < R * Dn; e += blockDim.x) {
+        if (half == 0) {
+          const int a = e / Dn, j = e % Dn;
+          MXs[a * FIT_RMAX + j] = m[a * Dn + j];
+          MYs[a * FIT_RMAX + j] = Qf[a * FIT_RMAX + j];
+        } else {
+          const int j = e / R, b = e % R;
+          MYs[b * FIT_RMAX + j] = m[j * R + b];
+          MXs[b * FIT_RMAX + j] = Qf[b * FIT_RMAX + j];
+        }
+      }
+      __syncthreads();
+      if (lead) tick(2);
+      // the residual form loses about log10(N / eps) digits: above 1e-8 N it
+      // is kept, below that the error is evaluated directly
+      if (eps_est > 1e-8 * N) {
+        eps = eps_est;
+      } else if (!group_error(eps)) {
+        ok = false;
+        break;
+      }
+      if (lead) tick(3);
+      if (st && tid == 0) {
+        st[16 + 2 * iter + half] = eps;
+        st[16 + 2 * fp.n_iter + 2 * iter + half] = tau;
+      }
+    }
+    if (!ok) break;
+    iters = iter + 1;
+    const bool stop = fp.early_stop && (prev - eps <= fp.conv_tol * N);
+    prev = eps;
+    if (stop) break;
+  }
+  if (!ok) {
+    redo();
+    return;
+  }
+  if (!lead) return;
+  // balancing (the leader), its buffers in the space of the g_s rows
+  FitShared<T> Sb;
+  Sb.y = y; Sb.MX = MXs; Sb.MY = MYs; Sb.Qf = Qf;
+  Sb.sa = gsl; Sb.sv = gsl + FIT_RMAX * FIT_RMAX; Sb.J = gsl + 2 * FIT_RMAX * FIT_RMAX; Sb.m = gsl + 3 * FIT_RMAX * FIT_RMAX;
+  Sb.s = sv_s; Sb.red = red; Sb.vec = vec; Sb.idx = nullptr;
+  // MX, MY were kept with stride FIT_RMAX over 16 rows: fit_qr_small reads R rows
+  __syncthreads();
+  const int Dk = fit_balance<T>(D, R, Dn, kappa, Sb, MXo + (size_t)it * R * D, MYo + (size_t)it * R * D, &flag);
+  tick(4);
+  if (st && tid == 0) {
+    st[9] = 3.0;  // certified by the metric repair
+    st[15] = cg_solves > 0 ? (double)cg_iters_total / cg_solves : 0.0;
+    st[10] = (double)tph0; st[11] = (double)tph1; st[12] = (double)tph2;
+    st[13] = (double)tph3; st[14] = (double)tph4;
+    st[2] = eps;
+    st[3] = N > 0 ? eps / N : 0.0;
+    st[5] = Dk;
+    st[6] = iters;
+    st[7] = 0;
+    st[8] = isfinite(eps) && isfinite(N) ? 0.0 : 1.0;
+    for (int j = 0; j < D; ++j) st[16 + 4 * fp.n_iter + j] = j < Dk ? Sb.s[j] / Sb.s[0] : 0.0;
+  }
+}
+
+// control words of every item to zero before a group launch (a kernel, not
+// a memset, so that a captured step holds no memset node)
+__global__ void k_grp_reset(int batch, unsigned* ctl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < batch * 4) ctl[(size_t)(i / 4) * GRP_CTL + i % 4] = 0u;
 }
 
 hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, const void* RX, const void* RY,
@@ -1103,27 +1821,76 @@ hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, co
   if (batch <= 0) return hipSuccess;
   if (R > FIT_RMAX || D > FIT_RMAX || R * D > 256) return hipErrorInvalidValue;
   size_t el = cplx ? 16 : 8;
+  constexpr size_t LDS_MAX = 160 * 1024 - 16 * 1024;
   // the n x CHOL_BS panel of the certification only for metrics it certifies
   const size_t cert_el = R * R <= FIT_CERT_NMAX ? (size_t)R * R * CHOL_BS : 0;
   const size_t work_el = std::max<size_t>(cert_el, (size_t)R * D * CHOL_BS + CHOL_BS * CHOL_BS + FAST_NX + 3 * CG_NX);
   size_t shm = fit_shared_fixed_bytes(el, R) + work_el * el;
   ph(PK_FIT, 0);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
   static bool attr_set[2] = {false, false};
+  static int ncu_of[64] = {};
   if (!attr_set[cplx ? 1 : 0]) {
     // allow the full 160 KiB of LDS for the dynamic part
-    hipError_t e = cplx ? hipFuncSetAttribute((const void*)k_bond_fit<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 16 * 1024)
-                        : hipFuncSetAttribute((const void*)k_bond_fit<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 16 * 1024);
+    e = cplx ? hipFuncSetAttribute((const void*)k_bond_fit<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_MAX)
+             : hipFuncSetAttribute((const void*)k_bond_fit<double>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_MAX);
+    if (e != hipSuccess) return e;
+    e = cplx ? hipFuncSetAttribute((const void*)k_bond_fit_grp<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_MAX)
+             : hipFuncSetAttribute((const void*)k_bond_fit_grp<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   LDS_MAX);
     if (e != hipSuccess) return e;
     attr_set[cplx ? 1 : 0] = true;
   }
-  if (shm > 160 * 1024 - 16 * 1024) return hipErrorInvalidValue;
+  if (dev >= 0 && dev < 64 && ncu_of[dev] == 0) {
+    int ncu = 0;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    ncu_of[dev] = ncu;
+  }
+  if (shm > LDS_MAX) return hipErrorInvalidValue;
+  // The group fit for certified items of a Trotter step (metric repair's
+  // certificate and the SVDU guess at hand), when every item's members fit
+  // on the chip at once (one workgroup per CU): G members per item, at most
+  // R, as few as give the same largest share of slabs.
+  int G = 0;
+  const int b8 = (batch + 7) / 8 * 8;
+  if (g && cert && guess && R <= 16 && D <= 8 && R * D <= GRP_NXMAX && D >= GRP_MIN_D && dev >= 0 && dev < 64) {
+    const int gmax = std::min(std::min(R, GRP_MAX), ncu_of[dev] / b8);
+    if (gmax >= 2) {
+      const int nsl = (R + gmax - 1) / gmax;
+      G = (R + nsl - 1) / nsl;
+      if (grp_shared_bytes(el, R, D, G) > LDS_MAX) G = 0;
+    }
+  }
+  const unsigned* redo = nullptr;
+  if (G >= 2) {
+    char* base = (char*)ws + align256((size_t)batch * fit_ws_elems(D, R) * el);
+    unsigned* ctl = (unsigned*)base;
+    base += align256((size_t)batch * GRP_CTL * 4);
+    char* xv = base;
+    base += align256((size_t)batch * 2 * R * R * el);
+    double* xs = (double*)base;
+    hipLaunchKernelGGL(k_grp_reset, dim3((batch * 4 + 255) / 256), dim3(256), 0, st, batch, ctl);
+    const size_t shg = grp_shared_bytes(el, R, D, G);
+    if (cplx)
+      hipLaunchKernelGGL(k_bond_fit_grp<cd>, dim3(b8 * G), dim3(FIT_THREADS), shg, st, batch, G, D, R, (const cd*)g,
+                         (const cd*)RX, (const cd*)RY, fp, (cd*)MX, (cd*)MY, stats, stats_stride, (cd*)ws, ctl,
+                         (cd*)xv, xs, cert, (const cd*)guess);
+    else
+      hipLaunchKernelGGL(k_bond_fit_grp<double>, dim3(b8 * G), dim3(FIT_THREADS), shg, st, batch, G, D, R,
+                         (const double*)g, (const double*)RX, (const double*)RY, fp, (double*)MX, (double*)MY, stats,
+                         stats_stride, (double*)ws, ctl, (double*)xv, xs, cert, (const double*)guess);
+    redo = ctl;
+  }
   if (cplx)
     hipLaunchKernelGGL(k_bond_fit<cd>, dim3(batch), dim3(FIT_THREADS), shm, st, D, R, (const cd*)g, (const cd*)RX,
-                       (const cd*)RY, fp, (cd*)MX, (cd*)MY, stats, stats_stride, (cd*)ws, cert, (const cd*)guess);
+                       (const cd*)RY, fp, (cd*)MX, (cd*)MY, stats, stats_stride, (cd*)ws, cert, (const cd*)guess, redo);
   else
     hipLaunchKernelGGL(k_bond_fit<double>, dim3(batch), dim3(FIT_THREADS), shm, st, D, R, (const double*)g,
                        (const double*)RX, (const double*)RY, fp, (double*)MX, (double*)MY, stats, stats_stride,
-                       (double*)ws, cert, (const double*)guess);
+                       (double*)ws, cert, (const double*)guess, redo);
   ph(PK_FIT, 1);
   return hipGetLastError();
 }
