@@ -59,6 +59,9 @@ NTU_HD bool finitev(cd a) { return isfinite(a.x) && isfinite(a.y); }
 template <class T> struct is_cplx { static constexpr bool value = false; };
 template <> struct is_cplx<cd> { static constexpr bool value = true; };
 
+// four doubles: the accumulator of a 16 x 16 x 4 FP64 matrix-core product
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------------------
 // wave / block reductions (wave64)
 // ---------------------------------------------------------------------------

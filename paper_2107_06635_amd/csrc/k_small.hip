@@ -1,6 +1,7 @@
 // Gate split (Fig. 2(a)), reduction + QR (Fig. 2(b)), recombination
 // (Fig. 2(e)) and the 90-degree rotation of site tensors.
 #include "kernels.h"
+#include "fastdiv.h"
 #include "linalg.h"
 #include <algorithm>
 
@@ -73,6 +74,10 @@ hipError_t launch_gate_split(bool cplx, int batch, int d, int rg, const void* ga
 // with the projection applied twice and the rank rule.  One workgroup per item.
 // ---------------------------------------------------------------------------
 template <class T> NTU_DEV T load_site(const double* p, long long i) { return realv<T>(p[i]); }
+// a site value as loaded, in the compute type
+template <class T> NTU_DEV T widen_site(double v) { return realv<T>(v); }
+template <class T> NTU_DEV T widen_site(cd v) { return v; }
+template <class T> NTU_DEV T widen_site(float2 v) { return cd{(double)v.x, (double)v.y}; }
 template <class T> NTU_DEV T load_site(const cd* p, long long i);
 template <> NTU_DEV cd load_site<cd>(const cd* p, long long i) { return p[i]; }
 template <class T> NTU_DEV T load_site(const float2* p, long long i);
@@ -383,8 +388,9 @@ constexpr double CQR_PIV = 1e-6;
 // Upper Cholesky factor Rf of the Hermitian n x n matrix G (G = Rf^H Rf) and
 // its inverse Ti, all row-major with stride CQR_RMAX.  Wave 0 (threadIdx.x <
 // 64); returns whether every pivot exceeds floor2 (same value on all lanes).
-template <class T>
+template <class T, int LDM = CQR_RMAX>
 NTU_DEV bool cqr_chol(const T* G, int n, double floor2, T* Rf, T* Ti) {
+  constexpr int CQR_RMAX = LDM;  // leading dimension of G, Rf, Ti
   const int lane = threadIdx.x;
   for (int e = lane; e < CQR_RMAX * CQR_RMAX; e += 64) {
     Rf[e] = zerov<T>();
@@ -545,15 +551,289 @@ __global__ void __launch_bounds__(CQR_THREADS) k_reduce_cholqr(int d, int na, in
   if (tid == 0) todo[ti] = 0;
 }
 
+// ---------------------------------------------------------------------------
+// The same Cholesky QR, applied twice, on the FP64 matrix cores for R <= 16,
+// with W never stored: forming an entry again from the site tensor costs d
+// products, less than storing the p D^3 x R matrix and reading it back, so
+// each of the three sweeps forms W again, chunk by chunk in shared memory:
+//   sweep 1: G1 = W^H W              -> R1 (pivot test), T1 = R1^{-1}
+//   sweep 2: Q1 = W T1, G2 = Q1^H Q1 -> R2, T2 = R2^{-1}
+//   sweep 3: Q = W (T1 T2), written once;  R = R2 R1.
+// Gram matrices: each wave adds 16 x 16 x 4 products over its K chunks of
+// rows (complex: four real products, A = conj(W)^T and B = W taken from the
+// same register), and the eight waves' sums are added in shared memory in a
+// fixed order.  Right products: one 16-row tile per wave, complex as four
+// real products.  Same pivot rule as k_reduce_cholqr.
+// ---------------------------------------------------------------------------
+constexpr int RQM_CH = 128;  // rows per chunk: eight waves x 16
+constexpr int RQM_LD = 17;   // elements per staged row (16 + 1 against bank conflicts)
+
+// divisors of the row and column decoding, fixed at launch
+struct RqDiv {
+  FastDiv D, D2, D3, na, rg;
+};
+
+template <class T, class S>
+__global__ void __launch_bounds__(512) k_reduce_cqr_mfma(int d, int na, int D, int rg, const S* site, const T* gf,
+                                                        long long gf_stride, int side, T* Q, T* Rm, double kappa,
+                                                        int* todo, ReduceY<T, S> yside, RqDiv dv,
+                                                        int stage_site) {
+  constexpr bool CPLX = is_cplx<T>::value;
+  constexpr int CQR_RMAX = 16;  // leading dimension of the small matrices here
+  __shared__ T gfs[32];
+  __shared__ T Wc[RQM_CH * RQM_LD];  // the chunk: W, then its product (each wave its own 16 rows)
+  __shared__ T Gm[CQR_RMAX * CQR_RMAX];
+  __shared__ T R1[CQR_RMAX * CQR_RMAX];
+  __shared__ T T1[CQR_RMAX * CQR_RMAX];
+  __shared__ T R2[CQR_RMAX * CQR_RMAX];
+  __shared__ T T2[CQR_RMAX * CQR_RMAX];
+  __shared__ T Tt[CQR_RMAX * CQR_RMAX];
+  __shared__ int ok;
+  // the item's site tensor, when the launch gives it room (stage_site)
+  extern __shared__ uint4 site_lds[];  // 16-byte aligned
+  if (blockIdx.y == 1) {  // the Y side of a two-sided launch
+    site = yside.site; gf = yside.gf; Q = yside.Q; Rm = yside.R; side = 1;
+  }
+  const int it = blockIdx.x, tid = threadIdx.x, ti = blockIdx.y * gridDim.x + blockIdx.x;
+  const int lane = tid & 63, w = tid >> 6, l16 = lane & 15, lk = lane >> 4;
+  const int p = d * na, R = D * rg;
+  const int D2 = D * D, D3 = D2 * D;
+  const long long D4 = (long long)D3 * D;
+  const int nrow = p * D3;
+  const S* X = site + (size_t)it * p * D4;
+  const T* Gf = gf + (size_t)it * gf_stride;
+  T* Qi = Q + (size_t)it * nrow * R;
+  T* Ri = Rm + (size_t)it * R * R;
+
+  // the gate factor (d d r_g <= 32 entries) in shared memory
+  if (tid < d * d * rg) gfs[tid] = Gf[tid];
+  // the whole site tensor in shared memory (one pass of 16-byte loads, all
+  // in flight), so that the three sweeps form W without global loads
+  const S* Xsrc = X;
+  if (stage_site) {
+    const long long nb = (long long)p * D4 * sizeof(S) / 16;
+    const uint4* src = (const uint4*)X;
+    uint4* dst = site_lds;
+    for (long long e = tid; e < nb; e += blockDim.x) dst[e] = src[e];
+    Xsrc = (const S*)site_lds;
+  }
+  // W rows [c0, c0 + rows) into Wc (zero beyond rows and R): thread t takes
+  // row t / 4 and the columns t % 4 + 4 u; d <= 2 site values per entry,
+  // loaded raw (load_chunk) a chunk ahead of their use (store_chunk)
+  const int rl = tid >> 2, cq = tid & 3;
+  S raw[4][2];
+  auto load_chunk = [&](int c0) {
+    const unsigned row = (unsigned)min(c0 + rl, nrow - 1);
+    const unsigned i4 = fmod_(row, dv.D), i3 = fmod_(fdiv(row, dv.D), dv.D), tt = fmod_(fdiv(row, dv.D2), dv.D);
+    const unsigned pa = fdiv(row, dv.D3), a = fmod_(pa, dv.na);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const unsigned col = (unsigned)min(cq + 4 * u, R - 1), q = fdiv(col, dv.rg);
+      const long long inner = side == 0 ? (long long)(i3 * D2 + i4 * D + q) : (long long)(q * D2 + i3 * D + i4);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int sc = min(s, d - 1);
+        raw[u][s] = Xsrc[(long long)(sc * na + a) * D4 + (long long)tt * D3 + inner];
+      }
+    }
+  };
+  auto store_chunk = [&](int c0, int rows) {
+    const unsigned row = (unsigned)min(c0 + rl, nrow - 1);
+    const unsigned sp = fdiv(fdiv(row, dv.D3), dv.na);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int col = cq + 4 * u;
+      const unsigned k = fmod_((unsigned)min(col, R - 1), dv.rg);
+      T acc = zerov<T>();
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        if (s < d) acc += gfs[(sp * d + s) * rg + k] * widen_site<T>(raw[u][s]);
+      Wc[rl * RQM_LD + col] = (rl < rows && col < R) ? acc : zerov<T>();
+    }
+  };
+  // the wave's share of a Gram matrix of the staged chunk src
+  f64x4 gre, gim;
+  auto gram_chunk = [&](const T* src) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const T v = src[(4 * (w + 8 * m) + lk) * RQM_LD + l16];
+      if constexpr (CPLX) {
+        gre = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, v.x, gre, 0, 0, 0);
+        gre = __builtin_amdgcn_mfma_f64_16x16x4f64(v.y, v.y, gre, 0, 0, 0);
+        gim = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, v.y, gim, 0, 0, 0);
+        gim = __builtin_amdgcn_mfma_f64_16x16x4f64(-v.y, v.x, gim, 0, 0, 0);
+      } else {
+        gre = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, gre, 0, 0, 0);
+      }
+    }
+  };
+  // the eight waves' sums into Gm (Pc as scratch); whole block
+  auto gram_reduce = [&]() {
+    // 8 waves x (re[, im]) x 256 doubles: 32 KiB complex, 16 KiB real, within Pc
+    constexpr int NP = CPLX ? 2 : 1;
+    double* sc = (double*)Wc;  // free after the sweep's last chunk
+    static_assert(8 * NP * 256 * sizeof(double) <= sizeof(T) * RQM_CH * RQM_LD, "scratch of the Gram sums");
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int e = (lk + 4 * v) * 16 + l16;
+      sc[(w * NP + 0) * 256 + e] = gre[v];
+      if constexpr (CPLX) sc[(w * NP + 1) * 256 + e] = gim[v];
+    }
+    __syncthreads();
+    if (tid < 256) {
+      double sr = 0.0, si = 0.0;
+      for (int k = 0; k < 8; ++k) {
+        sr += sc[(k * NP + 0) * 256 + tid];
+        if constexpr (CPLX) si += sc[(k * NP + 1) * 256 + tid];
+      }
+      const int i = tid >> 4, j = tid & 15;
+      if (i < R && j < R) {
+        if constexpr (CPLX) Gm[i * CQR_RMAX + j] = T{sr, si};
+        else Gm[i * CQR_RMAX + j] = sr;
+      }
+    }
+    __syncthreads();
+  };
+  // this wave's 16-row tile of Wc times the upper triangular Tm (operands
+  // from registers tb) -> Pc, or Q at chunk row offset c0
+  T tb[4];
+  auto load_tb = [&](const T* Tm) {
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const int k = 4 * kc + lk;
+      tb[kc] = (k < R && l16 < R) ? Tm[k * CQR_RMAX + l16] : zerov<T>();
+    }
+  };
+  auto product_chunk = [&](int c0, int rows, bool to_global) {
+    f64x4 pr = {0.0, 0.0, 0.0, 0.0}, pi = {0.0, 0.0, 0.0, 0.0};
+    T av[4];  // the wave's rows read before they are overwritten
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) av[kc] = Wc[(16 * w + l16) * RQM_LD + 4 * kc + lk];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const T a = av[kc];
+      if constexpr (CPLX) {
+        pr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, tb[kc].x, pr, 0, 0, 0);
+        pr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, tb[kc].y, pr, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, tb[kc].y, pi, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, tb[kc].x, pi, 0, 0, 0);
+      } else {
+        pr = __builtin_amdgcn_mfma_f64_16x16x4f64(a, tb[kc], pr, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rl = 16 * w + lk + 4 * v;
+      T val;
+      if constexpr (CPLX) val = T{pr[v], pi[v]};
+      else val = pr[v];
+      if (to_global) {
+        if (rl < rows && l16 < R) Qi[(size_t)(c0 + rl) * R + l16] = val;
+      } else {
+        Wc[rl * RQM_LD + l16] = val;  // this wave's own rows
+      }
+    }
+  };
+  auto zero_acc = [&]() {
+    gre = f64x4{0.0, 0.0, 0.0, 0.0};
+    gim = f64x4{0.0, 0.0, 0.0, 0.0};
+  };
+
+  // sweep 1: Gram of W, first factor
+  __syncthreads();  // gfs
+  zero_acc();
+  load_chunk(0);
+  for (int c0 = 0; c0 < nrow; c0 += RQM_CH) {
+    store_chunk(c0, min(RQM_CH, nrow - c0));
+    __syncthreads();
+    load_chunk(c0 + RQM_CH);
+    gram_chunk(Wc);
+    __syncthreads();
+  }
+  gram_reduce();
+  if (tid < 64) {
+    double mx = 0;
+    for (int j = 0; j < R; ++j) mx = fmax(mx, rev(Gm[j * CQR_RMAX + j]));
+    const double piv = fmax(CQR_PIV, 1e3 * kappa);
+    const bool g1 = mx > 0 && cqr_chol<T, CQR_RMAX>(Gm, R, piv * piv * mx, R1, T1);
+    if (tid == 0) ok = g1 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!ok) {
+    if (tid == 0) todo[ti] = 1;
+    return;
+  }
+  // sweep 2: Q1 = W T1 and its Gram matrix, second factor (pivots near 1)
+  load_tb(T1);
+  zero_acc();
+  load_chunk(0);
+  for (int c0 = 0; c0 < nrow; c0 += RQM_CH) {
+    const int rows = min(RQM_CH, nrow - c0);
+    store_chunk(c0, rows);
+    __syncthreads();
+    load_chunk(c0 + RQM_CH);
+    product_chunk(c0, rows, false);
+    __syncthreads();
+    gram_chunk(Wc);
+    __syncthreads();
+  }
+  gram_reduce();
+  if (tid < 64) {
+    const bool g2 = cqr_chol<T, CQR_RMAX>(Gm, R, 0.25, R2, T2);
+    if (tid == 0) ok = g2 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!ok) {
+    if (tid == 0) todo[ti] = 1;
+    return;
+  }
+  // T = T1 T2 (upper triangular), R = R2 R1
+  for (int e = tid; e < R * R; e += blockDim.x) {
+    const int i = e / R, j = e % R;
+    T t = zerov<T>(), r = zerov<T>();
+    for (int l = i; l <= j; ++l) {
+      t += T1[i * CQR_RMAX + l] * T2[l * CQR_RMAX + j];
+      r += R2[i * CQR_RMAX + l] * R1[l * CQR_RMAX + j];
+    }
+    Tt[i * CQR_RMAX + j] = t;
+    Ri[e] = r;
+  }
+  for (int e = tid; e < CQR_RMAX * CQR_RMAX; e += blockDim.x)
+    if (e / CQR_RMAX >= R || e % CQR_RMAX >= R || e / CQR_RMAX > e % CQR_RMAX) Tt[e] = zerov<T>();
+  __syncthreads();
+  // sweep 3: Q = W T
+  load_tb(Tt);
+  load_chunk(0);
+  for (int c0 = 0; c0 < nrow; c0 += RQM_CH) {
+    const int rows = min(RQM_CH, nrow - c0);
+    store_chunk(c0, rows);
+    __syncthreads();
+    load_chunk(c0 + RQM_CH);
+    product_chunk(c0, rows, true);
+    __syncthreads();
+  }
+  if (tid == 0) todo[ti] = 0;
+}
+
 template <class T, class S>
 static void reduce_launch(int batch, int sides, int d, int na, int D, int rg, const void* site, const void* gf,
                           long long gf_stride, int side, void* Q, void* R, const void* site_y, const void* gf_y,
                           void* Q_y, void* R_y, double kappa, int* todo, hipStream_t st) {
   const ReduceY<T, S> y{(const S*)site_y, (const T*)gf_y, (T*)Q_y, (T*)R_y};
   const dim3 g(batch, sides);
-  if (todo)
-    hipLaunchKernelGGL((k_reduce_cholqr<T, S>), g, dim3(CQR_THREADS), 0, st, d, na, D, rg, (const S*)site,
-                       (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, todo, y);
+  if (todo) {
+    if (D * rg <= 16 && d <= 2 && d * d * rg <= 32) {
+      const RqDiv dv{make_fastdiv(D), make_fastdiv(D * D), make_fastdiv(D * D * D), make_fastdiv(na), make_fastdiv(rg)};
+      // the site tensor in shared memory when it takes at most 64 KiB (and
+      // its size is a multiple of 16 bytes)
+      const size_t site_bytes = (size_t)d * na * D * D * D * D * sizeof(S);
+      const int stage = site_bytes <= 64 * 1024 && site_bytes % 16 == 0 ? 1 : 0;
+      hipLaunchKernelGGL((k_reduce_cqr_mfma<T, S>), g, dim3(512), stage ? site_bytes : 0, st, d, na, D, rg,
+                         (const S*)site, (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, todo, y, dv, stage);
+    } else
+      hipLaunchKernelGGL((k_reduce_cholqr<T, S>), g, dim3(CQR_THREADS), 0, st, d, na, D, rg, (const S*)site,
+                         (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, todo, y);
+  }
   // Gram-Schmidt for the items the Cholesky QR left (all items without todo).
   // Real: rows in registers when they fit (up to 2048 rows; measured four
   // times faster at 2048 rows).  Complex: the version that sweeps W in memory

@@ -434,8 +434,11 @@ def test_library_graph_steps_match_oracle(D, precision, storage):
     opts = ntu.step_opts(precision, n_iter=N_ITER, early_stop=True, conv_tol=CONV, graph=True)
     opts_e = ntu.step_opts(precision, n_iter=N_ITER, early_stop=True, conv_tol=CONV)
     # complex64 storage rounds the state to 6e-8 relative after every step;
-    # the two sides' rounding of the (gauge-equivalent) tensors differs at that level
-    tol_obs = 1e-6 if precision != "f64" else (1e-7 if storage == "c64" else 1e-9)
+    # the two sides return gauge-equivalent tensors (the phases of singular
+    # vector pairs are free), whose roundings differ by up to that much per
+    # entry, and the observables of such states by about 1e-7 (measured up
+    # to 1.7e-7 relative): 1e-6 on either path with complex64 storage
+    tol_obs = 1e-6 if (precision != "f64" or storage == "c64") else 1e-9
     for step in range(3):
         Ao, Bo, infos = O.trotter_step(A.astype(np.complex128), B.astype(np.complex128), pairs, D, n_iter=N_ITER,
                                        conv_tol=CONV)
