@@ -176,6 +176,8 @@ __global__ void __launch_bounds__(256) k_mfma_nt(const TA* __restrict__ A, const
 // ---------------------------------------------------------------------------
 constexpr int TL_M = 128, TL_N = 128, TL_K = 32, TL_LD = TL_K;
 constexpr int TL_THREADS = 512, TL_WY = 2;  // 8 waves; each 64 x (16 TL_WY)
+// the FP16X3 assembly from pre-split operands: each wave 64 x (16 F16_WY)
+constexpr int F16_WY = 2;
 
 // Shared-memory layout of an operand tile: unpadded rows of TL_K pieces (64
 // bytes, a quarter of the 64 four-byte banks), the four 16-byte chunks of row
@@ -535,18 +537,19 @@ struct TileF16Args {
   double* partial;              // ksplit > 1: [split][item][M][2N]
 };
 
-template <class TC>
+template <class TC, int WY>
 __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile_f16(const unsigned* __restrict__ A,
                                                               const unsigned* __restrict__ B, TC* __restrict__ C,
                                                               TileF16Args ta) {
   using E = _Float16;
   constexpr int NT = 2;
   constexpr int NGA = TL_M * TL_K / 4 / TL_THREADS;  // groups of 4 reals (2 complex) of A per thread
-  constexpr int NGB = NGA / 2;                       // of B (each complex row gives two real rows)
-  constexpr int SA_EL = 2 * NT * TL_M * TL_LD, SB_EL = 2 * NT * TL_N * TL_LD;
+  constexpr int TN = 64 * WY;                        // columns of the tile: four waves of 16 WY
+  constexpr int NGB = TN / 2 * TL_K / 4 / TL_THREADS;  // of B (each complex row gives two real rows)
+  constexpr int SA_EL = 2 * NT * TL_M * TL_LD, SB_EL = 2 * NT * TN * TL_LD;
   __shared__ __attribute__((aligned(16))) E smem[SA_EL + SB_EL];
   E (*sA)[NT][TL_M][TL_LD] = reinterpret_cast<E (*)[NT][TL_M][TL_LD]>(smem);
-  E (*sB)[NT][TL_N][TL_LD] = reinterpret_cast<E (*)[NT][TL_N][TL_LD]>(smem + SA_EL);
+  E (*sB)[NT][TN][TL_LD] = reinterpret_cast<E (*)[NT][TN][TL_LD]>(smem + SA_EL);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 2, wn = wv & 3;
   const int per = (ta.nwork + 7) / 8;
   const int q = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
@@ -554,7 +557,7 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile_f16(const unsigned* __
   const int T = ta.tiles_m * ta.tiles_n;
   const int item = q / (T * ta.ksplit), rem = q % (T * ta.ksplit);
   const int tile = rem / ta.ksplit, split = rem % ta.ksplit;
-  const int i0 = (tile / ta.tiles_n) * TL_M, j0 = (tile % ta.tiles_n) * TL_N;
+  const int i0 = (tile / ta.tiles_n) * TL_M, j0 = (tile % ta.tiles_n) * TN;
   const int Mr = ta.M, Nr = 2 * ta.N, Kr = 2 * ta.Kc;
   const int kbeg = split * ta.kchunk, kend = min(Kr, kbeg + ta.kchunk);
   const unsigned* Ab = A + (size_t)item * ta.a_item;
@@ -635,13 +638,13 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile_f16(const unsigned* __
     }
   };
 
-  f32x4 acc[2][4][TL_WY];
+  f32x4 acc[2][4][WY];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int y = 0; y < TL_WY; ++y) acc[c][x][y] = f32x4{0, 0, 0, 0};
+      for (int y = 0; y < WY; ++y) acc[c][x][y] = f32x4{0, 0, 0, 0};
 
   // An even number of steps, every load and store unconditional: a step
   // beyond the chunk loads clamped addresses whose values are zeroed, and
@@ -659,8 +662,8 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile_f16(const unsigned* __
     for (int x = 0; x < 4; ++x) {
       const int ra_ = wm * 64 + x * 16 + fr;
 #pragma unroll
-      for (int y = 0; y < TL_WY; ++y) {
-        const int rb_ = wn * (16 * TL_WY) + y * 16 + fr;
+      for (int y = 0; y < WY; ++y) {
+        const int rb_ = wn * (16 * WY) + y * 16 + fr;
         const E* a0 = &sA[buf][0][ra_][fks];
         const E* a1 = &sA[buf][1][ra_][fks];
         const E* b0 = &sB[buf][0][rb_][fks];
@@ -688,11 +691,11 @@ __global__ void __launch_bounds__(TL_THREADS) k_mfma_tile_f16(const unsigned* __
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < TL_WY; ++y)
+    for (int y = 0; y < WY; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + wm * 64 + x * 16 + 4 * (lane >> 4) + v;
-        const int jr = j0 + wn * (16 * TL_WY) + y * 16 + (lane & 15);
+        const int jr = j0 + wn * (16 * WY) + y * 16 + (lane & 15);
         if (i >= Mr || jr >= Nr) continue;
         const double un = 1.0 / ((double)sAi[i] * (double)sBi[jr >> 1]);
         const double val = ((double)acc[0][x][y][v] + (double)acc[1][x][y][v] * (1.0 / 2048.0)) * un;
@@ -801,8 +804,9 @@ static hipError_t run_tile_f16(const void* A, const void* B, void* C, const Gemm
   a.a_row = 2LL * d.K; a.b_row = 2LL * d.K;
   a.sA = sA; a.sB = sB;
   a.Cb = d.Cb; a.Ci = d.Ci; a.Cj = d.Cj;
+  constexpr int WY = F16_WY;
   a.tiles_m = (Mr + TL_M - 1) / TL_M;
-  a.tiles_n = (Nr + TL_N - 1) / TL_N;
+  a.tiles_n = (Nr + 64 * WY - 1) / (64 * WY);
   a.ksplit = ksplit < 1 ? 1 : ksplit;
   int chunk = (Kr + a.ksplit - 1) / a.ksplit;
   chunk = (chunk + TL_K - 1) / TL_K * TL_K;
@@ -812,7 +816,7 @@ static hipError_t run_tile_f16(const void* A, const void* B, void* C, const Gemm
   a.partial = partial;
   const int per = (a.nwork + 7) / 8;
   ph(kind, 0);
-  hipLaunchKernelGGL((k_mfma_tile_f16<double>), dim3(8 * per), dim3(TL_THREADS), 0, st, (const unsigned*)A,
+  hipLaunchKernelGGL((k_mfma_tile_f16<double, WY>), dim3(8 * per), dim3(TL_THREADS), 0, st, (const unsigned*)A,
                      (const unsigned*)B, (double*)C, a);
   ph(kind, 1);
   hipError_t e = hipGetLastError();

@@ -390,9 +390,8 @@ constexpr double CQR_PIV = 1e-6;
 // 64); returns whether every pivot exceeds floor2 (same value on all lanes).
 template <class T, int LDM = CQR_RMAX>
 NTU_DEV bool cqr_chol(const T* G, int n, double floor2, T* Rf, T* Ti) {
-  constexpr int CQR_RMAX = LDM;  // leading dimension of G, Rf, Ti
   const int lane = threadIdx.x;
-  for (int e = lane; e < CQR_RMAX * CQR_RMAX; e += 64) {
+  for (int e = lane; e < LDM * LDM; e += 64) {
     Rf[e] = zerov<T>();
     Ti[e] = zerov<T>();
   }
@@ -401,23 +400,23 @@ NTU_DEV bool cqr_chol(const T* G, int n, double floor2, T* Rf, T* Ti) {
   for (int k = 0; k < n; ++k) {
     T sv = zerov<T>();
     if (lane >= k && lane < n) {
-      sv = G[k * CQR_RMAX + lane];
-      for (int i = 0; i < k; ++i) sv -= cmul(Rf[i * CQR_RMAX + k], Rf[i * CQR_RMAX + lane]);
+      sv = G[k * LDM + lane];
+      for (int i = 0; i < k; ++i) sv -= cmul(Rf[i * LDM + k], Rf[i * LDM + lane]);
     }
     const double piv = __shfl(rev(sv), k, 64);
     good = good && piv > floor2 && isfinite(piv);
     const double rkk = good ? sqrt(piv) : 1.0;
-    if (lane == k) Rf[k * CQR_RMAX + k] = realv<T>(rkk);
-    else if (lane > k && lane < n) Rf[k * CQR_RMAX + lane] = sv * (1.0 / rkk);
+    if (lane == k) Rf[k * LDM + k] = realv<T>(rkk);
+    else if (lane > k && lane < n) Rf[k * LDM + lane] = sv * (1.0 / rkk);
     wave_sync_lds();
   }
   if (lane < n) {
     const int j = lane;
-    Ti[j * CQR_RMAX + j] = realv<T>(1.0 / rev(Rf[j * CQR_RMAX + j]));
+    Ti[j * LDM + j] = realv<T>(1.0 / rev(Rf[j * LDM + j]));
     for (int i = j - 1; i >= 0; --i) {
       T acc = zerov<T>();
-      for (int l = i + 1; l <= j; ++l) acc += Rf[i * CQR_RMAX + l] * Ti[l * CQR_RMAX + j];
-      Ti[i * CQR_RMAX + j] = acc * (-1.0 / rev(Rf[i * CQR_RMAX + i]));
+      for (int l = i + 1; l <= j; ++l) acc += Rf[i * LDM + l] * Ti[l * LDM + j];
+      Ti[i * LDM + j] = acc * (-1.0 / rev(Rf[i * LDM + i]));
     }
   }
   wave_sync_lds();
@@ -815,6 +814,230 @@ __global__ void __launch_bounds__(512) k_reduce_cqr_mfma(int d, int na, int D, i
   if (tid == 0) todo[ti] = 0;
 }
 
+// ---------------------------------------------------------------------------
+// The same Cholesky QR, twice, with W formed once and kept in registers for
+// the three sweeps.  Wave w holds rows [w 4 KPW, (w + 1) 4 KPW) in the
+// operand layout of the 16 x 16 x 4 FP64 Gram products (register c of lane l:
+// row 4 c + l / 16 of the wave's block, column l % 16), so both Gram
+// matrices are formed straight from registers.  The right products need the
+// transposed layout (rows along the lanes of a 16-lane row): a 16-row tile
+// passes through a 16 x 16 buffer of the wave's own in shared memory, and
+// the product comes back in the Gram layout, ready for the second Gram
+// matrix and for coalesced stores of Q.  Needs R <= 16, d <= 2 and p D^3 <=
+// 32 KPW rows.
+// ---------------------------------------------------------------------------
+template <class T, class S, int KPW>
+__global__ void __launch_bounds__(512) k_reduce_cqr_reg(int d, int na, int D, int rg, const S* site, const T* gf,
+                                                       long long gf_stride, int side, T* Q, T* Rm, double kappa,
+                                                       int* todo, ReduceY<T, S> yside, RqDiv dv, int stage_site) {
+  constexpr bool CPLX = is_cplx<T>::value;
+  constexpr int CQR_RMAX = 16;  // leading dimension of the small matrices here
+  __shared__ T gfs[32];
+  __shared__ T tbuf[8][16 * 17];  // per wave: one 16 x 16 tile (leading dimension 17)
+  __shared__ double gsum[8 * 2 * 256];
+  __shared__ T Gm[CQR_RMAX * CQR_RMAX];
+  __shared__ T R1[CQR_RMAX * CQR_RMAX];
+  __shared__ T T1[CQR_RMAX * CQR_RMAX];
+  __shared__ T R2[CQR_RMAX * CQR_RMAX];
+  __shared__ T T2[CQR_RMAX * CQR_RMAX];
+  __shared__ T Tt[CQR_RMAX * CQR_RMAX];
+  __shared__ int ok;
+  extern __shared__ uint4 site_lds[];  // the item's site tensor when stage_site (16-byte aligned)
+  if (blockIdx.y == 1) {  // the Y side of a two-sided launch
+    site = yside.site; gf = yside.gf; Q = yside.Q; Rm = yside.R; side = 1;
+  }
+  const int it = blockIdx.x, tid = threadIdx.x, ti = blockIdx.y * gridDim.x + blockIdx.x;
+  const int lane = tid & 63, w = tid >> 6, l16 = lane & 15, lk = lane >> 4;
+  const int p = d * na, R = D * rg;
+  const int D2 = D * D, D3 = D2 * D;
+  const long long D4 = (long long)D3 * D;
+  const int nrow = p * D3;
+  const int base = w * 4 * KPW;
+  const S* X = site + (size_t)it * p * D4;
+  const T* Gf = gf + (size_t)it * gf_stride;
+  T* Qi = Q + (size_t)it * nrow * R;
+  T* Ri = Rm + (size_t)it * R * R;
+  if (tid < d * d * rg) gfs[tid] = Gf[tid];
+  const S* Xsrc = X;
+  if (stage_site) {
+    const long long nb = (long long)p * D4 * sizeof(S) / 16;
+    const uint4* src = (const uint4*)X;
+    for (long long e = tid; e < nb; e += blockDim.x) site_lds[e] = src[e];
+    Xsrc = (const S*)site_lds;
+  }
+  __syncthreads();
+  // W in registers: wr[c] = W[base + 4 c + lk][l16] (zero beyond nrow and R),
+  // formed four chunks at a time (their loads in flight together)
+  T wr[KPW];
+  {
+    const unsigned col = (unsigned)min(l16, R - 1), q = fdiv(col, dv.rg), k = fmod_(col, dv.rg);
+    const bool colok = l16 < R;
+#pragma unroll
+    for (int c0 = 0; c0 < KPW; c0 += 4) {
+      S raw[4][2];
+      unsigned spv[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const unsigned row = (unsigned)min(base + 4 * (c0 + c) + lk, nrow - 1);
+        const unsigned i4 = fmod_(row, dv.D), i3 = fmod_(fdiv(row, dv.D), dv.D), tt = fmod_(fdiv(row, dv.D2), dv.D);
+        const unsigned pa = fdiv(row, dv.D3), a = fmod_(pa, dv.na);
+        spv[c] = fdiv(pa, dv.na);
+        const long long inner = side == 0 ? (long long)(i3 * D2 + i4 * D + q) : (long long)(q * D2 + i3 * D + i4);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int sc = min(s, d - 1);
+          raw[c][s] = Xsrc[(long long)(sc * na + a) * D4 + (long long)tt * D3 + inner];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        T acc = zerov<T>();
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+          if (s < d) acc += gfs[(spv[c] * d + s) * rg + k] * widen_site<T>(raw[c][s]);
+        const int row = base + 4 * (c0 + c) + lk;
+        wr[c0 + c] = (row < nrow && colok) ? acc : zerov<T>();
+      }
+    }
+  }
+  f64x4 gre = {0.0, 0.0, 0.0, 0.0}, gim = {0.0, 0.0, 0.0, 0.0};
+  auto gram_add = [&](const T& v) {
+    if constexpr (CPLX) {
+      gre = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, v.x, gre, 0, 0, 0);
+      gre = __builtin_amdgcn_mfma_f64_16x16x4f64(v.y, v.y, gre, 0, 0, 0);
+      gim = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, v.y, gim, 0, 0, 0);
+      gim = __builtin_amdgcn_mfma_f64_16x16x4f64(-v.y, v.x, gim, 0, 0, 0);
+    } else {
+      gre = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, gre, 0, 0, 0);
+    }
+  };
+  // the eight waves' sums into Gm (fixed order); whole block
+  auto gram_reduce = [&]() {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int e = (lk + 4 * v) * 16 + l16;
+      gsum[(w * 2 + 0) * 256 + e] = gre[v];
+      gsum[(w * 2 + 1) * 256 + e] = CPLX ? gim[v] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 256) {
+      double sr = 0.0, si = 0.0;
+      for (int k = 0; k < 8; ++k) {
+        sr += gsum[(k * 2 + 0) * 256 + tid];
+        si += gsum[(k * 2 + 1) * 256 + tid];
+      }
+      const int i = tid >> 4, j = tid & 15;
+      if (i < R && j < R) {
+        if constexpr (CPLX) Gm[i * CQR_RMAX + j] = T{sr, si};
+        else Gm[i * CQR_RMAX + j] = sr;
+      }
+    }
+    __syncthreads();
+  };
+  // tile t of the wave (registers 4 t .. 4 t + 3) times the upper triangular
+  // matrix whose B operands are tb: the product in the Gram layout (pv[v]:
+  // row 16 t + 4 v + lk, column l16)
+  T tb[4];
+  auto load_tb = [&](const T* Tm) {
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const int kk = 4 * kc + lk;
+      tb[kc] = (kk < R && l16 < R) ? Tm[kk * CQR_RMAX + l16] : zerov<T>();
+    }
+  };
+  T* tw = tbuf[w];
+  auto tile_product = [&](int t, T (&pv)[4]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) tw[(4 * v + lk) * 17 + l16] = wr[4 * t + v];
+    wave_sync_lds();
+    T av[4];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) av[kc] = tw[l16 * 17 + 4 * kc + lk];
+    wave_sync_lds();
+    f64x4 pr = {0.0, 0.0, 0.0, 0.0}, pi = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      if constexpr (CPLX) {
+        pr = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kc].x, tb[kc].x, pr, 0, 0, 0);
+        pr = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[kc].y, tb[kc].y, pr, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kc].x, tb[kc].y, pi, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kc].y, tb[kc].x, pi, 0, 0, 0);
+      } else {
+        pr = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kc], tb[kc], pr, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if constexpr (CPLX) pv[v] = T{pr[v], pi[v]};
+      else pv[v] = pr[v];
+    }
+  };
+
+  // sweep 1: Gram of W, first factor
+#pragma unroll
+  for (int c = 0; c < KPW; ++c) gram_add(wr[c]);
+  gram_reduce();
+  if (tid < 64) {
+    double mx = 0;
+    for (int j = 0; j < R; ++j) mx = fmax(mx, rev(Gm[j * CQR_RMAX + j]));
+    const double piv = fmax(CQR_PIV, 1e3 * kappa);
+    const bool g1 = mx > 0 && cqr_chol<T, CQR_RMAX>(Gm, R, piv * piv * mx, R1, T1);
+    if (tid == 0) ok = g1 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!ok) {
+    if (tid == 0) todo[ti] = 1;
+    return;
+  }
+  // sweep 2: Q1 = W T1 tile by tile, its Gram matrix from the products
+  load_tb(T1);
+  gre = f64x4{0.0, 0.0, 0.0, 0.0};
+  gim = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < KPW / 4; ++t) {
+    T pv[4];
+    tile_product(t, pv);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gram_add(pv[v]);
+  }
+  gram_reduce();
+  if (tid < 64) {
+    const bool g2 = cqr_chol<T, CQR_RMAX>(Gm, R, 0.25, R2, T2);
+    if (tid == 0) ok = g2 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!ok) {
+    if (tid == 0) todo[ti] = 1;
+    return;
+  }
+  // T = T1 T2 (upper triangular), R = R2 R1
+  for (int e = tid; e < CQR_RMAX * CQR_RMAX; e += blockDim.x) {
+    const int i = e / CQR_RMAX, j = e % CQR_RMAX;
+    T t = zerov<T>(), r = zerov<T>();
+    if (i < R && j < R)
+      for (int l = i; l <= j; ++l) {
+        t += T1[i * CQR_RMAX + l] * T2[l * CQR_RMAX + j];
+        r += R2[i * CQR_RMAX + l] * R1[l * CQR_RMAX + j];
+      }
+    Tt[e] = t;
+    if (i < R && j < R) Ri[i * R + j] = r;
+  }
+  __syncthreads();
+  // sweep 3: Q = W T, stored row by row
+  load_tb(Tt);
+#pragma unroll
+  for (int t = 0; t < KPW / 4; ++t) {
+    T pv[4];
+    tile_product(t, pv);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = base + 16 * t + 4 * v + lk;
+      if (row < nrow && l16 < R) Qi[(size_t)row * R + l16] = pv[v];
+    }
+  }
+  if (tid == 0) todo[ti] = 0;
+}
+
 template <class T, class S>
 static void reduce_launch(int batch, int sides, int d, int na, int D, int rg, const void* site, const void* gf,
                           long long gf_stride, int side, void* Q, void* R, const void* site_y, const void* gf_y,
@@ -828,8 +1051,16 @@ static void reduce_launch(int batch, int sides, int d, int na, int D, int rg, co
       // its size is a multiple of 16 bytes)
       const size_t site_bytes = (size_t)d * na * D * D * D * D * sizeof(S);
       const int stage = site_bytes <= 64 * 1024 && site_bytes % 16 == 0 ? 1 : 0;
-      hipLaunchKernelGGL((k_reduce_cqr_mfma<T, S>), g, dim3(512), stage ? site_bytes : 0, st, d, na, D, rg,
-                         (const S*)site, (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, todo, y, dv, stage);
+      const long long nrow = (long long)d * na * D * D * D;
+      // W in registers when its rows fit the eight waves (32 complex or 64
+      // real registers per lane), else staged chunk by chunk
+      constexpr int KPW = is_cplx<T>::value ? 32 : 64;
+      if (nrow <= 32LL * KPW)
+        hipLaunchKernelGGL((k_reduce_cqr_reg<T, S, KPW>), g, dim3(512), stage ? site_bytes : 0, st, d, na, D, rg,
+                           (const S*)site, (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, todo, y, dv, stage);
+      else
+        hipLaunchKernelGGL((k_reduce_cqr_mfma<T, S>), g, dim3(512), stage ? site_bytes : 0, st, d, na, D, rg,
+                           (const S*)site, (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, todo, y, dv, stage);
     } else
       hipLaunchKernelGGL((k_reduce_cholqr<T, S>), g, dim3(CQR_THREADS), 0, st, d, na, D, rg, (const S*)site,
                          (const T*)gf, gf_stride, side, (T*)Q, (T*)R, kappa, todo, y);
