@@ -368,8 +368,9 @@ class Runner:
         return ev0.elapsed_time(ev1), state, stats, prof
 
 
-KERNEL_OF = {"bond_fit": "k_bond_fit", "env_left_right": "k_right", "env_e4": "k_left_e45",
-             "reduce_qr": "k_reduce_cholqr", "recombine": "k_recombine",
+KERNEL_OF = {"bond_fit": "k_bond_fit_grp (with k_grp_reset, and k_bond_fit for the items it leaves)",
+             "env_left_right": "k_right", "env_e4": "k_left_e45",
+             "reduce_qr": "k_reduce_cqr_reg (with k_reduce_qr for the items it leaves)", "recombine": "k_recombine",
              "env_e5": "k_mfma_tile (L2)", "env_e6": "k_mfma_tile (g = L2 Right^T)"}
 
 
