@@ -59,6 +59,36 @@ def zz_gate(dt: float) -> np.ndarray:
     return np.diag(np.exp(1j * dt * np.diag(np.kron(PAULI_Z, PAULI_Z)).real))
 
 
+def hermitian_thermal_gate(hx: float, hz: float, dbeta: float) -> np.ndarray:
+    """Two-site gate of the manifestly Hermitian purification (Sec. IV).
+
+    The non-trivial bond gate of Eq. (10), ``exp(dbeta Z Z / 4)`` (equal to
+    ``1 + tanh(dbeta / 4) Z Z`` up to a scale), between the on-site field
+    gates ``s = exp((dbeta / 32)(h_x X + h_z Z))`` on both sites, before and
+    after: ``(s x s) exp(dbeta Z Z / 4) (s x s)``.  Every site has four bonds,
+    so one sweep over the four bond types gives each site ``s^8 =
+    exp(dbeta (h_x X + h_z Z) / 4)``, i.e. ``exp(-dbeta H / 4)`` of Eq. (9)
+    to first order in ``dbeta``.  The local factors leave the operator-Schmidt
+    rank of the bond gate at two (four for its action ``G rho G^dagger``).
+    Real, 4 x 4, rows ``(s1', s2')``, columns ``(s1, s2)``.
+    """
+    w, v = np.linalg.eigh((hx * PAULI_X + hz * PAULI_Z).real)
+    s = (v * np.exp(dbeta / 32.0 * w)) @ v.T
+    ss = np.kron(s, s)
+    zz = np.diag(np.exp(0.25 * dbeta * np.diag(np.kron(PAULI_Z, PAULI_Z)).real))
+    return ss @ zz @ ss
+
+
+def hermitian_identity(D: int) -> tuple[np.ndarray, np.ndarray]:
+    """beta = 0 state of the Hermitian purification: ``rho(0/2) = 1`` on every
+    site, i.e. coefficient 1 on the fourth basis operator (the identity, in
+    the basis ``O = (X, Y, Z, 1)`` of Fig. 8) and bond dimension 1, zero-padded
+    to ``D``.  Real, physical dimension ``d^2 = 4``."""
+    A = np.zeros((4, D, D, D, D))
+    A[3, 0, 0, 0, 0] = 1.0
+    return A, A.copy()
+
+
 def random_site_pair(rng: np.random.Generator, p: int, D: int,
                      dtype=np.complex128) -> tuple[np.ndarray, np.ndarray]:
     """Draw ``A`` then ``B``: i.i.d. ``x + i y`` with ``x, y ~ N(0, 1)``.
@@ -136,6 +166,17 @@ def workload_thermal(D: int = 8, hx: float = 2.5, hz: float = 0.0, dbeta: float 
     A, B = thermal_product_purification(D)
     gate = bond_gate(ising_bond_hamiltonian(hx, hz).real, dbeta, imaginary=True)
     return dict(A=A, B=B, gates=[gate] * 4, D=D, p=4)
+
+
+def workload_hermitian_thermal(D: int = 5, hx: float = 2.9, hz: float = 5e-4, dbeta: float = 0.0025):
+    """Imaginary-time evolution of the manifestly Hermitian purification
+    (Sec. IV; the field values and the step of Sec. V).  ``gate`` is the
+    two-site operator ``G`` of :func:`hermitian_thermal_gate`; the update
+    itself uses its action on the basis pairs (Eq. 11), which the library and
+    the oracle each form from ``G``.  Real arithmetic, ``p = d^2 = 4``, gate
+    rank 4 (``R = 4 D``)."""
+    A, B = hermitian_identity(D)
+    return dict(A=A, B=B, gate=hermitian_thermal_gate(hx, hz, dbeta), D=D, p=4, hx=hx, hz=hz, dbeta=dbeta)
 
 
 def workload_batched(seed: int = 4, n: int = 256, D_lo: int = 3, D_hi: int = 8,
