@@ -42,6 +42,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "NTU bond updates/sec at D=8, mixed-precision vs FP64 GPU path, at 1e-6 rel err"
+METRIC_HERM = ("NTU bond updates/sec of the manifestly Hermitian purification at D=5 (R=20), split precision "
+               "vs FP64 GPU path")
 METRIC_SVDU = "SVDU bond updates/sec (reduction, truncated SVD, recombination; no environment)"
 PEAK_BF16 = 2.5e15       # dense MFMA, FLOP/s
 PEAK_FP64 = 78.6e12      # FLOP/s (vector and matrix)
@@ -60,7 +62,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batched", choices=["batched", "thermal", "large"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "thermal", "large", "hermitian"])
     ap.add_argument("--precision", default=None, choices=["bf16x3", "bf16x6", "fp16x3", "f64"],
                     help="environment precision (default: fp16x3 for the batched workload; bf16x6 for the "
                          "others, whose real or D > 8 metrics take the tiled path FP16x3 does not cover)")
@@ -226,6 +228,26 @@ def thermal_job(ntu, torch, np, dev, inputs, D=8):
     return job
 
 
+def hermitian_job(ntu, torch, np, dev, inputs, D=5):
+    """Manifestly Hermitian purification (Sec. IV): the real iPEPS of rho(beta/2)
+    in the basis (X, Y, Z, 1), p = 4, its gate's action on the basis pairs
+    formed and split (rank 4, R = 4 D) on the GPU."""
+    w = inputs.workload_hermitian_thermal(D=D)
+    ctx = ntu.Context(complex_=False, d=4, d_anc=1, r_g=4, max_D=D, max_batch=1)
+    ctx.bind_stream()
+    G = torch.from_numpy(np.ascontiguousarray(w["gate"][None])).to(dev)
+    GA, GB, _ = ntu.ntu_gate_split(ctx, ntu.ntu_superop_gate(ctx, G))
+    gf = torch.stack([torch.stack([GA[0], GB[0]])] * 4)[None].contiguous()
+    A = torch.from_numpy(w["A"][None]).to(dev).contiguous()
+    B = torch.from_numpy(w["B"][None]).to(dev).contiguous()
+    job = Job()
+    job.cplx, job.p, job.d, job.rg, job.n_updates, job.w, job.label = False, 4, 4, 4, 4, w, "hermitian"
+    job.buckets = [dict(D=D, A=A, B=B, gf=gf, n=1, ctx=ctx, stream=torch.cuda.Stream(device=dev))]
+    job.order = (0, 1, 2, 3)
+    job.bonds_per_item = 4
+    return job
+
+
 def large_job(ntu, torch, np, dev, inputs, D=10):
     w = inputs.workload_large(D=D)
     ctx = ntu.Context(complex_=True, d=2, d_anc=1, r_g=2, max_D=D, max_batch=1)
@@ -336,7 +358,8 @@ class Runner:
                 ctx = bk["ctx"]
                 QX, _ = ntu.ntu_reduce_qr(ctx, A, bk["gf"][:, 0, 0].contiguous(), 0)
                 QY, _ = ntu.ntu_reduce_qr(ctx, B, bk["gf"][:, 0, 1].contiguous(), 1)
-                A, B = A.to(torch.complex128), B.to(torch.complex128)
+                if self.job.cplx:
+                    A, B = A.to(torch.complex128), B.to(torch.complex128)
                 ks, tms = ntu.ntu_tune_env(ctx, QX, QY, [B, B, B, A, A, A], precision, D=bk["D"])
                 tuning[str(bk["D"])] = {"e6_ksplit": ks, "env_ms": round(tms, 4)}
         torch.cuda.synchronize()
@@ -374,6 +397,20 @@ KERNEL_OF = {"bond_fit": "k_bond_fit_grp (with k_grp_reset, and k_bond_fit for t
              "env_e5": "k_mfma_tile (L2)", "env_e6": "k_mfma_tile (g = L2 Right^T)"}
 
 
+def kernel_of(cls, job, D):
+    """Kernel a class runs for a bucket of bond dimension D (the fit's group
+    path needs R <= 16 and 5 <= D <= 8; the matrix-core Cholesky QR R <= 16,
+    d <= 2 and d^2 r_g <= 32)."""
+    rg, d = getattr(job, "rg", 2), getattr(job, "d", 2)
+    R = rg * D
+    if cls == "bond_fit" and not (R <= 16 and 5 <= D <= 8):
+        return "k_bond_fit"
+    if cls == "reduce_qr" and not (R <= 16 and d <= 2 and d * d * rg <= 32):
+        return ("k_reduce_cholqr (with k_reduce_qr" + ("" if job.cplx else "_reg") +
+                " for the items it leaves)")
+    return KERNEL_OF[cls]
+
+
 def rooflines(job, args, stats, nsteps, prof, workload):
     """Per kernel class: algorithmic (and issued MFMA) rate over the average
     launch time of the profiled steps; stats: those steps' stats."""
@@ -383,7 +420,7 @@ def rooflines(job, args, stats, nsteps, prof, workload):
     fit_fl, env = 0.0, {}
     for bi, bk in enumerate(job.buckets):
         st = np.stack([x[bi].cpu().numpy() for x in stats])
-        R = 2 * bk["D"]
+        R = getattr(job, "rg", 2) * bk["D"]
         for row in st.reshape(-1, st.shape[-1]):
             fit_fl += fit_flops(R, row[8 + 4], 2 * row[8 + 6], row[8 + 15], job.cplx)
         fused = job.cplx and bk["D"] ** 2 <= 64 and args.precision != "f64"
@@ -396,7 +433,7 @@ def rooflines(job, args, stats, nsteps, prof, workload):
     # M of both sides and writes both site tensors
     hbm = {"reduce_qr": 0.0, "recombine": 0.0}
     for bk in job.buckets:
-        D, R, el = bk["D"], 2 * bk["D"], 16 if job.cplx else 8
+        D, R, el = bk["D"], getattr(job, "rg", 2) * bk["D"], 16 if job.cplx else 8
         site, q = job.p * D ** 4, job.p * D ** 3 * R
         nb = bk["n"] * job.bonds_per_item
         hbm["reduce_qr"] += nb * el * 2 * (site + q + R * R)
@@ -406,13 +443,13 @@ def rooflines(job, args, stats, nsteps, prof, workload):
         t = t_ms / nsteps / 1e3                        # s per step
         n_l = n_l / nsteps
         if cls in hbm:
-            rl[cls] = {"kernel": KERNEL_OF[cls], "bound": "hbm", "achieved": hbm[cls] / t / 1e9,
+            rl[cls] = {"kernel": kernel_of(cls, job, job.buckets[-1]["D"]), "bound": "hbm", "achieved": hbm[cls] / t / 1e9,
                        "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": hbm[cls] / t / PEAK_HBM,
                        "algorithmic_bytes_per_step": hbm[cls]}
         elif cls == "bond_fit" and args.scheme == "svdu":
             continue
         elif cls == "bond_fit":
-            rl[cls] = {"kernel": KERNEL_OF[cls], "bound": "alu", "achieved": fit_fl / t / 1e12,
+            rl[cls] = {"kernel": kernel_of(cls, job, job.buckets[-1]["D"]), "bound": "alu", "achieved": fit_fl / t / 1e12,
                        "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": fit_fl / t / PEAK_FP64,
                        "flops_per_step": fit_fl}
         elif cls in env:
@@ -595,6 +632,8 @@ def main():
             items, label = all_items, "configuration 4: 256 independent bond updates, D uniform in {3..8}"
         storage = torch.complex64 if args.storage == "c64" else torch.complex128
         job = bucket_job(ntu, torch, np, dev, items, label, storage)
+    elif args.workload == "hermitian":
+        job = hermitian_job(ntu, torch, np, dev, inputs)
     else:
         job = thermal_job(ntu, torch, np, dev, inputs)
     if args.aux == "shared":
@@ -607,7 +646,8 @@ def main():
 
     m = measure(job, args, ntu, torch, dev, opts, opts64, K, W)
     result = {
-        "metric": METRIC if args.scheme == "ntu" else METRIC_SVDU,
+        "metric": (METRIC_SVDU if args.scheme != "ntu" else METRIC_HERM if args.workload == "hermitian"
+                   else METRIC),
         "value": m["value"],
         "unit": "bond_updates/s",
         "n_gpus": 1,
@@ -636,6 +676,13 @@ def main():
             result["config"]["streams"] = (f"one per D bucket, side streams "
                                            f"{'one shared' if args.aux == 'shared' else 'one per bucket'}, "
                                            f"{args.hw_queues} hardware queues")
+    elif args.workload == "hermitian":
+        w = job.w
+        result["config"] = {"workload": "manifestly Hermitian purification (Sec. IV): one state, D=5, "
+                                        "p=d^2=4, real, gate action of rank 4 (R=20)", "D": w["D"],
+                            "h_x": w["hx"], "h_z": w["hz"], "dbeta": w["dbeta"], "env_precision": args.precision,
+                            "fit": "fp64, <=20 ALS iterations, early stop 1e-12 N", "bond_updates_per_step": 4,
+                            "start": f"rho(0/2) = 1 + {W} FP64 warm-up steps"}
     else:
         result["config"] = {"workload": "configuration 3: thermal purification, D=8, p=4, real", "D": 8,
                             "h_x": 2.5, "dbeta": 0.005, "env_precision": args.precision,
@@ -691,6 +738,20 @@ def main():
             sample = (f"{n_bonds} bond updates cycling in order through the {len(job.items)} items of the headline "
                       f"workload from their seeded state, oracle FP64 numpy/BLAS"
                       f"{', SVDU updates' if args.scheme == 'svdu' else ''}")
+        elif args.workload == "hermitian":
+            from oracle import hermitian as OH
+            r = m["runner"]
+            An, Bn = r.init[0][0].cpu().numpy()[0], r.init[0][1].cpu().numpy()[0]
+            D = job.buckets[0]["D"]
+            GAo, GBo, _ = OH.gate_factors(job.w["gate"])
+            pairs = {b: (GAo, GBo) for b in O.BONDS}
+            while n_bonds < 64 and time.perf_counter() - t0 < args.cpu_seconds:
+                for b in O.BONDS:
+                    An, Bn, _ = O.trotter_step(An, Bn, pairs, D, d=4, n_iter=20, conv_tol=1e-12, order=(b,),
+                                                scheme=args.scheme)
+                    n_bonds += 1
+            sample = (f"{n_bonds} bond updates of the D={D} Hermitian purification from the warmed-up state, "
+                      f"oracle FP64 numpy/BLAS")
         else:
             r = m["runner"]
             An, Bn = r.init[0][0].cpu().numpy()[0], r.init[0][1].cpu().numpy()[0]

@@ -146,6 +146,21 @@ ntu_status ntu_gate_split(ntu_ctx* ctx, int batch, const ntu_tensor* gate, ntu_t
                           ntu_tensor* sigma);
 
 /*
+ * Manifestly Hermitian purification, Sec. IV: Eq. (11) with the basis of
+ * Fig. 8.  For each item, the real matrix of rho -> G rho G^dagger on the
+ * products O^a x O^b of the spin-1/2 Hermitian basis O = (X, Y, Z, 1):
+ *   G (O^a x O^b) G^dagger = sum_{a' b'} S[(a' b'), (a b)] O^a' x O^b'.
+ * The half rho(beta/2) of Eq. (7), written in this basis, is an iPEPS with
+ * real tensors and a physical index a of dimension 4; S is its two-site gate
+ * (pass it to ntu_gate_split; for the gate of Eq. (10) its operator-Schmidt
+ * rank is 4, so r_g = 4).
+ * gate: (batch, 4, 4), NTU_F64 or NTU_C128, rows (s1' s2'), columns
+ * (s1 s2).  S: (batch, 16, 16) NTU_F64, written, rows (a' b'), columns (a b).
+ * The context must have d = 4 and d_anc = 1 (NTU_ERR_SHAPE otherwise).
+ */
+ntu_status ntu_superop_gate(ntu_ctx* ctx, int batch, const ntu_tensor* gate, ntu_tensor* S);
+
+/*
  * Reduction, Fig. 2(b).  Applies the gate factor to the site tensor and takes
  * the thin QR decomposition of the result:
  *   side 0 (X): W[(s',a,t,l,b), (r,k)] = sum_s GA[s',s,k] X[(s,a),t,l,b,r]
@@ -188,17 +203,24 @@ ntu_status ntu_env_contract(ntu_ctx* ctx, int batch, const ntu_tensor* QX, const
  * columns that are exactly zero are left out of the eigenproblem; when the
  * remaining block is certified positive definite (Gershgorin discs right of
  * zero, else a Cholesky factor exists) the clip is the identity and is
- * skipped.
+ * skipped.  Complex g, and real g with n < 128: Jacobi eigen-decomposition.
+ * Real g with n >= 128: g <- (g + g S) / 2 with S = sign(g) from a
+ * polynomial iteration of matrix products on the FP64 matrix cores; every
+ * eigenvalue of magnitude >= 1e-15 ||g||_F is resolved to rounding and a
+ * smaller one contributes at most its own size.
  * g: (batch, n, n) in place, compute type, n = (D r_g)^2 for a D of the
  * context.
  * stats (may be NULL): (batch, 8) NTU_F64, written
  *   [0] ||g - g^H||_F / ||g||_F  (input)      [1] ||g||_F (input)
  *   [2] smallest eigenvalue (NaN if not computed)
  *   [3] largest eigenvalue  (NaN if not computed)
- *   [4] clipped mass sum(-lambda_neg)/sum|lambda| (0 if certified)
- *   [5] 1 if the eigen-decomposition ran, 0 if certified
+ *   [4] clipped mass sum(-lambda_neg)/sum|lambda| (0 if certified; from
+ *       trace(g) and trace(g S) after the sign iteration)
+ *   [5] 1 if the eigen-decomposition ran, 2 if the sign iteration ran
+ *       ([2], [3] NaN), 0 if certified
  *   [6] number of non-finite entries in the input
- *   [7] Jacobi sweeps of the eigen-decomposition (0 when none was needed)
+ *   [7] Jacobi sweeps of the eigen-decomposition, or steps of the sign
+ *       iteration (0 when none was needed)
  */
 ntu_status ntu_metric_fix(ntu_ctx* ctx, int batch, ntu_tensor* g, int mode, ntu_tensor* stats);
 
@@ -372,9 +394,10 @@ const char* ntu_profile_kind_name(int kind);
  * complex arithmetic), n <= 1024, on the current device.
  * stats (may be NULL): (batch, 8) NTU_F64, written as by ntu_metric_fix.
  * The scratch needed is about 2 n^2 elements of g's type per item (the
- * eigen-solve's two matrices): 2 MiB per complex item at n = 256, so up to
- * 16 such items per call; larger requests return NTU_ERR_WORKSPACE before
- * any launch.  Errors are described by ntu_last_error(NULL).
+ * eigen-solve's two matrices; 3 n^2 doubles for real g with n >= 128, the
+ * sign iteration's three): 2 MiB per complex item at n = 256, so up to 16
+ * such items per call; larger requests return NTU_ERR_WORKSPACE before any
+ * launch.  Errors are described by ntu_last_error(NULL).
  * Every call on one GPU uses that GPU's one scratch array: calls that
  * overlap on a GPU (different streams or threads without ordering between
  * them) race and give wrong results.  Nothing in the scratch needs to start

@@ -414,6 +414,20 @@ ntu_status ntu_gate_split(ntu_ctx* c, int batch, const ntu_tensor* gate, ntu_ten
   return e == hipSuccess ? NTU_OK : hip_fail(c, e, "gate_split");
 }
 
+ntu_status ntu_superop_gate(ntu_ctx* c, int batch, const ntu_tensor* gate, ntu_tensor* S) {
+  NTU_CHECK(check_common(c, batch, 1));
+  if (c->d != 4 || c->na != 1) return fail(c, NTU_ERR_SHAPE, "superop_gate needs a context with d = 4, d_anc = 1");
+  if (batch == 0) return NTU_OK;
+  NTU_CHECK(check_tensor(c, gate, "gate", M_F64 | M_C128, {batch, 4, 4}));
+  NTU_CHECK(check_tensor(c, S, "S", M_F64, {batch, 16, 16}));
+  DeviceGuard guard(c->device);
+  const ntu::ProfHook ph = hook(c);
+  ph(ntu::PK_GATE, 0);
+  hipError_t e = ntu::launch_superop(gate->dtype == NTU_C128, batch, gate->data, (double*)S->data, c->stream);
+  ph(ntu::PK_GATE, 1);
+  return e == hipSuccess ? NTU_OK : hip_fail(c, e, "superop_gate");
+}
+
 ntu_status ntu_reduce_qr(ntu_ctx* c, int batch, const ntu_tensor* site, const ntu_tensor* gf, int side,
                          ntu_tensor* Q, ntu_tensor* R) {
   NTU_CHECK(check_common(c, batch, 1));

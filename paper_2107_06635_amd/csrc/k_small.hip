@@ -70,6 +70,59 @@ hipError_t launch_gate_split(bool cplx, int batch, int d, int rg, const void* ga
 }
 
 // ---------------------------------------------------------------------------
+// Action rho -> G rho G^dagger of a spin-1/2 two-site gate on the products of
+// the Hermitian basis O = (X, Y, Z, 1) (Eq. 11, Fig. 8):
+//   S[(a' b'), (a b)] = Tr((O^a' x O^b') G (O^a x O^b) G^dagger) / 4.
+// Each basis product is a signed permutation matrix: row (i1 i2) holds one
+// entry, phase ph_a(i1) ph_b(i2) in {+-1, +-i}, at column (pi_a(i1),
+// pi_b(i2)).  With P' = O^a' x O^b' and P = O^a x O^b the trace is
+//   sum_{i,k} ph'(i) G[pi'(i), k] ph(k) conj(G[i, pi(k)]),
+// sixteen products of two gate entries.  One thread per output entry, one
+// workgroup of 256 per item.
+// ---------------------------------------------------------------------------
+NTU_DEV int pauli_col(int a, int i) { return (a <= 1) ? 1 - i : i; }
+// phase of the entry of row i of basis operator a, as (re, im)
+NTU_DEV cd pauli_phase(int a, int i) {
+  switch (a) {
+    case 1: return i == 0 ? cd{0.0, -1.0} : cd{0.0, 1.0};  // Y
+    case 2: return i == 0 ? cd{1.0, 0.0} : cd{-1.0, 0.0};  // Z
+    default: return cd{1.0, 0.0};                          // X, 1
+  }
+}
+NTU_DEV cd gate_entry(const double* G, int r, int c) { return cd{G[r * 4 + c], 0.0}; }
+NTU_DEV cd gate_entry(const cd* G, int r, int c) { return G[r * 4 + c]; }
+
+template <class T>
+__global__ void __launch_bounds__(256) k_superop(const T* __restrict__ gate, double* __restrict__ S) {
+  const int it = blockIdx.x, e = threadIdx.x;
+  const int row = e >> 4, col = e & 15;
+  const int ap = row >> 2, bp = row & 3, a = col >> 2, b = col & 3;
+  const T* G = gate + (size_t)it * 16;
+  cd acc{0.0, 0.0};
+  for (int i = 0; i < 4; ++i) {
+    const int i1 = i >> 1, i2 = i & 1;
+    const int pi_p = pauli_col(ap, i1) * 2 + pauli_col(bp, i2);
+    const cd php = pauli_phase(ap, i1) * pauli_phase(bp, i2);
+    for (int k = 0; k < 4; ++k) {
+      const int k1 = k >> 1, k2 = k & 1;
+      const int pi_k = pauli_col(a, k1) * 2 + pauli_col(b, k2);
+      const cd ph = pauli_phase(a, k1) * pauli_phase(b, k2);
+      acc += php * gate_entry(G, pi_p, k) * ph * conjv(gate_entry(G, i, pi_k));
+    }
+  }
+  S[(size_t)it * 256 + e] = 0.25 * acc.x;
+}
+
+hipError_t launch_superop(bool cplx_gate, int batch, const void* gate, double* S, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  if (cplx_gate)
+    hipLaunchKernelGGL(k_superop<cd>, dim3(batch), dim3(256), 0, st, (const cd*)gate, S);
+  else
+    hipLaunchKernelGGL(k_superop<double>, dim3(batch), dim3(256), 0, st, (const double*)gate, S);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Reduction: W = gate factor applied to the site tensor, then Gram-Schmidt QR
 // with the projection applied twice and the rank rule.  One workgroup per item.
 // ---------------------------------------------------------------------------

@@ -23,6 +23,7 @@ struct ProfHook {
   }
 };
 
+hipError_t launch_superop(bool cplx_gate, int batch, const void* gate, double* S, hipStream_t st);
 hipError_t launch_gate_split(bool cplx, int batch, int d, int rg, const void* gate, void* GA, void* GB,
                              double* sigma, hipStream_t st);
 hipError_t launch_reduce_qr(bool cplx, int site_dtype, int batch, int d, int na, int D, int rg,

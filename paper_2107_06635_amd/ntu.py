@@ -33,7 +33,7 @@ EXPORTED = (
     "ntu_fit_opts_default", "ntu_bond_fit", "ntu_recombine", "ntu_step_opts_default", "ntu_trotter_step",
     "ntu_profile_enable", "ntu_profile_read", "ntu_profile_kind_name",
     "ntu_tune_env", "ntu_set_env_ksplit", "ntu_get_env_ksplit", "ntu_tune_save", "ntu_tune_load",
-    "ntu_metric_fix_noalloc",
+    "ntu_metric_fix_noalloc", "ntu_superop_gate",
 )
 
 
@@ -100,6 +100,7 @@ def load():
     L.ntu_profile_kind_name.argtypes = [i32]
     L.ntu_profile_kind_name.restype = ctypes.c_char_p
     L.ntu_metric_fix_noalloc.argtypes = [vp, i32, tp, i32, tp]
+    L.ntu_superop_gate.argtypes = [vp, i32, tp, tp]
     for name in EXPORTED:
         if name not in ("ntu_last_error", "ntu_workspace_bytes", "ntu_version", "ntu_fit_opts_default",
                         "ntu_step_opts_default", "ntu_profile_kind_name"):
@@ -217,6 +218,16 @@ def ntu_gate_split(ctx: Context, gate: torch.Tensor):
     ctx.bind_stream()
     ctx.check(ctx.L.ntu_gate_split(ctx.h, b, _ref(gate), _ref(GA), _ref(GB), _ref(sig)), "ntu_gate_split")
     return GA, GB, sig
+
+
+def ntu_superop_gate(ctx: Context, gate: torch.Tensor):
+    """gate: (batch, 4, 4) float64 or complex128 -> S: (batch, 16, 16) float64,
+    the action rho -> G rho G^dagger on the Hermitian basis pairs (Eq. 11)."""
+    b = gate.shape[0]
+    S = torch.empty(b, 16, 16, dtype=torch.float64, device=ctx.device)
+    ctx.bind_stream()
+    ctx.check(ctx.L.ntu_superop_gate(ctx.h, b, _ref(gate), _ref(S)), "ntu_superop_gate")
+    return S
 
 
 def ntu_reduce_qr(ctx: Context, site: torch.Tensor, gate_factor: torch.Tensor, side: int):
