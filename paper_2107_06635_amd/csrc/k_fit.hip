@@ -68,6 +68,20 @@ NTU_HD size_t fit_shared_fixed_bytes(size_t el, int R) {
   return (b + 15) / 16 * 16;
 }
 
+// elements of the fit kernel's shared work region (after the fixed part)
+NTU_HD size_t fit_work_elems(int R, int D) {
+  const size_t cert_el = R * R <= 256 ? (size_t)R * R * CHOL_BS : 0;
+  const size_t solve_el = (size_t)R * D * CHOL_BS + CHOL_BS * CHOL_BS + 200 + 3 * 200;
+  return cert_el > solve_el ? cert_el : solve_el;
+}
+// Real fits with R Dn <= FIT_PACKED_NX keep the ladder's eigenproblem in
+// shared memory, packed (n (n + 1) / 2 doubles after the work region).
+constexpr int FIT_PACKED_NX = 128;
+NTU_HD size_t fit_packed_bytes(bool cplx, int R, int D) {
+  const int nx = R * D;
+  return (!cplx && nx <= FIT_PACKED_NX) ? ((size_t)nx * (nx + 1) / 2 * 8 + 15) / 16 * 16 : 0;
+}
+
 template <class T> struct FitShared {
   T* y;    // R^2          vec(P)
   T* MX;   // R x D        row-major
@@ -251,8 +265,8 @@ NTU_DEV void fit_qr_small(const T* M, T* Q, T* Rf, int R, int Dn, double kappa, 
 // error of candidate m (whole-block call).
 template <class T, class Eval>
 NTU_DEV double fit_solve(const T* gs, int nx, const FitParams& fp, const FitShared<T>& S, T* A, T* X,
-                         double N, int* used_eig, Eval eval) {
-  __shared__ int m_sh, cnt;
+                         double N, int* used_eig, Eval eval, double* Ap) {
+  __shared__ int m_sh, cnt, rcnt[2];
   __shared__ double pc[256], ps[256];
   __shared__ T pe[256];
   __shared__ int pq[256];
@@ -327,18 +341,41 @@ NTU_DEV double fit_solve(const T* gs, int nx, const FitParams& fp, const FitShar
   }
   // eigendecomposition ladder
   *used_eig = 1;
-  for (long long e = tid; e < (long long)m * m; e += blockDim.x)
-    A[e] = gs[(size_t)S.idx[e / m] * nx + S.idx[e % m]];
-  __syncthreads();
-  block_jacobi_eigh<T>(A, m, m, X, m, pc, ps, pe, pq, &cnt, fro);
+  bool packed = false;
+  if constexpr (!is_cplx<T>::value) {
+    if (Ap != nullptr && m <= FIT_PACKED_NX) {
+      // real: the lower triangle in shared memory; the eigenvalues then go to
+      // the diagonal of A, where the ladder below reads them
+      packed = true;
+      for (int e = tid; e < m * (m + 1) / 2; e += blockDim.x) {
+        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while ((i + 1) * (i + 2) / 2 <= e) ++i;
+        while (i * (i + 1) / 2 > e) --i;
+        const int j = e - i * (i + 1) / 2;
+        Ap[e] = gs[(size_t)S.idx[i] * nx + S.idx[j]];
+      }
+      __syncthreads();
+      block_jacobi_eigh_packed(Ap, m, X, m, pc, ps, pq, &cnt, rcnt, fro);
+      for (int i = tid; i < m; i += blockDim.x) A[(size_t)i * m + i] = Ap[packed_at(i, i)];
+      __syncthreads();
+    }
+  }
+  if (!packed) {
+    for (long long e = tid; e < (long long)m * m; e += blockDim.x)
+      A[e] = gs[(size_t)S.idx[e / m] * nx + S.idx[e % m]];
+    __syncthreads();
+    block_jacobi_eigh<T>(A, m, m, X, m, pc, ps, pe, pq, &cnt, fro);
+  }
   double lmax = -INFINITY;
   for (int i = tid; i < m; i += blockDim.x) lmax = fmax(lmax, rev(A[(size_t)i * m + i]));
   lmax = block_max(lmax, S.red);
   if (!(lmax > 0.0)) return tol_max;  // nothing positive to invert: m = 0
+  // component r of eigenvector i (the packed solver stores them transposed)
+  const size_t xr = packed ? 1 : (size_t)m, xi = packed ? (size_t)m : 1;
   __shared__ T proj[256];
   for (int i = tid; i < m; i += blockDim.x) {
     T acc = zerov<T>();
-    for (int r = 0; r < m; ++r) acc += cmul(X[(size_t)r * m + i], S.J[S.idx[r]]);
+    for (int r = 0; r < m; ++r) acc += cmul(X[r * xr + i * xi], S.J[S.idx[r]]);
     proj[i] = acc;
   }
   __syncthreads();
@@ -355,7 +392,7 @@ NTU_DEV double fit_solve(const T* gs, int nx, const FitParams& fp, const FitShar
       T acc = zerov<T>();
       for (int i = 0; i < m; ++i) {
         double l = rev(A[(size_t)i * m + i]);
-        if (l > thr) acc += X[(size_t)r * m + i] * proj[i] * (1.0 / l);
+        if (l > thr) acc += X[r * xr + i * xi] * proj[i] * (1.0 / l);
       }
       S.m[S.idx[r]] = acc;
     }
@@ -375,7 +412,7 @@ NTU_DEV double fit_solve(const T* gs, int nx, const FitParams& fp, const FitShar
     T acc = zerov<T>();
     for (int i = 0; i < m; ++i) {
       double l = rev(A[(size_t)i * m + i]);
-      if (l > thr) acc += X[(size_t)r * m + i] * proj[i] * (1.0 / l);
+      if (l > thr) acc += X[r * xr + i * xi] * proj[i] * (1.0 / l);
     }
     S.m[S.idx[r]] = acc;
   }
@@ -937,6 +974,9 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
   // of the certification, and the Cholesky panel / diagonal block /
   // right-hand side of the half-step solve followed by the CG vectors
   T* work = (T*)((char*)shmem + fit_shared_fixed_bytes(sizeof(T), R));
+  double* packed_lds = fit_packed_bytes(is_cplx<T>::value, R, D) > 0
+                           ? (double*)((char*)work + fit_work_elems(R, D) * sizeof(T))
+                           : nullptr;
   T* pan = work;
   T* dblk = work + (size_t)R * D * CHOL_BS;
   T* sbz = dblk + CHOL_BS * CHOL_BS;
@@ -1151,7 +1191,7 @@ __global__ void __launch_bounds__(FIT_THREADS) k_bond_fit(int D, int R, const T*
         S.J[r] = v;
       }
       __syncthreads();
-      tau = fit_solve<T>(gs, nx, fp, S, A, X, N, &used_eig, eval);
+      tau = fit_solve<T>(gs, nx, fp, S, A, X, N, &used_eig, eval, packed_lds);
       }  // !fast_done
       if (!fast_done) tick(2);
       set_free(S.m);
@@ -1823,9 +1863,8 @@ hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, co
   size_t el = cplx ? 16 : 8;
   constexpr size_t LDS_MAX = 160 * 1024 - 16 * 1024;
   // the n x CHOL_BS panel of the certification only for metrics it certifies
-  const size_t cert_el = R * R <= FIT_CERT_NMAX ? (size_t)R * R * CHOL_BS : 0;
-  const size_t work_el = std::max<size_t>(cert_el, (size_t)R * D * CHOL_BS + CHOL_BS * CHOL_BS + FAST_NX + 3 * CG_NX);
-  size_t shm = fit_shared_fixed_bytes(el, R) + work_el * el;
+  static_assert(FIT_CERT_NMAX == 256 && FAST_NX == 200 && CG_NX == 200, "fit_work_elems");
+  size_t shm = fit_shared_fixed_bytes(el, R) + fit_work_elems(R, D) * el + fit_packed_bytes(cplx, R, D);
   ph(PK_FIT, 0);
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);

@@ -79,10 +79,12 @@ NTU_DEV void svd_serial(T* A, int m, int n, int lda, T* V, int ldv, double* s) {
 // over n2 (even) columns: pair k of the round is (first, second), each pair
 // disjoint, every unordered pair met once per n2-1 rounds.
 NTU_DEV void rr_pair(int n2, int r, int k, int& a, int& b) {
-  // player 0 fixed, others rotate
+  // player 0 fixed, others rotate (0 <= r < n2 - 1 and 0 <= slot < n2, so
+  // one conditional subtraction takes the place of the modulo)
   auto pos = [&](int slot) -> int {
     if (slot == 0) return 0;
-    return 1 + ((slot - 1 + r) % (n2 - 1));
+    const int x = slot - 1 + r;
+    return 1 + (x >= n2 - 1 ? x - (n2 - 1) : x);
   };
   int x = pos(k), y = pos(n2 - 1 - k);
   a = x < y ? x : y;
@@ -366,6 +368,205 @@ NTU_DEV int block_jacobi_eigh(T* A, int n, int lda, T* V, int ldv, double* pc, d
           V[I[u] * ldv + (pqk >> 16)] = s * x + c * y;
         }
       }
+      __syncthreads();
+    }
+    int cnt = *sh_cnt;
+    __syncthreads();
+    if (cnt == 0) return sweep + 1;
+  }
+  return 40;
+}
+
+// Offset of entry (i, j) of a symmetric matrix stored as its lower triangle,
+// row by row.
+NTU_DEV int packed_at(int i, int j) { return i >= j ? ((i * (i + 1)) >> 1) + j : ((j * (j + 1)) >> 1) + i; }
+
+// block_jacobi_eigh for a real symmetric n x n matrix held packed in shared
+// memory (Ap: n (n + 1) / 2 doubles, lower triangle row by row; on return its
+// diagonal holds the eigenvalues), eigenvectors into VT transposed (VT[j ldv
+// + i] = component i of vector j; global memory).  The same rotations,
+// round-robin ordering, skip and
+// stopping rules.  The update J^T A J takes each unordered pair of pairs
+// (k1 >= k2) once: the block of the other order is the transpose of this one
+// and shares its storage, and a diagonal block (k1 = k2) keeps its one
+// off-diagonal entry.  The pairs of a round depend only on its number, so
+// each round's parameter pass also writes the next round's pairs, and the
+// entries of V that a round rotates are loaded at its start: their latency
+// runs under the parameter pass and the update of A.  Entry u of a thread is
+// (pair, row) = divmod(tid + u blockDim, n), the same in every round (a wave
+// reads and writes consecutive components of one vector); the
+// first VB are loaded ahead (registers: the kernels that use this stay within
+// 256 VGPRs at VB = 8), any further ones after the update of A.  A round
+// without any rotation (most rounds of the last sweeps) skips both updates:
+// rc (two shared ints) counts the rotations of the current and the next
+// round.  pq: 2 (n + 1) / 2 ints.  Whole block.
+template <int VB = 8>
+NTU_DEV int block_jacobi_eigh_packed(double* Ap, int n, double* VT, int ldv, double* pc, double* ps, int* pq,
+                                     int* sh_cnt, int* rc, double fro) {
+  const int tid = threadIdx.x;
+  for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
+    int i = (int)(e / n), j = (int)(e % n);
+    VT[i * ldv + j] = i == j ? 1.0 : 0.0;
+  }
+  if (n < 2) {
+    __syncthreads();
+    return 0;
+  }
+  const int n2 = (n + 1) & ~1, np = n2 / 2, ntri = np * (np + 1) / 2;
+  const int bq = (int)blockDim.x / np, br = (int)blockDim.x % np;
+  const double tiny = 1e-14 * fro;
+  int* pq_cur = pq;
+  int* pq_nxt = pq + np;
+  for (int k = tid; k < np; k += blockDim.x) {
+    int p, q;
+    rr_pair(n2, 0, k, p, q);
+    pq_cur[k] = p | (q << 16);
+  }
+  if (tid == 0) rc[0] = rc[1] = 0;
+  // this thread's first entry of V: pair vk0, row vi0 (the others follow by
+  // steps of blockDim: rows advance by ri, pairs by rk)
+  const int vk0 = tid / n, vi0 = tid % n;
+  const int rk = (int)blockDim.x / n, ri = (int)blockDim.x % n;
+  __syncthreads();
+  const int rounds = n2 - 1;
+  int gr = 0;  // rounds so far over all sweeps: its parity selects the counter
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) *sh_cnt = 0;
+    __syncthreads();
+    for (int r = 0; r < rounds; ++r) {
+      // entries of V this round rotates (their pairs are known already)
+      double vx[VB], vy[VB];
+      {
+        int vi = vi0, vk = vk0;
+#pragma unroll
+        for (int u = 0; u < VB; ++u) {
+          const int pqk = pq_cur[min(vk, np - 1)];
+          vx[u] = VT[(pqk & 0xffff) * ldv + vi];
+          vy[u] = VT[min(pqk >> 16, n - 1) * ldv + vi];
+          vi += ri; vk += rk;
+          if (vi >= n) { vi -= n; ++vk; }
+        }
+      }
+      // rotation parameters of this round; the next round's pairs
+      const int rn = r + 1 < rounds ? r + 1 : 0;
+      for (int k = tid; k < np; k += blockDim.x) {
+        int p, q;
+        rr_pair(n2, rn, k, p, q);
+        pq_nxt[k] = p | (q << 16);
+        const int pqk = pq_cur[k];
+        p = pqk & 0xffff; q = pqk >> 16;
+        pc[k] = 1.0; ps[k] = 0.0;
+        if (q >= n) continue;
+        const double apq = Ap[packed_at(q, p)];
+        const double g = fabs(apq);
+        const double app = Ap[packed_at(p, p)], aqq = Ap[packed_at(q, q)];
+        if (!(g > 1e-15 * sqrt(fabs(app * aqq))) || !(g > tiny)) continue;
+        const double zeta = (aqq - app) / (2.0 * g);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        // the sign of apq (the phase of the complex form) folded into s
+        pc[k] = c; ps[k] = (apq < 0.0 ? -c : c) * t;
+        atomicAdd(&rc[gr & 1], 1);
+      }
+      __syncthreads();
+      // every thread reads this round's count; the next round's counter is
+      // cleared (nobody touches it before the barrier that ends this round)
+      const int nrot = rc[gr & 1];
+      if (tid == 0) {
+        *sh_cnt += nrot;
+        rc[(gr + 1) & 1] = 0;
+      }
+      ++gr;
+      if (nrot == 0) {
+        int* t = pq_cur; pq_cur = pq_nxt; pq_nxt = t;
+        __syncthreads();
+        continue;
+      }
+      // A <- J^T A J on the blocks k1 >= k2, TB at a time: all their pair
+      // data, then all their entries, then the rotations (the identity for
+      // a pair that does not rotate) and the stores of what changed
+      constexpr int TB = 3;
+      for (int e0 = tid; e0 < ntri; e0 += TB * (int)blockDim.x) {
+        int k1[TB], k2[TB];
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          const int e = min(e0 + u * (int)blockDim.x, ntri - 1);
+          int x = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+          x -= ((x * (x + 1)) >> 1) > e ? 1 : 0;
+          x += (((x + 1) * (x + 2)) >> 1) <= e ? 1 : 0;
+          k1[u] = x;
+          k2[u] = e - ((x * (x + 1)) >> 1);
+        }
+        int pq1[TB], pq2[TB];
+        double c1[TB], s1[TB], c2[TB], s2[TB];
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          pq1[u] = pq_cur[k1[u]]; pq2[u] = pq_cur[k2[u]];
+          c1[u] = pc[k1[u]]; s1[u] = ps[k1[u]];
+          c2[u] = pc[k2[u]]; s2[u] = ps[k2[u]];
+        }
+        double ea[TB], eb[TB], ec_[TB], ed[TB];
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          const int p1 = pq1[u] & 0xffff, q1 = min(pq1[u] >> 16, n - 1);
+          const int p2 = pq2[u] & 0xffff, q2 = min(pq2[u] >> 16, n - 1);
+          ea[u] = Ap[packed_at(p1, p2)];
+          eb[u] = Ap[packed_at(p1, q2)];
+          ec_[u] = Ap[packed_at(q1, p2)];
+          ed[u] = Ap[packed_at(q1, q2)];
+        }
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          // row rotation of pair k1, then column rotation of pair k2
+          double a = c1[u] * ea[u] - s1[u] * ec_[u];
+          double c_ = s1[u] * ea[u] + c1[u] * ec_[u];
+          double b = c1[u] * eb[u] - s1[u] * ed[u];
+          double d_ = s1[u] * eb[u] + c1[u] * ed[u];
+          const double a2 = c2[u] * a - s2[u] * b, b2 = s2[u] * a + c2[u] * b;
+          const double c2_ = c2[u] * c_ - s2[u] * d_, d2 = s2[u] * c_ + c2[u] * d_;
+          const bool live = e0 + u * (int)blockDim.x < ntri && (s1[u] != 0.0 || s2[u] != 0.0);
+          if (live) {
+            const int p1 = pq1[u] & 0xffff, q1 = pq1[u] >> 16, p2 = pq2[u] & 0xffff, q2 = pq2[u] >> 16;
+            const bool hq1 = q1 < n, hq2 = q2 < n;
+            Ap[packed_at(p1, p2)] = a2;
+            if (hq2) Ap[packed_at(p1, q2)] = b2;
+            // on a diagonal block (q1, p2) is (p2, q1) = (p1, q2), stored above
+            if (hq1 && k1[u] != k2[u]) Ap[packed_at(q1, p2)] = c2_;
+            if (hq1 && hq2) Ap[packed_at(q1, q2)] = d2;
+          }
+        }
+      }
+      // V <- V J: the entries loaded at the start of the round, then the
+      // rest in batches of VB (loaded here)
+      {
+        int vi = vi0, vk = vk0;
+        for (int b = 0; vk < np; ++b) {
+          if (b > 0) {
+            int wi = vi, wk = vk;
+#pragma unroll
+            for (int u = 0; u < VB; ++u) {
+              const int pqk = pq_cur[min(wk, np - 1)];
+              vx[u] = VT[(pqk & 0xffff) * ldv + wi];
+              vy[u] = VT[min(pqk >> 16, n - 1) * ldv + wi];
+              wi += ri; wk += rk;
+              if (wi >= n) { wi -= n; ++wk; }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < VB; ++u) {
+            const double s = vk < np ? ps[vk] : 0.0;
+            if (s != 0.0) {
+              const int pqk = pq_cur[vk];
+              const double c = pc[vk];
+              VT[(pqk & 0xffff) * ldv + vi] = c * vx[u] - s * vy[u];
+              VT[(pqk >> 16) * ldv + vi] = s * vx[u] + c * vy[u];
+            }
+            vi += ri; vk += rk;
+            if (vi >= n) { vi -= n; ++vk; }
+          }
+        }
+      }
+      int* t = pq_cur; pq_cur = pq_nxt; pq_nxt = t;
       __syncthreads();
     }
     int cnt = *sh_cnt;

@@ -385,10 +385,12 @@ def test_metric_fix(real):
 
 @pytest.mark.parametrize("real", [False, True])
 def test_metric_fix_eigensolver_full_size(real):
-    """The clip's eigen-solve at the largest metric of the workloads (n = 256,
-    D = 8, r = 2) and on an odd block (n = 144 with one zero row and column):
-    each thread of the Jacobi takes several chunks of rotation and
-    eigenvector updates per round, and the pair indices wrap across rows."""
+    """The clip at the largest metric of the workloads (n = 256, D = 8, r = 2)
+    and on an odd block (n = 144 with one zero row and column).  Complex: the
+    Jacobi eigen-solve, each thread taking several chunks of rotation and
+    eigenvector updates per round, the pair indices wrapping across rows.
+    Real (n >= 128): the sign iteration, (g + g sign(g)) / 2, with the
+    clipped mass from traces and no eigenvalues (NaN)."""
     rng = np.random.default_rng(31 + int(real))
     for n, D, zero in ((256, 8, ()), (144, 6, (7,))):
         M = rng.standard_normal((n, n)) + (0 if real else 1j * rng.standard_normal((n, n)))
@@ -402,8 +404,41 @@ def test_metric_fix_eigensolver_full_size(real):
         st = to_np(ntu.ntu_metric_fix(ctx, gt, D, ntu.FIX_HERM_CLIP))
         out = to_np(gt)
         assert rel(out[0], go) < 1e-12 and rel(out[1], 2.0 * go) < 1e-12, (n, rel(out[0], go))
-        assert np.all(st[:, 5] == 1.0)
-        assert abs(st[0, 2] - so['lam_min']) < 1e-12 * abs(so['lam_max'])
+        if real:
+            assert np.all(st[:, 5] == 2.0) and np.all(np.isnan(st[:, 2:4]))
+            assert abs(st[0, 4] - so['clipped']) < 1e-10 * so['clipped']
+            assert abs(st[1, 4] - so['clipped']) < 1e-10 * so['clipped']
+        else:
+            assert np.all(st[:, 5] == 1.0)
+            assert abs(st[0, 2] - so['lam_min']) < 1e-12 * abs(so['lam_max'])
+
+
+@pytest.mark.parametrize("n, D", [(400, 5), (256, 8)])
+def test_metric_fix_sign_iteration_degenerate(n, D):
+    """Real metrics of the thermal workloads (n = (D r_g)^2 = 400 for the
+    Hermitian purification at D = 5, r_g = 4; 256 at D = 8, r_g = 2): a
+    quarter of the spectrum spread over six decades, the rest a null space
+    with +-1e-7 noise (the split-precision departure from non-negativity).
+    The sign iteration's clip equals the oracle's eigen-decomposition clip
+    to 1e-12; in the same batch a positive definite item is certified and
+    left alone (the iteration skips it)."""
+    rng = np.random.default_rng(41 + n)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.concatenate([np.logspace(0, -6, n // 4), 1e-7 * rng.standard_normal(n - n // 4)])
+    g = (Q * lam) @ Q.T
+    g = 0.5 * (g + g.T)
+    gpd = (Q * np.linspace(0.5, 2.0, n)) @ Q.T
+    gpd = 0.5 * (gpd + gpd.T)
+    go, so = O.metric_fix(g)
+    rg = 4 if n == 400 else 2
+    ctx = ntu.Context(complex_=False, d=2, d_anc=2 if rg == 2 else 1, r_g=rg, max_D=D, max_batch=2)
+    gt = batched([g, gpd])
+    st = to_np(ntu.ntu_metric_fix(ctx, gt, D, ntu.FIX_HERM_CLIP))
+    out = to_np(gt)
+    assert rel(out[0], go) < 1e-12, rel(out[0], go)
+    assert np.array_equal(out[0], out[0].T)
+    assert st[0, 5] == 2.0 and abs(st[0, 4] - so['clipped']) < 1e-9 * so['clipped']
+    assert st[1, 5] == 0.0 and np.array_equal(out[1], gpd)
 
 # ------------------------------------------------------------------ fit
 
