@@ -78,6 +78,25 @@ def anticommutator_matrix(h: np.ndarray) -> np.ndarray:
     return K.real.copy()
 
 
+def anticommutator_matrix_1(h: np.ndarray) -> np.ndarray:
+    """One-site form of :func:`anticommutator_matrix`: ``K[a, a'] =
+    Tr(O^a {h, O^a'}) / 4`` (``h = 1`` gives the identity)."""
+    h = np.asarray(h, dtype=np.complex128)
+    K = np.array([[np.trace(BASIS[a] @ (h @ BASIS[b] + BASIS[b] @ h)) / 4.0 for b in range(4)] for a in range(4)])
+    assert np.abs(K.imag).max() <= 1e-12 * max(1.0, np.abs(K).max())
+    return K.real.copy()
+
+
+def ctmrg_ops():
+    """Operators of the CTMRG expectation values of the Hermitian
+    purification on its basis index: ``X``, ``Z`` (one site) and ``ZZ`` (two
+    sites) as the matrices of their anticommutators (``<O> = c^T K_O c / c^T
+    c``)."""
+    X_, Z_ = BASIS[0], BASIS[2]
+    return dict(X=anticommutator_matrix_1(X_), Z=anticommutator_matrix_1(Z_),
+                ZZ=anticommutator_matrix(np.kron(Z_, Z_)))
+
+
 def gate_factors(G: np.ndarray):
     """Rank-4 split (Fig. 2(a)) of the action of ``G``: ``(GA, GB, sigma)``
     with ``GA[a', a, k]``, ``GB[b', b, k]`` real."""
