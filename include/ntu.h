@@ -383,6 +383,51 @@ int ntu_profile_read(ntu_ctx* ctx, double* ms, int* count, int n);
 const char* ntu_profile_kind_name(int kind);
 
 /*
+ * CTMRG expectation values (the corner transfer matrix renormalisation the
+ * paper uses for observables, Secs. II, III and V) of the two-site
+ * checkerboard state (A, B): A on the sites (x, y) with x + y even, the r leg
+ * of (x, y) joined to the l leg of (x + 1, y), the t leg to the b leg of
+ * (x, y + 1); bonds H1 = A.r - B.l, H2 = B.r - A.l, V1 = A.t - B.b, V2 =
+ * B.t - A.b.  The network is the double layer sum_s conj(T[s']) T[s] of every
+ * site (with an operator O[s', s] on the physical index for expectation
+ * values), its environment built on a 2 x 2 cell by directional moves: each
+ * iteration is four left moves, the lattice turned a quarter turn clockwise
+ * after each; a left move absorbs a column into the left environment, the
+ * fused legs on each cut between two rows going through the chi leading left
+ * singular vectors of rho, the half-system density matrix of the 2 x 2 block
+ * around the cut.  Starting boundary: bond dimension 1 with the ket-bra
+ * identity on the inner legs.  Computation in complex128 on the GPU (one
+ * workgroup per cut for the singular vectors: chi D^2 <= 256).
+ *
+ * ntu_ctm_create: for physical dimension p (the full site index: d, d times
+ * the ancilla, or the 4 basis operators of the Hermitian purification), bond
+ * dimension D <= 8 and environment dimension chi; allocates its device
+ * memory.  NTU_ERR_SHAPE outside those limits.
+ * ntu_ctm_run: n_iter iterations for the state A, B ((p, D, D, D, D),
+ * NTU_F64 or NTU_C128, device) from the starting boundary (reset != 0, or
+ * the first call) or from the environment of the previous call.
+ * ntu_ctm_expect: expectation values in the current environment, written to
+ * out ((2 n1 + 4), NTU_C128, device): out[2k], out[2k + 1] = <O_k> at A and
+ * at B for the one-site operators ops1 ((n1, p, p), NTU_C128, n1 <= 16, row
+ * index s', column s); out[2 n1 + b], b = H1, H2, V1, V2, = <h> for the
+ * two-site operator h = sum_t ops2[t, 0] (x) ops2[t, 1] ((n2, 2, p, p),
+ * NTU_C128, 1 <= n2 <= 16), the first factor on A.r's site for H1, B's for
+ * H2, the lower site for V1 and V2.  Each value is the ratio of the network
+ * with the operators inserted to the norm network.
+ * All three run on the stream set by ntu_ctm_set_stream (default the null
+ * stream) without synchronising, except ntu_ctm_run's first call (it copies
+ * the starting boundary from the host).  Errors: ntu_ctm_last_error.
+ */
+typedef struct ntu_ctm ntu_ctm;
+ntu_status ntu_ctm_create(ntu_ctm** out, int device, int p, int D, int chi);
+ntu_status ntu_ctm_destroy(ntu_ctm* ctm);
+ntu_status ntu_ctm_set_stream(ntu_ctm* ctm, void* stream);
+const char* ntu_ctm_last_error(const ntu_ctm* ctm);
+ntu_status ntu_ctm_run(ntu_ctm* ctm, const ntu_tensor* A, const ntu_tensor* B, int n_iter, int reset);
+ntu_status ntu_ctm_expect(ntu_ctm* ctm, const ntu_tensor* A, const ntu_tensor* B, const ntu_tensor* ops1,
+                          const ntu_tensor* ops2, ntu_tensor* out);
+
+/*
  * Metric repair without allocation, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc): the same operation and kernels as ntu_metric_fix, with

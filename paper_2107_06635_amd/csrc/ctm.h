@@ -1,0 +1,37 @@
+// Device launchers of the CTMRG expectation values (k_ctm.hip).  Every
+// tensor is complex128, dense and row-major; every launcher enqueues on the
+// given stream, allocates nothing and does not synchronise.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "common.h"
+
+namespace ntu {
+
+constexpr int CTM_MAX_RANK = 8;
+
+// out[i_0 .. i_{r-1}] = op(in[...]) with in's axis perm[k] becoming out's
+// axis k: out_shape[k] = in_shape[perm[k]]; op = conj or identity.
+hipError_t ctm_permute(const cd* in, cd* out, int rank, const int* in_shape, const int* perm, bool conj,
+                       hipStream_t st);
+// C (M x N) = A (M x K) B (K x N), row-major; K = 0 writes zeros.
+hipError_t ctm_gemm(const cd* A, const cd* B, cd* C, int M, int N, int K, hipStream_t st);
+// dst[i] = src[i] (real to complex), n entries
+hipError_t ctm_widen(const double* src, cd* dst, long long n, hipStream_t st);
+// x /= max_i |x_i| (left unchanged when all zero); slot: one unsigned long
+// long of scratch
+hipError_t ctm_normalise(cd* x, long long n, unsigned long long* slot, hipStream_t st);
+// Z (n x k, orthonormal columns) = the left singular vectors of the k
+// largest singular values of the n x n matrix rho (n <= CTM_SVD_NMAX), in
+// descending order, completed by unit vectors where rho has rank below k;
+// ws: 8 n^2 entries of scratch.  One workgroup: cyclic Jacobi on the 2n x 2n
+// Hermitian matrix [[0, rho], [rho^H, 0]].
+constexpr int CTM_SVD_NMAX = 256;
+hipError_t ctm_svd_left(const cd* rho, int n, int k, cd* Z, cd* ws, hipStream_t st);
+// out[i] = num[i] / den[i], n entries
+hipError_t ctm_ratio(const cd* num, const cd* den, cd* out, int n, hipStream_t st);
+// out[b] = (sum_t term[b nt + t]) / den[b], nb entries
+hipError_t ctm_sum_ratio(const cd* term, const cd* den, cd* out, int nb, int nt, hipStream_t st);
+// x[i] = 0, n entries
+hipError_t ctm_zero(cd* x, long long n, hipStream_t st);
+
+}  // namespace ntu

@@ -34,6 +34,7 @@ EXPORTED = (
     "ntu_profile_enable", "ntu_profile_read", "ntu_profile_kind_name",
     "ntu_tune_env", "ntu_set_env_ksplit", "ntu_get_env_ksplit", "ntu_tune_save", "ntu_tune_load",
     "ntu_metric_fix_noalloc", "ntu_superop_gate",
+    "ntu_ctm_create", "ntu_ctm_destroy", "ntu_ctm_set_stream", "ntu_ctm_last_error", "ntu_ctm_run", "ntu_ctm_expect",
 )
 
 
@@ -101,9 +102,16 @@ def load():
     L.ntu_profile_kind_name.restype = ctypes.c_char_p
     L.ntu_metric_fix_noalloc.argtypes = [vp, i32, tp, i32, tp]
     L.ntu_superop_gate.argtypes = [vp, i32, tp, tp]
+    L.ntu_ctm_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32]
+    L.ntu_ctm_destroy.argtypes = [vp]
+    L.ntu_ctm_set_stream.argtypes = [vp, vp]
+    L.ntu_ctm_last_error.argtypes = [vp]
+    L.ntu_ctm_last_error.restype = ctypes.c_char_p
+    L.ntu_ctm_run.argtypes = [vp, tp, tp, i32, i32]
+    L.ntu_ctm_expect.argtypes = [vp, tp, tp, tp, tp, tp]
     for name in EXPORTED:
         if name not in ("ntu_last_error", "ntu_workspace_bytes", "ntu_version", "ntu_fit_opts_default",
-                        "ntu_step_opts_default", "ntu_profile_kind_name"):
+                        "ntu_step_opts_default", "ntu_profile_kind_name", "ntu_ctm_last_error"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -376,3 +384,49 @@ def ntu_profile_read(ctx: Context):
     if k < 0:
         raise RuntimeError("ntu_profile_read failed")
     return {ctx.L.ntu_profile_kind_name(i).decode(): (ms[i], cnt[i]) for i in range(k) if cnt[i] > 0}
+
+
+class CTM:
+    """CTMRG environment of a two-site checkerboard state (ntu_ctm_*)."""
+
+    def __init__(self, p, D, chi, device=0):
+        self.L = load()
+        self.p, self.D, self.chi = p, D, chi
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        st = self.L.ntu_ctm_create(ctypes.byref(h), device, p, D, chi)
+        if st != NTU_OK:
+            raise RuntimeError(f"ntu_ctm_create: status {st}: {self.L.ntu_last_error(None).decode()}")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ntu_ctm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != NTU_OK:
+            raise RuntimeError(f"{what}: status {st}: {self.L.ntu_ctm_last_error(self.h).decode()}")
+
+    def _bind(self):
+        self.L.ntu_ctm_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def run(self, A, B, n_iter, reset=True):
+        """n_iter iterations for the state (A, B) ((p, D, D, D, D) device tensors)."""
+        self._bind()
+        self._check(self.L.ntu_ctm_run(self.h, _ref(A), _ref(B), n_iter, int(reset)), "ntu_ctm_run")
+
+    def expect(self, A, B, ops1, ops2):
+        """ops1: (n1, p, p), ops2: (n2, 2, p, p) complex128 device tensors ->
+        (2 n1 + 4,) complex128: <O_k> at A and B, then <h> on H1, H2, V1, V2."""
+        out = torch.empty(2 * ops1.shape[0] + 4, dtype=torch.complex128, device=self.device)
+        self._bind()
+        self._check(self.L.ntu_ctm_expect(self.h, _ref(A), _ref(B), _ref(ops1), _ref(ops2), _ref(out)),
+                    "ntu_ctm_expect")
+        return out
