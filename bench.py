@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batched", choices=["batched", "thermal", "large", "hermitian"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "thermal", "large", "hermitian", "ctmrg"])
     ap.add_argument("--precision", default=None, choices=["bf16x3", "bf16x6", "fp16x3", "f64"],
                     help="environment precision (default: fp16x3 for the batched workload; bf16x6 for the "
                          "others, whose real or D > 8 metrics take the tiled path FP16x3 does not cover)")
@@ -85,6 +85,7 @@ def parse():
                     help="GPU_MAX_HW_QUEUES for this process (hardware queues the streams are spread over)")
     ap.add_argument("--aux", default="own", choices=["own", "shared"],
                     help="side stream of each bucket's Trotter step: the context's own, or one shared by all")
+    ap.add_argument("--ctm-D", type=int, default=3, help="bond dimension of the CTMRG workload (chi = 4 D)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (20 times) and print its "
                          "rate: the reference kernel for scaling HBM byte counters")
@@ -568,6 +569,79 @@ def main_large(args, ntu, torch, np, dev, inputs):
     print(json.dumps(result), flush=True)
 
 
+def main_ctmrg(args, ntu, torch, np, dev, inputs):
+    """CTMRG expectation values (the environment the paper uses for
+    observables, chi = 4 D as in Sec. III) of a configuration-2 quench state
+    evolved on the GPU; K iterations timed after W untimed ones."""
+    D = args.ctm_D
+    chi = 4 * D
+    K = args.steps if args.steps_given else 20
+    W = args.warmup
+    w = inputs.workload_quench(seed=2, D=D)
+    ctx = ntu.Context(complex_=True, d=2, d_anc=1, r_g=2, max_D=D, max_batch=1)
+    ctx.bind_stream()
+    G = torch.from_numpy(np.ascontiguousarray(w["gates"][0][None])).to(dev)
+    GA, GB, _ = ntu.ntu_gate_split(ctx, G)
+    gf = torch.stack([torch.stack([GA[0], GB[0]])] * 4)[None].contiguous()
+    A = torch.from_numpy(w["A"][None]).to(dev).contiguous()
+    B = torch.from_numpy(w["B"][None]).to(dev).contiguous()
+    o64 = ntu.step_opts("f64", n_iter=20, early_stop=True, conv_tol=1e-12)
+    for _ in range(5):
+        ntu.ntu_trotter_step(ctx, A, B, gf, o64)
+    torch.cuda.synchronize()
+    A0, B0 = A[0].contiguous(), B[0].contiguous()
+    ctm = ntu.CTM(2, D, chi)
+    ctm.run(A0, B0, max(W, 1))
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    ctm.run(A0, B0, K, reset=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    X = np.array([[0, 1], [1, 0]], complex)
+    Z = np.diag([1.0, -1.0]).astype(complex)
+    ops1 = torch.from_numpy(np.stack([X, Z])).to(dev)
+    ops2 = torch.from_numpy(np.stack([np.stack([Z, Z])])).to(dev)
+    t0 = time.perf_counter()
+    vals = ctm.expect(A0, B0, ops1, ops2).cpu().numpy()
+    t_exp = time.perf_counter() - t0
+    hx = inputs.H_CRIT
+    sx = 0.5 * (vals[0] + vals[1]).real
+    e = float(-0.5 * vals[4:8].sum().real - hx * sx)
+    result = {
+        "metric": f"CTMRG iterations/s at chi=4D (D={D})", "value": K / (ms / 1e3), "unit": "iterations/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": f"CTMRG environment of a configuration-2 quench state (seed 2, D={D}, five FP64 NTU "
+                               f"sweeps at dt=0.01 on the GPU), chi={chi}, 2x2 cell, four directional moves per "
+                               f"iteration, from the identity boundary", "D": D, "chi": chi},
+        "observables": {"energy_per_site": e, "sx": sx, "expect_seconds": t_exp,
+                        "after_iterations": K},
+    }
+    if not args.no_cpu:
+        from oracle import ctmrg as OC
+        An, Bn = A0.cpu().numpy(), B0.cpu().numpy()
+        t0 = time.perf_counter()
+        n = 0
+        env = None
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            env = OC.ctmrg(An, Bn, chi, 1, env=env)
+            n += 1
+        el = time.perf_counter() - t0
+        model, ncpu = host_cpu()
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count()
+        result["cpu_baseline"] = {"value": n / el, "unit": "iterations/s", "cores": cores, "kind": "oracle",
+                                  "sample": f"{n} CTMRG iterations of the same state from the identity boundary, "
+                                            f"oracle FP64 numpy/BLAS", "cpu_model": model,
+                                  "logical_cpus_visible": ncpu}
+    print(json.dumps(result), flush=True)
+
+
 def run_mixed_child(args, K, W):
     """The mixed workload (--bucket 0) in a child process; its JSON line
     reduced to the fields reported under mixed_workload."""
@@ -620,6 +694,9 @@ def main():
         args.no_fp64 = True
     if args.workload == "large":
         main_large(args, ntu, torch, np, dev, inputs)
+        return
+    if args.workload == "ctmrg":
+        main_ctmrg(args, ntu, torch, np, dev, inputs)
         return
     all_items = None
     if args.workload == "batched":

@@ -40,11 +40,16 @@ each cut replaced through ``Z``.  Moves in the other three directions are the
 left move of the lattice rotated by quarter turns (:func:`rotate`).  Every new
 tensor is divided by its largest modulus.
 
-Readings (also in the design doc): isometric projectors from the half-system
-density matrix of the 2 x 2 block (the paper does not specify the CTM
-variant); identity initial boundary; convergence when the normalised
-singular values of every corner change by less than ``tol`` between
-iterations.
+Readings (the paper does not specify the CTM variant): isometric projectors
+from the half-system density matrix of the 2 x 2 block; identity initial
+boundary; a fixed number of iterations (the corner spectra of these states hold
+degenerate multiplets whose order does not settle, so observables, not
+spectra, are what is compared; :func:`converged_observables` iterates until
+they stop moving); directions of a cut beyond the numerical rank of ``rho``
+(singular values at most ``RANK_EPS`` times the largest) fixed by Gram-Schmidt
+completion with unit vectors in order (:func:`complete_isometry`), since any
+orthonormal completion is a valid SVD there and the choice changes the
+environment that later iterations build on.
 """
 from __future__ import annotations
 
@@ -130,9 +135,36 @@ def _corners(env, sites, x, y):
     return Q1, Q2, Q3, Q4
 
 
+RANK_EPS = 1e-12
+
+
+def complete_isometry(U: np.ndarray, s: np.ndarray, k: int) -> np.ndarray:
+    """The first ``k`` columns of ``U`` whose singular values exceed
+    ``RANK_EPS * s[0]``, followed by unit vectors ``e_0, e_1, ...`` (each
+    tried once, in order) orthogonalised twice against every column before
+    them and kept when at least half of their length is left, until there are
+    ``k`` columns."""
+    n = U.shape[0]
+    r = int(np.sum(s[:k] > RANK_EPS * s[0])) if s.size and s[0] > 0 else 0
+    cols = [U[:, j] for j in range(r)]
+    unit = 0
+    while len(cols) < k:
+        v = np.zeros(n, dtype=U.dtype)
+        v[unit] = 1.0
+        unit += 1
+        for _ in range(2):
+            for q in cols:
+                v = v - q * np.vdot(q, v)
+        nv = np.linalg.norm(v)
+        if nv > 0.5:
+            cols.append(v / nv)
+    return np.stack(cols, axis=1)
+
+
 def cut_isometry(env, sites, x, y, chi):
     """Isometry of the left cut between rows y and y + 1 at column x:
-    ``chi`` leading left singular vectors of ``rho = H_u H_d^T``.  Returns
+    ``chi`` leading left singular vectors of ``rho = H_u H_d^T`` (completed
+    by :func:`complete_isometry` where ``rho`` has smaller rank).  Returns
     ``Z`` (rows: the fused index (edge bond, double-layer bond)) and the
     singular values of ``rho``."""
     Q1, Q2, Q3, Q4 = _corners(env, sites, x, y)
@@ -141,7 +173,7 @@ def cut_isometry(env, sites, x, y, chi):
     rho = Hu @ Hd.T
     U, s, _ = np.linalg.svd(rho)
     k = min(chi, U.shape[1])
-    return U[:, :k], s
+    return complete_isometry(U, s, k), s
 
 
 def left_move(env, sites, chi):

@@ -26,7 +26,7 @@ Index conventions
   (rows = bra pair), so that Eq. (2) reads ``eps = d^H g d`` with
   ``d = vec(MX MY^T - RX RY^T)`` in row-major ``(a, b)`` order.
 
-Readings of the paper that this file fixes (each also listed in the design doc):
+Readings of the paper that this file fixes (where it is silent or ambiguous):
 rank rule ``KAPPA`` for the QR and the truncation, the pseudo-inverse tolerance
 ladder ``TOL_LADDER`` with direct evaluation of the error, ties going to the
 larger tolerance, normalisation of the singular values by the largest one, and

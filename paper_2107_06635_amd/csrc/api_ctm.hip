@@ -226,7 +226,7 @@ Tn double_layer(ntu_ctm* c, Err& E, const Tn& T, const Tn* O) {
 }
 
 // ---------------------------------------------------------------- moves
-Tn cut_isometry(ntu_ctm* c, Err& E, int x, int y) {
+Tn cut_density(ntu_ctm* c, Err& E, int x, int y) {
   const int x1 = (x + 1) % 2, y1 = (y + 1) % 2;
   const EnvT &tl = c->env[x][y1], &tr = c->env[x1][y1], &br = c->env[x1][y], &bl = c->env[x][y];
   const Tn &atl = c->site[x][y1], &atr = c->site[x1][y1], &abr = c->site[x1][y], &abl = c->site[x][y];
@@ -250,16 +250,34 @@ Tn cut_isometry(ntu_ctm* c, Err& E, int x, int y) {
   Tn Q4 = reshape(q4, {q4.s[0] * q4.s[1], q4.s[2] * q4.s[3]});
   Tn Hu = contract(c, E, "ki,kw->iw", Q1, false, Q2, false);
   Tn Hd = contract(c, E, "jk,wk->jw", Q4, false, Q3, false);
-  Tn rho = contract(c, E, "iw,jw->ij", Hu, false, Hd, false);
-  if (E.e != hipSuccess) return Tn();
-  const int n = rho.s[0], k = n < c->chi ? n : c->chi;
-  int zs[2] = {n, k};
-  Tn Z = alloc(c, E, zs, 2);
-  cd* ws = arena_get(c, 8ll * n * n);
-  if (!ws) E.set(hipErrorOutOfMemory, "ctm arena");
-  if (E.e != hipSuccess) return Tn();
-  E.set(ntu::ctm_svd_left(rho.p, n, k, Z.p, ws, c->stream), "svd");
-  return Z;
+  return contract(c, E, "iw,jw->ij", Hu, false, Hd, false);
+}
+
+// The isometries of the two cuts of column x (between rows y and y + 1, for
+// y = 0, 1): one launch over both when their sizes agree.
+void cut_isometries(ntu_ctm* c, Err& E, int x, Tn Z[2]) {
+  Tn rho[2];
+  for (int y = 0; y < 2; ++y) rho[y] = cut_density(c, E, x, y);
+  if (E.e != hipSuccess) return;
+  cd* ws[2] = {nullptr, nullptr};
+  for (int y = 0; y < 2; ++y) {
+    const int n = rho[y].s[0], k = n < c->chi ? n : c->chi;
+    int zs[2] = {n, k};
+    Z[y] = alloc(c, E, zs, 2);
+    if (n > ntu::CTM_SVD_REG_NMAX) {
+      ws[y] = arena_get(c, (long long)n * n);
+      if (!ws[y]) E.set(hipErrorOutOfMemory, "ctm arena");
+    }
+  }
+  if (E.e != hipSuccess) return;
+  if (rho[0].s[0] == rho[1].s[0]) {
+    const cd* r2[2] = {rho[0].p, rho[1].p};
+    cd* z2[2] = {Z[0].p, Z[1].p};
+    E.set(ntu::ctm_svd_left(2, r2, rho[0].s[0], Z[0].s[1], z2, ws, c->stream), "svd");
+  } else {
+    for (int y = 0; y < 2 && E.e == hipSuccess; ++y)
+      E.set(ntu::ctm_svd_left(1, &rho[y].p, rho[y].s[0], Z[y].s[1], &Z[y].p, &ws[y], c->stream), "svd");
+  }
 }
 
 void left_move(ntu_ctm* c, Err& E) {
@@ -267,7 +285,7 @@ void left_move(ntu_ctm* c, Err& E) {
     const int x1 = (x + 1) % 2;
     c->arena_top = 0;
     Tn Z[2];
-    for (int y = 0; y < 2; ++y) Z[y] = cut_isometry(c, E, x, y);
+    cut_isometries(c, E, x, Z);
     Tn nC1[2], nT4[2], nC4[2];
     for (int y = 0; y < 2 && E.e == hipSuccess; ++y) {
       const EnvT& e = c->env[x][y];

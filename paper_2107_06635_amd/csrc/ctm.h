@@ -22,11 +22,18 @@ hipError_t ctm_widen(const double* src, cd* dst, long long n, hipStream_t st);
 hipError_t ctm_normalise(cd* x, long long n, unsigned long long* slot, hipStream_t st);
 // Z (n x k, orthonormal columns) = the left singular vectors of the k
 // largest singular values of the n x n matrix rho (n <= CTM_SVD_NMAX), in
-// descending order, completed by unit vectors where rho has rank below k;
-// ws: 8 n^2 entries of scratch.  One workgroup: cyclic Jacobi on the 2n x 2n
-// Hermitian matrix [[0, rho], [rho^H, 0]].
+// descending order; where rho has numerical rank r < k (singular values at
+// most CTM_RANK_EPS sigma_1 beyond), columns r..k-1 are unit vectors e_0,
+// e_1, .. in order, each orthogonalised twice against the columns before it
+// and kept when more than half its length is left;
+// count (<= CTM_SVD_BATCH) independent matrices of one size in one launch.
+// ws[b]: n^2 entries of scratch when n > CTM_SVD_REG_NMAX (else unused).
+// One-sided Jacobi on rho's columns, one workgroup per matrix.
 constexpr int CTM_SVD_NMAX = 256;
-hipError_t ctm_svd_left(const cd* rho, int n, int k, cd* Z, cd* ws, hipStream_t st);
+constexpr int CTM_SVD_REG_NMAX = 128;
+constexpr int CTM_SVD_BATCH = 4;
+constexpr double CTM_RANK_EPS = 1e-12;
+hipError_t ctm_svd_left(int count, const cd* const* rho, int n, int k, cd* const* Z, cd* const* ws, hipStream_t st);
 // out[i] = num[i] / den[i], n entries
 hipError_t ctm_ratio(const cd* num, const cd* den, cd* out, int n, hipStream_t st);
 // out[b] = (sum_t term[b nt + t]) / den[b], nb entries

@@ -1,6 +1,6 @@
 // Device primitives of the CTMRG expectation values: permutation of tensor
 // axes, complex products, normalisation by the largest modulus, and the
-// leading eigenvectors of a Hermitian matrix (the isometry of a cut).
+// leading left singular vectors of a matrix (the isometry of a cut).
 #include "ctm.h"
 #include "linalg.h"
 
@@ -146,93 +146,483 @@ hipError_t ctm_normalise(cd* x, long long n, unsigned long long* slot, hipStream
   return hipGetLastError();
 }
 
-// Leading left singular vectors of an n x n matrix rho without squaring its
-// singular values: the Hermitian matrix [[0, rho], [rho^H, 0]] (2n x 2n) has
-// the eigenvalues +-sigma_i with eigenvectors (u_i, +-v_i) / sqrt(2), so its
-// k largest eigenvalues give u_1..u_k, resolved down to rounding relative to
-// sigma_1 (the eigenproblem of rho rho^H would lose the singular values
-// below sqrt(eps) sigma_1).  Cyclic Jacobi on the 2n matrix (copied into A,
-// eigenvectors into V), the upper halves of the k leading eigenvectors times
-// sqrt(2) into Z, then Gram-Schmidt twice over Z's columns; a column with
-// nothing left after the projections (rho of rank below k) is replaced by
-// the first unit vector that leaves something, so Z always has orthonormal
-// columns.  One workgroup.
-__global__ void __launch_bounds__(1024) k_ctm_svd_left(const cd* __restrict__ rho, int n, int k, cd* __restrict__ Z,
-                                                       cd* __restrict__ A, cd* __restrict__ V) {
-  constexpr int NM = 2 * CTM_SVD_NMAX;
-  __shared__ double pc[NM / 2 + 1], ps[NM / 2 + 1];
-  __shared__ cd pe[NM / 2 + 1];
-  __shared__ int pq[NM / 2 + 1];
-  __shared__ int cnt, pick_sh;
-  __shared__ double lam[NM];
-  __shared__ double red[64];
-  __shared__ int rank_of[NM];
-  const int tid = threadIdx.x, m = 2 * n;
-  double fro = 0.0;
-  for (long long e = tid; e < (long long)m * m; e += blockDim.x) {
-    const int i = (int)(e / m), j = (int)(e % m);
-    cd v{0.0, 0.0};
-    if (i < n && j >= n) v = rho[(long long)i * n + (j - n)];
-    else if (i >= n && j < n) v = conjv(rho[(long long)j * n + (i - n)]);
-    A[e] = v;
-    fro += abs2(v);
+// Leading left singular vectors of an n x n matrix rho by one-sided
+// (Hestenes) Jacobi: the columns of W = rho are rotated pairwise, W <- W J
+// with J the 2 x 2 unitary that makes the pair orthogonal, until every pair
+// is; then W = U Sigma, and the k columns of largest norm, normalised, are
+// u_1..u_k.  The singular values are not squared, so a column of norm
+// sigma_j keeps its direction to about eps sigma_1 / sigma_j, which the
+// network weighs by sigma_j.  A pair is left alone when its inner product is
+// below tol sqrt(|w_p|^2 |w_q|^2), tol = 4 eps sqrt(n) (the rounding floor
+// of an n-term inner product, so a sweep with no rotation does come), or
+// below (1e-15 ||rho||_F)^2.  Gram-Schmidt twice over the chosen columns,
+// with unit vectors taking the place of columns beyond the numerical rank
+// (norm at most CTM_RANK_EPS sigma_1), makes Z orthonormal.  One workgroup of 1024 per matrix.
+
+constexpr int SVD_SWEEPS = 40;
+
+// the unitary of one pair from its Gram entries al = |w_p|^2, be = |w_q|^2,
+// ga = w_p^H w_q: with y = e^{-i arg ga} w_q the pair becomes real, and the
+// plane rotation (c, s) with t = s / c the smaller root of
+// t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 |ga|), zeroes its inner
+// product: w_p <- c w_p - s y, w_q <- s w_p + c y.  False: nothing to do.
+NTU_DEV bool hestenes_params(double al, double be, cd ga, double tiny, double tol, double& c, double& s, cd& em) {
+  const double g = absv(ga);
+  if (!(g > tiny) || !(g > tol * sqrt(al * be))) return false;
+  const double zeta = (be - al) / (2.0 * g);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = c * t;
+  em = cd{ga.x / g, -ga.y / g};
+  return true;
+}
+
+template <int PER> NTU_DEV void pair_gram(const cd (&a)[PER], const cd (&b)[PER], double& al, double& be, cd& ga) {
+  al = 0.0;
+  be = 0.0;
+  ga = cd{0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    al += abs2(a[u]);
+    be += abs2(b[u]);
+    ga += cmul(a[u], b[u]);
   }
-  fro = sqrt(block_sum(fro, red));
-  __syncthreads();
-  block_jacobi_eigh<cd>(A, m, m, V, m, pc, ps, pe, pq, &cnt, fro);
-  for (int i = tid; i < m; i += blockDim.x) lam[i] = A[(long long)i * m + i].x;
-  __syncthreads();
-  for (int i = tid; i < m; i += blockDim.x) {
-    int r = 0;
-    for (int j = 0; j < m; ++j) r += (lam[j] > lam[i] || (lam[j] == lam[i] && j < i)) ? 1 : 0;
-    rank_of[i] = r;
+}
+
+template <int PER> NTU_DEV void pair_rotate(cd (&a)[PER], cd (&b)[PER], double c, double s, cd em) {
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const cd y = em * b[u];
+    const cd an = c * a[u] - s * y;
+    b[u] = s * a[u] + c * y;
+    a[u] = an;
   }
-  __syncthreads();
-  const double sq2 = sqrt(2.0);
-  for (long long e = tid; e < (long long)n * m; e += blockDim.x) {
-    const int row = (int)(e / m), col = (int)(e % m);
-    const int r = rank_of[col];
-    if (r < k) Z[(long long)row * k + r] = V[(long long)row * m + col] * sq2;
-  }
-  __syncthreads();
-  // Gram-Schmidt twice, column by column, with completion
+}
+
+// Gram-Schmidt twice over the k columns of Z (n x k, row-major), in order,
+// replacing a column with nothing left by the next unit vector; then
+// normalised.  Every thread of the workgroup takes part.
+NTU_DEV void svd_orthonormalise(cd* Z, int n, int k, double* red, int* pick_sh) {
+  const int tid = threadIdx.x;
   int next_unit = 0;
-  for (int c = 0; c < k; ++c) {
+  for (int col = 0; col < k; ++col) {
     for (int attempt = 0; attempt <= n; ++attempt) {
       for (int pass = 0; pass < 2; ++pass)
-        for (int b = 0; b < c; ++b) {
+        for (int b = 0; b < col; ++b) {
           cd dot{0.0, 0.0};
-          for (int i = tid; i < n; i += blockDim.x) dot += cmul(Z[(long long)i * k + b], Z[(long long)i * k + c]);
+          for (int i = tid; i < n; i += blockDim.x) dot += cmul(Z[(long long)i * k + b], Z[(long long)i * k + col]);
           dot.x = block_sum(dot.x, red);
           dot.y = block_sum(dot.y, red);
           for (int i = tid; i < n; i += blockDim.x)
-            Z[(long long)i * k + c] = Z[(long long)i * k + c] - dot * Z[(long long)i * k + b];
+            Z[(long long)i * k + col] = Z[(long long)i * k + col] - dot * Z[(long long)i * k + b];
           __syncthreads();
         }
       double nn = 0.0;
-      for (int i = tid; i < n; i += blockDim.x) nn += abs2(Z[(long long)i * k + c]);
+      for (int i = tid; i < n; i += blockDim.x) nn += abs2(Z[(long long)i * k + col]);
       nn = sqrt(block_sum(nn, red));
       if (nn > 0.5) {
         const double inv = 1.0 / nn;
-        for (int i = tid; i < n; i += blockDim.x) Z[(long long)i * k + c] = Z[(long long)i * k + c] * inv;
+        for (int i = tid; i < n; i += blockDim.x) Z[(long long)i * k + col] = Z[(long long)i * k + col] * inv;
         __syncthreads();
         break;
       }
-      // nothing independent left: try the next unit vector
-      if (tid == 0) pick_sh = next_unit;
+      if (tid == 0) *pick_sh = next_unit;
       __syncthreads();
-      const int u = pick_sh;
-      for (int i = tid; i < n; i += blockDim.x) Z[(long long)i * k + c] = cd{i == u ? 1.0 : 0.0, 0.0};
+      const int u = *pick_sh;
+      for (int i = tid; i < n; i += blockDim.x) Z[(long long)i * k + col] = cd{i == u ? 1.0 : 0.0, 0.0};
       ++next_unit;
       __syncthreads();
     }
   }
 }
 
-hipError_t ctm_svd_left(const cd* rho, int n, int k, cd* Z, cd* ws, hipStream_t st) {
-  if (n < 1 || n > CTM_SVD_NMAX || k < 1 || k > n) return hipErrorInvalidValue;
-  const long long m = 2ll * n;
-  hipLaunchKernelGGL(k_ctm_svd_left, dim3(1), dim3(1024), 0, st, rho, n, k, Z, ws, ws + m * m);
+// rank_of[j] = the place of column j when the norms nrm[0..n) are sorted
+// descending (ties by index).  Returns the floor below which a column counts
+// as beyond the numerical rank: CTM_RANK_EPS times the largest norm.  Such
+// columns are written as zeros, so that the Gram-Schmidt completion puts
+// unit vectors in their place: any orthonormal completion is a singular
+// basis there, and this one is reproducible.
+NTU_DEV double svd_rank(const double* nrm, int* rank_of, int n) {
+  double mx = 0.0;
+  for (int j = 0; j < n; ++j) mx = fmax(mx, nrm[j]);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    int rk = 0;
+    for (int j = 0; j < n; ++j) rk += (nrm[j] > nrm[i] || (nrm[j] == nrm[i] && j < i)) ? 1 : 0;
+    rank_of[i] = rk;
+  }
+  __syncthreads();
+  return CTM_RANK_EPS * mx;
+}
+
+// y[first..C) moved one place down, y[first] to the end
+template <int PER, int C, int FIRST> NTU_DEV void shift_cols(cd (&y)[C][PER]) {
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const cd t = y[FIRST][u];
+#pragma unroll
+    for (int c = FIRST; c < C - 1; ++c) y[c][u] = y[c + 1][u];
+    y[C - 1][u] = t;
+  }
+}
+
+// NP disjoint pairs (a[ia + i], b[ib + di i]), i < NP, Gram entries summed
+// over the wave side by side, then rotated; returns the rotations made
+template <int PER, int C, int NP>
+NTU_DEV int svd_pairs(cd (&a)[C][PER], cd (&b)[C][PER], int ia, int ib, int di, double tiny, double tol) {
+  double al[NP], be[NP];
+  cd ga[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) pair_gram<PER>(a[ia + i], b[ib + di * i], al[i], be[i], ga[i]);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    al[i] = wave_sum(al[i]);
+    be[i] = wave_sum(be[i]);
+    ga[i] = wave_sum(ga[i]);
+  }
+  int rot = 0;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    double cs, sn;
+    cd em;
+    if (hestenes_params(al[i], be[i], ga[i], tiny, tol, cs, sn, em)) {
+      pair_rotate<PER>(a[ia + i], b[ib + di * i], cs, sn, em);
+      ++rot;
+    }
+  }
+  return rot;
+}
+
+struct SvdBatch {
+  const cd* rho[CTM_SVD_BATCH];
+  cd* Z[CTM_SVD_BATCH];
+  cd* W[CTM_SVD_BATCH];
+};
+
+// n <= 64 * PER and n <= 32 * C: the columns live in registers, in blocks of
+// C; wave w holds two blocks (rows lane + 64 u, u < PER), pairs its own
+// columns and passes the blocks on through LDS in round-robin order of the
+// blocks, so that every two columns meet once a sweep (the pairs inside a
+// block at the sweep's first round).  Dynamic LDS: (number of blocks) * C *
+// 64 entries.
+template <int PER, int C, int ILP, int NT>
+__global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k) {
+  extern __shared__ cd xbuf[];
+  __shared__ double red[64];
+  __shared__ double nrm[CTM_SVD_NMAX];
+  __shared__ int rank_of[CTM_SVD_NMAX];
+  __shared__ cd rowbuf[64 * PER];
+  __shared__ int cnt, pick_sh;
+  const cd* __restrict__ rho = bt.rho[blockIdx.x];
+  cd* __restrict__ Z = bt.Z[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nblk = (n + C - 1) / C, nb = nblk + (nblk & 1), nw = nb / 2;
+  const bool active = wave < nw;
+  const int me = active ? wave : 0;
+  cd x[2][C][PER];
+  int blk[2];
+  rr_pair(nb, 0, me, blk[0], blk[1]);
+  double fro = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int col = blk[h] * C + c, row = lane + 64 * u;
+        const cd v = active && col < n && row < n ? rho[(long long)row * n + col] : cd{0.0, 0.0};
+        x[h][c][u] = v;
+        fro += abs2(v);
+      }
+  fro = block_sum(fro, red);
+  // rho = L Q by Householder reflections from the right: row j of what is
+  // left, (r_j, .., r_{n-1}), becomes L[j, j] e_j with
+  // H = I - beta u u^H, u = conj(r) + conj(e) |r| e_j, e = r_j / |r_j|,
+  // beta = 1 / (|r| (|r| + |r_j|)), L[j, j] = -e |r|.  The rows of L are
+  // graded where rho's singular values spread over many orders, and the
+  // Jacobi sweeps on L's columns (left singular vectors those of rho) then
+  // end in a few rounds instead of tens.  Row sums of the update through
+  // LDS, one partial per wave.
+  for (int j = 0; j < n; ++j) {
+    if (active && lane == (j & 63))
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const int label = blk[h] * C + c;
+          if (label >= j && label < n) {
+            cd v{0.0, 0.0};
+#pragma unroll
+            for (int u = 0; u < PER; ++u)
+              if (u == (j >> 6)) v = x[h][c][u];
+            rowbuf[label] = v;
+          }
+        }
+    __syncthreads();
+    double s2 = 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int col = lane + 64 * u;
+      if (col >= j && col < n) s2 += abs2(rowbuf[col]);
+    }
+    const double nr = sqrt(wave_sum(s2));
+    if (!(nr > 0.0)) {
+      __syncthreads();  // row already zero beyond the diagonal
+      continue;
+    }
+    const cd rj = rowbuf[j];
+    const double arj = absv(rj);
+    const cd e = arj > 0.0 ? cd{rj.x / arj, rj.y / arj} : cd{1.0, 0.0};
+    const double beta = 1.0 / (nr * (nr + arj));
+    cd uc[2][C];
+    cd wp[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) wp[u] = cd{0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int label = blk[h] * C + c;
+        cd uv{0.0, 0.0};
+        if (active && label < n) {
+          if (label == j)
+            uv = conjv(e) * (arj + nr);
+          else if (label > j)
+            uv = conjv(rowbuf[label]);
+        }
+        uc[h][c] = uv;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) wp[u] += x[h][c][u] * uv;
+      }
+    if (active)
+#pragma unroll
+      for (int u = 0; u < PER; ++u) xbuf[wave * 64 * PER + lane + 64 * u] = wp[u];
+    __syncthreads();
+    if (active) {
+      cd w[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        w[u] = cd{0.0, 0.0};
+        for (int v = 0; v < nw; ++v) w[u] += xbuf[v * 64 * PER + lane + 64 * u];
+        w[u] = w[u] * beta;
+      }
+      const cd ljj = cd{-e.x * nr, -e.y * nr};
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const int label = blk[h] * C + c;
+          if (label >= j && label < n) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+              const int row = lane + 64 * u;
+              if (row == j)
+                x[h][c][u] = label == j ? ljj : cd{0.0, 0.0};
+              else
+                x[h][c][u] = x[h][c][u] - w[u] * conjv(uc[h][c]);
+            }
+          }
+        }
+    }
+  }
+  const double tiny = 1e-30 * fro, tol = 4.0 * 2.220446049250313e-16 * sqrt((double)n);
+  for (int sweep = 0; sweep < SVD_SWEEPS; ++sweep) {
+    if (tid == 0) cnt = 0;
+    __syncthreads();
+    int rot = 0;
+    for (int r = 0; r < nb - 1; ++r) {
+      if (active) {
+        if (r == 0) {
+          // pairs inside each block (circle method on its C columns: the
+          // first stays, the others move one place a round)
+#pragma unroll 1
+          for (int t = 0; t < C - 1; ++t) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) rot += svd_pairs<PER, C, C / 2>(x[h], x[h], 0, C - 1, -1, tiny, tol);
+            shift_cols<PER, C, 1>(x[0]);
+            shift_cols<PER, C, 1>(x[1]);
+          }
+        }
+        // pairs across the two blocks: column i of one with column i of the
+        // other, the second block moving one place a shift
+#pragma unroll 1
+        for (int sh = 0; sh < C; ++sh) {
+#pragma unroll
+          for (int i0 = 0; i0 < C; i0 += ILP) rot += svd_pairs<PER, C, ILP>(x[0], x[1], i0, i0, 1, tiny, tol);
+          shift_cols<PER, C, 0>(x[1]);
+        }
+      }
+      // hand the blocks on to the next round's holders
+      int nxt[2];
+      rr_pair(nb, r + 1 < nb - 1 ? r + 1 : 0, me, nxt[0], nxt[1]);
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        if (active)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int c = 0; c < C; ++c) xbuf[(blk[h] * C + c) * 64 + lane] = x[h][c][u];
+        __syncthreads();
+        if (active)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int c = 0; c < C; ++c) x[h][c][u] = xbuf[(nxt[h] * C + c) * 64 + lane];
+        __syncthreads();
+      }
+      blk[0] = nxt[0];
+      blk[1] = nxt[1];
+    }
+    if (rot && lane == 0) atomicAdd(&cnt, rot);
+    __syncthreads();
+    const int done = cnt == 0;
+    __syncthreads();
+    if (done) break;
+  }
+  // column norms, their order, the k largest columns normalised into Z
+  for (int j = tid; j < nb * C; j += blockDim.x) nrm[j] = 0.0;
+  __syncthreads();
+  if (active)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) v += abs2(x[h][c][u]);
+        v = wave_sum(v);
+        if (lane == 0) nrm[blk[h] * C + c] = sqrt(v);
+      }
+  __syncthreads();
+  const double floor_nrm = svd_rank(nrm, rank_of, n);
+  if (active)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int col = blk[h] * C + c;
+        if (col < n && rank_of[col] < k) {
+          const double nv = nrm[col];
+          const double inv = nv > floor_nrm ? 1.0 / nv : 0.0;
+#pragma unroll
+          for (int u = 0; u < PER; ++u) {
+            const int row = lane + 64 * u;
+            if (row < n) Z[(long long)row * k + rank_of[col]] = x[h][c][u] * inv;
+          }
+        }
+      }
+  __syncthreads();
+  svd_orthonormalise(Z, n, k, red, &pick_sh);
+}
+
+// Any n <= CTM_SVD_NMAX: the columns of W (scratch, n^2 entries, column j
+// contiguous) in global memory, one wave per pair of each round-robin round.
+__global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k) {
+  constexpr int PER = CTM_SVD_NMAX / 64;
+  __shared__ double red[64];
+  __shared__ double nrm[CTM_SVD_NMAX];
+  __shared__ int rank_of[CTM_SVD_NMAX];
+  __shared__ int cnt, pick_sh;
+  const cd* __restrict__ rho = bt.rho[blockIdx.x];
+  cd* __restrict__ Z = bt.Z[blockIdx.x];
+  cd* __restrict__ W = bt.W[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+  double fro = 0.0;
+  for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    const cd v = rho[e];
+    W[(long long)j * n + i] = v;
+    fro += abs2(v);
+  }
+  fro = block_sum(fro, red);
+  const double tiny = 1e-30 * fro, tol = 4.0 * 2.220446049250313e-16 * sqrt((double)n);
+  const int n2 = (n + 1) & ~1, np = n2 / 2;
+  for (int sweep = 0; sweep < SVD_SWEEPS; ++sweep) {
+    if (tid == 0) cnt = 0;
+    __syncthreads();
+    int rot = 0;
+    for (int r = 0; r < n2 - 1; ++r) {
+      for (int kp = wave; kp < np; kp += nwave) {
+        int p, q;
+        rr_pair(n2, r, kp, p, q);
+        if (q >= n) continue;
+        cd* wp = W + (long long)p * n;
+        cd* wq = W + (long long)q * n;
+        cd a[PER], b[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int i = lane + 64 * u;
+          a[u] = i < n ? wp[i] : cd{0.0, 0.0};
+          b[u] = i < n ? wq[i] : cd{0.0, 0.0};
+        }
+        double al, be;
+        cd ga;
+        pair_gram<PER>(a, b, al, be, ga);
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        double cs, sn;
+        cd em;
+        if (!hestenes_params(al, be, ga, tiny, tol, cs, sn, em)) continue;
+        pair_rotate<PER>(a, b, cs, sn, em);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int i = lane + 64 * u;
+          if (i < n) {
+            wp[i] = a[u];
+            wq[i] = b[u];
+          }
+        }
+        ++rot;
+      }
+      __syncthreads();
+    }
+    if (rot && lane == 0) atomicAdd(&cnt, rot);
+    __syncthreads();
+    const int done = cnt == 0;
+    __syncthreads();
+    if (done) break;
+  }
+  for (int j = wave; j < n; j += nwave) {
+    double v = 0.0;
+    for (int i = lane; i < n; i += 64) v += abs2(W[(long long)j * n + i]);
+    v = wave_sum(v);
+    if (lane == 0) nrm[j] = sqrt(v);
+  }
+  __syncthreads();
+  const double floor_nrm = svd_rank(nrm, rank_of, n);
+  for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
+    const int j = (int)(e / n), i = (int)(e % n);
+    const int rk = rank_of[j];
+    if (rk < k) Z[(long long)i * k + rk] = nrm[j] > floor_nrm ? W[e] * (1.0 / nrm[j]) : cd{0.0, 0.0};
+  }
+  __syncthreads();
+  svd_orthonormalise(Z, n, k, red, &pick_sh);
+}
+
+hipError_t ctm_svd_left(int count, const cd* const* rho, int n, int k, cd* const* Z, cd* const* ws, hipStream_t st) {
+  if (count < 1 || count > CTM_SVD_BATCH || n < 1 || n > CTM_SVD_NMAX || k < 1 || k > n) return hipErrorInvalidValue;
+  SvdBatch bt{};
+  for (int b = 0; b < count; ++b) {
+    bt.rho[b] = rho[b];
+    bt.Z[b] = Z[b];
+    bt.W[b] = ws[b];
+  }
+  if (n <= CTM_SVD_REG_NMAX) {
+    constexpr int PER = 2, C = 8, ILP = 4, NT = 512;
+    static bool attr = false;
+    const int nblk = (n + C - 1) / C, nb = nblk + (nblk & 1);
+    const size_t lds = (size_t)nb * C * 64 * sizeof(cd);
+    if (!attr) {
+      const hipError_t e =
+          hipFuncSetAttribute((const void*)k_ctm_svd_reg<PER, C, ILP, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(2 * (NT / 64) * C * 64 * sizeof(cd)));
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
+    hipLaunchKernelGGL((k_ctm_svd_reg<PER, C, ILP, NT>), dim3(count), dim3(NT), lds, st, bt, n, k);
+  } else {
+    hipLaunchKernelGGL(k_ctm_svd_mem, dim3(count), dim3(1024), 0, st, bt, n, k);
+  }
   return hipGetLastError();
 }
 

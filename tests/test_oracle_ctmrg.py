@@ -163,6 +163,30 @@ def test_ancilla_purification_is_onsager():
         assert abs(v - onsager_nn(2 * steps * dbeta)) < 1e-10
 
 
+def test_isometry_completion_closed_form():
+    """Beyond the numerical rank the isometry takes unit vectors in order,
+    orthogonalised against what is already there: rank 1 along
+    (e_0 + e_1)/sqrt2 gives (e_0 - e_1)/sqrt2 next (e_1 then has nothing
+    left and is skipped) and then e_2, e_3; a singular value just above the
+    floor is kept, one at the floor is not."""
+    n = 6
+    u = np.zeros(n)
+    u[0] = u[1] = 1 / np.sqrt(2)
+    U = np.linalg.qr(np.column_stack([u, np.eye(n)[:, 2:], np.eye(n)[:, 0]]))[0] * -1
+    U[:, 0] = u
+    s = np.array([2.0, 1e-13, 1e-14, 0, 0, 0])
+    Z = C.complete_isometry(U.astype(complex), s, 4)
+    want = np.column_stack([u, (np.eye(n)[:, 0] - np.eye(n)[:, 1]) / np.sqrt(2), np.eye(n)[:, 2], np.eye(n)[:, 3]])
+    assert np.abs(Z - want).max() < 1e-15
+    s2 = np.array([2.0, 2.1e-12, 0, 0, 0, 0])
+    Z2 = C.complete_isometry(U.astype(complex), s2, 3)
+    assert np.abs(Z2[:, :2] - U[:, :2]).max() == 0
+    s3 = np.array([2.0, 2e-12, 0, 0, 0, 0])
+    Z3 = C.complete_isometry(U.astype(complex), s3, 3)
+    assert np.abs(Z3[:, 1] - want[:, 1]).max() < 1e-15
+    assert np.abs(Z3.conj().T @ Z3 - np.eye(3)).max() < 1e-15
+
+
 def test_pins_catch_planted_mistakes(monkeypatch):
     """A corner turned without its transpose breaks the rotation pin (random
     square environment); the bond between the two sites of the two-site
