@@ -166,14 +166,17 @@ constexpr int SVD_SWEEPS = 40;
 // plane rotation (c, s) with t = s / c the smaller root of
 // t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 |ga|), zeroes its inner
 // product: w_p <- c w_p - s y, w_q <- s w_p + c y.  False: nothing to do.
-NTU_DEV bool hestenes_params(double al, double be, cd ga, double tiny, double tol, double& c, double& s, cd& em) {
+NTU_DEV bool hestenes_params(double al, double be, cd ga, double tiny, double tol, double& c, double& s, cd& em,
+                             double& tg) {
   const double g = absv(ga);
   if (!(g > tiny) || !(g > tol * sqrt(al * be))) return false;
   const double zeta = (be - al) / (2.0 * g);
   const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   c = 1.0 / sqrt(1.0 + t * t);
   s = c * t;
-  em = cd{ga.x / g, -ga.y / g};
+  const double ig = 1.0 / g;
+  em = cd{ga.x * ig, -ga.y * ig};
+  tg = t * g;  // |w_p|^2 falls and |w_q|^2 rises by t |ga|
   return true;
 }
 
@@ -236,6 +239,48 @@ NTU_DEV void svd_orthonormalise(cd* Z, int n, int k, double* red, int* pick_sh) 
   }
 }
 
+// The same Gram-Schmidt by one wave on Z held in LDS (column c at
+// zs + c * ld, row i at i; n <= 64 PER): no barriers, the column being
+// orthogonalised kept in registers.
+template <int PER> NTU_DEV void svd_orthonormalise_wave(cd* zs, int ld, int n, int k) {
+  const int lane = threadIdx.x & 63;
+  int next_unit = 0;
+  for (int col = 0; col < k; ++col) {
+    cd zc[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) zc[u] = lane + 64 * u < n ? zs[col * ld + lane + 64 * u] : cd{0.0, 0.0};
+    for (int attempt = 0; attempt <= n; ++attempt) {
+      for (int pass = 0; pass < 2; ++pass)
+        for (int b = 0; b < col; ++b) {
+          cd dot{0.0, 0.0};
+#pragma unroll
+          for (int u = 0; u < PER; ++u)
+            if (lane + 64 * u < n) dot += cmul(zs[b * ld + lane + 64 * u], zc[u]);
+          dot = wave_sum(dot);
+#pragma unroll
+          for (int u = 0; u < PER; ++u)
+            if (lane + 64 * u < n) zc[u] = zc[u] - dot * zs[b * ld + lane + 64 * u];
+        }
+      double nn = 0.0;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) nn += abs2(zc[u]);
+      nn = sqrt(wave_sum(nn));
+      if (nn > 0.5) {
+        const double inv = 1.0 / nn;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) zc[u] = zc[u] * inv;
+        break;
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) zc[u] = cd{lane + 64 * u == next_unit ? 1.0 : 0.0, 0.0};
+      ++next_unit;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+      if (lane + 64 * u < n) zs[col * ld + lane + 64 * u] = zc[u];
+  }
+}
+
 // rank_of[j] = the place of column j when the norms nrm[0..n) are sorted
 // descending (ties by index).  Returns the floor below which a column counts
 // as beyond the numerical rank: CTM_RANK_EPS times the largest norm.  Such
@@ -254,8 +299,9 @@ NTU_DEV double svd_rank(const double* nrm, int* rank_of, int n) {
   return CTM_RANK_EPS * mx;
 }
 
-// y[first..C) moved one place down, y[first] to the end
-template <int PER, int C, int FIRST> NTU_DEV void shift_cols(cd (&y)[C][PER]) {
+// y[first..C) moved one place down, y[first] to the end (with the squared
+// norms ny kept beside them)
+template <int PER, int C, int FIRST> NTU_DEV void shift_cols(cd (&y)[C][PER], double (&ny)[C]) {
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const cd t = y[FIRST][u];
@@ -263,33 +309,53 @@ template <int PER, int C, int FIRST> NTU_DEV void shift_cols(cd (&y)[C][PER]) {
     for (int c = FIRST; c < C - 1; ++c) y[c][u] = y[c + 1][u];
     y[C - 1][u] = t;
   }
+  const double t = ny[FIRST];
+#pragma unroll
+  for (int c = FIRST; c < C - 1; ++c) ny[c] = ny[c + 1];
+  ny[C - 1] = t;
 }
 
-// NP disjoint pairs (a[ia + i], b[ib + di i]), i < NP, Gram entries summed
-// over the wave side by side, then rotated; returns the rotations made
+// NP disjoint pairs (a[ia + i], b[ib + di i]), i < NP: inner products summed
+// over the wave side by side, then rotated, the squared norms na, nb moved
+// along; returns the rotations made
 template <int PER, int C, int NP>
-NTU_DEV int svd_pairs(cd (&a)[C][PER], cd (&b)[C][PER], int ia, int ib, int di, double tiny, double tol) {
-  double al[NP], be[NP];
+NTU_DEV int svd_pairs(cd (&a)[C][PER], cd (&b)[C][PER], double (&na)[C], double (&nb)[C], int ia, int ib, int di,
+                      double tiny, double tol) {
   cd ga[NP];
 #pragma unroll
-  for (int i = 0; i < NP; ++i) pair_gram<PER>(a[ia + i], b[ib + di * i], al[i], be[i], ga[i]);
-#pragma unroll
   for (int i = 0; i < NP; ++i) {
-    al[i] = wave_sum(al[i]);
-    be[i] = wave_sum(be[i]);
-    ga[i] = wave_sum(ga[i]);
+    ga[i] = cd{0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < PER; ++u) ga[i] += cmul(a[ia + i][u], b[ib + di * i][u]);
   }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) ga[i] = wave_sum(ga[i]);
   int rot = 0;
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
-    double cs, sn;
+    double cs, sn, tg;
     cd em;
-    if (hestenes_params(al[i], be[i], ga[i], tiny, tol, cs, sn, em)) {
+    if (hestenes_params(na[ia + i], nb[ib + di * i], ga[i], tiny, tol, cs, sn, em, tg)) {
       pair_rotate<PER>(a[ia + i], b[ib + di * i], cs, sn, em);
+      na[ia + i] = fmax(na[ia + i] - tg, 0.0);  // recomputed exactly each round
+      nb[ib + di * i] += tg;
       ++rot;
     }
   }
   return rot;
+}
+
+// squared norms of the columns a wave holds (exact, once a round)
+template <int PER, int C> NTU_DEV void col_norms(const cd (&y)[C][PER], double (&ny)[C]) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) v += abs2(y[c][u]);
+    ny[c] = v;
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) ny[c] = wave_sum(ny[c]);
 }
 
 struct SvdBatch {
@@ -305,12 +371,12 @@ struct SvdBatch {
 // block at the sweep's first round).  Dynamic LDS: (number of blocks) * C *
 // 64 entries.
 template <int PER, int C, int ILP, int NT>
-__global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k) {
+__global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k, int zs_cap) {
   extern __shared__ cd xbuf[];
   __shared__ double red[64];
   __shared__ double nrm[CTM_SVD_NMAX];
   __shared__ int rank_of[CTM_SVD_NMAX];
-  __shared__ cd rowbuf[64 * PER];
+  __shared__ cd rowbuf[2 * 64 * PER];
   __shared__ int cnt, pick_sh;
   const cd* __restrict__ rho = bt.rho[blockIdx.x];
   cd* __restrict__ Z = bt.Z[blockIdx.x];
@@ -343,6 +409,9 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k) {
   // end in a few rounds instead of tens.  Row sums of the update through
   // LDS, one partial per wave.
   for (int j = 0; j < n; ++j) {
+    // row j, double-buffered by step so that a wave still updating with
+    // step j's row never sees step j + 1's
+    cd* const rb = rowbuf + (j & 1) * 64 * PER;
     if (active && lane == (j & 63))
 #pragma unroll
       for (int h = 0; h < 2; ++h)
@@ -354,7 +423,7 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k) {
 #pragma unroll
             for (int u = 0; u < PER; ++u)
               if (u == (j >> 6)) v = x[h][c][u];
-            rowbuf[label] = v;
+            rb[label] = v;
           }
         }
     __syncthreads();
@@ -362,37 +431,31 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int col = lane + 64 * u;
-      if (col >= j && col < n) s2 += abs2(rowbuf[col]);
+      if (col >= j && col < n) s2 += abs2(rb[col]);
     }
     const double nr = sqrt(wave_sum(s2));
-    if (!(nr > 0.0)) {
-      __syncthreads();  // row already zero beyond the diagonal
-      continue;
-    }
-    const cd rj = rowbuf[j];
+    if (!(nr > 0.0)) continue;  // row already zero beyond the diagonal
+    const cd rj = rb[j];
     const double arj = absv(rj);
     const cd e = arj > 0.0 ? cd{rj.x / arj, rj.y / arj} : cd{1.0, 0.0};
     const double beta = 1.0 / (nr * (nr + arj));
-    cd uc[2][C];
+    const cd uj = conjv(e) * (arj + nr);
+    // u_c: column c's entry of the reflector (conj of the row beyond j)
+    auto ucol = [&](int label) -> cd {
+      return label == j ? uj : (label > j && label < n ? conjv(rb[label]) : cd{0.0, 0.0});
+    };
     cd wp[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) wp[u] = cd{0.0, 0.0};
+    if (active)
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const int label = blk[h] * C + c;
-        cd uv{0.0, 0.0};
-        if (active && label < n) {
-          if (label == j)
-            uv = conjv(e) * (arj + nr);
-          else if (label > j)
-            uv = conjv(rowbuf[label]);
+        for (int c = 0; c < C; ++c) {
+          const cd uv = ucol(blk[h] * C + c);
+#pragma unroll
+          for (int u = 0; u < PER; ++u) wp[u] += x[h][c][u] * uv;
         }
-        uc[h][c] = uv;
-#pragma unroll
-        for (int u = 0; u < PER; ++u) wp[u] += x[h][c][u] * uv;
-      }
     if (active)
 #pragma unroll
       for (int u = 0; u < PER; ++u) xbuf[wave * 64 * PER + lane + 64 * u] = wp[u];
@@ -412,17 +475,20 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k) {
         for (int c = 0; c < C; ++c) {
           const int label = blk[h] * C + c;
           if (label >= j && label < n) {
+            const cd ucc = conjv(ucol(label));
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
               const int row = lane + 64 * u;
               if (row == j)
                 x[h][c][u] = label == j ? ljj : cd{0.0, 0.0};
               else
-                x[h][c][u] = x[h][c][u] - w[u] * conjv(uc[h][c]);
+                x[h][c][u] = x[h][c][u] - w[u] * ucc;
             }
           }
         }
     }
+    // the partial sums are next written after the next step's barrier, which
+    // every wave reaches only once it has read them
   }
   const double tiny = 1e-30 * fro, tol = 4.0 * 2.220446049250313e-16 * sqrt((double)n);
   for (int sweep = 0; sweep < SVD_SWEEPS; ++sweep) {
@@ -431,15 +497,19 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k) {
     int rot = 0;
     for (int r = 0; r < nb - 1; ++r) {
       if (active) {
+        double nq[2][C];
+        col_norms<PER, C>(x[0], nq[0]);
+        col_norms<PER, C>(x[1], nq[1]);
         if (r == 0) {
           // pairs inside each block (circle method on its C columns: the
           // first stays, the others move one place a round)
 #pragma unroll 1
           for (int t = 0; t < C - 1; ++t) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) rot += svd_pairs<PER, C, C / 2>(x[h], x[h], 0, C - 1, -1, tiny, tol);
-            shift_cols<PER, C, 1>(x[0]);
-            shift_cols<PER, C, 1>(x[1]);
+            for (int h = 0; h < 2; ++h)
+              rot += svd_pairs<PER, C, C / 2>(x[h], x[h], nq[h], nq[h], 0, C - 1, -1, tiny, tol);
+            shift_cols<PER, C, 1>(x[0], nq[0]);
+            shift_cols<PER, C, 1>(x[1], nq[1]);
           }
         }
         // pairs across the two blocks: column i of one with column i of the
@@ -447,8 +517,9 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k) {
 #pragma unroll 1
         for (int sh = 0; sh < C; ++sh) {
 #pragma unroll
-          for (int i0 = 0; i0 < C; i0 += ILP) rot += svd_pairs<PER, C, ILP>(x[0], x[1], i0, i0, 1, tiny, tol);
-          shift_cols<PER, C, 0>(x[1]);
+          for (int i0 = 0; i0 < C; i0 += ILP)
+            rot += svd_pairs<PER, C, ILP>(x[0], x[1], nq[0], nq[1], i0, i0, 1, tiny, tol);
+          shift_cols<PER, C, 0>(x[1], nq[1]);
         }
       }
       // hand the blocks on to the next round's holders
@@ -494,6 +565,10 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k) {
       }
   __syncthreads();
   const double floor_nrm = svd_rank(nrm, rank_of, n);
+  // Z staged in LDS when it fits (column c at zs + c * 64 PER), else in
+  // global memory
+  constexpr int LD = 64 * PER;
+  const bool in_lds = k * LD <= zs_cap;
   if (active)
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -503,15 +578,28 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k) {
         if (col < n && rank_of[col] < k) {
           const double nv = nrm[col];
           const double inv = nv > floor_nrm ? 1.0 / nv : 0.0;
+          const int rk = rank_of[col];
 #pragma unroll
           for (int u = 0; u < PER; ++u) {
             const int row = lane + 64 * u;
-            if (row < n) Z[(long long)row * k + rank_of[col]] = x[h][c][u] * inv;
+            if (in_lds)
+              xbuf[rk * LD + row] = x[h][c][u] * inv;
+            else if (row < n)
+              Z[(long long)row * k + rk] = x[h][c][u] * inv;
           }
         }
       }
   __syncthreads();
-  svd_orthonormalise(Z, n, k, red, &pick_sh);
+  if (in_lds) {
+    if (wave == 0) svd_orthonormalise_wave<PER>(xbuf, LD, n, k);
+    __syncthreads();
+    for (int e = tid; e < n * k; e += blockDim.x) {
+      const int i = e / k, c = e % k;
+      Z[(long long)i * k + c] = xbuf[c * LD + i];
+    }
+  } else {
+    svd_orthonormalise(Z, n, k, red, &pick_sh);
+  }
 }
 
 // Any n <= CTM_SVD_NMAX: the columns of W (scratch, n^2 entries, column j
@@ -560,9 +648,9 @@ __global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k)
         al = wave_sum(al);
         be = wave_sum(be);
         ga = wave_sum(ga);
-        double cs, sn;
+        double cs, sn, tg;
         cd em;
-        if (!hestenes_params(al, be, ga, tiny, tol, cs, sn, em)) continue;
+        if (!hestenes_params(al, be, ga, tiny, tol, cs, sn, em, tg)) continue;
         pair_rotate<PER>(a, b, cs, sn, em);
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
@@ -599,6 +687,32 @@ __global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k)
   svd_orthonormalise(Z, n, k, red, &pick_sh);
 }
 
+// one workgroup of NT threads per matrix: n <= 2 C (NT / 64) (two blocks
+// of C columns per wave) and n <= 64 PER (PER rows per lane)
+template <int PER, int C, int ILP, int NT>
+static hipError_t launch_svd_reg(const SvdBatch& bt, int count, int n, int k, hipStream_t st) {
+  static_assert(C % 2 == 0 && C % ILP == 0, "block shape");
+  constexpr int NW = NT / 64;
+  constexpr size_t LDS_CAP = (size_t)(2 * NW * C * 64 > NW * 64 * PER ? 2 * NW * C * 64 : NW * 64 * PER) * sizeof(cd);
+  static_assert(LDS_CAP <= 144 * 1024, "LDS");
+  if (n > 2 * C * NW || n > 64 * PER) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_ctm_svd_reg<PER, C, ILP, NT>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_CAP);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int nblk = (n + C - 1) / C, nb = nblk + (nblk & 1);
+  const size_t ex = (size_t)nb * C * 64, part = (size_t)NW * 64 * PER, zs = (size_t)k * 64 * PER;
+  const size_t cap = LDS_CAP / sizeof(cd);
+  size_t ent = ex > part ? ex : part;
+  if (zs <= cap && zs > ent) ent = zs;  // Z staged in LDS when it fits
+  hipLaunchKernelGGL((k_ctm_svd_reg<PER, C, ILP, NT>), dim3(count), dim3(NT), ent * sizeof(cd), st, bt, n, k,
+                     (int)ent);
+  return hipGetLastError();
+}
+
 hipError_t ctm_svd_left(int count, const cd* const* rho, int n, int k, cd* const* Z, cd* const* ws, hipStream_t st) {
   if (count < 1 || count > CTM_SVD_BATCH || n < 1 || n > CTM_SVD_NMAX || k < 1 || k > n) return hipErrorInvalidValue;
   SvdBatch bt{};
@@ -607,20 +721,9 @@ hipError_t ctm_svd_left(int count, const cd* const* rho, int n, int k, cd* const
     bt.Z[b] = Z[b];
     bt.W[b] = ws[b];
   }
-  if (n <= CTM_SVD_REG_NMAX) {
-    constexpr int PER = 2, C = 8, ILP = 4, NT = 512;
-    static bool attr = false;
-    const int nblk = (n + C - 1) / C, nb = nblk + (nblk & 1);
-    const size_t lds = (size_t)nb * C * 64 * sizeof(cd);
-    if (!attr) {
-      const hipError_t e =
-          hipFuncSetAttribute((const void*)k_ctm_svd_reg<PER, C, ILP, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(2 * (NT / 64) * C * 64 * sizeof(cd)));
-      if (e != hipSuccess) return e;
-      attr = true;
-    }
-    hipLaunchKernelGGL((k_ctm_svd_reg<PER, C, ILP, NT>), dim3(count), dim3(NT), lds, st, bt, n, k);
-  } else {
+  if (n <= 64) return launch_svd_reg<1, 2, 2, 1024>(bt, count, n, k, st);
+  if (n <= CTM_SVD_REG_NMAX) return launch_svd_reg<2, 8, 4, 512>(bt, count, n, k, st);
+  {
     hipLaunchKernelGGL(k_ctm_svd_mem, dim3(count), dim3(1024), 0, st, bt, n, k);
   }
   return hipGetLastError();
