@@ -609,6 +609,8 @@ __global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k)
   __shared__ double red[64];
   __shared__ double nrm[CTM_SVD_NMAX];
   __shared__ int rank_of[CTM_SVD_NMAX];
+  __shared__ cd rowbuf[2][CTM_SVD_NMAX];
+  __shared__ cd part[4][CTM_SVD_NMAX];
   __shared__ int cnt, pick_sh;
   const cd* __restrict__ rho = bt.rho[blockIdx.x];
   cd* __restrict__ Z = bt.Z[blockIdx.x];
@@ -622,6 +624,40 @@ __global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k)
     fro += abs2(v);
   }
   fro = block_sum(fro, red);
+  // the LQ factorisation of k_ctm_svd_reg on the columns in global memory:
+  // row i = j + (tid % 256) of what is left (rows above j hold zeros beyond
+  // the diagonal), columns j + g, j + g + 4, .. for g = tid / 256
+  const int ri = tid & (CTM_SVD_NMAX - 1), g4 = tid / CTM_SVD_NMAX;
+  for (int j = 0; j < n; ++j) {
+    cd* const rb = rowbuf[j & 1];
+    for (int c = j + tid; c < n; c += blockDim.x) rb[c] = W[(long long)c * n + j];
+    __syncthreads();
+    double s2 = 0.0;
+    for (int c = j + lane; c < n; c += 64) s2 += abs2(rb[c]);
+    const double nr = sqrt(wave_sum(s2));
+    if (!(nr > 0.0)) continue;
+    const cd rj = rb[j];
+    const double arj = absv(rj);
+    const cd e = arj > 0.0 ? cd{rj.x / arj, rj.y / arj} : cd{1.0, 0.0};
+    const double beta = 1.0 / (nr * (nr + arj));
+    const cd uj = conjv(e) * (arj + nr);
+    auto ucol = [&](int c) -> cd { return c == j ? uj : conjv(rb[c]); };  // c >= j
+    const int i = j + ri;
+    cd wp{0.0, 0.0};
+    if (i < n)
+      for (int c = j + g4; c < n; c += 4) wp += W[(long long)c * n + i] * ucol(c);
+    part[g4][ri] = wp;
+    __syncthreads();
+    if (i < n) {
+      const cd w = (part[0][ri] + part[1][ri] + part[2][ri] + part[3][ri]) * beta;
+      const cd ljj = cd{-e.x * nr, -e.y * nr};
+      for (int c = j + g4; c < n; c += 4) {
+        cd* const at = W + (long long)c * n + i;
+        *at = i == j ? (c == j ? ljj : cd{0.0, 0.0}) : *at - w * conjv(ucol(c));
+      }
+    }
+    __syncthreads();  // the next row is read from what this step wrote
+  }
   const double tiny = 1e-30 * fro, tol = 4.0 * 2.220446049250313e-16 * sqrt((double)n);
   const int n2 = (n + 1) & ~1, np = n2 / 2;
   for (int sweep = 0; sweep < SVD_SWEEPS; ++sweep) {
