@@ -428,6 +428,54 @@ ntu_status ntu_ctm_expect(ntu_ctm* ctm, const ntu_tensor* A, const ntu_tensor* B
                           const ntu_tensor* ops2, ntu_tensor* out);
 
 /*
+ * A time-evolution run measured with CTMRG (Sec. III: the quench from a
+ * polarised state, observables from the CTM environment, each run ended once
+ * the energy per site has moved away from its initial value by more than a
+ * tolerance, 0.01 there).  Measurement 0 is taken before the first step,
+ * then one after every measure_every Trotter steps.  A measurement is
+ * ntu_ctm_run (ctm_iters iterations from the identity boundary, or from the
+ * previous measurement's environment when ctm_continue) and ntu_ctm_expect
+ * with ops1 and the bond operator hb; its energy per site is half the real
+ * part of the sum of <hb> over the four bonds H1, H2, V1, V2 (each site has
+ * two of them; hb carries a quarter of each one-site field on each of its
+ * sites).  The run ends after n_steps steps, or after the first measurement
+ * whose energy differs from measurement 0's by more than energy_tol (when
+ * energy_tol > 0).
+ * ctx, ctm: a context and a CTMRG object (ntu_ctm_create with the state's p
+ *   and D) on one device.  Every launch goes to the context's stream (the
+ *   CTMRG object's stream is set to it for the run and restored after).  The
+ *   call waits for that stream at every measurement (the stop decision reads
+ *   the energy on the host), so it cannot be captured into a graph.
+ * A, B: (1, p, D, D, D, D) NTU_C128 or NTU_F64, evolved in place (one state;
+ *   complex64 storage returns NTU_ERR_UNSUPPORTED before anything runs).
+ * gate_factors, step: as for ntu_trotter_step with batch 1 (any sweep order,
+ *   e.g. the second-order sweep of half-step gates).
+ * ops1: (n1, p, p) one-site operators; hb: (n2, 2, p, p) the bond operator
+ *   as operator-Schmidt terms, as ntu_ctm_expect takes them.
+ * history: (max_meas, 2 n1 + 4) NTU_C128 on the device: row m is measurement
+ *   m's ntu_ctm_expect output ([<O_k>_A, <O_k>_B] per operator, then <hb>
+ *   on H1, H2, V1, V2); max_meas >= n_steps / measure_every + 1.
+ * energy: host array of max_meas doubles (may be NULL): the energies.
+ * n_meas, steps_done: host; the measurements written and the steps taken.
+ * Errors: arguments are checked before anything runs (NTU_ERR_ARG,
+ *   NTU_ERR_SHAPE, NTU_ERR_DTYPE, NTU_ERR_UNSUPPORTED).  An error of a
+ *   Trotter step is reported by ntu_last_error(ctx), every other by
+ *   ntu_ctm_last_error(ctm); A, B then hold the steps taken (steps_done).
+ */
+typedef struct ntu_evolve_opts {
+  int n_steps;        /* Trotter steps at most (>= 0)                          */
+  int measure_every;  /* steps between measurements (>= 1)                     */
+  int ctm_iters;      /* CTMRG iterations per measurement (>= 1)               */
+  int ctm_continue;   /* 0: each measurement from the identity boundary; 1: from
+                         the previous measurement's environment               */
+  double energy_tol;  /* stop tolerance on |e - e_0| (<= 0: run every step)   */
+} ntu_evolve_opts;
+
+ntu_status ntu_evolve(ntu_ctx* ctx, ntu_ctm* ctm, ntu_tensor* A, ntu_tensor* B, const ntu_tensor* gate_factors,
+                      const ntu_step_opts* step, const ntu_evolve_opts* ev, const ntu_tensor* ops1,
+                      const ntu_tensor* hb, ntu_tensor* history, double* energy, int* n_meas, int* steps_done);
+
+/*
  * Metric repair without allocation, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc): the same operation and kernels as ntu_metric_fix, with

@@ -53,6 +53,9 @@ struct ntu_ctx {
   std::vector<char> graph_key;
 };
 
+// the context's stream, for the evolution run of api_ctm.hip
+hipStream_t ntu_internal_ctx_stream(const ntu_ctx* c) { return c->stream; }
+
 namespace {
 
 thread_local std::string g_create_err;

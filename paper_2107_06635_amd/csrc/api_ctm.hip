@@ -16,6 +16,7 @@
 // vectors of rho = H_u H_d^T, the half-system density matrix of the 2 x 2
 // block around the cut.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -662,3 +663,87 @@ ntu_status ntu_ctm_expect(ntu_ctm* c, const ntu_tensor* A, const ntu_tensor* B, 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Evolution run with CTMRG measurements (ntu_evolve)
+// ---------------------------------------------------------------------------
+hipStream_t ntu_internal_ctx_stream(const ntu_ctx* c);
+
+namespace {
+
+// item 0 of a batched (1, ...) descriptor as an unbatched one
+ntu_tensor drop_batch(const ntu_tensor& t) {
+  ntu_tensor r = t;
+  r.ndim = t.ndim - 1;
+  for (int i = 0; i + 1 < t.ndim; ++i) {
+    r.shape[i] = t.shape[i + 1];
+    r.stride[i] = t.stride[i + 1];
+  }
+  return r;
+}
+
+}  // namespace
+
+extern "C" ntu_status ntu_evolve(ntu_ctx* ctx, ntu_ctm* c, ntu_tensor* A, ntu_tensor* B,
+                                 const ntu_tensor* gate_factors, const ntu_step_opts* step,
+                                 const ntu_evolve_opts* ev, const ntu_tensor* ops1, const ntu_tensor* hb,
+                                 ntu_tensor* history, double* energy, int* n_meas, int* steps_done) {
+  if (!c) return cfail(nullptr, NTU_ERR_ARG, "ctm is NULL");
+  if (!ctx || !A || !B || !gate_factors || !step || !ev || !ops1 || !hb || !history || !n_meas || !steps_done)
+    return cfail(c, NTU_ERR_ARG, "ntu_evolve: NULL argument");
+  *n_meas = 0;
+  *steps_done = 0;
+  if (ev->n_steps < 0 || ev->measure_every < 1 || ev->ctm_iters < 1)
+    return cfail(c, NTU_ERR_ARG, "ntu_evolve: n_steps >= 0, measure_every >= 1, ctm_iters >= 1");
+  if (A->dtype == NTU_C64 || B->dtype == NTU_C64)
+    return cfail(c, NTU_ERR_UNSUPPORTED, "ntu_evolve: complex64 storage (CTMRG takes complex128 or real tensors)");
+  if (A->ndim != 6 || B->ndim != 6 || A->shape[0] != 1 || B->shape[0] != 1)
+    return cfail(c, NTU_ERR_SHAPE, "ntu_evolve: A, B must be (1, p, D, D, D, D)");
+  if (ops1->ndim != 3) return cfail(c, NTU_ERR_SHAPE, "ntu_evolve: ops1 must be (n1, p, p)");
+  const long long width = 2 * ops1->shape[0] + 4;
+  const long long need = ev->n_steps / ev->measure_every + 1;
+  if (history->dtype != NTU_C128) return cfail(c, NTU_ERR_DTYPE, "ntu_evolve: history must be NTU_C128");
+  if (history->ndim != 2 || history->shape[1] != width || history->shape[0] < need || history->stride[1] != 1 ||
+      history->stride[0] != width || !history->data)
+    return cfail(c, NTU_ERR_SHAPE, "ntu_evolve: history must be dense (max_meas >= " + std::to_string(need) +
+                                       ", " + std::to_string(width) + ")");
+  const ntu_tensor A0 = drop_batch(*A), B0 = drop_batch(*B);
+  NTU_CTM_CHECK(check_arg(c, &A0, "A[0]", {c->p, c->D, c->D, c->D, c->D}, true));
+  NTU_CTM_CHECK(check_arg(c, &B0, "B[0]", {c->p, c->D, c->D, c->D, c->D}, true));
+  const hipStream_t st = ntu_internal_ctx_stream(ctx);
+  const hipStream_t saved = c->stream;
+  c->stream = st;
+  int m = 0;
+  auto measure = [&](bool reset, double& e) -> ntu_status {
+    NTU_CTM_CHECK(ntu_ctm_run(c, &A0, &B0, ev->ctm_iters, reset ? 1 : 0));
+    ntu_tensor row = *history;
+    row.ndim = 1;
+    row.shape[0] = width;
+    row.stride[0] = 1;
+    row.data = (cd*)history->data + (long long)m * width;
+    NTU_CTM_CHECK(ntu_ctm_expect(c, &A0, &B0, ops1, hb, &row));
+    cd v[4];
+    Dev g(c->device);
+    hipError_t he = hipMemcpyAsync(v, (cd*)row.data + (width - 4), sizeof v, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return cfail(c, NTU_ERR_HIP, std::string("ntu_evolve: ") + hipGetErrorString(he));
+    e = 0.5 * (v[0].x + v[1].x + v[2].x + v[3].x);
+    if (energy) energy[m] = e;
+    *n_meas = ++m;
+    return NTU_OK;
+  };
+  double e0 = 0.0;
+  ntu_status s = measure(true, e0);
+  for (int k = 1; s == NTU_OK && k <= ev->n_steps; ++k) {
+    s = ntu_trotter_step(ctx, 1, A, B, gate_factors, step, nullptr);
+    if (s != NTU_OK) break;
+    *steps_done = k;
+    if (k % ev->measure_every == 0) {
+      double e = 0.0;
+      s = measure(!ev->ctm_continue, e);
+      if (s == NTU_OK && ev->energy_tol > 0.0 && std::fabs(e - e0) > ev->energy_tol) break;
+    }
+  }
+  c->stream = saved;
+  return s;
+}

@@ -141,6 +141,15 @@ def plus_product_state(D: int) -> tuple[np.ndarray, np.ndarray]:
 # Workloads.  Each returns plain arrays; sizes follow the benchmark configs.
 # --------------------------------------------------------------------------
 
+def polarised_x(D: int, dtype=np.complex128):
+    """The fully polarised state along x of the quench (Sec. III): A = B =
+    |+> on every site, bond dimension 1 padded with zeros to D; legs (p, t,
+    l, b, r)."""
+    A = np.zeros((2, D, D, D, D), dtype=dtype)
+    A[:, 0, 0, 0, 0] = 1.0 / np.sqrt(2.0)
+    return A, A.copy()
+
+
 def workload_single_bond(seed: int = 1, D: int = 2, hx: float = H_CRIT, dt: float = 0.01):
     """One complex bond update of a random state (configuration 1 at ``D = 2``)."""
     rng = np.random.default_rng(seed)

@@ -35,6 +35,7 @@ EXPORTED = (
     "ntu_tune_env", "ntu_set_env_ksplit", "ntu_get_env_ksplit", "ntu_tune_save", "ntu_tune_load",
     "ntu_metric_fix_noalloc", "ntu_superop_gate",
     "ntu_ctm_create", "ntu_ctm_destroy", "ntu_ctm_set_stream", "ntu_ctm_last_error", "ntu_ctm_run", "ntu_ctm_expect",
+    "ntu_evolve",
 )
 
 
@@ -47,6 +48,11 @@ class FitOpts(ctypes.Structure):
 class StepOpts(ctypes.Structure):
     _fields_ = [("n_bonds", ctypes.c_int), ("order", ctypes.c_int * 8), ("precision", ctypes.c_int),
                 ("fix_mode", ctypes.c_int), ("fit", FitOpts), ("scheme", ctypes.c_int), ("graph", ctypes.c_int)]
+
+
+class EvolveOpts(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int), ("measure_every", ctypes.c_int), ("ctm_iters", ctypes.c_int),
+                ("ctm_continue", ctypes.c_int), ("energy_tol", ctypes.c_double)]
 
 
 MAX_DIMS = 8
@@ -109,6 +115,8 @@ def load():
     L.ntu_ctm_last_error.restype = ctypes.c_char_p
     L.ntu_ctm_run.argtypes = [vp, tp, tp, i32, i32]
     L.ntu_ctm_expect.argtypes = [vp, tp, tp, tp, tp, tp]
+    L.ntu_evolve.argtypes = [vp, vp, tp, tp, tp, ctypes.POINTER(StepOpts), ctypes.POINTER(EvolveOpts), tp, tp, tp,
+                             dp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     for name in EXPORTED:
         if name not in ("ntu_last_error", "ntu_workspace_bytes", "ntu_version", "ntu_fit_opts_default",
                         "ntu_step_opts_default", "ntu_profile_kind_name", "ntu_ctm_last_error"):
@@ -430,3 +438,25 @@ class CTM:
         self._check(self.L.ntu_ctm_expect(self.h, _ref(A), _ref(B), _ref(ops1), _ref(ops2), _ref(out)),
                     "ntu_ctm_expect")
         return out
+
+
+def ntu_evolve(ctx: Context, ctm: CTM, A, B, gate_factors, step: StepOpts, n_steps, measure_every, ctm_iters, ops1,
+               hb_terms, energy_tol=0.01, ctm_continue=False):
+    """An evolution run measured with CTMRG, in place on A, B (1, p, D, D,
+    D, D); ops1 (n1, p, p) and hb_terms (n2, 2, p, p) complex128 device
+    tensors.  Returns (history (n_meas, 2 n1 + 4) complex128 device tensor,
+    energies (n_meas,) numpy, steps taken)."""
+    import numpy as np
+    max_meas = n_steps // measure_every + 1
+    hist = torch.zeros(max_meas, 2 * ops1.shape[0] + 4, dtype=torch.complex128, device=A.device)
+    energy = (ctypes.c_double * max_meas)()
+    n_meas, steps = ctypes.c_int(0), ctypes.c_int(0)
+    ev = EvolveOpts(n_steps, measure_every, ctm_iters, int(ctm_continue), energy_tol)
+    ctx.bind_stream()
+    st = ctx.L.ntu_evolve(ctx.h, ctm.h, _ref(A), _ref(B), _ref(gate_factors), ctypes.byref(step), ctypes.byref(ev),
+                          _ref(ops1), _ref(hb_terms), _ref(hist), energy, ctypes.byref(n_meas), ctypes.byref(steps))
+    if st != NTU_OK:
+        raise RuntimeError(f"ntu_evolve: status {st}: {ctm.L.ntu_ctm_last_error(ctm.h).decode()} / "
+                           f"{ctx.L.ntu_last_error(ctx.h).decode()}")
+    k = n_meas.value
+    return hist[:k], np.array(energy[:k]), steps.value

@@ -61,7 +61,7 @@ def test_host_only_defaults(lib):
 
 def test_struct_layouts_match_header(tmp_path):
     """The binding's ctypes structures have the C layout of ntu_tensor,
-    ntu_fit_opts and ntu_step_opts (offsets printed by a program compiled
+    ntu_fit_opts, ntu_step_opts and ntu_evolve_opts (offsets printed by a program compiled
     against the header with the host C compiler)."""
     import shutil
     import subprocess
@@ -72,7 +72,9 @@ def test_struct_layouts_match_header(tmp_path):
     fields = {"ntu_tensor": (ntu.Tensor, ["data", "dtype", "ndim", "shape", "stride"]),
               "ntu_fit_opts": (ntu.FitOpts, ["n_iter", "early_stop", "conv_tol", "kappa", "n_tol", "tol", "tie"]),
               "ntu_step_opts": (ntu.StepOpts, ["n_bonds", "order", "precision", "fix_mode", "fit", "scheme",
-                                               "graph"])}
+                                               "graph"]),
+              "ntu_evolve_opts": (ntu.EvolveOpts, ["n_steps", "measure_every", "ctm_iters", "ctm_continue",
+                                                   "energy_tol"])}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "ntu.h"', "int main(void) {"]
     for st, (_, names) in fields.items():
         src.append(f'  printf("{st} size %zu\\n", sizeof({st}));')
