@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batched", choices=["batched", "thermal", "large", "hermitian", "ctmrg"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "thermal", "large", "hermitian", "ctmrg", "quench"])
     ap.add_argument("--precision", default=None, choices=["bf16x3", "bf16x6", "fp16x3", "f64"],
                     help="environment precision (default: fp16x3 for the batched workload; bf16x6 for the "
                          "others, whose real or D > 8 metrics take the tiled path FP16x3 does not cover)")
@@ -85,7 +85,8 @@ def parse():
                     help="GPU_MAX_HW_QUEUES for this process (hardware queues the streams are spread over)")
     ap.add_argument("--aux", default="own", choices=["own", "shared"],
                     help="side stream of each bucket's Trotter step: the context's own, or one shared by all")
-    ap.add_argument("--ctm-D", type=int, default=3, help="bond dimension of the CTMRG workload (chi = 4 D)")
+    ap.add_argument("--ctm-D", type=int, default=3,
+                    help="bond dimension of the CTMRG and quench workloads (chi = 4 D)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (20 times) and print its "
                          "rate: the reference kernel for scaling HBM byte counters")
@@ -642,6 +643,94 @@ def main_ctmrg(args, ntu, torch, np, dev, inputs):
     print(json.dumps(result), flush=True)
 
 
+def main_quench(args, ntu, torch, np, dev, inputs):
+    """The quench run of Sec. III through ntu_evolve: from |+> at h_x = h_c,
+    second-order sweeps of half-step gates at dt = 0.01 (the paper's step),
+    FP64, a CTMRG measurement (chi = 4 D, 15 iterations continued from the
+    previous environment) every 10 steps and the 0.01 energy stop; K steps
+    timed (default 40) after W untimed ones."""
+    D = args.ctm_D
+    chi = 4 * D
+    K = args.steps if args.steps_given else 40
+    W = args.warmup
+    dt, hx, every, iters = 0.01, inputs.H_CRIT, 10, 15
+    order = ["H1", "H2", "V1", "V2", "V2", "V1", "H2", "H1"]
+    codes = dict(H1=ntu.BOND_H1, H2=ntu.BOND_H2, V1=ntu.BOND_V1, V2=ntu.BOND_V2)
+    ctx = ntu.Context(complex_=True, d=2, d_anc=1, r_g=2, max_D=D, max_batch=1)
+    ctx.bind_stream()
+    Gh = torch.from_numpy(inputs.bond_gate(inputs.ising_bond_hamiltonian(hx), dt / 2)[None]).to(dev)
+    GA, GB, _ = ntu.ntu_gate_split(ctx, Gh)
+    gf = torch.stack([torch.stack([GA[0], GB[0]])] * 4)[None].contiguous()
+    step = ntu.step_opts("f64", order=[codes[b] for b in order], n_iter=20, early_stop=True, conv_tol=1e-12)
+    X = np.array([[0, 1], [1, 0]], complex)
+    Zm = np.diag([1.0, -1.0]).astype(complex)
+    hb = inputs.ising_bond_hamiltonian(hx)
+    # h_b = -ZZ - (h_x / 4)(X 1 + 1 X) as a sum of products
+    I2 = np.eye(2, dtype=complex)
+    terms = np.stack([np.stack([-Zm, Zm]), np.stack([-0.25 * hx * X, I2]), np.stack([I2, -0.25 * hx * X])])
+    assert np.abs(sum(np.kron(a, b) for a, b in terms) - hb).max() < 1e-14
+    ops1 = torch.from_numpy(np.stack([X, Zm])).to(dev)
+    hbt = torch.from_numpy(terms).to(dev)
+    A0, B0 = inputs.polarised_x(D)
+    ctm = ntu.CTM(2, D, chi)
+    if W:
+        A = torch.from_numpy(A0[None]).to(dev)
+        B = torch.from_numpy(B0[None]).to(dev)
+        ntu.ntu_evolve(ctx, ctm, A, B, gf, step, W, every, iters, ops1, hbt, 0.01, True)
+    A = torch.from_numpy(A0[None]).to(dev)
+    B = torch.from_numpy(B0[None]).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist, e, steps = ntu.ntu_evolve(ctx, ctm, A, B, gf, step, K, every, iters, ops1, hbt, 0.01, True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    h = hist.cpu().numpy()
+    result = {
+        "metric": f"quench run: Trotter steps/s with CTMRG measurements (D={D}, chi={chi})",
+        "value": steps / el, "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": W,
+        "ms_per_step": 1e3 * el / max(steps, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": f"Sec. III quench from |+> at h_x=3.04438, D={D}, second-order sweeps of half-step "
+                               f"gates at dt=0.01, FP64, CTMRG chi={chi} ({iters} iterations continued) every "
+                               f"{every} steps, 0.01 energy stop", "D": D, "chi": chi},
+        "observables": {"t": [round(k * every * dt, 4) for k in range(len(e))], "energy": [float(v) for v in e],
+                        "sx": [float(0.5 * (r[0] + r[1]).real) for r in h], "steps_done": steps},
+    }
+    if not args.no_cpu:
+        from oracle import evolve as OE
+        from oracle import ntu as ON
+        GAo, GBo, _ = ON.gate_split(inputs.bond_gate(hb, dt / 2), 2, 2)
+        gd = {b: (GAo, GBo) for b in ON.BONDS}
+        # the oracle's cost of one step and of one measurement, composed into
+        # the GPU run's schedule (K steps, a measurement before them and one
+        # every `every` steps)
+        t0 = time.perf_counter()
+        env, _ = OE.measure(A0, B0, chi, iters, [X, Zm], hb)
+        t_meas = time.perf_counter() - t0
+        An, Bn = A0, B0
+        n_cpu = 2
+        t0 = time.perf_counter()
+        for _ in range(n_cpu):
+            An, Bn, _ = ON.trotter_step(An, Bn, gd, D, n_iter=20, conv_tol=1e-12, order=order)
+        t_step = (time.perf_counter() - t0) / n_cpu
+        n_meas = steps // every + 1
+        model, ncpu = host_cpu()
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count()
+        result["cpu_baseline"] = {"value": steps / (steps * t_step + n_meas * t_meas), "unit": "steps/s",
+                                  "cores": cores, "kind": "oracle",
+                                  "sample": f"oracle: one measurement ({t_meas:.2f} s, {iters} CTMRG iterations "
+                                            f"from the identity boundary) and {n_cpu} second-order steps "
+                                            f"({t_step:.2f} s each) of the same run, composed into the GPU run's "
+                                            f"{steps} steps and {n_meas} measurements",
+                                  "cpu_model": model, "logical_cpus_visible": ncpu}
+    ctm.close()
+    print(json.dumps(result), flush=True)
+
+
 def run_mixed_child(args, K, W):
     """The mixed workload (--bucket 0) in a child process; its JSON line
     reduced to the fields reported under mixed_workload."""
@@ -697,6 +786,9 @@ def main():
         return
     if args.workload == "ctmrg":
         main_ctmrg(args, ntu, torch, np, dev, inputs)
+        return
+    if args.workload == "quench":
+        main_quench(args, ntu, torch, np, dev, inputs)
         return
     all_items = None
     if args.workload == "batched":
