@@ -428,6 +428,45 @@ ntu_status ntu_ctm_expect(ntu_ctm* ctm, const ntu_tensor* A, const ntu_tensor* B
                           const ntu_tensor* ops2, ntu_tensor* out);
 
 /*
+ * One Trotter sweep of a larger unit cell (Sec. II: the environment of each
+ * update is its cluster of nearest neighbours, so updates whose clusters do
+ * not touch are independent and run side by side).  The cell holds Lx x Ly
+ * distinct site tensors on the torus the cell repeats on; bonds are updated
+ * in the given order, each a full NTU (or SVDU) update of bond (x, y, dir):
+ * dir 0 joins (x, y).r to (x + 1, y).l (X = (x, y), Y = (x + 1, y)); dir 1
+ * joins (x, y).t to (x, y + 1).b and runs in the frame turned a quarter turn
+ * clockwise (X = (x, y), Y = (x, y + 1)), as the vertical bonds of
+ * ntu_trotter_step.  The cluster of a horizontal bond is L = (x - 1, y),
+ * TX = (x, y + 1), BX = (x, y - 1), TY = (x + 1, y + 1), BY = (x + 1, y - 1),
+ * Rn = (x + 2, y) (coordinates modulo the cell); of a vertical bond, in the
+ * turned frame, L = (x, y - 1), TX = (x - 1, y), BX = (x + 1, y),
+ * TY = (x - 1, y + 1), BY = (x + 1, y + 1), Rn = (x, y + 2).
+ * Consecutive bonds of the order of which none changes a site of another's
+ * cluster are one launch group (at most min(max_batch, 48) bonds): their
+ * clusters are gathered into batches, updated by one chain of batched
+ * launches and scattered back; since such updates commute, the result is
+ * that of updating the bonds one after another.  Order the bonds so that
+ * independent ones are adjacent (e.g. horizontal bonds with rows and columns
+ * in classes of 3 and 4, then vertical ones) to form large groups.
+ * T: (Lx Ly, p, D, D, D, D) in place, the compute type; site (x, y) is item
+ *   x + Lx y.  Lx, Ly >= 2, Lx Ly <= 4096.
+ * bonds: host array of n_bonds triples (x, y, dir), 0 <= x < Lx,
+ *   0 <= y < Ly, in sweep order.
+ * gate_factors: (n_bonds, 2, d, d, r_g): bond k's (GA, GB), GA acting on X.
+ * opts: precision, fix_mode, fit and scheme as for ntu_trotter_step (n_bonds,
+ *   order and graph are not used; the sweep runs eagerly).
+ * work: one-dimensional device array of the compute type with at least
+ *   8 min(max_batch, 48) p D^4 elements (the gathered clusters).
+ * stats (may be NULL): (n_bonds, NTU_STEP_STATS_LEN) NTU_F64, bond k's row as
+ *   in ntu_trotter_step.
+ * n_groups (host, may be NULL): the launch groups the sweep took.
+ * Errors: every argument is checked before anything runs.
+ */
+ntu_status ntu_cell_step(ntu_ctx* ctx, int Lx, int Ly, ntu_tensor* T, int n_bonds, const int* bonds,
+                         const ntu_tensor* gate_factors, const ntu_step_opts* opts, ntu_tensor* work,
+                         ntu_tensor* stats, int* n_groups);
+
+/*
  * A time-evolution run measured with CTMRG (Sec. III: the quench from a
  * polarised state, observables from the CTM environment, each run ended once
  * the energy per site has moved away from its initial value by more than a

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["api.hip", "api_noalloc.hip", "api_ctm.hip", "k_small.hip", "k_env.hip", "k_mfma.hip", "k_e45.hip", "k_herm.hip",
-           "k_fit.hip", "k_ctm.hip"]
+           "k_fit.hip", "k_ctm.hip", "k_cell.hip"]
 LIB = os.path.join(HERE, "libntu.so")
 ARCH = "gfx950"
 

@@ -9,8 +9,10 @@
 #include <utility>
 #include <vector>
 #include <algorithm>
+#include <array>
 #include "ntu.h"
 #include "kernels.h"
+#include "cell.h"
 #include "mfma_gemm.h"
 
 namespace {
@@ -561,17 +563,20 @@ ntu_status ntu_recombine(ntu_ctx* c, int batch, const ntu_tensor* QX, const ntu_
 
 namespace {
 
-// The launches of one Trotter step (everything after argument checks).  A, B
-// are compute-type site tensors; for complex64 storage (c64) the caller's
-// tensors are A64, B64 and A, B are the context's working copies.
-hipError_t step_launches(ntu_ctx* c, int batch, int D, char* A, char* B, void* A64, void* B64, bool c64,
-                         const char* gate_factors, const ntu_step_opts* opts, double* stats, const ntu::ProfHook& ph,
+// The launches of one bond update over a batch of independent items: X, Y
+// and the six neighbours nbr = [L, TX, BX, TY, BY, Rn] in the bond's
+// canonical frame (compute type, item stride p D^4), the gate factors of item
+// i at gA + i gf_item, gB + i gf_item; the new X, Y written to outX, outY
+// (rotated back a quarter turn when vertical).  sb: the item-0 stats of this
+// update (NTU_STEP_STATS_LEN doubles) with item stride s_item, or NULL.
+hipError_t bond_launches(ntu_ctx* c, int batch, int D, const char* X, const char* Y, const void* const nbr[6],
+                         const char* gA, const char* gB, long long gf_item, void* outX, void* outY, bool vertical,
+                         const ntu_step_opts* opts, double* sb, long long s_item, const ntu::ProfHook& ph,
                          const char** where) {
   const bool cp = c->cplx;
   const int p = pdim(c), R = D * c->rg;
   const size_t el = elem_size(c);
   const Persist L = persist_layout(p, D, c->rg, c->d);
-  // persistent buffers: laid out per buffer kind, item stride = one item's elements
   auto buf = [&](long long off) -> char* { return c->step + (size_t)off * el * batch; };
   char* QX = buf(L.QX);
   char* QY = buf(L.QY);
@@ -580,17 +585,9 @@ hipError_t step_launches(ntu_ctx* c, int batch, int D, char* A, char* B, void* A
   char* G = buf(L.g);
   char* MX = buf(L.MX);
   char* MY = buf(L.MY);
-  char* rA = buf(L.rA);
-  char* rB = buf(L.rB);
   double* cert = (double*)buf(L.cert);
   char* guess = buf(L.guess);
   int* todo = (int*)buf(L.todo);
-  const long long gfs = (long long)c->d * c->d * c->rg;  // elements of one factor
-  const long long gf_item = 8 * gfs;                      // 4 bonds x (GA, GB)
-  const int fl = ntu::fit_stats_len(opts->fit.n_iter, D);
-  const int sl = 8 + fl;
-  const long long s_item = (long long)opts->n_bonds * sl;
-  const long long nsite = (long long)p * D * D * D * D;
   const ntu::FitParams fp = fit_params(&opts->fit);
   hipError_t e = hipSuccess;
   // Fork/join bookkeeping: once the side stream has been forked, every exit
@@ -605,6 +602,84 @@ hipError_t step_launches(ntu_ctx* c, int batch, int D, char* A, char* B, void* A
     if (hipEventRecord(c->ev_join, aux) == hipSuccess) (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
   };
 #define NTU_STEP(x, what) do { e = (x); if (e != hipSuccess) { *where = what; join(); return e; } } while (0)
+  if (opts->scheme == NTU_SCHEME_SVDU) {
+    // SVDU update (Fig. 2): reduction, truncated SVD of RX RY^T, the fit's
+    // balancing without a metric, recombination; all on the context stream
+    ph(ntu::PK_REDUCE, 0);
+    NTU_STEP(ntu::launch_reduce_qr_pair(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, Y, gB, gf_item, QX, RX, QY,
+                                        RY, opts->fit.kappa, todo, c->stream), "reduce_qr");
+    ph(ntu::PK_REDUCE, 1);
+    NTU_STEP(ntu::launch_svdu_guess(cp, batch, D, R, RX, RY, opts->fit.kappa, guess, c->stream), "svdu_guess");
+    NTU_STEP(ntu::launch_bond_fit(cp, batch, D, R, nullptr, RX, RY, fp, MX, MY, sb ? sb + 8 : nullptr, (int)s_item,
+                                  c->ws, c->stream, ph, nullptr, guess), "bond_fit");
+    ph(ntu::PK_RECOMB, 0);
+    NTU_STEP(ntu::launch_recombine(cp, batch, p, D, R, QX, QY, MX, MY, outX, outY, vertical ? 1 : 0, c->stream),
+             "recombine");
+    ph(ntu::PK_RECOMB, 1);
+    return hipSuccess;
+  }
+  // The side stream (aux) takes the work that does not need the reduction:
+  // the edge tensors and transfers (they read only the neighbours) while
+  // the reduction runs, then the fit's SVDU guess (it needs only RX, RY)
+  // while the environment is contracted.  Events order the two streams.
+  const ntu::ProfHook none{nullptr, nullptr};
+  NTU_STEP(hipEventRecord(c->ev_fork, c->stream), "fork");
+  NTU_STEP(hipStreamWaitEvent(aux, c->ev_fork, 0), "fork");
+  forked = true;
+  NTU_STEP(ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, nullptr, nullptr, nbr, nullptr, c->ws,
+                                    c->ws_bytes, aux, none, 1), "env_contract (edges)");
+  NTU_STEP(hipEventRecord(c->ev_edges, aux), "fork");
+  ph(ntu::PK_REDUCE, 0);
+  NTU_STEP(ntu::launch_reduce_qr_pair(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, Y, gB, gf_item, QX, RX, QY,
+                                      RY, opts->fit.kappa, todo, c->stream), "reduce_qr");
+  ph(ntu::PK_REDUCE, 1);
+  NTU_STEP(hipEventRecord(c->ev_red, c->stream), "fork");
+  NTU_STEP(hipStreamWaitEvent(aux, c->ev_red, 0), "fork");
+  NTU_STEP(ntu::launch_svdu_guess(cp, batch, D, R, RX, RY, opts->fit.kappa, guess, aux), "svdu_guess");
+  NTU_STEP(hipStreamWaitEvent(c->stream, c->ev_edges, 0), "join");
+  NTU_STEP(ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, QX, QY, nbr, G, c->ws, c->ws_bytes,
+                                    c->stream, ph, 2, env_ks(c, D, opts->precision)), "env_contract");
+  // with the clip, the repair also tests the fit's certificate (g minus
+  // 10 tau_max ||g||_F I positive definite, see the fit) and hands it over
+  const bool clip = opts->fix_mode == NTU_FIX_HERM_CLIP;
+  const double shift = 10.0 * fp.tol[fp.n_tol - 1];
+  NTU_STEP(ntu::launch_metric_fix(cp, batch, R * R, G, opts->fix_mode, sb, (int)s_item, c->ws, c->stream, ph,
+                                  clip ? shift : 0.0, clip ? cert : nullptr),
+           "metric_fix");
+  // the SVDU guess is ready: join the side stream
+  NTU_STEP(hipEventRecord(c->ev_join, aux), "join");
+  NTU_STEP(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join");
+  forked = false;
+  NTU_STEP(ntu::launch_bond_fit(cp, batch, D, R, G, RX, RY, fp, MX, MY, sb ? sb + 8 : nullptr, (int)s_item, c->ws,
+                                c->stream, ph, clip ? cert : nullptr, guess), "bond_fit");
+  ph(ntu::PK_RECOMB, 0);
+  NTU_STEP(ntu::launch_recombine(cp, batch, p, D, R, QX, QY, MX, MY, outX, outY, vertical ? 1 : 0, c->stream),
+           "recombine");
+  ph(ntu::PK_RECOMB, 1);
+#undef NTU_STEP
+  return hipSuccess;
+}
+
+// The launches of one Trotter step (everything after argument checks).  A, B
+// are compute-type site tensors; for complex64 storage (c64) the caller's
+// tensors are A64, B64 and A, B are the context's working copies.
+hipError_t step_launches(ntu_ctx* c, int batch, int D, char* A, char* B, void* A64, void* B64, bool c64,
+                         const char* gate_factors, const ntu_step_opts* opts, double* stats, const ntu::ProfHook& ph,
+                         const char** where) {
+  const bool cp = c->cplx;
+  const int p = pdim(c);
+  const size_t el = elem_size(c);
+  const Persist L = persist_layout(p, D, c->rg, c->d);
+  auto buf = [&](long long off) -> char* { return c->step + (size_t)off * el * batch; };
+  char* rA = buf(L.rA);
+  char* rB = buf(L.rB);
+  const long long gfs = (long long)c->d * c->d * c->rg;  // elements of one factor
+  const long long gf_item = 8 * gfs;                      // 4 bonds x (GA, GB)
+  const int sl = 8 + ntu::fit_stats_len(opts->fit.n_iter, D);
+  const long long s_item = (long long)opts->n_bonds * sl;
+  const long long nsite = (long long)p * D * D * D * D;
+  hipError_t e = hipSuccess;
+#define NTU_STEP(x, what) do { e = (x); if (e != hipSuccess) { *where = what; return e; } } while (0)
   if (c64) {
     NTU_STEP(ntu::launch_cast_c64(batch * nsite, A64, A, 0, c->stream), "complex64 load");
     NTU_STEP(ntu::launch_cast_c64(batch * nsite, B64, B, 0, c->stream), "complex64 load");
@@ -630,61 +705,10 @@ hipError_t step_launches(ntu_ctx* c, int batch, int D, char* A, char* B, void* A
     void* outX = x_is_a ? A : B;
     void* outY = x_is_a ? B : A;
     double* sb = stats ? stats + (size_t)bi * sl : nullptr;
-    if (opts->scheme == NTU_SCHEME_SVDU) {
-      // SVDU update (Fig. 2): reduction, truncated SVD of RX RY^T, the fit's
-      // balancing without a metric, recombination; all on the context stream
-      ph(ntu::PK_REDUCE, 0);
-      NTU_STEP(ntu::launch_reduce_qr_pair(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, Y, gB, gf_item, QX, RX, QY,
-                                          RY, opts->fit.kappa, todo, c->stream), "reduce_qr");
-      ph(ntu::PK_REDUCE, 1);
-      NTU_STEP(ntu::launch_svdu_guess(cp, batch, D, R, RX, RY, opts->fit.kappa, guess, c->stream), "svdu_guess");
-      NTU_STEP(ntu::launch_bond_fit(cp, batch, D, R, nullptr, RX, RY, fp, MX, MY, sb ? sb + 8 : nullptr, (int)s_item,
-                                    c->ws, c->stream, ph, nullptr, guess), "bond_fit");
-      ph(ntu::PK_RECOMB, 0);
-      NTU_STEP(ntu::launch_recombine(cp, batch, p, D, R, QX, QY, MX, MY, outX, outY, vertical ? 1 : 0, c->stream),
-               "recombine");
-      ph(ntu::PK_RECOMB, 1);
-      continue;
-    }
-    // The side stream (aux) takes the work that does not need the reduction:
-    // the edge tensors and transfers (they read only the neighbours) while
-    // the reduction runs, then the fit's SVDU guess (it needs only RX, RY)
-    // while the environment is contracted.  Events order the two streams.
+    // on the two-site checkerboard X's neighbours are of Y's type and vice versa
     const void* nbr[6] = {Y, Y, Y, X, X, X};
-    const ntu::ProfHook none{nullptr, nullptr};
-    NTU_STEP(hipEventRecord(c->ev_fork, c->stream), "fork");
-    NTU_STEP(hipStreamWaitEvent(aux, c->ev_fork, 0), "fork");
-    forked = true;
-    NTU_STEP(ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, nullptr, nullptr, nbr, nullptr, c->ws,
-                                      c->ws_bytes, aux, none, 1), "env_contract (edges)");
-    NTU_STEP(hipEventRecord(c->ev_edges, aux), "fork");
-    ph(ntu::PK_REDUCE, 0);
-    NTU_STEP(ntu::launch_reduce_qr_pair(cp, c->dtype, batch, c->d, c->na, D, c->rg, X, gA, Y, gB, gf_item, QX, RX, QY,
-                                        RY, opts->fit.kappa, todo, c->stream), "reduce_qr");
-    ph(ntu::PK_REDUCE, 1);
-    NTU_STEP(hipEventRecord(c->ev_red, c->stream), "fork");
-    NTU_STEP(hipStreamWaitEvent(aux, c->ev_red, 0), "fork");
-    NTU_STEP(ntu::launch_svdu_guess(cp, batch, D, R, RX, RY, opts->fit.kappa, guess, aux), "svdu_guess");
-    NTU_STEP(hipStreamWaitEvent(c->stream, c->ev_edges, 0), "join");
-    NTU_STEP(ntu::launch_env_contract(cp, opts->precision, batch, p, D, R, QX, QY, nbr, G, c->ws, c->ws_bytes,
-                                      c->stream, ph, 2, env_ks(c, D, opts->precision)), "env_contract");
-    // with the clip, the repair also tests the fit's certificate (g minus
-    // 10 tau_max ||g||_F I positive definite, see the fit) and hands it over
-    const bool clip = opts->fix_mode == NTU_FIX_HERM_CLIP;
-    const double shift = 10.0 * fp.tol[fp.n_tol - 1];
-    NTU_STEP(ntu::launch_metric_fix(cp, batch, R * R, G, opts->fix_mode, sb, (int)s_item, c->ws, c->stream, ph,
-                                    clip ? shift : 0.0, clip ? cert : nullptr),
-             "metric_fix");
-    // the SVDU guess is ready: join the side stream
-    NTU_STEP(hipEventRecord(c->ev_join, aux), "join");
-    NTU_STEP(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join");
-    forked = false;
-    NTU_STEP(ntu::launch_bond_fit(cp, batch, D, R, G, RX, RY, fp, MX, MY, sb ? sb + 8 : nullptr, (int)s_item, c->ws,
-                                  c->stream, ph, clip ? cert : nullptr, guess), "bond_fit");
-    ph(ntu::PK_RECOMB, 0);
-    NTU_STEP(ntu::launch_recombine(cp, batch, p, D, R, QX, QY, MX, MY, outX, outY, vertical ? 1 : 0, c->stream),
-             "recombine");
-    ph(ntu::PK_RECOMB, 1);
+    NTU_STEP(bond_launches(c, batch, D, X, Y, nbr, gA, gB, gf_item, outX, outY, vertical, opts, sb, s_item, ph, where),
+             *where);
   }
   if (c64) {
     NTU_STEP(ntu::launch_cast_c64(batch * nsite, A, A64, 1, c->stream), "complex64 store");
@@ -791,6 +815,104 @@ ntu_status ntu_trotter_step(ntu_ctx* c, int batch, ntu_tensor* A, ntu_tensor* B,
   }
   e = hipGraphLaunch(c->graph_exec, c->stream);
   return e == hipSuccess ? NTU_OK : hip_fail(c, e, "graph launch");
+}
+
+ntu_status ntu_cell_step(ntu_ctx* c, int Lx, int Ly, ntu_tensor* T, int n_bonds, const int* bonds,
+                         const ntu_tensor* gate_factors, const ntu_step_opts* opts, ntu_tensor* work,
+                         ntu_tensor* stats, int* n_groups) {
+  NTU_CHECK(check_common(c, 1, 1));
+  if (n_groups) *n_groups = 0;
+  if (!opts) return fail(c, NTU_ERR_ARG, "step options are NULL");
+  if (opts->precision < NTU_PREC_F64 || opts->precision > NTU_PREC_BF16X6) return fail(c, NTU_ERR_ARG, "unknown precision");
+  if (opts->fix_mode != NTU_FIX_HERM && opts->fix_mode != NTU_FIX_HERM_CLIP) return fail(c, NTU_ERR_ARG, "unknown fix mode");
+  NTU_CHECK(check_fit_opts(c, &opts->fit));
+  if (opts->scheme != NTU_SCHEME_NTU && opts->scheme != NTU_SCHEME_SVDU) return fail(c, NTU_ERR_ARG, "unknown scheme");
+  if (Lx < 2 || Ly < 2 || (long long)Lx * Ly > 4096) return fail(c, NTU_ERR_SHAPE, "cell: Lx, Ly >= 2 and Lx Ly <= 4096");
+  if (n_bonds < 0 || n_bonds > 65536) return fail(c, NTU_ERR_ARG, "n_bonds outside [0, 65536]");
+  if (n_bonds > 0 && !bonds) return fail(c, NTU_ERR_ARG, "bonds is NULL");
+  for (int k = 0; k < n_bonds; ++k) {
+    const int x = bonds[3 * k], y = bonds[3 * k + 1], dir = bonds[3 * k + 2];
+    if (x < 0 || x >= Lx || y < 0 || y >= Ly || (dir != 0 && dir != 1))
+      return fail(c, NTU_ERR_ARG, "bond " + std::to_string(k) + ": x in [0, Lx), y in [0, Ly), dir 0 or 1");
+  }
+  if (n_bonds == 0) return NTU_OK;
+  const int D = dim_of(T, 2);
+  NTU_CHECK(check_common(c, 1, D));
+  const long long p = pdim(c);
+  const long long nsite = p * D * D * D * D;
+  NTU_CHECK(check_tensor(c, T, "T", compute_mask(c), {(long long)Lx * Ly, p, D, D, D, D}));
+  NTU_CHECK(check_tensor(c, gate_factors, "gate_factors", compute_mask(c), {n_bonds, 2, c->d, c->d, c->rg}));
+  const int G = std::min(c->max_batch, ntu::CELL_GROUP_MAX);
+  if (!work || work->ndim != 1) return fail(c, NTU_ERR_SHAPE, "work: a one-dimensional array");
+  NTU_CHECK(check_tensor(c, work, "work", compute_mask(c), {work->shape[0]}));
+  if (work->shape[0] < 8 * G * nsite)
+    return fail(c, NTU_ERR_WORKSPACE, "work: " + std::to_string(8 * G * nsite) + " elements needed (8 min(max_batch, " +
+                                          std::to_string(ntu::CELL_GROUP_MAX) + ") p D^4)");
+  const int sl = 8 + ntu::fit_stats_len(opts->fit.n_iter, D);
+  if (stats) NTU_CHECK(check_tensor(c, stats, "stats", M_F64, {n_bonds, sl}));
+  if (opts->scheme == NTU_SCHEME_NTU && !ntu::env_precision_supported(c->cplx, opts->precision, D))
+    return fail(c, NTU_ERR_UNSUPPORTED, "precision not available for this dtype");
+  DeviceGuard guard(c->device);
+  // cluster sites [X, Y, L, TX, BX, TY, BY, Rn] of every bond, in the bond's
+  // frame (vertical bonds: the lattice turned a quarter turn clockwise, so
+  // left is below, up is left)
+  auto site = [&](int i, int j) { return ((i % Lx) + Lx) % Lx + Lx * (((j % Ly) + Ly) % Ly); };
+  std::vector<std::array<int, 8>> cl(n_bonds);
+  for (int k = 0; k < n_bonds; ++k) {
+    const int x = bonds[3 * k], y = bonds[3 * k + 1];
+    if (bonds[3 * k + 2] == 0)
+      cl[k] = {site(x, y), site(x + 1, y), site(x - 1, y), site(x, y + 1), site(x, y - 1), site(x + 1, y + 1),
+               site(x + 1, y - 1), site(x + 2, y)};
+    else
+      cl[k] = {site(x, y), site(x, y + 1), site(x, y - 1), site(x - 1, y), site(x + 1, y), site(x - 1, y + 1),
+               site(x + 1, y + 1), site(x, y + 2)};
+  }
+  // two updates commute when neither changes a site of the other's cluster
+  auto independent = [&](int a, int b) {
+    for (int u = 0; u < 2; ++u)
+      for (int r = 0; r < 8; ++r)
+        if (cl[a][u] == cl[b][r] || cl[b][u] == cl[a][r]) return false;
+    return true;
+  };
+  const size_t el = elem_size(c);
+  const long long gfs = (long long)c->d * c->d * c->rg;
+  char* W = (char*)work->data;
+  const char* GF = (const char*)gate_factors->data;
+  double* st = stats ? (double*)stats->data : nullptr;
+  const ntu::ProfHook ph = hook(c);
+  int groups = 0;
+  for (int k0 = 0; k0 < n_bonds;) {
+    int k1 = k0 + 1;
+    while (k1 < n_bonds && k1 - k0 < G) {
+      bool ok = true;
+      for (int j = k0; j < k1 && ok; ++j) ok = independent(j, k1);
+      if (!ok) break;
+      ++k1;
+    }
+    ntu::CellGroup g{};
+    g.n = k1 - k0;
+    for (int k = 0; k < g.n; ++k) {
+      for (int r = 0; r < 8; ++r) g.site[k][r] = cl[k0 + k][r];
+      g.vert[k] = bonds[3 * (k0 + k) + 2];
+    }
+    auto role = [&](int r) { return W + (size_t)r * g.n * nsite * el; };
+    hipError_t e = ntu::launch_cell_gather(c->cplx, T->data, W, (int)p, D, g, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "cell gather");
+    const void* nbr[6] = {role(2), role(3), role(4), role(5), role(6), role(7)};
+    const char* where = "";
+    // the new X, Y are written over roles 0 and 1 in the bond's frame (the
+    // reduction has read them by then) and turned back by the scatter
+    e = bond_launches(c, g.n, D, role(0), role(1), nbr, GF + (size_t)(2 * k0) * gfs * el,
+                      GF + (size_t)(2 * k0 + 1) * gfs * el, 2 * gfs, role(0), role(1), false, opts,
+                      st ? st + (size_t)k0 * sl : nullptr, sl, ph, &where);
+    if (e != hipSuccess) return hip_fail(c, e, where);
+    e = ntu::launch_cell_scatter(c->cplx, T->data, W, (int)p, D, g, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "cell scatter");
+    ++groups;
+    k0 = k1;
+  }
+  if (n_groups) *n_groups = groups;
+  return NTU_OK;
 }
 
 ntu_status ntu_tune_env(ntu_ctx* c, int batch, int precision, const ntu_tensor* QX, const ntu_tensor* QY,

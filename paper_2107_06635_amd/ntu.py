@@ -35,7 +35,7 @@ EXPORTED = (
     "ntu_tune_env", "ntu_set_env_ksplit", "ntu_get_env_ksplit", "ntu_tune_save", "ntu_tune_load",
     "ntu_metric_fix_noalloc", "ntu_superop_gate",
     "ntu_ctm_create", "ntu_ctm_destroy", "ntu_ctm_set_stream", "ntu_ctm_last_error", "ntu_ctm_run", "ntu_ctm_expect",
-    "ntu_evolve",
+    "ntu_evolve", "ntu_cell_step",
 )
 
 
@@ -115,6 +115,8 @@ def load():
     L.ntu_ctm_last_error.restype = ctypes.c_char_p
     L.ntu_ctm_run.argtypes = [vp, tp, tp, i32, i32]
     L.ntu_ctm_expect.argtypes = [vp, tp, tp, tp, tp, tp]
+    L.ntu_cell_step.argtypes = [vp, i32, i32, tp, i32, ctypes.POINTER(i32), tp, ctypes.POINTER(StepOpts), tp, tp,
+                                ctypes.POINTER(i32)]
     L.ntu_evolve.argtypes = [vp, vp, tp, tp, tp, ctypes.POINTER(StepOpts), ctypes.POINTER(EvolveOpts), tp, tp, tp,
                              dp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     for name in EXPORTED:
@@ -184,7 +186,7 @@ class Context:
         self.L = load()
         self.cplx = complex_
         self.dtype = torch.complex128 if complex_ else torch.float64
-        self.d, self.d_anc, self.r_g, self.max_D = d, d_anc, r_g, max_D
+        self.d, self.d_anc, self.r_g, self.max_D, self.max_batch = d, d_anc, r_g, max_D, max_batch
         self.p = d * d_anc
         self.device = torch.device("cuda", device)
         h = ctypes.c_void_p()
@@ -460,3 +462,24 @@ def ntu_evolve(ctx: Context, ctm: CTM, A, B, gate_factors, step: StepOpts, n_ste
                            f"{ctx.L.ntu_last_error(ctx.h).decode()}")
     k = n_meas.value
     return hist[:k], np.array(energy[:k]), steps.value
+
+
+CELL_GROUP_MAX = 48
+
+
+def ntu_cell_step(ctx: Context, Lx, Ly, T, bonds, gate_factors, opts: StepOpts | None = None, stats=True):
+    """One sweep of the bonds (x, y, dir) of an Lx x Ly cell, in place on T
+    (Lx Ly, p, D, D, D, D); gate_factors (n_bonds, 2, d, d, r_g).  Returns
+    (stats (n_bonds, step_stats_len) or None, launch groups)."""
+    opts = opts or step_opts()
+    n = len(bonds)
+    flat = (ctypes.c_int * max(3 * n, 1))(*[int(v) for b in bonds for v in b])
+    D = T.shape[2]
+    G = min(ctx.max_batch, CELL_GROUP_MAX)
+    work = torch.empty(8 * G * T[0].numel(), dtype=T.dtype, device=T.device)
+    st = ctx.zeros(n, step_stats_len(opts.fit.n_iter, D), dtype=torch.float64) if stats and n else None
+    groups = ctypes.c_int(0)
+    ctx.bind_stream()
+    ctx.check(ctx.L.ntu_cell_step(ctx.h, Lx, Ly, _ref(T), n, flat, _ref(gate_factors), ctypes.byref(opts), _ref(work),
+                                  _ref(st), ctypes.byref(groups)), "ntu_cell_step")
+    return st, groups.value
