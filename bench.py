@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batched", choices=["batched", "thermal", "large", "hermitian", "ctmrg", "quench"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "thermal", "large", "hermitian", "ctmrg", "quench", "cell"])
     ap.add_argument("--precision", default=None, choices=["bf16x3", "bf16x6", "fp16x3", "f64"],
                     help="environment precision (default: fp16x3 for the batched workload; bf16x6 for the "
                          "others, whose real or D > 8 metrics take the tiled path FP16x3 does not cover)")
@@ -85,6 +85,8 @@ def parse():
                     help="GPU_MAX_HW_QUEUES for this process (hardware queues the streams are spread over)")
     ap.add_argument("--aux", default="own", choices=["own", "shared"],
                     help="side stream of each bucket's Trotter step: the context's own, or one shared by all")
+    ap.add_argument("--cell", default="24x24", help="cell workload: Lx x Ly of the unit cell")
+    ap.add_argument("--cell-D", type=int, default=8, help="cell workload: bond dimension")
     ap.add_argument("--ctm-D", type=int, default=3,
                     help="bond dimension of the CTMRG and quench workloads (chi = 4 D)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -731,6 +733,78 @@ def main_quench(args, ntu, torch, np, dev, inputs):
     print(json.dumps(result), flush=True)
 
 
+def main_cell(args, ntu, torch, np, dev, inputs):
+    """One sweep over every bond of an Lx x Ly unit cell of distinct random
+    complex tensors (ntu_cell_step, the library's sweep order; the quench
+    gate at dt = 0.01 on every bond): bond updates/s in the chosen precision
+    and in FP64, K sweeps timed (default 5) after W untimed ones."""
+    Lx, Ly = (int(v) for v in args.cell.lower().split("x"))
+    D = args.cell_D
+    K = args.steps if args.steps_given else 5
+    W = args.warmup
+    rng = np.random.default_rng(6)
+    sites = np.stack([inputs.random_site_pair(rng, 2, D)[0] for _ in range(Lx * Ly)])
+    bonds = inputs.cell_bond_order(Lx, Ly)
+    G = inputs.bond_gate(inputs.ising_bond_hamiltonian(inputs.H_CRIT), 0.01)
+    ctx = ntu.Context(complex_=True, d=2, d_anc=1, r_g=2, max_D=D, max_batch=48)
+    ctx.bind_stream()
+    GA, GB, _ = ntu.ntu_gate_split(ctx, torch.from_numpy(G[None]).to(dev))
+    gf = torch.stack([GA[0], GB[0]])[None].expand(len(bonds), 2, *GA.shape[1:]).contiguous()
+    out = {}
+    for prec in (args.precision, "f64"):
+        T = torch.from_numpy(sites).to(dev)
+        opts = ntu.step_opts(prec, n_iter=20, early_stop=True, conv_tol=1e-12)
+        for _ in range(W):
+            ntu.ntu_cell_step(ctx, Lx, Ly, T, bonds, gf, opts, stats=False)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n = K if prec == args.precision else max(1, min(K, 2))
+        ev0.record()
+        groups = 0
+        for _ in range(n):
+            _, groups = ntu.ntu_cell_step(ctx, Lx, Ly, T, bonds, gf, opts, stats=False)
+        ev1.record()
+        torch.cuda.synchronize()
+        out[prec] = (ev0.elapsed_time(ev1) / n, groups)
+    ms, groups = out[args.precision]
+    ms64 = out["f64"][0]
+    nb = len(bonds)
+    result = {
+        "metric": f"NTU bond updates/s over a {Lx}x{Ly} unit cell at D={D}", "value": nb / (ms / 1e3),
+        "unit": "bond_updates/s", "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{Lx}x{Ly} unit cell of distinct random complex site tensors (seed 6), D={D}, "
+                               f"one sweep of its {nb} bonds (critical quench gate, dt=0.01) per step in "
+                               f"{groups} launch groups of independent bonds", "D": D, "bonds": nb,
+                   "groups": groups},
+        "fp64_path": {"value": nb / (ms64 / 1e3), "ms_per_step": ms64},
+    }
+    if not args.no_cpu:
+        from oracle import cell as OCE
+        from oracle import ntu as ON
+        GAo, GBo, _ = ON.gate_split(G, 2, 2)
+        T0 = {(k % Lx, k // Lx): sites[k] for k in range(Lx * Ly)}
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < args.cpu_seconds and done < nb:
+            k = min(8, nb - done)
+            T0, _ = OCE.cell_sweep(T0, Lx, Ly, bonds[done:done + k], [(GAo, GBo)] * k, D, n_iter=20,
+                                   conv_tol=1e-12)
+            done += k
+        el = time.perf_counter() - t0
+        model, ncpu = host_cpu()
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count()
+        result["cpu_baseline"] = {"value": done / el, "unit": "bond_updates/s", "cores": cores, "kind": "oracle",
+                                  "sample": f"the first {done} bond updates of the same sweep, oracle FP64 "
+                                            f"numpy/BLAS", "cpu_model": model, "logical_cpus_visible": ncpu}
+    print(json.dumps(result), flush=True)
+
+
 def run_mixed_child(args, K, W):
     """The mixed workload (--bucket 0) in a child process; its JSON line
     reduced to the fields reported under mixed_workload."""
@@ -766,7 +840,8 @@ def main():
         return
     K, W = args.steps, args.warmup
     if args.precision is None:
-        args.precision = "fp16x3" if args.workload == "batched" else "bf16x6"
+        args.precision = ("fp16x3" if args.workload == "batched" or (args.workload == "cell" and args.cell_D <= 8)
+                          else "bf16x6")
     # extra: all 256 items of configuration 4 (mixed D), measured first, in a
     # child process, before this process touches the GPU: its thirteen
     # streams then have the hardware queues to themselves
@@ -789,6 +864,9 @@ def main():
         return
     if args.workload == "quench":
         main_quench(args, ntu, torch, np, dev, inputs)
+        return
+    if args.workload == "cell":
+        main_cell(args, ntu, torch, np, dev, inputs)
         return
     all_items = None
     if args.workload == "batched":
