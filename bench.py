@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--scheme", default="ntu", choices=["ntu", "svdu"],
                     help="bond-update scheme: full NTU, or the SVDU update (no environment; implies --no-fp64)")
+    ap.add_argument("--e6-tile", type=int, default=0, choices=[0, 128, 256],
+                    help="FP16x3: fix the output tile width of the metric assembly after tuning (0: the tuned one)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in K split of the metric assembly instead of autotuning it per bucket")
     ap.add_argument("--bucket", type=int, default=8,
@@ -352,7 +354,8 @@ class Runner:
         self.init = state0
 
     def tune(self, precision):
-        """The K split of the split-precision metric assembly, per bucket, on
+        """The schedule (K split; FP16x3 also the output tile width) of the
+        split-precision metric assembly, per bucket, on
         that bucket's own isometries and neighbours after the warm-up (H1
         cluster: neighbours B, B, B, A, A, A)."""
         torch, ntu = self.torch, self.ntu
@@ -364,8 +367,13 @@ class Runner:
                 QY, _ = ntu.ntu_reduce_qr(ctx, B, bk["gf"][:, 0, 1].contiguous(), 1)
                 if self.job.cplx:
                     A, B = A.to(torch.complex128), B.to(torch.complex128)
-                ks, tms = ntu.ntu_tune_env(ctx, QX, QY, [B, B, B, A, A, A], precision, D=bk["D"])
-                tuning[str(bk["D"])] = {"e6_ksplit": ks, "env_ms": round(tms, 4)}
+                ks, tms = ntu.ntu_tune_env(ctx, QX, QY, [B, B, B, A, A, A], precision, D=bk["D"], reps=10)
+                rec = {"e6_ksplit": ks, "env_ms": round(tms, 4)}
+                if precision == "fp16x3":
+                    if self.args.e6_tile:
+                        ntu.ntu_set_env_tile(ctx, bk["D"], precision, self.args.e6_tile)
+                    rec["e6_tile"] = ntu.ntu_get_env_tile(ctx, bk["D"], precision)
+                tuning[str(bk["D"])] = rec
         torch.cuda.synchronize()
         return tuning
 

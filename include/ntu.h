@@ -338,34 +338,44 @@ ntu_status ntu_trotter_step(ntu_ctx* ctx, int batch, ntu_tensor* A, ntu_tensor* 
                             const ntu_tensor* gate_factors, const ntu_step_opts* opts, ntu_tensor* stats);
 
 /*
- * Autotuning of the split-precision environment contraction (a launch
- * parameter, not part of the method): the number of K chunks of the final
+ * Autotuning of the split-precision environment contraction (launch
+ * parameters, not part of the method): the number of K chunks of the final
  * assembly g = L2 Right^T (Fig. 4(d,e)), whose FP64 partial sums are then
- * added.  More chunks fill the GPU better at small batch; fewer move fewer
- * partial sums.  Any choice gives the same metric up to FP64 rounding of the
- * chunk sums.
+ * added, and for NTU_PREC_FP16X3 the width of that assembly's output tiles
+ * (128 or 256 columns of the real-embedded g; 128 rows each, eight waves).
+ * More chunks and narrower tiles fill the GPU better at small batch; fewer
+ * chunks move fewer partial sums, wider tiles read each row of L2 fewer
+ * times.  Any choice gives the same metric up to FP64 rounding of the chunk
+ * sums.
  *
  * ntu_tune_env times ntu_env_contract on the caller's operands (same
- * arguments; g is overwritten) for every candidate split (1 .. 4, and the
- * built-in heuristic's choice when larger), reps timed calls each after one
- * untimed call, with HIP events on the context stream, and synchronises.  It
- * keeps the fastest for (D, precision) in the context, where
- * ntu_env_contract and ntu_trotter_step then use it, and returns it in
- * best_ks (and its mean time in best_ms), either may be NULL.  The choice is
- * made for this batch size.  Precision must be one of the split
- * precisions (NTU_ERR_ARG otherwise); reps >= 1.  The operands are those of
- * ntu_env_contract (D taken from nbr[0]).
- * ntu_set_env_ksplit sets it directly (ks = 0: the heuristic again);
- * ntu_get_env_ksplit returns it (0: the heuristic).
+ * arguments; g is overwritten) for every candidate (K split 1 .. 4, and the
+ * built-in heuristic's choice when larger; for FP16X3 each with both tile
+ * widths), reps timed calls each after one untimed call, with HIP events on
+ * the context stream, and synchronises.  It keeps the fastest for
+ * (D, precision) in the context, where ntu_env_contract, ntu_trotter_step
+ * and ntu_cell_step then use it, and returns its K split in best_ks (and
+ * its mean time in best_ms), either may be NULL; ntu_get_env_tile gives its
+ * tile width.  The choice is made for this batch size.  Precision must be
+ * one of the split precisions (NTU_ERR_ARG otherwise); reps >= 1.  The
+ * operands are those of ntu_env_contract (D taken from nbr[0]).
+ * ntu_set_env_ksplit sets the K split directly (ks = 0: the heuristic
+ * again); ntu_get_env_ksplit returns it (0: the heuristic).
+ * ntu_set_env_tile sets the FP16X3 tile width (0: the default, 128 columns;
+ * 128 or 256; other precisions NTU_ERR_ARG); ntu_get_env_tile returns it
+ * (0: the default).
  * ntu_tune_save writes the context's choices to a text file, one line
- * "D precision ksplit" each; ntu_tune_load reads such a file into the
- * context (entries for D > max_D or other precisions are skipped; a
- * malformed line gives NTU_ERR_ARG, after the lines before it are taken).
+ * "D precision ksplit tile_width" each (0: not set); ntu_tune_load reads
+ * such a file (or lines of the first three fields) into the context
+ * (entries for D > max_D or other precisions are skipped; a malformed line
+ * gives NTU_ERR_ARG, after the lines before it are taken).
  */
 ntu_status ntu_tune_env(ntu_ctx* ctx, int batch, int precision, const ntu_tensor* QX, const ntu_tensor* QY,
                         const ntu_tensor nbr[6], ntu_tensor* g, int reps, int* best_ks, float* best_ms);
 ntu_status ntu_set_env_ksplit(ntu_ctx* ctx, int D, int precision, int ks);
 int ntu_get_env_ksplit(ntu_ctx* ctx, int D, int precision);
+ntu_status ntu_set_env_tile(ntu_ctx* ctx, int D, int precision, int width);
+int ntu_get_env_tile(ntu_ctx* ctx, int D, int precision);
 ntu_status ntu_tune_save(ntu_ctx* ctx, const char* path);
 ntu_status ntu_tune_load(ntu_ctx* ctx, const char* path);
 

@@ -48,6 +48,9 @@ struct ntu_ctx {
   // tuned K split of the split-precision metric assembly per (D, precision)
   // (ntu_tune_env / ntu_set_env_ksplit); absent: the heuristic
   std::map<std::pair<int, int>, int> e6_ks;
+  // tuned output tile width of the FP16X3 assembly per (D, precision)
+  // (ntu_tune_env / ntu_set_env_tile); absent: the default
+  std::map<std::pair<int, int>, int> e6_tile;
   // the Trotter step captured by ntu_trotter_step (opts.graph = 1) and the
   // arguments it was captured with
   hipGraph_t graph = nullptr;
@@ -98,9 +101,19 @@ ntu_status hip_fail(ntu_ctx* c, hipError_t e, const char* where) {
 size_t elem_size(const ntu_ctx* c) { return c->cplx ? 16 : 8; }
 
 // tuned K split of the metric assembly for (D, precision), 0 = heuristic
-int env_ks(const ntu_ctx* c, int D, int precision) {
+int env_ks_only(const ntu_ctx* c, int D, int precision) {
   auto it = c->e6_ks.find({D, precision});
   return it == c->e6_ks.end() ? 0 : it->second;
+}
+// tuned output tile width (columns) of the FP16X3 assembly, 0 = default
+int env_tile(const ntu_ctx* c, int D, int precision) {
+  auto it = c->e6_tile.find({D, precision});
+  return it == c->e6_tile.end() ? 0 : it->second;
+}
+// the schedule handed to the environment contraction: K split in the low
+// byte, tile width / 64 above it (0: the defaults)
+int env_ks(const ntu_ctx* c, int D, int precision) {
+  return env_ks_only(c, D, precision) | ((env_tile(c, D, precision) / 64) << 8);
 }
 int pdim(const ntu_ctx* c) { return c->d * c->na; }
 
@@ -931,13 +944,20 @@ ntu_status ntu_tune_env(ntu_ctx* c, int batch, int precision, const ntu_tensor* 
   DeviceGuard guard(c->device);
   const int R = D * c->rg;
   const int kdef = ntu::e6_ksplit_default(c->cplx, batch, R, D), kcap = ntu::e6_ksplit_max(c->cplx, batch, R, D);
+  std::vector<int> ks_cand;
+  for (int k = 1; k <= std::min(kcap, ntu::E6_KS_TUNE_MAX); ++k) ks_cand.push_back(k);
+  if (kdef > ntu::E6_KS_TUNE_MAX) ks_cand.push_back(kdef);
+  // candidates: (K split, tile width) as the schedule code of env_ks; the
+  // tile width is a choice of the FP16X3 assembly only
+  std::vector<int> tiles = {0};
+  if (precision == NTU_PREC_FP16X3) tiles = {128, 256};
   std::vector<int> cand;
-  for (int k = 1; k <= std::min(kcap, ntu::E6_KS_TUNE_MAX); ++k) cand.push_back(k);
-  if (kdef > ntu::E6_KS_TUNE_MAX) cand.push_back(kdef);
+  for (int t : tiles)
+    for (int k : ks_cand) cand.push_back(k | ((t / 64) << 8));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  int best = kdef;
+  int best = kdef | ((tiles[0] / 64) << 8);
   float tbest = -1.0f;
   const ntu::ProfHook none{nullptr, nullptr};
   for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
@@ -961,8 +981,10 @@ ntu_status ntu_tune_env(ntu_ctx* c, int batch, int precision, const ntu_tensor* 
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(c, e, "tune_env");
-  c->e6_ks[{D, precision}] = best;
-  if (best_ks) *best_ks = best;
+  c->e6_ks[{D, precision}] = best & 0xff;
+  if (best >> 8) c->e6_tile[{D, precision}] = (best >> 8) * 64;
+  else c->e6_tile.erase({D, precision});
+  if (best_ks) *best_ks = best & 0xff;
   if (best_ms) *best_ms = tbest;
   return NTU_OK;
 }
@@ -980,15 +1002,34 @@ ntu_status ntu_set_env_ksplit(ntu_ctx* c, int D, int precision, int ks) {
 
 int ntu_get_env_ksplit(ntu_ctx* c, int D, int precision) {
   if (!c) return NTU_ERR_ARG;
-  return env_ks(c, D, precision);
+  return env_ks_only(c, D, precision);
+}
+
+ntu_status ntu_set_env_tile(ntu_ctx* c, int D, int precision, int width) {
+  if (!c) return NTU_ERR_ARG;
+  if (D < 1 || D > c->max_D) return fail(c, NTU_ERR_SHAPE, "D outside [1, max_D]");
+  if (precision != NTU_PREC_FP16X3) return fail(c, NTU_ERR_ARG, "the tile width applies to NTU_PREC_FP16X3");
+  if (width != 0 && width != 128 && width != 256) return fail(c, NTU_ERR_ARG, "tile width must be 0, 128 or 256");
+  if (width == 0) c->e6_tile.erase({D, precision});
+  else c->e6_tile[{D, precision}] = width;
+  return NTU_OK;
+}
+
+int ntu_get_env_tile(ntu_ctx* c, int D, int precision) {
+  if (!c) return NTU_ERR_ARG;
+  return env_tile(c, D, precision);
 }
 
 ntu_status ntu_tune_save(ntu_ctx* c, const char* path) {
   if (!c || !path) return NTU_ERR_ARG;
   FILE* f = fopen(path, "w");
   if (!f) return fail(c, NTU_ERR_ARG, std::string("cannot write ") + path);
-  fprintf(f, "# D precision e6_ksplit\n");
-  for (const auto& kv : c->e6_ks) fprintf(f, "%d %d %d\n", kv.first.first, kv.first.second, kv.second);
+  fprintf(f, "# D precision e6_ksplit tile_width\n");
+  std::map<std::pair<int, int>, std::pair<int, int>> rows;
+  for (const auto& kv : c->e6_ks) rows[kv.first].first = kv.second;
+  for (const auto& kv : c->e6_tile) rows[kv.first].second = kv.second;
+  for (const auto& kv : rows)
+    fprintf(f, "%d %d %d %d\n", kv.first.first, kv.first.second, kv.second.first, kv.second.second);
   const bool ok = fclose(f) == 0;
   return ok ? NTU_OK : fail(c, NTU_ERR_ARG, std::string("cannot write ") + path);
 }
@@ -1001,14 +1042,16 @@ ntu_status ntu_tune_load(ntu_ctx* c, const char* path) {
   ntu_status s = NTU_OK;
   while (fgets(line, sizeof line, f)) {
     if (line[0] == '#' || line[0] == '\n') continue;
-    int D = 0, prec = 0, ks = 0;
-    if (sscanf(line, "%d %d %d", &D, &prec, &ks) != 3) {
+    int D = 0, prec = 0, ks = 0, tile = 0;
+    const int got = sscanf(line, "%d %d %d %d", &D, &prec, &ks, &tile);
+    if (got < 3 || ks < 0 || (got == 4 && tile != 0 && tile != 128 && tile != 256)) {
       s = fail(c, NTU_ERR_ARG, std::string("malformed line in ") + path);
       break;
     }
-    if (D >= 1 && D <= c->max_D && (prec == NTU_PREC_BF16X3 || prec == NTU_PREC_BF16X6 || prec == NTU_PREC_FP16X3) &&
-        ks > 0)
-      c->e6_ks[{D, prec}] = ks;
+    if (D >= 1 && D <= c->max_D && (prec == NTU_PREC_BF16X3 || prec == NTU_PREC_BF16X6 || prec == NTU_PREC_FP16X3)) {
+      if (ks > 0) c->e6_ks[{D, prec}] = ks;
+      if (got == 4 && tile > 0 && prec == NTU_PREC_FP16X3) c->e6_tile[{D, prec}] = tile;
+    }
   }
   fclose(f);
   return s;

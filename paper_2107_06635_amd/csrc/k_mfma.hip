@@ -794,9 +794,10 @@ static hipError_t run_tile(const void* A, const void* B, void* C, const GemmNT& 
 // E6 in FP16X3 from the pre-split rows of the fused kernels (complex):
 // A rows (L2) and B rows (Right) of Kc complex entries, 2 Kc words each,
 // item strides in words; output through the maps of d (C side only)
-static hipError_t run_tile_f16(const void* A, const void* B, void* C, const GemmNT& d, long long a_item,
-                               long long b_item, const float* sA, const float* sB, int ksplit, double* partial,
-                               hipStream_t st, const ProfHook& ph, int kind) {
+template <int WY>
+static hipError_t run_tile_f16_w(const void* A, const void* B, void* C, const GemmNT& d, long long a_item,
+                                 long long b_item, const float* sA, const float* sB, int ksplit, double* partial,
+                                 hipStream_t st, const ProfHook& ph, int kind) {
   const int Mr = d.M, Nr = 2 * d.N, Kr = 2 * d.K;
   TileF16Args a{};
   a.M = d.M; a.N = d.N; a.Kc = d.K; a.batch = d.batch;
@@ -804,7 +805,6 @@ static hipError_t run_tile_f16(const void* A, const void* B, void* C, const Gemm
   a.a_row = 2LL * d.K; a.b_row = 2LL * d.K;
   a.sA = sA; a.sB = sB;
   a.Cb = d.Cb; a.Ci = d.Ci; a.Cj = d.Cj;
-  constexpr int WY = F16_WY;
   a.tiles_m = (Mr + TL_M - 1) / TL_M;
   a.tiles_n = (Nr + 64 * WY - 1) / (64 * WY);
   a.ksplit = ksplit < 1 ? 1 : ksplit;
@@ -827,6 +827,17 @@ static hipError_t run_tile_f16(const void* A, const void* B, void* C, const Gemm
   hipLaunchKernelGGL((k_splitk_reduce<true, double>), dim3(gx), dim3(256), 0, st, partial, (double*)C, d, a.ksplit);
   ph(PK_E6RED, 1);
   return hipGetLastError();
+}
+
+// the FP16X3 assembly with output tiles of 64 wy columns (wy 2 or 4; any
+// other value takes the default F16_WY; the load mapping needs wy >= 2)
+static hipError_t run_tile_f16(const void* A, const void* B, void* C, const GemmNT& d, long long a_item,
+                               long long b_item, const float* sA, const float* sB, int ksplit, double* partial,
+                               hipStream_t st, const ProfHook& ph, int kind, int wy) {
+  switch (wy) {
+    case 4: return run_tile_f16_w<4>(A, B, C, d, a_item, b_item, sA, sB, ksplit, partial, st, ph, kind);
+    default: return run_tile_f16_w<F16_WY>(A, B, C, d, a_item, b_item, sA, sB, ksplit, partial, st, ph, kind);
+  }
 }
 
 // K chunks of the tiled assembly: about three blocks per CU (one runs at a
@@ -911,14 +922,16 @@ static hipError_t env_heavy(int batch, int p, int D, int R, const void* QXe, con
   q.Ai = idx1(D4); q.Ak = idx1(1); q.Bj = idx1(D4); q.Bk = idx1(1);
   q.Ci = idx2(R, R, (long long)R * R * R); q.Cj = idx2(R, 1, (long long)R * R);
   const int Nr = (CPLX ? 2 : 1) * q.N, Kr = (CPLX ? 2 : 1) * q.K;
-  // the tuned K split when one is given (at most the reserved e6_ks_cap)
-  const int ks = e6_ks > 0 ? std::min(e6_ks, e6_ks_cap(CPLX, batch, R, D)) : tile_ksplit(batch, q.M, Nr, Kr);
+  // the tuned schedule when one is given: K split in the low byte (at most
+  // the reserved e6_ks_cap), FP16X3 tile width code above it
+  const int ksq = e6_ks & 0xff, wy = (e6_ks >> 8) & 0xff;
+  const int ks = ksq > 0 ? std::min(ksq, e6_ks_cap(CPLX, batch, R, D)) : tile_ksplit(batch, q.M, Nr, Kr);
   // partial sums live right after H2 (the workspace reserves mixed_partial_bytes there)
   double* partial = (double*)((char*)H2 + (size_t)batch * hs * (CPLX ? 8 : 4));
   if constexpr (PREC == NTU_PREC_FP16X3 && CPLX) {
     // the fused kernels wrote L2 and Right as scaled float16 pieces
     const E45Scales sc = e45_scales(H1, PREC, batch, D, R);
-    return run_tile_f16(H0, H2, g, q, 2 * hs, 2 * hs, sc.left, sc.right, ks, partial, st, ph, PK_E6);
+    return run_tile_f16(H0, H2, g, q, 2 * hs, 2 * hs, sc.left, sc.right, ks, partial, st, ph, PK_E6, wy);
   }
   return run_tile<PREC, CPLX, float, float, T64>(H0, H2, g, q, ks, partial, st, ph, PK_E6);
 }

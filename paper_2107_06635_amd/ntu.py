@@ -32,7 +32,8 @@ EXPORTED = (
     "ntu_version", "ntu_gate_split", "ntu_reduce_qr", "ntu_env_contract", "ntu_metric_fix",
     "ntu_fit_opts_default", "ntu_bond_fit", "ntu_recombine", "ntu_step_opts_default", "ntu_trotter_step",
     "ntu_profile_enable", "ntu_profile_read", "ntu_profile_kind_name",
-    "ntu_tune_env", "ntu_set_env_ksplit", "ntu_get_env_ksplit", "ntu_tune_save", "ntu_tune_load",
+    "ntu_tune_env", "ntu_set_env_ksplit", "ntu_get_env_ksplit", "ntu_set_env_tile", "ntu_get_env_tile",
+    "ntu_tune_save", "ntu_tune_load",
     "ntu_metric_fix_noalloc", "ntu_superop_gate",
     "ntu_ctm_create", "ntu_ctm_destroy", "ntu_ctm_set_stream", "ntu_ctm_last_error", "ntu_ctm_run", "ntu_ctm_expect",
     "ntu_evolve", "ntu_cell_step",
@@ -101,6 +102,8 @@ def load():
     L.ntu_tune_env.argtypes = [vp, i32, i32, tp, tp, tp, tp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
     L.ntu_set_env_ksplit.argtypes = [vp, i32, i32, i32]
     L.ntu_get_env_ksplit.argtypes = [vp, i32, i32]
+    L.ntu_set_env_tile.argtypes = [vp, i32, i32, i32]
+    L.ntu_get_env_tile.argtypes = [vp, i32, i32]
     L.ntu_tune_save.argtypes = [vp, ctypes.c_char_p]
     L.ntu_tune_load.argtypes = [vp, ctypes.c_char_p]
     L.ntu_profile_read.argtypes = [vp, dp, ctypes.POINTER(i32), i32]
@@ -280,8 +283,9 @@ def ntu_env_contract(ctx: Context, QX, QY, nbr, precision="f64", D=None):
 
 
 def ntu_tune_env(ctx: Context, QX, QY, nbr, precision="bf16x6", D=None, reps=3):
-    """Times the metric assembly's K split candidates on these operands, keeps
-    the fastest in the context; -> (K split, mean ms)."""
+    """Times the metric assembly's schedule candidates (K split; for FP16X3
+    also the tile width) on these operands, keeps the fastest in the
+    context; -> (K split, mean ms); ntu_get_env_tile gives the width."""
     b = QX.shape[0]
     if D is None:
         D = nbr[0].shape[2]
@@ -303,6 +307,16 @@ def ntu_set_env_ksplit(ctx: Context, D, precision, ks):
 def ntu_get_env_ksplit(ctx: Context, D, precision):
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     return ctx.L.ntu_get_env_ksplit(ctx.h, D, prec)
+
+
+def ntu_set_env_tile(ctx: Context, D, precision, width):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    ctx.check(ctx.L.ntu_set_env_tile(ctx.h, D, prec, width), "ntu_set_env_tile")
+
+
+def ntu_get_env_tile(ctx: Context, D, precision):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return ctx.L.ntu_get_env_tile(ctx.h, D, prec)
 
 
 def ntu_tune_save(ctx: Context, path):

@@ -302,10 +302,11 @@ def test_env_contract_mixed(prec, tol, D, p, real):
 
 
 def test_env_tuning(tmp_path):
-    """Autotuned K split of the split-precision metric assembly: every
-    candidate gives the metric within the BF16x6 budget of the oracle; the
-    tuned choice is kept and used, set and reset by hand, and survives a
-    save / load round trip into a fresh context."""
+    """Autotuned schedule of the split-precision metric assembly (K split;
+    for FP16x3 also the output tile width): every candidate gives the metric
+    within the BF16x6 budget of the oracle; the tuned choice is kept and
+    used, set and reset by hand, survives a save / load round trip into a
+    fresh context, and refused values raise."""
     D, p = 5, 2
     X, Y, nbr, G, GA, GB = _case(310, D, p, False)
     QX, _ = O.reduce_site(X, GA, 'X', 2)
@@ -333,12 +334,32 @@ def test_env_tuning(tmp_path):
     assert ntu.ntu_get_env_ksplit(fresh, D, "bf16x6") == 3 and ntu.ntu_get_env_ksplit(fresh, 4, "bf16x3") == 2
     with pytest.raises(RuntimeError):
         ntu.ntu_tune_env(ctx, q(QX), q(QY), nb, "f64", D=D)
-    # FP16x3 tunes the same launch parameter
+    # FP16x3 tunes the K split and the width of the assembly's output tiles
     ks, ms = ntu.ntu_tune_env(ctx, q(QX), q(QY), nb, "fp16x3", D=D)
     assert ks >= 1 and ntu.ntu_get_env_ksplit(ctx, D, "fp16x3") == ks
+    assert ntu.ntu_get_env_tile(ctx, D, "fp16x3") in (128, 256)
     g = to_np(ntu.ntu_env_contract(ctx, q(QX), q(QY), nb, "fp16x3"))
     for i in range(2):
         assert rel(g[i], go) < 1e-6, i
+    for w in (128, 256, 0):
+        for k in (1, 3):
+            ntu.ntu_set_env_ksplit(ctx, D, "fp16x3", k)
+            ntu.ntu_set_env_tile(ctx, D, "fp16x3", w)
+            assert ntu.ntu_get_env_tile(ctx, D, "fp16x3") == w
+            g = to_np(ntu.ntu_env_contract(ctx, q(QX), q(QY), nb, "fp16x3"))
+            for i in range(2):
+                assert rel(g[i], go) < 1e-6, (w, k, i)
+    ntu.ntu_set_env_tile(ctx, D, "fp16x3", 256)
+    ntu.ntu_tune_save(ctx, path)
+    fresh = _ctx(max_D=D)
+    ntu.ntu_tune_load(fresh, path)
+    assert ntu.ntu_get_env_tile(fresh, D, "fp16x3") == 256 and ntu.ntu_get_env_ksplit(fresh, D, "fp16x3") == 3
+    for bad in (("bf16x6", 256), ("fp16x3", 64)):
+        with pytest.raises(RuntimeError):
+            ntu.ntu_set_env_tile(ctx, D, *bad)
+    (tmp_path / "bad.txt").write_text("5 2 2 100\n")
+    with pytest.raises(RuntimeError):
+        ntu.ntu_tune_load(fresh, tmp_path / "bad.txt")
 
 
 # ------------------------------------------------------------------ metric fix
