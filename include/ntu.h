@@ -407,7 +407,7 @@ const char* ntu_profile_kind_name(int kind);
  * singular vectors of rho, the half-system density matrix of the 2 x 2 block
  * around the cut.  Starting boundary: bond dimension 1 with the ket-bra
  * identity on the inner legs.  Computation in complex128 on the GPU (one
- * workgroup per cut for the singular vectors: chi D^2 <= 256).
+ * workgroup per cut for the singular vectors: chi D^2 <= 1024).
  *
  * ntu_ctm_create: for physical dimension p (the full site index: d, d times
  * the ancilla, or the 4 basis operators of the Hermitian purification), bond

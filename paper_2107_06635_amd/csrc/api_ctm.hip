@@ -200,7 +200,12 @@ Tn contract(ntu_ctm* c, Err& E, const char* spec, const Tn& A, bool cA, const Tn
   return permute(c, E, C, po, false);
 }
 
-void normalise(ntu_ctm* c, Err& E, Tn& t) { E.set(ntu::ctm_normalise(t.p, t.n(), c->norm_slot, c->stream), "norm"); }
+// every launch below is skipped once an error is recorded: a failed step
+// leaves empty tensors (no data) behind it
+void normalise(ntu_ctm* c, Err& E, Tn& t) {
+  if (E.e != hipSuccess || !t.p) return;
+  E.set(ntu::ctm_normalise(t.p, t.n(), c->norm_slot, c->stream), "norm");
+}
 
 // copy a temporary into a pool slot
 Tn keep(ntu_ctm* c, Err& E, const Tn& t, int* slot) {
@@ -402,11 +407,15 @@ void init_state(ntu_ctm* c, Err& E, const ntu_tensor* A, const ntu_tensor* B, bo
       for (int y = 0; y < 2; ++y) {
         EnvT& en = c->env[x][y];
         int* sl = c->env_slot[x][y];
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 4 && E.e == hipSuccess; ++k) {
           sl[k] = slot_get(c);
+          sl[4 + k] = slot_get(c);
+          if (sl[k] < 0 || sl[4 + k] < 0) {
+            E.set(hipErrorOutOfMemory, "ctm pool");
+            break;
+          }
           en.C[k] = shaped(slot_ptr(c, sl[k]), {1, 1});
           E.set(hipMemcpyAsync(en.C[k].p, one.data(), sizeof(cd), hipMemcpyHostToDevice, c->stream), "init");
-          sl[4 + k] = slot_get(c);
           en.T[k] = shaped(slot_ptr(c, sl[4 + k]), {1, 1, D * D});
           E.set(hipMemcpyAsync(en.T[k].p, e.data(), sizeof(cd) * D * D, hipMemcpyHostToDevice, c->stream), "init");
         }
@@ -516,9 +525,14 @@ ntu_status ntu_ctm_create(ntu_ctm** out, int device, int p, int D, int chi) {
   // in flight during a rotation
   c->slot_el = std::max<long long>({(long long)chi * chi * D2, D2 * D2 * D2 * D2, 64});
   c->nslot = 96;
-  // arena: the largest temporaries of a move or an evaluation
-  c->arena_el = std::max<long long>(1 << 20, 16 * N * N * std::max<long long>(D2, 4) + 8 * D2 * D2 * D2 * D2 +
-                                                 8 * (long long)p * D2 * D2);
+  // arena: the temporaries of a column of a move (the cut matrices and
+  // corners of both cuts, the isometries and SVD scratch, the absorbed edges:
+  // terms of chi^2 D^6 and chi^2 D^4) or of an evaluation; the sum below
+  // covers the peak of the allocation sequence with a third to spare for
+  // D = 1..8 and chi D^2 up to 1024
+  const long long cc = (long long)chi * chi;
+  c->arena_el = std::max<long long>(1 << 20, 10 * cc * D2 * D2 * D2 + 64 * cc * D2 * D2 + 2 * N * N +
+                                                 8 * D2 * D2 * D2 * D2 + 8 * (long long)p * D2 * D2);
   hipError_t e = hipMalloc((void**)&c->pool, sizeof(cd) * c->slot_el * c->nslot);
   if (e == hipSuccess) e = hipMalloc((void**)&c->arena, sizeof(cd) * c->arena_el);
   if (e == hipSuccess) e = hipMalloc((void**)&c->norm_slot, 256);
@@ -568,9 +582,12 @@ ntu_status ntu_ctm_run(ntu_ctm* c, const ntu_tensor* A, const ntu_tensor* B, int
   for (int it = 0; it < n_iter && E.e == hipSuccess; ++it)
     for (int m = 0; m < 4 && E.e == hipSuccess; ++m) {
       left_move(c, E);
-      rotate(c, E);
+      if (E.e == hipSuccess) rotate(c, E);
     }
-  if (E.e != hipSuccess) return cfail(c, NTU_ERR_HIP, "ctm_run (" + E.what + "): " + hipGetErrorString(E.e));
+  if (E.e != hipSuccess) {
+    c->have_env = false;  // a move may be half done: the next run starts afresh
+    return cfail(c, NTU_ERR_HIP, "ctm_run (" + E.what + "): " + hipGetErrorString(E.e));
+  }
   return NTU_OK;
 }
 
@@ -612,6 +629,7 @@ ntu_status ntu_ctm_expect(ntu_ctm* c, const ntu_tensor* A, const ntu_tensor* B, 
   cd* den2 = den1 + 32;
   cd* term = den2 + 4;
   auto put = [&](const Tn& v, cd* dst) {
+    if (E.e != hipSuccess || !v.p) return;
     E.set(hipMemcpyAsync(dst, v.p, sizeof(cd), hipMemcpyDeviceToDevice, c->stream), "copy");
   };
   const cd* o1 = (const cd*)ops1->data;
@@ -655,10 +673,13 @@ ntu_status ntu_ctm_expect(ntu_ctm* c, const ntu_tensor* A, const ntu_tensor* B, 
   rotate(c, E);
   rotate(c, E);
   cd* o = (cd*)out->data;
-  E.set(ntu::ctm_ratio(num1, den1, o, (int)(2 * n1), c->stream), "ratio");
-  E.set(ntu::ctm_sum_ratio(term, den2, o + 2 * n1, 4, (int)n2, c->stream), "ratio");
+  if (E.e == hipSuccess) E.set(ntu::ctm_ratio(num1, den1, o, (int)(2 * n1), c->stream), "ratio");
+  if (E.e == hipSuccess) E.set(ntu::ctm_sum_ratio(term, den2, o + 2 * n1, 4, (int)n2, c->stream), "ratio");
   for (int k = 0; k < 4; ++k) slot_put(c, sslot[k]);
-  if (E.e != hipSuccess) return cfail(c, NTU_ERR_HIP, "ctm_expect (" + E.what + "): " + hipGetErrorString(E.e));
+  if (E.e != hipSuccess) {
+    c->have_env = false;  // the turns may be half done: the next run starts afresh
+    return cfail(c, NTU_ERR_HIP, "ctm_expect (" + E.what + "): " + hipGetErrorString(E.e));
+  }
   return NTU_OK;
 }
 

@@ -29,7 +29,7 @@ hipError_t ctm_normalise(cd* x, long long n, unsigned long long* slot, hipStream
 // count (<= CTM_SVD_BATCH) independent matrices of one size in one launch.
 // ws[b]: n^2 entries of scratch when n > CTM_SVD_REG_NMAX (else unused).
 // One-sided Jacobi on rho's columns, one workgroup per matrix.
-constexpr int CTM_SVD_NMAX = 256;
+constexpr int CTM_SVD_NMAX = 1024;
 constexpr int CTM_SVD_REG_NMAX = 128;
 constexpr int CTM_SVD_BATCH = 4;
 constexpr double CTM_RANK_EPS = 1e-12;

@@ -374,8 +374,8 @@ template <int PER, int C, int ILP, int NT>
 __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k, int zs_cap) {
   extern __shared__ cd xbuf[];
   __shared__ double red[64];
-  __shared__ double nrm[CTM_SVD_NMAX];
-  __shared__ int rank_of[CTM_SVD_NMAX];
+  __shared__ double nrm[CTM_SVD_REG_NMAX];
+  __shared__ int rank_of[CTM_SVD_REG_NMAX];
   __shared__ cd rowbuf[2 * 64 * PER];
   __shared__ int cnt, pick_sh;
   const cd* __restrict__ rho = bt.rho[blockIdx.x];
@@ -603,14 +603,15 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k, i
 }
 
 // Any n <= CTM_SVD_NMAX: the columns of W (scratch, n^2 entries, column j
-// contiguous) in global memory, one wave per pair of each round-robin round.
+// contiguous) in global memory, one wave per pair of each round-robin
+// round, its rows read in chunks of 64 (once for the inner products, again
+// for the rotation: the second read hits the cache).
 __global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k) {
-  constexpr int PER = CTM_SVD_NMAX / 64;
   __shared__ double red[64];
   __shared__ double nrm[CTM_SVD_NMAX];
   __shared__ int rank_of[CTM_SVD_NMAX];
   __shared__ cd rowbuf[2][CTM_SVD_NMAX];
-  __shared__ cd part[4][CTM_SVD_NMAX];
+  __shared__ cd part[CTM_SVD_NMAX];
   __shared__ int cnt, pick_sh;
   const cd* __restrict__ rho = bt.rho[blockIdx.x];
   cd* __restrict__ Z = bt.Z[blockIdx.x];
@@ -625,9 +626,11 @@ __global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k)
   }
   fro = block_sum(fro, red);
   // the LQ factorisation of k_ctm_svd_reg on the columns in global memory:
-  // row i = j + (tid % 256) of what is left (rows above j hold zeros beyond
-  // the diagonal), columns j + g, j + g + 4, .. for g = tid / 256
-  const int ri = tid & (CTM_SVD_NMAX - 1), g4 = tid / CTM_SVD_NMAX;
+  // row i = j + (tid % RG) of what is left (rows above j hold zeros beyond
+  // the diagonal), columns j + g, j + g + G, .. for g = tid / RG: four
+  // groups of 256 rows for n <= 256, one of 1024 beyond
+  const int RG = n <= 256 ? 256 : 1024, G = (int)blockDim.x / RG;
+  const int ri = tid % RG, gq = tid / RG;
   for (int j = 0; j < n; ++j) {
     cd* const rb = rowbuf[j & 1];
     for (int c = j + tid; c < n; c += blockDim.x) rb[c] = W[(long long)c * n + j];
@@ -645,13 +648,15 @@ __global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k)
     const int i = j + ri;
     cd wp{0.0, 0.0};
     if (i < n)
-      for (int c = j + g4; c < n; c += 4) wp += W[(long long)c * n + i] * ucol(c);
-    part[g4][ri] = wp;
+      for (int c = j + gq; c < n; c += G) wp += W[(long long)c * n + i] * ucol(c);
+    part[tid] = wp;
     __syncthreads();
     if (i < n) {
-      const cd w = (part[0][ri] + part[1][ri] + part[2][ri] + part[3][ri]) * beta;
+      cd w{0.0, 0.0};
+      for (int g = 0; g < G; ++g) w += part[g * RG + ri];
+      w = w * beta;
       const cd ljj = cd{-e.x * nr, -e.y * nr};
-      for (int c = j + g4; c < n; c += 4) {
+      for (int c = j + gq; c < n; c += G) {
         cd* const at = W + (long long)c * n + i;
         *at = i == j ? (c == j ? ljj : cd{0.0, 0.0}) : *at - w * conjv(ucol(c));
       }
@@ -671,30 +676,24 @@ __global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k)
         if (q >= n) continue;
         cd* wp = W + (long long)p * n;
         cd* wq = W + (long long)q * n;
-        cd a[PER], b[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int i = lane + 64 * u;
-          a[u] = i < n ? wp[i] : cd{0.0, 0.0};
-          b[u] = i < n ? wq[i] : cd{0.0, 0.0};
+        double al = 0.0, be = 0.0;
+        cd ga{0.0, 0.0};
+        for (int i = lane; i < n; i += 64) {
+          const cd a = wp[i], b = wq[i];
+          al += abs2(a);
+          be += abs2(b);
+          ga += cmul(a, b);
         }
-        double al, be;
-        cd ga;
-        pair_gram<PER>(a, b, al, be, ga);
         al = wave_sum(al);
         be = wave_sum(be);
         ga = wave_sum(ga);
         double cs, sn, tg;
         cd em;
         if (!hestenes_params(al, be, ga, tiny, tol, cs, sn, em, tg)) continue;
-        pair_rotate<PER>(a, b, cs, sn, em);
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int i = lane + 64 * u;
-          if (i < n) {
-            wp[i] = a[u];
-            wq[i] = b[u];
-          }
+        for (int i = lane; i < n; i += 64) {
+          const cd a = wp[i], y = em * wq[i];
+          wp[i] = cs * a - sn * y;
+          wq[i] = sn * a + cs * y;
         }
         ++rot;
       }
