@@ -90,6 +90,27 @@ __global__ void __launch_bounds__(256) k_e45_scale(int n, const cd* __restrict__
 // with the operands exchanged (it computes the transposed tile), so that
 // lane l holds row 16 mt + l % 16 and the four consecutive real columns
 // 32 w + 16 y + 4 (l / 16) + v: two whole complex outputs.
+// FP16X3: the power-of-two scale of each isometry block (n x K complex
+// entries: QXe[a], QXp[a], QYe[b], QYp[b] for a, b < R), once per item, for
+// the fused kernels (each block enters R of their workgroups).  The largest
+// |re|, |im| of a block, as the workgroups would find it themselves.
+__global__ void __launch_bounds__(256) k_e45_blockscale(int n, int K, int R, const cd* __restrict__ QXe,
+                                                        const cd* __restrict__ QXp, const cd* __restrict__ QYe,
+                                                        const cd* __restrict__ QYp, long long qs,
+                                                        float* __restrict__ blk) {
+  __shared__ float red[16];
+  const int a = blockIdx.x, which = blockIdx.y, item = blockIdx.z;
+  const cd* base = which == 0 ? QXe : which == 1 ? QXp : which == 2 ? QYe : QYp;
+  const cd* Q = base + (size_t)item * qs + (size_t)a * n * K;
+  float v = 0.0f;
+  for (int e = threadIdx.x; e < n * K; e += blockDim.x) {
+    const cd z = Q[e];
+    v = fmaxf(v, fmaxf(fabsf((float)z.x), fabsf((float)z.y)));
+  }
+  v = wg_maxf(v, red);
+  if (threadIdx.x == 0) blk[((size_t)item * 4 + which) * R + a] = f16_scale(v);
+}
+
 template <int PREC, int NPAD> struct E45 {
   static constexpr int NP = SplitTraits<PREC>::NT;
   static constexpr bool F16 = PREC == NTU_PREC_FP16X3;
@@ -143,20 +164,6 @@ template <int PREC, int NPAD> struct E45 {
     for (int p = 0; p < NP; ++p) {
       typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
       f[p] = __builtin_bit_cast(V8, (u32x4){w[p][0], w[p][1], w[p][2], w[p][3]});
-    }
-  }
-
-  // FP16X3: scale of an n x K complex block (its largest |re|, |im|); 1 otherwise
-  static NTU_DEV float block_scale(const cd* __restrict__ Q, int n, int K, float* red) {
-    if constexpr (!F16) {
-      return 1.0f;
-    } else {
-      float v = 0.0f;
-      for (int e = threadIdx.x; e < n * K; e += blockDim.x) {
-        const cd z = Q[e];
-        v = fmaxf(v, fmaxf(fabsf((float)z.x), fabsf((float)z.y)));
-      }
-      return f16_scale(wg_maxf(v, red));
     }
   }
 
@@ -334,7 +341,8 @@ template <int PREC, int D, int NPAD = ((D * D + 15) / 16) * 16>
 __global__ void __launch_bounds__(NPAD * 4, 2) k_left_e45(int R, int K, int nwork, const cd* __restrict__ QXe,
                                                        const cd* __restrict__ QXp, long long qs, float* __restrict__ out,
                                                        long long hs, const typename SplitTraits<PREC>::E* __restrict__ frag,
-                                                       const float* __restrict__ escale, float* __restrict__ rowscale) {
+                                                       const float* __restrict__ escale, float* __restrict__ rowscale,
+                                                       const float* __restrict__ blk) {
   using S = E45<PREC, NPAD>;
   using E = typename S::E;
   constexpr int NP = S::NP, LD = S::LD;
@@ -362,8 +370,8 @@ __global__ void __launch_bounds__(NPAD * 4, 2) k_left_e45(int R, int K, int nwor
   // FP16X3 scales; tot: the factor the values in acc carry
   float se = 1.0f, sp = 1.0f, tot = 1.0f, sn = 1.0f;
   if constexpr (F16) {
-    se = S::block_scale(Qe, n, K, red);
-    sp = S::block_scale(Qp, n, K, red);
+    se = blk[((size_t)item * 4 + 0) * R + a];
+    sp = blk[((size_t)item * 4 + 1) * R + ap];
   }
   S::pair_product(acc, Qe, Qp, n, K, w, lane, se, sp);
   if constexpr (F16) {
@@ -420,7 +428,8 @@ __global__ void __launch_bounds__(NPAD * 4, 2) k_left_e45(int R, int K, int nwor
 template <int PREC, int D, int NPAD = ((D * D + 15) / 16) * 16>
 __global__ void __launch_bounds__(NPAD * 4, 2) k_right(int R, int K, int nwork, const cd* __restrict__ QYe,
                                                     const cd* __restrict__ QYp, long long qs, float* __restrict__ out,
-                                                    long long hs, float* __restrict__ rowscale) {
+                                                    long long hs, float* __restrict__ rowscale,
+                                                    const float* __restrict__ blk) {
   using S = E45<PREC, NPAD>;
   __shared__ __attribute__((aligned(16))) float2 st[NPAD * NPAD];
   __shared__ float red[16];
@@ -435,8 +444,8 @@ __global__ void __launch_bounds__(NPAD * 4, 2) k_right(int R, int K, int nwork, 
   typename S::Acc acc;
   float se = 1.0f, sp = 1.0f, sn = 1.0f;
   if constexpr (S::F16) {
-    se = S::block_scale(Qe, n, K, red);
-    sp = S::block_scale(Qp, n, K, red);
+    se = blk[((size_t)item * 4 + 2) * R + b];
+    sp = blk[((size_t)item * 4 + 3) * R + bp];
   }
   S::pair_product(acc, Qe, Qp, n, K, w, lane, se, sp);
   if constexpr (S::F16) sn = S::acc_scale(acc, red);
@@ -469,17 +478,21 @@ size_t e45_frag_bytes(int precision, int batch, int D) {
 }
 
 // FP16X3 scales after the prepared fragments in H1: per item the two
-// operand scales of EtopT / EbotT, then the row scales of L2 and of Right
+// operand scales of EtopT / EbotT, then the row scales of L2 and of Right,
+// then the scales of the isometry blocks
 E45Scales e45_scales(void* H1, int precision, int batch, int D, int R) {
   E45Scales sc;
   float* base = (float*)((char*)H1 + ((e45_frag_bytes(precision, batch, D) + 255) / 256) * 256);
   sc.e = base;
   sc.left = base + 2 * (size_t)batch;
   sc.right = sc.left + (size_t)batch * R * R;
+  sc.blk = sc.right + (size_t)batch * R * R;
   return sc;
 }
 
-size_t e45_scale_bytes(int batch, int R) { return (2 + 2 * (size_t)R * R) * batch * sizeof(float) + 256; }
+size_t e45_scale_bytes(int batch, int R) {
+  return (2 + 2 * (size_t)R * R + 4 * (size_t)R) * batch * sizeof(float) + 256;
+}
 
 template <int PREC, int D>
 static void fused_launch(int batch, int p, int R, const cd* QXe, const cd* QXp, const cd* QYe, const cd* QYp,
@@ -490,11 +503,14 @@ static void fused_launch(int batch, int p, int R, const cd* QXe, const cd* QXp, 
   const int nwork = batch * R * R;
   const dim3 g(8 * ((nwork + 7) / 8)), b(NPAD * 4);
   ph(PK_LEFTRIGHT, 0);
-  hipLaunchKernelGGL((k_right<PREC, D>), g, b, 0, st, R, p * D, nwork, QYe, QYp, qs, Right, hs, sc.right);
+  if (PREC == NTU_PREC_FP16X3)
+    hipLaunchKernelGGL(k_e45_blockscale, dim3(R, 4, batch), dim3(256), 0, st, D * D, p * D, R, QXe, QXp, QYe, QYp, qs,
+                       sc.blk);
+  hipLaunchKernelGGL((k_right<PREC, D>), g, b, 0, st, R, p * D, nwork, QYe, QYp, qs, Right, hs, sc.right, sc.blk);
   ph(PK_LEFTRIGHT, 1);
   ph(PK_E4, 0);
   hipLaunchKernelGGL((k_left_e45<PREC, D>), g, b, 0, st, R, p * D, nwork, QXe, QXp, qs, L2, hs, frag, sc.e,
-                     sc.left);
+                     sc.left, sc.blk);
   ph(PK_E4, 1);
 }
 

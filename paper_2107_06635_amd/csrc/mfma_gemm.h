@@ -38,6 +38,7 @@ struct E45Scales {
   float* e;
   float* left;
   float* right;
+  float* blk;  // per item the scales of the isometry blocks QXe[a], QXp[a], QYe[b], QYp[b] (4 R)
 };
 E45Scales e45_scales(void* H1, int precision, int batch, int D, int R);
 size_t e45_scale_bytes(int batch, int R);
