@@ -91,6 +91,29 @@ def test_cell_8x6_groups_match_oracle(precision, tol):
         assert np.abs(st[k, s0:s0 + D] - info['S']).max() <= tol, (k, st[k, s0:s0 + D], info['S'])
 
 
+def test_cell_svdu_sweep_matches_oracle():
+    """The SVDU scheme through the cell sweep (no environment): a 4 x 3 cell
+    at D = 2 after one sweep of all bonds, by the torus state vector (1e-9
+    after phase and norm)."""
+    rng = np.random.default_rng(83)
+    Lx, Ly, D = 4, 3, 2
+    T = _cell(rng, Lx, Ly, D)
+    bonds = inputs.cell_bond_order(Lx, Ly)
+    gates = _gates(rng, len(bonds), 0.05)
+    ctx = ntu.Context(complex_=True, d=2, d_anc=1, r_g=2, max_D=D, max_batch=8)
+    Tt = to_dev(np.stack([T[(x, y)] for y in range(Ly) for x in range(Lx)]))
+    gf = to_dev(np.stack([np.stack([a, b]) for a, b in gates]))
+    ntu.ntu_cell_step(ctx, Lx, Ly, Tt, bonds, gf, ntu.step_opts("f64", scheme="svdu"))
+    Tn = to_np(Tt)
+    Tg = {(x, y): Tn[x + Lx * y] for y in range(Ly) for x in range(Lx)}
+    To, _ = CE.cell_sweep(T, Lx, Ly, bonds, gates, D, scheme='svdu')
+    pg, po = _torus_vector(Tg, Lx, Ly), _torus_vector(To, Lx, Ly)
+    pg, po = pg / np.linalg.norm(pg), po / np.linalg.norm(po)
+    ph = np.vdot(pg, po)
+    ph /= abs(ph)
+    assert np.linalg.norm(pg * ph - po) < 1e-9
+
+
 def test_cell_errors_before_anything_runs():
     """Refused before any launch, the cell untouched: a cell of one column,
     a bond outside the cell, an unknown direction, a short work array, gate

@@ -7,9 +7,11 @@ import torch
 
 from oracle import ctmrg as C
 from oracle import evolve as EV
+from oracle import hermitian as H
 from oracle import ntu as O
 from paper_2107_06635_amd import inputs, ntu
 from tests.gpu_util import to_dev, to_np
+from tests.test_oracle_ctmrg import onsager_nn
 
 pytestmark = pytest.mark.gpu
 
@@ -80,6 +82,34 @@ def test_critical_quench_energy_stop_matches_oracle():
         assert np.abs(hist[m, 4:] - rec['bonds']).max() < 1e-8, (s, hist[m, 4:], rec['bonds'])
         assert abs(e[m] - rec['energy']) < 1e-8
     assert abs(e[-1] - e[0]) > 0.011 and abs(e[-2] - e[0]) < 0.009
+    ctm.close()
+
+
+def test_hermitian_purification_run_is_onsager():
+    """The run on a real state: the Hermitian purification (d^2 = 4, R = 4 D)
+    at h_x = 0, D = 2 (exact), dbeta = 0.05, six steps measured every two at
+    chi = 16 after 40 iterations, the bond operator the anticommutator matrix
+    of ZZ: <ZZ> on every bond is Onsager's value at K = beta (0.1, 0.2, 0.3),
+    0 at beta = 0."""
+    D, dbeta = 2, 0.05
+    w = inputs.workload_hermitian_thermal(D=D, hx=0.0, hz=0.0, dbeta=dbeta)
+    GA, GB, _ = H.gate_factors(w['gate'])
+    ctx = ntu.Context(complex_=False, d=4, d_anc=1, r_g=4, max_D=D, max_batch=1)
+    ctm = ntu.CTM(4, D, 16)
+    gf = to_dev(np.stack([np.stack([GA, GB])] * 4)[None])
+    ops = H.ctmrg_ops()
+    At, Bt = to_dev(w['A'][None]), to_dev(w['B'][None])
+    step = ntu.step_opts("f64", n_iter=3)
+    hist, e, steps = ntu.ntu_evolve(ctx, ctm, At, Bt, gf, step, 6, 2, 40,
+                                    to_dev(np.stack([ops['X'], ops['Z']]).astype(complex)),
+                                    to_dev(_terms(ops['ZZ'], 4)), energy_tol=0.0)
+    hist = to_np(hist)
+    assert steps == 6 and hist.shape[0] == 4
+    assert np.abs(hist[0, 4:]).max() < 1e-12
+    for m in range(1, 4):
+        want = onsager_nn(2 * m * dbeta)
+        assert np.abs(hist[m, 4:] - want).max() < 1e-10, (m, hist[m, 4:], want)
+        assert abs(e[m] - 2 * want) < 1e-9
     ctm.close()
 
 
