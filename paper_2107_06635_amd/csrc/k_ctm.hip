@@ -168,13 +168,15 @@ constexpr int SVD_SWEEPS = 40;
 // product: w_p <- c w_p - s y, w_q <- s w_p + c y.  False: nothing to do.
 NTU_DEV bool hestenes_params(double al, double be, cd ga, double tiny, double tol, double& c, double& s, cd& em,
                              double& tg) {
-  const double g = absv(ga);
-  if (!(g > tiny) || !(g > tol * sqrt(al * be))) return false;
-  const double zeta = (be - al) / (2.0 * g);
+  // the tests on squares (g^2 against tiny^2 and tol^2 al be): one square
+  // root fewer per pair; the values here are far from the overflow range
+  const double g2 = abs2(ga);
+  if (!(g2 > tiny * tiny) || !(g2 > tol * tol * al * be)) return false;
+  const double g = sqrt(g2), ig = 1.0 / g;
+  const double zeta = 0.5 * (be - al) * ig;
   const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   c = 1.0 / sqrt(1.0 + t * t);
   s = c * t;
-  const double ig = 1.0 / g;
   em = cd{ga.x * ig, -ga.y * ig};
   tg = t * g;  // |w_p|^2 falls and |w_q|^2 rises by t |ga|
   return true;
