@@ -411,8 +411,15 @@ const char* ntu_profile_kind_name(int kind);
  *
  * ntu_ctm_create: for physical dimension p (the full site index: d, d times
  * the ancilla, or the 4 basis operators of the Hermitian purification), bond
- * dimension D <= 8 and environment dimension chi; allocates its device
- * memory.  NTU_ERR_SHAPE outside those limits.
+ * dimension D <= 8 and environment dimension chi (chi D^2 <= 1024);
+ * allocates its device memory once: 96 tensors of max(chi^2 D^2, D^8)
+ * complex entries and a scratch arena of
+ * 10 chi^2 D^6 + 64 chi^2 D^4 + 2 (chi D^2)^2 + 8 D^8 + 8 p D^4 entries
+ * (16 bytes each; e.g. 0.2 GB at D = 2, chi = 80, 40 GB at D = 8, chi = 16).
+ * NTU_ERR_SHAPE outside those limits, NTU_ERR_HIP if the memory is not
+ * there.  After an error of ntu_ctm_run or ntu_ctm_expect the environment
+ * is dropped: the next ntu_ctm_run starts from the boundary and
+ * ntu_ctm_expect returns NTU_ERR_ARG until then.
  * ntu_ctm_run: n_iter iterations for the state A, B ((p, D, D, D, D),
  * NTU_F64 or NTU_C128, device) from the starting boundary (reset != 0, or
  * the first call) or from the environment of the previous call.
