@@ -92,7 +92,7 @@ def test_quench_closed_form():
     assert abs(g['xA'] - np.cos(2 * t) ** 4) < 1e-11 and abs(g['xB'] - np.cos(2 * t) ** 4) < 1e-11
 
 
-@pytest.mark.parametrize("D, steps, chi", [(3, 4, 12), (2, 6, 16), (2, 6, 8), (3, 4, 16)])
+@pytest.mark.parametrize("D, steps, chi", [(3, 4, 12), (2, 6, 16), (2, 6, 8), (3, 4, 16), (4, 3, 16)])
 def test_ntu_quench_state(D, steps, chi):
     """A state of the configuration-2 quench (h_x = 3.04438, dt = 0.05,
     random start, A != B) after some NTU sweeps of the oracle, at chi = 4 D
