@@ -271,7 +271,7 @@ void cut_isometries(ntu_ctm* c, Err& E, int x, Tn Z[2]) {
     int zs[2] = {n, k};
     Z[y] = alloc(c, E, zs, 2);
     if (n > ntu::CTM_SVD_REG_NMAX) {
-      ws[y] = arena_get(c, (long long)n * n);
+      ws[y] = arena_get(c, (long long)n * n + ntu::CTM_SVD_WS_EXTRA);
       if (!ws[y]) E.set(hipErrorOutOfMemory, "ctm arena");
     }
   }

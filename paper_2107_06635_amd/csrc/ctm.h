@@ -27,12 +27,14 @@ hipError_t ctm_normalise(cd* x, long long n, unsigned long long* slot, hipStream
 // e_1, .. in order, each orthogonalised twice against the columns before it
 // and kept when more than half its length is left;
 // count (<= CTM_SVD_BATCH) independent matrices of one size in one launch.
-// ws[b]: n^2 entries of scratch when n > CTM_SVD_REG_NMAX (else unused).
+// ws[b]: CTM_SVD_WS_EXTRA + n^2 entries of scratch when n > CTM_SVD_REG_NMAX
+// (else unused).
 // One-sided Jacobi on rho's columns, one workgroup per matrix.
 constexpr int CTM_SVD_NMAX = 1024;
 constexpr int CTM_SVD_REG_NMAX = 128;
 constexpr int CTM_SVD_BATCH = 4;
 constexpr double CTM_RANK_EPS = 1e-12;
+constexpr int CTM_SVD_WS_EXTRA = 64;  // entries beyond n^2: rotation counts and a norm
 hipError_t ctm_svd_left(int count, const cd* const* rho, int n, int k, cd* const* Z, cd* const* ws, hipStream_t st);
 // out[i] = num[i] / den[i], n entries
 hipError_t ctm_ratio(const cd* num, const cd* den, cd* out, int n, hipStream_t st);

@@ -157,7 +157,7 @@ hipError_t ctm_normalise(cd* x, long long n, unsigned long long* slot, hipStream
 // of an n-term inner product, so a sweep with no rotation does come), or
 // below (1e-15 ||rho||_F)^2.  Gram-Schmidt twice over the chosen columns,
 // with unit vectors taking the place of columns beyond the numerical rank
-// (norm at most CTM_RANK_EPS sigma_1), makes Z orthonormal.  One workgroup of 1024 per matrix.
+// (norm at most CTM_RANK_EPS sigma_1), makes Z orthonormal.
 
 constexpr int SVD_SWEEPS = 40;
 
@@ -241,27 +241,29 @@ NTU_DEV void svd_orthonormalise(cd* Z, int n, int k, double* red, int* pick_sh) 
   }
 }
 
-// The same Gram-Schmidt by one wave on Z held in LDS (column c at
-// zs + c * ld, row i at i; n <= 64 PER): no barriers, the column being
+// The same Gram-Schmidt by one wave: entry (i, c) of Z at zs + i srow +
+// c scol (LDS or global memory; n <= 64 PER); no barriers, the column being
 // orthogonalised kept in registers.
-template <int PER> NTU_DEV void svd_orthonormalise_wave(cd* zs, int ld, int n, int k) {
+template <int PER>
+NTU_DEV void svd_orthonormalise_wave(cd* zs, long long srow, long long scol, int n, int k) {
   const int lane = threadIdx.x & 63;
+  auto at = [&](int i, int c) -> cd& { return zs[(long long)i * srow + (long long)c * scol]; };
   int next_unit = 0;
   for (int col = 0; col < k; ++col) {
     cd zc[PER];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) zc[u] = lane + 64 * u < n ? zs[col * ld + lane + 64 * u] : cd{0.0, 0.0};
+    for (int u = 0; u < PER; ++u) zc[u] = lane + 64 * u < n ? at(lane + 64 * u, col) : cd{0.0, 0.0};
     for (int attempt = 0; attempt <= n; ++attempt) {
       for (int pass = 0; pass < 2; ++pass)
         for (int b = 0; b < col; ++b) {
           cd dot{0.0, 0.0};
 #pragma unroll
           for (int u = 0; u < PER; ++u)
-            if (lane + 64 * u < n) dot += cmul(zs[b * ld + lane + 64 * u], zc[u]);
+            if (lane + 64 * u < n) dot += cmul(at(lane + 64 * u, b), zc[u]);
           dot = wave_sum(dot);
 #pragma unroll
           for (int u = 0; u < PER; ++u)
-            if (lane + 64 * u < n) zc[u] = zc[u] - dot * zs[b * ld + lane + 64 * u];
+            if (lane + 64 * u < n) zc[u] = zc[u] - dot * at(lane + 64 * u, b);
         }
       double nn = 0.0;
 #pragma unroll
@@ -279,7 +281,7 @@ template <int PER> NTU_DEV void svd_orthonormalise_wave(cd* zs, int ld, int n, i
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u)
-      if (lane + 64 * u < n) zs[col * ld + lane + 64 * u] = zc[u];
+      if (lane + 64 * u < n) at(lane + 64 * u, col) = zc[u];
   }
 }
 
@@ -593,7 +595,7 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k, i
       }
   __syncthreads();
   if (in_lds) {
-    if (wave == 0) svd_orthonormalise_wave<PER>(xbuf, LD, n, k);
+    if (wave == 0) svd_orthonormalise_wave<PER>(xbuf, 1, LD, n, k);
     __syncthreads();
     for (int e = tid; e < n * k; e += blockDim.x) {
       const int i = e / k, c = e % k;
@@ -604,21 +606,44 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k, i
   }
 }
 
-// Any n <= CTM_SVD_NMAX: the columns of W (scratch, n^2 entries, column j
-// contiguous) in global memory, one wave per pair of each round-robin
-// round, its rows read in chunks of 64 (once for the inner products, again
-// for the rotation: the second read hits the cache).
-__global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k) {
+// n > CTM_SVD_REG_NMAX: three kinds of launches on the columns of W in
+// global memory (scratch ws[b]: W, n^2 entries with column j contiguous,
+// then the rotation counts of the sweeps and ||rho||_F^2):
+//   k_ctm_svd_lq     one workgroup per matrix: W = rho, then the LQ
+//                    factorisation of k_ctm_svd_reg (the columns of L);
+//   k_ctm_svd_round  one round of the round-robin order on blocks of
+//                    SVD_MB columns, one workgroup per pair of blocks (all
+//                    pairs across them, and at the sweep's first round the
+//                    pairs inside them), one wave per column pair at a time;
+//                    a sweep's rounds return at once when the sweep before
+//                    made no rotation;
+//   k_ctm_svd_final  one workgroup per matrix: norms, order, Z, and the
+//                    Gram-Schmidt of one wave.
+constexpr int SVD_MB = 16;                 // columns per block (one wave each)
+constexpr int SVD_SWEEPS_MULTI = 24;       // sweeps launched (most end early)
+
+struct SvdMemWs {
+  cd* W;
+  int* rot;      // rotations made in each sweep
+  double* fro;   // ||rho||_F^2
+};
+NTU_DEV SvdMemWs svd_mem_ws(cd* base, int n) {
+  SvdMemWs w;
+  w.W = base;
+  w.rot = (int*)(base + (long long)n * n);
+  w.fro = (double*)(w.rot + 2 * SVD_SWEEPS_MULTI);
+  return w;
+}
+
+__global__ void __launch_bounds__(1024) k_ctm_svd_lq(SvdBatch bt, int n) {
   __shared__ double red[64];
-  __shared__ double nrm[CTM_SVD_NMAX];
-  __shared__ int rank_of[CTM_SVD_NMAX];
   __shared__ cd rowbuf[2][CTM_SVD_NMAX];
   __shared__ cd part[CTM_SVD_NMAX];
-  __shared__ int cnt, pick_sh;
   const cd* __restrict__ rho = bt.rho[blockIdx.x];
-  cd* __restrict__ Z = bt.Z[blockIdx.x];
-  cd* __restrict__ W = bt.W[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+  const SvdMemWs ws = svd_mem_ws(bt.W[blockIdx.x], n);
+  cd* __restrict__ W = ws.W;
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < SVD_SWEEPS_MULTI) ws.rot[tid] = 0;
   double fro = 0.0;
   for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
     const int i = (int)(e / n), j = (int)(e % n);
@@ -627,6 +652,7 @@ __global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k)
     fro += abs2(v);
   }
   fro = block_sum(fro, red);
+  if (tid == 0) *ws.fro = fro;
   // the LQ factorisation of k_ctm_svd_reg on the columns in global memory:
   // row i = j + (tid % RG) of what is left (rows above j hold zeros beyond
   // the diagonal), columns j + g, j + g + G, .. for g = tid / RG: four
@@ -665,48 +691,78 @@ __global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k)
     }
     __syncthreads();  // the next row is read from what this step wrote
   }
+}
+
+// one pair of columns by one wave, rows in chunks of 64 (read once for the
+// inner products, again for the rotation); returns 1 when it rotated
+NTU_DEV int svd_mem_pair(cd* W, int n, int p, int q, double tiny, double tol) {
+  const int lane = threadIdx.x & 63;
+  if (p >= n || q >= n) return 0;
+  cd* wp = W + (long long)p * n;
+  cd* wq = W + (long long)q * n;
+  double al = 0.0, be = 0.0;
+  cd ga{0.0, 0.0};
+  for (int i = lane; i < n; i += 64) {
+    const cd a = wp[i], b = wq[i];
+    al += abs2(a);
+    be += abs2(b);
+    ga += cmul(a, b);
+  }
+  al = wave_sum(al);
+  be = wave_sum(be);
+  ga = wave_sum(ga);
+  double cs, sn, tg;
+  cd em;
+  if (!hestenes_params(al, be, ga, tiny, tol, cs, sn, em, tg)) return 0;
+  for (int i = lane; i < n; i += 64) {
+    const cd a = wp[i], y = em * wq[i];
+    wp[i] = cs * a - sn * y;
+    wq[i] = sn * a + cs * y;
+  }
+  return 1;
+}
+
+__global__ void __launch_bounds__(64 * SVD_MB) k_ctm_svd_round(SvdBatch bt, int n, int nb, int sweep, int r) {
+  const SvdMemWs ws = svd_mem_ws(bt.W[blockIdx.y], n);
+  if (sweep > 0 && ws.rot[sweep - 1] == 0) return;  // converged
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int P, Q;
+  rr_pair(nb, r, blockIdx.x, P, Q);
+  const double fro = *ws.fro;
   const double tiny = 1e-30 * fro, tol = 4.0 * 2.220446049250313e-16 * sqrt((double)n);
-  const int n2 = (n + 1) & ~1, np = n2 / 2;
-  for (int sweep = 0; sweep < SVD_SWEEPS; ++sweep) {
-    if (tid == 0) cnt = 0;
-    __syncthreads();
-    int rot = 0;
-    for (int r = 0; r < n2 - 1; ++r) {
-      for (int kp = wave; kp < np; kp += nwave) {
-        int p, q;
-        rr_pair(n2, r, kp, p, q);
-        if (q >= n) continue;
-        cd* wp = W + (long long)p * n;
-        cd* wq = W + (long long)q * n;
-        double al = 0.0, be = 0.0;
-        cd ga{0.0, 0.0};
-        for (int i = lane; i < n; i += 64) {
-          const cd a = wp[i], b = wq[i];
-          al += abs2(a);
-          be += abs2(b);
-          ga += cmul(a, b);
-        }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        double cs, sn, tg;
-        cd em;
-        if (!hestenes_params(al, be, ga, tiny, tol, cs, sn, em, tg)) continue;
-        for (int i = lane; i < n; i += 64) {
-          const cd a = wp[i], y = em * wq[i];
-          wp[i] = cs * a - sn * y;
-          wq[i] = sn * a + cs * y;
-        }
-        ++rot;
-      }
+  int rot = 0;
+  if (r == 0) {
+    // pairs inside each block: circle method on its SVD_MB columns (the
+    // first fixed), SVD_MB / 2 pairs per block a step, one per wave
+    for (int t = 0; t < SVD_MB - 1; ++t) {
+      const int h = wave / (SVD_MB / 2), k = wave % (SVD_MB / 2);
+      auto pos = [&](int slot) {
+        if (slot == 0) return 0;
+        const int x = slot - 1 + t;
+        return 1 + (x >= SVD_MB - 1 ? x - (SVD_MB - 1) : x);
+      };
+      const int B = h == 0 ? P : Q;
+      rot += svd_mem_pair(ws.W, n, B * SVD_MB + pos(k), B * SVD_MB + pos(SVD_MB - 1 - k), tiny, tol);
       __syncthreads();
     }
-    if (rot && lane == 0) atomicAdd(&cnt, rot);
-    __syncthreads();
-    const int done = cnt == 0;
-    __syncthreads();
-    if (done) break;
   }
+  // pairs across the blocks: column i of P with column (i + sh) of Q
+  for (int sh = 0; sh < SVD_MB; ++sh) {
+    rot += svd_mem_pair(ws.W, n, P * SVD_MB + wave, Q * SVD_MB + (wave + sh) % SVD_MB, tiny, tol);
+    __syncthreads();
+  }
+  if (rot && lane == 0) atomicAdd(&ws.rot[sweep], rot);
+}
+
+// 256 threads: the Gram-Schmidt wave keeps a column of up to 1024 rows in
+// registers (a wave per SIMD leaves it room)
+__global__ void __launch_bounds__(256) k_ctm_svd_final(SvdBatch bt, int n, int k) {
+  __shared__ double nrm[CTM_SVD_NMAX];
+  __shared__ int rank_of[CTM_SVD_NMAX];
+  cd* __restrict__ Z = bt.Z[blockIdx.x];
+  const SvdMemWs ws = svd_mem_ws(bt.W[blockIdx.x], n);
+  const cd* __restrict__ W = ws.W;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
   for (int j = wave; j < n; j += nwave) {
     double v = 0.0;
     for (int i = lane; i < n; i += 64) v += abs2(W[(long long)j * n + i]);
@@ -721,7 +777,7 @@ __global__ void __launch_bounds__(1024) k_ctm_svd_mem(SvdBatch bt, int n, int k)
     if (rk < k) Z[(long long)i * k + rk] = nrm[j] > floor_nrm ? W[e] * (1.0 / nrm[j]) : cd{0.0, 0.0};
   }
   __syncthreads();
-  svd_orthonormalise(Z, n, k, red, &pick_sh);
+  if (wave == 0) svd_orthonormalise_wave<CTM_SVD_NMAX / 64>(Z, k, 1, n, k);
 }
 
 // one workgroup of NT threads per matrix: n <= 2 C (NT / 64) (two blocks
@@ -760,9 +816,16 @@ hipError_t ctm_svd_left(int count, const cd* const* rho, int n, int k, cd* const
   }
   if (n <= 64) return launch_svd_reg<1, 2, 2, 1024>(bt, count, n, k, st);
   if (n <= CTM_SVD_REG_NMAX) return launch_svd_reg<2, 8, 4, 512>(bt, count, n, k, st);
-  {
-    hipLaunchKernelGGL(k_ctm_svd_mem, dim3(count), dim3(1024), 0, st, bt, n, k);
-  }
+  const int nblk = (n + SVD_MB - 1) / SVD_MB, nb = nblk + (nblk & 1);
+  hipLaunchKernelGGL(k_ctm_svd_lq, dim3(count), dim3(1024), 0, st, bt, n);
+  hipError_t e = hipGetLastError();
+  for (int sweep = 0; sweep < SVD_SWEEPS_MULTI && e == hipSuccess; ++sweep)
+    for (int r = 0; r < nb - 1 && e == hipSuccess; ++r) {
+      hipLaunchKernelGGL(k_ctm_svd_round, dim3(nb / 2, count), dim3(64 * SVD_MB), 0, st, bt, n, nb, sweep, r);
+      e = hipGetLastError();
+    }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ctm_svd_final, dim3(count), dim3(256), 0, st, bt, n, k);
   return hipGetLastError();
 }
 
