@@ -619,8 +619,9 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k, i
 //                    made no rotation;
 //   k_ctm_svd_final  one workgroup per matrix: norms, order, Z, and the
 //                    Gram-Schmidt of one wave.
-constexpr int SVD_MB = 16;                 // columns per block (one wave each)
-constexpr int SVD_SWEEPS_MULTI = 24;       // sweeps launched (most end early)
+constexpr int SVD_MB = 8;                  // columns per block (one wave each)
+constexpr int SVD_SWEEPS_MULTI = 24;       // at most this many sweeps
+constexpr int SVD_SWEEPS_FIRST = 8;        // sweeps launched before the first look at the counts
 
 struct SvdMemWs {
   cd* W;
@@ -695,11 +696,9 @@ __global__ void __launch_bounds__(1024) k_ctm_svd_lq(SvdBatch bt, int n) {
 
 // one pair of columns by one wave, rows in chunks of 64 (read once for the
 // inner products, again for the rotation); returns 1 when it rotated
-NTU_DEV int svd_mem_pair(cd* W, int n, int p, int q, double tiny, double tol) {
+NTU_DEV int svd_mem_pair(cd* wp, cd* wq, int n, bool valid, double tiny, double tol) {
   const int lane = threadIdx.x & 63;
-  if (p >= n || q >= n) return 0;
-  cd* wp = W + (long long)p * n;
-  cd* wq = W + (long long)q * n;
+  if (!valid) return 0;
   double al = 0.0, be = 0.0;
   cd ga{0.0, 0.0};
   for (int i = lane; i < n; i += 64) {
@@ -722,12 +721,29 @@ NTU_DEV int svd_mem_pair(cd* W, int n, int p, int q, double tiny, double tol) {
   return 1;
 }
 
+// IN_LDS: the round's two blocks are copied to LDS first (2 SVD_MB n
+// entries of dynamic LDS) and back at the end; otherwise every step reads
+// and writes W
+constexpr int SVD_LDS_NMAX = 576;  // 2 SVD_MB n entries within 144 KB
+template <bool IN_LDS>
 __global__ void __launch_bounds__(64 * SVD_MB) k_ctm_svd_round(SvdBatch bt, int n, int nb, int sweep, int r) {
+  extern __shared__ cd xbuf[];
   const SvdMemWs ws = svd_mem_ws(bt.W[blockIdx.y], n);
   if (sweep > 0 && ws.rot[sweep - 1] == 0) return;  // converged
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int P, Q;
   rr_pair(nb, r, blockIdx.x, P, Q);
+  // column i < 2 SVD_MB of the pair: column i % SVD_MB of block P (i <
+  // SVD_MB) or Q; beyond n in the last (or the padding) block
+  auto gcol = [&](int i) { return (i < SVD_MB ? P : Q) * SVD_MB + i % SVD_MB; };
+  auto col = [&](int i) -> cd* { return IN_LDS ? xbuf + (long long)i * n : ws.W + (long long)gcol(i) * n; };
+  if (IN_LDS) {
+    for (int e = threadIdx.x; e < 2 * SVD_MB * n; e += blockDim.x) {
+      const int i = e / n, row = e % n;
+      if (gcol(i) < n) xbuf[e] = ws.W[(long long)gcol(i) * n + row];
+    }
+    __syncthreads();
+  }
   const double fro = *ws.fro;
   const double tiny = 1e-30 * fro, tol = 4.0 * 2.220446049250313e-16 * sqrt((double)n);
   int rot = 0;
@@ -741,16 +757,22 @@ __global__ void __launch_bounds__(64 * SVD_MB) k_ctm_svd_round(SvdBatch bt, int 
         const int x = slot - 1 + t;
         return 1 + (x >= SVD_MB - 1 ? x - (SVD_MB - 1) : x);
       };
-      const int B = h == 0 ? P : Q;
-      rot += svd_mem_pair(ws.W, n, B * SVD_MB + pos(k), B * SVD_MB + pos(SVD_MB - 1 - k), tiny, tol);
+      const int a = h * SVD_MB + pos(k), b = h * SVD_MB + pos(SVD_MB - 1 - k);
+      rot += svd_mem_pair(col(a), col(b), n, gcol(a) < n && gcol(b) < n, tiny, tol);
       __syncthreads();
     }
   }
   // pairs across the blocks: column i of P with column (i + sh) of Q
   for (int sh = 0; sh < SVD_MB; ++sh) {
-    rot += svd_mem_pair(ws.W, n, P * SVD_MB + wave, Q * SVD_MB + (wave + sh) % SVD_MB, tiny, tol);
+    const int a = wave, b = SVD_MB + (wave + sh) % SVD_MB;
+    rot += svd_mem_pair(col(a), col(b), n, gcol(a) < n && gcol(b) < n, tiny, tol);
     __syncthreads();
   }
+  if (IN_LDS)
+    for (int e = threadIdx.x; e < 2 * SVD_MB * n; e += blockDim.x) {
+      const int i = e / n, row = e % n;
+      if (gcol(i) < n) ws.W[(long long)gcol(i) * n + row] = xbuf[e];
+    }
   if (rot && lane == 0) atomicAdd(&ws.rot[sweep], rot);
 }
 
@@ -817,13 +839,46 @@ hipError_t ctm_svd_left(int count, const cd* const* rho, int n, int k, cd* const
   if (n <= 64) return launch_svd_reg<1, 2, 2, 1024>(bt, count, n, k, st);
   if (n <= CTM_SVD_REG_NMAX) return launch_svd_reg<2, 8, 4, 512>(bt, count, n, k, st);
   const int nblk = (n + SVD_MB - 1) / SVD_MB, nb = nblk + (nblk & 1);
+  const bool in_lds = n <= SVD_LDS_NMAX;
+  const size_t lds = in_lds ? (size_t)2 * SVD_MB * n * sizeof(cd) : 0;
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_ctm_svd_round<true>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(2 * SVD_MB * SVD_LDS_NMAX * sizeof(cd)));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
   hipLaunchKernelGGL(k_ctm_svd_lq, dim3(count), dim3(1024), 0, st, bt, n);
   hipError_t e = hipGetLastError();
-  for (int sweep = 0; sweep < SVD_SWEEPS_MULTI && e == hipSuccess; ++sweep)
-    for (int r = 0; r < nb - 1 && e == hipSuccess; ++r) {
-      hipLaunchKernelGGL(k_ctm_svd_round, dim3(nb / 2, count), dim3(64 * SVD_MB), 0, st, bt, n, nb, sweep, r);
-      e = hipGetLastError();
+  // the first SVD_SWEEPS_FIRST sweeps, then two at a time until a sweep of
+  // every matrix made no rotation (the rotation counts read back after each
+  // batch: the stream waits there); a sweep after a sweep without rotation
+  // returns at once on the device
+  int sweep = 0;
+  while (e == hipSuccess && sweep < SVD_SWEEPS_MULTI) {
+    const int upto = sweep == 0 ? SVD_SWEEPS_FIRST : (sweep + 2 < SVD_SWEEPS_MULTI ? sweep + 2 : SVD_SWEEPS_MULTI);
+    for (; sweep < upto && e == hipSuccess; ++sweep)
+      for (int r = 0; r < nb - 1 && e == hipSuccess; ++r) {
+        if (in_lds)
+          hipLaunchKernelGGL(k_ctm_svd_round<true>, dim3(nb / 2, count), dim3(64 * SVD_MB), lds, st, bt, n, nb,
+                             sweep, r);
+        else
+          hipLaunchKernelGGL(k_ctm_svd_round<false>, dim3(nb / 2, count), dim3(64 * SVD_MB), 0, st, bt, n, nb,
+                             sweep, r);
+        e = hipGetLastError();
+      }
+    if (e != hipSuccess || sweep >= SVD_SWEEPS_MULTI) break;
+    bool done = true;
+    for (int b = 0; b < count && e == hipSuccess; ++b) {
+      int last = 0;
+      const int* rot = (const int*)(ws[b] + (long long)n * n);  // the layout of svd_mem_ws
+      e = hipMemcpyAsync(&last, rot + sweep - 1, sizeof(int), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      done = done && last == 0;
     }
+    if (done) break;
+  }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_ctm_svd_final, dim3(count), dim3(256), 0, st, bt, n, k);
   return hipGetLastError();
