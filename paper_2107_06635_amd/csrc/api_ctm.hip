@@ -532,7 +532,7 @@ ntu_status ntu_ctm_create(ntu_ctm** out, int device, int p, int D, int chi) {
   // D = 1..8 and chi D^2 up to 1024
   const long long cc = (long long)chi * chi;
   c->arena_el = std::max<long long>(1 << 20, 10 * cc * D2 * D2 * D2 + 64 * cc * D2 * D2 + 2 * N * N +
-                                                 8 * D2 * D2 * D2 * D2 + 8 * (long long)p * D2 * D2);
+                                                 2 * ntu::CTM_SVD_WS_EXTRA + 8 * D2 * D2 * D2 * D2 + 8 * (long long)p * D2 * D2);
   hipError_t e = hipMalloc((void**)&c->pool, sizeof(cd) * c->slot_el * c->nslot);
   if (e == hipSuccess) e = hipMalloc((void**)&c->arena, sizeof(cd) * c->arena_el);
   if (e == hipSuccess) e = hipMalloc((void**)&c->norm_slot, 256);

@@ -29,9 +29,12 @@ hipError_t ctm_normalise(cd* x, long long n, unsigned long long* slot, hipStream
 // count (<= CTM_SVD_BATCH) independent matrices of one size in one launch.
 // ws[b]: CTM_SVD_WS_EXTRA + n^2 entries of scratch when n > CTM_SVD_REG_NMAX
 // (else unused).
-// One-sided Jacobi on rho's columns, one workgroup per matrix.
+// One-sided Jacobi on rho's columns: n <= CTM_SVD_REG_NMAX in registers,
+// one workgroup per matrix; beyond, in ws, over several workgroups per
+// matrix and a chain of launches (the host reads a rotation count back
+// between batches of sweeps, so the call waits on the stream).
 constexpr int CTM_SVD_NMAX = 1024;
-constexpr int CTM_SVD_REG_NMAX = 128;
+constexpr int CTM_SVD_REG_NMAX = 64;
 constexpr int CTM_SVD_BATCH = 4;
 constexpr double CTM_RANK_EPS = 1e-12;
 constexpr int CTM_SVD_WS_EXTRA = 64;  // entries beyond n^2: rotation counts and a norm

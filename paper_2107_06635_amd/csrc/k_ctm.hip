@@ -836,8 +836,7 @@ hipError_t ctm_svd_left(int count, const cd* const* rho, int n, int k, cd* const
     bt.Z[b] = Z[b];
     bt.W[b] = ws[b];
   }
-  if (n <= 64) return launch_svd_reg<1, 2, 2, 1024>(bt, count, n, k, st);
-  if (n <= CTM_SVD_REG_NMAX) return launch_svd_reg<2, 8, 4, 512>(bt, count, n, k, st);
+  if (n <= CTM_SVD_REG_NMAX) return launch_svd_reg<1, 2, 2, 1024>(bt, count, n, k, st);
   const int nblk = (n + SVD_MB - 1) / SVD_MB, nb = nblk + (nblk & 1);
   const bool in_lds = n <= SVD_LDS_NMAX;
   const size_t lds = in_lds ? (size_t)2 * SVD_MB * n * sizeof(cd) : 0;
