@@ -636,14 +636,27 @@ NTU_DEV SvdMemWs svd_mem_ws(cd* base, int n) {
   return w;
 }
 
+// The LQ factorisation of k_ctm_svd_reg by panels of bp = min(LQ_BP,
+// LQ_PANEL_ENT / n) rows: a panel's rows (their columns j0..n-1) are
+// factored in LDS one reflector H_k = 1 - beta_k v_k v_k^H at a time, and
+// the rows below take the whole panel at once through the compact form
+// H_0 .. H_{b-1} = 1 - V T V^H (T upper triangular, T_kk = beta_k,
+// T_ik = -beta_k sum_l T_il v_l^H v_k): W_rest <- W_rest - (W_rest V) T V^H.
+constexpr int LQ_PANEL_ENT = 3072;  // entries of a panel (and of V)
+constexpr int LQ_BP = 16;           // rows per panel at most
+constexpr int LQ_KK = 6;            // sums of Y = W_rest V per thread and pass
+
 __global__ void __launch_bounds__(1024) k_ctm_svd_lq(SvdBatch bt, int n) {
   __shared__ double red[64];
-  __shared__ cd rowbuf[2][CTM_SVD_NMAX];
-  __shared__ cd part[CTM_SVD_NMAX];
+  __shared__ cd Pn[LQ_PANEL_ENT];   // panel row k, column j0 + c at k m + c; then Y at r b + k
+  __shared__ cd Vs[LQ_PANEL_ENT];   // v_k at k m + c (zero for c < k)
+  __shared__ cd Gm[LQ_BP * LQ_BP];  // v_l^H v_k (l < k) at l LQ_BP + k
+  __shared__ cd Tm[LQ_BP * LQ_BP];  // T_ik at i LQ_BP + k (i <= k)
+  __shared__ double bet[LQ_BP];
   const cd* __restrict__ rho = bt.rho[blockIdx.x];
   const SvdMemWs ws = svd_mem_ws(bt.W[blockIdx.x], n);
   cd* __restrict__ W = ws.W;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
   if (tid < SVD_SWEEPS_MULTI) ws.rot[tid] = 0;
   double fro = 0.0;
   for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
@@ -652,45 +665,136 @@ __global__ void __launch_bounds__(1024) k_ctm_svd_lq(SvdBatch bt, int n) {
     W[(long long)j * n + i] = v;
     fro += abs2(v);
   }
-  fro = block_sum(fro, red);
+  fro = block_sum(fro, red);  // its barriers also publish W
   if (tid == 0) *ws.fro = fro;
-  // the LQ factorisation of k_ctm_svd_reg on the columns in global memory:
-  // row i = j + (tid % RG) of what is left (rows above j hold zeros beyond
-  // the diagonal), columns j + g, j + g + G, .. for g = tid / RG: four
-  // groups of 256 rows for n <= 256, one of 1024 beyond
-  const int RG = n <= 256 ? 256 : 1024, G = (int)blockDim.x / RG;
-  const int ri = tid % RG, gq = tid / RG;
-  for (int j = 0; j < n; ++j) {
-    cd* const rb = rowbuf[j & 1];
-    for (int c = j + tid; c < n; c += blockDim.x) rb[c] = W[(long long)c * n + j];
+  const int bp = min(LQ_BP, LQ_PANEL_ENT / n);
+  for (int j0 = 0; j0 < n; j0 += bp) {
+    const int b = min(bp, n - j0), m = n - j0;
+    for (int e = tid; e < b * m; e += blockDim.x) {
+      const int k = e % b, c = e / b;
+      Pn[k * m + c] = W[(long long)(j0 + c) * n + j0 + k];
+    }
     __syncthreads();
-    double s2 = 0.0;
-    for (int c = j + lane; c < n; c += 64) s2 += abs2(rb[c]);
-    const double nr = sqrt(wave_sum(s2));
-    if (!(nr > 0.0)) continue;
-    const cd rj = rb[j];
-    const double arj = absv(rj);
-    const cd e = arj > 0.0 ? cd{rj.x / arj, rj.y / arj} : cd{1.0, 0.0};
-    const double beta = 1.0 / (nr * (nr + arj));
-    const cd uj = conjv(e) * (arj + nr);
-    auto ucol = [&](int c) -> cd { return c == j ? uj : conjv(rb[c]); };  // c >= j
-    const int i = j + ri;
-    cd wp{0.0, 0.0};
-    if (i < n)
-      for (int c = j + gq; c < n; c += G) wp += W[(long long)c * n + i] * ucol(c);
-    part[tid] = wp;
+    for (int k = 0; k < b; ++k) {
+      cd* const row = Pn + k * m;
+      double s2 = 0.0;
+      for (int c = k + lane; c < m; c += 64) s2 += abs2(row[c]);
+      const double nr = sqrt(wave_sum(s2));  // the same on every wave
+      const cd rj = row[k];
+      const double arj = absv(rj);
+      const cd e = arj > 0.0 ? cd{rj.x / arj, rj.y / arj} : cd{1.0, 0.0};
+      const bool act = nr > 0.0;  // else H_k = 1 (the row is zero from k on)
+      const double beta = act ? 1.0 / (nr * (nr + arj)) : 0.0;
+      const cd uj = conjv(e) * (arj + nr);
+      auto ucol = [&](int c) -> cd { return c == k ? uj : conjv(row[c]); };  // c >= k
+      for (int c = tid; c < m; c += blockDim.x) Vs[k * m + c] = (c < k || !act) ? cd{0.0, 0.0} : ucol(c);
+      if (tid == 0) bet[k] = beta;
+      if (act)
+        for (int r = k + 1 + wave; r < b; r += nwave) {  // the panel's later rows, a wave each
+          cd* const pr = Pn + r * m;
+          cd w{0.0, 0.0};
+          for (int c = k + lane; c < m; c += 64) w += pr[c] * ucol(c);
+          w = wave_sum(w) * beta;
+          for (int c = k + lane; c < m; c += 64) pr[c] = pr[c] - w * conjv(ucol(c));
+        }
+      __syncthreads();
+      // row k of L: -e |r| on the diagonal, zeros beyond (the next step
+      // reads only rows k + 1 ..)
+      if (act)
+        for (int c = k + tid; c < m; c += blockDim.x) row[c] = c == k ? cd{-e.x * nr, -e.y * nr} : cd{0.0, 0.0};
+    }
     __syncthreads();
-    if (i < n) {
-      cd w{0.0, 0.0};
-      for (int g = 0; g < G; ++g) w += part[g * RG + ri];
-      w = w * beta;
-      const cd ljj = cd{-e.x * nr, -e.y * nr};
-      for (int c = j + gq; c < n; c += G) {
-        cd* const at = W + (long long)c * n + i;
-        *at = i == j ? (c == j ? ljj : cd{0.0, 0.0}) : *at - w * conjv(ucol(c));
+    for (int e = tid; e < b * m; e += blockDim.x) {
+      const int k = e % b, c = e / b;
+      W[(long long)(j0 + c) * n + j0 + k] = Pn[k * m + c];
+    }
+    const int R = n - j0 - b;  // rows below the panel
+    if (R <= 0) break;
+    for (int p = wave; p < b * b; p += nwave) {
+      const int l = p / b, k = p % b;
+      if (l < k) {
+        cd g{0.0, 0.0};
+        for (int c = lane; c < m; c += 64) g += cmul(Vs[l * m + c], Vs[k * m + c]);
+        g = wave_sum(g);
+        if (lane == 0) Gm[l * LQ_BP + k] = g;
       }
     }
-    __syncthreads();  // the next row is read from what this step wrote
+    __syncthreads();
+    if (tid < b) {  // lane i of wave 0 builds row i of T
+      const int i = tid;
+      Tm[i * LQ_BP + i] = cd{bet[i], 0.0};
+      for (int k = i + 1; k < b; ++k) {
+        cd t{0.0, 0.0};
+        for (int l = i; l < k; ++l) t += Tm[i * LQ_BP + l] * Gm[l * LQ_BP + k];
+        Tm[i * LQ_BP + k] = t * (-bet[k]);
+      }
+    }
+    // Y = W_rest V: thread (r, g) sums row j0 + b + r against v_k for
+    // k = g, g + ng, ..
+    const int Rp = (R + 63) & ~63, ng = (int)blockDim.x / Rp;  // R < n <= 1024: ng >= 1
+    const int r = tid % Rp, g = tid / Rp;
+    const bool mine = g < ng && r < R;
+    cd* const wr = W + j0 + b + r;  // column j0 + c of the row at wr[(j0 + c) n]
+    __syncthreads();  // the panel's rows are back in W: Pn takes Y
+    // LQ_KK sums per thread and pass (one pass unless b > LQ_KK ng: with
+    // 1024 threads ng >= 5 for n <= 204 and b <= 5 for n > 512, so at most
+    // five are needed)
+    for (int k0 = g; k0 < b; k0 += LQ_KK * ng) {
+      cd acc[LQ_KK];
+#pragma unroll
+      for (int kk = 0; kk < LQ_KK; ++kk) acc[kk] = cd{0.0, 0.0};
+      if (mine)
+        for (int c0 = 0; c0 < m; c0 += 4) {  // four loads in flight
+          cd w[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w[q] = c0 + q < m ? wr[(long long)(j0 + c0 + q) * n] : cd{0.0, 0.0};
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (c0 + q < m)
+#pragma unroll
+              for (int kk = 0; kk < LQ_KK; ++kk) {
+                const int k = k0 + kk * ng;
+                if (k < b) acc[kk] += w[q] * Vs[k * m + c0 + q];
+              }
+        }
+      if (mine)
+#pragma unroll
+        for (int kk = 0; kk < LQ_KK; ++kk) {
+          const int k = k0 + kk * ng;
+          if (k < b) Pn[r * b + k] = acc[kk];
+        }
+    }
+    __syncthreads();
+    // W_rest <- W_rest - (Y T) V^H, thread (r, g) on the columns c = g, g + ng, ..
+    cd yt[LQ_BP];
+#pragma unroll
+    for (int k = 0; k < LQ_BP; ++k) {
+      cd t{0.0, 0.0};
+      if (mine && k < b)
+        for (int l = 0; l <= k; ++l) t += Pn[r * b + l] * Tm[l * LQ_BP + k];
+      yt[k] = t;
+    }
+    if (mine)
+      for (int c0 = g; c0 < m; c0 += 2 * ng) {  // two loads in flight
+        cd w[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int c = c0 + q * ng;
+          w[q] = c < m ? wr[(long long)(j0 + c) * n] : cd{0.0, 0.0};
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int c = c0 + q * ng;
+          if (c < m) {
+            cd t{0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < LQ_BP; ++k)
+              if (k < b) t += yt[k] * conjv(Vs[k * m + c]);
+            wr[(long long)(j0 + c) * n] = w[q] - t;
+          }
+        }
+      }
+    __syncthreads();  // the next panel reads these rows and rewrites Pn, Vs
   }
 }
 
