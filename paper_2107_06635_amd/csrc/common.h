@@ -84,19 +84,18 @@ NTU_DEV double row_sum16(double v) {
   v += dpp_move<0x140>(v);
   return v;
 }
-// Sum over the wave; every lane gets the same (bit-identical) value.
-NTU_DEV double wave_sum(double v) {
-  v = row_sum16(v);
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
-  return v;
-}
 // Value of lane `src` (uniform across the wave, through a scalar register).
 NTU_DEV double lane_value(double v, int src) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
   const int lo = __builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), src);
   const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
   return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// Sum over the wave, (r0 + r16) + (r32 + r48) of the row sums read from
+// lanes 0, 16, 32, 48 (no LDS permutes); every lane gets the same value.
+NTU_DEV double wave_sum(double v) {
+  v = row_sum16(v);
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 // Sum over lanes 0..31 only (rows of a small matrix held one per lane); the
 // result is the same scalar on every lane.  Lanes 32..63 do not contribute.
