@@ -413,9 +413,10 @@ const char* ntu_profile_kind_name(int kind);
  * the ancilla, or the 4 basis operators of the Hermitian purification), bond
  * dimension D <= 8 and environment dimension chi (chi D^2 <= 1024);
  * allocates its device memory once: 96 tensors of max(chi^2 D^2, D^8)
- * complex entries and a scratch arena of
- * 10 chi^2 D^6 + 64 chi^2 D^4 + 2 (chi D^2)^2 + 8 D^8 + 8 p D^4 entries
- * (16 bytes each; e.g. 0.2 GB at D = 2, chi = 80, 40 GB at D = 8, chi = 16).
+ * complex entries, a scratch arena of
+ * 10 chi^2 D^6 + 64 chi^2 D^4 + 2 (chi D^2)^2 + 8 D^8 + 8 p D^4 + 128 entries
+ * (16 bytes each; e.g. 0.2 GB at D = 2, chi = 80, 40 GB at D = 8, chi = 16)
+ * and 4 MB of partial sums for products split along their sums.
  * NTU_ERR_SHAPE outside those limits, NTU_ERR_HIP if the memory is not
  * there.  After an error of ntu_ctm_run or ntu_ctm_expect the environment
  * is dropped: the next ntu_ctm_run starts from the boundary and
@@ -432,8 +433,11 @@ const char* ntu_profile_kind_name(int kind);
  * H2, the lower site for V1 and V2.  Each value is the ratio of the network
  * with the operators inserted to the norm network.
  * All three run on the stream set by ntu_ctm_set_stream (default the null
- * stream) without synchronising, except ntu_ctm_run's first call (it copies
- * the starting boundary from the host).  Errors: ntu_ctm_last_error.
+ * stream).  ntu_ctm_expect does not synchronise; ntu_ctm_run does on its
+ * first call (it copies the starting boundary from the host) and, for
+ * chi D^2 > 64, inside each cut's SVD (it reads the rotation count of the
+ * last Jacobi sweep back between batches of sweeps).  Errors:
+ * ntu_ctm_last_error.
  */
 typedef struct ntu_ctm ntu_ctm;
 ntu_status ntu_ctm_create(ntu_ctm** out, int device, int p, int D, int chi);

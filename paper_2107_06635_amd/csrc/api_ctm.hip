@@ -67,6 +67,7 @@ struct ntu_ctm {
   long long arena_el = 0, arena_top = 0;
   unsigned long long* norm_slot = nullptr;
   cd* scalars = nullptr;  // 256 values of an evaluation (network values)
+  cd* gemm_ws = nullptr;  // partial sums of split products (CTM_GEMM_WS entries)
   EnvT env[2][2];
   int env_slot[2][2][8];
   Tn site[2][2];
@@ -190,7 +191,7 @@ Tn contract(ntu_ctm* c, Err& E, const char* spec, const Tn& A, bool cA, const Tn
   Tn C = alloc(c, E, sh, r);
   if (E.e != hipSuccess) return none;
   if (K == 0 || M * N == 0) E.set(ntu::ctm_zero(C.p, M * N, c->stream), "zero");
-  else E.set(ntu::ctm_gemm(Ap.p, Bp.p, C.p, (int)M, (int)N, (int)K, c->stream), "gemm");
+  else E.set(ntu::ctm_gemm(Ap.p, Bp.p, C.p, (int)M, (int)N, (int)K, c->gemm_ws, ntu::CTM_GEMM_WS, c->stream), "gemm");
   if (mid == lo || lo.empty()) {
     if (lo.empty()) C.r = 0;
     return C;
@@ -537,12 +538,14 @@ ntu_status ntu_ctm_create(ntu_ctm** out, int device, int p, int D, int chi) {
   if (e == hipSuccess) e = hipMalloc((void**)&c->arena, sizeof(cd) * c->arena_el);
   if (e == hipSuccess) e = hipMalloc((void**)&c->norm_slot, 256);
   if (e == hipSuccess) e = hipMalloc((void**)&c->scalars, sizeof(cd) * 256);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->gemm_ws, sizeof(cd) * ntu::CTM_GEMM_WS);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(c->pool);
     (void)hipFree(c->arena);
     (void)hipFree(c->norm_slot);
     (void)hipFree(c->scalars);
+    (void)hipFree(c->gemm_ws);
     delete c;
     return cfail(nullptr, NTU_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
@@ -558,6 +561,7 @@ ntu_status ntu_ctm_destroy(ntu_ctm* c) {
   (void)hipFree(c->arena);
   (void)hipFree(c->norm_slot);
   (void)hipFree(c->scalars);
+  (void)hipFree(c->gemm_ws);
   delete c;
   return NTU_OK;
 }

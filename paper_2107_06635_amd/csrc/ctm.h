@@ -13,8 +13,11 @@ constexpr int CTM_MAX_RANK = 8;
 // axis k: out_shape[k] = in_shape[perm[k]]; op = conj or identity.
 hipError_t ctm_permute(const cd* in, cd* out, int rank, const int* in_shape, const int* perm, bool conj,
                        hipStream_t st);
-// C (M x N) = A (M x K) B (K x N), row-major; K = 0 writes zeros.
-hipError_t ctm_gemm(const cd* A, const cd* B, cd* C, int M, int N, int K, hipStream_t st);
+// C (M x N) = A (M x K) B (K x N), row-major; K = 0 writes zeros.  ws
+// (ws_el entries, may be null): partial sums when few output tiles meet a
+// long K (the K range then split over several workgroups per tile).
+hipError_t ctm_gemm(const cd* A, const cd* B, cd* C, int M, int N, int K, cd* ws, long long ws_el, hipStream_t st);
+constexpr long long CTM_GEMM_WS = 1ll << 18;  // entries of the partial-sum buffer of a CTMRG object
 // dst[i] = src[i] (real to complex), n entries
 hipError_t ctm_widen(const double* src, cd* dst, long long n, hipStream_t st);
 // x /= max_i |x_i| (left unchanged when all zero); slot: one unsigned long

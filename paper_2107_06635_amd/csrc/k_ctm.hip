@@ -54,22 +54,27 @@ hipError_t ctm_permute(const cd* in, cd* out, int rank, const int* in_shape, con
 
 // 32 x 32 tile of C per workgroup of 256 threads (2 x 2 outputs each), K in
 // chunks of 16 through shared memory; out-of-range operands read as zero.
+// One 32 x 32 tile of C per workgroup over the K range [z kc, min(K, (z + 1) kc))
+// of blockIdx.z = z, written to C + z cstride (z = 0, kc = K: C itself).
 __global__ void __launch_bounds__(256) k_ctm_gemm(const cd* __restrict__ A, const cd* __restrict__ B,
-                                                  cd* __restrict__ C, int M, int N, int K) {
+                                                  cd* __restrict__ C, int M, int N, int K, int kc,
+                                                  long long cstride) {
   constexpr int T = 32, KC = 16;
   __shared__ cd As[KC][T + 1];
   __shared__ cd Bs[KC][T + 1];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int i0 = blockIdx.y * T, j0 = blockIdx.x * T;
+  const int kb0 = blockIdx.z * kc, kend = min(K, kb0 + kc);
+  C += blockIdx.z * cstride;
   cd acc[2][2] = {{cd{0, 0}, cd{0, 0}}, {cd{0, 0}, cd{0, 0}}};
-  for (int k0 = 0; k0 < K; k0 += KC) {
+  for (int k0 = kb0; k0 < kend; k0 += KC) {
     for (int e = tid; e < KC * T; e += 256) {
       const int r = e / KC, kk = e % KC;            // A: row r of the tile, column kk of the chunk
       const int i = i0 + r, k = k0 + kk;
-      As[kk][r] = (i < M && k < K) ? A[(long long)i * K + k] : cd{0, 0};
+      As[kk][r] = (i < M && k < kend) ? A[(long long)i * K + k] : cd{0, 0};
       const int kb = e / T, c = e % T;              // B: row kb of the chunk, column c of the tile
       const int kk2 = k0 + kb, j = j0 + c;
-      Bs[kb][c] = (kk2 < K && j < N) ? B[(long long)kk2 * N + j] : cd{0, 0};
+      Bs[kb][c] = (kk2 < kend && j < N) ? B[(long long)kk2 * N + j] : cd{0, 0};
     }
     __syncthreads();
 #pragma unroll
@@ -90,10 +95,37 @@ __global__ void __launch_bounds__(256) k_ctm_gemm(const cd* __restrict__ A, cons
     }
 }
 
-hipError_t ctm_gemm(const cd* A, const cd* B, cd* C, int M, int N, int K, hipStream_t st) {
+// C[e] = sum_z P[z mn + e], z = 0 .. S - 1 in order
+__global__ void k_ctm_sum_splits(const cd* __restrict__ P, cd* __restrict__ C, long long mn, int S) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < mn; e += (long long)gridDim.x * blockDim.x) {
+    cd t{0.0, 0.0};
+    for (int z = 0; z < S; ++z) t += P[z * mn + e];
+    C[e] = t;
+  }
+}
+
+hipError_t ctm_gemm(const cd* A, const cd* B, cd* C, int M, int N, int K, cd* ws, long long ws_el, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  const dim3 g((N + 31) / 32, (M + 31) / 32);
-  hipLaunchKernelGGL(k_ctm_gemm, g, dim3(256), 0, st, A, B, C, M, N, K);
+  const int tiles = ((N + 31) / 32) * ((M + 31) / 32);
+  const long long mn = (long long)M * N;
+  // few output tiles over a long K: the K range split over S workgroups per
+  // tile (at least 512 columns of K each, about 512 workgroups in all), the
+  // partial tiles summed in order by a second launch
+  int S = 1;
+  if (ws && tiles < 128 && K >= 1024) {
+    S = (int)std::min<long long>({(long long)(512 + tiles - 1) / tiles, (long long)K / 512, ws_el / mn, 1024});
+    if (S < 2) S = 1;
+  }
+  if (S == 1) {
+    hipLaunchKernelGGL(k_ctm_gemm, dim3((N + 31) / 32, (M + 31) / 32, 1), dim3(256), 0, st, A, B, C, M, N, K, K, 0ll);
+    return hipGetLastError();
+  }
+  const int kc = ((K + S - 1) / S + 15) & ~15;
+  S = (K + kc - 1) / kc;  // every split non-empty
+  hipLaunchKernelGGL(k_ctm_gemm, dim3((N + 31) / 32, (M + 31) / 32, S), dim3(256), 0, st, A, B, ws, M, N, K, kc, mn);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ctm_sum_splits, dim3(grid_for(mn, 256)), dim3(256), 0, st, ws, C, mn, S);
   return hipGetLastError();
 }
 
