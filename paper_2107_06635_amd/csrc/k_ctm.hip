@@ -204,10 +204,12 @@ NTU_DEV bool hestenes_params(double al, double be, cd ga, double tiny, double to
   // root fewer per pair; the values here are far from the overflow range
   const double g2 = abs2(ga);
   if (!(g2 > tiny * tiny) || !(g2 > tol * tol * al * be)) return false;
-  const double g = sqrt(g2), ig = 1.0 / g;
+  // 1 / |ga| and c = 1 / sqrt(1 + t^2) as reciprocal square roots (one
+  // dependent operation each instead of a square root and a division)
+  const double ig = rsqrt(g2), g = g2 * ig;
   const double zeta = 0.5 * (be - al) * ig;
   const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  c = 1.0 / sqrt(1.0 + t * t);
+  c = rsqrt(1.0 + t * t);
   s = c * t;
   em = cd{ga.x * ig, -ga.y * ig};
   tg = t * g;  // |w_p|^2 falls and |w_q|^2 rises by t |ga|
