@@ -173,6 +173,49 @@ Tn contract(ntu_ctm* c, Err& E, const char* spec, const Tn& A, bool cA, const Tn
       E.set(hipErrorInvalidValue, "contract: label");
       return none;
     }
+  long long M = 1, N = 1, K = 1;
+  for (char ch : freeA) M *= dim_of(ch);
+  for (char ch : freeB) N *= dim_of(ch);
+  for (char ch : sum) K *= dim_of(ch);
+  if (K > 0 && K < 1024 && M * K <= 65536 && K * N <= 65536 && M * N <= 65536) {
+    // small: one launch gathers the operands from their own layouts and
+    // writes the result in the output's order (no permuted copies)
+    int sh[ntu::CTM_MAX_RANK], r = 0;
+    for (char ch : lo) sh[r++] = dim_of(ch);
+    Tn C = alloc(c, E, sh, r);
+    if (E.e != hipSuccess) return none;
+    auto strides = [](const int* s, int rk, long long* st) {
+      long long v = 1;
+      for (int i = rk - 1; i >= 0; --i) {
+        st[i] = v;
+        v *= s[i];
+      }
+    };
+    long long sa[ntu::CTM_MAX_RANK], sb[ntu::CTM_MAX_RANK], so[ntu::CTM_MAX_RANK];
+    strides(A.s, A.r, sa);
+    strides(B.s, B.r, sb);
+    strides(sh, r, so);
+    auto axes = [&](const std::string& labels, const std::string& in, const long long* st) {
+      ntu::CtmAxes g;
+      for (char ch : labels) {
+        g.dim[g.n] = dim_of(ch);
+        g.stride[g.n++] = st[in.find(ch)];
+      }
+      return g;
+    };
+    ntu::CtmGather gd;
+    gd.ra = axes(freeA, la, sa);
+    gd.ca = axes(sum, la, sa);
+    gd.rb = axes(sum, lb, sb);
+    gd.cb = axes(freeB, lb, sb);
+    gd.rc = axes(freeA, lo, so);
+    gd.cc = axes(freeB, lo, so);
+    gd.conj_a = cA;
+    gd.conj_b = cB;
+    E.set(ntu::ctm_gemm_gather(A.p, B.p, C.p, (int)M, (int)N, (int)K, gd, c->stream), "gemm");
+    if (lo.empty()) C.r = 0;
+    return C;
+  }
   int pa[ntu::CTM_MAX_RANK], pb[ntu::CTM_MAX_RANK], k = 0;
   for (char ch : freeA) pa[k++] = (int)la.find(ch);
   for (char ch : sum) pa[k++] = (int)la.find(ch);
@@ -181,10 +224,6 @@ Tn contract(ntu_ctm* c, Err& E, const char* spec, const Tn& A, bool cA, const Tn
   for (char ch : freeB) pb[k++] = (int)lb.find(ch);
   const Tn Ap = permute(c, E, A, pa, cA);
   const Tn Bp = permute(c, E, B, pb, cB);
-  long long M = 1, N = 1, K = 1;
-  for (char ch : freeA) M *= dim_of(ch);
-  for (char ch : freeB) N *= dim_of(ch);
-  for (char ch : sum) K *= dim_of(ch);
   int sh[ntu::CTM_MAX_RANK], r = 0;
   const std::string mid = freeA + freeB;
   for (char ch : mid) sh[r++] = dim_of(ch);

@@ -18,6 +18,21 @@ hipError_t ctm_permute(const cd* in, cd* out, int rank, const int* in_shape, con
 // long K (the K range then split over several workgroups per tile).
 hipError_t ctm_gemm(const cd* A, const cd* B, cd* C, int M, int N, int K, cd* ws, long long ws_el, hipStream_t st);
 constexpr long long CTM_GEMM_WS = 1ll << 18;  // entries of the partial-sum buffer of a CTMRG object
+// A row or column index as digits over n axes (the last fastest): axis a
+// has extent dim[a] and moves the address by stride[a] entries.
+struct CtmAxes {
+  int n = 0;
+  int dim[CTM_MAX_RANK] = {};
+  long long stride[CTM_MAX_RANK] = {};
+};
+struct CtmGather {
+  CtmAxes ra, ca, rb, cb, rc, cc;  // rows and columns of A, B, C
+  int conj_a = 0, conj_b = 0;
+};
+// C = A B with A (M x K), B (K x N) read and C written through the offsets
+// of gd (no permuted copies); K = 0 leaves C untouched.
+hipError_t ctm_gemm_gather(const cd* A, const cd* B, cd* C, int M, int N, int K, const CtmGather& gd,
+                           hipStream_t st);
 // dst[i] = src[i] (real to complex), n entries
 hipError_t ctm_widen(const double* src, cd* dst, long long n, hipStream_t st);
 // x /= max_i |x_i| (left unchanged when all zero); slot: one unsigned long

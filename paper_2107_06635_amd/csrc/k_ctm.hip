@@ -129,6 +129,76 @@ hipError_t ctm_gemm(const cd* A, const cd* B, cd* C, int M, int N, int K, cd* ws
   return hipGetLastError();
 }
 
+// The same tiles with the operands gathered and the result scattered through
+// separable offsets: entry (i, k) of A is A[off(ra, i) + off(ca, k)], where
+// off(g, x) splits x into the digits of g's axes (last axis fastest) and sums
+// digit times stride; likewise B (rows rb, columns cb) and C (rc, cc).
+// conj_a, conj_b conjugate the operands on load.
+NTU_DEV long long gather_off(const CtmAxes& g, int x) {
+  long long o = 0;
+  for (int a = g.n - 1; a >= 0; --a) {
+    const int q = x / g.dim[a];
+    o += (long long)(x - q * g.dim[a]) * g.stride[a];
+    x = q;
+  }
+  return o;
+}
+
+__global__ void __launch_bounds__(256) k_ctm_gemm_gather(const cd* __restrict__ A, const cd* __restrict__ B,
+                                                         cd* __restrict__ C, int M, int N, int K, CtmGather gd) {
+  constexpr int T = 32, KC = 16;
+  __shared__ cd As[KC][T + 1];
+  __shared__ cd Bs[KC][T + 1];
+  __shared__ long long offA[T], offB[T], kA[KC], kB[KC];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int i0 = blockIdx.y * T, j0 = blockIdx.x * T;
+  if (tid < T) offA[tid] = i0 + tid < M ? gather_off(gd.ra, i0 + tid) : 0;
+  else if (tid < 2 * T) offB[tid - T] = j0 + tid - T < N ? gather_off(gd.cb, j0 + tid - T) : 0;
+  cd acc[2][2] = {{cd{0, 0}, cd{0, 0}}, {cd{0, 0}, cd{0, 0}}};
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    if (tid < KC) kA[tid] = k0 + tid < K ? gather_off(gd.ca, k0 + tid) : 0;
+    else if (tid < 2 * KC) kB[tid - KC] = k0 + tid - KC < K ? gather_off(gd.rb, k0 + tid - KC) : 0;
+    __syncthreads();
+    for (int e = tid; e < KC * T; e += 256) {
+      const int r = e / KC, kk = e % KC;
+      const int i = i0 + r, k = k0 + kk;
+      cd a = (i < M && k < K) ? A[offA[r] + kA[kk]] : cd{0, 0};
+      if (gd.conj_a) a.y = -a.y;
+      As[kk][r] = a;
+      const int kb = e / T, c = e % T;
+      const int kk2 = k0 + kb, j = j0 + c;
+      cd b = (kk2 < K && j < N) ? B[kB[kb] + offB[c]] : cd{0, 0};
+      if (gd.conj_b) b.y = -b.y;
+      Bs[kb][c] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const cd a0 = As[kk][ty], a1 = As[kk][ty + 16];
+      const cd b0 = Bs[kk][tx], b1 = Bs[kk][tx + 16];
+      acc[0][0] += a0 * b0;
+      acc[0][1] += a0 * b1;
+      acc[1][0] += a1 * b0;
+      acc[1][1] += a1 * b1;
+    }
+    __syncthreads();
+  }
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      const int i = i0 + ty + 16 * u, j = j0 + tx + 16 * v;
+      if (i < M && j < N) C[gather_off(gd.rc, i) + gather_off(gd.cc, j)] = acc[u][v];
+    }
+}
+
+hipError_t ctm_gemm_gather(const cd* A, const cd* B, cd* C, int M, int N, int K, const CtmGather& gd,
+                           hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  for (const CtmAxes* g : {&gd.ra, &gd.ca, &gd.rb, &gd.cb, &gd.rc, &gd.cc})
+    if (g->n < 0 || g->n > CTM_MAX_RANK) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ctm_gemm_gather, dim3((N + 31) / 32, (M + 31) / 32), dim3(256), 0, st, A, B, C, M, N, K, gd);
+  return hipGetLastError();
+}
+
 __global__ void k_ctm_widen(const double* __restrict__ src, cd* __restrict__ dst, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     dst[i] = cd{src[i], 0.0};
