@@ -286,18 +286,6 @@ NTU_DEV bool hestenes_params(double al, double be, cd ga, double tiny, double to
   return true;
 }
 
-template <int PER> NTU_DEV void pair_gram(const cd (&a)[PER], const cd (&b)[PER], double& al, double& be, cd& ga) {
-  al = 0.0;
-  be = 0.0;
-  ga = cd{0.0, 0.0};
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    al += abs2(a[u]);
-    be += abs2(b[u]);
-    ga += cmul(a[u], b[u]);
-  }
-}
-
 template <int PER> NTU_DEV void pair_rotate(cd (&a)[PER], cd (&b)[PER], double c, double s, cd em) {
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
