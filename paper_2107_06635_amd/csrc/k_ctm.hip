@@ -998,6 +998,20 @@ __global__ void __launch_bounds__(256) k_ctm_svd_final(SvdBatch bt, int n, int k
   if (wave == 0) svd_orthonormalise_wave<CTM_SVD_NMAX / 64>(Z, k, 1, n, k);
 }
 
+// The dynamic LDS limit of a kernel, set once per device (done[dev]; set
+// again every call on devices beyond the table).
+constexpr int SVD_ATTR_DEVICES = 64;
+static hipError_t set_lds_attr(const void* fn, int bytes, bool* done) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const bool in_table = dev >= 0 && dev < SVD_ATTR_DEVICES;
+  if (in_table && done[dev]) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess && in_table) done[dev] = true;
+  return e;
+}
+
 // one workgroup of NT threads per matrix: n <= 2 C (NT / 64) (two blocks
 // of C columns per wave) and n <= 64 PER (PER rows per lane)
 template <int PER, int C, int ILP, int NT>
@@ -1007,13 +1021,9 @@ static hipError_t launch_svd_reg(const SvdBatch& bt, int count, int n, int k, hi
   constexpr size_t LDS_CAP = (size_t)(2 * NW * C * 64 > NW * 64 * PER ? 2 * NW * C * 64 : NW * 64 * PER) * sizeof(cd);
   static_assert(LDS_CAP <= 144 * 1024, "LDS");
   if (n > 2 * C * NW || n > 64 * PER) return hipErrorInvalidValue;
-  static bool attr = false;
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_ctm_svd_reg<PER, C, ILP, NT>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_CAP);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static bool attr[SVD_ATTR_DEVICES] = {};
+  const hipError_t ea = set_lds_attr((const void*)k_ctm_svd_reg<PER, C, ILP, NT>, (int)LDS_CAP, attr);
+  if (ea != hipSuccess) return ea;
   const int nblk = (n + C - 1) / C, nb = nblk + (nblk & 1);
   const size_t ex = (size_t)nb * C * 64, part = (size_t)NW * 64 * PER, zs = (size_t)k * 64 * PER;
   const size_t cap = LDS_CAP / sizeof(cd);
@@ -1036,14 +1046,10 @@ hipError_t ctm_svd_left(int count, const cd* const* rho, int n, int k, cd* const
   const int nblk = (n + SVD_MB - 1) / SVD_MB, nb = nblk + (nblk & 1);
   const bool in_lds = n <= SVD_LDS_NMAX;
   const size_t lds = in_lds ? (size_t)2 * SVD_MB * n * sizeof(cd) : 0;
-  static bool attr = false;
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_ctm_svd_round<true>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)(2 * SVD_MB * SVD_LDS_NMAX * sizeof(cd)));
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static bool attr[SVD_ATTR_DEVICES] = {};
+  const hipError_t ea = set_lds_attr((const void*)k_ctm_svd_round<true>,
+                                     (int)(2 * SVD_MB * SVD_LDS_NMAX * sizeof(cd)), attr);
+  if (ea != hipSuccess) return ea;
   hipLaunchKernelGGL(k_ctm_svd_lq, dim3(count), dim3(1024), 0, st, bt, n);
   hipError_t e = hipGetLastError();
   // the first SVD_SWEEPS_FIRST sweeps, then two at a time until a sweep of

@@ -1869,9 +1869,12 @@ hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, co
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  static bool attr_set[2] = {false, false};
+  // the LDS limit once per device and element type (every call on devices
+  // beyond the table)
+  static bool attr_set[64][2] = {};
   static int ncu_of[64] = {};
-  if (!attr_set[cplx ? 1 : 0]) {
+  const bool in_table = dev >= 0 && dev < 64;
+  if (!in_table || !attr_set[dev][cplx ? 1 : 0]) {
     // allow the full 160 KiB of LDS for the dynamic part
     e = cplx ? hipFuncSetAttribute((const void*)k_bond_fit<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_MAX)
              : hipFuncSetAttribute((const void*)k_bond_fit<double>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_MAX);
@@ -1880,7 +1883,7 @@ hipError_t launch_bond_fit(bool cplx, int batch, int D, int R, const void* g, co
              : hipFuncSetAttribute((const void*)k_bond_fit_grp<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    LDS_MAX);
     if (e != hipSuccess) return e;
-    attr_set[cplx ? 1 : 0] = true;
+    if (in_table) attr_set[dev][cplx ? 1 : 0] = true;
   }
   if (dev >= 0 && dev < 64 && ncu_of[dev] == 0) {
     int ncu = 0;
