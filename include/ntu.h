@@ -62,7 +62,7 @@ enum {
   NTU_ERR_HIP = -4,         /* a HIP runtime call failed                     */
   NTU_ERR_NONFINITE = -5,   /* reserved: non-finite values are flagged in stats */
   NTU_ERR_WORKSPACE = -6,   /* request exceeds the context's workspace       */
-  NTU_ERR_UNSUPPORTED = -7  /* valid request this build does not implement   */
+  NTU_ERR_UNSUPPORTED = -7  /* valid request the library does not implement  */
 };
 
 /* element types */
