@@ -73,14 +73,17 @@ def test_onsager(K):
     _compare(g, _oracle(A, A, 16, 40, C.pauli_ops()), 1e-10)
 
 
-def test_onsager_large_cut():
-    """The Ising PEPS at K = 0.3 with chi = 80: cuts of n = chi D^2 = 320
-    (the global-memory SVD, whose cuts beyond rank chi get the completion
-    rule) still give Onsager's value on every bond to 1e-10."""
+@pytest.mark.parametrize("chi", [80, 150])
+def test_onsager_large_cut(chi):
+    """The Ising PEPS at K = 0.3 with chi = 80 and 150: cuts of n = chi D^2
+    = 320 and 600 (the multi-workgroup SVD with its column blocks staged in
+    LDS, and read from global memory beyond n = 576; the cuts beyond rank
+    chi get the completion rule) still give Onsager's value on every bond to
+    1e-10."""
     K = 0.3
     A = _bond_peps(np.exp(0.5 * K * np.outer([1, -1], [1, -1])))
     Z = np.diag([1.0, -1.0]).astype(complex)
-    g = _gpu(A, A, 80, 40, dict(X=np.eye(2, dtype=complex), Z=Z, ZZ=np.kron(Z, Z)))
+    g = _gpu(A, A, chi, 40, dict(X=np.eye(2, dtype=complex), Z=Z, ZZ=np.kron(Z, Z)))
     for b in O.BONDS:
         assert abs(g['zz'][b] - onsager_nn(K)) < 1e-10, (b, g['zz'][b])
 
@@ -136,7 +139,7 @@ def test_hermitian_purification():
 
 
 def test_errors():
-    """Sizes beyond the eigenproblem's limit and an evaluation without an
+    """Sizes beyond the cut SVD's limit and an evaluation without an
     environment are refused with their codes."""
     with pytest.raises(RuntimeError, match="status -2"):
         ntu.CTM(2, 8, 20)            # chi D^2 = 1280 > 1024
