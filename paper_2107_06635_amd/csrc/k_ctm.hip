@@ -712,7 +712,7 @@ __global__ void __launch_bounds__(NT) k_ctm_svd_reg(SvdBatch bt, int n, int k, i
 //   k_ctm_svd_final  one workgroup per matrix: norms, order, Z, and the
 //                    Gram-Schmidt of one wave.
 constexpr int SVD_MB = 8;                  // columns per block (one wave each)
-constexpr int SVD_SWEEPS_MULTI = 24;       // at most this many sweeps
+constexpr int SVD_SWEEPS_MULTI = SVD_SWEEPS;  // at most this many sweeps (as the register kernel)
 constexpr int SVD_SWEEPS_FIRST = 8;        // sweeps launched before the first look at the counts
 
 struct SvdMemWs {
